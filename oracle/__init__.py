@@ -1,0 +1,24 @@
+"""Plain FP64 CPU oracle for the damped-wave QEP discretised with IGA / rIGA.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute anything under this package; only the test-suite, the package smoke
+check and the CPU-baseline leg of the benchmark use it.  It shares no code,
+tables or constants with the HIP library and is written for a reader who has
+the paper beside it: every function names the section or equation it follows.
+
+What it computes is the *definition* of the result, not the paper's method:
+the N_ev eigenvalues of the discrete QEP (K + lam C + lam^2 M) u = 0
+(Sec. 4.2, eq. QuadEig) nearest the shift sigma, for a given B-spline space.
+Shift-and-invert, linearisation, Arnoldi, restarting and multifrontal
+factorisation are ways of reaching exactly this set faster.
+
+Modules
+    bspline   knot vectors (eq. KnotsX/KnotsY), Cox--de Boor (eq. BasisFunBi0/Bip),
+              Gauss--Legendre rule
+    space     1-D supports, dimension and sparsity counts (Sec. 3.2-3.3, fig. MatPatterns)
+    assemble  K, M, C on the unit square, Dirichlet elimination, Q(sigma)
+    eigen     dense companion-pencil QZ (eq. Linearization), Rayleigh-damping closed
+              form, sparse shift-and-invert (eq. BlockOperatorVector), residual,
+              canonical ordering
+    adjoint   d lam / d c_e for a per-element damping field
+"""
