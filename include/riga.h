@@ -1,0 +1,182 @@
+/*
+ * riga.h -- C ABI of the MI355X shift-and-invert solver for the damped-wave
+ * quadratic eigenvalue problem (K + lam C + lam^2 M) u = 0 discretised with
+ * maximum-continuity IGA or refined IGA (rIGA) B-splines on the unit square.
+ *
+ * Paper: Hashemian, Garcia, Pardo, Calo, "Performance of refined isogeometric
+ * analysis in solving quadratic eigenvalue problems" (arXiv 2112.14064).
+ *
+ * The calls follow the input/output statement of the paper's quadratic
+ * eigen-procedure (Sec. 4.2.1, Alg. 2): system matrices K, C, M; a target
+ * shift; the number of requested eigenpairs; the Krylov subspace size; an
+ * initial vector; a tolerance -> eigenpairs.
+ *
+ * Conventions (all entry points):
+ *   - Dofs are the tensor-product B-splines B_i(x) B_j(y) that vanish on the
+ *     boundary (homogeneous Dirichlet: the first and last 1-D function of each
+ *     direction are removed), numbered lexicographically, x fastest:
+ *     dof = j * n1d + i.
+ *   - "device" pointers are HIP device memory owned by the caller and must stay
+ *     valid for the duration of the call; "host" pointers are ordinary memory.
+ *     The library owns everything it allocates internally (matrices, factor,
+ *     Krylov workspace) and frees it in riga_destroy.
+ *   - All work is queued on the stream given to riga_create.  Calls return
+ *     after the result they report is known: riga_factor, riga_eigs and
+ *     riga_adjoint synchronise the stream; riga_assemble, riga_solve_q and
+ *     riga_apply_op return as soon as the work is queued.
+ *   - A negative status is an error: outputs are not written (except where a
+ *     diagnostic such as *bad_pivot is documented).  A positive status is a
+ *     warning: outputs are valid as documented.
+ *   - A handle is not thread-safe: use one handle per host thread / stream.
+ *   - Floating-point arguments and results are IEEE binary64.
+ */
+#ifndef RIGA_H
+#define RIGA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct riga_problem riga_problem;
+
+typedef enum {
+  RIGA_OK = 0,
+  RIGA_ERR_INVALID_ARG = -1,   /* bad size, degree, pointer or option          */
+  RIGA_ERR_NOT_SPD = -2,       /* a Cholesky pivot of Q(sigma) was <= 0       */
+  RIGA_ERR_HIP = -3,           /* a HIP runtime call failed                    */
+  RIGA_ERR_OOM = -4,           /* device allocation failed                     */
+  RIGA_ERR_STATE = -5,         /* call out of order (e.g. eigs before factor)  */
+  RIGA_WARN_NOT_CONVERGED = 1  /* eigs stopped at maxit with nconv < nev       */
+} riga_status;
+
+/* Discretisation (Sec. 3.1-3.3).
+ *   p            B-spline degree, 1 <= p <= 8.
+ *   ne           elements per direction on (0,1)^2, ne >= 2.
+ *   hyper_every  0: maximum-continuity IGA (interior knots of multiplicity 1,
+ *                C^{p-1}; Sec. 3.2).  s > 0: rIGA, knots at multiples of s/ne
+ *                get multiplicity p, i.e. C^0 hyperplanes that cut the square
+ *                into (ne/s)^2 macroelements (Sec. 3.3); ne % s == 0 required.
+ *   leaf         IGA only: nested-dissection boxes stop splitting once both
+ *                sides are <= leaf elements (0 = default 16).  Ignored for rIGA,
+ *                whose leaves are the macroelements.                           */
+typedef struct {
+  int p, ne, hyper_every, leaf;
+} riga_mesh;
+
+/* Damping C = alpha M + beta K + sum_e c_e M_e (Rayleigh part plus an optional
+ * per-element viscous field).  c_elem: device, ne*ne doubles indexed
+ * e = ey*ne + ex, or NULL for none.  Read during riga_assemble and kept by
+ * reference for riga_adjoint (the caller keeps it alive until then).          */
+typedef struct {
+  double alpha, beta;
+  const double* c_elem;
+} riga_damping;
+
+/* Eigensolver options (Alg. 2 and Sec. 4.1.3).
+ *   nev     requested eigenpairs nearest sigma, 1 <= nev < 2N.
+ *   m       Krylov subspace size, nev + block <= m <= 2N (0: max(2 nev, 20)).
+ *   maxit   maximum number of restarts (0: 200).
+ *   block   block size of the Krylov iteration, 1..4 (0: 2).  Blocks of 2 resolve
+ *           the exact double eigenvalues of the x<->y symmetric square.
+ *   tol     relative Ritz residual for convergence (0: 1e-12).
+ *   seed    seed of the library's counter-based start block (used if v0 NULL).
+ *   v0      device, 2N x block column-major start block, or NULL.             */
+typedef struct {
+  int nev, m, maxit, block;
+  double tol;
+  uint64_t seed;
+  const double* v0;
+} riga_options;
+
+typedef struct {
+  int64_t n1d;          /* 1-D functions per direction after Dirichlet          */
+  int64_t ndof;         /* N = n1d^2                                            */
+  int64_t nnz;          /* structural nonzeros of K, M, C and Q                 */
+  int64_t nnodes;       /* nodes of the nested-dissection tree                  */
+  int64_t nleaves;      /* leaves (rIGA: macroelements)                         */
+  int64_t height;       /* levels of the tree (leaves = level 0)                */
+  int64_t max_front;    /* largest front (own + boundary dofs)                  */
+  int64_t leaf_own;     /* largest number of dofs eliminated in one leaf        */
+  int64_t factor_entries;   /* stored entries of the factor (dense fronts)      */
+  double  factor_flops_dense; /* flops executed by the dense-front factorization */
+  double  solve_bytes;  /* bytes of factor read by one forward+backward solve   */
+} riga_info_t;
+
+typedef struct {
+  int64_t n_it;         /* Krylov-Schur restarts performed (N_it)               */
+  int64_t n_fb;         /* forward/backward solves (one per vector, N_fb)       */
+  int64_t n_mv;         /* sparse matrix-vector products (N_mv)                 */
+  int64_t n_vv;         /* length-N vector-vector products (N_vv)               */
+  double t_assemble_ms, t_factor_ms, t_eigs_ms;  /* last call, device time     */
+} riga_stats_t;
+
+/* Build the discretisation and the nested-dissection plan on the host and
+ * allocate device storage on `device` (HIP ordinal).  hip_stream: a
+ * hipStream_t, or NULL for the default stream.  *out receives the handle.   */
+riga_status riga_create(riga_problem** out, const riga_mesh* mesh, int device, void* hip_stream);
+
+/* Sizes of the discretisation and of the factor plan (host output).          */
+riga_status riga_info(const riga_problem* h, riga_info_t* info);
+
+/* Assemble K, M and C on the device (Sec. 3.1; element integrals by the
+ * (p+1)^2-point Gauss rule).  Invalidates an existing factorization.         */
+riga_status riga_assemble(riga_problem* h, const riga_damping* damping);
+
+/* Copy one assembled matrix out in CSR form: which = 0 K, 1 M, 2 C.
+ *   rowptr: host, ndof+1 int64;  col: host, nnz int32;  val: device, nnz
+ *   doubles.  Rows are dofs, columns ascend within a row.  Any of the three
+ *   pointers may be NULL to skip it.                                         */
+riga_status riga_export_csr(riga_problem* h, int which, int64_t* rowptr, int32_t* col, double* val);
+
+/* Factor Q(sigma) = sigma^2 M + sigma C + K = L L^T (sigma > 0 makes Q SPD;
+ * Sec. 4.2 and line 2 of Alg. 2) by a multifrontal Cholesky over the
+ * nested-dissection tree whose separators are the rIGA hyperplanes.
+ * On RIGA_ERR_NOT_SPD, *bad_pivot (if not NULL) receives the dof whose pivot
+ * failed, else -1.                                                           */
+riga_status riga_factor(riga_problem* h, double sigma, int64_t* bad_pivot);
+
+/* x = Q(sigma)^{-1} b by the forward and backward sweeps of the factor
+ * (Sec. 5.2.2).  b, x: device, ndof x nrhs column-major, 1 <= nrhs <= 4;
+ * x may alias b.                                                             */
+riga_status riga_solve_q(riga_problem* h, int nrhs, const double* b, double* x);
+
+/* r = (A - sigma B)^{-1} B v for the companion pencil of eq. Linearization,
+ * applied blockwise as in eq. BlockOperatorVector:
+ *   r_u = -Q(sigma)^{-1} (sigma M v_u + C v_u + M v_l),  r_l = sigma r_u + v_u.
+ * v, r: device, 2*ndof x nvec column-major (upper half u, lower half l),
+ * 1 <= nvec <= 4; r must not alias v.                                        */
+riga_status riga_apply_op(riga_problem* h, int nvec, const double* v, double* r);
+
+/* The nev eigenpairs of the QEP nearest sigma (Alg. 2): block Krylov-Schur on
+ * the shift-and-invert operator with B-orthogonal (CGS2) bases.
+ *   lam: host, 2*nev doubles (re, im) in canonical order: increasing
+ *        |lam - sigma|, ties (relative 1e-9) by decreasing Im, then Re.
+ *   X:   device, ndof x nev complex (interleaved re, im), column k the
+ *        eigenvector of lam_k normalised to u^H M u = 1 with its largest
+ *        entry real positive; or NULL.
+ *   eta: host, nev scaled residuals
+ *        ||Q(lam)u|| / ((|lam|^2 ||M||_1 + |lam| ||C||_1 + ||K||_1) ||u||), or NULL.
+ *   nconv: host, number of converged pairs returned in order.
+ * RIGA_WARN_NOT_CONVERGED if maxit was reached first.                        */
+riga_status riga_eigs(riga_problem* h, const riga_options* opt, double* lam, double* X,
+                      double* eta, int* nconv);
+
+/* Operation counters of the cost model of Sec. 5.1 (eq. Cost) and phase times. */
+riga_status riga_stats(const riga_problem* h, riga_stats_t* stats);
+
+/* Host-only self-test of the dense small eigensolver used for the Ritz values
+ * (Rayleigh-Ritz on the projected matrix, eq. ArnoldiRitz): a is n x n real
+ * column-major (host); on return w holds the n eigenvalues (re, im pairs) and
+ * resid the max ||a y - w y|| / ||a|| over the computed eigenvectors.  Touches
+ * no device.                                                                 */
+riga_status riga_selftest_small_eig(int n, const double* a, double* w, double* resid);
+
+const char* riga_status_str(riga_status s);
+void riga_destroy(riga_problem* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RIGA_H */

@@ -1,0 +1,938 @@
+// C ABI of the solver and the host driver of the Krylov iteration.
+//
+// Everything that touches N-sized data runs in the device kernels; the host
+// keeps only the projected matrix (at most ~100 x 100) and the tree plan.
+#include "../../include/riga.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <functional>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "small_eig.hpp"
+
+using riga::cplx;
+
+namespace {
+
+struct HipError {
+  hipError_t e;
+};
+inline void ck(hipError_t e) {
+  if (e != hipSuccess) throw HipError{e};
+}
+
+// (p+1)-point Gauss--Legendre rule on [-1, 1]: Newton iteration on the
+// three-term Legendre recurrence started from the Chebyshev-like guesses.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0); w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = 0.0;
+      for (int k = 1; k <= n; ++k) {
+        double p2 = p1;
+        p1 = p0;
+        p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+      }
+      double dp = n * (z * p0 - p1) / (z * z - 1.0);
+      double dz = p0 / dp;
+      z -= dz;
+      if (std::abs(dz) < 1e-16) {
+        // final derivative at the converged node
+        p0 = 1.0; p1 = 0.0;
+        for (int k = 1; k <= n; ++k) {
+          double p2 = p1;
+          p1 = p0;
+          p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+        }
+        dp = n * (z * p0 - p1) / (z * z - 1.0);
+        break;
+      }
+    }
+    double p0 = 1.0, p1 = 0.0;
+    for (int k = 1; k <= n; ++k) {
+      double p2 = p1;
+      p1 = p0;
+      p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+    }
+    double dp = n * (z * p0 - p1) / (z * z - 1.0);
+    x[n - 1 - i] = z;
+    w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Canonical order of eigenvalues: increasing |lam - sigma|, clusters (relative
+// 1e-9) by decreasing Im, then increasing Re.
+std::vector<int> canonical_order(const std::vector<cplx>& lam, double sigma) {
+  std::vector<int> idx(lam.size());
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+    return std::abs(lam[a] - sigma) < std::abs(lam[b] - sigma);
+  });
+  std::vector<int> out;
+  size_t i = 0;
+  while (i < idx.size()) {
+    double d0 = std::abs(lam[idx[i]] - sigma);
+    size_t j = i + 1;
+    while (j < idx.size() && std::abs(lam[idx[j]] - sigma) - d0 <= 1e-9 * std::max(d0, 1e-300)) ++j;
+    std::vector<int> g(idx.begin() + i, idx.begin() + j);
+    std::stable_sort(g.begin(), g.end(), [&](int a, int b) {
+      if (lam[a].imag() != lam[b].imag()) return lam[a].imag() > lam[b].imag();
+      return lam[a].real() < lam[b].real();
+    });
+    out.insert(out.end(), g.begin(), g.end());
+    i = j;
+  }
+  return out;
+}
+
+}  // namespace
+
+struct riga_problem {
+  int device = 0;
+  hipStream_t st = nullptr;
+  riga_mesh mesh{};
+  riga::Plan plan;
+  std::vector<void*> allocs;
+  riga::DevSpace ds{};
+  riga::DevTree dt{};
+  int* d_level_nodes = nullptr;
+  double *d_gx = nullptr, *d_gw = nullptr, *d_tabM = nullptr, *d_tabK = nullptr;
+  double *d_K = nullptr, *d_M = nullptr, *d_C = nullptr;
+  double *d_L = nullptr, *d_U = nullptr, *d_upd = nullptr, *d_tmp = nullptr, *d_tmp2 = nullptr;
+  int64_t* d_status = nullptr;
+  double* d_part = nullptr;       // reduction scratch
+  unsigned* d_ticket = nullptr;
+  int64_t upd_len = 0;
+  bool assembled = false, factored = false;
+  double alpha = 0, beta = 0, sigma = 0;
+  const double* c_elem = nullptr;
+  double norms[3] = {-1, -1, -1};  // ||K||_1, ||C||_1, ||M||_1
+  riga_stats_t stats{};
+  // Krylov workspace
+  int64_t kw_cols = 0, kw_b = 0, kw_nev = 0;
+  double *Vu = nullptr, *Vl = nullptr, *Wl = nullptr, *Vu2 = nullptr, *Vl2 = nullptr, *Wl2 = nullptr;
+  double *Ru = nullptr, *Rl = nullptr, *MRl = nullptr, *Tv = nullptr, *Mvu = nullptr;
+  double *d_small = nullptr;      // device staging for h1, h2, G and small matrices
+  double *P = nullptr, *MP = nullptr, *CP = nullptr, *KP = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  template <class T>
+  T* dalloc(size_t count) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) throw std::bad_alloc();
+    allocs.push_back(p);
+    return (T*)p;
+  }
+  void dfree(void* p) {
+    if (!p) return;
+    auto it = std::find(allocs.begin(), allocs.end(), p);
+    if (it != allocs.end()) { hipFree(p); allocs.erase(it); }
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v) {
+    T* d = dalloc<T>(v.size());
+    if (!v.empty()) ck(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return d;
+  }
+  int64_t N() const { return plan.ndof; }
+};
+
+namespace {
+
+riga_status run(const std::function<riga_status()>& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return RIGA_ERR_OOM;
+  } catch (const HipError&) {
+    return RIGA_ERR_HIP;
+  }
+}
+
+// ---- forward / backward solve -------------------------------------------------
+void solve_levels(riga_problem* h, int nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
+                  double* r_l, const double* v_u, int64_t ldv, double sig) {
+  const riga::Plan& P = h->plan;
+  const int H = P.height;
+  for (int lv = 0; lv < H; ++lv) {
+    int a = P.level_off[lv], c = P.level_off[lv + 1] - a;
+    riga::launch_fwd_level(h->dt, h->d_level_nodes + a, c, nrhs, h->d_L, b, ldb, h->d_tmp, h->N(),
+                           h->d_upd, P.max_front, h->st);
+  }
+  for (int lv = H - 1; lv >= 0; --lv) {
+    int a = P.level_off[lv], c = P.level_off[lv + 1] - a;
+    riga::launch_bwd_level(h->dt, h->d_level_nodes + a, c, nrhs, h->d_L, h->d_tmp, h->N(), x, ldx,
+                           r_l, v_u, ldv, sig, P.max_front, h->st);
+  }
+}
+
+// S v for a block of `nb` vectors (eq. BlockOperatorVector):
+//   t = sigma M v_u + C v_u + (M v_l),   r_u = -Q^{-1} t,   r_l = sigma r_u + v_u,
+// with M v_l supplied (Wl) and M v_u returned in Mvu.
+void apply_block(riga_problem* h, int nb, const double* vu, const double* wl, int64_t ld,
+                 double* ru, double* rl, double* t, double* mvu) {
+  const int64_t N = h->N();
+  riga::launch_spmv(h->ds, N, nb, h->d_M, h->sigma, h->d_C, 1.0, nullptr, 0.0, vu, ld, t, N, wl, ld,
+                    1.0, mvu, N, h->st);
+  solve_levels(h, nb, t, N, ru, N, rl, vu, ld, h->sigma);
+}
+
+double host_norm1(riga_problem* h, const double* A) {
+  const int nblk = 512;
+  riga::launch_rowabs(h->plan.rowptr.empty() ? nullptr : h->ds.rowptr, h->N(), A, h->d_part, nblk, h->st);
+  std::vector<double> part(nblk);
+  ck(hipMemcpyAsync(part.data(), h->d_part, nblk * sizeof(double), hipMemcpyDeviceToHost, h->st));
+  ck(hipStreamSynchronize(h->st));
+  return *std::max_element(part.begin(), part.end());
+}
+
+void ensure_norms(riga_problem* h) {
+  if (h->norms[0] >= 0) return;
+  h->norms[0] = host_norm1(h, h->d_K);
+  h->norms[1] = host_norm1(h, h->d_C);
+  h->norms[2] = host_norm1(h, h->d_M);
+}
+
+void ensure_krylov(riga_problem* h, int cols, int b) {
+  if (h->kw_cols >= cols && h->kw_b >= b) return;
+  for (double* p : {h->Vu, h->Vl, h->Wl, h->Vu2, h->Vl2, h->Wl2, h->Ru, h->Rl, h->MRl, h->Tv, h->Mvu,
+                    h->d_small})
+    h->dfree(p);
+  const int64_t N = h->N();
+  cols = std::max<int>(cols, (int)h->kw_cols);
+  b = std::max<int>(b, (int)h->kw_b);
+  h->Vu = h->dalloc<double>(N * cols); h->Vl = h->dalloc<double>(N * cols); h->Wl = h->dalloc<double>(N * cols);
+  h->Vu2 = h->dalloc<double>(N * cols); h->Vl2 = h->dalloc<double>(N * cols); h->Wl2 = h->dalloc<double>(N * cols);
+  h->Ru = h->dalloc<double>(N * b); h->Rl = h->dalloc<double>(N * b); h->MRl = h->dalloc<double>(N * b);
+  h->Tv = h->dalloc<double>(N * b); h->Mvu = h->dalloc<double>(N * b);
+  h->d_small = h->dalloc<double>((size_t)4 * cols * cols + 64);
+  h->kw_cols = cols; h->kw_b = b;
+}
+
+void ensure_post(riga_problem* h, int nev) {
+  if (h->kw_nev >= nev) return;
+  for (double* p : {h->P, h->MP, h->CP, h->KP}) h->dfree(p);
+  const int64_t N = h->N();
+  h->P = h->dalloc<double>(N * 2 * nev); h->MP = h->dalloc<double>(N * 2 * nev);
+  h->CP = h->dalloc<double>(N * 2 * nev); h->KP = h->dalloc<double>(N * 2 * nev);
+  h->kw_nev = nev;
+}
+
+// Cholesky of a small SPD b x b matrix G = R^T R (R upper, column-major).
+// Returns the index of the first failing pivot, or -1.
+int small_chol(int b, const std::vector<double>& G, std::vector<double>& R, double rel) {
+  R.assign((size_t)b * b, 0.0);
+  for (int j = 0; j < b; ++j) {
+    for (int i = 0; i <= j; ++i) {
+      double s = G[i + (size_t)j * b];
+      for (int k = 0; k < i; ++k) s -= R[k + (size_t)i * b] * R[k + (size_t)j * b];
+      if (i == j) {
+        if (!(s > rel * G[j + (size_t)j * b]) || !(s > 0)) return j;
+        R[j + (size_t)j * b] = std::sqrt(s);
+      } else {
+        R[i + (size_t)j * b] = s / R[i + (size_t)i * b];
+      }
+    }
+  }
+  return -1;
+}
+
+std::vector<double> upper_inverse(int b, const std::vector<double>& R) {
+  std::vector<double> X((size_t)b * b, 0.0);
+  for (int j = 0; j < b; ++j) {
+    X[j + (size_t)j * b] = 1.0 / R[j + (size_t)j * b];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int k = i + 1; k <= j; ++k) s += R[i + (size_t)k * b] * X[k + (size_t)j * b];
+      X[i + (size_t)j * b] = -s / R[i + (size_t)i * b];
+    }
+  }
+  return X;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* riga_status_str(riga_status s) {
+  switch (s) {
+    case RIGA_OK: return "ok";
+    case RIGA_ERR_INVALID_ARG: return "invalid argument";
+    case RIGA_ERR_NOT_SPD: return "Q(sigma) is not positive definite";
+    case RIGA_ERR_HIP: return "HIP runtime error";
+    case RIGA_ERR_OOM: return "out of device memory";
+    case RIGA_ERR_STATE: return "call out of order";
+    case RIGA_WARN_NOT_CONVERGED: return "not all requested eigenpairs converged";
+  }
+  return "unknown status";
+}
+
+riga_status riga_create(riga_problem** out, const riga_mesh* mesh, int device, void* hip_stream) {
+  if (!out || !mesh) return RIGA_ERR_INVALID_ARG;
+  *out = nullptr;
+  riga_problem* h = new (std::nothrow) riga_problem();
+  if (!h) return RIGA_ERR_OOM;
+  h->mesh = *mesh;
+  if (h->plan.build(mesh->p, mesh->ne, mesh->hyper_every, mesh->leaf) != 0) {
+    delete h;
+    return RIGA_ERR_INVALID_ARG;
+  }
+  riga_status rc = run([&]() -> riga_status {
+    ck(hipSetDevice(device));
+    h->device = device;
+    h->st = (hipStream_t)hip_stream;
+    const riga::Plan& P = h->plan;
+    const riga::Space1D& S = P.sp;
+    h->ds.p = S.p; h->ds.ne = S.ne; h->ds.n = S.n;
+    h->ds.knots = h->upload(S.knots);
+    h->ds.sup0 = h->upload(S.sup0); h->ds.sup1 = h->upload(S.sup1);
+    h->ds.lo = h->upload(S.lo); h->ds.hi = h->upload(S.hi);
+    h->ds.first = h->upload(S.first);
+    h->ds.rowptr = h->upload(P.rowptr);
+    h->dt.nf = h->upload(P.nf); h->dt.no = h->upload(P.no); h->dt.nb = h->upload(P.nb);
+    h->dt.loff = h->upload(P.loff); h->dt.uoff = h->upload(P.uoff);
+    h->dt.foff = h->upload(P.foff); h->dt.fdofs = h->upload(P.fdofs);
+    h->dt.fkey = h->upload(P.fkey); h->dt.fpos = h->upload(P.fpos);
+    h->dt.coff = h->upload(P.coff); h->dt.clist = h->upload(P.clist);
+    h->dt.moff = h->upload(P.moff); h->dt.maps = h->upload(P.maps);
+    std::vector<int> voff(P.nb.size() + 1, 0);
+    for (size_t v = 0; v < P.nb.size(); ++v) voff[v + 1] = voff[v] + P.nb[v];
+    h->upd_len = voff.back();
+    h->dt.voff = h->upload(voff);
+    h->d_level_nodes = h->upload(P.level_nodes);
+    std::vector<double> gx, gw;
+    gauss_legendre(S.p + 1, gx, gw);
+    h->d_gx = h->upload(gx); h->d_gw = h->upload(gw);
+    const int np = S.p + 1;
+    h->d_tabM = h->dalloc<double>((size_t)S.ne * np * np);
+    h->d_tabK = h->dalloc<double>((size_t)S.ne * np * np);
+    h->d_K = h->dalloc<double>(P.nnz); h->d_M = h->dalloc<double>(P.nnz); h->d_C = h->dalloc<double>(P.nnz);
+    h->d_L = h->dalloc<double>(P.lsize); h->d_U = h->dalloc<double>(P.usize);
+    h->d_upd = h->dalloc<double>((size_t)h->upd_len * 4);
+    h->d_tmp = h->dalloc<double>((size_t)P.ndof * 4);
+    h->d_tmp2 = h->dalloc<double>((size_t)P.ndof * 4);
+    h->d_status = h->dalloc<int64_t>(1);
+    h->d_part = h->dalloc<double>((size_t)512 * 400 * 4 + 64);
+    h->d_ticket = h->dalloc<unsigned>(4);
+    ck(hipMemset(h->d_ticket, 0, 4 * sizeof(unsigned)));
+    ck(hipEventCreate(&h->ev0));
+    ck(hipEventCreate(&h->ev1));
+    return RIGA_OK;
+  });
+  if (rc != RIGA_OK) {
+    riga_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return RIGA_OK;
+}
+
+void riga_destroy(riga_problem* h) {
+  if (!h) return;
+  hipSetDevice(h->device);
+  if (h->st) hipStreamSynchronize(h->st); else hipDeviceSynchronize();
+  for (void* p : h->allocs) hipFree(p);
+  if (h->ev0) hipEventDestroy(h->ev0);
+  if (h->ev1) hipEventDestroy(h->ev1);
+  delete h;
+}
+
+riga_status riga_info(const riga_problem* h, riga_info_t* info) {
+  if (!h || !info) return RIGA_ERR_INVALID_ARG;
+  const riga::Plan& P = h->plan;
+  info->n1d = P.n1d;
+  info->ndof = P.ndof;
+  info->nnz = P.nnz;
+  info->nnodes = (int64_t)P.nodes.size();
+  info->nleaves = P.level_off.size() > 1 ? P.level_off[1] : 0;
+  info->height = P.height;
+  info->max_front = P.max_front;
+  info->leaf_own = P.max_own;
+  info->factor_entries = P.lsize;
+  info->factor_flops_dense = P.flops_dense;
+  info->solve_bytes = P.solve_bytes;
+  return RIGA_OK;
+}
+
+riga_status riga_assemble(riga_problem* h, const riga_damping* damping) {
+  if (!h || !damping) return RIGA_ERR_INVALID_ARG;
+  return run([&]() -> riga_status {
+    ck(hipSetDevice(h->device));
+    ck(hipEventRecord(h->ev0, h->st));
+    riga::launch_bspline_tables(h->ds, h->d_gx, h->d_gw, h->d_tabM, h->d_tabK, h->st);
+    riga::launch_assemble(h->ds, h->d_tabM, h->d_tabK, damping->alpha, damping->beta, damping->c_elem,
+                          h->d_K, h->d_M, h->d_C, h->N(), h->st);
+    ck(hipGetLastError());
+    ck(hipEventRecord(h->ev1, h->st));
+    h->alpha = damping->alpha; h->beta = damping->beta; h->c_elem = damping->c_elem;
+    h->assembled = true;
+    h->factored = false;
+    h->norms[0] = h->norms[1] = h->norms[2] = -1;
+    h->stats.t_assemble_ms = -1;  // resolved lazily (the call does not synchronise)
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_export_csr(riga_problem* h, int which, int64_t* rowptr, int32_t* col, double* val) {
+  if (!h || which < 0 || which > 2) return RIGA_ERR_INVALID_ARG;
+  if (val && !h->assembled) return RIGA_ERR_STATE;
+  return run([&]() -> riga_status {
+    const riga::Plan& P = h->plan;
+    const riga::Space1D& S = P.sp;
+    if (rowptr) std::memcpy(rowptr, P.rowptr.data(), (P.ndof + 1) * sizeof(int64_t));
+    if (col) {
+      const int n = S.n;
+      int64_t k = 0;
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i)
+          for (int jj = S.lo[j]; jj <= S.hi[j]; ++jj)
+            for (int ii = S.lo[i]; ii <= S.hi[i]; ++ii) col[k++] = jj * n + ii;
+    }
+    if (val) {
+      const double* src = which == 0 ? h->d_K : which == 1 ? h->d_M : h->d_C;
+      ck(hipMemcpyAsync(val, src, P.nnz * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+    }
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_factor(riga_problem* h, double sigma, int64_t* bad_pivot) {
+  if (bad_pivot) *bad_pivot = -1;
+  if (!h || !(sigma > 0.0) || !std::isfinite(sigma)) return RIGA_ERR_INVALID_ARG;
+  if (!h->assembled) return RIGA_ERR_STATE;
+  return run([&]() -> riga_status {
+    ck(hipSetDevice(h->device));
+    const riga::Plan& P = h->plan;
+    ck(hipMemsetAsync(h->d_status, 0xFF, sizeof(int64_t), h->st));
+    ck(hipEventRecord(h->ev0, h->st));
+    for (int lv = 0; lv < P.height; ++lv) {
+      int a = P.level_off[lv], c = P.level_off[lv + 1] - a;
+      riga::launch_front_factor(h->ds, h->dt, h->d_level_nodes + a, c, sigma * sigma, sigma, h->d_K, h->d_M,
+                                h->d_C, h->d_L, h->d_U, h->d_status, h->st);
+    }
+    ck(hipGetLastError());
+    ck(hipEventRecord(h->ev1, h->st));
+    int64_t stat = -1;
+    ck(hipMemcpyAsync(&stat, h->d_status, sizeof(int64_t), hipMemcpyDeviceToHost, h->st));
+    ck(hipStreamSynchronize(h->st));
+    float ms = 0;
+    ck(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    h->stats.t_factor_ms = ms;
+    if (stat >= 0) {
+      if (bad_pivot) *bad_pivot = stat;
+      h->factored = false;
+      return RIGA_ERR_NOT_SPD;
+    }
+    h->sigma = sigma;
+    h->factored = true;
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_solve_q(riga_problem* h, int nrhs, const double* b, double* x) {
+  if (!h || nrhs < 1 || nrhs > 4 || !b || !x) return RIGA_ERR_INVALID_ARG;
+  if (!h->factored) return RIGA_ERR_STATE;
+  return run([&]() -> riga_status {
+    ck(hipSetDevice(h->device));
+    solve_levels(h, nrhs, b, h->N(), x, h->N(), nullptr, nullptr, 0, 0.0);
+    ck(hipGetLastError());
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_apply_op(riga_problem* h, int nvec, const double* v, double* r) {
+  if (!h || nvec < 1 || nvec > 4 || !v || !r || v == r) return RIGA_ERR_INVALID_ARG;
+  if (!h->factored) return RIGA_ERR_STATE;
+  return run([&]() -> riga_status {
+    ck(hipSetDevice(h->device));
+    const int64_t N = h->N();
+    // M v_l into tmp2, then the common block operator
+    riga::launch_spmv(h->ds, N, nvec, h->d_M, 1.0, nullptr, 0.0, nullptr, 0.0, v + N, 2 * N, h->d_tmp2, N,
+                      nullptr, 0, 0.0, nullptr, 0, h->st);
+    double* t = r + N;  // r_l doubles as scratch for t until the backward sweep writes it
+    double* mvu = h->d_upd;  // unused here; Y2 not requested
+    (void)mvu;
+    riga::launch_spmv(h->ds, N, nvec, h->d_M, h->sigma, h->d_C, 1.0, nullptr, 0.0, v, 2 * N, t, 2 * N,
+                      h->d_tmp2, N, 1.0, nullptr, 0, h->st);
+    solve_levels(h, nvec, t, 2 * N, r, 2 * N, r + N, v, 2 * N, h->sigma);
+    ck(hipGetLastError());
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_stats(const riga_problem* h, riga_stats_t* stats) {
+  if (!h || !stats) return RIGA_ERR_INVALID_ARG;
+  *stats = h->stats;
+  return RIGA_OK;
+}
+
+riga_status riga_selftest_small_eig(int n, const double* a, double* w, double* resid) {
+  if (n < 1 || !a || !w) return RIGA_ERR_INVALID_ARG;
+  std::vector<cplx> T, Z, Y;
+  if (riga::schur_complex(n, a, T, Z) != 0) return RIGA_WARN_NOT_CONVERGED;
+  riga::schur_eigvecs(n, T, Z, Y, 1e-12);
+  double an = 0.0;
+  for (int i = 0; i < n * n; ++i) an = std::max(an, std::abs(a[i]));
+  double worst = 0.0;
+  for (int k = 0; k < n; ++k) {
+    cplx lam = T[k + (size_t)k * n];
+    w[2 * k] = lam.real();
+    w[2 * k + 1] = lam.imag();
+    for (int i = 0; i < n; ++i) {
+      cplx s = 0.0;
+      for (int j = 0; j < n; ++j) s += a[i + (size_t)j * n] * Y[j + (size_t)k * n];
+      worst = std::max(worst, std::abs(s - lam * Y[i + (size_t)k * n]) / std::max(an, 1e-300));
+    }
+  }
+  if (resid) *resid = worst;
+  return RIGA_OK;
+}
+
+}  // extern "C"
+
+// =============================================================================
+// Block Krylov--Schur on S = L(sigma)^{-1} B (Sec. 4.1.2-4.1.3, Alg. 2).
+//
+// Basis V = [V_u; V_l] is B-orthonormal, B = diag(I, M); W_l = M V_l is kept
+// beside it so that every B-inner product costs no extra sparse product:
+//   <x, y>_B = x_u^T y_u + x_l^T M y_l = x_u^T y_u + (M x_l)^T y_l.
+// The Krylov decomposition is S V_k = V_{k+b} H, with H (k+b) x k.
+// =============================================================================
+namespace {
+
+struct KrylovRun {
+  riga_problem* h;
+  int64_t N;
+  int b, m, nev, maxit, ldh;
+  double tol;
+  std::vector<double> H;   // ldh x ldh, column-major
+  int k = 0;               // processed columns
+  int64_t n_fb = 0, n_mv = 0, n_vv = 0;
+
+  double& Hat(int r, int c) { return H[r + (size_t)c * ldh]; }
+
+  // B-orthonormalise the block (Ru, Rl, MRl = M Rl) against V[:, 0:nc] by
+  // classical Gram--Schmidt applied twice (the coefficients of both passes
+  // are summed into hsum, nc x b) and write it to V[:, nc:nc+b] so that
+  //   block = V[:, 0:nc] hsum + V[:, nc:nc+b] R.
+  // R comes from a Cholesky factorisation of the b x b B-Gram matrix of the
+  // projected block.  If the block has lost rank (a column lies in the span of
+  // V: an invariant subspace was found), a pivoted factorisation keeps the r
+  // independent combinations; the remaining b - r columns of the new block are
+  // random directions B-orthogonal to everything, and their rows of R are zero.
+  void project(int nc, int nq, double* ru, double* rl, double* mrl, double* dh, std::vector<double>* hsum) {
+    const int64_t n = N;
+    for (int pass = 0; pass < 2; ++pass) {
+      riga::launch_dots(n, nc, h->Vu, h->Wl, n, nq, ru, rl, n, h->d_part, h->d_ticket, dh + (size_t)pass * ldh * b,
+                        h->st);
+      riga::launch_cgs_update(n, nc, nq, dh + (size_t)pass * ldh * b, h->Vu, ru, h->Vl, rl, h->Wl, mrl, n, n, h->st);
+    }
+    n_vv += 8LL * nc * nq;
+    if (hsum) {
+      std::vector<double> host((size_t)2 * ldh * b);
+      ck(hipMemcpyAsync(host.data(), dh, host.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
+      ck(hipStreamSynchronize(h->st));
+      hsum->assign((size_t)nc * nq, 0.0);
+      for (int c = 0; c < nc; ++c)
+        for (int q = 0; q < nq; ++q)
+          (*hsum)[c + (size_t)q * nc] = host[(size_t)c * nq + q] + host[(size_t)ldh * b + (size_t)c * nq + q];
+    }
+  }
+
+  std::vector<double> gram(int nq, double* ru, double* rl, double* mrl) {
+    double* dG = h->d_small + (size_t)2 * ldh * b;
+    riga::launch_dots(N, nq, ru, mrl, N, nq, ru, rl, N, h->d_part, h->d_ticket, dG, h->st);
+    n_vv += 2LL * nq * nq;
+    std::vector<double> G((size_t)nq * nq);
+    ck(hipMemcpyAsync(G.data(), dG, G.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    ck(hipStreamSynchronize(h->st));
+    for (int c = 0; c < nq; ++c)       // symmetrise the two half-sums
+      for (int q = c + 1; q < nq; ++q) {
+        double v = 0.5 * (G[c + (size_t)q * nq] + G[q + (size_t)c * nq]);
+        G[c + (size_t)q * nq] = G[q + (size_t)c * nq] = v;
+      }
+    return G;
+  }
+
+  // Out columns = In (N x kin) times Qm (kin x kout), for the u, l and M l parts.
+  void combine(const double* iu, const double* il, const double* iml, int kin, const std::vector<double>& Qm,
+               int kout, int dst) {
+    double* dQ = h->d_small + (size_t)2 * ldh * b + 32;
+    ck(hipMemcpyAsync(dQ, Qm.data(), Qm.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
+    const size_t o = (size_t)dst * N;
+    riga::launch_gemm_tall(N, iu, N, kin, dQ, kout, h->Vu + o, 1, N, h->st);
+    riga::launch_gemm_tall(N, il, N, kin, dQ, kout, h->Vl + o, 1, N, h->st);
+    riga::launch_gemm_tall(N, iml, N, kin, dQ, kout, h->Wl + o, 1, N, h->st);
+    ck(hipStreamSynchronize(h->st));  // dQ is host-staged again by the next call
+  }
+
+  void orthonormalize(int nc, std::vector<double>& hsum, std::vector<double>& R, uint64_t seed) {
+    double* dh = h->d_small;
+    if (nc > 0) project(nc, b, h->Ru, h->Rl, h->MRl, dh, &hsum);
+    else hsum.clear();
+    std::vector<double> G = gram(b, h->Ru, h->Rl, h->MRl);
+    // squared B-norm of each column before the projection (Pythagoras)
+    std::vector<double> n0(b);
+    for (int q = 0; q < b; ++q) {
+      double s = G[q + (size_t)q * b];
+      for (int c = 0; c < nc; ++c) s += hsum[c + (size_t)q * nc] * hsum[c + (size_t)q * nc];
+      n0[q] = s;
+    }
+    const double brk = 1e-24;  // (1e-12)^2: relative size of a column that counts as lost
+    // Cholesky with symmetric pivoting on the largest remaining diagonal
+    std::vector<double> A = G;
+    std::vector<int> piv(b);
+    std::iota(piv.begin(), piv.end(), 0);
+    R.assign((size_t)b * b, 0.0);
+    int r = 0;
+    std::vector<double> Rp((size_t)b * b, 0.0);  // in pivoted column order
+    for (int j = 0; j < b; ++j) {
+      int best = j;
+      for (int c = j + 1; c < b; ++c)
+        if (A[c + (size_t)c * b] / n0[piv[c]] > A[best + (size_t)best * b] / n0[piv[best]]) best = c;
+      if (!(A[best + (size_t)best * b] > brk * n0[piv[best]])) break;
+      if (best != j) {
+        std::swap(piv[j], piv[best]);
+        for (int c = 0; c < b; ++c) std::swap(A[j + (size_t)c * b], A[best + (size_t)c * b]);
+        for (int c = 0; c < b; ++c) std::swap(A[c + (size_t)j * b], A[c + (size_t)best * b]);
+        for (int c = 0; c < j; ++c) std::swap(Rp[c + (size_t)j * b], Rp[c + (size_t)best * b]);
+      }
+      double d = std::sqrt(A[j + (size_t)j * b]);
+      Rp[j + (size_t)j * b] = d;
+      for (int c = j + 1; c < b; ++c) Rp[j + (size_t)c * b] = A[j + (size_t)c * b] / d;
+      for (int c = j + 1; c < b; ++c)
+        for (int q = j + 1; q < b; ++q) A[c + (size_t)q * b] -= Rp[j + (size_t)c * b] * Rp[j + (size_t)q * b];
+      ++r;
+    }
+    // new basis columns nc .. nc+r-1 = block[:, piv[0:r]] R11^{-1}
+    if (r > 0) {
+      std::vector<double> R11((size_t)r * r);
+      for (int c = 0; c < r; ++c)
+        for (int q = 0; q < r; ++q) R11[c + (size_t)q * r] = Rp[c + (size_t)q * b];
+      std::vector<double> Ri = upper_inverse(r, R11);
+      std::vector<double> Qm((size_t)b * r, 0.0);
+      for (int c = 0; c < r; ++c)
+        for (int j = 0; j < r; ++j) Qm[piv[c] + (size_t)j * b] = Ri[c + (size_t)j * r];
+      combine(h->Ru, h->Rl, h->MRl, b, Qm, r, nc);
+    }
+    // R[c][q] = Rp[c][position of q]: block column q = sum_c newV_c R[c][q]
+    for (int pos = 0; pos < b; ++pos)
+      for (int c = 0; c < r; ++c) R[c + (size_t)piv[pos] * b] = Rp[c + (size_t)pos * b];
+    if (r < b) {
+      // fresh random directions, B-orthogonal to V[:, 0:nc+r]
+      const int nf = b - r;
+      riga::launch_random_fill(h->Ru, N, nf, N, seed * 7919u + 17u, h->st);
+      riga::launch_random_fill(h->Rl, N, nf, N, seed * 7919u + 29u, h->st);
+      riga::launch_spmv(h->ds, N, nf, h->d_M, 1.0, nullptr, 0, nullptr, 0, h->Rl, N, h->MRl, N, nullptr, 0, 0.0,
+                        nullptr, 0, h->st);
+      project(nc + r, nf, h->Ru, h->Rl, h->MRl, dh, nullptr);
+      std::vector<double> Gf = gram(nf, h->Ru, h->Rl, h->MRl);
+      std::vector<double> Rf;
+      small_chol(nf, Gf, Rf, 0.0);
+      combine(h->Ru, h->Rl, h->MRl, nf, upper_inverse(nf, Rf), nf, nc + r);
+    }
+  }
+
+  void step(uint64_t seed) {
+    const int64_t n = N;
+    const size_t o = (size_t)k * n;
+    apply_block(h, b, h->Vu + o, h->Wl + o, n, h->Ru, h->Rl, h->Tv, h->Mvu);
+    // M r_l = sigma M r_u + M v_u
+    riga::launch_spmv(h->ds, n, b, h->d_M, h->sigma, nullptr, 0, nullptr, 0, h->Ru, n, h->MRl, n, h->Mvu, n,
+                      1.0, nullptr, 0, h->st);
+    n_fb += b;
+    n_mv += 3LL * b;
+    std::vector<double> hs, R;
+    const int nc = k + b;
+    orthonormalize(nc, hs, R, seed);
+    for (int q = 0; q < b; ++q) {
+      for (int c = 0; c < nc; ++c) Hat(c, k + q) = hs[c + (size_t)q * nc];
+      for (int c = 0; c < b; ++c) Hat(nc + c, k + q) = R[c + (size_t)q * b];
+    }
+    k += b;
+  }
+};
+
+}  // namespace
+
+extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, double* lam, double* X,
+                                 double* eta, int* nconv) {
+  if (!h || !opt || !lam) return RIGA_ERR_INVALID_ARG;
+  if (!h->factored) return RIGA_ERR_STATE;
+  const int64_t N = h->N();
+  const int nev = opt->nev;
+  const int b = opt->block > 0 ? opt->block : 2;
+  int m = opt->m > 0 ? opt->m : std::max(2 * nev, 20);
+  const int maxit = opt->maxit > 0 ? opt->maxit : 200;
+  const double tol = opt->tol > 0 ? opt->tol : 1e-12;
+  if (nev < 1 || b < 1 || b > 4 || (int64_t)nev >= 2 * N) return RIGA_ERR_INVALID_ARG;
+  if ((int64_t)m > 2 * N) m = (int)(2 * N);
+  if (m < nev + b || m + b > 400) return RIGA_ERR_INVALID_ARG;
+  return run([&]() -> riga_status {
+    ck(hipSetDevice(h->device));
+    ensure_norms(h);
+    const int ldh = m + 2 * b;
+    ensure_krylov(h, ldh, b);
+    ck(hipEventRecord(h->ev0, h->st));
+    KrylovRun kr{h, N, b, m, nev, maxit, ldh, tol};
+    kr.H.assign((size_t)ldh * ldh, 0.0);
+    // start block, B-orthonormalised
+    if (opt->v0) {
+      for (int q = 0; q < b; ++q) {
+        ck(hipMemcpyAsync(h->Ru + (size_t)q * N, opt->v0 + (size_t)q * 2 * N, N * sizeof(double),
+                          hipMemcpyDeviceToDevice, h->st));
+        ck(hipMemcpyAsync(h->Rl + (size_t)q * N, opt->v0 + (size_t)q * 2 * N + N, N * sizeof(double),
+                          hipMemcpyDeviceToDevice, h->st));
+      }
+    } else {
+      riga::launch_random_fill(h->Ru, N, b, N, opt->seed * 2 + 1, h->st);
+      riga::launch_random_fill(h->Rl, N, b, N, opt->seed * 2 + 2, h->st);
+    }
+    riga::launch_spmv(h->ds, N, b, h->d_M, 1.0, nullptr, 0, nullptr, 0, h->Rl, N, h->MRl, N, nullptr, 0, 0.0,
+                      nullptr, 0, h->st);
+    {
+      std::vector<double> hs, R;
+      kr.orthonormalize(0, hs, R, opt->seed + 99);
+    }
+    kr.k = 0;
+    int it = 0;
+    bool converged = false;
+    std::vector<cplx> T, Z, Y;
+    std::vector<int> wanted;
+    std::vector<cplx> theta;
+    uint64_t step_seed = opt->seed * 1000003u + 5;
+    for (;;) {
+      while (kr.k + b <= m) kr.step(step_seed++);
+      const int k = kr.k;
+      // Rayleigh--Ritz on H_k (eq. ArnoldiRitz)
+      std::vector<double> Hk((size_t)k * k);
+      for (int c = 0; c < k; ++c)
+        for (int r = 0; r < k; ++r) Hk[r + (size_t)c * k] = kr.Hat(r, c);
+      if (riga::schur_complex(k, Hk.data(), T, Z) != 0) throw HipError{hipErrorUnknown};
+      theta.resize(k);
+      for (int i = 0; i < k; ++i) theta[i] = T[i + (size_t)i * k];
+      // sort by |theta| descending (= |lam - sigma| ascending), clusters kept together
+      std::vector<int> ord(k);
+      std::iota(ord.begin(), ord.end(), 0);
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return std::abs(theta[a]) > std::abs(theta[c]); });
+      auto cluster_end = [&](int pos) {  // extend pos to the end of its |theta| cluster
+        while (pos < k && std::abs(std::abs(theta[ord[pos]]) - std::abs(theta[ord[pos - 1]])) <=
+                              1e-9 * std::abs(theta[ord[pos - 1]]))
+          ++pos;
+        return pos;
+      };
+      int nw = cluster_end(std::min(nev, k));
+      // Ritz vectors and residual estimates ||E y|| (E = rows k..k+b of H)
+      riga::schur_eigvecs(k, T, Z, Y, 1e-11);
+      std::vector<double> res(k);
+      for (int i = 0; i < k; ++i) {
+        double s = 0.0;
+        for (int r = 0; r < b; ++r) {
+          cplx acc = 0.0;
+          for (int c = 0; c < k; ++c) acc += kr.Hat(k + r, c) * Y[c + (size_t)i * k];
+          s += std::norm(acc);
+        }
+        res[i] = std::sqrt(s);
+      }
+      int nc = 0;
+      for (int p = 0; p < nw; ++p)
+        if (res[ord[p]] <= tol * std::abs(theta[ord[p]])) ++nc;
+      ++it;
+      if (nc == nw) { converged = true; wanted.assign(ord.begin(), ord.begin() + nw); break; }
+      if (it >= maxit) { wanted.assign(ord.begin(), ord.begin() + nw); break; }
+      // --- Krylov--Schur restart: keep the nearest Ritz values ------------------
+      int kk = nev + (k - nev) / 2;
+      kk = std::min(kk, m - b);
+      kk = std::max(kk, std::min(nw, m - b));
+      int kend = cluster_end(std::max(1, kk));
+      if (kend + b <= m) kk = kend;
+      else {  // step back to a cluster boundary
+        while (kk > 1 && std::abs(std::abs(theta[ord[kk]]) - std::abs(theta[ord[kk - 1]])) <=
+                             1e-9 * std::abs(theta[ord[kk - 1]]))
+          --kk;
+      }
+      std::vector<int> keep(ord.begin(), ord.begin() + kk);
+      riga::schur_reorder(k, T, Z, keep);
+      std::vector<double> Qk;
+      int r = riga::realify(k, kk, Z, Qk);
+      // T_new = Qk^T H_k Qk, E_new = E Qk
+      std::vector<double> HQ((size_t)k * r, 0.0), Tn((size_t)r * r, 0.0), En((size_t)b * r, 0.0);
+      for (int c = 0; c < r; ++c)
+        for (int t2 = 0; t2 < k; ++t2) {
+          double q = Qk[t2 + (size_t)c * k];
+          if (q == 0.0) continue;
+          for (int rr = 0; rr < k; ++rr) HQ[rr + (size_t)c * k] += Hk[rr + (size_t)t2 * k] * q;
+        }
+      for (int c = 0; c < r; ++c)
+        for (int rr = 0; rr < r; ++rr) {
+          double s = 0.0;
+          for (int t2 = 0; t2 < k; ++t2) s += Qk[t2 + (size_t)rr * k] * HQ[t2 + (size_t)c * k];
+          Tn[rr + (size_t)c * r] = s;
+        }
+      for (int c = 0; c < r; ++c)
+        for (int rr = 0; rr < b; ++rr) {
+          double s = 0.0;
+          for (int t2 = 0; t2 < k; ++t2) s += kr.Hat(k + rr, t2) * Qk[t2 + (size_t)c * k];
+          En[rr + (size_t)c * b] = s;
+        }
+      // V_new = [V_k Qk, V_{k:k+b}] in the alternate buffers
+      const int kin = k + b, kout = r + b;
+      std::vector<double> Qe((size_t)kin * kout, 0.0);
+      for (int c = 0; c < r; ++c)
+        for (int t2 = 0; t2 < k; ++t2) Qe[t2 + (size_t)c * kin] = Qk[t2 + (size_t)c * k];
+      for (int q = 0; q < b; ++q) Qe[(k + q) + (size_t)(r + q) * kin] = 1.0;
+      double* dQ = h->d_small;
+      ck(hipMemcpyAsync(dQ, Qe.data(), Qe.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
+      riga::launch_gemm_tall(N, h->Vu, N, kin, dQ, kout, h->Vu2, 1, N, h->st);
+      riga::launch_gemm_tall(N, h->Vl, N, kin, dQ, kout, h->Vl2, 1, N, h->st);
+      riga::launch_gemm_tall(N, h->Wl, N, kin, dQ, kout, h->Wl2, 1, N, h->st);
+      ck(hipStreamSynchronize(h->st));
+      std::swap(h->Vu, h->Vu2); std::swap(h->Vl, h->Vl2); std::swap(h->Wl, h->Wl2);
+      std::fill(kr.H.begin(), kr.H.end(), 0.0);
+      for (int c = 0; c < r; ++c) {
+        for (int rr = 0; rr < r; ++rr) kr.Hat(rr, c) = Tn[rr + (size_t)c * r];
+        for (int rr = 0; rr < b; ++rr) kr.Hat(r + rr, c) = En[rr + (size_t)c * b];
+      }
+      kr.k = r;
+    }
+    // --- eigenpairs: u = V_u y for the wanted Ritz vectors --------------------------
+    const int k = kr.k;
+    const int nw = (int)wanted.size();
+    std::vector<double> Yr((size_t)k * nw), Yi((size_t)k * nw);
+    for (int j = 0; j < nw; ++j)
+      for (int c = 0; c < k; ++c) {
+        cplx y = Y[c + (size_t)wanted[j] * k];
+        Yr[c + (size_t)j * k] = y.real();
+        Yi[c + (size_t)j * k] = y.imag();
+      }
+    ensure_post(h, nw);
+    double* dQ = h->d_small;
+    ck(hipMemcpyAsync(dQ, Yr.data(), Yr.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
+    riga::launch_gemm_tall(N, h->Vu, N, k, dQ, nw, h->P, 1, N, h->st);
+    ck(hipStreamSynchronize(h->st));
+    ck(hipMemcpyAsync(dQ, Yi.data(), Yi.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
+    riga::launch_gemm_tall(N, h->Vu, N, k, dQ, nw, h->P + (size_t)nw * N, 1, N, h->st);
+    // M, C, K times the planar real and imaginary parts
+    for (int c0 = 0; c0 < 2 * nw; c0 += 8) {
+      int nc = std::min(8, 2 * nw - c0);
+      const double* x = h->P + (size_t)c0 * N;
+      riga::launch_spmv(h->ds, N, nc, h->d_M, 1.0, nullptr, 0, nullptr, 0, x, N, h->MP + (size_t)c0 * N, N,
+                        nullptr, 0, 0.0, nullptr, 0, h->st);
+      riga::launch_spmv(h->ds, N, nc, h->d_C, 1.0, nullptr, 0, nullptr, 0, x, N, h->CP + (size_t)c0 * N, N,
+                        nullptr, 0, 0.0, nullptr, 0, h->st);
+      riga::launch_spmv(h->ds, N, nc, h->d_K, 1.0, nullptr, 0, nullptr, 0, x, N, h->KP + (size_t)c0 * N, N,
+                        nullptr, 0, 0.0, nullptr, 0, h->st);
+    }
+    const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, N / 4096));
+    riga::launch_pair_forms(N, nw, h->P, h->MP, h->CP, h->KP, N, h->d_part, nsplit, h->st);
+    std::vector<double> part((size_t)nw * nsplit * 11);
+    ck(hipMemcpyAsync(part.data(), h->d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    ck(hipStreamSynchronize(h->st));
+    std::vector<cplx> lam_rq(nw);
+    std::vector<double> uMu(nw), unorm2(nw);
+    for (int j = 0; j < nw; ++j) {
+      double f[11] = {0};
+      for (int x = 0; x < nsplit; ++x)
+        for (int t2 = 0; t2 < 11; ++t2) f[t2] += part[((size_t)j * nsplit + x) * 11 + t2];
+      // unconjugated forms u^T A u = a^T A a - b^T A b + 2i a^T A b
+      cplx qm(f[0] - f[1], 2 * f[2]), qc(f[3] - f[4], 2 * f[5]), qk(f[6] - f[7], 2 * f[8]);
+      uMu[j] = f[0] + f[1];
+      unorm2[j] = f[9] + f[10];
+      cplx ritz = h->sigma + 1.0 / theta[wanted[j]];
+      // two-sided Rayleigh functional: u^T Q(lam) u = 0, root nearest the Ritz value
+      cplx disc = std::sqrt(qc * qc - 4.0 * qm * qk);
+      cplx r1 = (-qc + disc) / (2.0 * qm), r2 = (-qc - disc) / (2.0 * qm);
+      cplx pick = std::abs(r1 - ritz) < std::abs(r2 - ritz) ? r1 : r2;
+      lam_rq[j] = (std::isfinite(pick.real()) && std::isfinite(pick.imag())) ? pick : ritz;
+    }
+    std::vector<double> lamd((size_t)2 * nw);
+    for (int j = 0; j < nw; ++j) { lamd[2 * j] = lam_rq[j].real(); lamd[2 * j + 1] = lam_rq[j].imag(); }
+    double* dlam = h->d_small + 8;
+    ck(hipMemcpyAsync(dlam, lamd.data(), lamd.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
+    riga::launch_pair_resid(N, nw, h->P, h->MP, h->CP, h->KP, N, dlam, h->d_part, nsplit, h->st);
+    std::vector<double> rpart((size_t)nw * nsplit * 3);
+    ck(hipMemcpyAsync(rpart.data(), h->d_part, rpart.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    ck(hipStreamSynchronize(h->st));
+    std::vector<double> etav(nw);
+    std::vector<int64_t> imax(nw);
+    for (int j = 0; j < nw; ++j) {
+      double s = 0.0, best = -1.0;
+      int64_t bi = 0;
+      for (int x = 0; x < nsplit; ++x) {
+        const double* o = &rpart[((size_t)j * nsplit + x) * 3];
+        s += o[0];
+        if (o[1] > best) { best = o[1]; bi = (int64_t)o[2]; }
+      }
+      imax[j] = bi;
+      double al = std::abs(lam_rq[j]);
+      etav[j] = std::sqrt(s) / ((al * al * h->norms[2] + al * h->norms[1] + h->norms[0]) * std::sqrt(unorm2[j]));
+    }
+    std::vector<int> order = canonical_order(lam_rq, h->sigma);
+    const int nout = std::min(nev, nw);
+    int conv_out = converged ? nout : 0;
+    if (!converged) {
+      // count converged pairs in canonical order
+      for (int j = 0; j < nout; ++j) {
+        if (etav[order[j]] <= 1e-10) ++conv_out; else break;
+      }
+    }
+    for (int j = 0; j < nout; ++j) {
+      lam[2 * j] = lam_rq[order[j]].real();
+      lam[2 * j + 1] = lam_rq[order[j]].imag();
+      if (eta) eta[j] = etav[order[j]];
+    }
+    if (X) {
+      // scale: u^H M u = 1 and the largest entry real positive
+      std::vector<double> pv((size_t)2 * N);
+      std::vector<double> sc((size_t)2 * nw);
+      for (int j = 0; j < nw; ++j) {
+        double ar = 0, ai = 0;
+        ck(hipMemcpy(&ar, h->P + (size_t)j * N + imax[j], sizeof(double), hipMemcpyDeviceToHost));
+        ck(hipMemcpy(&ai, h->P + (size_t)(nw + j) * N + imax[j], sizeof(double), hipMemcpyDeviceToHost));
+        cplx ph = std::conj(cplx(ar, ai)) / std::abs(cplx(ar, ai));
+        cplx s = ph / std::sqrt(uMu[j]);
+        sc[2 * j] = s.real();
+        sc[2 * j + 1] = s.imag();
+      }
+      // permute columns into canonical order through a small device copy of P
+      std::vector<double> scp((size_t)2 * nout);
+      double* dsc = h->d_small + 8;
+      for (int j = 0; j < nout; ++j) {
+        int src = order[j];
+        scp[2 * j] = sc[2 * src];
+        scp[2 * j + 1] = sc[2 * src + 1];
+        // gather column src of the planar parts into slot j of MP (free now)
+        ck(hipMemcpyAsync(h->MP + (size_t)j * N, h->P + (size_t)src * N, N * sizeof(double),
+                          hipMemcpyDeviceToDevice, h->st));
+        ck(hipMemcpyAsync(h->MP + (size_t)(nout + j) * N, h->P + (size_t)(nw + src) * N, N * sizeof(double),
+                          hipMemcpyDeviceToDevice, h->st));
+      }
+      ck(hipMemcpyAsync(dsc, scp.data(), scp.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
+      riga::launch_finalize(N, nout, h->MP, N, dsc, X, h->st);
+      ck(hipStreamSynchronize(h->st));
+    }
+    ck(hipEventRecord(h->ev1, h->st));
+    ck(hipStreamSynchronize(h->st));
+    float ms = 0;
+    ck(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    h->stats.t_eigs_ms = ms;
+    h->stats.n_it = it;
+    h->stats.n_fb = kr.n_fb;
+    h->stats.n_mv = kr.n_mv;
+    h->stats.n_vv = kr.n_vv;
+    if (nconv) *nconv = conv_out;
+    return converged ? RIGA_OK : RIGA_WARN_NOT_CONVERGED;
+  });
+}

@@ -1,0 +1,427 @@
+// Building blocks of the Krylov iteration (Alg. 2): sparse products with the
+// assembled matrices (lines 8-11), B-inner products and Gram--Schmidt updates
+// (lines 9-12), and tall-skinny products for restarts and Ritz vectors.
+// All of these are HBM-bound: rows are the long dimension, columns (Krylov
+// vectors) the short one, and every kernel streams each matrix or basis column
+// once with coalesced accesses.
+#include "kernels.hpp"
+
+#include <algorithm>
+
+namespace riga {
+
+// ---------------------------------------------------------------------------
+// SpMV with the implicit tensor sparsity: row (i, j) couples to columns
+// (ii, jj) with ii in [lo(i), hi(i)], jj in [lo(j), hi(j)], stored row-major
+// in that order, so no column-index array is read.  16 lanes per row.
+constexpr int SPMV_THREADS = 256;
+constexpr int SPMV_G = 16;
+
+template <int NC>
+__global__ __launch_bounds__(SPMV_THREADS) void k_spmv(
+    int n, const int* __restrict__ lo, const int* __restrict__ hi, const int64_t* __restrict__ rowptr,
+    int64_t ndof, const double* __restrict__ A0, double a0, const double* __restrict__ A1, double a1,
+    const double* __restrict__ A2, double a2, const double* __restrict__ X, int64_t ldx,
+    double* __restrict__ Y, int64_t ldy, const double* __restrict__ Z, int64_t ldz, double bz,
+    double* __restrict__ Y2, int64_t ldy2) {
+  const int g = threadIdx.x % SPMV_G;
+  const int64_t r = ((int64_t)blockIdx.x * SPMV_THREADS + threadIdx.x) / SPMV_G;
+  const bool active = r < ndof;
+  double s0[NC], s1[NC], s2[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) { s0[q] = 0.0; s1[q] = 0.0; s2[q] = 0.0; }
+  if (active) {
+    const int i = (int)(r % n), j = (int)(r / n);
+    const int lx = lo[i], wx = hi[i] - lo[i] + 1, ly = lo[j];
+    const int64_t k0 = rowptr[r], len = rowptr[r + 1] - k0;
+    for (int o = g; o < len; o += SPMV_G) {
+      const int64_t col = (int64_t)(ly + o / wx) * n + lx + o % wx;
+      const double v0 = A0[k0 + o];
+      const double v1 = A1 ? A1[k0 + o] : 0.0;
+      const double v2 = A2 ? A2[k0 + o] : 0.0;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const double xv = X[col + q * ldx];
+        s0[q] += v0 * xv;
+        s1[q] += v1 * xv;
+        s2[q] += v2 * xv;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NC; ++q)
+#pragma unroll
+    for (int off = SPMV_G / 2; off > 0; off >>= 1) {
+      s0[q] += __shfl_xor(s0[q], off, SPMV_G);
+      s1[q] += __shfl_xor(s1[q], off, SPMV_G);
+      s2[q] += __shfl_xor(s2[q], off, SPMV_G);
+    }
+  if (active && g == 0) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      double val = a0 * s0[q] + a1 * s1[q] + a2 * s2[q];
+      if (Z) val += bz * Z[r + q * ldz];
+      Y[r + q * ldy] = val;
+      if (Y2) Y2[r + q * ldy2] = s0[q];
+    }
+  }
+}
+
+void launch_spmv(const DevSpace& s, int64_t ndof, int ncols,
+                 const double* A0, double a0, const double* A1, double a1, const double* A2, double a2,
+                 const double* X, int64_t ldx, double* Y, int64_t ldy,
+                 const double* Z, int64_t ldz, double bz, double* Y2, int64_t ldy2, hipStream_t st) {
+  int64_t blocks = (ndof * SPMV_G + SPMV_THREADS - 1) / SPMV_THREADS;
+#define RIGA_SPMV(NC)                                                                              \
+  hipLaunchKernelGGL(k_spmv<NC>, dim3((unsigned)blocks), dim3(SPMV_THREADS), 0, st, s.n, s.lo, s.hi, \
+                     s.rowptr, ndof, A0, a0, A1, a1, A2, a2, X, ldx, Y, ldy, Z, ldz, bz, Y2, ldy2)
+  switch (ncols) {
+    case 1: RIGA_SPMV(1); break;
+    case 2: RIGA_SPMV(2); break;
+    case 3: RIGA_SPMV(3); break;
+    case 4: RIGA_SPMV(4); break;
+    case 5: RIGA_SPMV(5); break;
+    case 6: RIGA_SPMV(6); break;
+    case 7: RIGA_SPMV(7); break;
+    default: RIGA_SPMV(8); break;
+  }
+#undef RIGA_SPMV
+}
+
+// ---------------------------------------------------------------------------
+// Multi-dot products out[c][q] = sum_i Au[i,c] Xu[i,q] + Al[i,c] Xl[i,q]:
+// each block owns a slice of rows, each wave owns a set of columns c and its
+// lanes stride the slice; partial sums per block are combined by the last
+// block to finish, in block order (deterministic).
+constexpr int DOT_THREADS = 256;
+
+int dots_blocks(int64_t n) {
+  int64_t b = (n + 127) / 128;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 512));
+}
+
+template <int NQ>
+__global__ __launch_bounds__(DOT_THREADS) void k_dots(
+    int64_t n, int nc, const double* __restrict__ Au, const double* __restrict__ Al, int64_t lda,
+    const double* __restrict__ Xu, const double* __restrict__ Xl, int64_t ldx,
+    double* __restrict__ partial, unsigned* __restrict__ ticket, double* __restrict__ out) {
+  const int nblk = gridDim.x;
+  const int64_t per = (n + nblk - 1) / nblk;
+  const int64_t i0 = (int64_t)blockIdx.x * per;
+  const int64_t i1 = min(n, i0 + per);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = wave; c < nc; c += DOT_THREADS / 64) {
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    const double* au = Au + (int64_t)c * lda;
+    const double* al = Al ? Al + (int64_t)c * lda : nullptr;
+    for (int64_t i = i0 + lane; i < i1; i += 64) {
+      const double u = au[i];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) acc[q] += u * Xu[i + q * ldx];
+      if (al) {
+        const double l = al[i];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] += l * Xl[i + q * ldx];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off, 64);
+    if (lane == 0)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) partial[((int64_t)blockIdx.x * nc + c) * NQ + q] = acc[q];
+  }
+  __threadfence();
+  __syncthreads();
+  __shared__ bool last;
+  if (threadIdx.x == 0) last = (atomicAdd(ticket, 1u) == (unsigned)(nblk - 1));
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  for (int idx = threadIdx.x; idx < nc * NQ; idx += DOT_THREADS) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += __builtin_nontemporal_load(&partial[(int64_t)b * nc * NQ + idx]);
+    out[idx] = s;
+  }
+  if (threadIdx.x == 0) atomicExch(ticket, 0u);
+}
+
+void launch_dots(int64_t n, int nc, const double* Au, const double* Al, int64_t lda,
+                 int nq, const double* Xu, const double* Xl, int64_t ldx,
+                 double* partial, unsigned* ticket, double* out, hipStream_t st) {
+  if (nc <= 0) return;
+  int blocks = dots_blocks(n);
+#define RIGA_DOTS(NQ)                                                                          \
+  hipLaunchKernelGGL(k_dots<NQ>, dim3(blocks), dim3(DOT_THREADS), 0, st, n, nc, Au, Al, lda, Xu, \
+                     Xl, ldx, partial, ticket, out)
+  switch (nq) {
+    case 1: RIGA_DOTS(1); break;
+    case 2: RIGA_DOTS(2); break;
+    case 3: RIGA_DOTS(3); break;
+    default: RIGA_DOTS(4); break;
+  }
+#undef RIGA_DOTS
+}
+
+// ---------------------------------------------------------------------------
+// Gram--Schmidt update Z[:, q] -= sum_c A[:, c] h[c][q] for up to three
+// (A, Z) pairs sharing h (upper part, lower part, and M times the lower part).
+constexpr int UPD_THREADS = 256;
+
+template <int NQ>
+__global__ __launch_bounds__(UPD_THREADS) void k_cgs_update(
+    int64_t n, int nc, const double* __restrict__ h,
+    const double* __restrict__ A0, double* __restrict__ Z0, const double* __restrict__ A1,
+    double* __restrict__ Z1, const double* __restrict__ A2, double* __restrict__ Z2,
+    int64_t lda, int64_t ldz) {
+  extern __shared__ double hs[];
+  for (int k = threadIdx.x; k < nc * NQ; k += UPD_THREADS) hs[k] = h[k];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * UPD_THREADS + threadIdx.x;
+  if (i >= n) return;
+  const double* As[3] = {A0, A1, A2};
+  double* Zs[3] = {Z0, Z1, Z2};
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    if (!As[m]) continue;
+    double z[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) z[q] = Zs[m][i + q * ldz];
+    for (int c = 0; c < nc; ++c) {
+      const double a = As[m][i + (int64_t)c * lda];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) z[q] -= a * hs[c * NQ + q];
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) Zs[m][i + q * ldz] = z[q];
+  }
+}
+
+void launch_cgs_update(int64_t n, int nc, int nq, const double* h,
+                       const double* A0, double* Z0, const double* A1, double* Z1,
+                       const double* A2, double* Z2, int64_t lda, int64_t ldz, hipStream_t st) {
+  if (nc <= 0) return;
+  int64_t blocks = (n + UPD_THREADS - 1) / UPD_THREADS;
+#define RIGA_UPD(NQ)                                                                              \
+  hipLaunchKernelGGL(k_cgs_update<NQ>, dim3((unsigned)blocks), dim3(UPD_THREADS),                 \
+                     (size_t)nc * NQ * sizeof(double), st, n, nc, h,                               \
+                     A0, Z0, A1, Z1, A2, Z2, lda, ldz)
+  switch (nq) {
+    case 1: RIGA_UPD(1); break;
+    case 2: RIGA_UPD(2); break;
+    case 3: RIGA_UPD(3); break;
+    default: RIGA_UPD(4); break;
+  }
+#undef RIGA_UPD
+}
+
+// ---------------------------------------------------------------------------
+// Out = In * Q for a tall In (n x kin) and a small Q (kin x kout) held in LDS.
+constexpr int GEMM_THREADS = 256;
+constexpr int GEMM_CHUNK = 8;
+
+__global__ __launch_bounds__(GEMM_THREADS) void k_gemm_tall(
+    int64_t n, const double* __restrict__ In, int64_t ldi, int kin, const double* __restrict__ Q,
+    int kout, double* __restrict__ Out, int64_t out_rs, int64_t out_cs) {
+  extern __shared__ double qs[];
+  for (int k = threadIdx.x; k < kin * kout; k += GEMM_THREADS) qs[k] = Q[k];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * GEMM_THREADS + threadIdx.x;
+  if (i >= n) return;
+  for (int c0 = 0; c0 < kout; c0 += GEMM_CHUNK) {
+    double acc[GEMM_CHUNK];
+#pragma unroll
+    for (int c = 0; c < GEMM_CHUNK; ++c) acc[c] = 0.0;
+    for (int tt = 0; tt < kin; ++tt) {
+      const double a = In[i + (int64_t)tt * ldi];
+#pragma unroll
+      for (int c = 0; c < GEMM_CHUNK; ++c)
+        if (c0 + c < kout) acc[c] += a * qs[(c0 + c) * kin + tt];
+    }
+#pragma unroll
+    for (int c = 0; c < GEMM_CHUNK; ++c)
+      if (c0 + c < kout) Out[i * out_rs + (int64_t)(c0 + c) * out_cs] = acc[c];
+  }
+}
+
+void launch_gemm_tall(int64_t n, const double* In, int64_t ldi, int kin, const double* Q, int kout,
+                      double* Out, int64_t out_rs, int64_t out_cs, hipStream_t st) {
+  if (kout <= 0 || kin <= 0) return;
+  int64_t blocks = (n + GEMM_THREADS - 1) / GEMM_THREADS;
+  // Q columns in chunks that keep the LDS copy within 48 KB
+  const int cols = std::max(1, std::min(kout, (int)(6144 / kin)));
+  for (int c0 = 0; c0 < kout; c0 += cols) {
+    const int kc = std::min(cols, kout - c0);
+    size_t shm = (size_t)kin * kc * sizeof(double);
+    hipLaunchKernelGGL(k_gemm_tall, dim3((unsigned)blocks), dim3(GEMM_THREADS), shm, st, n, In, ldi, kin,
+                       Q + (size_t)c0 * kin, kc, Out + (int64_t)c0 * out_cs, out_rs, out_cs);
+  }
+}
+
+// ---------------------------------------------------------------------------
+__device__ inline uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+__global__ void k_random_fill(double* X, int64_t n, int ncols, int64_t ld, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int c = 0; c < ncols; ++c) {
+    uint64_t z = splitmix64(seed * 0x100000001B3ull + (uint64_t)c * (uint64_t)n + (uint64_t)i);
+    // 53 random bits -> uniform in (-1, 1)
+    X[i + c * ld] = 2.0 * (((double)(z >> 11) + 0.5) * (1.0 / 9007199254740992.0)) - 1.0;
+  }
+}
+
+void launch_random_fill(double* X, int64_t n, int ncols, int64_t ld, uint64_t seed, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_random_fill, dim3((unsigned)blocks), dim3(256), 0, st, X, n, ncols, ld, seed);
+}
+
+// ---------------------------------------------------------------------------
+// Per-pair reductions for the returned eigenvectors u_k = a_k + i b_k, stored
+// planar: P[:, k] = a_k, P[:, nv + k] = b_k, and likewise for M P, C P, K P.
+// Block (x, k) sums rows of its slice into part[(k * nsplit + x) * 11 + f]:
+//   f: aMa bMb aMb aCa bCb aCb aKa bKb aKb aa bb
+__global__ __launch_bounds__(256) void k_pair_forms(int64_t n, int nv, const double* __restrict__ P,
+                                                    const double* __restrict__ MP, const double* __restrict__ CP,
+                                                    const double* __restrict__ KP, int64_t ld,
+                                                    double* __restrict__ part) {
+  const int k = blockIdx.y, nsplit = gridDim.x;
+  const int64_t per = (n + nsplit - 1) / nsplit;
+  const int64_t i0 = (int64_t)blockIdx.x * per, i1 = min(n, i0 + per);
+  double f[11];
+#pragma unroll
+  for (int t = 0; t < 11; ++t) f[t] = 0.0;
+  const int64_t ca = (int64_t)k * ld, cb = (int64_t)(nv + k) * ld;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+    const double a = P[ca + i], b = P[cb + i];
+    const double ma = MP[ca + i], mb = MP[cb + i];
+    const double cA = CP[ca + i], cB = CP[cb + i];
+    const double ka = KP[ca + i], kb = KP[cb + i];
+    f[0] += a * ma; f[1] += b * mb; f[2] += a * mb;
+    f[3] += a * cA; f[4] += b * cB; f[5] += a * cB;
+    f[6] += a * ka; f[7] += b * kb; f[8] += a * kb;
+    f[9] += a * a;  f[10] += b * b;
+  }
+  __shared__ double red[11][256];
+#pragma unroll
+  for (int t = 0; t < 11; ++t) red[t][threadIdx.x] = f[t];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+#pragma unroll
+      for (int t = 0; t < 11; ++t) red[t][threadIdx.x] += red[t][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < 11) part[((int64_t)k * nsplit + blockIdx.x) * 11 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+void launch_pair_forms(int64_t n, int nv, const double* P, const double* MP, const double* CP,
+                       const double* KP, int64_t ld, double* part, int nsplit, hipStream_t st) {
+  hipLaunchKernelGGL(k_pair_forms, dim3(nsplit, nv), dim3(256), 0, st, n, nv, P, MP, CP, KP, ld, part);
+}
+
+// ||K u + lam C u + lam^2 M u||^2 per pair (lam[2k], lam[2k+1] = re, im) and
+// max |u_i|^2 with its index: part[(k * nsplit + x) * 3 + {0: sum, 1: max, 2: index}]
+__global__ __launch_bounds__(256) void k_pair_resid(int64_t n, int nv, const double* __restrict__ P,
+                                                    const double* __restrict__ MP, const double* __restrict__ CP,
+                                                    const double* __restrict__ KP, int64_t ld,
+                                                    const double* __restrict__ lam, double* __restrict__ part) {
+  const int k = blockIdx.y, nsplit = gridDim.x;
+  const int64_t per = (n + nsplit - 1) / nsplit;
+  const int64_t i0 = (int64_t)blockIdx.x * per, i1 = min(n, i0 + per);
+  const double lr = lam[2 * k], li = lam[2 * k + 1];
+  const double l2r = lr * lr - li * li, l2i = 2.0 * lr * li;
+  const int64_t ca = (int64_t)k * ld, cb = (int64_t)(nv + k) * ld;
+  double s = 0.0, best = -1.0;
+  int64_t bi = 0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+    const double ka = KP[ca + i], kb = KP[cb + i];
+    const double cA = CP[ca + i], cB = CP[cb + i];
+    const double ma = MP[ca + i], mb = MP[cb + i];
+    const double rr = ka + (lr * cA - li * cB) + (l2r * ma - l2i * mb);
+    const double ri = kb + (lr * cB + li * cA) + (l2r * mb + l2i * ma);
+    s += rr * rr + ri * ri;
+    const double a = P[ca + i], b = P[cb + i];
+    const double m = a * a + b * b;
+    if (m > best) { best = m; bi = i; }
+  }
+  __shared__ double rs[256], rv[256];
+  __shared__ int64_t ri_[256];
+  rs[threadIdx.x] = s; rv[threadIdx.x] = best; ri_[threadIdx.x] = bi;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      rs[threadIdx.x] += rs[threadIdx.x + st];
+      double o = rv[threadIdx.x + st];
+      int64_t oi = ri_[threadIdx.x + st];
+      if (o > rv[threadIdx.x] || (o == rv[threadIdx.x] && oi < ri_[threadIdx.x])) {
+        rv[threadIdx.x] = o; ri_[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double* o = part + ((int64_t)k * nsplit + blockIdx.x) * 3;
+    o[0] = rs[0]; o[1] = rv[0]; o[2] = (double)ri_[0];
+  }
+}
+
+void launch_pair_resid(int64_t n, int nv, const double* P, const double* MP, const double* CP,
+                       const double* KP, int64_t ld, const double* lam, double* part, int nsplit,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_pair_resid, dim3(nsplit, nv), dim3(256), 0, st, n, nv, P, MP, CP, KP, ld, lam, part);
+}
+
+// X[2 (i + k n) + {0,1}] = s_k (a_k + i b_k): scaled eigenvectors, interleaved complex.
+__global__ void k_finalize(int64_t n, int nv, const double* __restrict__ P, int64_t ld,
+                           const double* __restrict__ s, double* __restrict__ X) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < nv; ++k) {
+    const double a = P[(int64_t)k * ld + i], b = P[(int64_t)(nv + k) * ld + i];
+    const double sr = s[2 * k], si = s[2 * k + 1];
+    X[2 * ((int64_t)k * n + i)] = a * sr - b * si;
+    X[2 * ((int64_t)k * n + i) + 1] = a * si + b * sr;
+  }
+}
+
+void launch_finalize(int64_t n, int nv, const double* P, int64_t ld, const double* s, double* X,
+                     hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks), dim3(256), 0, st, n, nv, P, ld, s, X);
+}
+
+// Largest absolute row sum of a CSR value array (the 1-norm of a symmetric
+// matrix); per-block maxima in part[blockIdx.x].
+__global__ __launch_bounds__(256) void k_rowabs(const int64_t* __restrict__ rowptr, int64_t ndof,
+                                                const double* __restrict__ A, double* __restrict__ part) {
+  double best = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < ndof; r += (int64_t)gridDim.x * 256) {
+    double s = 0.0;
+    for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) s += fabs(A[k]);
+    best = fmax(best, s);
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+void launch_rowabs(const int64_t* rowptr, int64_t ndof, const double* A, double* part, int nblk,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_rowabs, dim3(nblk), dim3(256), 0, st, rowptr, ndof, A, part);
+}
+
+}  // namespace riga

@@ -1,0 +1,91 @@
+// Launchers of the gfx950 kernels (host side).  Every pointer is device memory
+// unless stated otherwise; every launch is asynchronous on `st`.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace riga {
+
+// Device copy of the 1-D space and of the nested-dissection plan.
+struct DevSpace {
+  int p, ne, n;                 // degree, elements, Dirichlet functions per direction
+  const int* knots;             // element-boundary indices, length nall + p + 1
+  const int* sup0; const int* sup1;
+  const int* lo; const int* hi;
+  const int* first;             // per element
+  const int64_t* rowptr;        // CSR row pointers (ndof + 1)
+};
+
+struct DevTree {
+  const int* nf; const int* no; const int* nb;
+  const int64_t* loff; const int64_t* uoff;
+  const int* foff; const int* fdofs; const int* fkey; const int* fpos;
+  const int* coff; const int* clist; const int* moff; const int* maps;
+  const int* voff;              // per node: offset of its solve update vector (nb entries)
+};
+
+// --- assembly ---------------------------------------------------------------
+// 1-D element mass / stiffness blocks tabM/tabK[e][a][b], a,b in 0..p, from
+// the Cox--de Boor values at the (p+1)-point Gauss rule (gx, gw on [-1, 1]).
+void launch_bspline_tables(const DevSpace& s, const double* gx, const double* gw,
+                           double* tabM, double* tabK, hipStream_t st);
+// CSR values of K, M and C = alpha M + beta K + sum_e c_e M_e by gather.
+void launch_assemble(const DevSpace& s, const double* tabM, const double* tabK,
+                     double alpha, double beta, const double* c_elem,
+                     double* K, double* M, double* C, int64_t ndof, hipStream_t st);
+
+// --- factorization ------------------------------------------------------------
+// One launch per tree level: assemble each front (original entries of
+// Q = s2 M + s1 C + K plus the children's update blocks) and eliminate its own
+// dofs by a blocked right-looking Cholesky with FP64 MFMA trailing updates.
+void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count,
+                         double s2, double s1, const double* K, const double* M, const double* C,
+                         double* L, double* U, int64_t* status, hipStream_t st);
+
+// --- forward / backward solves ------------------------------------------------
+void launch_fwd_level(const DevTree& t, const int* level_nodes, int count, int nrhs,
+                      const double* L, const double* b, int64_t ldb, double* y, int64_t ldy,
+                      double* upd, int max_front, hipStream_t st);
+// Backward sweep; if r_l != nullptr the result is written as the operator
+// epilogue r_u = -x, r_l = sig * r_u + v_u (v_u given with ldv), else x = y-solve.
+void launch_bwd_level(const DevTree& t, const int* level_nodes, int count, int nrhs,
+                      const double* L, const double* y, int64_t ldy, double* x, int64_t ldx,
+                      double* r_l, const double* v_u, int64_t ldv, double sig,
+                      int max_front, hipStream_t st);
+
+// --- Krylov building blocks -----------------------------------------------------
+// Y = a0 A0 X + a1 A1 X + a2 A2 X + bz Z   (A* share the CSR pattern; A1/A2 may be null)
+// and optionally Y2 = A0 X.  X, Y, Z, Y2: ndof x ncols (ld given), ncols <= 8.
+void launch_spmv(const DevSpace& s, int64_t ndof, int ncols,
+                 const double* A0, double a0, const double* A1, double a1, const double* A2, double a2,
+                 const double* X, int64_t ldx, double* Y, int64_t ldy,
+                 const double* Z, int64_t ldz, double bz, double* Y2, int64_t ldy2, hipStream_t st);
+// out[c*nq + q] = sum_i Au[i,c] Xu[i,q] + Al[i,c] Xl[i,q]  (Al/Xl may be null),
+// c < nc, q < nq <= 4; deterministic two-stage reduction.  partial: >= nblk*nc*nq
+// doubles of scratch, ticket: one zeroed uint32.
+void launch_dots(int64_t n, int nc, const double* Au, const double* Al, int64_t lda,
+                 int nq, const double* Xu, const double* Xl, int64_t ldx,
+                 double* partial, unsigned* ticket, double* out, hipStream_t st);
+int dots_blocks(int64_t n);
+// Z[:, q] -= sum_c A[:, c] h[c*nq+q] for up to three (A, Z) pairs sharing h.
+void launch_cgs_update(int64_t n, int nc, int nq, const double* h,
+                       const double* A0, double* Z0, const double* A1, double* Z1,
+                       const double* A2, double* Z2, int64_t lda, int64_t ldz, hipStream_t st);
+// Out[i, c] (stride so, co) = sum_t In[i, t] Q[t, c] (Q device, kin x kout col-major).
+void launch_gemm_tall(int64_t n, const double* In, int64_t ldi, int kin, const double* Q, int kout,
+                      double* Out, int64_t out_rs, int64_t out_cs, hipStream_t st);
+// Counter-based uniform(-1, 1) fill of a ndof x ncols block (splitmix64 of seed, index).
+void launch_random_fill(double* X, int64_t n, int ncols, int64_t ld, uint64_t seed, hipStream_t st);
+// Eigenvector post-processing on planar complex columns P = [a_1..a_nv | b_1..b_nv]
+// (ld rows each) with MP = M P, CP = C P, KP = K P; see k_krylov.hip.
+void launch_pair_forms(int64_t n, int nv, const double* P, const double* MP, const double* CP,
+                       const double* KP, int64_t ld, double* part, int nsplit, hipStream_t st);
+void launch_pair_resid(int64_t n, int nv, const double* P, const double* MP, const double* CP,
+                       const double* KP, int64_t ld, const double* lam, double* part, int nsplit,
+                       hipStream_t st);
+void launch_finalize(int64_t n, int nv, const double* P, int64_t ld, const double* s, double* X,
+                     hipStream_t st);
+void launch_rowabs(const int64_t* rowptr, int64_t ndof, const double* A, double* part, int nblk,
+                   hipStream_t st);
+
+}  // namespace riga

@@ -1,0 +1,246 @@
+// Host-side symbolic plan (integer work only; no device calls).
+//
+// The nested-dissection tree follows the observation of Sec. 3.3: in rIGA the
+// C^0 hyperplanes coincide with the separators of a multifrontal solver, so
+// the domain is bisected along hyperplanes until single macroelements remain.
+// A separator holds every function whose support crosses the cutting line:
+// one function thick at a C^0 hyperplane, p functions thick at an ordinary
+// element interface of maximum-continuity IGA.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <functional>
+
+namespace riga {
+
+void Space1D::build(int p_, int ne_, int s_) {
+  p = p_; ne = ne_; s = s_;
+  knots.clear();
+  for (int i = 0; i <= p; ++i) knots.push_back(0);
+  for (int k = 1; k < ne; ++k) {
+    int mult = (s > 0 && k % s == 0) ? p : 1;
+    for (int r = 0; r < mult; ++r) knots.push_back(k);
+  }
+  for (int i = 0; i <= p; ++i) knots.push_back(ne);
+  nall = (int)knots.size() - p - 1;
+  n = nall - 2;
+  sup0.resize(n); sup1.resize(n);
+  for (int d = 0; d < n; ++d) {
+    sup0[d] = knots[d + 1];
+    sup1[d] = knots[d + 1 + p + 1];
+  }
+  lo.resize(n); hi.resize(n);
+  for (int d = 0; d < n; ++d) {
+    int a = d, b = d;
+    while (a > 0 && std::max(sup0[a - 1], sup0[d]) < std::min(sup1[a - 1], sup1[d])) --a;
+    while (b + 1 < n && std::max(sup0[b + 1], sup0[d]) < std::min(sup1[b + 1], sup1[d])) ++b;
+    lo[d] = a; hi[d] = b;
+  }
+  first.resize(ne);
+  for (int e = 0; e < ne; ++e) {
+    int cnt = (int)(std::upper_bound(knots.begin(), knots.end(), e) - knots.begin());
+    first[e] = cnt - 1 - p;   // span index minus p
+  }
+}
+
+namespace {
+
+// Cut candidates strictly inside (lo, hi): hyperplanes for rIGA, any element
+// interface for IGA while the box is larger than the leaf size.
+int pick_cut(int lo, int hi, int s, int leaf) {
+  int mid2 = lo + hi;  // twice the midpoint
+  int best = -1, bestd = 1 << 30;
+  if (s > 0) {
+    for (int c = (lo / s + 1) * s; c < hi; c += s) {
+      int d = std::abs(2 * c - mid2);
+      if (d < bestd) { bestd = d; best = c; }
+    }
+  } else if (hi - lo > leaf) {
+    best = (lo + hi) / 2;
+  }
+  return best;
+}
+
+}  // namespace
+
+int Plan::build(int p, int ne, int s, int leaf) {
+  if (p < 1 || p > 8 || ne < 2) return -1;
+  if (s < 0 || (s > 0 && ne % s != 0)) return -1;
+  if (leaf <= 0) leaf = 16;
+  sp.build(p, ne, s);
+  n1d = sp.n;
+  if (n1d < 1) return -1;
+  ndof = n1d * n1d;
+  const int n = sp.n;
+
+  rowptr.assign(ndof + 1, 0);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      int64_t r = (int64_t)j * n + i;
+      rowptr[r + 1] = rowptr[r] + (int64_t)(sp.hi[i] - sp.lo[i] + 1) * (sp.hi[j] - sp.lo[j] + 1);
+    }
+  nnz = rowptr[ndof];
+
+  // --- tree of boxes -------------------------------------------------------
+  std::vector<Node> tmp;
+  std::function<int(int, int, int, int)> make = [&](int x0, int x1, int y0, int y1) -> int {
+    int id = (int)tmp.size();
+    tmp.push_back(Node{});
+    tmp[id].x0 = x0; tmp[id].x1 = x1; tmp[id].y0 = y0; tmp[id].y1 = y1;
+    int cx = pick_cut(x0, x1, s, leaf), cy = pick_cut(y0, y1, s, leaf);
+    int dir = -1, cut = -1;
+    if (x1 - x0 >= y1 - y0) {
+      if (cx >= 0) { dir = 0; cut = cx; } else if (cy >= 0) { dir = 1; cut = cy; }
+    } else {
+      if (cy >= 0) { dir = 1; cut = cy; } else if (cx >= 0) { dir = 0; cut = cx; }
+    }
+    tmp[id].dir = dir; tmp[id].cut = cut;
+    if (dir >= 0) {
+      int a, b;
+      if (dir == 0) { a = make(x0, cut, y0, y1); b = make(cut, x1, y0, y1); }
+      else          { a = make(x0, x1, y0, cut); b = make(x0, x1, cut, y1); }
+      tmp[id].children = {a, b};
+      tmp[a].parent = id; tmp[b].parent = id;
+    }
+    return id;
+  };
+  int root_tmp = make(0, ne, 0, ne);
+
+  // postorder renumbering
+  std::vector<int> order;
+  std::function<void(int)> dfs = [&](int v) {
+    for (int c : tmp[v].children) dfs(c);
+    order.push_back(v);
+  };
+  dfs(root_tmp);
+  std::vector<int> newid(tmp.size());
+  for (size_t k = 0; k < order.size(); ++k) newid[order[k]] = (int)k;
+  nodes.assign(tmp.size(), Node{});
+  for (size_t k = 0; k < order.size(); ++k) {
+    Node nd = tmp[order[k]];
+    nd.parent = nd.parent >= 0 ? newid[nd.parent] : -1;
+    for (int& c : nd.children) c = newid[c];
+    nd.post = (int)k;
+    nodes[k] = nd;
+  }
+  for (auto& nd : nodes) {
+    nd.first_desc = nd.post;
+    nd.height = 0;
+    for (int c : nd.children) {
+      nd.first_desc = std::min(nd.first_desc, nodes[c].first_desc);
+      nd.height = std::max(nd.height, nodes[c].height + 1);
+    }
+  }
+  const int root = (int)nodes.size() - 1;
+  height = nodes[root].height + 1;
+
+  // --- assign dofs -----------------------------------------------------------
+  node_of_dof.assign(ndof, -1);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      int v = root;
+      for (;;) {
+        const Node& nd = nodes[v];
+        if (nd.dir < 0) break;
+        int a0 = nd.dir == 0 ? sp.sup0[i] : sp.sup0[j];
+        int a1 = nd.dir == 0 ? sp.sup1[i] : sp.sup1[j];
+        if (a0 < nd.cut && nd.cut < a1) break;
+        v = (a1 <= nd.cut) ? nd.children[0] : nd.children[1];
+      }
+      int d = j * n + i;
+      node_of_dof[d] = v;
+      nodes[v].own.push_back(d);  // increasing dof id by construction
+    }
+  elim_pos.assign(ndof, -1);
+  int64_t pos = 0;
+  for (auto& nd : nodes)
+    for (int d : nd.own) elim_pos[d] = pos++;
+
+  // --- boundary sets ---------------------------------------------------------
+  std::vector<int> stamp(ndof, -1);
+  for (auto& nd : nodes) {
+    std::vector<int> S;
+    auto is_anc = [&](int w) {
+      const Node& a = nodes[w];
+      return a.post > nd.post && a.first_desc <= nd.post;
+    };
+    for (int c : nd.children)
+      for (int g : nodes[c].bnd)
+        if (node_of_dof[g] != nd.post && stamp[g] != nd.post) { stamp[g] = nd.post; S.push_back(g); }
+    for (int d : nd.own) {
+      int i = d % n, j = d / n;
+      for (int jj = sp.lo[j]; jj <= sp.hi[j]; ++jj)
+        for (int ii = sp.lo[i]; ii <= sp.hi[i]; ++ii) {
+          int g = jj * n + ii;
+          int w = node_of_dof[g];
+          if (w != nd.post && is_anc(w) && stamp[g] != nd.post) { stamp[g] = nd.post; S.push_back(g); }
+        }
+    }
+    std::sort(S.begin(), S.end(), [&](int a, int b) { return elim_pos[a] < elim_pos[b]; });
+    nd.bnd = std::move(S);
+  }
+
+  // --- flatten -----------------------------------------------------------------
+  const int nn = (int)nodes.size();
+  nf.resize(nn); no.resize(nn); nb.resize(nn);
+  loff.resize(nn); uoff.resize(nn); foff.resize(nn + 1);
+  lsize = usize = 0;
+  foff[0] = 0;
+  flops_dense = 0; solve_bytes = 0;
+  max_front = max_own = max_nb = 0;
+  for (int v = 0; v < nn; ++v) {
+    no[v] = (int)nodes[v].own.size();
+    nb[v] = (int)nodes[v].bnd.size();
+    nf[v] = no[v] + nb[v];
+    loff[v] = lsize; lsize += (int64_t)nf[v] * no[v];
+    uoff[v] = usize; usize += (int64_t)nb[v] * nb[v];
+    foff[v + 1] = foff[v] + nf[v];
+    max_front = std::max(max_front, nf[v]);
+    max_own = std::max(max_own, no[v]);
+    max_nb = std::max(max_nb, nb[v]);
+    double o = no[v], b = nb[v];
+    flops_dense += o * o * o / 3.0 + b * o * o + b * b * o;
+    solve_bytes += 2.0 * 8.0 * (o * (o + 1) / 2 + b * o);
+  }
+  fdofs.resize(foff[nn]); fkey.resize(foff[nn]); fpos.resize(foff[nn]);
+  for (int v = 0; v < nn; ++v) {
+    int o = foff[v];
+    std::vector<std::pair<int, int>> kp;
+    int t = 0;
+    for (int d : nodes[v].own) { fdofs[o + t] = d; kp.push_back({d, t}); ++t; }
+    for (int d : nodes[v].bnd) { fdofs[o + t] = d; kp.push_back({d, t}); ++t; }
+    std::sort(kp.begin(), kp.end());
+    for (int k = 0; k < t; ++k) { fkey[o + k] = kp[k].first; fpos[o + k] = kp[k].second; }
+  }
+  coff.assign(nn + 1, 0);
+  clist.clear();
+  for (int v = 0; v < nn; ++v) {
+    for (int c : nodes[v].children) clist.push_back(c);
+    coff[v + 1] = (int)clist.size();
+  }
+  moff.assign(nn + 1, 0);
+  maps.clear();
+  std::vector<int> posmap(ndof, -1);
+  for (int v = 0; v < nn; ++v) moff[v + 1] = moff[v] + nb[v];
+  maps.resize(moff[nn]);
+  for (int u = 0; u < nn; ++u) {
+    for (int t = 0; t < nf[u]; ++t) posmap[fdofs[foff[u] + t]] = t;
+    for (int c : nodes[u].children)
+      for (int k = 0; k < nb[c]; ++k) {
+        int pz = posmap[nodes[c].bnd[k]];
+        if (pz < 0) return -2;  // bnd(c) must lie in the parent front
+        maps[moff[c] + k] = pz;
+      }
+    for (int t = 0; t < nf[u]; ++t) posmap[fdofs[foff[u] + t]] = -1;
+  }
+  // levels by height
+  level_off.assign(height + 1, 0);
+  for (auto& nd : nodes) level_off[nd.height + 1]++;
+  for (int h = 0; h < height; ++h) level_off[h + 1] += level_off[h];
+  level_nodes.assign(nn, 0);
+  std::vector<int> fill(level_off.begin(), level_off.end() - 1);
+  for (auto& nd : nodes) level_nodes[fill[nd.height]++] = nd.post;
+  return 0;
+}
+
+}  // namespace riga

@@ -1,0 +1,62 @@
+// Host-side symbolic plan: B-spline spaces, sparsity, nested-dissection tree
+// whose separators are the rIGA hyperplanes, and the frontal index maps.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+namespace riga {
+
+// One direction of the tensor-product space (Sec. 3.1).  Knot positions are
+// kept as integers in element units: the open knot vector of eq. KnotsX with
+// interior knots of multiplicity 1 (IGA, Sec. 3.2) or p at every s-th
+// element boundary (rIGA with C^0 hyperplanes, Sec. 3.3).
+struct Space1D {
+  int p = 0, ne = 0, s = 0;
+  std::vector<int> knots;      // element-boundary indices 0..ne
+  int nall = 0;                // functions before boundary elimination
+  int n = 0;                   // Dirichlet functions: full indices 1..nall-2
+  std::vector<int> sup0, sup1; // support [sup0, sup1) in elements, per Dirichlet function
+  std::vector<int> lo, hi;     // coupled Dirichlet functions form the range [lo, hi]
+  std::vector<int> first;      // per element: full index of its first nonzero function
+  void build(int p_, int ne_, int s_);
+};
+
+struct Node {
+  int x0, x1, y0, y1;          // box in element units
+  int dir = -1, cut = -1;      // separator line: dir 0 -> x = cut, 1 -> y = cut, -1 leaf
+  int parent = -1;
+  std::vector<int> children;
+  std::vector<int> own;        // dofs eliminated here, increasing dof id
+  std::vector<int> bnd;        // ancestor dofs coupled to the subtree, elimination order
+  int height = 0;
+  int post = 0;                // postorder index
+  int first_desc = 0;          // smallest postorder index in the subtree
+};
+
+struct Plan {
+  Space1D sp;                  // identical in x and y
+  int64_t n1d = 0, ndof = 0, nnz = 0;
+  std::vector<int64_t> rowptr; // CSR row pointers of the tensor sparsity
+  std::vector<Node> nodes;     // in postorder
+  int height = 0;
+  std::vector<int> level_nodes;    // node ids grouped by height
+  std::vector<int> level_off;      // height h: level_nodes[level_off[h] .. level_off[h+1])
+  std::vector<int> node_of_dof;
+  std::vector<int64_t> elim_pos;   // dof -> elimination position
+  // flattened frontal data
+  std::vector<int> nf, no, nb;
+  std::vector<int64_t> loff, uoff; // factor block (nf x no) and update block (nb x nb)
+  int64_t lsize = 0, usize = 0;
+  std::vector<int> foff;           // front dof list offsets
+  std::vector<int> fdofs;          // front dofs: own then bnd
+  std::vector<int> fkey, fpos;     // front dofs sorted by dof id, with their front positions
+  std::vector<int> coff, clist;    // children (CSR)
+  std::vector<int> moff, maps;     // per node: positions of its bnd dofs in the parent front
+  int max_front = 0, max_own = 0, max_nb = 0;
+  double flops_dense = 0.0;
+  double solve_bytes = 0.0;
+
+  int build(int p, int ne, int s, int leaf);  // 0 ok, <0 invalid
+};
+
+}  // namespace riga

@@ -1,0 +1,35 @@
+// Dense eigen-decomposition of the small projected matrix of the Krylov
+// iteration (Rayleigh--Ritz, eq. ArnoldiRitz) and the Krylov--Schur restart
+// helpers (Sec. 4.1.3).  Host code; sizes are the subspace dimension (<= ~100).
+#pragma once
+#include <complex>
+#include <vector>
+
+namespace riga {
+
+using cplx = std::complex<double>;
+
+// A = Z T Z^H for a real n x n column-major A: T upper triangular, Z unitary
+// (both n x n column-major complex).  Householder reduction to Hessenberg
+// form, then single-shift complex QR iterations with Wilkinson shifts.
+// Returns 0, or -1 if the iteration did not converge.
+int schur_complex(int n, const double* A, std::vector<cplx>& T, std::vector<cplx>& Z);
+
+// Reorder the Schur form so that the eigenvalues at positions order[0..k-1]
+// (positions in the current T) come first, in that order.
+void schur_reorder(int n, std::vector<cplx>& T, std::vector<cplx>& Z, const std::vector<int>& order);
+
+// Eigenvectors of A from its Schur form, columns of Y (n x n) normalised to unit
+// 2-norm.  Diagonal entries of T that agree to `cluster_tol` (relative to the
+// largest |T_ii|) are treated as one multiple eigenvalue whose eigenvectors
+// are taken from the Schur basis (the coupling of a semisimple multiple
+// eigenvalue vanishes in exact arithmetic).
+void schur_eigvecs(int n, const std::vector<cplx>& T, const std::vector<cplx>& Z,
+                   std::vector<cplx>& Y, double cluster_tol);
+
+// Real orthonormal basis Q (n x r, column-major) of span{Re z, Im z} over the
+// first k columns of Z (n x n).  When those columns span a subspace closed
+// under conjugation, r == k.  Returns r.
+int realify(int n, int k, const std::vector<cplx>& Z, std::vector<double>& Q);
+
+}  // namespace riga

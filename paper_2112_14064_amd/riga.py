@@ -1,0 +1,215 @@
+"""ctypes binding of libriga.so (argument marshalling only).
+
+Function names mirror the C ABI in include/riga.h.  Device buffers are torch
+tensors on a HIP device; the library queues its work on the stream given to
+riga_create (torch's current stream by default).  Every computation happens
+in the library's kernels; this module only moves pointers and sizes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libriga.so")
+
+RIGA_OK = 0
+RIGA_ERR_INVALID_ARG = -1
+RIGA_ERR_NOT_SPD = -2
+RIGA_ERR_HIP = -3
+RIGA_ERR_OOM = -4
+RIGA_ERR_STATE = -5
+RIGA_WARN_NOT_CONVERGED = 1
+
+
+class riga_mesh(C.Structure):
+    _fields_ = [("p", C.c_int), ("ne", C.c_int), ("hyper_every", C.c_int), ("leaf", C.c_int)]
+
+
+class riga_damping(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("beta", C.c_double), ("c_elem", C.c_void_p)]
+
+
+class riga_options(C.Structure):
+    _fields_ = [("nev", C.c_int), ("m", C.c_int), ("maxit", C.c_int), ("block", C.c_int),
+                ("tol", C.c_double), ("seed", C.c_uint64), ("v0", C.c_void_p)]
+
+
+class riga_info_t(C.Structure):
+    _fields_ = [("n1d", C.c_int64), ("ndof", C.c_int64), ("nnz", C.c_int64), ("nnodes", C.c_int64),
+                ("nleaves", C.c_int64), ("height", C.c_int64), ("max_front", C.c_int64),
+                ("leaf_own", C.c_int64), ("factor_entries", C.c_int64),
+                ("factor_flops_dense", C.c_double), ("solve_bytes", C.c_double)]
+
+
+class riga_stats_t(C.Structure):
+    _fields_ = [("n_it", C.c_int64), ("n_fb", C.c_int64), ("n_mv", C.c_int64), ("n_vv", C.c_int64),
+                ("t_assemble_ms", C.c_double), ("t_factor_ms", C.c_double), ("t_eigs_ms", C.c_double)]
+
+
+EXPORTS = ["riga_create", "riga_info", "riga_assemble", "riga_export_csr", "riga_factor",
+           "riga_solve_q", "riga_apply_op", "riga_eigs", "riga_stats", "riga_selftest_small_eig",
+           "riga_status_str", "riga_destroy"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the in-tree library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2112_14064_amd.build`")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    lib.riga_create.argtypes = [C.POINTER(P), C.POINTER(riga_mesh), C.c_int, P]
+    lib.riga_info.argtypes = [P, C.POINTER(riga_info_t)]
+    lib.riga_assemble.argtypes = [P, C.POINTER(riga_damping)]
+    lib.riga_export_csr.argtypes = [P, C.c_int, P, P, P]
+    lib.riga_factor.argtypes = [P, C.c_double, C.POINTER(C.c_int64)]
+    lib.riga_solve_q.argtypes = [P, C.c_int, P, P]
+    lib.riga_apply_op.argtypes = [P, C.c_int, P, P]
+    lib.riga_eigs.argtypes = [P, C.POINTER(riga_options), P, P, P, C.POINTER(C.c_int)]
+    lib.riga_stats.argtypes = [P, C.POINTER(riga_stats_t)]
+    lib.riga_selftest_small_eig.argtypes = [C.c_int, P, P, P]
+    lib.riga_status_str.argtypes = [C.c_int]
+    lib.riga_status_str.restype = C.c_char_p
+    lib.riga_destroy.argtypes = [P]
+    lib.riga_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("riga_status_str", "riga_destroy"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+class RigaError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = load().riga_status_str(status).decode()
+        super().__init__(f"{where}: {msg} (status {status})")
+
+
+def _check(status: int, where: str, allow_warn: bool = False) -> int:
+    if status < 0 or (status > 0 and not allow_warn):
+        raise RigaError(status, where)
+    return status
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def riga_selftest_small_eig(a: np.ndarray):
+    """Eigenvalues of a small real matrix by the library's dense Schur solver
+    (host only) and the worst relative eigenvector residual."""
+    lib = load()
+    a = np.asfortranarray(np.asarray(a, dtype=np.float64))
+    n = a.shape[0]
+    w = np.zeros(2 * n)
+    res = C.c_double(0.0)
+    _check(lib.riga_selftest_small_eig(n, a.ctypes.data_as(C.c_void_p), w.ctypes.data_as(C.c_void_p),
+                                       C.cast(C.pointer(res), C.c_void_p)), "riga_selftest_small_eig")
+    return w[0::2] + 1j * w[1::2], res.value
+
+
+class Problem:
+    """One discretised QEP on one device (owns a riga_problem handle)."""
+
+    def __init__(self, p: int, ne: int, hyper_every: int, leaf: int = 0, device: int = 0, stream=None):
+        import torch
+
+        self.torch = torch
+        self.lib = load()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self.h = C.c_void_p()
+        mesh = riga_mesh(p, ne, hyper_every, leaf)
+        _check(self.lib.riga_create(C.byref(self.h), C.byref(mesh), device, C.c_void_p(stream.cuda_stream)),
+               "riga_create")
+        self._c_elem = None
+        inf = riga_info_t()
+        _check(self.lib.riga_info(self.h, C.byref(inf)), "riga_info")
+        self.info = {f: getattr(inf, f) for f, _ in riga_info_t._fields_}
+        self.ndof = inf.ndof
+        self.n1d = inf.n1d
+        self.nnz = inf.nnz
+
+    def close(self):
+        if self.h:
+            self.lib.riga_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def assemble(self, alpha: float = 0.0, beta: float = 0.0, c_elem=None):
+        """c_elem: None or a float64 tensor (ne, ne) [ey, ex] on this device."""
+        if c_elem is not None:
+            c_elem = c_elem.to(device=self.device, dtype=self.torch.float64).contiguous()
+        self._c_elem = c_elem  # kept alive while the handle may read it
+        d = riga_damping(alpha, beta, _ptr(c_elem))
+        _check(self.lib.riga_assemble(self.h, C.byref(d)), "riga_assemble")
+
+    def export_csr(self, which: int):
+        torch = self.torch
+        rowptr = np.zeros(self.ndof + 1, dtype=np.int64)
+        col = np.zeros(self.nnz, dtype=np.int32)
+        val = torch.empty(self.nnz, dtype=torch.float64, device=self.device)
+        _check(self.lib.riga_export_csr(self.h, which, rowptr.ctypes.data_as(C.c_void_p),
+                                        col.ctypes.data_as(C.c_void_p), _ptr(val)), "riga_export_csr")
+        self.stream.synchronize()
+        return rowptr, col, val
+
+    def factor(self, sigma: float):
+        bad = C.c_int64(-1)
+        st = self.lib.riga_factor(self.h, sigma, C.byref(bad))
+        if st == RIGA_ERR_NOT_SPD:
+            err = RigaError(st, "riga_factor")
+            err.bad_pivot = bad.value
+            raise err
+        _check(st, "riga_factor")
+
+    def solve_q(self, b):
+        """x = Q(sigma)^{-1} b for b of shape (nrhs, ndof) (rows are vectors)."""
+        b = b.to(device=self.device, dtype=self.torch.float64).contiguous()
+        x = self.torch.empty_like(b)
+        _check(self.lib.riga_solve_q(self.h, b.shape[0], _ptr(b), _ptr(x)), "riga_solve_q")
+        return x
+
+    def apply_op(self, v):
+        """r = (A - sigma B)^{-1} B v for v of shape (nvec, 2*ndof)."""
+        v = v.to(device=self.device, dtype=self.torch.float64).contiguous()
+        r = self.torch.empty_like(v)
+        _check(self.lib.riga_apply_op(self.h, v.shape[0], _ptr(v), _ptr(r)), "riga_apply_op")
+        return r
+
+    def eigs(self, nev: int, m: int = 0, block: int = 0, tol: float = 0.0, maxit: int = 0, seed: int = 0,
+             v0=None, vectors: bool = True):
+        """Returns (lam complex ndarray, X complex tensor (nev, ndof) or None, eta ndarray, nconv, status)."""
+        torch = self.torch
+        lam = np.zeros(2 * nev)
+        eta = np.zeros(nev)
+        X = torch.empty((nev, self.ndof, 2), dtype=torch.float64, device=self.device) if vectors else None
+        if v0 is not None:
+            v0 = v0.to(device=self.device, dtype=torch.float64).contiguous()
+        opt = riga_options(nev, m, maxit, block, tol, seed, _ptr(v0))
+        nconv = C.c_int(0)
+        st = self.lib.riga_eigs(self.h, C.byref(opt), lam.ctypes.data_as(C.c_void_p), _ptr(X),
+                                eta.ctypes.data_as(C.c_void_p), C.byref(nconv))
+        _check(st, "riga_eigs", allow_warn=True)
+        Xc = torch.view_as_complex(X) if X is not None else None
+        return lam[0::2] + 1j * lam[1::2], Xc, eta, nconv.value, st
+
+    def stats(self):
+        s = riga_stats_t()
+        _check(self.lib.riga_stats(self.h, C.byref(s)), "riga_stats")
+        return {f: getattr(s, f) for f, _ in riga_stats_t._fields_}
