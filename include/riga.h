@@ -76,7 +76,8 @@ typedef struct {
 
 /* Eigensolver options (Alg. 2 and Sec. 4.1.3).
  *   nev     requested eigenpairs nearest sigma, 1 <= nev < 2N.
- *   m       Krylov subspace size, nev + block <= m <= 2N (0: max(2 nev, 20)).
+ *   m       Krylov subspace size, nev + block <= m, m <= 2N, m + 2 block <= 256
+ *           (0: max(2 nev, 20)).
  *   maxit   maximum number of restarts (0: 200).
  *   block   block size of the Krylov iteration, 1..4 (0: 2).  Blocks of 2 resolve
  *           the exact double eigenvalues of the x<->y symmetric square.
@@ -154,8 +155,9 @@ riga_status riga_apply_op(riga_problem* h, int nvec, const double* v, double* r)
  *   lam: host, 2*nev doubles (re, im) in canonical order: increasing
  *        |lam - sigma|, ties (relative 1e-9) by decreasing Im, then Re.
  *   X:   device, ndof x nev complex (interleaved re, im), column k the
- *        eigenvector of lam_k normalised to u^H M u = 1 with its largest
- *        entry real positive; or NULL.
+ *        eigenvector of lam_k normalised to u^H M u = 1 with an entry of
+ *        largest modulus real positive (among entries tied up to rounding, the
+ *        smallest dof); or NULL.
  *   eta: host, nev scaled residuals
  *        ||Q(lam)u|| / ((|lam|^2 ||M||_1 + |lam| ||C||_1 + ||K||_1) ||u||), or NULL.
  *   nconv: host, number of converged pairs returned in order.
@@ -165,6 +167,20 @@ riga_status riga_eigs(riga_problem* h, const riga_options* opt, double* lam, dou
 
 /* Operation counters of the cost model of Sec. 5.1 (eq. Cost) and phase times. */
 riga_status riga_stats(const riga_problem* h, riga_stats_t* stats);
+
+/* Measurement hook: time `reps` repetitions of one kernel family over all
+ * tree levels with HIP events on the handle's stream (synchronises).
+ *   which = 0  forward-sweep kernel, 1  backward-sweep kernel (nrhs vectors),
+ *           2  front-factorization kernel (re-factors Q(sigma) in place).
+ *   avg_ms            average duration of one launch (one tree level)
+ *   work_per_launch   algorithmic work of one launch averaged over the levels:
+ *                     bytes for the sweeps (factor entries read, lower triangle
+ *                     of L_oo^{-1} and the boundary block, plus the vectors),
+ *                     flops for the factorization (dense fronts).
+ *   launches          launches per repetition (tree levels), may be NULL.
+ * Requires a factored handle.                                                */
+riga_status riga_time_kernel(riga_problem* h, int which, int nrhs, int reps, double* avg_ms,
+                             double* work_per_launch, int* launches);
 
 /* Host-only self-test of the dense small eigensolver used for the Ritz values
  * (Rayleigh-Ritz on the projected matrix, eq. ArnoldiRitz): a is n x n real

@@ -109,7 +109,9 @@ struct riga_problem {
   int* d_level_nodes = nullptr;
   double *d_gx = nullptr, *d_gw = nullptr, *d_tabM = nullptr, *d_tabK = nullptr;
   double *d_K = nullptr, *d_M = nullptr, *d_C = nullptr;
-  double *d_L = nullptr, *d_U = nullptr, *d_upd = nullptr, *d_tmp = nullptr, *d_tmp2 = nullptr;
+  double *d_L = nullptr, *d_U = nullptr, *d_T = nullptr, *d_upd = nullptr, *d_tmp = nullptr, *d_tmp2 = nullptr;
+  int4 *d_ftasks = nullptr, *d_btasks = nullptr;   // solve tasks, grouped by level
+  std::vector<int> ftask_off, btask_off;
   int64_t* d_status = nullptr;
   double* d_part = nullptr;       // reduction scratch
   unsigned* d_ticket = nullptr;
@@ -124,6 +126,8 @@ struct riga_problem {
   double *Vu = nullptr, *Vl = nullptr, *Wl = nullptr, *Vu2 = nullptr, *Vl2 = nullptr, *Wl2 = nullptr;
   double *Ru = nullptr, *Rl = nullptr, *MRl = nullptr, *Tv = nullptr, *Mvu = nullptr;
   double *d_small = nullptr;      // device staging for h1, h2, G and small matrices
+  double *d_H = nullptr;          // device copy of the projected matrix (fast path)
+  int* d_flag = nullptr;          // breakdown flag of the fast path
   double *P = nullptr, *MP = nullptr, *CP = nullptr, *KP = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
@@ -167,14 +171,14 @@ void solve_levels(riga_problem* h, int nrhs, const double* b, int64_t ldb, doubl
   const riga::Plan& P = h->plan;
   const int H = P.height;
   for (int lv = 0; lv < H; ++lv) {
-    int a = P.level_off[lv], c = P.level_off[lv + 1] - a;
-    riga::launch_fwd_level(h->dt, h->d_level_nodes + a, c, nrhs, h->d_L, b, ldb, h->d_tmp, h->N(),
-                           h->d_upd, P.max_front, h->st);
+    int a = h->ftask_off[lv], c = h->ftask_off[lv + 1] - a;
+    riga::launch_fwd_level(h->dt, h->d_ftasks + a, c, nrhs, h->d_L, b, ldb, h->d_tmp, h->N(), h->d_upd,
+                           P.max_front, h->st);
   }
   for (int lv = H - 1; lv >= 0; --lv) {
-    int a = P.level_off[lv], c = P.level_off[lv + 1] - a;
-    riga::launch_bwd_level(h->dt, h->d_level_nodes + a, c, nrhs, h->d_L, h->d_tmp, h->N(), x, ldx,
-                           r_l, v_u, ldv, sig, P.max_front, h->st);
+    int a = h->btask_off[lv], c = h->btask_off[lv + 1] - a;
+    riga::launch_bwd_level(h->dt, h->d_btasks + a, c, nrhs, h->d_T, h->d_tmp, h->N(), x, ldx, r_l, v_u, ldv,
+                           sig, P.max_front, h->st);
   }
 }
 
@@ -208,7 +212,7 @@ void ensure_norms(riga_problem* h) {
 void ensure_krylov(riga_problem* h, int cols, int b) {
   if (h->kw_cols >= cols && h->kw_b >= b) return;
   for (double* p : {h->Vu, h->Vl, h->Wl, h->Vu2, h->Vl2, h->Wl2, h->Ru, h->Rl, h->MRl, h->Tv, h->Mvu,
-                    h->d_small})
+                    h->d_small, h->d_H})
     h->dfree(p);
   const int64_t N = h->N();
   cols = std::max<int>(cols, (int)h->kw_cols);
@@ -218,6 +222,8 @@ void ensure_krylov(riga_problem* h, int cols, int b) {
   h->Ru = h->dalloc<double>(N * b); h->Rl = h->dalloc<double>(N * b); h->MRl = h->dalloc<double>(N * b);
   h->Tv = h->dalloc<double>(N * b); h->Mvu = h->dalloc<double>(N * b);
   h->d_small = h->dalloc<double>((size_t)4 * cols * cols + 64);
+  h->d_H = h->dalloc<double>((size_t)cols * cols);
+  if (!h->d_flag) h->d_flag = h->dalloc<int>(4);
   h->kw_cols = cols; h->kw_b = b;
 }
 
@@ -320,6 +326,24 @@ riga_status riga_create(riga_problem** out, const riga_mesh* mesh, int device, v
     h->d_tabK = h->dalloc<double>((size_t)S.ne * np * np);
     h->d_K = h->dalloc<double>(P.nnz); h->d_M = h->dalloc<double>(P.nnz); h->d_C = h->dalloc<double>(P.nnz);
     h->d_L = h->dalloc<double>(P.lsize); h->d_U = h->dalloc<double>(P.usize);
+    h->d_T = h->dalloc<double>(P.lsize);
+    {
+      // Row tasks of the solve sweeps: blocks of 64 consecutive rows of one node.
+      std::vector<int4> ft, bt;
+      h->ftask_off.assign(P.height + 1, 0);
+      h->btask_off.assign(P.height + 1, 0);
+      for (int lv = 0; lv < P.height; ++lv) {
+        for (int k = P.level_off[lv]; k < P.level_off[lv + 1]; ++k) {
+          const int v = P.level_nodes[k];
+          for (int r = 0; r < P.nf[v]; r += 64) ft.push_back(int4{v, r, std::min(r + 64, P.nf[v]), 0});
+          for (int r = 0; r < P.no[v]; r += 64) bt.push_back(int4{v, r, std::min(r + 64, P.no[v]), 0});
+        }
+        h->ftask_off[lv + 1] = (int)ft.size();
+        h->btask_off[lv + 1] = (int)bt.size();
+      }
+      h->d_ftasks = h->upload(ft);
+      h->d_btasks = h->upload(bt);
+    }
     h->d_upd = h->dalloc<double>((size_t)h->upd_len * 4);
     h->d_tmp = h->dalloc<double>((size_t)P.ndof * 4);
     h->d_tmp2 = h->dalloc<double>((size_t)P.ndof * 4);
@@ -420,7 +444,7 @@ riga_status riga_factor(riga_problem* h, double sigma, int64_t* bad_pivot) {
     for (int lv = 0; lv < P.height; ++lv) {
       int a = P.level_off[lv], c = P.level_off[lv + 1] - a;
       riga::launch_front_factor(h->ds, h->dt, h->d_level_nodes + a, c, sigma * sigma, sigma, h->d_K, h->d_M,
-                                h->d_C, h->d_L, h->d_U, h->d_status, h->st);
+                                h->d_C, h->d_L, h->d_U, h->d_T, h->d_status, h->st);
     }
     ck(hipGetLastError());
     ck(hipEventRecord(h->ev1, h->st));
@@ -500,6 +524,56 @@ riga_status riga_selftest_small_eig(int n, const double* a, double* w, double* r
   return RIGA_OK;
 }
 
+riga_status riga_time_kernel(riga_problem* h, int which, int nrhs, int reps, double* avg_ms,
+                             double* work_per_launch, int* launches) {
+  if (!h || which < 0 || which > 2 || nrhs < 1 || nrhs > 4 || reps < 1 || !avg_ms || !work_per_launch)
+    return RIGA_ERR_INVALID_ARG;
+  if (!h->factored) return RIGA_ERR_STATE;
+  return run([&]() -> riga_status {
+    ck(hipSetDevice(h->device));
+    const riga::Plan& P = h->plan;
+    const int64_t N = h->N();
+    const int H = P.height;
+    // a defined right-hand side and forward state for the sweeps
+    riga::launch_random_fill(h->d_tmp2, N, nrhs, N, 12345, h->st);
+    solve_levels(h, nrhs, h->d_tmp2, N, h->d_tmp2, N, nullptr, nullptr, 0, 0.0);
+    double work = 0.0;
+    for (int v = 0; v < (int)P.nf.size(); ++v) {
+      const double o = P.no[v], b = P.nb[v], f = P.nf[v];
+      if (which == 2) work += o * o * o / 3.0 + b * o * o + b * b * o;
+      else work += 8.0 * (o * (o + 1) / 2 + b * o) + 8.0 * nrhs * (f + (which == 0 ? f : o));
+    }
+    ck(hipEventRecord(h->ev0, h->st));
+    for (int r = 0; r < reps; ++r) {
+      for (int lv = 0; lv < H; ++lv) {
+        if (which == 0) {
+          int a = h->ftask_off[lv], c = h->ftask_off[lv + 1] - a;
+          riga::launch_fwd_level(h->dt, h->d_ftasks + a, c, nrhs, h->d_L, h->d_tmp2, N, h->d_tmp, N, h->d_upd,
+                                 P.max_front, h->st);
+        } else if (which == 1) {
+          int l2 = H - 1 - lv;
+          int a = h->btask_off[l2], c = h->btask_off[l2 + 1] - a;
+          riga::launch_bwd_level(h->dt, h->d_btasks + a, c, nrhs, h->d_T, h->d_tmp, N, h->d_tmp2, N, nullptr,
+                                 nullptr, 0, 0.0, P.max_front, h->st);
+        } else {
+          int a = P.level_off[lv], c = P.level_off[lv + 1] - a;
+          riga::launch_front_factor(h->ds, h->dt, h->d_level_nodes + a, c, h->sigma * h->sigma, h->sigma, h->d_K,
+                                    h->d_M, h->d_C, h->d_L, h->d_U, h->d_T, h->d_status, h->st);
+        }
+      }
+    }
+    ck(hipGetLastError());
+    ck(hipEventRecord(h->ev1, h->st));
+    ck(hipEventSynchronize(h->ev1));
+    float ms = 0;
+    ck(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    *avg_ms = ms / ((double)reps * H);
+    *work_per_launch = work / H;
+    if (launches) *launches = H;
+    return RIGA_OK;
+  });
+}
+
 }  // extern "C"
 
 // =============================================================================
@@ -519,6 +593,7 @@ struct KrylovRun {
   double tol;
   std::vector<double> H;   // ldh x ldh, column-major
   int k = 0;               // processed columns
+  bool fast = true;        // device-resident normalisation, no host round-trip per step
   int64_t n_fb = 0, n_mv = 0, n_vv = 0;
 
   double& Hat(int r, int c) { return H[r + (size_t)c * ldh]; }
@@ -576,6 +651,28 @@ struct KrylovRun {
     riga::launch_gemm_tall(N, il, N, kin, dQ, kout, h->Vl + o, 1, N, h->st);
     riga::launch_gemm_tall(N, iml, N, kin, dQ, kout, h->Wl + o, 1, N, h->st);
     ck(hipStreamSynchronize(h->st));  // dQ is host-staged again by the next call
+  }
+
+  // Device path of orthonormalize: same arithmetic, the b x b factor computed by
+  // a one-workgroup kernel, H written on the device (dest = nullptr: not recorded).
+  void orthonormalize_device(int nc, double* dest, int col) {
+    double* h1 = h->d_small;
+    double* h2 = h->d_small + (size_t)ldh * b;
+    double* dG = h->d_small + (size_t)2 * ldh * b;
+    double* dRinv = h->d_small + (size_t)2 * ldh * b + 16;
+    if (nc > 0) {
+      riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, h1, h->st);
+      riga::launch_cgs_update(N, nc, b, h1, h->Vu, h->Ru, h->Vl, h->Rl, h->Wl, h->MRl, N, N, h->st);
+      riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, h2, h->st);
+      riga::launch_cgs_update(N, nc, b, h2, h->Vu, h->Ru, h->Vl, h->Rl, h->Wl, h->MRl, N, N, h->st);
+      n_vv += 8LL * nc * b;
+    }
+    riga::launch_dots(N, b, h->Ru, h->MRl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, dG, h->st);
+    n_vv += 2LL * b * b;
+    riga::launch_block_normalize(nc, b, nc > 0 ? h1 : nullptr, nc > 0 ? h2 : nullptr, dG, dest, ldh, col, dRinv,
+                                 h->d_flag, h->st);
+    const size_t o = (size_t)nc * N;
+    riga::launch_gemm3(N, b, dRinv, h->Ru, h->Vu + o, h->Rl, h->Vl + o, h->MRl, h->Wl + o, N, h->st);
   }
 
   void orthonormalize(int nc, std::vector<double>& hsum, std::vector<double>& R, uint64_t seed) {
@@ -654,12 +751,16 @@ struct KrylovRun {
                       1.0, nullptr, 0, h->st);
     n_fb += b;
     n_mv += 3LL * b;
-    std::vector<double> hs, R;
     const int nc = k + b;
-    orthonormalize(nc, hs, R, seed);
-    for (int q = 0; q < b; ++q) {
-      for (int c = 0; c < nc; ++c) Hat(c, k + q) = hs[c + (size_t)q * nc];
-      for (int c = 0; c < b; ++c) Hat(nc + c, k + q) = R[c + (size_t)q * b];
+    if (fast) {
+      orthonormalize_device(nc, h->d_H, k);
+    } else {
+      std::vector<double> hs, R;
+      orthonormalize(nc, hs, R, seed);
+      for (int q = 0; q < b; ++q) {
+        for (int c = 0; c < nc; ++c) Hat(c, k + q) = hs[c + (size_t)q * nc];
+        for (int c = 0; c < b; ++c) Hat(nc + c, k + q) = R[c + (size_t)q * b];
+      }
     }
     k += b;
   }
@@ -679,7 +780,7 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
   const double tol = opt->tol > 0 ? opt->tol : 1e-12;
   if (nev < 1 || b < 1 || b > 4 || (int64_t)nev >= 2 * N) return RIGA_ERR_INVALID_ARG;
   if ((int64_t)m > 2 * N) m = (int)(2 * N);
-  if (m < nev + b || m + b > 400) return RIGA_ERR_INVALID_ARG;
+  if (m < nev + b || m + 2 * b > 256) return RIGA_ERR_INVALID_ARG;
   return run([&]() -> riga_status {
     ck(hipSetDevice(h->device));
     ensure_norms(h);
@@ -687,7 +788,23 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     ensure_krylov(h, ldh, b);
     ck(hipEventRecord(h->ev0, h->st));
     KrylovRun kr{h, N, b, m, nev, maxit, ldh, tol};
+    int it = 0;
+    bool converged = false;
+    std::vector<cplx> T, Z, Y;
+    std::vector<int> wanted;
+    std::vector<cplx> theta;
+    uint64_t step_seed = opt->seed * 1000003u + 5;
+    // First attempt on the fast path; a breakdown reported by the device sends
+    // the solve once more through the host-checked path.
+    for (int attempt = 0; attempt < 2; ++attempt) {
+    kr.fast = (attempt == 0);
     kr.H.assign((size_t)ldh * ldh, 0.0);
+    kr.n_fb = kr.n_mv = kr.n_vv = 0;
+    it = 0;
+    converged = false;
+    step_seed = opt->seed * 1000003u + 5;
+    ck(hipMemsetAsync(h->d_flag, 0, sizeof(int), h->st));
+    ck(hipMemsetAsync(h->d_H, 0, sizeof(double) * (size_t)ldh * ldh, h->st));
     // start block, B-orthonormalised
     if (opt->v0) {
       for (int q = 0; q < b; ++q) {
@@ -702,19 +819,23 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     }
     riga::launch_spmv(h->ds, N, b, h->d_M, 1.0, nullptr, 0, nullptr, 0, h->Rl, N, h->MRl, N, nullptr, 0, 0.0,
                       nullptr, 0, h->st);
-    {
+    if (kr.fast) {
+      kr.orthonormalize_device(0, nullptr, 0);
+    } else {
       std::vector<double> hs, R;
       kr.orthonormalize(0, hs, R, opt->seed + 99);
     }
     kr.k = 0;
-    int it = 0;
-    bool converged = false;
-    std::vector<cplx> T, Z, Y;
-    std::vector<int> wanted;
-    std::vector<cplx> theta;
-    uint64_t step_seed = opt->seed * 1000003u + 5;
+    bool broke = false;
     for (;;) {
       while (kr.k + b <= m) kr.step(step_seed++);
+      if (kr.fast) {
+        int flag = 0;
+        ck(hipMemcpyAsync(kr.H.data(), h->d_H, sizeof(double) * (size_t)ldh * ldh, hipMemcpyDeviceToHost, h->st));
+        ck(hipMemcpyAsync(&flag, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, h->st));
+        ck(hipStreamSynchronize(h->st));
+        if (flag) { broke = true; break; }
+      }
       const int k = kr.k;
       // Rayleigh--Ritz on H_k (eq. ArnoldiRitz)
       std::vector<double> Hk((size_t)k * k);
@@ -805,8 +926,12 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
         for (int rr = 0; rr < r; ++rr) kr.Hat(rr, c) = Tn[rr + (size_t)c * r];
         for (int rr = 0; rr < b; ++rr) kr.Hat(r + rr, c) = En[rr + (size_t)c * b];
       }
+      if (kr.fast)
+        ck(hipMemcpyAsync(h->d_H, kr.H.data(), sizeof(double) * (size_t)ldh * ldh, hipMemcpyHostToDevice, h->st));
       kr.k = r;
     }
+    if (!broke) break;
+    }  // attempts
     // --- eigenpairs: u = V_u y for the wanted Ritz vectors --------------------------
     const int k = kr.k;
     const int nw = (int)wanted.size();

@@ -12,6 +12,15 @@
 // blocked Cholesky with 16-wide panels: the diagonal 16x16 block by one wave in
 // LDS, the panel below by a row-parallel triangular solve, and the trailing
 // lower triangle (including the update block) by FP64 MFMA 16x16x4 tiles.
+//
+// For the solves the factor columns are then replaced by
+//   F = [L_oo^{-1}; L_bo L_oo^{-1}],
+// obtained row by row from X L_oo = [I; L_bo] (a triangular solve from the
+// right, MFMA for the panel updates).  F is kept column-major in the L block
+// and transposed (no x nf, column-major) in the T block, so each sweep of a
+// forward/backward solve is one matrix-vector product per node:
+//   forward   [y_own; w] = F f_own,  update to the parent = f_bnd - w
+//   backward  x_own = F^T [y_own; -x_bnd].
 #include "kernels.hpp"
 #include "mfma_layout.hpp"
 
@@ -31,7 +40,8 @@ __global__ __launch_bounds__(FT) void k_front_factor(
     int n, const int* __restrict__ lo, const int* __restrict__ hi, const int64_t* __restrict__ rowptr,
     DevTree t, const int* __restrict__ level_nodes, double s2, double s1,
     const double* __restrict__ Kv, const double* __restrict__ Mv, const double* __restrict__ Cv,
-    double* __restrict__ Lbuf, double* __restrict__ Ubuf, int64_t* __restrict__ status) {
+    double* __restrict__ Lbuf, double* __restrict__ Ubuf, double* __restrict__ Tbuf,
+    int64_t* __restrict__ status) {
   const int v = level_nodes[blockIdx.x];
   Front F{Lbuf + t.loff[v], Ubuf + t.uoff[v], t.nf[v], t.no[v], t.nb[v]};
   const int nf = F.nf, no = F.no, nb = F.nb;
@@ -174,14 +184,81 @@ __global__ __launch_bounds__(FT) void k_front_factor(
     }
     __syncthreads();
   }
+
+  // --- E: X L_oo = [I; L_bo], row tiles per wave, panels from the right --------------
+  double* T = Tbuf + t.loff[v];      // X row r at T[r * no + 0 .. no)
+  __shared__ double tb[FT / 64][PW][PW + 1];
+  __shared__ double lp[FT / 64][PW][PW + 1];
+  const int npan = (no + PW - 1) / PW;
+  const int nrt = (nf + PW - 1) / PW;
+  for (int rt = wave; rt < nrt; rt += FT / 64) {
+    const int r0 = rt * PW;
+    for (int P = npan - 1; P >= 0; --P) {
+      const int c0 = P * PW, w = min(PW, no - c0);
+      const bool top = (r0 + PW <= no);          // every row of the tile is an own row
+      if (top && r0 + PW - 1 < c0) {             // X[r][c] = 0 for c > r < no
+        for (int idx = lane; idx < PW * PW; idx += 64) {
+          int i = idx / PW, j = idx % PW;
+          if (j < w) T[(int64_t)(r0 + i) * no + c0 + j] = 0.0;
+        }
+        continue;
+      }
+      dvec4 acc;
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) {
+        const int r = r0 + mfma_d_row(lane, vv), c = c0 + mfma_d_col(lane);
+        double val = 0.0;
+        if (r < nf && c < c0 + w) val = (r < no) ? (r == c ? 1.0 : 0.0) : F.L[(int64_t)c * nf + r];
+        acc[vv] = val;
+      }
+      // minus X[r][k] L_oo[k][c] over the already solved columns k >= c0 + w
+      const int kend = top ? min(no, r0 + PW) : no;
+      for (int k0 = c0 + w; k0 < kend; k0 += 4) {
+        const int ra = r0 + mfma_a_row(lane), ka = k0 + mfma_ab_k(lane);
+        const int cb = c0 + mfma_b_col(lane);
+        const double av = (ra < nf && ka < no) ? -T[(int64_t)ra * no + ka] : 0.0;
+        const double bv = (ka < no && cb < c0 + w) ? F.L[(int64_t)cb * nf + ka] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) tb[wave][mfma_d_row(lane, vv)][mfma_d_col(lane)] = acc[vv];
+      for (int idx = lane; idx < PW * PW; idx += 64) {
+        int i = idx / PW, j = idx % PW;
+        lp[wave][i][j] = (i < w && j <= i) ? F.L[(int64_t)(c0 + j) * nf + c0 + i] : 0.0;
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      if (lane < PW) {  // row lane: x L_PP = acc, from the last column back
+        for (int j = w - 1; j >= 0; --j) {
+          double sacc = tb[wave][lane][j];
+          for (int k = j + 1; k < w; ++k) sacc -= tb[wave][lane][k] * lp[wave][k][j];
+          tb[wave][lane][j] = sacc / lp[wave][j][j];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      for (int idx = lane; idx < PW * PW; idx += 64) {
+        int i = idx / PW, j = idx % PW;
+        if (r0 + i < nf && j < w) T[(int64_t)(r0 + i) * no + c0 + j] = tb[wave][i][j];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  // F column-major into the L block
+  for (int64_t idx = tid; idx < (int64_t)nf * no; idx += FT) {
+    const int r = (int)(idx % nf), a = (int)(idx / nf);
+    F.L[idx] = T[(int64_t)r * no + a];
+  }
 }
 
 void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count,
                          double s2, double s1, const double* K, const double* M, const double* C,
-                         double* L, double* U, int64_t* status, hipStream_t st) {
+                         double* L, double* U, double* T, int64_t* status, hipStream_t st) {
   if (count <= 0) return;
   hipLaunchKernelGGL(k_front_factor, dim3(count), dim3(FT), 0, st, s.n, s.lo, s.hi, s.rowptr, t,
-                     level_nodes, s2, s1, K, M, C, L, U, status);
+                     level_nodes, s2, s1, K, M, C, L, U, T, status);
 }
 
 }  // namespace riga

@@ -91,8 +91,9 @@ void launch_spmv(const DevSpace& s, int64_t ndof, int ncols,
 // ---------------------------------------------------------------------------
 // Multi-dot products out[c][q] = sum_i Au[i,c] Xu[i,q] + Al[i,c] Xl[i,q]:
 // each block owns a slice of rows, each wave owns a set of columns c and its
-// lanes stride the slice; partial sums per block are combined by the last
-// block to finish, in block order (deterministic).
+// lanes stride the slice (coalesced loads, two columns in flight per wave).
+// Per-block partial sums are stored output-major, partial[(c*NQ+q)*nblk + blk],
+// and a second kernel reduces each output with one wave (deterministic order).
 constexpr int DOT_THREADS = 256;
 
 int dots_blocks(int64_t n) {
@@ -104,59 +105,73 @@ template <int NQ>
 __global__ __launch_bounds__(DOT_THREADS) void k_dots(
     int64_t n, int nc, const double* __restrict__ Au, const double* __restrict__ Al, int64_t lda,
     const double* __restrict__ Xu, const double* __restrict__ Xl, int64_t ldx,
-    double* __restrict__ partial, unsigned* __restrict__ ticket, double* __restrict__ out) {
+    double* __restrict__ partial) {
   const int nblk = gridDim.x;
   const int64_t per = (n + nblk - 1) / nblk;
   const int64_t i0 = (int64_t)blockIdx.x * per;
   const int64_t i1 = min(n, i0 + per);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int c = wave; c < nc; c += DOT_THREADS / 64) {
-    double acc[NQ];
+  constexpr int NW = DOT_THREADS / 64;
+  for (int c = wave; c < nc; c += 2 * NW) {
+    const int c2 = c + NW;
+    const bool two = c2 < nc;
+    double acc[NQ], acc2[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    for (int q = 0; q < NQ; ++q) { acc[q] = 0.0; acc2[q] = 0.0; }
     const double* au = Au + (int64_t)c * lda;
     const double* al = Al ? Al + (int64_t)c * lda : nullptr;
+    const double* bu = Au + (int64_t)(two ? c2 : c) * lda;
+    const double* bl = Al ? Al + (int64_t)(two ? c2 : c) * lda : nullptr;
     for (int64_t i = i0 + lane; i < i1; i += 64) {
-      const double u = au[i];
+      const double u = au[i], u2 = bu[i];
+      const double l = al ? al[i] : 0.0, l2 = bl ? bl[i] : 0.0;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) acc[q] += u * Xu[i + q * ldx];
-      if (al) {
-        const double l = al[i];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) acc[q] += l * Xl[i + q * ldx];
+      for (int q = 0; q < NQ; ++q) {
+        const double xu = Xu[i + q * ldx];
+        const double xl = Xl ? Xl[i + q * ldx] : 0.0;
+        acc[q] += u * xu + l * xl;
+        acc2[q] += u2 * xu + l2 * xl;
       }
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off, 64);
-    if (lane == 0)
+      for (int off = 32; off > 0; off >>= 1) {
+        acc[q] += __shfl_xor(acc[q], off, 64);
+        acc2[q] += __shfl_xor(acc2[q], off, 64);
+      }
+    if (lane == 0) {
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) partial[((int64_t)blockIdx.x * nc + c) * NQ + q] = acc[q];
+      for (int q = 0; q < NQ; ++q) {
+        partial[((int64_t)c * NQ + q) * nblk + blockIdx.x] = acc[q];
+        if (two) partial[((int64_t)c2 * NQ + q) * nblk + blockIdx.x] = acc2[q];
+      }
+    }
   }
-  __threadfence();
-  __syncthreads();
-  __shared__ bool last;
-  if (threadIdx.x == 0) last = (atomicAdd(ticket, 1u) == (unsigned)(nblk - 1));
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  for (int idx = threadIdx.x; idx < nc * NQ; idx += DOT_THREADS) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += __builtin_nontemporal_load(&partial[(int64_t)b * nc * NQ + idx]);
-    out[idx] = s;
-  }
-  if (threadIdx.x == 0) atomicExch(ticket, 0u);
+}
+
+__global__ __launch_bounds__(256) void k_dots_final(int nout, int nblk, const double* __restrict__ partial,
+                                                    double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (idx >= nout) return;
+  const double* p = partial + (int64_t)idx * nblk;
+  double s = 0.0;
+  for (int b = lane; b < nblk; b += 64) s += p[b];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) out[idx] = s;
 }
 
 void launch_dots(int64_t n, int nc, const double* Au, const double* Al, int64_t lda,
                  int nq, const double* Xu, const double* Xl, int64_t ldx,
                  double* partial, unsigned* ticket, double* out, hipStream_t st) {
+  (void)ticket;
   if (nc <= 0) return;
   int blocks = dots_blocks(n);
 #define RIGA_DOTS(NQ)                                                                          \
   hipLaunchKernelGGL(k_dots<NQ>, dim3(blocks), dim3(DOT_THREADS), 0, st, n, nc, Au, Al, lda, Xu, \
-                     Xl, ldx, partial, ticket, out)
+                     Xl, ldx, partial)
   switch (nq) {
     case 1: RIGA_DOTS(1); break;
     case 2: RIGA_DOTS(2); break;
@@ -164,6 +179,8 @@ void launch_dots(int64_t n, int nc, const double* Au, const double* Al, int64_t 
     default: RIGA_DOTS(4); break;
   }
 #undef RIGA_DOTS
+  const int nout = nc * nq;
+  hipLaunchKernelGGL(k_dots_final, dim3((nout + 3) / 4), dim3(256), 0, st, nout, blocks, partial, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -220,30 +237,44 @@ void launch_cgs_update(int64_t n, int nc, int nq, const double* h,
 
 // ---------------------------------------------------------------------------
 // Out = In * Q for a tall In (n x kin) and a small Q (kin x kout) held in LDS.
+// Thread per row; 32 output columns per pass kept in registers; the inner
+// loop issues 8 independent coalesced loads of In before using them.
 constexpr int GEMM_THREADS = 256;
-constexpr int GEMM_CHUNK = 8;
+constexpr int GEMM_CHUNK = 32;
+constexpr int GEMM_UNROLL = 8;
 
 __global__ __launch_bounds__(GEMM_THREADS) void k_gemm_tall(
     int64_t n, const double* __restrict__ In, int64_t ldi, int kin, const double* __restrict__ Q,
     int kout, double* __restrict__ Out, int64_t out_rs, int64_t out_cs) {
-  extern __shared__ double qs[];
-  for (int k = threadIdx.x; k < kin * kout; k += GEMM_THREADS) qs[k] = Q[k];
-  __syncthreads();
+  extern __shared__ double qs[];   // qs[tt * GEMM_CHUNK + c] for the current chunk
   const int64_t i = (int64_t)blockIdx.x * GEMM_THREADS + threadIdx.x;
-  if (i >= n) return;
+  const bool live = i < n;
   for (int c0 = 0; c0 < kout; c0 += GEMM_CHUNK) {
+    const int kc = min(GEMM_CHUNK, kout - c0);
+    __syncthreads();
+    for (int k = threadIdx.x; k < kin * GEMM_CHUNK; k += GEMM_THREADS) {
+      const int tt = k / GEMM_CHUNK, c = k % GEMM_CHUNK;
+      qs[k] = (c < kc) ? Q[(int64_t)(c0 + c) * kin + tt] : 0.0;
+    }
+    __syncthreads();
+    if (!live) continue;
     double acc[GEMM_CHUNK];
 #pragma unroll
     for (int c = 0; c < GEMM_CHUNK; ++c) acc[c] = 0.0;
-    for (int tt = 0; tt < kin; ++tt) {
-      const double a = In[i + (int64_t)tt * ldi];
+    for (int t0 = 0; t0 < kin; t0 += GEMM_UNROLL) {
+      double a[GEMM_UNROLL];
 #pragma unroll
-      for (int c = 0; c < GEMM_CHUNK; ++c)
-        if (c0 + c < kout) acc[c] += a * qs[(c0 + c) * kin + tt];
+      for (int u = 0; u < GEMM_UNROLL; ++u) a[u] = (t0 + u < kin) ? In[i + (int64_t)(t0 + u) * ldi] : 0.0;
+#pragma unroll
+      for (int u = 0; u < GEMM_UNROLL; ++u) {
+        const int tt = min(t0 + u, kin - 1);
+#pragma unroll
+        for (int c = 0; c < GEMM_CHUNK; ++c) acc[c] += a[u] * qs[tt * GEMM_CHUNK + c];
+      }
     }
 #pragma unroll
     for (int c = 0; c < GEMM_CHUNK; ++c)
-      if (c0 + c < kout) Out[i * out_rs + (int64_t)(c0 + c) * out_cs] = acc[c];
+      if (c < kc) Out[i * out_rs + (int64_t)(c0 + c) * out_cs] = acc[c];
   }
 }
 
@@ -251,14 +282,11 @@ void launch_gemm_tall(int64_t n, const double* In, int64_t ldi, int kin, const d
                       double* Out, int64_t out_rs, int64_t out_cs, hipStream_t st) {
   if (kout <= 0 || kin <= 0) return;
   int64_t blocks = (n + GEMM_THREADS - 1) / GEMM_THREADS;
-  // Q columns in chunks that keep the LDS copy within 48 KB
-  const int cols = std::max(1, std::min(kout, (int)(6144 / kin)));
-  for (int c0 = 0; c0 < kout; c0 += cols) {
-    const int kc = std::min(cols, kout - c0);
-    size_t shm = (size_t)kin * kc * sizeof(double);
-    hipLaunchKernelGGL(k_gemm_tall, dim3((unsigned)blocks), dim3(GEMM_THREADS), shm, st, n, In, ldi, kin,
-                       Q + (size_t)c0 * kin, kc, Out + (int64_t)c0 * out_cs, out_rs, out_cs);
-  }
+  // the Q rows in LDS: kin x 32 doubles per pass, at most 64 KB
+  // callers keep kin <= 256 (the subspace size plus one block)
+  size_t shm = (size_t)kin * GEMM_CHUNK * sizeof(double);
+  hipLaunchKernelGGL(k_gemm_tall, dim3((unsigned)blocks), dim3(GEMM_THREADS), shm, st, n, In, ldi, kin, Q,
+                     kout, Out, out_rs, out_cs);
 }
 
 // ---------------------------------------------------------------------------
@@ -422,6 +450,116 @@ __global__ __launch_bounds__(256) void k_rowabs(const int64_t* __restrict__ rowp
 void launch_rowabs(const int64_t* rowptr, int64_t ndof, const double* A, double* part, int nblk,
                    hipStream_t st) {
   hipLaunchKernelGGL(k_rowabs, dim3(nblk), dim3(256), 0, st, rowptr, ndof, A, part);
+}
+
+// ---------------------------------------------------------------------------
+// Device-side end of a block Gram--Schmidt step: with h1, h2 (nc x nq, the two
+// projection passes, output-major c*nq+q) and G (nq x nq, the B-Gram matrix of
+// the projected block), write H[0:nc, k+q] = h1 + h2, factor G = R^T R, write
+// H[nc+c, k+q] = R[c][q] and Rinv = R^{-1} (column-major nq x nq).  A column
+// whose squared B-norm after projection falls below 1e-24 of its norm before
+// projection (an invariant subspace was reached) sets *flag = 1; the caller
+// then redoes the solve on the host-checked path.
+__global__ void k_block_normalize(int nc, int nq, const double* __restrict__ h1, const double* __restrict__ h2,
+                                  const double* __restrict__ G, double* __restrict__ H, int ldh, int k,
+                                  double* __restrict__ Rinv, int* __restrict__ flag) {
+  for (int idx = threadIdx.x; H && idx < nc * nq; idx += blockDim.x) {
+    const int c = idx / nq, q = idx % nq;
+    H[c + (int64_t)(k + q) * ldh] = (h1 ? h1[idx] : 0.0) + (h2 ? h2[idx] : 0.0);
+  }
+  // squared norms of the projection coefficients, one wave per column q
+  __shared__ double hn[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (wv < nq) {
+    double sacc = 0.0;
+    for (int c = lane; c < nc; c += 64) {
+      const double hv = (h1 ? h1[c * nq + wv] : 0.0) + (h2 ? h2[c * nq + wv] : 0.0);
+      sacc += hv * hv;
+    }
+    for (int off = 32; off > 0; off >>= 1) sacc += __shfl_xor(sacc, off, 64);
+    if (lane == 0) hn[wv] = sacc;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double R[4][4] = {{0}}, X[4][4] = {{0}};
+  bool bad = false;
+  for (int j = 0; j < nq; ++j) {
+    const double n0 = G[j * nq + j] + hn[j];
+    for (int i = 0; i <= j; ++i) {
+      double sacc = 0.5 * (G[i * nq + j] + G[j * nq + i]);
+      for (int kk = 0; kk < i; ++kk) sacc -= R[kk][i] * R[kk][j];
+      if (i == j) {
+        if (!(sacc > 1e-24 * n0)) { bad = true; sacc = 1.0; }
+        R[j][j] = sqrt(sacc);
+      } else {
+        R[i][j] = sacc / R[i][i];
+      }
+    }
+  }
+  for (int j = 0; j < nq; ++j) {
+    X[j][j] = 1.0 / R[j][j];
+    for (int i = j - 1; i >= 0; --i) {
+      double sacc = 0.0;
+      for (int kk = i + 1; kk <= j; ++kk) sacc += R[i][kk] * X[kk][j];
+      X[i][j] = -sacc / R[i][i];
+    }
+  }
+  for (int q = 0; q < nq; ++q)
+    for (int c = 0; c < nq; ++c) {
+      if (H) H[nc + c + (int64_t)(k + q) * ldh] = R[c][q];
+      Rinv[c + q * nq] = X[c][q];
+    }
+  if (bad) *flag = 1;
+}
+
+void launch_block_normalize(int nc, int nq, const double* h1, const double* h2, const double* G, double* H,
+                            int ldh, int k, double* Rinv, int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_block_normalize, dim3(1), dim3(256), 0, st, nc, nq, h1, h2, G, H, ldh, k, Rinv, flag);
+}
+
+// Out_m[:, 0:nq] = In_m[:, 0:nq] Q for three (In, Out) pairs; Q nq x nq on the device.
+template <int NQ>
+__global__ __launch_bounds__(256) void k_gemm3(int64_t n, const double* __restrict__ Q,
+                                               const double* __restrict__ I0, double* __restrict__ O0,
+                                               const double* __restrict__ I1, double* __restrict__ O1,
+                                               const double* __restrict__ I2, double* __restrict__ O2,
+                                               int64_t ld) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double q[NQ][NQ];
+#pragma unroll
+  for (int a = 0; a < NQ; ++a)
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) q[a][c] = Q[a + c * NQ];
+  const double* Is[3] = {I0, I1, I2};
+  double* Os[3] = {O0, O1, O2};
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    double x[NQ];
+#pragma unroll
+    for (int a = 0; a < NQ; ++a) x[a] = Is[m][i + a * ld];
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < NQ; ++a) acc += x[a] * q[a][c];
+      Os[m][i + c * ld] = acc;
+    }
+  }
+}
+
+void launch_gemm3(int64_t n, int nq, const double* Q, const double* I0, double* O0, const double* I1, double* O1,
+                  const double* I2, double* O2, int64_t ld, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+#define RIGA_G3(NQ) \
+  hipLaunchKernelGGL(k_gemm3<NQ>, dim3((unsigned)blocks), dim3(256), 0, st, n, Q, I0, O0, I1, O1, I2, O2, ld)
+  switch (nq) {
+    case 1: RIGA_G3(1); break;
+    case 2: RIGA_G3(2); break;
+    case 3: RIGA_G3(3); break;
+    default: RIGA_G3(4); break;
+  }
+#undef RIGA_G3
 }
 
 }  // namespace riga

@@ -1,32 +1,63 @@
 // Forward and backward sweeps with the multifrontal factor (Sec. 5.2.2: one
 // forward/backward elimination per Arnoldi step, line 8 of Alg. 2).
 //
-// Forward (leaves to root), per node v, front vector f (own then boundary):
-//   f_own = b[own] + sum of the children's update vectors mapped into the front,
-//   y_own = L_oo^{-1} f_own,   upd_v = f_bnd - L_bo y_own  (kept for the parent).
-// Backward (root to leaves):
-//   x_own = L_oo^{-T} (y_own - L_bo^T x[bnd]).
-// The forward pass gathers children's vectors instead of scattering into shared
-// boundary entries, so neither sweep needs atomics and results are bitwise
-// reproducible.  One workgroup per node; up to 4 right-hand sides share every
-// read of the factor.
+// The factorization leaves, per node, F = [L_oo^{-1}; L_bo L_oo^{-1}]
+// (nf x no, column-major) and its transpose.  With the front vector f (own
+// entries of the right-hand side plus the children's update vectors):
+//   forward   y_own = L_oo^{-1} f_own,   upd_v = f_bnd - (L_bo L_oo^{-1}) f_own
+//             i.e. one product F f_own;
+//   backward  x_own = L_oo^{-T} (y_own - L_bo^T x_bnd)
+//                   = L_oo^{-T} y_own - (L_bo L_oo^{-1})^T x_bnd
+//             i.e. one product F^T [y_own; -x_bnd].
+// Every node is therefore a single matrix-vector product with no dependency
+// chain inside it; only the tree levels are sequential.  A node's rows are split
+// into tasks of 64 rows (one workgroup each: lane = row, the 8 waves take
+// interleaved 8-column chunks, partial sums combined in LDS), so every load of
+// F is coalesced and each row has many loads in flight; up to 4 right-hand
+// sides share every load.
+// The forward pass gathers children's vectors instead of scattering into
+// shared boundary entries, so neither sweep needs atomics and results are
+// bitwise reproducible.
 #include "kernels.hpp"
 
 namespace riga {
 
-constexpr int ST = 256;
-constexpr int SW = 16;   // substitution panel width
+constexpr int ST = 512;           // threads per task: 8 waves
+constexpr int SR = 64;            // rows per task: one per lane
+constexpr int SC = 8;             // consecutive columns per wave and round
+constexpr int SW = ST / 64;
+
+// acc[q] of row `lane` summed over the waves through LDS; wave 0 ends with the
+// total for its lane.
+template <int NR>
+__device__ __forceinline__ void reduce_waves(double (&acc)[NR], double* red, int lane, int wave) {
+#pragma unroll
+  for (int q = 0; q < NR; ++q) red[(wave * SR + lane) * NR + q] = acc[q];
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < SW; ++w2) s2 += red[(w2 * SR + lane) * NR + q];
+      acc[q] = s2;
+    }
+  }
+}
 
 template <int NR>
-__global__ __launch_bounds__(ST) void k_fwd(DevTree t, const int* __restrict__ level_nodes,
+__global__ __launch_bounds__(ST) void k_fwd(DevTree t, const int4* __restrict__ tasks,
                                             const double* __restrict__ Lbuf,
                                             const double* __restrict__ b, int64_t ldb,
                                             double* __restrict__ y, int64_t ldy,
                                             double* __restrict__ upd) {
-  extern __shared__ double f[];   // f[pos * NR + q]
-  const int v = level_nodes[blockIdx.x];
-  const int nf = t.nf[v], no = t.no[v], nb = t.nb[v];
-  const double* L = Lbuf + t.loff[v];
+  extern __shared__ double shm[];
+  double* f = shm;                       // f[pos * NR + q], front vector
+  const int4 tk = tasks[blockIdx.x];
+  const int v = tk.x, r0 = tk.y, r1 = tk.z;
+  const int nf = t.nf[v], no = t.no[v];
+  double* red = shm + (size_t)nf * NR;   // SW x SR x NR partial sums
+  const double* F = Lbuf + t.loff[v];
   const int* fd = t.fdofs + t.foff[v];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
@@ -44,73 +75,53 @@ __global__ __launch_bounds__(ST) void k_fwd(DevTree t, const int* __restrict__ l
       for (int q = 0; q < NR; ++q) f[mp[k] * NR + q] += uc[k * NR + q];
     __syncthreads();
   }
-
-  for (int k0 = 0; k0 < no; k0 += SW) {
-    const int w = min(SW, no - k0);
-    // diagonal block: lane (q, r) holds row r of the block for right-hand side q
-    if (wave == 0 && lane < SW * NR) {
-      const int r = lane % SW, q = lane / SW;
-      double row[SW];
+  const int r = r0 + lane;
+  const bool live = r < r1;
+  // columns past the diagonal of L_oo^{-1} are exact zeros: an own-row block
+  // stops at its last row's diagonal
+  const int jend = (r1 - 1 < no) ? r1 : no;
+  double acc[NR];
 #pragma unroll
-      for (int c = 0; c < SW; ++c) row[c] = (r < w && c <= r) ? L[(int64_t)(k0 + c) * nf + k0 + r] : 0.0;
-      double fr = (r < w) ? f[(k0 + r) * NR + q] : 0.0;
+  for (int q = 0; q < NR; ++q) acc[q] = 0.0;
+  const double* col = F + (live ? r : r0);
+  for (int j0 = wave * SC; j0 < jend; j0 += SW * SC) {
+    double a[SC];
 #pragma unroll
-      for (int c = 0; c < SW; ++c) {
-        if (c < w) {
-          if (r == c) fr = fr / row[c];
-          double yc = __shfl(fr, q * SW + c, 64);
-          if (r > c) fr -= row[c] * yc;
-        }
-      }
-      if (r < w) f[(k0 + r) * NR + q] = fr;
+    for (int u = 0; u < SC; ++u) a[u] = (j0 + u < jend) ? col[(int64_t)(j0 + u) * nf] : 0.0;
+#pragma unroll
+    for (int u = 0; u < SC; ++u) {
+      const int j = min(j0 + u, jend - 1);
+#pragma unroll
+      for (int q = 0; q < NR; ++q) acc[q] += a[u] * f[j * NR + q];
     }
-    __syncthreads();
-    // rows below the block
-    for (int i = k0 + w + tid; i < nf; i += ST) {
-      double acc[NR];
-#pragma unroll
-      for (int q = 0; q < NR; ++q) acc[q] = f[i * NR + q];
-#pragma unroll
-      for (int c = 0; c < SW; ++c) {
-        if (c < w) {
-          double l = L[(int64_t)(k0 + c) * nf + i];
-#pragma unroll
-          for (int q = 0; q < NR; ++q) acc[q] -= l * f[(k0 + c) * NR + q];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < NR; ++q) f[i * NR + q] = acc[q];
-    }
-    __syncthreads();
   }
-  for (int p = tid; p < no; p += ST)
+  reduce_waves<NR>(acc, red, lane, wave);
+  if (wave == 0 && live) {
+    if (r < no) {
 #pragma unroll
-    for (int q = 0; q < NR; ++q) y[fd[p] + q * ldy] = f[p * NR + q];
-  double* uv = upd + (int64_t)t.voff[v] * NR;
-  for (int k = tid; k < nb; k += ST)
+      for (int q = 0; q < NR; ++q) y[fd[r] + q * ldy] = acc[q];
+    } else {
+      double* uv = upd + (int64_t)(t.voff[v] + r - no) * NR;
 #pragma unroll
-    for (int q = 0; q < NR; ++q) uv[k * NR + q] = f[(no + k) * NR + q];
+      for (int q = 0; q < NR; ++q) uv[q] = f[r * NR + q] - acc[q];
+    }
+  }
 }
 
 template <int NR>
-__device__ __forceinline__ void wave_sum(double (&a)[NR]) {
-#pragma unroll
-  for (int q = 0; q < NR; ++q)
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) a[q] += __shfl_xor(a[q], off, 64);
-}
-
-template <int NR>
-__global__ __launch_bounds__(ST) void k_bwd(DevTree t, const int* __restrict__ level_nodes,
-                                            const double* __restrict__ Lbuf,
+__global__ __launch_bounds__(ST) void k_bwd(DevTree t, const int4* __restrict__ tasks,
+                                            const double* __restrict__ Tbuf,
                                             const double* __restrict__ y, int64_t ldy,
                                             double* __restrict__ x, int64_t ldx,
                                             double* __restrict__ r_l, const double* __restrict__ v_u,
                                             int64_t ldv, double sig) {
-  extern __shared__ double s[];   // s[pos * NR + q]: own rhs / solution, then x on the boundary
-  const int v = level_nodes[blockIdx.x];
-  const int nf = t.nf[v], no = t.no[v], nb = t.nb[v];
-  const double* L = Lbuf + t.loff[v];
+  extern __shared__ double shm[];
+  double* w = shm;                       // [y_own; -x_bnd]
+  const int4 tk = tasks[blockIdx.x];
+  const int v = tk.x, a0 = tk.y, a1 = tk.z;
+  const int nf = t.nf[v], no = t.no[v];
+  double* red = shm + (size_t)nf * NR;
+  const double* T = Tbuf + t.loff[v];   // element (a, i) of F^T at T[i * no + a]
   const int* fd = t.fdofs + t.foff[v];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool epilogue = (r_l != nullptr);
@@ -119,115 +130,80 @@ __global__ __launch_bounds__(ST) void k_bwd(DevTree t, const int* __restrict__ l
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
       double val;
-      if (p < no) val = y[fd[p] + q * ldy];
-      else {
+      if (p < no) {
+        val = y[fd[p] + q * ldy];
+      } else {
         val = x[fd[p] + q * ldx];
-        if (epilogue) val = -val;   // ancestors stored r_u = -x
+        if (!epilogue) val = -val;   // with the epilogue, ancestors stored r_u = -x already
       }
-      s[p * NR + q] = val;
+      w[p * NR + q] = val;
     }
   __syncthreads();
-  // own -= L_bo^T x_bnd: one wave per column, lanes along the column
-  if (nb > 0) {
-    for (int a = wave; a < no; a += ST / 64) {
-      double acc[NR];
+  const int a = a0 + lane;
+  const bool live = a < a1;
+  double acc[NR];
 #pragma unroll
-      for (int q = 0; q < NR; ++q) acc[q] = 0.0;
-      const double* col = L + (int64_t)a * nf + no;
-      for (int k = lane; k < nb; k += 64) {
-        double l = col[k];
+  for (int q = 0; q < NR; ++q) acc[q] = 0.0;
+  // entries above the diagonal of L_oo^{-T} vanish: start at the block's first row
+  const double* row = T + (live ? a : a0);
+  for (int i0 = a0 + wave * SC; i0 < nf; i0 += SW * SC) {
+    double e[SC];
 #pragma unroll
-        for (int q = 0; q < NR; ++q) acc[q] += l * s[(no + k) * NR + q];
-      }
-      wave_sum<NR>(acc);
-      if (lane == 0)
+    for (int u = 0; u < SC; ++u) e[u] = (i0 + u < nf) ? row[(int64_t)(i0 + u) * no] : 0.0;
 #pragma unroll
-        for (int q = 0; q < NR; ++q) s[a * NR + q] -= acc[q];
+    for (int u = 0; u < SC; ++u) {
+      const int i = min(i0 + u, nf - 1);
+#pragma unroll
+      for (int q = 0; q < NR; ++q) acc[q] += e[u] * w[i * NR + q];
     }
-    __syncthreads();
   }
-  const int last = ((no - 1) / SW) * SW;
-  for (int k0 = last; k0 >= 0 && no > 0; k0 -= SW) {
-    const int w = min(SW, no - k0);
-    // subtract the already solved own rows below the block
-    if (k0 + w < no) {
-      for (int a = k0 + wave; a < k0 + w; a += ST / 64) {
-        double acc[NR];
-#pragma unroll
-        for (int q = 0; q < NR; ++q) acc[q] = 0.0;
-        const double* col = L + (int64_t)a * nf;
-        for (int i = k0 + w + lane; i < no; i += 64) {
-          double l = col[i];
-#pragma unroll
-          for (int q = 0; q < NR; ++q) acc[q] += l * s[i * NR + q];
-        }
-        wave_sum<NR>(acc);
-        if (lane == 0)
-#pragma unroll
-          for (int q = 0; q < NR; ++q) s[a * NR + q] -= acc[q];
-      }
-      __syncthreads();
-    }
-    // transposed diagonal block: lane (q, r) holds column r of the block
-    if (wave == 0 && lane < SW * NR) {
-      const int r = lane % SW, q = lane / SW;
-      double col[SW];
-#pragma unroll
-      for (int c = 0; c < SW; ++c) col[c] = (r < w && c >= r && c < w) ? L[(int64_t)(k0 + r) * nf + k0 + c] : 0.0;
-      double tr = (r < w) ? s[(k0 + r) * NR + q] : 0.0;
-#pragma unroll
-      for (int c = SW - 1; c >= 0; --c) {
-        if (c < w) {
-          if (r == c) tr = tr / col[c];
-          double xc = __shfl(tr, q * SW + c, 64);
-          if (r < c) tr -= col[c] * xc;
-        }
-      }
-      if (r < w) s[(k0 + r) * NR + q] = tr;
-    }
-    __syncthreads();
-  }
-  for (int p = tid; p < no; p += ST) {
-    const int d = fd[p];
+  reduce_waves<NR>(acc, red, lane, wave);
+  if (wave == 0 && live) {
+    const int d = fd[a];
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-      double val = s[p * NR + q];
       if (epilogue) {
-        double ru = -val;
+        const double ru = -acc[q];
         x[d + q * ldx] = ru;
         r_l[d + q * ldx] = sig * ru + v_u[d + q * ldv];
       } else {
-        x[d + q * ldx] = val;
+        x[d + q * ldx] = acc[q];
       }
     }
   }
 }
 
-void launch_fwd_level(const DevTree& t, const int* level_nodes, int count, int nrhs,
-                      const double* L, const double* b, int64_t ldb, double* y, int64_t ldy,
-                      double* upd, int max_front, hipStream_t st) {
+void launch_fwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* L,
+                      const double* b, int64_t ldb, double* y, int64_t ldy, double* upd, int max_front,
+                      hipStream_t st) {
   if (count <= 0) return;
-  size_t shm = (size_t)max_front * nrhs * sizeof(double);
+  size_t shm = ((size_t)max_front + SW * SR) * nrhs * sizeof(double);
+#define RIGA_FWD(NR) \
+  hipLaunchKernelGGL(k_fwd<NR>, dim3(count), dim3(ST), shm, st, t, tasks, L, b, ldb, y, ldy, upd)
   switch (nrhs) {
-    case 1: hipLaunchKernelGGL(k_fwd<1>, dim3(count), dim3(ST), shm, st, t, level_nodes, L, b, ldb, y, ldy, upd); break;
-    case 2: hipLaunchKernelGGL(k_fwd<2>, dim3(count), dim3(ST), shm, st, t, level_nodes, L, b, ldb, y, ldy, upd); break;
-    case 3: hipLaunchKernelGGL(k_fwd<3>, dim3(count), dim3(ST), shm, st, t, level_nodes, L, b, ldb, y, ldy, upd); break;
-    default: hipLaunchKernelGGL(k_fwd<4>, dim3(count), dim3(ST), shm, st, t, level_nodes, L, b, ldb, y, ldy, upd); break;
+    case 1: RIGA_FWD(1); break;
+    case 2: RIGA_FWD(2); break;
+    case 3: RIGA_FWD(3); break;
+    default: RIGA_FWD(4); break;
   }
+#undef RIGA_FWD
 }
 
-void launch_bwd_level(const DevTree& t, const int* level_nodes, int count, int nrhs,
-                      const double* L, const double* y, int64_t ldy, double* x, int64_t ldx,
-                      double* r_l, const double* v_u, int64_t ldv, double sig,
-                      int max_front, hipStream_t st) {
+void launch_bwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* T,
+                      const double* y, int64_t ldy, double* x, int64_t ldx, double* r_l, const double* v_u,
+                      int64_t ldv, double sig, int max_front, hipStream_t st) {
   if (count <= 0) return;
-  size_t shm = (size_t)max_front * nrhs * sizeof(double);
+  size_t shm = ((size_t)max_front + SW * SR) * nrhs * sizeof(double);
+#define RIGA_BWD(NR)                                                                               \
+  hipLaunchKernelGGL(k_bwd<NR>, dim3(count), dim3(ST), shm, st, t, tasks, T, y, ldy, x, ldx, r_l, v_u, \
+                     ldv, sig)
   switch (nrhs) {
-    case 1: hipLaunchKernelGGL(k_bwd<1>, dim3(count), dim3(ST), shm, st, t, level_nodes, L, y, ldy, x, ldx, r_l, v_u, ldv, sig); break;
-    case 2: hipLaunchKernelGGL(k_bwd<2>, dim3(count), dim3(ST), shm, st, t, level_nodes, L, y, ldy, x, ldx, r_l, v_u, ldv, sig); break;
-    case 3: hipLaunchKernelGGL(k_bwd<3>, dim3(count), dim3(ST), shm, st, t, level_nodes, L, y, ldy, x, ldx, r_l, v_u, ldv, sig); break;
-    default: hipLaunchKernelGGL(k_bwd<4>, dim3(count), dim3(ST), shm, st, t, level_nodes, L, y, ldy, x, ldx, r_l, v_u, ldv, sig); break;
+    case 1: RIGA_BWD(1); break;
+    case 2: RIGA_BWD(2); break;
+    case 3: RIGA_BWD(3); break;
+    default: RIGA_BWD(4); break;
   }
+#undef RIGA_BWD
 }
 
 }  // namespace riga

@@ -36,22 +36,24 @@ void launch_assemble(const DevSpace& s, const double* tabM, const double* tabK,
 
 // --- factorization ------------------------------------------------------------
 // One launch per tree level: assemble each front (original entries of
-// Q = s2 M + s1 C + K plus the children's update blocks) and eliminate its own
-// dofs by a blocked right-looking Cholesky with FP64 MFMA trailing updates.
+// Q = s2 M + s1 C + K plus the children's update blocks), eliminate its own
+// dofs by a blocked right-looking Cholesky with FP64 MFMA trailing updates, and
+// leave F = [L_oo^{-1}; L_bo L_oo^{-1}] column-major in L (nf x no per node) and
+// transposed in T (no x nf per node, same offsets).
 void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count,
                          double s2, double s1, const double* K, const double* M, const double* C,
-                         double* L, double* U, int64_t* status, hipStream_t st);
+                         double* L, double* U, double* T, int64_t* status, hipStream_t st);
 
 // --- forward / backward solves ------------------------------------------------
-void launch_fwd_level(const DevTree& t, const int* level_nodes, int count, int nrhs,
-                      const double* L, const double* b, int64_t ldb, double* y, int64_t ldy,
-                      double* upd, int max_front, hipStream_t st);
-// Backward sweep; if r_l != nullptr the result is written as the operator
-// epilogue r_u = -x, r_l = sig * r_u + v_u (v_u given with ldv), else x = y-solve.
-void launch_bwd_level(const DevTree& t, const int* level_nodes, int count, int nrhs,
-                      const double* L, const double* y, int64_t ldy, double* x, int64_t ldx,
-                      double* r_l, const double* v_u, int64_t ldv, double sig,
-                      int max_front, hipStream_t st);
+// One launch per tree level; tasks[k] = {node, first row, end row, 0}.
+void launch_fwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* L,
+                      const double* b, int64_t ldb, double* y, int64_t ldy, double* upd, int max_front,
+                      hipStream_t st);
+// Backward sweep with the transposed blocks T; if r_l != nullptr the result is
+// written as the operator epilogue r_u = -x (into x), r_l = sig r_u + v_u.
+void launch_bwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* T,
+                      const double* y, int64_t ldy, double* x, int64_t ldx, double* r_l, const double* v_u,
+                      int64_t ldv, double sig, int max_front, hipStream_t st);
 
 // --- Krylov building blocks -----------------------------------------------------
 // Y = a0 A0 X + a1 A1 X + a2 A2 X + bz Z   (A* share the CSR pattern; A1/A2 may be null)
@@ -87,5 +89,14 @@ void launch_finalize(int64_t n, int nv, const double* P, int64_t ld, const doubl
                      hipStream_t st);
 void launch_rowabs(const int64_t* rowptr, int64_t ndof, const double* A, double* part, int nblk,
                    hipStream_t st);
+
+// Device-side block normalisation (see k_krylov.hip): H columns k..k+nq from the
+// projection coefficients h1 + h2 and the Cholesky factor of the Gram matrix G;
+// Rinv = R^{-1}; *flag = 1 when a column was lost (breakdown).
+void launch_block_normalize(int nc, int nq, const double* h1, const double* h2, const double* G, double* H,
+                            int ldh, int k, double* Rinv, int* flag, hipStream_t st);
+// Out_m = In_m Q (n x nq times nq x nq) for three pairs sharing Q and ld.
+void launch_gemm3(int64_t n, int nq, const double* Q, const double* I0, double* O0, const double* I1, double* O1,
+                  const double* I2, double* O2, int64_t ld, hipStream_t st);
 
 }  // namespace riga

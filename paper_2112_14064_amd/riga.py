@@ -50,8 +50,8 @@ class riga_stats_t(C.Structure):
 
 
 EXPORTS = ["riga_create", "riga_info", "riga_assemble", "riga_export_csr", "riga_factor",
-           "riga_solve_q", "riga_apply_op", "riga_eigs", "riga_stats", "riga_selftest_small_eig",
-           "riga_status_str", "riga_destroy"]
+           "riga_solve_q", "riga_apply_op", "riga_eigs", "riga_stats", "riga_time_kernel",
+           "riga_selftest_small_eig", "riga_status_str", "riga_destroy"]
 
 _lib = None
 
@@ -74,6 +74,8 @@ def load(path: str = LIB_PATH):
     lib.riga_apply_op.argtypes = [P, C.c_int, P, P]
     lib.riga_eigs.argtypes = [P, C.POINTER(riga_options), P, P, P, C.POINTER(C.c_int)]
     lib.riga_stats.argtypes = [P, C.POINTER(riga_stats_t)]
+    lib.riga_time_kernel.argtypes = [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.POINTER(C.c_int)]
     lib.riga_selftest_small_eig.argtypes = [C.c_int, P, P, P]
     lib.riga_status_str.argtypes = [C.c_int]
     lib.riga_status_str.restype = C.c_char_p
@@ -208,6 +210,14 @@ class Problem:
         _check(st, "riga_eigs", allow_warn=True)
         Xc = torch.view_as_complex(X) if X is not None else None
         return lam[0::2] + 1j * lam[1::2], Xc, eta, nconv.value, st
+
+    def time_kernel(self, which: int, nrhs: int = 2, reps: int = 20):
+        """(avg ms per launch, work per launch, launches per repetition) of one
+        kernel family (0 forward sweep, 1 backward sweep, 2 factorization)."""
+        ms, work, nl = C.c_double(0), C.c_double(0), C.c_int(0)
+        _check(self.lib.riga_time_kernel(self.h, which, nrhs, reps, C.byref(ms), C.byref(work), C.byref(nl)),
+               "riga_time_kernel")
+        return ms.value, work.value, nl.value
 
     def stats(self):
         s = riga_stats_t()

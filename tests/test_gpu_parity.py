@@ -101,8 +101,10 @@ def _check_pairs(pr, lam, X, eta, K, C, M, ref, nev, sigma, tol=1e-10):
             u = U[:, k]
             assert oeig.residual(K, C, M, lam[k], u, norms) <= 1e-10
             assert abs(np.vdot(u, M @ u) - 1.0) < 1e-10
-            i = np.argmax(np.abs(u))
-            assert abs(u[i].imag) <= 1e-12 * abs(u[i]) and u[i].real > 0
+            # an entry of largest modulus (ties within rounding: symmetric modes
+            # have several) is real positive
+            big = np.flatnonzero(np.abs(u) >= (1 - 1e-9) * np.abs(u).max())
+            assert any(abs(u[i].imag) <= 1e-12 * abs(u[i]) and u[i].real > 0 for i in big)
 
 
 def test_eigs_small_config_rayleigh():
