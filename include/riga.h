@@ -58,9 +58,10 @@ typedef enum {
  *                C^{p-1}; Sec. 3.2).  s > 0: rIGA, knots at multiples of s/ne
  *                get multiplicity p, i.e. C^0 hyperplanes that cut the square
  *                into (ne/s)^2 macroelements (Sec. 3.3); ne % s == 0 required.
- *   leaf         IGA only: nested-dissection boxes stop splitting once both
- *                sides are <= leaf elements (0 = default 16).  Ignored for rIGA,
- *                whose leaves are the macroelements.                           */
+ *   leaf         nested-dissection boxes without an interior hyperplane are
+ *                bisected at element interfaces until both sides are <= leaf
+ *                elements (0 = default 16).  With s <= leaf the rIGA leaves are
+ *                the macroelements.                                             */
 typedef struct {
   int p, ne, hyper_every, leaf;
 } riga_mesh;
@@ -164,6 +165,20 @@ riga_status riga_apply_op(riga_problem* h, int nvec, const double* v, double* r)
  * RIGA_WARN_NOT_CONVERGED if maxit was reached first.                        */
 riga_status riga_eigs(riga_problem* h, const riga_options* opt, double* lam, double* X,
                       double* eta, int* nconv);
+
+/* Gradient of a real function L(lam_1..lam_nev) with respect to the per-element
+ * damping field, for C = alpha M + beta K + sum_e c_e M_e.  For the
+ * complex-symmetric pencil the left eigenvector is conj(u), so
+ *   d lam_k / d c_e = -lam_k u_k^T M_e u_k / u_k^T (2 lam_k M + C) u_k
+ * (unconjugated transposes; valid for simple eigenvalues), and
+ *   grad_c[e] = sum_k dL/dRe(lam_k) Re(d lam_k/d c_e) + dL/dIm(lam_k) Im(d lam_k/d c_e).
+ *   lam:     host, 2*nev doubles (re, im), e.g. from riga_eigs.
+ *   X:       device, ndof x nev complex interleaved eigenvectors (any scaling).
+ *   dL_dlam: host, 2*nev doubles (dL/dRe lam_k, dL/dIm lam_k).
+ *   grad_c:  device, ne*ne doubles, e = ey*ne + ex.
+ * Requires riga_assemble (the element tables); synchronises.                */
+riga_status riga_adjoint(riga_problem* h, int nev, const double* lam, const double* X, const double* dL_dlam,
+                         double* grad_c);
 
 /* Operation counters of the cost model of Sec. 5.1 (eq. Cost) and phase times. */
 riga_status riga_stats(const riga_problem* h, riga_stats_t* stats);

@@ -13,15 +13,19 @@ dof(i, j) = j * n1d + i over the remaining functions.
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 import scipy.sparse as sp
 
 from .bspline import basis, basis_deriv, gauss_legendre, knot_vector, n_functions
 
 
+@functools.lru_cache(maxsize=16)
 def _element_tables(p, ne, hyper_every):
     """Per element: index of the first of its p+1 nonzero functions, and the
-    values / derivatives of those functions at the element's Gauss points."""
+    values / derivatives of those functions at the element's Gauss points.
+    Cached per space; callers treat the arrays as read-only."""
     kv = knot_vector(p, ne, hyper_every)
     xg, wg = gauss_legendre(p + 1)
     h = 1.0 / ne

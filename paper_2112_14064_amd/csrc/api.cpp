@@ -111,6 +111,8 @@ struct riga_problem {
   double *d_K = nullptr, *d_M = nullptr, *d_C = nullptr;
   double *d_L = nullptr, *d_U = nullptr, *d_T = nullptr, *d_upd = nullptr, *d_tmp = nullptr, *d_tmp2 = nullptr;
   int4 *d_ftasks = nullptr, *d_btasks = nullptr;   // solve tasks, grouped by level
+  double* d_D = nullptr;                            // 64x64 diagonal-block inverses
+  std::vector<int> lvl_max_no, lvl_max_nf;
   std::vector<int> ftask_off, btask_off;
   int64_t* d_status = nullptr;
   double* d_part = nullptr;       // reduction scratch
@@ -328,6 +330,20 @@ riga_status riga_create(riga_problem** out, const riga_mesh* mesh, int device, v
     h->d_L = h->dalloc<double>(P.lsize); h->d_U = h->dalloc<double>(P.usize);
     h->d_T = h->dalloc<double>(P.lsize);
     {
+      std::vector<int64_t> doff(P.nf.size() + 1, 0);
+      for (size_t v = 0; v < P.nf.size(); ++v) doff[v + 1] = doff[v] + (P.no[v] + 63) / 64;
+      h->dt.doff = h->upload(doff);
+      h->d_D = h->dalloc<double>((size_t)doff.back() * 4096);
+      h->lvl_max_no.assign(P.height, 0);
+      h->lvl_max_nf.assign(P.height, 0);
+      for (int lv = 0; lv < P.height; ++lv)
+        for (int k = P.level_off[lv]; k < P.level_off[lv + 1]; ++k) {
+          const int v = P.level_nodes[k];
+          h->lvl_max_no[lv] = std::max(h->lvl_max_no[lv], P.no[v]);
+          h->lvl_max_nf[lv] = std::max(h->lvl_max_nf[lv], P.nf[v]);
+        }
+    }
+    {
       // Row tasks of the solve sweeps: blocks of 64 consecutive rows of one node.
       std::vector<int4> ft, bt;
       h->ftask_off.assign(P.height + 1, 0);
@@ -443,8 +459,9 @@ riga_status riga_factor(riga_problem* h, double sigma, int64_t* bad_pivot) {
     ck(hipEventRecord(h->ev0, h->st));
     for (int lv = 0; lv < P.height; ++lv) {
       int a = P.level_off[lv], c = P.level_off[lv + 1] - a;
-      riga::launch_front_factor(h->ds, h->dt, h->d_level_nodes + a, c, sigma * sigma, sigma, h->d_K, h->d_M,
-                                h->d_C, h->d_L, h->d_U, h->d_T, h->d_status, h->st);
+      riga::launch_front_factor(h->ds, h->dt, h->d_level_nodes + a, c, h->lvl_max_no[lv], h->lvl_max_nf[lv],
+                                sigma * sigma, sigma, h->d_K, h->d_M, h->d_C, h->d_L, h->d_U, h->d_T, h->d_D,
+                                h->d_status, h->st);
     }
     ck(hipGetLastError());
     ck(hipEventRecord(h->ev1, h->st));
@@ -557,8 +574,9 @@ riga_status riga_time_kernel(riga_problem* h, int which, int nrhs, int reps, dou
                                  nullptr, 0, 0.0, P.max_front, h->st);
         } else {
           int a = P.level_off[lv], c = P.level_off[lv + 1] - a;
-          riga::launch_front_factor(h->ds, h->dt, h->d_level_nodes + a, c, h->sigma * h->sigma, h->sigma, h->d_K,
-                                    h->d_M, h->d_C, h->d_L, h->d_U, h->d_T, h->d_status, h->st);
+          riga::launch_front_factor(h->ds, h->dt, h->d_level_nodes + a, c, h->lvl_max_no[lv], h->lvl_max_nf[lv],
+                                    h->sigma * h->sigma, h->sigma, h->d_K, h->d_M, h->d_C, h->d_L, h->d_U, h->d_T,
+                                    h->d_D, h->d_status, h->st);
         }
       }
     }
@@ -570,6 +588,51 @@ riga_status riga_time_kernel(riga_problem* h, int which, int nrhs, int reps, dou
     *avg_ms = ms / ((double)reps * H);
     *work_per_launch = work / H;
     if (launches) *launches = H;
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_adjoint(riga_problem* h, int nev, const double* lam, const double* X, const double* dL_dlam,
+                         double* grad_c) {
+  if (!h || nev < 1 || !lam || !X || !dL_dlam || !grad_c) return RIGA_ERR_INVALID_ARG;
+  if (!h->assembled) return RIGA_ERR_STATE;
+  return run([&]() -> riga_status {
+    ck(hipSetDevice(h->device));
+    const int64_t N = h->N();
+    ensure_post(h, nev);
+    riga::launch_deinterleave(N, nev, X, h->P, h->st);
+    for (int c0 = 0; c0 < 2 * nev; c0 += 8) {
+      const int nc = std::min(8, 2 * nev - c0);
+      const double* x = h->P + (size_t)c0 * N;
+      riga::launch_spmv(h->ds, N, nc, h->d_M, 1.0, nullptr, 0, nullptr, 0, x, N, h->MP + (size_t)c0 * N, N,
+                        nullptr, 0, 0.0, nullptr, 0, h->st);
+      riga::launch_spmv(h->ds, N, nc, h->d_C, 1.0, nullptr, 0, nullptr, 0, x, N, h->CP + (size_t)c0 * N, N,
+                        nullptr, 0, 0.0, nullptr, 0, h->st);
+    }
+    const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, N / 4096));
+    // the K slots of the pair reduction are not needed: pass M P there
+    riga::launch_pair_forms(N, nev, h->P, h->MP, h->CP, h->MP, N, h->d_part, nsplit, h->st);
+    std::vector<double> part((size_t)nev * nsplit * 11);
+    ck(hipMemcpyAsync(part.data(), h->d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    ck(hipStreamSynchronize(h->st));
+    std::vector<double> w((size_t)2 * nev);
+    for (int k = 0; k < nev; ++k) {
+      double f[11] = {0};
+      for (int x = 0; x < nsplit; ++x)
+        for (int t2 = 0; t2 < 11; ++t2) f[t2] += part[((size_t)k * nsplit + x) * 11 + t2];
+      const cplx qm(f[0] - f[1], 2 * f[2]), qc(f[3] - f[4], 2 * f[5]);
+      const cplx l(lam[2 * k], lam[2 * k + 1]);
+      const cplx den = 2.0 * l * qm + qc;          // u^T (2 lam M + C) u
+      const cplx g(dL_dlam[2 * k], dL_dlam[2 * k + 1]);
+      const cplx wk = std::conj(g) * (-l / den);
+      w[2 * k] = wk.real();
+      w[2 * k + 1] = wk.imag();
+    }
+    double* dw = h->d_part;   // reuse: the reduction scratch is free again
+    ck(hipMemcpyAsync(dw, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
+    riga::launch_adjoint(h->ds, h->d_tabM, nev, h->P, N, dw, grad_c, h->st);
+    ck(hipGetLastError());
+    ck(hipStreamSynchronize(h->st));
     return RIGA_OK;
   });
 }

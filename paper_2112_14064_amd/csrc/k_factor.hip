@@ -4,30 +4,37 @@
 //
 // A front of node v holds its own dofs (eliminated here) followed by its
 // boundary dofs (ancestors coupled to the subtree).  Storage per node:
-//   L block  nf x no, column-major (ld nf): columns of the factor for the own
-//            dofs, rows own+boundary.
+//   L block  nf x no, column-major (ld nf): the own columns of the front;
 //   U block  nb x nb, column-major: the update (Schur complement) matrix that
-//            the parent adds into its front ("extend-add").
-// One workgroup per front.  The own block is factored by a right-looking
-// blocked Cholesky with 16-wide panels: the diagonal 16x16 block by one wave in
-// LDS, the panel below by a row-parallel triangular solve, and the trailing
-// lower triangle (including the update block) by FP64 MFMA 16x16x4 tiles.
-//
-// For the solves the factor columns are then replaced by
-//   F = [L_oo^{-1}; L_bo L_oo^{-1}],
-// obtained row by row from X L_oo = [I; L_bo] (a triangular solve from the
-// right, MFMA for the panel updates).  F is kept column-major in the L block
-// and transposed (no x nf, column-major) in the T block, so each sweep of a
-// forward/backward solve is one matrix-vector product per node:
-//   forward   [y_own; w] = F f_own,  update to the parent = f_bnd - w
-//   backward  x_own = F^T [y_own; -x_bnd].
+//            the parent adds into its front ("extend-add");
+//   T block  no x nf, column-major (same offset as L): scratch, then F^T.
+// A tree level is processed by a pipeline of batched kernels whose grids span
+// every node of the level:
+//   k_front_assemble   zero the front, add the original entries of Q and the
+//                      children's update blocks (one workgroup per node);
+//   per 64-wide panel of own columns:
+//     k_potrf_diag     Cholesky of the 64x64 diagonal block and its inverse
+//                      D_k = L_kk^{-1} (one workgroup per node, in LDS);
+//     k_trsm_panel     panel rows below the block: X = A D_k^T   (MFMA)
+//     k_syrk_update    trailing lower triangle, own and update parts:
+//                      C -= P_I P_J^T on 64x64 tiles             (MFMA)
+//   k_rtrsm            rows of F = [L_oo^{-1}; L_bo L_oo^{-1}] from
+//                      X L_oo = [I; L_bo], block column by block column from
+//                      the right with the stored D_k               (MFMA)
+//   k_transpose        F column-major into the L block (T keeps F^T).
+// With F, each forward/backward sweep is one matrix-vector product per node.
+// All products use v_mfma_f64_16x16x4_f64 on 64x64 tiles staged in LDS; each
+// of the four waves owns a 32x32 quadrant (2x2 MFMA tiles).
 #include "kernels.hpp"
 #include "mfma_layout.hpp"
 
+#include <algorithm>
+
 namespace riga {
 
-constexpr int FT = 256;   // threads per front
-constexpr int PW = 16;    // panel width = MFMA tile
+constexpr int FT = 256;     // threads per workgroup
+constexpr int TB = 64;      // panel / tile width
+constexpr int LDT = TB + 1; // LDS row stride (doubles)
 
 struct Front {
   double* L; double* U; int nf, no, nb;
@@ -36,26 +43,55 @@ struct Front {
   }
 };
 
-__global__ __launch_bounds__(FT) void k_front_factor(
+__device__ __forceinline__ Front front_of(const DevTree& t, int v, double* Lbuf, double* Ubuf) {
+  return Front{Lbuf + t.loff[v], Ubuf + t.uoff[v], t.nf[v], t.no[v], t.nb[v]};
+}
+
+// acc += sign * A (64 x kw) B (kw x 64), A at As[i * LDT + k], B at Bs[k * LDT + j];
+// wave w owns rows 32 (w >> 1) .. and columns 32 (w & 1) .., as 2 x 2 MFMA tiles.
+__device__ __forceinline__ void mma64(const double* As, const double* Bs, int kw, dvec4 (&acc)[2][2],
+                                      int lane, int wave, double sign) {
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  for (int k0 = 0; k0 < kw; k0 += 4) {
+    const int k = k0 + mfma_ab_k(lane);
+    double a[2], b[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      a[t] = (k < kw) ? sign * As[(wr + 16 * t + mfma_a_row(lane)) * LDT + k] : 0.0;
+      b[t] = (k < kw) ? Bs[k * LDT + wc + 16 * t + mfma_b_col(lane)] : 0.0;
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+        acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ int acc_row(int lane, int wave, int ti, int v) {
+  return (wave >> 1) * 32 + 16 * ti + mfma_d_row(lane, v);
+}
+__device__ __forceinline__ int acc_col(int lane, int wave, int tj) {
+  return (wave & 1) * 32 + 16 * tj + mfma_d_col(lane);
+}
+
+// ---------------------------------------------------------------------------------
+__global__ __launch_bounds__(FT) void k_front_assemble(
     int n, const int* __restrict__ lo, const int* __restrict__ hi, const int64_t* __restrict__ rowptr,
     DevTree t, const int* __restrict__ level_nodes, double s2, double s1,
     const double* __restrict__ Kv, const double* __restrict__ Mv, const double* __restrict__ Cv,
-    double* __restrict__ Lbuf, double* __restrict__ Ubuf, double* __restrict__ Tbuf,
-    int64_t* __restrict__ status) {
+    double* __restrict__ Lbuf, double* __restrict__ Ubuf) {
   const int v = level_nodes[blockIdx.x];
-  Front F{Lbuf + t.loff[v], Ubuf + t.uoff[v], t.nf[v], t.no[v], t.nb[v]};
+  const Front F = front_of(t, v, Lbuf, Ubuf);
   const int nf = F.nf, no = F.no, nb = F.nb;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   const int* fd = t.fdofs + t.foff[v];
   const int* fk = t.fkey + t.foff[v];
   const int* fp = t.fpos + t.foff[v];
-
-  // --- A: clear the front -------------------------------------------------------
   for (int64_t idx = tid; idx < (int64_t)nf * no; idx += FT) F.L[idx] = 0.0;
   for (int64_t idx = tid; idx < (int64_t)nb * nb; idx += FT) F.U[idx] = 0.0;
   __syncthreads();
-
-  // --- B: original entries Q[g, d] for own d, g in the front, g at or below d ----
+  // original entries Q[g, d] for own d and g in the front at or below d
   for (int a = tid; a < no; a += FT) {
     const int d = fd[a];
     const int i = d % n, j = d / n;
@@ -64,9 +100,9 @@ __global__ __launch_bounds__(FT) void k_front_factor(
     for (int64_t k = k0; k < k1; ++k) {
       const int o = (int)(k - k0);
       const int g = (lo[j] + o / wx) * n + lo[i] + o % wx;
-      int x0 = 0, x1 = nf;  // binary search g in the sorted front keys
+      int x0 = 0, x1 = nf;  // binary search of g among the sorted front keys
       while (x1 - x0 > 1) {
-        int c = (x0 + x1) >> 1;
+        const int c = (x0 + x1) >> 1;
         if (fk[c] <= g) x0 = c; else x1 = c;
       }
       if (nf > 0 && fk[x0] == g) {
@@ -76,8 +112,7 @@ __global__ __launch_bounds__(FT) void k_front_factor(
     }
   }
   __syncthreads();
-
-  // --- C: extend-add of the children's update blocks ------------------------------
+  // extend-add of the children's update blocks, one child at a time
   for (int ci = t.coff[v]; ci < t.coff[v + 1]; ++ci) {
     const int c = t.clist[ci];
     const int nbc = t.nb[c];
@@ -89,176 +124,282 @@ __global__ __launch_bounds__(FT) void k_front_factor(
     }
     __syncthreads();
   }
+}
 
-  // --- D: partial Cholesky of the own columns --------------------------------------
-  __shared__ double dg[PW][PW + 1];
-  for (int k0 = 0; k0 < no; k0 += PW) {
-    const int w = min(PW, no - k0);
-    // D1: diagonal block by wave 0 (wave-synchronous LDS)
-    if (wave == 0) {
-      for (int idx = lane; idx < PW * PW; idx += 64) {
-        int r = idx / PW, c = idx % PW;
-        dg[r][c] = (r < w && c <= r) ? *F.at(k0 + r, k0 + c) : 0.0;
+// ---------------------------------------------------------------------------------
+// Cholesky of the diagonal block [k0, k0+w) and D = its inverse (lower), stored
+// at D + (doff[v] + k0/64) * 4096 as D[r * 64 + c].
+__global__ __launch_bounds__(FT) void k_potrf_diag(DevTree t, const int* __restrict__ level_nodes, int k0,
+                                                   double* __restrict__ Lbuf, double* __restrict__ Ubuf,
+                                                   double* __restrict__ Dbuf,
+                                                   int64_t* __restrict__ status) {
+  const int v = level_nodes[blockIdx.x];
+  const Front F = front_of(t, v, Lbuf, Ubuf);
+  if (F.no <= k0) return;
+  const int w = min(TB, F.no - k0);
+  const int tid = threadIdx.x;
+  __shared__ double S[TB][LDT];
+  __shared__ double Dl[TB][LDT];
+  __shared__ double piv_s;
+  for (int idx = tid; idx < TB * TB; idx += FT) {
+    const int r = idx % TB, c = idx / TB;       // coalesced along the column
+    S[r][c] = (r < w && c <= r) ? F.L[(int64_t)(k0 + c) * F.nf + k0 + r] : 0.0;
+  }
+  __syncthreads();
+  for (int c = 0; c < w; ++c) {
+    if (tid == 0) {
+      double piv = S[c][c];
+      if (!(piv > 0.0)) {           // not SPD (or NaN): record, continue with 1
+        atomicCAS((unsigned long long*)status, (unsigned long long)(-1ll),
+                  (unsigned long long)t.fdofs[t.foff[v] + k0 + c]);
+        piv = 1.0;
       }
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      for (int c = 0; c < w; ++c) {
-        double piv = dg[c][c];
-        if (!(piv > 0.0)) {           // not SPD (or NaN): record, continue with 1
-          if (lane == 0) atomicCAS((unsigned long long*)status, (unsigned long long)(-1ll),
-                                   (unsigned long long)fd[k0 + c]);
-          piv = 1.0;
-        }
-        const double dd = sqrt(piv), inv = 1.0 / dd;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        if (lane > c && lane < w) dg[lane][c] *= inv;
-        if (lane == c) dg[c][c] = dd;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        // rank-1 update of the remaining lower triangle (r, cc), c < cc <= r < w
-        for (int idx = lane; idx < PW * PW; idx += 64) {
-          int r = idx / PW, cc = idx % PW;
-          if (r < w && cc > c && cc <= r) dg[r][cc] -= dg[r][c] * dg[cc][c];
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      }
-      for (int idx = lane; idx < PW * PW; idx += 64) {
-        int r = idx / PW, c = idx % PW;
-        if (r < w && c <= r) *F.at(k0 + r, k0 + c) = dg[r][c];
-      }
+      piv_s = sqrt(piv);
+      S[c][c] = piv_s;
     }
     __syncthreads();
-    // D2: panel rows below the diagonal block: x L_kk^T = a
-    for (int i = k0 + w + tid; i < nf; i += FT) {
-      double x[PW];
-#pragma unroll
-      for (int c = 0; c < PW; ++c) x[c] = (c < w) ? F.L[(int64_t)(k0 + c) * nf + i] : 0.0;
-#pragma unroll
-      for (int c = 0; c < PW; ++c) {
-        if (c < w) {
-          double s = x[c];
-#pragma unroll
-          for (int c2 = 0; c2 < PW; ++c2)
-            if (c2 < c) s -= x[c2] * dg[c][c2];
-          x[c] = s / dg[c][c];
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < PW; ++c)
-        if (c < w) F.L[(int64_t)(k0 + c) * nf + i] = x[c];
-    }
+    const double inv = 1.0 / piv_s;
+    for (int r = c + 1 + tid; r < w; r += FT) S[r][c] *= inv;
     __syncthreads();
-    // D3: trailing update A22 -= P P^T on the lower triangle, 16x16 MFMA tiles
-    const int s0 = k0 + w;
-    const int nt = (nf - s0 + PW - 1) / PW;
-    const int ntiles = nt * (nt + 1) / 2;
-    for (int tile = wave; tile < ntiles; tile += FT / 64) {
-      int I = 0;
-      while ((I + 1) * (I + 2) / 2 <= tile) ++I;
-      const int J = tile - I * (I + 1) / 2;
-      const int rI = s0 + PW * I, rJ = s0 + PW * J;
-      dvec4 acc;
-#pragma unroll
-      for (int vv = 0; vv < 4; ++vv) {
-        int r = rI + mfma_d_row(lane, vv), c = rJ + mfma_d_col(lane);
-        acc[vv] = (r < nf && c < nf && r >= c) ? *F.at(r, c) : 0.0;
-      }
-#pragma unroll
-      for (int kk = 0; kk < PW / 4; ++kk) {
-        const int pc = 4 * kk + mfma_ab_k(lane);     // panel column
-        const int ra = rI + mfma_a_row(lane), rb = rJ + mfma_b_col(lane);
-        double av = 0.0, bv = 0.0;
-        if (pc < w) {
-          if (ra < nf) av = -F.L[(int64_t)(k0 + pc) * nf + ra];
-          if (rb < nf) bv = F.L[(int64_t)(k0 + pc) * nf + rb];
-        }
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-      }
-#pragma unroll
-      for (int vv = 0; vv < 4; ++vv) {
-        int r = rI + mfma_d_row(lane, vv), c = rJ + mfma_d_col(lane);
-        if (r < nf && c < nf && r >= c) *F.at(r, c) = acc[vv];
-      }
+    const int m = w - c - 1;   // trailing order
+    for (int idx = tid; idx < m * m; idx += FT) {
+      const int r = c + 1 + idx / m, cc = c + 1 + idx % m;
+      if (cc <= r) S[r][cc] -= S[r][c] * S[cc][c];
     }
     __syncthreads();
   }
-
-  // --- E: X L_oo = [I; L_bo], row tiles per wave, panels from the right --------------
-  double* T = Tbuf + t.loff[v];      // X row r at T[r * no + 0 .. no)
-  __shared__ double tb[FT / 64][PW][PW + 1];
-  __shared__ double lp[FT / 64][PW][PW + 1];
-  const int npan = (no + PW - 1) / PW;
-  const int nrt = (nf + PW - 1) / PW;
-  for (int rt = wave; rt < nrt; rt += FT / 64) {
-    const int r0 = rt * PW;
-    for (int P = npan - 1; P >= 0; --P) {
-      const int c0 = P * PW, w = min(PW, no - c0);
-      const bool top = (r0 + PW <= no);          // every row of the tile is an own row
-      if (top && r0 + PW - 1 < c0) {             // X[r][c] = 0 for c > r < no
-        for (int idx = lane; idx < PW * PW; idx += 64) {
-          int i = idx / PW, j = idx % PW;
-          if (j < w) T[(int64_t)(r0 + i) * no + c0 + j] = 0.0;
-        }
-        continue;
+  // inverse of the lower-triangular block, one column per thread
+  if (tid < TB) {
+    const int c = tid;
+    for (int r = 0; r < TB; ++r) Dl[r][c] = 0.0;
+    if (c < w) {
+      Dl[c][c] = 1.0 / S[c][c];
+      for (int r = c + 1; r < w; ++r) {
+        double sacc = 0.0;
+        for (int k = c; k < r; ++k) sacc += S[r][k] * Dl[k][c];
+        Dl[r][c] = -sacc / S[r][r];
       }
-      dvec4 acc;
-#pragma unroll
-      for (int vv = 0; vv < 4; ++vv) {
-        const int r = r0 + mfma_d_row(lane, vv), c = c0 + mfma_d_col(lane);
-        double val = 0.0;
-        if (r < nf && c < c0 + w) val = (r < no) ? (r == c ? 1.0 : 0.0) : F.L[(int64_t)c * nf + r];
-        acc[vv] = val;
-      }
-      // minus X[r][k] L_oo[k][c] over the already solved columns k >= c0 + w
-      const int kend = top ? min(no, r0 + PW) : no;
-      for (int k0 = c0 + w; k0 < kend; k0 += 4) {
-        const int ra = r0 + mfma_a_row(lane), ka = k0 + mfma_ab_k(lane);
-        const int cb = c0 + mfma_b_col(lane);
-        const double av = (ra < nf && ka < no) ? -T[(int64_t)ra * no + ka] : 0.0;
-        const double bv = (ka < no && cb < c0 + w) ? F.L[(int64_t)cb * nf + ka] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-      }
-#pragma unroll
-      for (int vv = 0; vv < 4; ++vv) tb[wave][mfma_d_row(lane, vv)][mfma_d_col(lane)] = acc[vv];
-      for (int idx = lane; idx < PW * PW; idx += 64) {
-        int i = idx / PW, j = idx % PW;
-        lp[wave][i][j] = (i < w && j <= i) ? F.L[(int64_t)(c0 + j) * nf + c0 + i] : 0.0;
-      }
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      if (lane < PW) {  // row lane: x L_PP = acc, from the last column back
-        for (int j = w - 1; j >= 0; --j) {
-          double sacc = tb[wave][lane][j];
-          for (int k = j + 1; k < w; ++k) sacc -= tb[wave][lane][k] * lp[wave][k][j];
-          tb[wave][lane][j] = sacc / lp[wave][j][j];
-        }
-      }
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      for (int idx = lane; idx < PW * PW; idx += 64) {
-        int i = idx / PW, j = idx % PW;
-        if (r0 + i < nf && j < w) T[(int64_t)(r0 + i) * no + c0 + j] = tb[wave][i][j];
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-      __builtin_amdgcn_wave_barrier();
     }
   }
   __syncthreads();
-  // F column-major into the L block
-  for (int64_t idx = tid; idx < (int64_t)nf * no; idx += FT) {
-    const int r = (int)(idx % nf), a = (int)(idx / nf);
-    F.L[idx] = T[(int64_t)r * no + a];
+  for (int idx = tid; idx < TB * TB; idx += FT) {
+    const int r = idx % TB, c = idx / TB;
+    if (r < w && c <= r) F.L[(int64_t)(k0 + c) * F.nf + k0 + r] = S[r][c];
+  }
+  double* D = Dbuf + ((int64_t)t.doff[v] + k0 / TB) * (TB * TB);
+  for (int idx = tid; idx < TB * TB; idx += FT) D[idx] = Dl[idx / TB][idx % TB];
+}
+
+// Panel rows [k0 + w + 64 y, +64) of columns [k0, k0 + w): X = A D^T.
+__global__ __launch_bounds__(FT) void k_trsm_panel(DevTree t, const int* __restrict__ level_nodes, int k0,
+                                                   double* __restrict__ Lbuf, double* __restrict__ Ubuf,
+                                                   const double* __restrict__ Dbuf) {
+  const int v = level_nodes[blockIdx.x];
+  const Front F = front_of(t, v, Lbuf, Ubuf);
+  if (F.no <= k0) return;
+  const int w = min(TB, F.no - k0);
+  const int r0 = k0 + w + TB * blockIdx.y;
+  if (r0 >= F.nf) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double As[TB * LDT];
+  __shared__ double Bs[TB * LDT];
+  const double* D = Dbuf + ((int64_t)t.doff[v] + k0 / TB) * (TB * TB);
+  for (int idx = tid; idx < TB * TB; idx += FT) {
+    const int i = idx % TB, k = idx / TB;        // row i of the tile, column k (coalesced in i)
+    const int r = r0 + i;
+    As[i * LDT + k] = (r < F.nf && k < w) ? F.L[(int64_t)(k0 + k) * F.nf + r] : 0.0;
+    const int kk = idx / TB, j = idx % TB;        // Bs[k][j] = D[j][k]
+    Bs[kk * LDT + j] = D[j * TB + kk];
+  }
+  __syncthreads();
+  dvec4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = dvec4{0.0, 0.0, 0.0, 0.0};
+  mma64(As, Bs, w, acc, lane, wave, 1.0);
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) {
+        const int r = r0 + acc_row(lane, wave, ti, vv), c = acc_col(lane, wave, tj);
+        if (r < F.nf && c < w) F.L[(int64_t)(k0 + c) * F.nf + r] = acc[ti][tj][vv];
+      }
+}
+
+// Trailing update below the panel [k0, k0 + w): tiles (I, J), J <= I, of the
+// front rows/columns from s0 = k0 + w, pair index in blockIdx.y.
+__global__ __launch_bounds__(FT) void k_syrk_update(DevTree t, const int* __restrict__ level_nodes, int k0,
+                                                    double* __restrict__ Lbuf, double* __restrict__ Ubuf) {
+  const int v = level_nodes[blockIdx.x];
+  const Front F = front_of(t, v, Lbuf, Ubuf);
+  if (F.no <= k0) return;
+  const int w = min(TB, F.no - k0);
+  const int s0 = k0 + w;
+  const int pidx = blockIdx.y;
+  int I = (int)((sqrt(8.0 * pidx + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= pidx) ++I;
+  while (I * (I + 1) / 2 > pidx) --I;
+  const int J = pidx - I * (I + 1) / 2;
+  const int rI = s0 + TB * I, rJ = s0 + TB * J;
+  if (rI >= F.nf) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double As[TB * LDT];
+  __shared__ double Bs[TB * LDT];
+  for (int idx = tid; idx < TB * TB; idx += FT) {
+    const int i = idx % TB, k = idx / TB;
+    const int ra = rI + i, rb = rJ + i;
+    As[i * LDT + k] = (ra < F.nf && k < w) ? F.L[(int64_t)(k0 + k) * F.nf + ra] : 0.0;
+    Bs[k * LDT + i] = (rb < F.nf && k < w) ? F.L[(int64_t)(k0 + k) * F.nf + rb] : 0.0;
+  }
+  __syncthreads();
+  dvec4 acc[2][2];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) {
+        const int r = rI + acc_row(lane, wave, ti, vv), c = rJ + acc_col(lane, wave, tj);
+        acc[ti][tj][vv] = (r < F.nf && c < F.nf && r >= c) ? *F.at(r, c) : 0.0;
+      }
+  mma64(As, Bs, w, acc, lane, wave, -1.0);
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) {
+        const int r = rI + acc_row(lane, wave, ti, vv), c = rJ + acc_col(lane, wave, tj);
+        if (r < F.nf && c < F.nf && r >= c) *F.at(r, c) = acc[ti][tj][vv];
+      }
+}
+
+// Rows [64 y, +64) of X with X L_oo = [I; L_bo]; X row r at T[r * no + ...].
+__global__ __launch_bounds__(FT) void k_rtrsm(DevTree t, const int* __restrict__ level_nodes,
+                                              double* __restrict__ Lbuf, double* __restrict__ Ubuf,
+                                              double* __restrict__ Tbuf, const double* __restrict__ Dbuf) {
+  const int v = level_nodes[blockIdx.x];
+  const Front F = front_of(t, v, Lbuf, Ubuf);
+  const int nf = F.nf, no = F.no;
+  const int r0 = TB * blockIdx.y;
+  if (r0 >= nf || no == 0) return;
+  double* T = Tbuf + t.loff[v];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double As[TB * LDT];
+  __shared__ double Bs[TB * LDT];
+  const int npan = (no + TB - 1) / TB;
+  const bool top = (r0 + TB <= no);            // every row of the block is an own row
+  for (int P = npan - 1; P >= 0; --P) {
+    const int c0 = P * TB, w = min(TB, no - c0);
+    if (top && r0 + TB - 1 < c0) {               // X[r][c] = 0 for c > r < no
+      for (int idx = tid; idx < TB * TB; idx += FT) {
+        const int i = idx / TB, j = idx % TB;
+        if (j < w) T[(int64_t)(r0 + i) * no + c0 + j] = 0.0;
+      }
+      continue;
+    }
+    dvec4 acc[2][2];
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) {
+          const int r = r0 + acc_row(lane, wave, ti, vv), c = c0 + acc_col(lane, wave, tj);
+          double val = 0.0;
+          if (r < nf && c < c0 + w) val = (r < no) ? (r == c ? 1.0 : 0.0) : F.L[(int64_t)c * nf + r];
+          acc[ti][tj][vv] = val;
+        }
+    // minus X[:, kb] L[kb, P] over solved block columns kb > P (X vanishes past the diagonal for top rows)
+    const int kbmax = top ? min(npan - 1, (r0 + TB - 1) / TB) : npan - 1;
+    for (int kb = P + 1; kb <= kbmax; ++kb) {
+      const int cb = kb * TB, wb = min(TB, no - cb);
+      __syncthreads();
+      for (int idx = tid; idx < TB * TB; idx += FT) {
+        const int k = idx % TB, i = idx / TB;      // As[i][k] = X[r0 + i][cb + k], coalesced in k
+        As[i * LDT + k] = (r0 + i < nf && k < wb) ? T[(int64_t)(r0 + i) * no + cb + k] : 0.0;
+        const int j = idx / TB, kk = idx % TB;     // Bs[k][j] = L[cb + k][c0 + j], coalesced in k
+        Bs[kk * LDT + j] = (kk < wb && j < w) ? F.L[(int64_t)(c0 + j) * nf + cb + kk] : 0.0;
+      }
+      __syncthreads();
+      mma64(As, Bs, wb, acc, lane, wave, -1.0);
+    }
+    // X[:, P] = acc D_P
+    __syncthreads();
+    const double* D = Dbuf + ((int64_t)t.doff[v] + P) * (TB * TB);
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv)
+          As[acc_row(lane, wave, ti, vv) * LDT + acc_col(lane, wave, tj)] = acc[ti][tj][vv];
+    for (int idx = tid; idx < TB * TB; idx += FT) Bs[(idx / TB) * LDT + idx % TB] = D[idx];
+    __syncthreads();
+    dvec4 x[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) x[a][b] = dvec4{0.0, 0.0, 0.0, 0.0};
+    mma64(As, Bs, w, x, lane, wave, 1.0);
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) {
+          const int r = r0 + acc_row(lane, wave, ti, vv), c = acc_col(lane, wave, tj);
+          if (r < nf && c < w) T[(int64_t)r * no + c0 + c] = x[ti][tj][vv];
+        }
+    __syncthreads();   // T of this block column is read as the next panel's A operand
   }
 }
 
-void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count,
-                         double s2, double s1, const double* K, const double* M, const double* C,
-                         double* L, double* U, double* T, int64_t* status, hipStream_t st) {
+// F (rows of T) column-major into the L block, 64 x 64 tiles through LDS.
+__global__ __launch_bounds__(FT) void k_transpose(DevTree t, const int* __restrict__ level_nodes,
+                                                  double* __restrict__ Lbuf, const double* __restrict__ Tbuf) {
+  const int v = level_nodes[blockIdx.x];
+  const int nf = t.nf[v], no = t.no[v];
+  const int ntr = (nf + TB - 1) / TB;
+  const int tr = blockIdx.y % ntr, tc = blockIdx.y / ntr;
+  const int r0 = tr * TB, c0 = tc * TB;
+  if (c0 >= no || r0 >= nf) return;
+  double* L = Lbuf + t.loff[v];
+  const double* T = Tbuf + t.loff[v];
+  __shared__ double S[TB * LDT];
+  for (int idx = threadIdx.x; idx < TB * TB; idx += FT) {
+    const int i = idx / TB, c = idx % TB;         // read row r0 + i, contiguous in c
+    S[i * LDT + c] = (r0 + i < nf && c0 + c < no) ? T[(int64_t)(r0 + i) * no + c0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < TB * TB; idx += FT) {
+    const int c = idx / TB, i = idx % TB;         // write column c0 + c, contiguous in i
+    if (r0 + i < nf && c0 + c < no) L[(int64_t)(c0 + c) * nf + r0 + i] = S[i * LDT + c];
+  }
+}
+
+void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
+                         int max_nf, double s2, double s1, const double* K, const double* M, const double* C,
+                         double* L, double* U, double* T, double* D, int64_t* status,
+                         hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_front_factor, dim3(count), dim3(FT), 0, st, s.n, s.lo, s.hi, s.rowptr, t,
-                     level_nodes, s2, s1, K, M, C, L, U, T, status);
+  hipLaunchKernelGGL(k_front_assemble, dim3(count), dim3(FT), 0, st, s.n, s.lo, s.hi, s.rowptr, t, level_nodes,
+                     s2, s1, K, M, C, L, U);
+  for (int k0 = 0; k0 < max_no; k0 += TB) {
+    hipLaunchKernelGGL(k_potrf_diag, dim3(count), dim3(FT), 0, st, t, level_nodes, k0, L, U, D, status);
+    // rows and trailing tiles below a block that is at least one column wide
+    const int below = std::max(1, max_nf - k0 - 1);
+    const int nrc = (below + TB - 1) / TB;
+    hipLaunchKernelGGL(k_trsm_panel, dim3(count, nrc), dim3(FT), 0, st, t, level_nodes, k0, L, U, D);
+    hipLaunchKernelGGL(k_syrk_update, dim3(count, nrc * (nrc + 1) / 2), dim3(FT), 0, st, t, level_nodes, k0, L, U);
+  }
+  const int nrt = (max_nf + TB - 1) / TB;
+  hipLaunchKernelGGL(k_rtrsm, dim3(count, nrt), dim3(FT), 0, st, t, level_nodes, L, U, T, D);
+  const int nct = (max_no + TB - 1) / TB;
+  hipLaunchKernelGGL(k_transpose, dim3(count, nrt * nct), dim3(FT), 0, st, t, level_nodes, L, T);
 }
 
 }  // namespace riga

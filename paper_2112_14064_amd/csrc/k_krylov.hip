@@ -562,4 +562,90 @@ void launch_gemm3(int64_t n, int nq, const double* Q, const double* I0, double* 
 #undef RIGA_G3
 }
 
+// ---------------------------------------------------------------------------
+// Interleaved complex columns X (n x nv) -> planar P = [Re X | Im X].
+__global__ void k_deinterleave(int64_t n, int nv, const double* __restrict__ X, double* __restrict__ P) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < nv; ++k) {
+    P[(int64_t)k * n + i] = X[2 * ((int64_t)k * n + i)];
+    P[(int64_t)(nv + k) * n + i] = X[2 * ((int64_t)k * n + i) + 1];
+  }
+}
+
+void launch_deinterleave(int64_t n, int nv, const double* X, double* P, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_deinterleave, dim3((unsigned)blocks), dim3(256), 0, st, n, nv, X, P);
+}
+
+// Element sensitivities of the eigenvalues to a per-element damping field
+// C = C0 + sum_e c_e M_e.  For a complex-symmetric pencil the left eigenvector
+// is conj(u), so d lam / d c_e = -lam u^T M_e u / u^T (2 lam M + C) u
+// (unconjugated transposes).  With w_k = conj(dL/dlam_k) (-lam_k / d_k) given,
+// grad[e] = sum_k Re(w_k q_ke), q_ke = u_k^T M_e u_k; M_e = m_ey (x) m_ex from the
+// 1-D element tables.  One thread per element; u read from the planar P.
+constexpr int MAXP1 = 9;
+
+__global__ __launch_bounds__(256) void k_adjoint(int p, int ne, int n, const int* __restrict__ first,
+                                                 const double* __restrict__ tabM, int nv,
+                                                 const double* __restrict__ P, int64_t ndof,
+                                                 const double* __restrict__ w, double* __restrict__ grad) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)ne * ne) return;
+  const int ex = (int)(e % ne), ey = (int)(e / ne);
+  const int np = p + 1;
+  const double* mx = tabM + (int64_t)ex * np * np;
+  const double* my = tabM + (int64_t)ey * np * np;
+  // Dirichlet index of the local functions (-1: removed boundary function)
+  int gx[MAXP1], gy[MAXP1];
+  for (int l = 0; l < np; ++l) {
+    const int fx = first[ex] + l - 1, fy = first[ey] + l - 1;
+    gx[l] = (fx >= 0 && fx < n) ? fx : -1;
+    gy[l] = (fy >= 0 && fy < n) ? fy : -1;
+  }
+  double acc = 0.0;
+  for (int k = 0; k < nv; ++k) {
+    const double* a = P + (int64_t)k * ndof;
+    const double* bi = P + (int64_t)(nv + k) * ndof;
+    double ur[MAXP1 * MAXP1], ui[MAXP1 * MAXP1];
+    for (int ly = 0; ly < np; ++ly)
+      for (int lx = 0; lx < np; ++lx) {
+        const bool ok = gx[lx] >= 0 && gy[ly] >= 0;
+        const int64_t d = ok ? (int64_t)gy[ly] * n + gx[lx] : 0;
+        ur[ly * np + lx] = ok ? a[d] : 0.0;
+        ui[ly * np + lx] = ok ? bi[d] : 0.0;
+      }
+    // t = (m_ey (x) m_ex) u, then q = u^T t (complex, unconjugated)
+    double qr = 0.0, qi = 0.0;
+    for (int ly = 0; ly < np; ++ly)
+      for (int lx = 0; lx < np; ++lx) {
+        double tr = 0.0, ti = 0.0;
+        for (int my2 = 0; my2 < np; ++my2) {
+          double sr = 0.0, si = 0.0;
+          for (int mx2 = 0; mx2 < np; ++mx2) {
+            const double m = mx[lx * np + mx2];
+            sr += m * ur[my2 * np + mx2];
+            si += m * ui[my2 * np + mx2];
+          }
+          const double m = my[ly * np + my2];
+          tr += m * sr;
+          ti += m * si;
+        }
+        const double vr = ur[ly * np + lx], vi = ui[ly * np + lx];
+        qr += vr * tr - vi * ti;
+        qi += vr * ti + vi * tr;
+      }
+    acc += w[2 * k] * qr - w[2 * k + 1] * qi;   // Re(w q)
+  }
+  grad[e] = acc;
+}
+
+void launch_adjoint(const DevSpace& s, const double* tabM, int nv, const double* P, int64_t ndof,
+                    const double* w, double* grad, hipStream_t st) {
+  const int64_t ne2 = (int64_t)s.ne * s.ne;
+  const int64_t blocks = (ne2 + 255) / 256;
+  hipLaunchKernelGGL(k_adjoint, dim3((unsigned)blocks), dim3(256), 0, st, s.p, s.ne, s.n, s.first, tabM, nv, P,
+                     ndof, w, grad);
+}
+
 }  // namespace riga

@@ -22,6 +22,7 @@ struct DevTree {
   const int* foff; const int* fdofs; const int* fkey; const int* fpos;
   const int* coff; const int* clist; const int* moff; const int* maps;
   const int* voff;              // per node: offset of its solve update vector (nb entries)
+  const int64_t* doff;          // per node: first 64x64 block of its diagonal inverses
 };
 
 // --- assembly ---------------------------------------------------------------
@@ -35,14 +36,15 @@ void launch_assemble(const DevSpace& s, const double* tabM, const double* tabK,
                      double* K, double* M, double* C, int64_t ndof, hipStream_t st);
 
 // --- factorization ------------------------------------------------------------
-// One launch per tree level: assemble each front (original entries of
-// Q = s2 M + s1 C + K plus the children's update blocks), eliminate its own
-// dofs by a blocked right-looking Cholesky with FP64 MFMA trailing updates, and
-// leave F = [L_oo^{-1}; L_bo L_oo^{-1}] column-major in L (nf x no per node) and
-// transposed in T (no x nf per node, same offsets).
-void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count,
-                         double s2, double s1, const double* K, const double* M, const double* C,
-                         double* L, double* U, double* T, int64_t* status, hipStream_t st);
+// One tree level: assemble each front (original entries of Q = s2 M + s1 C + K
+// plus the children's update blocks), eliminate its own dofs by a 64-wide
+// blocked right-looking Cholesky with FP64 MFMA panel and trailing updates,
+// and leave F = [L_oo^{-1}; L_bo L_oo^{-1}] column-major in L (nf x no per node)
+// and transposed in T (no x nf per node, same offsets).  D holds the 64x64
+// inverses of the diagonal blocks (doff); max_no / max_nf bound the level.
+void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
+                         int max_nf, double s2, double s1, const double* K, const double* M, const double* C,
+                         double* L, double* U, double* T, double* D, int64_t* status, hipStream_t st);
 
 // --- forward / backward solves ------------------------------------------------
 // One launch per tree level; tasks[k] = {node, first row, end row, 0}.
@@ -98,5 +100,11 @@ void launch_block_normalize(int nc, int nq, const double* h1, const double* h2, 
 // Out_m = In_m Q (n x nq times nq x nq) for three pairs sharing Q and ld.
 void launch_gemm3(int64_t n, int nq, const double* Q, const double* I0, double* O0, const double* I1, double* O1,
                   const double* I2, double* O2, int64_t ld, hipStream_t st);
+
+// Interleaved complex columns -> planar [Re | Im].
+void launch_deinterleave(int64_t n, int nv, const double* X, double* P, hipStream_t st);
+// grad[e] = sum_k Re(w_k u_k^T M_e u_k) for every element e (see k_krylov.hip).
+void launch_adjoint(const DevSpace& s, const double* tabM, int nv, const double* P, int64_t ndof,
+                    const double* w, double* grad, hipStream_t st);
 
 }  // namespace riga

@@ -2,7 +2,9 @@
 //
 // The nested-dissection tree follows the observation of Sec. 3.3: in rIGA the
 // C^0 hyperplanes coincide with the separators of a multifrontal solver, so
-// the domain is bisected along hyperplanes until single macroelements remain.
+// the domain is bisected along hyperplanes until single macroelements remain;
+// macroelements longer than the leaf size are bisected further at element
+// interfaces.
 // A separator holds every function whose support crosses the cutting line:
 // one function thick at a C^0 hyperplane, p functions thick at an ordinary
 // element interface of maximum-continuity IGA.
@@ -45,8 +47,11 @@ void Space1D::build(int p_, int ne_, int s_) {
 
 namespace {
 
-// Cut candidates strictly inside (lo, hi): hyperplanes for rIGA, any element
-// interface for IGA while the box is larger than the leaf size.
+// Cut position strictly inside (lo, hi).  rIGA boxes are cut at the C^0
+// hyperplane nearest the middle; a box without an interior hyperplane (inside
+// one macroelement) and every IGA box is cut at its middle element interface
+// while it is longer than `leaf` elements (the separator there is p functions
+// thick, as in maximum-continuity IGA).
 int pick_cut(int lo, int hi, int s, int leaf) {
   int mid2 = lo + hi;  // twice the midpoint
   int best = -1, bestd = 1 << 30;
@@ -55,9 +60,9 @@ int pick_cut(int lo, int hi, int s, int leaf) {
       int d = std::abs(2 * c - mid2);
       if (d < bestd) { bestd = d; best = c; }
     }
-  } else if (hi - lo > leaf) {
-    best = (lo + hi) / 2;
+    if (best >= 0) return best;
   }
+  if (hi - lo > leaf) best = (lo + hi) / 2;
   return best;
 }
 

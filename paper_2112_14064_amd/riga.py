@@ -50,7 +50,7 @@ class riga_stats_t(C.Structure):
 
 
 EXPORTS = ["riga_create", "riga_info", "riga_assemble", "riga_export_csr", "riga_factor",
-           "riga_solve_q", "riga_apply_op", "riga_eigs", "riga_stats", "riga_time_kernel",
+           "riga_solve_q", "riga_apply_op", "riga_eigs", "riga_adjoint", "riga_stats", "riga_time_kernel",
            "riga_selftest_small_eig", "riga_status_str", "riga_destroy"]
 
 _lib = None
@@ -73,6 +73,7 @@ def load(path: str = LIB_PATH):
     lib.riga_solve_q.argtypes = [P, C.c_int, P, P]
     lib.riga_apply_op.argtypes = [P, C.c_int, P, P]
     lib.riga_eigs.argtypes = [P, C.POINTER(riga_options), P, P, P, C.POINTER(C.c_int)]
+    lib.riga_adjoint.argtypes = [P, C.c_int, P, P, P, P]
     lib.riga_stats.argtypes = [P, C.POINTER(riga_stats_t)]
     lib.riga_time_kernel.argtypes = [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.POINTER(C.c_int)]
@@ -132,6 +133,7 @@ class Problem:
         self.stream = stream
         self.h = C.c_void_p()
         mesh = riga_mesh(p, ne, hyper_every, leaf)
+        self.p, self.ne, self.hyper_every = p, ne, hyper_every
         _check(self.lib.riga_create(C.byref(self.h), C.byref(mesh), device, C.c_void_p(stream.cuda_stream)),
                "riga_create")
         self._c_elem = None
@@ -218,6 +220,21 @@ class Problem:
         _check(self.lib.riga_time_kernel(self.h, which, nrhs, reps, C.byref(ms), C.byref(work), C.byref(nl)),
                "riga_time_kernel")
         return ms.value, work.value, nl.value
+
+    def adjoint(self, lam, X, dL_dlam):
+        """dL/dc_e for every element, a float64 tensor (ne, ne) [ey, ex].
+        lam: complex ndarray (nev,); X: complex tensor (nev, ndof) on this device;
+        dL_dlam: complex ndarray (nev,), dL/dRe(lam) + 1j dL/dIm(lam)."""
+        torch = self.torch
+        nev = len(lam)
+        lam_h = np.ascontiguousarray(np.stack([np.real(lam), np.imag(lam)], 1).reshape(-1), dtype=np.float64)
+        g_h = np.ascontiguousarray(np.stack([np.real(dL_dlam), np.imag(dL_dlam)], 1).reshape(-1), dtype=np.float64)
+        Xr = torch.view_as_real(X.to(self.device).contiguous()).contiguous()
+        ne = self.ne
+        grad = torch.empty((ne, ne), dtype=torch.float64, device=self.device)
+        _check(self.lib.riga_adjoint(self.h, nev, lam_h.ctypes.data_as(C.c_void_p), _ptr(Xr),
+                                     g_h.ctypes.data_as(C.c_void_p), _ptr(grad)), "riga_adjoint")
+        return grad
 
     def stats(self):
         s = riga_stats_t()
