@@ -20,7 +20,9 @@
  *     valid for the duration of the call; "host" pointers are ordinary memory.
  *     The library owns everything it allocates internally (matrices, factor,
  *     Krylov workspace) and frees it in riga_destroy.
- *   - All work is queued on the stream given to riga_create.  Calls return
+ *   - All work is ordered after the caller's earlier work on the stream given
+ *     to riga_create; riga_eigs runs its Krylov loop on a stream owned by the
+ *     handle (fenced to the caller's stream with an event).  Calls return
  *     after the result they report is known: riga_factor, riga_eigs and
  *     riga_adjoint synchronise the stream; riga_assemble, riga_solve_q and
  *     riga_apply_op return as soon as the work is queued.
@@ -84,12 +86,16 @@ typedef struct {
  *           the exact double eigenvalues of the x<->y symmetric square.
  *   tol     relative Ritz residual for convergence (0: 1e-12).
  *   seed    seed of the library's counter-based start block (used if v0 NULL).
- *   v0      device, 2N x block column-major start block, or NULL.             */
+ *   v0      device, 2N x block column-major start block, or NULL.
+ *   flags   bit 0: launch every block step eagerly instead of replaying its
+ *           captured HIP graph; bit 1: check every block step on the host (the
+ *           path otherwise taken only after a device-detected breakdown).    */
 typedef struct {
   int nev, m, maxit, block;
   double tol;
   uint64_t seed;
   const double* v0;
+  int flags;
 } riga_options;
 
 typedef struct {

@@ -32,9 +32,16 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found: the HIP toolchain is required to build libriga.so")
 
 
+# host-only sources: plain complex multiplication (no IEEE inf/nan recovery
+# calls) for the small projected eigenproblem, whose entries are finite and
+# well scaled
+HOST_FLAGS = ["-fcx-limited-range"]
+
+
 def _compile(src: str, hipcc: str) -> str:
     obj = os.path.join(OUT_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    extra = HOST_FLAGS if src.endswith(".cpp") else []
+    cmd = [hipcc, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -12,6 +12,8 @@
 #include <complex>
 #include <cstring>
 #include <functional>
+#include <map>
+#include <tuple>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -112,7 +114,7 @@ struct riga_problem {
   double *d_L = nullptr, *d_U = nullptr, *d_T = nullptr, *d_upd = nullptr, *d_tmp = nullptr, *d_tmp2 = nullptr;
   int4 *d_ftasks = nullptr, *d_btasks = nullptr;   // solve tasks, grouped by level
   double* d_D = nullptr;                            // 64x64 diagonal-block inverses
-  std::vector<int> lvl_max_no, lvl_max_nf;
+  std::vector<int> lvl_max_no, lvl_max_nf, lvl_max_cnb;
   std::vector<int> ftask_off, btask_off;
   int64_t* d_status = nullptr;
   double* d_part = nullptr;       // reduction scratch
@@ -132,6 +134,29 @@ struct riga_problem {
   int* d_flag = nullptr;          // breakdown flag of the fast path
   double *P = nullptr, *MP = nullptr, *CP = nullptr, *KP = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // The Krylov loop runs on a stream of its own (fenced to the caller's stream)
+  // so that its block steps can be captured as HIP graphs and replayed.
+  hipStream_t own_st = nullptr;
+  hipEvent_t ev_fence = nullptr;
+  double* pin = nullptr;            // pinned host staging (projected matrix, small blocks)
+  size_t pin_len = 0;
+  double* pinned(size_t len) {
+    if (pin_len < len) {
+      if (pin) hipHostFree(pin);
+      pin = nullptr;
+      pin_len = 0;
+      if (hipHostMalloc((void**)&pin, len * sizeof(double), 0) != hipSuccess) throw std::bad_alloc();
+      pin_len = len;
+    }
+    return pin;
+  }
+  std::map<std::tuple<int, int, const double*>, hipGraphExec_t> graphs;   // (k, b, V_u)
+  double graph_sigma = 0.0;
+
+  void clear_graphs() {
+    for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
 
   template <class T>
   T* dalloc(size_t count) {
@@ -213,6 +238,7 @@ void ensure_norms(riga_problem* h) {
 
 void ensure_krylov(riga_problem* h, int cols, int b) {
   if (h->kw_cols >= cols && h->kw_b >= b) return;
+  h->clear_graphs();
   for (double* p : {h->Vu, h->Vl, h->Wl, h->Vu2, h->Vl2, h->Wl2, h->Ru, h->Rl, h->MRl, h->Tv, h->Mvu,
                     h->d_small, h->d_H})
     h->dfree(p);
@@ -336,11 +362,13 @@ riga_status riga_create(riga_problem** out, const riga_mesh* mesh, int device, v
       h->d_D = h->dalloc<double>((size_t)doff.back() * 4096);
       h->lvl_max_no.assign(P.height, 0);
       h->lvl_max_nf.assign(P.height, 0);
+      h->lvl_max_cnb.assign(P.height, 0);
       for (int lv = 0; lv < P.height; ++lv)
         for (int k = P.level_off[lv]; k < P.level_off[lv + 1]; ++k) {
           const int v = P.level_nodes[k];
           h->lvl_max_no[lv] = std::max(h->lvl_max_no[lv], P.no[v]);
           h->lvl_max_nf[lv] = std::max(h->lvl_max_nf[lv], P.nf[v]);
+          for (int c : P.nodes[v].children) h->lvl_max_cnb[lv] = std::max(h->lvl_max_cnb[lv], P.nb[c]);
         }
     }
     {
@@ -369,6 +397,8 @@ riga_status riga_create(riga_problem** out, const riga_mesh* mesh, int device, v
     ck(hipMemset(h->d_ticket, 0, 4 * sizeof(unsigned)));
     ck(hipEventCreate(&h->ev0));
     ck(hipEventCreate(&h->ev1));
+    ck(hipEventCreateWithFlags(&h->ev_fence, hipEventDisableTiming));
+    ck(hipStreamCreateWithFlags(&h->own_st, hipStreamNonBlocking));
     return RIGA_OK;
   });
   if (rc != RIGA_OK) {
@@ -383,9 +413,14 @@ void riga_destroy(riga_problem* h) {
   if (!h) return;
   hipSetDevice(h->device);
   if (h->st) hipStreamSynchronize(h->st); else hipDeviceSynchronize();
+  if (h->own_st) hipStreamSynchronize(h->own_st);
+  h->clear_graphs();
   for (void* p : h->allocs) hipFree(p);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
+  if (h->ev_fence) hipEventDestroy(h->ev_fence);
+  if (h->pin) hipHostFree(h->pin);
+  if (h->own_st) hipStreamDestroy(h->own_st);
   delete h;
 }
 
@@ -459,7 +494,7 @@ riga_status riga_factor(riga_problem* h, double sigma, int64_t* bad_pivot) {
     ck(hipEventRecord(h->ev0, h->st));
     for (int lv = 0; lv < P.height; ++lv) {
       int a = P.level_off[lv], c = P.level_off[lv + 1] - a;
-      riga::launch_front_factor(h->ds, h->dt, h->d_level_nodes + a, c, h->lvl_max_no[lv], h->lvl_max_nf[lv],
+      riga::launch_front_factor(h->ds, h->dt, h->d_level_nodes + a, c, h->lvl_max_no[lv], h->lvl_max_nf[lv], h->lvl_max_cnb[lv],
                                 sigma * sigma, sigma, h->d_K, h->d_M, h->d_C, h->d_L, h->d_U, h->d_T, h->d_D,
                                 h->d_status, h->st);
     }
@@ -574,7 +609,7 @@ riga_status riga_time_kernel(riga_problem* h, int which, int nrhs, int reps, dou
                                  nullptr, 0, 0.0, P.max_front, h->st);
         } else {
           int a = P.level_off[lv], c = P.level_off[lv + 1] - a;
-          riga::launch_front_factor(h->ds, h->dt, h->d_level_nodes + a, c, h->lvl_max_no[lv], h->lvl_max_nf[lv],
+          riga::launch_front_factor(h->ds, h->dt, h->d_level_nodes + a, c, h->lvl_max_no[lv], h->lvl_max_nf[lv], h->lvl_max_cnb[lv],
                                     h->sigma * h->sigma, h->sigma, h->d_K, h->d_M, h->d_C, h->d_L, h->d_U, h->d_T,
                                     h->d_D, h->d_status, h->st);
         }
@@ -657,6 +692,7 @@ struct KrylovRun {
   std::vector<double> H;   // ldh x ldh, column-major
   int k = 0;               // processed columns
   bool fast = true;        // device-resident normalisation, no host round-trip per step
+  bool graphs = true;      // replay captured block steps (fast path only)
   int64_t n_fb = 0, n_mv = 0, n_vv = 0;
 
   double& Hat(int r, int c) { return H[r + (size_t)c * ldh]; }
@@ -728,10 +764,8 @@ struct KrylovRun {
       riga::launch_cgs_update(N, nc, b, h1, h->Vu, h->Ru, h->Vl, h->Rl, h->Wl, h->MRl, N, N, h->st);
       riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, h2, h->st);
       riga::launch_cgs_update(N, nc, b, h2, h->Vu, h->Ru, h->Vl, h->Rl, h->Wl, h->MRl, N, N, h->st);
-      n_vv += 8LL * nc * b;
     }
     riga::launch_dots(N, b, h->Ru, h->MRl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, dG, h->st);
-    n_vv += 2LL * b * b;
     riga::launch_block_normalize(nc, b, nc > 0 ? h1 : nullptr, nc > 0 ? h2 : nullptr, dG, dest, ldh, col, dRinv,
                                  h->d_flag, h->st);
     const size_t o = (size_t)nc * N;
@@ -805,19 +839,54 @@ struct KrylovRun {
     }
   }
 
-  void step(uint64_t seed) {
+  // One block step on the device: S applied to V[:, k:k+b], CGS2 against
+  // V[:, 0:k+b], device normalisation into V[:, k+b:k+2b] and H.
+  void enqueue_step_device() {
     const int64_t n = N;
     const size_t o = (size_t)k * n;
     apply_block(h, b, h->Vu + o, h->Wl + o, n, h->Ru, h->Rl, h->Tv, h->Mvu);
     // M r_l = sigma M r_u + M v_u
     riga::launch_spmv(h->ds, n, b, h->d_M, h->sigma, nullptr, 0, nullptr, 0, h->Ru, n, h->MRl, n, h->Mvu, n,
                       1.0, nullptr, 0, h->st);
-    n_fb += b;
-    n_mv += 3LL * b;
+    orthonormalize_device(k + b, h->d_H, k);
+  }
+
+  void step(uint64_t seed) {
+    const int64_t n = N;
+    const size_t o = (size_t)k * n;
     const int nc = k + b;
     if (fast) {
-      orthonormalize_device(nc, h->d_H, k);
-    } else {
+      if (graphs) {
+        auto key = std::make_tuple(k, b, (const double*)h->Vu);
+        auto it = h->graphs.find(key);
+        if (it == h->graphs.end()) {
+          ck(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+          enqueue_step_device();
+          hipGraph_t g = nullptr;
+          ck(hipStreamEndCapture(h->st, &g));
+          hipGraphExec_t ex = nullptr;
+          hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+          hipGraphDestroy(g);
+          ck(e);
+          it = h->graphs.emplace(key, ex).first;
+        }
+        ck(hipGraphLaunch(it->second, h->st));
+      } else {
+        enqueue_step_device();
+      }
+      n_fb += b;
+      n_mv += 3LL * b;
+      n_vv += 8LL * nc * b + 2LL * b * b;
+      k += b;
+      return;
+    }
+    apply_block(h, b, h->Vu + o, h->Wl + o, n, h->Ru, h->Rl, h->Tv, h->Mvu);
+    // M r_l = sigma M r_u + M v_u
+    riga::launch_spmv(h->ds, n, b, h->d_M, h->sigma, nullptr, 0, nullptr, 0, h->Ru, n, h->MRl, n, h->Mvu, n,
+                      1.0, nullptr, 0, h->st);
+    n_fb += b;
+    n_mv += 3LL * b;
+    {
       std::vector<double> hs, R;
       orthonormalize(nc, hs, R, seed);
       for (int q = 0; q < b; ++q) {
@@ -844,8 +913,18 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
   if (nev < 1 || b < 1 || b > 4 || (int64_t)nev >= 2 * N) return RIGA_ERR_INVALID_ARG;
   if ((int64_t)m > 2 * N) m = (int)(2 * N);
   if (m < nev + b || m + 2 * b > 256) return RIGA_ERR_INVALID_ARG;
+  // the solve runs on the handle's own stream, fenced to the caller's stream
+  hipStream_t user_st = h->st;
+  struct Restore {
+    riga_problem* h; hipStream_t s;
+    ~Restore() { h->st = s; }
+  } restore{h, user_st};
   return run([&]() -> riga_status {
     ck(hipSetDevice(h->device));
+    ck(hipEventRecord(h->ev_fence, user_st));
+    ck(hipStreamWaitEvent(h->own_st, h->ev_fence, 0));
+    h->st = h->own_st;
+    if (h->graph_sigma != h->sigma) { h->clear_graphs(); h->graph_sigma = h->sigma; }
     ensure_norms(h);
     const int ldh = m + 2 * b;
     ensure_krylov(h, ldh, b);
@@ -860,7 +939,9 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     // First attempt on the fast path; a breakdown reported by the device sends
     // the solve once more through the host-checked path.
     for (int attempt = 0; attempt < 2; ++attempt) {
-    kr.fast = (attempt == 0);
+    kr.fast = (attempt == 0) && !(opt->flags & 2);
+    kr.graphs = !(opt->flags & 1);
+    if (!kr.fast && attempt == 0) attempt = 1;
     kr.H.assign((size_t)ldh * ldh, 0.0);
     kr.n_fb = kr.n_mv = kr.n_vv = 0;
     it = 0;
@@ -893,10 +974,14 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     for (;;) {
       while (kr.k + b <= m) kr.step(step_seed++);
       if (kr.fast) {
-        int flag = 0;
-        ck(hipMemcpyAsync(kr.H.data(), h->d_H, sizeof(double) * (size_t)ldh * ldh, hipMemcpyDeviceToHost, h->st));
-        ck(hipMemcpyAsync(&flag, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, h->st));
+        const size_t hl = (size_t)ldh * ldh;
+        double* stage = h->pinned(2 * hl + 8);
+        ck(hipMemcpyAsync(stage, h->d_H, sizeof(double) * hl, hipMemcpyDeviceToHost, h->st));
+        ck(hipMemcpyAsync(stage + 2 * hl, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, h->st));
         ck(hipStreamSynchronize(h->st));
+        std::memcpy(kr.H.data(), stage, sizeof(double) * hl);
+        int flag = 0;
+        std::memcpy(&flag, stage + 2 * hl, sizeof(int));
         if (flag) { broke = true; break; }
       }
       const int k = kr.k;
@@ -978,7 +1063,11 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
         for (int t2 = 0; t2 < k; ++t2) Qe[t2 + (size_t)c * kin] = Qk[t2 + (size_t)c * k];
       for (int q = 0; q < b; ++q) Qe[(k + q) + (size_t)(r + q) * kin] = 1.0;
       double* dQ = h->d_small;
-      ck(hipMemcpyAsync(dQ, Qe.data(), Qe.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
+      {
+        double* stage = h->pinned(2 * (size_t)ldh * ldh + 8);
+        std::memcpy(stage, Qe.data(), Qe.size() * sizeof(double));
+        ck(hipMemcpyAsync(dQ, stage, Qe.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
+      }
       riga::launch_gemm_tall(N, h->Vu, N, kin, dQ, kout, h->Vu2, 1, N, h->st);
       riga::launch_gemm_tall(N, h->Vl, N, kin, dQ, kout, h->Vl2, 1, N, h->st);
       riga::launch_gemm_tall(N, h->Wl, N, kin, dQ, kout, h->Wl2, 1, N, h->st);
@@ -989,8 +1078,12 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
         for (int rr = 0; rr < r; ++rr) kr.Hat(rr, c) = Tn[rr + (size_t)c * r];
         for (int rr = 0; rr < b; ++rr) kr.Hat(r + rr, c) = En[rr + (size_t)c * b];
       }
-      if (kr.fast)
-        ck(hipMemcpyAsync(h->d_H, kr.H.data(), sizeof(double) * (size_t)ldh * ldh, hipMemcpyHostToDevice, h->st));
+      if (kr.fast) {
+        // the pinned block is free again: the restart GEMMs were synchronised
+        double* stage = h->pinned(2 * (size_t)ldh * ldh + 8);
+        std::memcpy(stage, kr.H.data(), sizeof(double) * (size_t)ldh * ldh);
+        ck(hipMemcpyAsync(h->d_H, stage, sizeof(double) * (size_t)ldh * ldh, hipMemcpyHostToDevice, h->st));
+      }
       kr.k = r;
     }
     if (!broke) break;
@@ -1050,20 +1143,18 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     double* dlam = h->d_small + 8;
     ck(hipMemcpyAsync(dlam, lamd.data(), lamd.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
     riga::launch_pair_resid(N, nw, h->P, h->MP, h->CP, h->KP, N, dlam, h->d_part, nsplit, h->st);
-    std::vector<double> rpart((size_t)nw * nsplit * 3);
+    std::vector<double> rpart((size_t)nw * nsplit * 5);
     ck(hipMemcpyAsync(rpart.data(), h->d_part, rpart.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
     ck(hipStreamSynchronize(h->st));
     std::vector<double> etav(nw);
-    std::vector<int64_t> imax(nw);
+    std::vector<cplx> umax(nw);
     for (int j = 0; j < nw; ++j) {
       double s = 0.0, best = -1.0;
-      int64_t bi = 0;
       for (int x = 0; x < nsplit; ++x) {
-        const double* o = &rpart[((size_t)j * nsplit + x) * 3];
+        const double* o = &rpart[((size_t)j * nsplit + x) * 5];
         s += o[0];
-        if (o[1] > best) { best = o[1]; bi = (int64_t)o[2]; }
+        if (o[1] > best) { best = o[1]; umax[j] = cplx(o[3], o[4]); }
       }
-      imax[j] = bi;
       double al = std::abs(lam_rq[j]);
       etav[j] = std::sqrt(s) / ((al * al * h->norms[2] + al * h->norms[1] + h->norms[0]) * std::sqrt(unorm2[j]));
     }
@@ -1082,34 +1173,21 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
       if (eta) eta[j] = etav[order[j]];
     }
     if (X) {
-      // scale: u^H M u = 1 and the largest entry real positive
-      std::vector<double> pv((size_t)2 * N);
-      std::vector<double> sc((size_t)2 * nw);
-      for (int j = 0; j < nw; ++j) {
-        double ar = 0, ai = 0;
-        ck(hipMemcpy(&ar, h->P + (size_t)j * N + imax[j], sizeof(double), hipMemcpyDeviceToHost));
-        ck(hipMemcpy(&ai, h->P + (size_t)(nw + j) * N + imax[j], sizeof(double), hipMemcpyDeviceToHost));
-        cplx ph = std::conj(cplx(ar, ai)) / std::abs(cplx(ar, ai));
-        cplx s = ph / std::sqrt(uMu[j]);
-        sc[2 * j] = s.real();
-        sc[2 * j + 1] = s.imag();
-      }
-      // permute columns into canonical order through a small device copy of P
-      std::vector<double> scp((size_t)2 * nout);
-      double* dsc = h->d_small + 8;
+      // scale u^H M u = 1 with an entry of largest modulus real positive, in output order
+      std::vector<double> sc((size_t)3 * nout);
       for (int j = 0; j < nout; ++j) {
-        int src = order[j];
-        scp[2 * j] = sc[2 * src];
-        scp[2 * j + 1] = sc[2 * src + 1];
-        // gather column src of the planar parts into slot j of MP (free now)
-        ck(hipMemcpyAsync(h->MP + (size_t)j * N, h->P + (size_t)src * N, N * sizeof(double),
-                          hipMemcpyDeviceToDevice, h->st));
-        ck(hipMemcpyAsync(h->MP + (size_t)(nout + j) * N, h->P + (size_t)(nw + src) * N, N * sizeof(double),
-                          hipMemcpyDeviceToDevice, h->st));
+        const int src = order[j];
+        const cplx ph = std::conj(umax[src]) / std::abs(umax[src]);
+        const cplx s = ph / std::sqrt(uMu[src]);
+        sc[3 * j] = s.real();
+        sc[3 * j + 1] = s.imag();
+        sc[3 * j + 2] = (double)src;
       }
-      ck(hipMemcpyAsync(dsc, scp.data(), scp.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
-      riga::launch_finalize(N, nout, h->MP, N, dsc, X, h->st);
-      ck(hipStreamSynchronize(h->st));
+      double* dsc = h->d_small + 8;
+      double* stage = h->pinned(sc.size() + 8);
+      std::memcpy(stage, sc.data(), sc.size() * sizeof(double));
+      ck(hipMemcpyAsync(dsc, stage, sc.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
+      riga::launch_finalize(N, nw, nout, h->P, N, dsc, X, h->st);
     }
     ck(hipEventRecord(h->ev1, h->st));
     ck(hipStreamSynchronize(h->st));

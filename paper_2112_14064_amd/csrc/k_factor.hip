@@ -10,8 +10,10 @@
 //   T block  no x nf, column-major (same offset as L): scratch, then F^T.
 // A tree level is processed by a pipeline of batched kernels whose grids span
 // every node of the level:
-//   k_front_assemble   zero the front, add the original entries of Q and the
-//                      children's update blocks (one workgroup per node);
+//   k_front_assemble   zero the front and add the original entries of Q
+//                      (64 front columns per workgroup);
+//   k_front_extend     add the children's update blocks, one child slot per
+//                      launch (64 child columns per workgroup);
 //   per 64-wide panel of own columns:
 //     k_potrf_diag     Cholesky of the 64x64 diagonal block and its inverse
 //                      D_k = L_kk^{-1} (one workgroup per node, in LDS);
@@ -76,6 +78,10 @@ __device__ __forceinline__ int acc_col(int lane, int wave, int tj) {
 }
 
 // ---------------------------------------------------------------------------------
+// Front assembly, columns [64 y, 64 y + 64) of the front per workgroup: zero
+// them (own columns in the L block, boundary columns in the U block) and add
+// the original entries Q[g, d] for the own dofs d of the chunk and front dofs g
+// at or below d.
 __global__ __launch_bounds__(FT) void k_front_assemble(
     int n, const int* __restrict__ lo, const int* __restrict__ hi, const int64_t* __restrict__ rowptr,
     DevTree t, const int* __restrict__ level_nodes, double s2, double s1,
@@ -84,15 +90,21 @@ __global__ __launch_bounds__(FT) void k_front_assemble(
   const int v = level_nodes[blockIdx.x];
   const Front F = front_of(t, v, Lbuf, Ubuf);
   const int nf = F.nf, no = F.no, nb = F.nb;
+  const int c0 = TB * blockIdx.y, c1 = min(nf, c0 + TB);
+  if (c0 >= nf) return;
   const int tid = threadIdx.x;
   const int* fd = t.fdofs + t.foff[v];
   const int* fk = t.fkey + t.foff[v];
   const int* fp = t.fpos + t.foff[v];
-  for (int64_t idx = tid; idx < (int64_t)nf * no; idx += FT) F.L[idx] = 0.0;
-  for (int64_t idx = tid; idx < (int64_t)nb * nb; idx += FT) F.U[idx] = 0.0;
+  for (int c = c0; c < c1; ++c) {
+    if (c < no) {
+      for (int r = tid; r < nf; r += FT) F.L[(int64_t)c * nf + r] = 0.0;
+    } else {
+      for (int r = tid; r < nb; r += FT) F.U[(int64_t)(c - no) * nb + r] = 0.0;
+    }
+  }
   __syncthreads();
-  // original entries Q[g, d] for own d and g in the front at or below d
-  for (int a = tid; a < no; a += FT) {
+  for (int a = c0 + tid; a < min(c1, no); a += FT) {
     const int d = fd[a];
     const int i = d % n, j = d / n;
     const int wx = hi[i] - lo[i] + 1;
@@ -105,25 +117,30 @@ __global__ __launch_bounds__(FT) void k_front_assemble(
         const int c = (x0 + x1) >> 1;
         if (fk[c] <= g) x0 = c; else x1 = c;
       }
-      if (nf > 0 && fk[x0] == g) {
+      if (fk[x0] == g) {
         const int pos = fp[x0];
-        if (pos >= a) *F.at(pos, a) = s2 * Mv[k] + s1 * Cv[k] + Kv[k];
+        if (pos >= a) F.L[(int64_t)a * nf + pos] = s2 * Mv[k] + s1 * Cv[k] + Kv[k];
       }
     }
   }
-  __syncthreads();
-  // extend-add of the children's update blocks, one child at a time
-  for (int ci = t.coff[v]; ci < t.coff[v + 1]; ++ci) {
-    const int c = t.clist[ci];
-    const int nbc = t.nb[c];
-    const double* Uc = Ubuf + t.uoff[c];
-    const int* mp = t.maps + t.moff[c];
-    for (int64_t idx = tid; idx < (int64_t)nbc * nbc; idx += FT) {
-      const int l = (int)(idx / nbc), k = (int)(idx % nbc);
-      if (k >= l) *F.at(mp[k], mp[l]) += Uc[idx];
-    }
-    __syncthreads();
-  }
+}
+
+// Extend-add of child number `slot` of every node: child columns [64 y, +64);
+// the map from child boundary to parent front positions is injective, so the
+// workgroups of one launch write disjoint entries.
+__global__ __launch_bounds__(FT) void k_front_extend(DevTree t, const int* __restrict__ level_nodes, int slot,
+                                                     double* __restrict__ Lbuf, double* __restrict__ Ubuf) {
+  const int v = level_nodes[blockIdx.x];
+  if (t.coff[v] + slot >= t.coff[v + 1]) return;
+  const Front F = front_of(t, v, Lbuf, Ubuf);
+  const int c = t.clist[t.coff[v] + slot];
+  const int nbc = t.nb[c];
+  const int l0 = TB * blockIdx.y, l1 = min(nbc, l0 + TB);
+  if (l0 >= nbc) return;
+  const double* Uc = Ubuf + t.uoff[c];
+  const int* mp = t.maps + t.moff[c];
+  for (int l = l0; l < l1; ++l)
+    for (int k = l + threadIdx.x; k < nbc; k += FT) *F.at(mp[k], mp[l]) += Uc[(int64_t)l * nbc + k];
 }
 
 // ---------------------------------------------------------------------------------
@@ -382,12 +399,17 @@ __global__ __launch_bounds__(FT) void k_transpose(DevTree t, const int* __restri
 }
 
 void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
-                         int max_nf, double s2, double s1, const double* K, const double* M, const double* C,
+                         int max_nf, int max_child_nb, double s2, double s1, const double* K, const double* M, const double* C,
                          double* L, double* U, double* T, double* D, int64_t* status,
                          hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_front_assemble, dim3(count), dim3(FT), 0, st, s.n, s.lo, s.hi, s.rowptr, t, level_nodes,
-                     s2, s1, K, M, C, L, U);
+  const int ncol = (max_nf + TB - 1) / TB;
+  hipLaunchKernelGGL(k_front_assemble, dim3(count, ncol), dim3(FT), 0, st, s.n, s.lo, s.hi, s.rowptr, t,
+                     level_nodes, s2, s1, K, M, C, L, U);
+  if (max_child_nb > 0)
+    for (int slot = 0; slot < 2; ++slot)
+      hipLaunchKernelGGL(k_front_extend, dim3(count, (max_child_nb + TB - 1) / TB), dim3(FT), 0, st, t,
+                         level_nodes, slot, L, U);
   for (int k0 = 0; k0 < max_no; k0 += TB) {
     hipLaunchKernelGGL(k_potrf_diag, dim3(count), dim3(FT), 0, st, t, level_nodes, k0, L, U, D, status);
     // rows and trailing tiles below a block that is at least one column wide

@@ -357,7 +357,8 @@ void launch_pair_forms(int64_t n, int nv, const double* P, const double* MP, con
 }
 
 // ||K u + lam C u + lam^2 M u||^2 per pair (lam[2k], lam[2k+1] = re, im) and
-// max |u_i|^2 with its index: part[(k * nsplit + x) * 3 + {0: sum, 1: max, 2: index}]
+// max |u_i|^2 with its index and value:
+// part[(k * nsplit + x) * 5 + {0: sum, 1: max, 2: index, 3: re u_i, 4: im u_i}]
 __global__ __launch_bounds__(256) void k_pair_resid(int64_t n, int nv, const double* __restrict__ P,
                                                     const double* __restrict__ MP, const double* __restrict__ CP,
                                                     const double* __restrict__ KP, int64_t ld,
@@ -397,8 +398,9 @@ __global__ __launch_bounds__(256) void k_pair_resid(int64_t n, int nv, const dou
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    double* o = part + ((int64_t)k * nsplit + blockIdx.x) * 3;
+    double* o = part + ((int64_t)k * nsplit + blockIdx.x) * 5;
     o[0] = rs[0]; o[1] = rv[0]; o[2] = (double)ri_[0];
+    o[3] = P[ca + ri_[0]]; o[4] = P[cb + ri_[0]];
   }
 }
 
@@ -408,23 +410,26 @@ void launch_pair_resid(int64_t n, int nv, const double* P, const double* MP, con
   hipLaunchKernelGGL(k_pair_resid, dim3(nsplit, nv), dim3(256), 0, st, n, nv, P, MP, CP, KP, ld, lam, part);
 }
 
-// X[2 (i + k n) + {0,1}] = s_k (a_k + i b_k): scaled eigenvectors, interleaved complex.
-__global__ void k_finalize(int64_t n, int nv, const double* __restrict__ P, int64_t ld,
+// X[2 (i + k n) + {0,1}] = s_k (a_j + i b_j) with j = src[k] (s[3k], s[3k+1] the
+// complex scale, s[3k+2] the source column): scaled eigenvectors in output
+// order, interleaved complex; P has nv planar pairs.
+__global__ void k_finalize(int64_t n, int nv, int nout, const double* __restrict__ P, int64_t ld,
                            const double* __restrict__ s, double* __restrict__ X) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  for (int k = 0; k < nv; ++k) {
-    const double a = P[(int64_t)k * ld + i], b = P[(int64_t)(nv + k) * ld + i];
-    const double sr = s[2 * k], si = s[2 * k + 1];
+  for (int k = 0; k < nout; ++k) {
+    const int j = (int)s[3 * k + 2];
+    const double a = P[(int64_t)j * ld + i], b = P[(int64_t)(nv + j) * ld + i];
+    const double sr = s[3 * k], si = s[3 * k + 1];
     X[2 * ((int64_t)k * n + i)] = a * sr - b * si;
     X[2 * ((int64_t)k * n + i) + 1] = a * si + b * sr;
   }
 }
 
-void launch_finalize(int64_t n, int nv, const double* P, int64_t ld, const double* s, double* X,
+void launch_finalize(int64_t n, int nv, int nout, const double* P, int64_t ld, const double* s, double* X,
                      hipStream_t st) {
   int64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks), dim3(256), 0, st, n, nv, P, ld, s, X);
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks), dim3(256), 0, st, n, nv, nout, P, ld, s, X);
 }
 
 // Largest absolute row sum of a CSR value array (the 1-norm of a symmetric

@@ -43,7 +43,7 @@ void launch_assemble(const DevSpace& s, const double* tabM, const double* tabK,
 // and transposed in T (no x nf per node, same offsets).  D holds the 64x64
 // inverses of the diagonal blocks (doff); max_no / max_nf bound the level.
 void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
-                         int max_nf, double s2, double s1, const double* K, const double* M, const double* C,
+                         int max_nf, int max_child_nb, double s2, double s1, const double* K, const double* M, const double* C,
                          double* L, double* U, double* T, double* D, int64_t* status, hipStream_t st);
 
 // --- forward / backward solves ------------------------------------------------
@@ -87,7 +87,7 @@ void launch_pair_forms(int64_t n, int nv, const double* P, const double* MP, con
 void launch_pair_resid(int64_t n, int nv, const double* P, const double* MP, const double* CP,
                        const double* KP, int64_t ld, const double* lam, double* part, int nsplit,
                        hipStream_t st);
-void launch_finalize(int64_t n, int nv, const double* P, int64_t ld, const double* s, double* X,
+void launch_finalize(int64_t n, int nv, int nout, const double* P, int64_t ld, const double* s, double* X,
                      hipStream_t st);
 void launch_rowabs(const int64_t* rowptr, int64_t ndof, const double* A, double* part, int nblk,
                    hipStream_t st);

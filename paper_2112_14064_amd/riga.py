@@ -34,7 +34,7 @@ class riga_damping(C.Structure):
 
 class riga_options(C.Structure):
     _fields_ = [("nev", C.c_int), ("m", C.c_int), ("maxit", C.c_int), ("block", C.c_int),
-                ("tol", C.c_double), ("seed", C.c_uint64), ("v0", C.c_void_p)]
+                ("tol", C.c_double), ("seed", C.c_uint64), ("v0", C.c_void_p), ("flags", C.c_int)]
 
 
 class riga_info_t(C.Structure):
@@ -197,7 +197,7 @@ class Problem:
         return r
 
     def eigs(self, nev: int, m: int = 0, block: int = 0, tol: float = 0.0, maxit: int = 0, seed: int = 0,
-             v0=None, vectors: bool = True):
+             v0=None, vectors: bool = True, flags: int = 0):
         """Returns (lam complex ndarray, X complex tensor (nev, ndof) or None, eta ndarray, nconv, status)."""
         torch = self.torch
         lam = np.zeros(2 * nev)
@@ -205,7 +205,7 @@ class Problem:
         X = torch.empty((nev, self.ndof, 2), dtype=torch.float64, device=self.device) if vectors else None
         if v0 is not None:
             v0 = v0.to(device=self.device, dtype=torch.float64).contiguous()
-        opt = riga_options(nev, m, maxit, block, tol, seed, _ptr(v0))
+        opt = riga_options(nev, m, maxit, block, tol, seed, _ptr(v0), flags)
         nconv = C.c_int(0)
         st = self.lib.riga_eigs(self.h, C.byref(opt), lam.ctypes.data_as(C.c_void_p), _ptr(X),
                                 eta.ctypes.data_as(C.c_void_p), C.byref(nconv))
