@@ -117,6 +117,8 @@ typedef struct {
   int64_t n_fb;         /* forward/backward solves (one per vector, N_fb)       */
   int64_t n_mv;         /* sparse matrix-vector products (N_mv)                 */
   int64_t n_vv;         /* length-N vector-vector products (N_vv)               */
+  int64_t n_ir;         /* FP64 refinement sweeps of the mixed factor (per vector;
+                           each is one residual product and one FP32 solve)    */
   double t_assemble_ms, t_factor_ms, t_eigs_ms;  /* last call, device time     */
 } riga_stats_t;
 
@@ -144,6 +146,34 @@ riga_status riga_export_csr(riga_problem* h, int which, int64_t* rowptr, int32_t
  * On RIGA_ERR_NOT_SPD, *bad_pivot (if not NULL) receives the dof whose pivot
  * failed, else -1.                                                           */
 riga_status riga_factor(riga_problem* h, double sigma, int64_t* bad_pivot);
+
+/* Largest number of refinement sweeps per solve of a mixed factor.          */
+#define RIGA_IR_MAX 10
+
+/* Mixed-precision variant of riga_factor (the shift-and-invert factorization
+ * of Sec. 4.2 / Alg. 2 with a reduced-precision factor and FP64 iterative
+ * refinement).  Fronts of the tree levels below the top `fp64_levels` levels
+ * (by height; 0 means 1, i.e. the root separator only) are factored in FP32
+ * (FP32 MFMA products and accumulation) and stored in FP32; the top levels are
+ * FP64.  Every later solve (riga_solve_q, riga_apply_op, the operator inside
+ * riga_eigs) becomes x_0 = Q~^{-1} b, x_k = x_{k-1} + Q~^{-1}(b - Q x_{k-1}),
+ * k = 1..ir_sweeps, with FP64 residuals of Q(sigma) (its values are kept
+ * beside K, M, C) and FP64 sweep arithmetic over the FP32 blocks.
+ *   ir_sweeps  0..RIGA_IR_MAX, or -1: measured here from a seeded right-hand
+ *              side, the number of sweeps after which one more sweep would
+ *              reduce the residual by less than a factor 4.
+ *   ir_hist    host, RIGA_IR_MAX+1 doubles, or NULL: ||b - Q x_k|| / ||b|| for
+ *              k = 0..RIGA_IR_MAX of that calibration solve (written whenever
+ *              not NULL).
+ *   bad_pivot  as for riga_factor.
+ * Synchronises.  riga_factor switches the handle back to FP64.  Device memory
+ * for the FP32 blocks (half the size of the FP64 factor) and the Q values is
+ * allocated at the first call and kept.                                      */
+riga_status riga_factor_mixed(riga_problem* h, double sigma, int fp64_levels, int ir_sweeps, double* ir_hist,
+                              int64_t* bad_pivot);
+
+/* Refinement sweeps per solve of the current factor (-1 for an FP64 factor). */
+riga_status riga_ir_sweeps(const riga_problem* h, int* sweeps);
 
 /* x = Q(sigma)^{-1} b by the forward and backward sweeps of the factor
  * (Sec. 5.2.2).  b, x: device, ndof x nrhs column-major, 1 <= nrhs <= 4;

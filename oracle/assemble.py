@@ -32,15 +32,20 @@ def _element_tables(p, ne, hyper_every):
     first = np.zeros(ne, dtype=np.int64)
     B = np.zeros((ne, p + 1, p + 1))   # [element, gauss point, local function]
     D = np.zeros((ne, p + 1, p + 1))
+    # every element's Gauss points in one call: the recursion acts pointwise,
+    # so each point gets the same arithmetic as if evaluated on its own
+    pts_all = (np.arange(ne)[:, None] * h + (xg[None, :] + 1.0) * 0.5 * h).reshape(-1)
+    Ball_all = basis(kv, p, pts_all)
+    Dall_all = basis_deriv(kv, p, pts_all)
+    nl = p + 1
     for e in range(ne):
         a = e * h
-        pts = a + (xg + 1.0) * 0.5 * h
         # the knot span holding the element: last knot index with t_k <= midpoint
         mid = a + 0.5 * h
         k = int(np.searchsorted(kv, mid, side="right") - 1)
         first[e] = k - p
-        Ball = basis(kv, p, pts)
-        Dall = basis_deriv(kv, p, pts)
+        Ball = Ball_all[e * nl:(e + 1) * nl]
+        Dall = Dall_all[e * nl:(e + 1) * nl]
         B[e] = Ball[:, k - p:k + 1]
         D[e] = Dall[:, k - p:k + 1]
         # every other function must vanish on this element

@@ -38,32 +38,34 @@ def _hipcc() -> str:
 HOST_FLAGS = ["-fcx-limited-range"]
 
 
-def _compile(src: str, hipcc: str) -> str:
-    obj = os.path.join(OUT_DIR, os.path.splitext(src)[0] + ".o")
+def _compile(src: str, hipcc: str, out_dir: str, defines: list) -> str:
+    obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
     extra = HOST_FLAGS if src.endswith(".cpp") else []
-    cmd = [hipcc, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc, *FLAGS, *extra, *defines, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source for gfx950 and link libriga.so; returns its path."""
-    os.makedirs(OUT_DIR, exist_ok=True)
+def build(verbose: bool = False, lib: str = LIB, out_dir: str = OUT_DIR, defines=()) -> str:
+    """Compile every source for gfx950 and link `lib` (default: the in-tree
+    libriga.so); `defines` are extra -D options (tile and launch-shape
+    constants); returns the library path."""
+    os.makedirs(out_dir, exist_ok=True)
     hipcc = _hipcc()
     jobs = min(len(SOURCES), max(1, min(8, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, hipcc), SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, hipcc, out_dir, list(defines)), SOURCES))
+    tmp = lib + ".tmp"
     cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {lib}")
+    return lib
 
 
 if __name__ == "__main__":

@@ -112,6 +112,8 @@ struct riga_problem {
   double *d_gx = nullptr, *d_gw = nullptr, *d_tabM = nullptr, *d_tabK = nullptr;
   double *d_K = nullptr, *d_M = nullptr, *d_C = nullptr;
   double *d_L = nullptr, *d_U = nullptr, *d_T = nullptr, *d_upd = nullptr, *d_tmp = nullptr, *d_tmp2 = nullptr;
+  double *d_Lp = nullptr, *d_Tp = nullptr;         // F in the sweep layouts
+  int64_t lpsize = 0, tpsize = 0;
   int4 *d_ftasks = nullptr, *d_btasks = nullptr;   // solve tasks, grouped by level
   double* d_D = nullptr;                            // 64x64 diagonal-block inverses
   std::vector<int> lvl_max_no, lvl_max_nf, lvl_max_cnb;
@@ -152,6 +154,20 @@ struct riga_problem {
   }
   std::map<std::tuple<int, int, const double*>, hipGraphExec_t> graphs;   // (k, b, V_u)
   double graph_sigma = 0.0;
+  int64_t graph_key = 0;            // factor mode the captured graphs were recorded for
+  // Mixed-precision factor: nodes of height < mixed_thr are FP32 (same offsets
+  // as the FP64 blocks, in arrays of their own); every solve is refined
+  // ir_sweeps times with FP64 residuals of Q, whose values are kept in d_Q.
+  bool mixed = false;
+  int mixed_thr = 0, ir_sweeps = 0;
+  float *d_L32 = nullptr, *d_T32 = nullptr, *d_U32 = nullptr, *d_D32 = nullptr;
+  float *d_Lp32 = nullptr, *d_Tp32 = nullptr;
+  double *d_Q = nullptr, *d_irX = nullptr, *d_irR = nullptr, *d_irD = nullptr;
+  unsigned char* d_prec = nullptr;
+  int prec_thr = -1;                // threshold d_prec was written for
+  int64_t n_ir = 0;                 // refinement sweeps issued outside the Krylov loop
+  int64_t factor_key() const { return mixed ? 1 + (int64_t)ir_sweeps * 64 + (int64_t)mixed_thr * 4096 : 0; }
+  bool level_f32(int lv) const { return mixed && lv < mixed_thr; }
 
   void clear_graphs() {
     for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
@@ -193,19 +209,56 @@ riga_status run(const std::function<riga_status()>& f) {
 }
 
 // ---- forward / backward solve -------------------------------------------------
-void solve_levels(riga_problem* h, int nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
-                  double* r_l, const double* v_u, int64_t ldv, double sig) {
+// One forward and one backward sweep over all levels, each level with the
+// precision its factor blocks were computed in.
+void sweep(riga_problem* h, int nrhs, const double* b, int64_t ldb, const riga::BwdOut& o) {
   const riga::Plan& P = h->plan;
   const int H = P.height;
   for (int lv = 0; lv < H; ++lv) {
     int a = h->ftask_off[lv], c = h->ftask_off[lv + 1] - a;
-    riga::launch_fwd_level(h->dt, h->d_ftasks + a, c, nrhs, h->d_L, b, ldb, h->d_tmp, h->N(), h->d_upd,
-                           P.max_front, h->st);
+    const bool f32 = h->level_f32(lv);
+    riga::launch_fwd_level(h->dt, h->d_ftasks + a, c, nrhs, h->d_Lp, f32 ? h->d_Lp32 : nullptr, b, ldb, h->d_tmp,
+                           h->N(), h->d_upd, P.max_front, h->st);
   }
   for (int lv = H - 1; lv >= 0; --lv) {
     int a = h->btask_off[lv], c = h->btask_off[lv + 1] - a;
-    riga::launch_bwd_level(h->dt, h->d_btasks + a, c, nrhs, h->d_T, h->d_tmp, h->N(), x, ldx, r_l, v_u, ldv,
-                           sig, P.max_front, h->st);
+    const bool f32 = h->level_f32(lv);
+    riga::launch_bwd_level(h->dt, h->d_btasks + a, c, nrhs, h->d_Tp, f32 ? h->d_Tp32 : nullptr, h->d_tmp, h->N(), o,
+                           P.max_front, h->st);
+  }
+}
+
+// x = Q^{-1} b, or with r_l the operator epilogue r_u = -Q^{-1} b (into x),
+// r_l = sig r_u + v_u.  With the mixed factor the solution is refined with
+// FP64 residuals: x_0 = Q~^{-1} b, x_k = x_{k-1} + Q~^{-1}(b - Q x_{k-1}).
+// b is read for the last time before x or r_l is written, so either may alias it.
+void solve_levels(riga_problem* h, int nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
+                  double* r_l, const double* v_u, int64_t ldv, double sig) {
+  const int K = h->mixed ? h->ir_sweeps : 0;
+  riga::BwdOut o;
+  if (K == 0) {
+    o.xs = x; o.ldxs = ldx; o.neg = r_l != nullptr ? 1 : 0;
+    o.rl = r_l; o.v_u = v_u; o.ldv = ldv; o.ldr = ldx; o.sig = sig;
+    sweep(h, nrhs, b, ldb, o);
+    return;
+  }
+  const int64_t N = h->N();
+  o.xs = h->d_irX; o.ldxs = N;
+  sweep(h, nrhs, b, ldb, o);
+  for (int k = 1; k <= K; ++k) {
+    riga::launch_spmv(h->ds, N, nrhs, h->d_Q, -1.0, nullptr, 0.0, nullptr, 0.0, h->d_irX, N, h->d_irR, N, b, ldb,
+                      1.0, nullptr, 0, h->st);
+    riga::BwdOut c;
+    c.xs = h->d_irD; c.ldxs = N;
+    c.base = h->d_irX; c.ldbase = N;
+    if (k < K) {
+      c.ru = h->d_irX; c.ldr = N;
+    } else {
+      c.ru = x; c.ldr = ldx;
+      c.scale = r_l != nullptr ? -1.0 : 1.0;
+      c.rl = r_l; c.v_u = v_u; c.ldv = ldv; c.sig = sig;
+    }
+    sweep(h, nrhs, h->d_irR, N, c);
   }
 }
 
@@ -356,6 +409,20 @@ riga_status riga_create(riga_problem** out, const riga_mesh* mesh, int device, v
     h->d_L = h->dalloc<double>(P.lsize); h->d_U = h->dalloc<double>(P.usize);
     h->d_T = h->dalloc<double>(P.lsize);
     {
+      // sweep layouts: every node padded to groups of 4 columns / rows
+      std::vector<int64_t> lpoff(P.nf.size() + 1, 0), tpoff(P.nf.size() + 1, 0);
+      for (size_t v = 0; v < P.nf.size(); ++v) {
+        lpoff[v + 1] = lpoff[v] + (int64_t)((P.no[v] + 3) / 4 * 4) * P.nf[v];
+        tpoff[v + 1] = tpoff[v] + (int64_t)((P.nf[v] + 3) / 4 * 4) * P.no[v];
+      }
+      h->lpsize = lpoff.back();
+      h->tpsize = tpoff.back();
+      h->dt.lpoff = h->upload(lpoff);
+      h->dt.tpoff = h->upload(tpoff);
+      h->d_Lp = h->dalloc<double>(h->lpsize);
+      h->d_Tp = h->dalloc<double>(h->tpsize);
+    }
+    {
       std::vector<int64_t> doff(P.nf.size() + 1, 0);
       for (size_t v = 0; v < P.nf.size(); ++v) doff[v + 1] = doff[v] + (P.no[v] + 63) / 64;
       h->dt.doff = h->upload(doff);
@@ -483,38 +550,157 @@ riga_status riga_export_csr(riga_problem* h, int which, int64_t* rowptr, int32_t
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+// Factor level lv of the tree (FP32 if the mixed threshold says so).
+void factor_level(riga_problem* h, int lv, double sigma) {
+  const riga::Plan& P = h->plan;
+  int a = P.level_off[lv], c = P.level_off[lv + 1] - a;
+  riga::DevTree t = h->dt;
+  if (h->mixed) t.prec = h->d_prec;
+  if (h->level_f32(lv))
+    riga::launch_front_factor(h->ds, t, h->d_level_nodes + a, c, h->lvl_max_no[lv], h->lvl_max_nf[lv],
+                              h->lvl_max_cnb[lv], sigma * sigma, sigma, h->d_K, h->d_M, h->d_C, h->d_L32, h->d_U32,
+                              h->d_T32, h->d_D32, h->d_Lp32, h->d_Tp32, h->d_status, h->st);
+  else
+    riga::launch_front_factor(h->ds, t, h->d_level_nodes + a, c, h->lvl_max_no[lv], h->lvl_max_nf[lv],
+                              h->lvl_max_cnb[lv], sigma * sigma, sigma, h->d_K, h->d_M, h->d_C, h->d_L, h->d_U,
+                              h->d_T, h->d_D, h->d_Lp, h->d_Tp, h->d_U32, h->d_status, h->st);
+}
+
+// Factor every level; RIGA_ERR_NOT_SPD with *bad_pivot on a failed pivot.
+riga_status factor_all(riga_problem* h, double sigma, int64_t* bad_pivot) {
+  const riga::Plan& P = h->plan;
+  ck(hipMemsetAsync(h->d_status, 0xFF, sizeof(int64_t), h->st));
+  ck(hipEventRecord(h->ev0, h->st));
+  for (int lv = 0; lv < P.height; ++lv) factor_level(h, lv, sigma);
+  if (h->mixed) riga::launch_combine_q(P.nnz, sigma * sigma, sigma, h->d_K, h->d_M, h->d_C, h->d_Q, h->st);
+  ck(hipGetLastError());
+  ck(hipEventRecord(h->ev1, h->st));
+  int64_t stat = -1;
+  ck(hipMemcpyAsync(&stat, h->d_status, sizeof(int64_t), hipMemcpyDeviceToHost, h->st));
+  ck(hipStreamSynchronize(h->st));
+  float ms = 0;
+  ck(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  h->stats.t_factor_ms = ms;
+  if (stat >= 0) {
+    if (bad_pivot) *bad_pivot = stat;
+    h->factored = false;
+    return RIGA_ERR_NOT_SPD;
+  }
+  h->sigma = sigma;
+  h->factored = true;
+  return RIGA_OK;
+}
+
+// ||b - Q x|| / ||b|| history of a refined solve of one seeded right-hand side
+// (hist[0] after the unrefined solve, hist[k] after k refinement sweeps).
+void ir_history(riga_problem* h, int kmax, std::vector<double>& hist) {
+  const int64_t N = h->N();
+  double* b = h->d_tmp2;
+  riga::launch_random_fill(b, N, 1, N, 0x5eed1234ULL, h->st);
+  const int nblk = riga::dots_blocks(N);
+  double* out = h->d_part + nblk + 8;
+  auto norm2 = [&](const double* v) {
+    riga::launch_dots(N, 1, v, nullptr, N, 1, v, nullptr, N, h->d_part, h->d_ticket, out, h->st);
+    double r = 0;
+    ck(hipMemcpyAsync(&r, out, sizeof(double), hipMemcpyDeviceToHost, h->st));
+    ck(hipStreamSynchronize(h->st));
+    return std::sqrt(r);
+  };
+  const double nb = norm2(b);
+  riga::BwdOut o;
+  o.xs = h->d_irX; o.ldxs = N;
+  sweep(h, 1, b, N, o);
+  hist.clear();
+  for (int k = 0; k <= kmax; ++k) {
+    riga::launch_spmv(h->ds, N, 1, h->d_Q, -1.0, nullptr, 0.0, nullptr, 0.0, h->d_irX, N, h->d_irR, N, b, N, 1.0,
+                      nullptr, 0, h->st);
+    hist.push_back(norm2(h->d_irR) / nb);
+    if (k == kmax) break;
+    riga::BwdOut c;
+    c.xs = h->d_irD; c.ldxs = N; c.base = h->d_irX; c.ldbase = N; c.ru = h->d_irX; c.ldr = N;
+    sweep(h, 1, h->d_irR, N, c);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
 riga_status riga_factor(riga_problem* h, double sigma, int64_t* bad_pivot) {
   if (bad_pivot) *bad_pivot = -1;
   if (!h || !(sigma > 0.0) || !std::isfinite(sigma)) return RIGA_ERR_INVALID_ARG;
   if (!h->assembled) return RIGA_ERR_STATE;
   return run([&]() -> riga_status {
     ck(hipSetDevice(h->device));
+    h->mixed = false;
+    return factor_all(h, sigma, bad_pivot);
+  });
+}
+
+riga_status riga_factor_mixed(riga_problem* h, double sigma, int fp64_levels, int ir_sweeps, double* ir_hist,
+                              int64_t* bad_pivot) {
+  if (bad_pivot) *bad_pivot = -1;
+  if (!h || !(sigma > 0.0) || !std::isfinite(sigma) || fp64_levels < 0 || ir_sweeps < -1 ||
+      ir_sweeps > RIGA_IR_MAX)
+    return RIGA_ERR_INVALID_ARG;
+  if (!h->assembled) return RIGA_ERR_STATE;
+  return run([&]() -> riga_status {
+    ck(hipSetDevice(h->device));
     const riga::Plan& P = h->plan;
-    ck(hipMemsetAsync(h->d_status, 0xFF, sizeof(int64_t), h->st));
-    ck(hipEventRecord(h->ev0, h->st));
-    for (int lv = 0; lv < P.height; ++lv) {
-      int a = P.level_off[lv], c = P.level_off[lv + 1] - a;
-      riga::launch_front_factor(h->ds, h->dt, h->d_level_nodes + a, c, h->lvl_max_no[lv], h->lvl_max_nf[lv], h->lvl_max_cnb[lv],
-                                sigma * sigma, sigma, h->d_K, h->d_M, h->d_C, h->d_L, h->d_U, h->d_T, h->d_D,
-                                h->d_status, h->st);
+    const int64_t N = h->N();
+    if (!h->d_L32) {
+      std::vector<int64_t> doff_last(1);
+      ck(hipMemcpy(doff_last.data(), h->dt.doff + P.nf.size(), sizeof(int64_t), hipMemcpyDeviceToHost));
+      h->d_L32 = h->dalloc<float>(P.lsize); h->d_T32 = h->dalloc<float>(P.lsize);
+      h->d_Lp32 = h->dalloc<float>(h->lpsize); h->d_Tp32 = h->dalloc<float>(h->tpsize);
+      h->d_U32 = h->dalloc<float>(P.usize);
+      h->d_D32 = h->dalloc<float>((size_t)doff_last[0] * 4096);
+      h->d_Q = h->dalloc<double>(P.nnz);
+      h->d_irX = h->dalloc<double>((size_t)N * 4); h->d_irR = h->dalloc<double>((size_t)N * 4);
+      h->d_irD = h->dalloc<double>((size_t)N * 4);
+      h->d_prec = h->dalloc<unsigned char>(P.nf.size());
     }
-    ck(hipGetLastError());
-    ck(hipEventRecord(h->ev1, h->st));
-    int64_t stat = -1;
-    ck(hipMemcpyAsync(&stat, h->d_status, sizeof(int64_t), hipMemcpyDeviceToHost, h->st));
-    ck(hipStreamSynchronize(h->st));
-    float ms = 0;
-    ck(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-    h->stats.t_factor_ms = ms;
-    if (stat >= 0) {
-      if (bad_pivot) *bad_pivot = stat;
-      h->factored = false;
-      return RIGA_ERR_NOT_SPD;
+    const int keep = std::min(std::max(fp64_levels, 1), P.height);
+    const int thr = P.height - keep;
+    if (h->prec_thr != thr) {
+      std::vector<unsigned char> prec(P.nf.size(), 0);
+      for (size_t v = 0; v < P.nodes.size(); ++v) prec[v] = P.nodes[v].height < thr ? 1 : 0;
+      ck(hipMemcpy(h->d_prec, prec.data(), prec.size(), hipMemcpyHostToDevice));
+      h->prec_thr = thr;
     }
-    h->sigma = sigma;
-    h->factored = true;
+    h->mixed = true;
+    h->mixed_thr = thr;
+    h->ir_sweeps = 0;
+    riga_status rc = factor_all(h, sigma, bad_pivot);
+    if (rc != RIGA_OK) return rc;
+    if (ir_sweeps < 0 || ir_hist) {
+      std::vector<double> hist;
+      ir_history(h, RIGA_IR_MAX, hist);
+      if (ir_hist)
+        for (int k = 0; k <= RIGA_IR_MAX; ++k) ir_hist[k] = k < (int)hist.size() ? hist[k] : -1.0;
+      if (ir_sweeps < 0) {
+        // fewest sweeps after which a further sweep gains less than a factor 4
+        int best = 0;
+        for (int k = 1; k < (int)hist.size(); ++k) {
+          if (hist[k] > 0.25 * hist[best]) break;
+          best = k;
+        }
+        ir_sweeps = best;
+      }
+    }
+    h->ir_sweeps = ir_sweeps;
     return RIGA_OK;
   });
+}
+
+riga_status riga_ir_sweeps(const riga_problem* h, int* sweeps) {
+  if (!h || !sweeps) return RIGA_ERR_INVALID_ARG;
+  *sweeps = h->mixed ? h->ir_sweeps : -1;
+  return RIGA_OK;
 }
 
 riga_status riga_solve_q(riga_problem* h, int nrhs, const double* b, double* x) {
@@ -592,26 +778,26 @@ riga_status riga_time_kernel(riga_problem* h, int which, int nrhs, int reps, dou
     double work = 0.0;
     for (int v = 0; v < (int)P.nf.size(); ++v) {
       const double o = P.no[v], b = P.nb[v], f = P.nf[v];
+      const double esz = h->level_f32(P.nodes[v].height) ? 4.0 : 8.0;
       if (which == 2) work += o * o * o / 3.0 + b * o * o + b * b * o;
-      else work += 8.0 * (o * (o + 1) / 2 + b * o) + 8.0 * nrhs * (f + (which == 0 ? f : o));
+      else work += esz * (o * (o + 1) / 2 + b * o) + 8.0 * nrhs * (f + (which == 0 ? f : o));
     }
+    riga::BwdOut o;
+    o.xs = h->d_tmp2; o.ldxs = N;
     ck(hipEventRecord(h->ev0, h->st));
     for (int r = 0; r < reps; ++r) {
       for (int lv = 0; lv < H; ++lv) {
         if (which == 0) {
           int a = h->ftask_off[lv], c = h->ftask_off[lv + 1] - a;
-          riga::launch_fwd_level(h->dt, h->d_ftasks + a, c, nrhs, h->d_L, h->d_tmp2, N, h->d_tmp, N, h->d_upd,
-                                 P.max_front, h->st);
+          riga::launch_fwd_level(h->dt, h->d_ftasks + a, c, nrhs, h->d_Lp, h->level_f32(lv) ? h->d_Lp32 : nullptr,
+                                 h->d_tmp2, N, h->d_tmp, N, h->d_upd, P.max_front, h->st);
         } else if (which == 1) {
           int l2 = H - 1 - lv;
           int a = h->btask_off[l2], c = h->btask_off[l2 + 1] - a;
-          riga::launch_bwd_level(h->dt, h->d_btasks + a, c, nrhs, h->d_T, h->d_tmp, N, h->d_tmp2, N, nullptr,
-                                 nullptr, 0, 0.0, P.max_front, h->st);
+          riga::launch_bwd_level(h->dt, h->d_btasks + a, c, nrhs, h->d_Tp, h->level_f32(l2) ? h->d_Tp32 : nullptr,
+                                 h->d_tmp, N, o, P.max_front, h->st);
         } else {
-          int a = P.level_off[lv], c = P.level_off[lv + 1] - a;
-          riga::launch_front_factor(h->ds, h->dt, h->d_level_nodes + a, c, h->lvl_max_no[lv], h->lvl_max_nf[lv], h->lvl_max_cnb[lv],
-                                    h->sigma * h->sigma, h->sigma, h->d_K, h->d_M, h->d_C, h->d_L, h->d_U, h->d_T,
-                                    h->d_D, h->d_status, h->st);
+          factor_level(h, lv, h->sigma);
         }
       }
     }
@@ -924,7 +1110,11 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     ck(hipEventRecord(h->ev_fence, user_st));
     ck(hipStreamWaitEvent(h->own_st, h->ev_fence, 0));
     h->st = h->own_st;
-    if (h->graph_sigma != h->sigma) { h->clear_graphs(); h->graph_sigma = h->sigma; }
+    if (h->graph_sigma != h->sigma || h->graph_key != h->factor_key()) {
+      h->clear_graphs();
+      h->graph_sigma = h->sigma;
+      h->graph_key = h->factor_key();
+    }
     ensure_norms(h);
     const int ldh = m + 2 * b;
     ensure_krylov(h, ldh, b);
@@ -1196,7 +1386,8 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     h->stats.t_eigs_ms = ms;
     h->stats.n_it = it;
     h->stats.n_fb = kr.n_fb;
-    h->stats.n_mv = kr.n_mv;
+    h->stats.n_ir = h->mixed ? kr.n_fb * h->ir_sweeps : 0;
+    h->stats.n_mv = kr.n_mv + h->stats.n_ir;   // one residual product per refinement sweep
     h->stats.n_vv = kr.n_vv;
     if (nconv) *nconv = conv_out;
     return converged ? RIGA_OK : RIGA_WARN_NOT_CONVERGED;

@@ -7,7 +7,7 @@
 //   L block  nf x no, column-major (ld nf): the own columns of the front;
 //   U block  nb x nb, column-major: the update (Schur complement) matrix that
 //            the parent adds into its front ("extend-add");
-//   T block  no x nf, column-major (same offset as L): scratch, then F^T.
+//   T block  no x nf, column-major (same offset as L): F^T, the rows of F.
 // A tree level is processed by a pipeline of batched kernels whose grids span
 // every node of the level:
 //   k_front_assemble   zero the front and add the original entries of Q
@@ -23,10 +23,15 @@
 //   k_rtrsm            rows of F = [L_oo^{-1}; L_bo L_oo^{-1}] from
 //                      X L_oo = [I; L_bo], block column by block column from
 //                      the right with the stored D_k               (MFMA)
-//   k_transpose        F column-major into the L block (T keeps F^T).
+//   k_pack             F in the two sweep layouts Lp / Tp (16-byte groups of
+//                      columns / rows).
 // With F, each forward/backward sweep is one matrix-vector product per node.
-// All products use v_mfma_f64_16x16x4_f64 on 64x64 tiles staged in LDS; each
-// of the four waves owns a 32x32 quadrant (2x2 MFMA tiles).
+// Every kernel is a template over the element type E of the node's front:
+// double (v_mfma_f64_16x16x4_f64) or float (v_mfma_f32_16x16x4_f32, FP32
+// products and accumulation) for the mixed-precision factorization, where the
+// lower tree levels are FP32 and the top levels FP64.  Products run on 64x64
+// tiles staged in LDS; each of the four waves owns a 32x32 quadrant (2x2 MFMA
+// tiles).
 #include "kernels.hpp"
 #include "mfma_layout.hpp"
 
@@ -36,42 +41,48 @@ namespace riga {
 
 constexpr int FT = 256;     // threads per workgroup
 constexpr int TB = 64;      // panel / tile width
-constexpr int LDT = TB + 1; // LDS row stride (doubles)
+constexpr int LDT = TB + 1; // LDS row stride (elements)
 
+template <class E>
 struct Front {
-  double* L; double* U; int nf, no, nb;
-  __device__ __forceinline__ double* at(int i, int j) const {  // requires i >= j
+  E* L; E* U; int nf, no, nb;
+  __device__ __forceinline__ E* at(int i, int j) const {  // requires i >= j
     return j < no ? L + (int64_t)j * nf + i : U + (int64_t)(j - no) * nb + (i - no);
   }
 };
 
-__device__ __forceinline__ Front front_of(const DevTree& t, int v, double* Lbuf, double* Ubuf) {
-  return Front{Lbuf + t.loff[v], Ubuf + t.uoff[v], t.nf[v], t.no[v], t.nb[v]};
+template <class E>
+__device__ __forceinline__ Front<E> front_of(const DevTree& t, int v, E* Lbuf, E* Ubuf) {
+  return Front<E>{Lbuf + t.loff[v], Ubuf + t.uoff[v], t.nf[v], t.no[v], t.nb[v]};
 }
+
+template <class E> using acc_t = typename Mfma<E>::acc_t;
 
 // acc += sign * A (64 x kw) B (kw x 64), A at As[i * LDT + k], B at Bs[k * LDT + j];
 // wave w owns rows 32 (w >> 1) .. and columns 32 (w & 1) .., as 2 x 2 MFMA tiles.
-__device__ __forceinline__ void mma64(const double* As, const double* Bs, int kw, dvec4 (&acc)[2][2],
-                                      int lane, int wave, double sign) {
+template <class E>
+__device__ __forceinline__ void mma64(const E* As, const E* Bs, int kw, acc_t<E> (&acc)[2][2],
+                                      int lane, int wave, E sign) {
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   for (int k0 = 0; k0 < kw; k0 += 4) {
     const int k = k0 + mfma_ab_k(lane);
-    double a[2], b[2];
+    E a[2], b[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      a[t] = (k < kw) ? sign * As[(wr + 16 * t + mfma_a_row(lane)) * LDT + k] : 0.0;
-      b[t] = (k < kw) ? Bs[k * LDT + wc + 16 * t + mfma_b_col(lane)] : 0.0;
+      a[t] = (k < kw) ? sign * As[(wr + 16 * t + mfma_a_row(lane)) * LDT + k] : E(0);
+      b[t] = (k < kw) ? Bs[k * LDT + wc + 16 * t + mfma_b_col(lane)] : E(0);
     }
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
       for (int tj = 0; tj < 2; ++tj)
-        acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+        acc[ti][tj] = Mfma<E>::mma(a[ti], b[tj], acc[ti][tj]);
   }
 }
 
+template <class E>
 __device__ __forceinline__ int acc_row(int lane, int wave, int ti, int v) {
-  return (wave >> 1) * 32 + 16 * ti + mfma_d_row(lane, v);
+  return (wave >> 1) * 32 + 16 * ti + Mfma<E>::drow(lane, v);
 }
 __device__ __forceinline__ int acc_col(int lane, int wave, int tj) {
   return (wave & 1) * 32 + 16 * tj + mfma_d_col(lane);
@@ -81,14 +92,15 @@ __device__ __forceinline__ int acc_col(int lane, int wave, int tj) {
 // Front assembly, columns [64 y, 64 y + 64) of the front per workgroup: zero
 // them (own columns in the L block, boundary columns in the U block) and add
 // the original entries Q[g, d] for the own dofs d of the chunk and front dofs g
-// at or below d.
+// at or below d (formed in FP64, stored in E).
+template <class E>
 __global__ __launch_bounds__(FT) void k_front_assemble(
     int n, const int* __restrict__ lo, const int* __restrict__ hi, const int64_t* __restrict__ rowptr,
     DevTree t, const int* __restrict__ level_nodes, double s2, double s1,
     const double* __restrict__ Kv, const double* __restrict__ Mv, const double* __restrict__ Cv,
-    double* __restrict__ Lbuf, double* __restrict__ Ubuf) {
+    E* __restrict__ Lbuf, E* __restrict__ Ubuf) {
   const int v = level_nodes[blockIdx.x];
-  const Front F = front_of(t, v, Lbuf, Ubuf);
+  const Front<E> F = front_of(t, v, Lbuf, Ubuf);
   const int nf = F.nf, no = F.no, nb = F.nb;
   const int c0 = TB * blockIdx.y, c1 = min(nf, c0 + TB);
   if (c0 >= nf) return;
@@ -98,9 +110,9 @@ __global__ __launch_bounds__(FT) void k_front_assemble(
   const int* fp = t.fpos + t.foff[v];
   for (int c = c0; c < c1; ++c) {
     if (c < no) {
-      for (int r = tid; r < nf; r += FT) F.L[(int64_t)c * nf + r] = 0.0;
+      for (int r = tid; r < nf; r += FT) F.L[(int64_t)c * nf + r] = E(0);
     } else {
-      for (int r = tid; r < nb; r += FT) F.U[(int64_t)(c - no) * nb + r] = 0.0;
+      for (int r = tid; r < nb; r += FT) F.U[(int64_t)(c - no) * nb + r] = E(0);
     }
   }
   __syncthreads();
@@ -119,7 +131,7 @@ __global__ __launch_bounds__(FT) void k_front_assemble(
       }
       if (fk[x0] == g) {
         const int pos = fp[x0];
-        if (pos >= a) F.L[(int64_t)a * nf + pos] = s2 * Mv[k] + s1 * Cv[k] + Kv[k];
+        if (pos >= a) F.L[(int64_t)a * nf + pos] = (E)(s2 * Mv[k] + s1 * Cv[k] + Kv[k]);
       }
     }
   }
@@ -127,55 +139,66 @@ __global__ __launch_bounds__(FT) void k_front_assemble(
 
 // Extend-add of child number `slot` of every node: child columns [64 y, +64);
 // the map from child boundary to parent front positions is injective, so the
-// workgroups of one launch write disjoint entries.
+// workgroups of one launch write disjoint entries.  A child's update block is
+// FP32 (U32) when t.prec marks the child, else FP64 (U64).
+template <class E>
 __global__ __launch_bounds__(FT) void k_front_extend(DevTree t, const int* __restrict__ level_nodes, int slot,
-                                                     double* __restrict__ Lbuf, double* __restrict__ Ubuf) {
+                                                     E* __restrict__ Lbuf, E* __restrict__ Ubuf,
+                                                     const float* __restrict__ U32,
+                                                     const double* __restrict__ U64) {
   const int v = level_nodes[blockIdx.x];
   if (t.coff[v] + slot >= t.coff[v + 1]) return;
-  const Front F = front_of(t, v, Lbuf, Ubuf);
+  const Front<E> F = front_of(t, v, Lbuf, Ubuf);
   const int c = t.clist[t.coff[v] + slot];
   const int nbc = t.nb[c];
   const int l0 = TB * blockIdx.y, l1 = min(nbc, l0 + TB);
   if (l0 >= nbc) return;
-  const double* Uc = Ubuf + t.uoff[c];
   const int* mp = t.maps + t.moff[c];
-  for (int l = l0; l < l1; ++l)
-    for (int k = l + threadIdx.x; k < nbc; k += FT) *F.at(mp[k], mp[l]) += Uc[(int64_t)l * nbc + k];
+  if (t.prec != nullptr && t.prec[c]) {
+    const float* Uc = U32 + t.uoff[c];
+    for (int l = l0; l < l1; ++l)
+      for (int k = l + threadIdx.x; k < nbc; k += FT) *F.at(mp[k], mp[l]) += (E)Uc[(int64_t)l * nbc + k];
+  } else {
+    const double* Uc = U64 + t.uoff[c];
+    for (int l = l0; l < l1; ++l)
+      for (int k = l + threadIdx.x; k < nbc; k += FT) *F.at(mp[k], mp[l]) += (E)Uc[(int64_t)l * nbc + k];
+  }
 }
 
 // ---------------------------------------------------------------------------------
 // Cholesky of the diagonal block [k0, k0+w) and D = its inverse (lower), stored
 // at D + (doff[v] + k0/64) * 4096 as D[r * 64 + c].
+template <class E>
 __global__ __launch_bounds__(FT) void k_potrf_diag(DevTree t, const int* __restrict__ level_nodes, int k0,
-                                                   double* __restrict__ Lbuf, double* __restrict__ Ubuf,
-                                                   double* __restrict__ Dbuf,
+                                                   E* __restrict__ Lbuf, E* __restrict__ Ubuf,
+                                                   E* __restrict__ Dbuf,
                                                    int64_t* __restrict__ status) {
   const int v = level_nodes[blockIdx.x];
-  const Front F = front_of(t, v, Lbuf, Ubuf);
+  const Front<E> F = front_of(t, v, Lbuf, Ubuf);
   if (F.no <= k0) return;
   const int w = min(TB, F.no - k0);
   const int tid = threadIdx.x;
-  __shared__ double S[TB][LDT];
-  __shared__ double Dl[TB][LDT];
-  __shared__ double piv_s;
+  __shared__ E S[TB][LDT];
+  __shared__ E Dl[TB][LDT];
+  __shared__ E piv_s;
   for (int idx = tid; idx < TB * TB; idx += FT) {
     const int r = idx % TB, c = idx / TB;       // coalesced along the column
-    S[r][c] = (r < w && c <= r) ? F.L[(int64_t)(k0 + c) * F.nf + k0 + r] : 0.0;
+    S[r][c] = (r < w && c <= r) ? F.L[(int64_t)(k0 + c) * F.nf + k0 + r] : E(0);
   }
   __syncthreads();
   for (int c = 0; c < w; ++c) {
     if (tid == 0) {
-      double piv = S[c][c];
+      double piv = (double)S[c][c];
       if (!(piv > 0.0)) {           // not SPD (or NaN): record, continue with 1
         atomicCAS((unsigned long long*)status, (unsigned long long)(-1ll),
                   (unsigned long long)t.fdofs[t.foff[v] + k0 + c]);
         piv = 1.0;
       }
-      piv_s = sqrt(piv);
+      piv_s = (E)sqrt(piv);
       S[c][c] = piv_s;
     }
     __syncthreads();
-    const double inv = 1.0 / piv_s;
+    const E inv = E(1) / piv_s;
     for (int r = c + 1 + tid; r < w; r += FT) S[r][c] *= inv;
     __syncthreads();
     const int m = w - c - 1;   // trailing order
@@ -188,11 +211,11 @@ __global__ __launch_bounds__(FT) void k_potrf_diag(DevTree t, const int* __restr
   // inverse of the lower-triangular block, one column per thread
   if (tid < TB) {
     const int c = tid;
-    for (int r = 0; r < TB; ++r) Dl[r][c] = 0.0;
+    for (int r = 0; r < TB; ++r) Dl[r][c] = E(0);
     if (c < w) {
-      Dl[c][c] = 1.0 / S[c][c];
+      Dl[c][c] = E(1) / S[c][c];
       for (int r = c + 1; r < w; ++r) {
-        double sacc = 0.0;
+        E sacc = E(0);
         for (int k = c; k < r; ++k) sacc += S[r][k] * Dl[k][c];
         Dl[r][c] = -sacc / S[r][r];
       }
@@ -203,55 +226,57 @@ __global__ __launch_bounds__(FT) void k_potrf_diag(DevTree t, const int* __restr
     const int r = idx % TB, c = idx / TB;
     if (r < w && c <= r) F.L[(int64_t)(k0 + c) * F.nf + k0 + r] = S[r][c];
   }
-  double* D = Dbuf + ((int64_t)t.doff[v] + k0 / TB) * (TB * TB);
+  E* D = Dbuf + ((int64_t)t.doff[v] + k0 / TB) * (TB * TB);
   for (int idx = tid; idx < TB * TB; idx += FT) D[idx] = Dl[idx / TB][idx % TB];
 }
 
 // Panel rows [k0 + w + 64 y, +64) of columns [k0, k0 + w): X = A D^T.
+template <class E>
 __global__ __launch_bounds__(FT) void k_trsm_panel(DevTree t, const int* __restrict__ level_nodes, int k0,
-                                                   double* __restrict__ Lbuf, double* __restrict__ Ubuf,
-                                                   const double* __restrict__ Dbuf) {
+                                                   E* __restrict__ Lbuf, E* __restrict__ Ubuf,
+                                                   const E* __restrict__ Dbuf) {
   const int v = level_nodes[blockIdx.x];
-  const Front F = front_of(t, v, Lbuf, Ubuf);
+  const Front<E> F = front_of(t, v, Lbuf, Ubuf);
   if (F.no <= k0) return;
   const int w = min(TB, F.no - k0);
   const int r0 = k0 + w + TB * blockIdx.y;
   if (r0 >= F.nf) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ double As[TB * LDT];
-  __shared__ double Bs[TB * LDT];
-  const double* D = Dbuf + ((int64_t)t.doff[v] + k0 / TB) * (TB * TB);
+  __shared__ E As[TB * LDT];
+  __shared__ E Bs[TB * LDT];
+  const E* D = Dbuf + ((int64_t)t.doff[v] + k0 / TB) * (TB * TB);
   for (int idx = tid; idx < TB * TB; idx += FT) {
     const int i = idx % TB, k = idx / TB;        // row i of the tile, column k (coalesced in i)
     const int r = r0 + i;
-    As[i * LDT + k] = (r < F.nf && k < w) ? F.L[(int64_t)(k0 + k) * F.nf + r] : 0.0;
+    As[i * LDT + k] = (r < F.nf && k < w) ? F.L[(int64_t)(k0 + k) * F.nf + r] : E(0);
     const int kk = idx / TB, j = idx % TB;        // Bs[k][j] = D[j][k]
     Bs[kk * LDT + j] = D[j * TB + kk];
   }
   __syncthreads();
-  dvec4 acc[2][2];
+  acc_t<E> acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = dvec4{0.0, 0.0, 0.0, 0.0};
-  mma64(As, Bs, w, acc, lane, wave, 1.0);
+    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t<E>{0, 0, 0, 0};
+  mma64<E>(As, Bs, w, acc, lane, wave, E(1));
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
       for (int vv = 0; vv < 4; ++vv) {
-        const int r = r0 + acc_row(lane, wave, ti, vv), c = acc_col(lane, wave, tj);
+        const int r = r0 + acc_row<E>(lane, wave, ti, vv), c = acc_col(lane, wave, tj);
         if (r < F.nf && c < w) F.L[(int64_t)(k0 + c) * F.nf + r] = acc[ti][tj][vv];
       }
 }
 
 // Trailing update below the panel [k0, k0 + w): tiles (I, J), J <= I, of the
 // front rows/columns from s0 = k0 + w, pair index in blockIdx.y.
+template <class E>
 __global__ __launch_bounds__(FT) void k_syrk_update(DevTree t, const int* __restrict__ level_nodes, int k0,
-                                                    double* __restrict__ Lbuf, double* __restrict__ Ubuf) {
+                                                    E* __restrict__ Lbuf, E* __restrict__ Ubuf) {
   const int v = level_nodes[blockIdx.x];
-  const Front F = front_of(t, v, Lbuf, Ubuf);
+  const Front<E> F = front_of(t, v, Lbuf, Ubuf);
   if (F.no <= k0) return;
   const int w = min(TB, F.no - k0);
   const int s0 = k0 + w;
@@ -263,50 +288,51 @@ __global__ __launch_bounds__(FT) void k_syrk_update(DevTree t, const int* __rest
   const int rI = s0 + TB * I, rJ = s0 + TB * J;
   if (rI >= F.nf) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ double As[TB * LDT];
-  __shared__ double Bs[TB * LDT];
+  __shared__ E As[TB * LDT];
+  __shared__ E Bs[TB * LDT];
   for (int idx = tid; idx < TB * TB; idx += FT) {
     const int i = idx % TB, k = idx / TB;
     const int ra = rI + i, rb = rJ + i;
-    As[i * LDT + k] = (ra < F.nf && k < w) ? F.L[(int64_t)(k0 + k) * F.nf + ra] : 0.0;
-    Bs[k * LDT + i] = (rb < F.nf && k < w) ? F.L[(int64_t)(k0 + k) * F.nf + rb] : 0.0;
+    As[i * LDT + k] = (ra < F.nf && k < w) ? F.L[(int64_t)(k0 + k) * F.nf + ra] : E(0);
+    Bs[k * LDT + i] = (rb < F.nf && k < w) ? F.L[(int64_t)(k0 + k) * F.nf + rb] : E(0);
   }
   __syncthreads();
-  dvec4 acc[2][2];
+  acc_t<E> acc[2][2];
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
       for (int vv = 0; vv < 4; ++vv) {
-        const int r = rI + acc_row(lane, wave, ti, vv), c = rJ + acc_col(lane, wave, tj);
-        acc[ti][tj][vv] = (r < F.nf && c < F.nf && r >= c) ? *F.at(r, c) : 0.0;
+        const int r = rI + acc_row<E>(lane, wave, ti, vv), c = rJ + acc_col(lane, wave, tj);
+        acc[ti][tj][vv] = (r < F.nf && c < F.nf && r >= c) ? *F.at(r, c) : E(0);
       }
-  mma64(As, Bs, w, acc, lane, wave, -1.0);
+  mma64<E>(As, Bs, w, acc, lane, wave, E(-1));
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
       for (int vv = 0; vv < 4; ++vv) {
-        const int r = rI + acc_row(lane, wave, ti, vv), c = rJ + acc_col(lane, wave, tj);
+        const int r = rI + acc_row<E>(lane, wave, ti, vv), c = rJ + acc_col(lane, wave, tj);
         if (r < F.nf && c < F.nf && r >= c) *F.at(r, c) = acc[ti][tj][vv];
       }
 }
 
 // Rows [64 y, +64) of X with X L_oo = [I; L_bo]; X row r at T[r * no + ...].
+template <class E>
 __global__ __launch_bounds__(FT) void k_rtrsm(DevTree t, const int* __restrict__ level_nodes,
-                                              double* __restrict__ Lbuf, double* __restrict__ Ubuf,
-                                              double* __restrict__ Tbuf, const double* __restrict__ Dbuf) {
+                                              E* __restrict__ Lbuf, E* __restrict__ Ubuf,
+                                              E* __restrict__ Tbuf, const E* __restrict__ Dbuf) {
   const int v = level_nodes[blockIdx.x];
-  const Front F = front_of(t, v, Lbuf, Ubuf);
+  const Front<E> F = front_of(t, v, Lbuf, Ubuf);
   const int nf = F.nf, no = F.no;
   const int r0 = TB * blockIdx.y;
   if (r0 >= nf || no == 0) return;
-  double* T = Tbuf + t.loff[v];
+  E* T = Tbuf + t.loff[v];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ double As[TB * LDT];
-  __shared__ double Bs[TB * LDT];
+  __shared__ E As[TB * LDT];
+  __shared__ E Bs[TB * LDT];
   const int npan = (no + TB - 1) / TB;
   const bool top = (r0 + TB <= no);            // every row of the block is an own row
   for (int P = npan - 1; P >= 0; --P) {
@@ -314,20 +340,20 @@ __global__ __launch_bounds__(FT) void k_rtrsm(DevTree t, const int* __restrict__
     if (top && r0 + TB - 1 < c0) {               // X[r][c] = 0 for c > r < no
       for (int idx = tid; idx < TB * TB; idx += FT) {
         const int i = idx / TB, j = idx % TB;
-        if (j < w) T[(int64_t)(r0 + i) * no + c0 + j] = 0.0;
+        if (j < w) T[(int64_t)(r0 + i) * no + c0 + j] = E(0);
       }
       continue;
     }
-    dvec4 acc[2][2];
+    acc_t<E> acc[2][2];
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
       for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
         for (int vv = 0; vv < 4; ++vv) {
-          const int r = r0 + acc_row(lane, wave, ti, vv), c = c0 + acc_col(lane, wave, tj);
-          double val = 0.0;
-          if (r < nf && c < c0 + w) val = (r < no) ? (r == c ? 1.0 : 0.0) : F.L[(int64_t)c * nf + r];
+          const int r = r0 + acc_row<E>(lane, wave, ti, vv), c = c0 + acc_col(lane, wave, tj);
+          E val = E(0);
+          if (r < nf && c < c0 + w) val = (r < no) ? (r == c ? E(1) : E(0)) : F.L[(int64_t)c * nf + r];
           acc[ti][tj][vv] = val;
         }
     // minus X[:, kb] L[kb, P] over solved block columns kb > P (X vanishes past the diagonal for top rows)
@@ -337,91 +363,128 @@ __global__ __launch_bounds__(FT) void k_rtrsm(DevTree t, const int* __restrict__
       __syncthreads();
       for (int idx = tid; idx < TB * TB; idx += FT) {
         const int k = idx % TB, i = idx / TB;      // As[i][k] = X[r0 + i][cb + k], coalesced in k
-        As[i * LDT + k] = (r0 + i < nf && k < wb) ? T[(int64_t)(r0 + i) * no + cb + k] : 0.0;
+        As[i * LDT + k] = (r0 + i < nf && k < wb) ? T[(int64_t)(r0 + i) * no + cb + k] : E(0);
         const int j = idx / TB, kk = idx % TB;     // Bs[k][j] = L[cb + k][c0 + j], coalesced in k
-        Bs[kk * LDT + j] = (kk < wb && j < w) ? F.L[(int64_t)(c0 + j) * nf + cb + kk] : 0.0;
+        Bs[kk * LDT + j] = (kk < wb && j < w) ? F.L[(int64_t)(c0 + j) * nf + cb + kk] : E(0);
       }
       __syncthreads();
-      mma64(As, Bs, wb, acc, lane, wave, -1.0);
+      mma64<E>(As, Bs, wb, acc, lane, wave, E(-1));
     }
     // X[:, P] = acc D_P
     __syncthreads();
-    const double* D = Dbuf + ((int64_t)t.doff[v] + P) * (TB * TB);
+    const E* D = Dbuf + ((int64_t)t.doff[v] + P) * (TB * TB);
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
       for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
         for (int vv = 0; vv < 4; ++vv)
-          As[acc_row(lane, wave, ti, vv) * LDT + acc_col(lane, wave, tj)] = acc[ti][tj][vv];
+          As[acc_row<E>(lane, wave, ti, vv) * LDT + acc_col(lane, wave, tj)] = acc[ti][tj][vv];
     for (int idx = tid; idx < TB * TB; idx += FT) Bs[(idx / TB) * LDT + idx % TB] = D[idx];
     __syncthreads();
-    dvec4 x[2][2];
+    acc_t<E> x[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) x[a][b] = dvec4{0.0, 0.0, 0.0, 0.0};
-    mma64(As, Bs, w, x, lane, wave, 1.0);
+      for (int b = 0; b < 2; ++b) x[a][b] = acc_t<E>{0, 0, 0, 0};
+    mma64<E>(As, Bs, w, x, lane, wave, E(1));
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
       for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
         for (int vv = 0; vv < 4; ++vv) {
-          const int r = r0 + acc_row(lane, wave, ti, vv), c = acc_col(lane, wave, tj);
+          const int r = r0 + acc_row<E>(lane, wave, ti, vv), c = acc_col(lane, wave, tj);
           if (r < nf && c < w) T[(int64_t)r * no + c0 + c] = x[ti][tj][vv];
         }
     __syncthreads();   // T of this block column is read as the next panel's A operand
   }
 }
 
-// F (rows of T) column-major into the L block, 64 x 64 tiles through LDS.
-__global__ __launch_bounds__(FT) void k_transpose(DevTree t, const int* __restrict__ level_nodes,
-                                                  double* __restrict__ Lbuf, const double* __restrict__ Tbuf) {
+// Sweep layout of F (rows of T, F[r][c] at T[r * no + c]) with K = 16 bytes /
+// element consecutive entries side by side, so that one lane reads K of them
+// with a single 16-byte load:
+//   Lp: columns in groups of K, F[r][gK + s] at Lp[(g nf + r) K + s],
+//       g < ceil(no/K) (forward sweep: lane = row);
+//   Tp: rows in groups of K, F[gK + s][a] at Tp[(g no + a) K + s],
+//       g < ceil(nf/K) (backward sweep: lane = own column a).
+// Padding columns / rows are written as zeros.  64 x 64 tiles through LDS.
+template <class E>
+__global__ __launch_bounds__(FT) void k_pack(DevTree t, const int* __restrict__ level_nodes,
+                                             const E* __restrict__ Tbuf, E* __restrict__ Lp, E* __restrict__ Tp) {
+  constexpr int K = 16 / sizeof(E);
   const int v = level_nodes[blockIdx.x];
   const int nf = t.nf[v], no = t.no[v];
-  const int ntr = (nf + TB - 1) / TB;
+  const int nfp = (nf + K - 1) / K * K, nop = (no + K - 1) / K * K;
+  const int ntr = (nfp + TB - 1) / TB;
   const int tr = blockIdx.y % ntr, tc = blockIdx.y / ntr;
   const int r0 = tr * TB, c0 = tc * TB;
-  if (c0 >= no || r0 >= nf) return;
-  double* L = Lbuf + t.loff[v];
-  const double* T = Tbuf + t.loff[v];
-  __shared__ double S[TB * LDT];
+  if (r0 >= nfp || c0 >= nop) return;
+  const E* T = Tbuf + t.loff[v];
+  __shared__ E S[TB * LDT];
   for (int idx = threadIdx.x; idx < TB * TB; idx += FT) {
-    const int i = idx / TB, c = idx % TB;         // read row r0 + i, contiguous in c
-    S[i * LDT + c] = (r0 + i < nf && c0 + c < no) ? T[(int64_t)(r0 + i) * no + c0 + c] : 0.0;
+    const int i = idx / TB, c = idx % TB;         // row r0 + i, contiguous in c
+    S[i * LDT + c] = (r0 + i < nf && c0 + c < no) ? T[(int64_t)(r0 + i) * no + c0 + c] : E(0);
   }
   __syncthreads();
+  E* L = Lp + t.lpoff[v];
   for (int idx = threadIdx.x; idx < TB * TB; idx += FT) {
-    const int c = idx / TB, i = idx % TB;         // write column c0 + c, contiguous in i
-    if (r0 + i < nf && c0 + c < no) L[(int64_t)(c0 + c) * nf + r0 + i] = S[i * LDT + c];
+    const int gl = idx / (TB * K), rem = idx % (TB * K), r = rem / K, sl = rem % K;
+    const int c = gl * K + sl;
+    if (r0 + r < nf && c0 + c < nop) L[((int64_t)((c0 + c) / K) * nf + r0 + r) * K + sl] = S[r * LDT + c];
+  }
+  E* Tq = Tp + t.tpoff[v];
+  for (int idx = threadIdx.x; idx < TB * TB; idx += FT) {
+    const int gl = idx / (TB * K), rem = idx % (TB * K), c = rem / K, sl = rem % K;
+    const int r = gl * K + sl;
+    if (r0 + r < nfp && c0 + c < no) Tq[((int64_t)((r0 + r) / K) * no + c0 + c) * K + sl] = S[r * LDT + c];
   }
 }
 
-void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
-                         int max_nf, int max_child_nb, double s2, double s1, const double* K, const double* M, const double* C,
-                         double* L, double* U, double* T, double* D, int64_t* status,
-                         hipStream_t st) {
+template <class E>
+void front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
+                  int max_nf, int max_child_nb, double s2, double s1, const double* K, const double* M,
+                  const double* C, E* L, E* U, E* T, E* D, E* Lp, E* Tp, const float* U32,
+                  const double* U64, int64_t* status, hipStream_t st) {
   if (count <= 0) return;
   const int ncol = (max_nf + TB - 1) / TB;
-  hipLaunchKernelGGL(k_front_assemble, dim3(count, ncol), dim3(FT), 0, st, s.n, s.lo, s.hi, s.rowptr, t,
+  hipLaunchKernelGGL(k_front_assemble<E>, dim3(count, ncol), dim3(FT), 0, st, s.n, s.lo, s.hi, s.rowptr, t,
                      level_nodes, s2, s1, K, M, C, L, U);
   if (max_child_nb > 0)
     for (int slot = 0; slot < 2; ++slot)
-      hipLaunchKernelGGL(k_front_extend, dim3(count, (max_child_nb + TB - 1) / TB), dim3(FT), 0, st, t,
-                         level_nodes, slot, L, U);
+      hipLaunchKernelGGL(k_front_extend<E>, dim3(count, (max_child_nb + TB - 1) / TB), dim3(FT), 0, st, t,
+                         level_nodes, slot, L, U, U32, U64);
   for (int k0 = 0; k0 < max_no; k0 += TB) {
-    hipLaunchKernelGGL(k_potrf_diag, dim3(count), dim3(FT), 0, st, t, level_nodes, k0, L, U, D, status);
+    hipLaunchKernelGGL(k_potrf_diag<E>, dim3(count), dim3(FT), 0, st, t, level_nodes, k0, L, U, D, status);
     // rows and trailing tiles below a block that is at least one column wide
     const int below = std::max(1, max_nf - k0 - 1);
     const int nrc = (below + TB - 1) / TB;
-    hipLaunchKernelGGL(k_trsm_panel, dim3(count, nrc), dim3(FT), 0, st, t, level_nodes, k0, L, U, D);
-    hipLaunchKernelGGL(k_syrk_update, dim3(count, nrc * (nrc + 1) / 2), dim3(FT), 0, st, t, level_nodes, k0, L, U);
+    hipLaunchKernelGGL(k_trsm_panel<E>, dim3(count, nrc), dim3(FT), 0, st, t, level_nodes, k0, L, U,
+                       (const E*)D);
+    hipLaunchKernelGGL(k_syrk_update<E>, dim3(count, nrc * (nrc + 1) / 2), dim3(FT), 0, st, t, level_nodes,
+                       k0, L, U);
   }
   const int nrt = (max_nf + TB - 1) / TB;
-  hipLaunchKernelGGL(k_rtrsm, dim3(count, nrt), dim3(FT), 0, st, t, level_nodes, L, U, T, D);
-  const int nct = (max_no + TB - 1) / TB;
-  hipLaunchKernelGGL(k_transpose, dim3(count, nrt * nct), dim3(FT), 0, st, t, level_nodes, L, T);
+  hipLaunchKernelGGL(k_rtrsm<E>, dim3(count, nrt), dim3(FT), 0, st, t, level_nodes, L, U, T, (const E*)D);
+  const int nct = (max_no + 3 + TB - 1) / TB, nrp = (max_nf + 3 + TB - 1) / TB;
+  hipLaunchKernelGGL(k_pack<E>, dim3(count, nrp * nct), dim3(FT), 0, st, t, level_nodes, (const E*)T, Lp, Tp);
+}
+
+void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
+                         int max_nf, int max_child_nb, double s2, double s1, const double* K, const double* M,
+                         const double* C, double* L, double* U, double* T, double* D, double* Lp, double* Tp,
+                         const float* U32, int64_t* status, hipStream_t st) {
+  front_factor<double>(s, t, level_nodes, count, max_no, max_nf, max_child_nb, s2, s1, K, M, C, L, U, T, D, Lp, Tp,
+                       U32, U, status, st);
+}
+
+void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
+                         int max_nf, int max_child_nb, double s2, double s1, const double* K, const double* M,
+                         const double* C, float* L, float* U, float* T, float* D, float* Lp, float* Tp,
+                         int64_t* status, hipStream_t st) {
+  // FP32 fronts only have FP32 children
+  front_factor<float>(s, t, level_nodes, count, max_no, max_nf, max_child_nb, s2, s1, K, M, C, L, U, T, D, Lp, Tp,
+                      U, nullptr, status, st);
 }
 
 }  // namespace riga

@@ -457,6 +457,22 @@ void launch_rowabs(const int64_t* rowptr, int64_t ndof, const double* A, double*
   hipLaunchKernelGGL(k_rowabs, dim3(nblk), dim3(256), 0, st, rowptr, ndof, A, part);
 }
 
+// Values of Q = s2 M + s1 C + K on the common CSR pattern, for the FP64
+// residuals of the refined mixed-precision solves.
+__global__ __launch_bounds__(256) void k_combine_q(int64_t nnz, double s2, double s1, const double* __restrict__ K,
+                                                   const double* __restrict__ M, const double* __restrict__ C,
+                                                   double* __restrict__ Q) {
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * 256)
+    Q[k] = s2 * M[k] + s1 * C[k] + K[k];
+}
+
+void launch_combine_q(int64_t nnz, double s2, double s1, const double* K, const double* M, const double* C,
+                      double* Q, hipStream_t st) {
+  const int64_t blocks = std::min<int64_t>((nnz + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_combine_q, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, nnz, s2, s1, K,
+                     M, C, Q);
+}
+
 // ---------------------------------------------------------------------------
 // Device-side end of a block Gram--Schmidt step: with h1, h2 (nc x nq, the two
 // projection passes, output-major c*nq+q) and G (nq x nq, the B-Gram matrix of

@@ -12,9 +12,11 @@
 // Every node is therefore a single matrix-vector product with no dependency
 // chain inside it; only the tree levels are sequential.  A node's rows are split
 // into tasks of 64 rows (one workgroup each: lane = row, the 8 waves take
-// interleaved 8-column chunks, partial sums combined in LDS), so every load of
-// F is coalesced and each row has many loads in flight; up to 4 right-hand
-// sides share every load.
+// interleaved chunks of column groups, partial sums combined in LDS); every
+// load is a coalesced 16-byte load per lane (2 FP64 or 4 FP32 entries, from
+// the packed layouts of the factorization) and up to 4 right-hand sides share
+// it.  F may be stored in FP32 (mixed-precision factor): its entries are
+// widened on load and every sum is accumulated in FP64.
 // The forward pass gathers children's vectors instead of scattering into
 // shared boundary entries, so neither sweep needs atomics and results are
 // bitwise reproducible.
@@ -24,8 +26,20 @@ namespace riga {
 
 constexpr int ST = 512;           // threads per task: 8 waves
 constexpr int SR = 64;            // rows per task: one per lane
-constexpr int SC = 8;             // consecutive columns per wave and round
-constexpr int SW = ST / 64;
+constexpr int SW = ST / 64;       // waves per task
+// Factor blocks are read in the sweep layouts written by the factorization:
+// K = 16 bytes / element consecutive columns (forward) or rows (backward) of
+// F side by side, one 16-byte load per lane and group; each wave keeps SG
+// group loads in flight per round.
+#ifndef RIGA_SWEEP_GROUPS
+#define RIGA_SWEEP_GROUPS 4
+#endif
+constexpr int SG = RIGA_SWEEP_GROUPS;
+template <class E>
+struct Pack {
+  static constexpr int K = 16 / sizeof(E);
+  typedef E V __attribute__((ext_vector_type(K)));
+};
 
 // acc[q] of row `lane` summed over the waves through LDS; wave 0 ends with the
 // total for its lane.
@@ -45,9 +59,9 @@ __device__ __forceinline__ void reduce_waves(double (&acc)[NR], double* red, int
   }
 }
 
-template <int NR>
+template <int NR, class E>
 __global__ __launch_bounds__(ST) void k_fwd(DevTree t, const int4* __restrict__ tasks,
-                                            const double* __restrict__ Lbuf,
+                                            const E* __restrict__ Lp,
                                             const double* __restrict__ b, int64_t ldb,
                                             double* __restrict__ y, int64_t ldy,
                                             double* __restrict__ upd) {
@@ -57,7 +71,6 @@ __global__ __launch_bounds__(ST) void k_fwd(DevTree t, const int4* __restrict__ 
   const int v = tk.x, r0 = tk.y, r1 = tk.z;
   const int nf = t.nf[v], no = t.no[v];
   double* red = shm + (size_t)nf * NR;   // SW x SR x NR partial sums
-  const double* F = Lbuf + t.loff[v];
   const int* fd = t.fdofs + t.foff[v];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
@@ -83,17 +96,23 @@ __global__ __launch_bounds__(ST) void k_fwd(DevTree t, const int4* __restrict__ 
   double acc[NR];
 #pragma unroll
   for (int q = 0; q < NR; ++q) acc[q] = 0.0;
-  const double* col = F + (live ? r : r0);
-  for (int j0 = wave * SC; j0 < jend; j0 += SW * SC) {
-    double a[SC];
+  constexpr int K = Pack<E>::K;
+  typedef typename Pack<E>::V V;
+  // group g of row r at col[g * nf]; entries past the diagonal are stored zeros
+  const V* col = reinterpret_cast<const V*>(Lp + t.lpoff[v]) + (live ? r : r0);
+  const int gend = (jend + K - 1) / K;
+  for (int g0 = wave * SG; g0 < gend; g0 += SW * SG) {
+    V a[SG];
 #pragma unroll
-    for (int u = 0; u < SC; ++u) a[u] = (j0 + u < jend) ? col[(int64_t)(j0 + u) * nf] : 0.0;
+    for (int u = 0; u < SG; ++u) a[u] = (g0 + u < gend) ? col[(int64_t)(g0 + u) * nf] : V{};
 #pragma unroll
-    for (int u = 0; u < SC; ++u) {
-      const int j = min(j0 + u, jend - 1);
+    for (int u = 0; u < SG; ++u)
 #pragma unroll
-      for (int q = 0; q < NR; ++q) acc[q] += a[u] * f[j * NR + q];
-    }
+      for (int e = 0; e < K; ++e) {
+        const int j = min((g0 + u) * K + e, nf - 1);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) acc[q] += (double)a[u][e] * f[j * NR + q];
+      }
   }
   reduce_waves<NR>(acc, red, lane, wave);
   if (wave == 0 && live) {
@@ -108,12 +127,19 @@ __global__ __launch_bounds__(ST) void k_fwd(DevTree t, const int4* __restrict__ 
   }
 }
 
-template <int NR>
+// Backward sweep of one level.  The sweep's own result x (needed by the
+// descendants as boundary values) is kept in xs, negated when `neg` is set.
+// Optional outputs: ru = scale (x + base) (base may be null; ru may alias
+// base: each entry is read and written by one thread) and
+// rl = sig val + v_u, where val is the ru value or, without ru, the xs value.
+template <int NR, class E>
 __global__ __launch_bounds__(ST) void k_bwd(DevTree t, const int4* __restrict__ tasks,
-                                            const double* __restrict__ Tbuf,
+                                            const E* __restrict__ Tp,
                                             const double* __restrict__ y, int64_t ldy,
-                                            double* __restrict__ x, int64_t ldx,
-                                            double* __restrict__ r_l, const double* __restrict__ v_u,
+                                            double* __restrict__ xs, int64_t ldxs, int neg,
+                                            const double* base, int64_t ldbase, double* ru, int64_t ldr,
+                                            double scale,
+                                            double* __restrict__ rl, const double* __restrict__ v_u,
                                             int64_t ldv, double sig) {
   extern __shared__ double shm[];
   double* w = shm;                       // [y_own; -x_bnd]
@@ -121,10 +147,8 @@ __global__ __launch_bounds__(ST) void k_bwd(DevTree t, const int4* __restrict__ 
   const int v = tk.x, a0 = tk.y, a1 = tk.z;
   const int nf = t.nf[v], no = t.no[v];
   double* red = shm + (size_t)nf * NR;
-  const double* T = Tbuf + t.loff[v];   // element (a, i) of F^T at T[i * no + a]
   const int* fd = t.fdofs + t.foff[v];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bool epilogue = (r_l != nullptr);
 
   for (int p = tid; p < nf; p += ST)
 #pragma unroll
@@ -133,8 +157,8 @@ __global__ __launch_bounds__(ST) void k_bwd(DevTree t, const int4* __restrict__ 
       if (p < no) {
         val = y[fd[p] + q * ldy];
       } else {
-        val = x[fd[p] + q * ldx];
-        if (!epilogue) val = -val;   // with the epilogue, ancestors stored r_u = -x already
+        val = xs[fd[p] + q * ldxs];
+        if (!neg) val = -val;
       }
       w[p * NR + q] = val;
     }
@@ -145,64 +169,85 @@ __global__ __launch_bounds__(ST) void k_bwd(DevTree t, const int4* __restrict__ 
 #pragma unroll
   for (int q = 0; q < NR; ++q) acc[q] = 0.0;
   // entries above the diagonal of L_oo^{-T} vanish: start at the block's first row
-  const double* row = T + (live ? a : a0);
-  for (int i0 = a0 + wave * SC; i0 < nf; i0 += SW * SC) {
-    double e[SC];
+  constexpr int K = Pack<E>::K;
+  typedef typename Pack<E>::V V;
+  // rows of F in groups of K: group g of own column a at row[g * no]; rows
+  // above the diagonal are stored zeros, so the block starts at group a0 / K
+  const V* row = reinterpret_cast<const V*>(Tp + t.tpoff[v]) + (live ? a : a0);
+  const int gbeg = a0 / K, gend = (nf + K - 1) / K;
+  for (int g0 = gbeg + wave * SG; g0 < gend; g0 += SW * SG) {
+    V e[SG];
 #pragma unroll
-    for (int u = 0; u < SC; ++u) e[u] = (i0 + u < nf) ? row[(int64_t)(i0 + u) * no] : 0.0;
+    for (int u = 0; u < SG; ++u) e[u] = (g0 + u < gend) ? row[(int64_t)(g0 + u) * no] : V{};
 #pragma unroll
-    for (int u = 0; u < SC; ++u) {
-      const int i = min(i0 + u, nf - 1);
+    for (int u = 0; u < SG; ++u)
 #pragma unroll
-      for (int q = 0; q < NR; ++q) acc[q] += e[u] * w[i * NR + q];
-    }
+      for (int k = 0; k < K; ++k) {
+        const int i = min((g0 + u) * K + k, nf - 1);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) acc[q] += (double)e[u][k] * w[i * NR + q];
+      }
   }
   reduce_waves<NR>(acc, red, lane, wave);
   if (wave == 0 && live) {
     const int d = fd[a];
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-      if (epilogue) {
-        const double ru = -acc[q];
-        x[d + q * ldx] = ru;
-        r_l[d + q * ldx] = sig * ru + v_u[d + q * ldv];
-      } else {
-        x[d + q * ldx] = acc[q];
+      double val = neg ? -acc[q] : acc[q];
+      xs[d + q * ldxs] = val;
+      if (ru != nullptr) {
+        val = scale * (acc[q] + (base != nullptr ? base[d + q * ldbase] : 0.0));
+        ru[d + q * ldr] = val;
       }
+      if (rl != nullptr) rl[d + q * ldr] = sig * val + v_u[d + q * ldv];
     }
   }
 }
 
-void launch_fwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* L,
-                      const double* b, int64_t ldb, double* y, int64_t ldy, double* upd, int max_front,
-                      hipStream_t st) {
+void launch_fwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* Lp64,
+                      const float* Lp32, const double* b, int64_t ldb, double* y, int64_t ldy, double* upd,
+                      int max_front, hipStream_t st) {
   if (count <= 0) return;
   size_t shm = ((size_t)max_front + SW * SR) * nrhs * sizeof(double);
-#define RIGA_FWD(NR) \
-  hipLaunchKernelGGL(k_fwd<NR>, dim3(count), dim3(ST), shm, st, t, tasks, L, b, ldb, y, ldy, upd)
-  switch (nrhs) {
-    case 1: RIGA_FWD(1); break;
-    case 2: RIGA_FWD(2); break;
-    case 3: RIGA_FWD(3); break;
-    default: RIGA_FWD(4); break;
+#define RIGA_FWD(NR, E, L) \
+  hipLaunchKernelGGL((k_fwd<NR, E>), dim3(count), dim3(ST), shm, st, t, tasks, L, b, ldb, y, ldy, upd)
+#define RIGA_FWD_NR(E, L)           \
+  switch (nrhs) {                   \
+    case 1: RIGA_FWD(1, E, L); break; \
+    case 2: RIGA_FWD(2, E, L); break; \
+    case 3: RIGA_FWD(3, E, L); break; \
+    default: RIGA_FWD(4, E, L); break; \
   }
+  if (Lp32 != nullptr) {
+    RIGA_FWD_NR(float, Lp32)
+  } else {
+    RIGA_FWD_NR(double, Lp64)
+  }
+#undef RIGA_FWD_NR
 #undef RIGA_FWD
 }
 
-void launch_bwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* T,
-                      const double* y, int64_t ldy, double* x, int64_t ldx, double* r_l, const double* v_u,
-                      int64_t ldv, double sig, int max_front, hipStream_t st) {
+void launch_bwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* Tp64,
+                      const float* Tp32, const double* y, int64_t ldy, const BwdOut& o, int max_front,
+                      hipStream_t st) {
   if (count <= 0) return;
   size_t shm = ((size_t)max_front + SW * SR) * nrhs * sizeof(double);
-#define RIGA_BWD(NR)                                                                               \
-  hipLaunchKernelGGL(k_bwd<NR>, dim3(count), dim3(ST), shm, st, t, tasks, T, y, ldy, x, ldx, r_l, v_u, \
-                     ldv, sig)
-  switch (nrhs) {
-    case 1: RIGA_BWD(1); break;
-    case 2: RIGA_BWD(2); break;
-    case 3: RIGA_BWD(3); break;
-    default: RIGA_BWD(4); break;
+#define RIGA_BWD(NR, E, T)                                                                            \
+  hipLaunchKernelGGL((k_bwd<NR, E>), dim3(count), dim3(ST), shm, st, t, tasks, T, y, ldy, o.xs, o.ldxs, \
+                     o.neg, o.base, o.ldbase, o.ru, o.ldr, o.scale, o.rl, o.v_u, o.ldv, o.sig)
+#define RIGA_BWD_NR(E, T)           \
+  switch (nrhs) {                   \
+    case 1: RIGA_BWD(1, E, T); break; \
+    case 2: RIGA_BWD(2, E, T); break; \
+    case 3: RIGA_BWD(3, E, T); break; \
+    default: RIGA_BWD(4, E, T); break; \
   }
+  if (Tp32 != nullptr) {
+    RIGA_BWD_NR(float, Tp32)
+  } else {
+    RIGA_BWD_NR(double, Tp64)
+  }
+#undef RIGA_BWD_NR
 #undef RIGA_BWD
 }
 

@@ -23,6 +23,9 @@ struct DevTree {
   const int* coff; const int* clist; const int* moff; const int* maps;
   const int* voff;              // per node: offset of its solve update vector (nb entries)
   const int64_t* doff;          // per node: first 64x64 block of its diagonal inverses
+  const unsigned char* prec;    // per node: 1 = FP32 front (mixed factor), or null (all FP64)
+  const int64_t* lpoff;         // per node: sweep layouts of F (multiples of 4 elements):
+  const int64_t* tpoff;         //   ceil(no/4)*4*nf and ceil(nf/4)*4*no entries
 };
 
 // --- assembly ---------------------------------------------------------------
@@ -38,24 +41,44 @@ void launch_assemble(const DevSpace& s, const double* tabM, const double* tabK,
 // --- factorization ------------------------------------------------------------
 // One tree level: assemble each front (original entries of Q = s2 M + s1 C + K
 // plus the children's update blocks), eliminate its own dofs by a 64-wide
-// blocked right-looking Cholesky with FP64 MFMA panel and trailing updates,
-// and leave F = [L_oo^{-1}; L_bo L_oo^{-1}] column-major in L (nf x no per node)
-// and transposed in T (no x nf per node, same offsets).  D holds the 64x64
-// inverses of the diagonal blocks (doff); max_no / max_nf bound the level.
+// blocked right-looking Cholesky with MFMA panel and trailing updates, and
+// leave F = [L_oo^{-1}; L_bo L_oo^{-1}] column-major in L (nf x no per node)
+// and F in the sweep layouts Lp (lpoff: groups of 16 bytes of columns) and
+// Tp (tpoff: groups of rows); L, U, T are working storage of the
+// factorization.  D holds the 64x64 inverses of the diagonal blocks (doff);
+// max_no / max_nf bound the level.
+// FP64 level: children flagged in t.prec keep their update blocks in U32.
 void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
-                         int max_nf, int max_child_nb, double s2, double s1, const double* K, const double* M, const double* C,
-                         double* L, double* U, double* T, double* D, int64_t* status, hipStream_t st);
+                         int max_nf, int max_child_nb, double s2, double s1, const double* K, const double* M,
+                         const double* C, double* L, double* U, double* T, double* D, double* Lp, double* Tp,
+                         const float* U32, int64_t* status, hipStream_t st);
+// FP32 level (FP32 products and accumulation); all children are FP32.
+void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
+                         int max_nf, int max_child_nb, double s2, double s1, const double* K, const double* M,
+                         const double* C, float* L, float* U, float* T, float* D, float* Lp, float* Tp,
+                         int64_t* status, hipStream_t st);
+// Q = s2 M + s1 C + K on the shared CSR pattern (nnz values).
+void launch_combine_q(int64_t nnz, double s2, double s1, const double* K, const double* M, const double* C,
+                      double* Q, hipStream_t st);
 
 // --- forward / backward solves ------------------------------------------------
-// One launch per tree level; tasks[k] = {node, first row, end row, 0}.
-void launch_fwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* L,
-                      const double* b, int64_t ldb, double* y, int64_t ldy, double* upd, int max_front,
+// One launch per tree level; tasks[k] = {node, first row, end row, 0}.  The
+// level's factor is read in its sweep layouts, FP64 (Lp64/Tp64) or FP32
+// (Lp32/Tp32 non-null).
+void launch_fwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* Lp64,
+                      const float* Lp32, const double* b, int64_t ldb, double* y, int64_t ldy, double* upd,
+                      int max_front, hipStream_t st);
+// Outputs of the backward sweep (see k_bwd): xs holds the sweep's solution
+// (negated if neg), optionally ru = scale (x + base) and rl = sig val + v_u.
+struct BwdOut {
+  double* xs = nullptr; int64_t ldxs = 0; int neg = 0;
+  const double* base = nullptr; int64_t ldbase = 0;
+  double* ru = nullptr; int64_t ldr = 0; double scale = 1.0;
+  double* rl = nullptr; const double* v_u = nullptr; int64_t ldv = 0; double sig = 0.0;
+};
+void launch_bwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* Tp64,
+                      const float* Tp32, const double* y, int64_t ldy, const BwdOut& o, int max_front,
                       hipStream_t st);
-// Backward sweep with the transposed blocks T; if r_l != nullptr the result is
-// written as the operator epilogue r_u = -x (into x), r_l = sig r_u + v_u.
-void launch_bwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* T,
-                      const double* y, int64_t ldy, double* x, int64_t ldx, double* r_l, const double* v_u,
-                      int64_t ldv, double sig, int max_front, hipStream_t st);
 
 // --- Krylov building blocks -----------------------------------------------------
 // Y = a0 A0 X + a1 A1 X + a2 A2 X + bz Z   (A* share the CSR pattern; A1/A2 may be null)

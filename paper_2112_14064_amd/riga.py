@@ -22,6 +22,7 @@ RIGA_ERR_HIP = -3
 RIGA_ERR_OOM = -4
 RIGA_ERR_STATE = -5
 RIGA_WARN_NOT_CONVERGED = 1
+RIGA_IR_MAX = 10
 
 
 class riga_mesh(C.Structure):
@@ -46,10 +47,11 @@ class riga_info_t(C.Structure):
 
 class riga_stats_t(C.Structure):
     _fields_ = [("n_it", C.c_int64), ("n_fb", C.c_int64), ("n_mv", C.c_int64), ("n_vv", C.c_int64),
-                ("t_assemble_ms", C.c_double), ("t_factor_ms", C.c_double), ("t_eigs_ms", C.c_double)]
+                ("n_ir", C.c_int64), ("t_assemble_ms", C.c_double), ("t_factor_ms", C.c_double), ("t_eigs_ms", C.c_double)]
 
 
-EXPORTS = ["riga_create", "riga_info", "riga_assemble", "riga_export_csr", "riga_factor",
+EXPORTS = ["riga_create", "riga_info", "riga_assemble", "riga_export_csr", "riga_factor", "riga_factor_mixed",
+           "riga_ir_sweeps",
            "riga_solve_q", "riga_apply_op", "riga_eigs", "riga_adjoint", "riga_stats", "riga_time_kernel",
            "riga_selftest_small_eig", "riga_status_str", "riga_destroy"]
 
@@ -70,6 +72,8 @@ def load(path: str = LIB_PATH):
     lib.riga_assemble.argtypes = [P, C.POINTER(riga_damping)]
     lib.riga_export_csr.argtypes = [P, C.c_int, P, P, P]
     lib.riga_factor.argtypes = [P, C.c_double, C.POINTER(C.c_int64)]
+    lib.riga_factor_mixed.argtypes = [P, C.c_double, C.c_int, C.c_int, P, C.POINTER(C.c_int64)]
+    lib.riga_ir_sweeps.argtypes = [P, C.POINTER(C.c_int)]
     lib.riga_solve_q.argtypes = [P, C.c_int, P, P]
     lib.riga_apply_op.argtypes = [P, C.c_int, P, P]
     lib.riga_eigs.argtypes = [P, C.POINTER(riga_options), P, P, P, C.POINTER(C.c_int)]
@@ -173,14 +177,35 @@ class Problem:
         self.stream.synchronize()
         return rowptr, col, val
 
-    def factor(self, sigma: float):
+    def factor(self, sigma: float, precision: str = "fp64", fp64_levels: int = 1, ir_sweeps: int = -1):
+        """Factor Q(sigma).  precision "fp64" (riga_factor) or "mixed"
+        (riga_factor_mixed: FP32 fronts below the top fp64_levels levels, FP64
+        refinement of every solve; ir_sweeps -1 lets the library choose).  For
+        "mixed" returns the calibration residual history (RIGA_IR_MAX+1 values)."""
         bad = C.c_int64(-1)
-        st = self.lib.riga_factor(self.h, sigma, C.byref(bad))
+        hist = None
+        if precision == "fp64":
+            st = self.lib.riga_factor(self.h, sigma, C.byref(bad))
+            where = "riga_factor"
+        elif precision == "mixed":
+            hist = np.full(RIGA_IR_MAX + 1, -1.0)
+            st = self.lib.riga_factor_mixed(self.h, sigma, fp64_levels, ir_sweeps, hist.ctypes.data_as(C.c_void_p),
+                                            C.byref(bad))
+            where = "riga_factor_mixed"
+        else:
+            raise ValueError(f"unknown precision {precision!r}")
         if st == RIGA_ERR_NOT_SPD:
-            err = RigaError(st, "riga_factor")
+            err = RigaError(st, where)
             err.bad_pivot = bad.value
             raise err
-        _check(st, "riga_factor")
+        _check(st, where)
+        return hist
+
+    def ir_sweeps(self) -> int:
+        """Refinement sweeps per solve of the current factor (-1: FP64 factor)."""
+        k = C.c_int(0)
+        _check(self.lib.riga_ir_sweeps(self.h, C.byref(k)), "riga_ir_sweeps")
+        return k.value
 
     def solve_q(self, b):
         """x = Q(sigma)^{-1} b for b of shape (nrhs, ndof) (rows are vectors)."""
