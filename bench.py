@@ -12,7 +12,10 @@ normalisation and residuals.  Inputs are generated (and resident on the
 device) before the timed region.  The IGA discretisation and the CPU oracle are
 measured after the timed steps and reported beside it.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-iga]
+The precision form (FP32 fronts + FP64 refinement against the FP64 path on
+the p=4, 1024^2, s=32 workload) is measured last and reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-iga] [--no-mixed]
 """
 from __future__ import annotations
 
@@ -94,6 +97,55 @@ def roofline(pr, res, block):
     return out
 
 
+def precision_form(torch, riga, W, ir_tol=1e-9):
+    """FP64 path vs the mixed path (FP32 fronts below the FP64 root level, FP64
+    refinement of every solve) on the p=4, 1024^2, s=32 workload with a
+    lognormal element damping field: phase times, eigenpairs/s and the error of
+    every mixed eigenvalue against the FP64 one."""
+    import numpy as np
+
+    P = W.cfg_precision()
+    pr = riga.Problem(P.p, P.ne, P.hyper_every, leaf=16)
+    info = pr.info
+    c = torch.from_numpy(P.c_elem).to(pr.device)
+    out = {"workload": f"p={P.p}, {P.ne}x{P.ne}, s={P.hyper_every}, c_e lognormal(-3,0.5) seed 0, "
+                       f"sigma={P.sigma}, {P.nev} pairs, subspace {P.m}", "ndof": int(info["ndof"])}
+    lams = {}
+    for prec in ("fp64", "mixed"):
+        def one():
+            pr.assemble(0.0, 0.0, c)
+            if prec == "fp64":
+                pr.factor(P.sigma)
+                hist = None
+            else:
+                hist = pr.factor(P.sigma, "mixed", fp64_levels=1, ir_sweeps=-1, ir_tol=ir_tol)
+            r = pr.eigs(P.nev, P.m, block=2, seed=0, vectors=False)
+            return hist, r
+        one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist, (lam, _, eta, nconv, st) = one()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        stats = pr.stats()
+        good = int(sum(1 for e in eta[:nconv] if e <= 1e-10))
+        lams[prec] = lam
+        rec = {"ms_per_step": ms, "eigenpairs_per_s": good * 1e3 / ms, "pairs_ok": good,
+               "factor_ms": stats["t_factor_ms"], "eigs_ms": stats["t_eigs_ms"],
+               "factor_gflops_dense": info["factor_flops_dense"] / (stats["t_factor_ms"] * 1e-3) / 1e9,
+               "n_fb": int(stats["n_fb"]), "n_ir": int(stats["n_ir"]), "max_eta": float(max(eta))}
+        if hist is not None:
+            rec["ir_sweeps"] = pr.ir_sweeps()
+            rec["ir_tol"] = ir_tol
+            rec["ir_residual_history"] = [float(x) for x in hist]
+        out[prec] = rec
+    rel = np.abs(lams["mixed"] - lams["fp64"]) / np.abs(lams["fp64"])
+    out["mixed"]["rel_err_vs_fp64"] = [float(x) for x in rel]
+    out["mixed"]["max_rel_err_vs_fp64"] = float(rel.max())
+    pr.close()
+    return out
+
+
 def cpu_baseline(P, lam_gpu):
     """The oracle as it stands: SciPy sparse LU of Q(sigma) + ARPACK on the
     shift-and-invert operator, same workload (full solve, ~30 s)."""
@@ -122,6 +174,7 @@ def main():
     ap.add_argument("--block", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-iga", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path",
@@ -170,6 +223,8 @@ def main():
             "eigs": iga["eigs_ms"] / res["eigs_ms"],
             "step": iga["ms_per_step"] / res["ms_per_step"],
         }
+    if not args.no_mixed:
+        out["precision_form"] = precision_form(torch, riga, W)
     if roof is not None:
         out["roofline"] = roof
     if not args.no_cpu:

@@ -159,9 +159,12 @@ riga_status riga_factor(riga_problem* h, double sigma, int64_t* bad_pivot);
  * riga_eigs) becomes x_0 = Q~^{-1} b, x_k = x_{k-1} + Q~^{-1}(b - Q x_{k-1}),
  * k = 1..ir_sweeps, with FP64 residuals of Q(sigma) (its values are kept
  * beside K, M, C) and FP64 sweep arithmetic over the FP32 blocks.
- *   ir_sweeps  0..RIGA_IR_MAX, or -1: measured here from a seeded right-hand
- *              side, the number of sweeps after which one more sweep would
- *              reduce the residual by less than a factor 4.
+ *   ir_sweeps  0..RIGA_IR_MAX, or -1: chosen here from a refined solve of a
+ *              seeded right-hand side: the fewest sweeps whose relative
+ *              residual ||b - Q x_k|| / ||b|| is <= ir_tol, but never more
+ *              than the point after which one more sweep would reduce it by
+ *              less than a factor 4 (ir_tol = 0: that point).
+ *   ir_tol     >= 0, used with ir_sweeps = -1.
  *   ir_hist    host, RIGA_IR_MAX+1 doubles, or NULL: ||b - Q x_k|| / ||b|| for
  *              k = 0..RIGA_IR_MAX of that calibration solve (written whenever
  *              not NULL).
@@ -169,8 +172,8 @@ riga_status riga_factor(riga_problem* h, double sigma, int64_t* bad_pivot);
  * Synchronises.  riga_factor switches the handle back to FP64.  Device memory
  * for the FP32 blocks (half the size of the FP64 factor) and the Q values is
  * allocated at the first call and kept.                                      */
-riga_status riga_factor_mixed(riga_problem* h, double sigma, int fp64_levels, int ir_sweeps, double* ir_hist,
-                              int64_t* bad_pivot);
+riga_status riga_factor_mixed(riga_problem* h, double sigma, int fp64_levels, int ir_sweeps, double ir_tol,
+                              double* ir_hist, int64_t* bad_pivot);
 
 /* Refinement sweeps per solve of the current factor (-1 for an FP64 factor). */
 riga_status riga_ir_sweeps(const riga_problem* h, int* sweeps);

@@ -2,7 +2,7 @@
 byte counters (FETCH_SIZE / WRITE_SIZE) of rocprofv3: the counters read for
 this copy are compared with the 2 x 512 MiB it must move.
 
-Usage: python -m paper_2112_14064_amd.copy_probe
+Usage: python paper_2112_14064_amd/copy_probe.py
 """
 import torch
 

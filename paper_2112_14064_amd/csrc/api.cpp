@@ -641,11 +641,11 @@ riga_status riga_factor(riga_problem* h, double sigma, int64_t* bad_pivot) {
   });
 }
 
-riga_status riga_factor_mixed(riga_problem* h, double sigma, int fp64_levels, int ir_sweeps, double* ir_hist,
-                              int64_t* bad_pivot) {
+riga_status riga_factor_mixed(riga_problem* h, double sigma, int fp64_levels, int ir_sweeps, double ir_tol,
+                              double* ir_hist, int64_t* bad_pivot) {
   if (bad_pivot) *bad_pivot = -1;
   if (!h || !(sigma > 0.0) || !std::isfinite(sigma) || fp64_levels < 0 || ir_sweeps < -1 ||
-      ir_sweeps > RIGA_IR_MAX)
+      ir_sweeps > RIGA_IR_MAX || !(ir_tol >= 0.0))
     return RIGA_ERR_INVALID_ARG;
   if (!h->assembled) return RIGA_ERR_STATE;
   return run([&]() -> riga_status {
@@ -683,10 +683,11 @@ riga_status riga_factor_mixed(riga_problem* h, double sigma, int fp64_levels, in
       if (ir_hist)
         for (int k = 0; k <= RIGA_IR_MAX; ++k) ir_hist[k] = k < (int)hist.size() ? hist[k] : -1.0;
       if (ir_sweeps < 0) {
-        // fewest sweeps after which a further sweep gains less than a factor 4
+        // fewest sweeps reaching ir_tol, and never past the point where a
+        // further sweep gains less than a factor 4
         int best = 0;
         for (int k = 1; k < (int)hist.size(); ++k) {
-          if (hist[k] > 0.25 * hist[best]) break;
+          if (hist[best] <= ir_tol || hist[k] > 0.25 * hist[best]) break;
           best = k;
         }
         ir_sweeps = best;

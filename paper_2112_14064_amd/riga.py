@@ -72,7 +72,7 @@ def load(path: str = LIB_PATH):
     lib.riga_assemble.argtypes = [P, C.POINTER(riga_damping)]
     lib.riga_export_csr.argtypes = [P, C.c_int, P, P, P]
     lib.riga_factor.argtypes = [P, C.c_double, C.POINTER(C.c_int64)]
-    lib.riga_factor_mixed.argtypes = [P, C.c_double, C.c_int, C.c_int, P, C.POINTER(C.c_int64)]
+    lib.riga_factor_mixed.argtypes = [P, C.c_double, C.c_int, C.c_int, C.c_double, P, C.POINTER(C.c_int64)]
     lib.riga_ir_sweeps.argtypes = [P, C.POINTER(C.c_int)]
     lib.riga_solve_q.argtypes = [P, C.c_int, P, P]
     lib.riga_apply_op.argtypes = [P, C.c_int, P, P]
@@ -177,11 +177,13 @@ class Problem:
         self.stream.synchronize()
         return rowptr, col, val
 
-    def factor(self, sigma: float, precision: str = "fp64", fp64_levels: int = 1, ir_sweeps: int = -1):
+    def factor(self, sigma: float, precision: str = "fp64", fp64_levels: int = 1, ir_sweeps: int = -1,
+               ir_tol: float = 0.0):
         """Factor Q(sigma).  precision "fp64" (riga_factor) or "mixed"
         (riga_factor_mixed: FP32 fronts below the top fp64_levels levels, FP64
-        refinement of every solve; ir_sweeps -1 lets the library choose).  For
-        "mixed" returns the calibration residual history (RIGA_IR_MAX+1 values)."""
+        refinement of every solve; ir_sweeps -1 lets the library choose, with
+        the residual target ir_tol).  For "mixed" returns the calibration
+        residual history (RIGA_IR_MAX+1 values)."""
         bad = C.c_int64(-1)
         hist = None
         if precision == "fp64":
@@ -189,8 +191,8 @@ class Problem:
             where = "riga_factor"
         elif precision == "mixed":
             hist = np.full(RIGA_IR_MAX + 1, -1.0)
-            st = self.lib.riga_factor_mixed(self.h, sigma, fp64_levels, ir_sweeps, hist.ctypes.data_as(C.c_void_p),
-                                            C.byref(bad))
+            st = self.lib.riga_factor_mixed(self.h, sigma, fp64_levels, ir_sweeps, ir_tol,
+                                            hist.ctypes.data_as(C.c_void_p), C.byref(bad))
             where = "riga_factor_mixed"
         else:
             raise ValueError(f"unknown precision {precision!r}")

@@ -103,6 +103,12 @@ def test_calibration_history(levels):
     assert k == _riga().RIGA_IR_MAX or hist[k + 1] > 0.25 * hist[k]
     for j in range(1, k + 1):
         assert hist[j] <= 0.25 * hist[j - 1]
+    # with a residual target: the fewest sweeps reaching it
+    for tol in (1e-6, 1e-9, 1e-12):
+        h2 = pr.factor(5.0, "mixed", fp64_levels=levels, ir_sweeps=-1, ir_tol=tol)
+        k2 = pr.ir_sweeps()
+        assert np.array_equal(h2, hist)         # the calibration solve is deterministic
+        assert hist[k2] <= tol and (k2 == 0 or hist[k2 - 1] > tol), (tol, k2, hist)
     pr.close()
 
 
@@ -190,7 +196,7 @@ def test_precision_workload_full_size():
     pr.factor(P.sigma)
     lam64, X64, eta64, n64, st64 = pr.eigs(P.nev, P.m, block=2, seed=0)
     print("[full] fp64 done", pr.stats(), flush=True)
-    hist = pr.factor(P.sigma, "mixed", fp64_levels=1, ir_sweeps=-1)
+    hist = pr.factor(P.sigma, "mixed", fp64_levels=1, ir_sweeps=-1, ir_tol=1e-9)
     k = pr.ir_sweeps()
     lam, X, eta, nconv, st = pr.eigs(P.nev, P.m, block=2, seed=0)
     print("[full] mixed done, sweeps", k, "hist", hist, pr.stats(), flush=True)
