@@ -243,6 +243,55 @@ riga_status riga_time_kernel(riga_problem* h, int which, int nrhs, int reps, dou
  * no device.                                                                 */
 riga_status riga_selftest_small_eig(int n, const double* a, double* w, double* resid);
 
+/* ---- Batched form -----------------------------------------------------------
+ * Many independent problems of different sizes (degree, mesh, hyperplane
+ * spacing, damping, shift) solved together: the nested-dissection trees are
+ * merged into one forest, so each factorization level and each sweep is one
+ * set of launches for all problems, and the Krylov--Schur iterations of all
+ * problems run in lockstep, one captured HIP graph per block step of every
+ * problem.  Each problem follows exactly the single-problem method above
+ * (same operator, orthogonalisation, restart and convergence test).          */
+typedef struct riga_batch riga_batch;
+
+/* n >= 1 problems; meshes: host array of n (as for riga_create).  Builds every
+ * plan on the host and allocates the forest on `device`.                     */
+riga_status riga_batch_create(riga_batch** out, int n, const riga_mesh* meshes, int device, void* hip_stream);
+
+/* Total dofs and (if dof_offsets is not NULL, host n+1) the first dof of every
+ * problem in the forest numbering: problem p owns rows
+ * [dof_offsets[p], dof_offsets[p+1]).                                         */
+riga_status riga_batch_info(const riga_batch* bh, int64_t* total_dofs, int64_t* dof_offsets);
+
+/* Assemble every problem; damping: host array of n (c_elem device or NULL).    */
+riga_status riga_batch_assemble(riga_batch* bh, const riga_damping* damping);
+
+/* Factor Q_p(sigma_p) of every problem; sigmas: host, n values > 0.  On
+ * RIGA_ERR_NOT_SPD, bad_pivot (host n, or NULL) holds the failing dof of the
+ * problem it occurred in (-1 elsewhere).                                     */
+riga_status riga_batch_factor(riga_batch* bh, const double* sigmas, int64_t* bad_pivot);
+
+/* The opt->nev eigenpairs nearest sigma_p of every problem (options as for
+ * riga_eigs; opt->v0 must be NULL: the start blocks come from the library's
+ * generator; 2 N_p >= m for every problem).
+ *   lam:   host, n * 2 * nev doubles, problem p at lam + 2 nev p, canonical order.
+ *   X:     device, 2 * nev * total_dofs doubles or NULL: problem p's block at
+ *          X + 2 nev dof_offsets[p], column k at + 2 k N_p, normalised as in
+ *          riga_eigs.
+ *   eta:   host, n * nev scaled residuals, or NULL.
+ *   nconv: host, n counts.
+ * A problem whose block step broke down (an exact invariant subspace) is
+ * solved again on its own with the host-checked path.  Synchronises.
+ * RIGA_WARN_NOT_CONVERGED if any problem has nconv < nev.                     */
+riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam, double* X, double* eta,
+                            int* nconv);
+
+/* Phase times and counters of the last calls (n_it: lockstep cycles; n_fb:
+ * vectors through the sweeps summed over problems); n_resolved (or NULL): the
+ * problems solved again one by one in the last riga_batch_eigs.              */
+riga_status riga_batch_stats(const riga_batch* bh, riga_stats_t* stats, int* n_resolved);
+
+void riga_batch_destroy(riga_batch* bh);
+
 const char* riga_status_str(riga_status s);
 void riga_destroy(riga_problem* h);
 

@@ -2,36 +2,20 @@
 //
 // Everything that touches N-sized data runs in the device kernels; the host
 // keeps only the projected matrix (at most ~100 x 100) and the tree plan.
-#include "../../include/riga.h"
-
-#include <hip/hip_runtime.h>
+#include "problem.hpp"
+#include "ks_host.hpp"
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
-#include <complex>
 #include <cstring>
-#include <functional>
-#include <map>
-#include <tuple>
-#include <new>
 #include <numeric>
-#include <vector>
-
-#include "kernels.hpp"
-#include "plan.hpp"
-#include "small_eig.hpp"
 
 using riga::cplx;
+using namespace riga::detail;
 
-namespace {
-
-struct HipError {
-  hipError_t e;
-};
-inline void ck(hipError_t e) {
-  if (e != hipSuccess) throw HipError{e};
-}
+namespace riga {
+namespace detail {
 
 // (p+1)-point Gauss--Legendre rule on [-1, 1]: Newton iteration on the
 // three-term Legendre recurrence started from the Chebyshev-like guesses.
@@ -98,105 +82,12 @@ std::vector<int> canonical_order(const std::vector<cplx>& lam, double sigma) {
   return out;
 }
 
-}  // namespace
+}  // namespace detail
+}  // namespace riga
 
-struct riga_problem {
-  int device = 0;
-  hipStream_t st = nullptr;
-  riga_mesh mesh{};
-  riga::Plan plan;
-  std::vector<void*> allocs;
-  riga::DevSpace ds{};
-  riga::DevTree dt{};
-  int* d_level_nodes = nullptr;
-  double *d_gx = nullptr, *d_gw = nullptr, *d_tabM = nullptr, *d_tabK = nullptr;
-  double *d_K = nullptr, *d_M = nullptr, *d_C = nullptr;
-  double *d_L = nullptr, *d_U = nullptr, *d_T = nullptr, *d_upd = nullptr, *d_tmp = nullptr, *d_tmp2 = nullptr;
-  double *d_Lp = nullptr, *d_Tp = nullptr;         // F in the sweep layouts
-  int64_t lpsize = 0, tpsize = 0;
-  int4 *d_ftasks = nullptr, *d_btasks = nullptr;   // solve tasks, grouped by level
-  double* d_D = nullptr;                            // 64x64 diagonal-block inverses
-  std::vector<int> lvl_max_no, lvl_max_nf, lvl_max_cnb;
-  std::vector<int> ftask_off, btask_off;
-  int64_t* d_status = nullptr;
-  double* d_part = nullptr;       // reduction scratch
-  unsigned* d_ticket = nullptr;
-  int64_t upd_len = 0;
-  bool assembled = false, factored = false;
-  double alpha = 0, beta = 0, sigma = 0;
-  const double* c_elem = nullptr;
-  double norms[3] = {-1, -1, -1};  // ||K||_1, ||C||_1, ||M||_1
-  riga_stats_t stats{};
-  // Krylov workspace
-  int64_t kw_cols = 0, kw_b = 0, kw_nev = 0;
-  double *Vu = nullptr, *Vl = nullptr, *Wl = nullptr, *Vu2 = nullptr, *Vl2 = nullptr, *Wl2 = nullptr;
-  double *Ru = nullptr, *Rl = nullptr, *MRl = nullptr, *Tv = nullptr, *Mvu = nullptr;
-  double *d_small = nullptr;      // device staging for h1, h2, G and small matrices
-  double *d_H = nullptr;          // device copy of the projected matrix (fast path)
-  int* d_flag = nullptr;          // breakdown flag of the fast path
-  double *P = nullptr, *MP = nullptr, *CP = nullptr, *KP = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  // The Krylov loop runs on a stream of its own (fenced to the caller's stream)
-  // so that its block steps can be captured as HIP graphs and replayed.
-  hipStream_t own_st = nullptr;
-  hipEvent_t ev_fence = nullptr;
-  double* pin = nullptr;            // pinned host staging (projected matrix, small blocks)
-  size_t pin_len = 0;
-  double* pinned(size_t len) {
-    if (pin_len < len) {
-      if (pin) hipHostFree(pin);
-      pin = nullptr;
-      pin_len = 0;
-      if (hipHostMalloc((void**)&pin, len * sizeof(double), 0) != hipSuccess) throw std::bad_alloc();
-      pin_len = len;
-    }
-    return pin;
-  }
-  std::map<std::tuple<int, int, const double*>, hipGraphExec_t> graphs;   // (k, b, V_u)
-  double graph_sigma = 0.0;
-  int64_t graph_key = 0;            // factor mode the captured graphs were recorded for
-  // Mixed-precision factor: nodes of height < mixed_thr are FP32 (same offsets
-  // as the FP64 blocks, in arrays of their own); every solve is refined
-  // ir_sweeps times with FP64 residuals of Q, whose values are kept in d_Q.
-  bool mixed = false;
-  int mixed_thr = 0, ir_sweeps = 0;
-  float *d_L32 = nullptr, *d_T32 = nullptr, *d_U32 = nullptr, *d_D32 = nullptr;
-  float *d_Lp32 = nullptr, *d_Tp32 = nullptr;
-  double *d_Q = nullptr, *d_irX = nullptr, *d_irR = nullptr, *d_irD = nullptr;
-  unsigned char* d_prec = nullptr;
-  int prec_thr = -1;                // threshold d_prec was written for
-  int64_t n_ir = 0;                 // refinement sweeps issued outside the Krylov loop
-  int64_t factor_key() const { return mixed ? 1 + (int64_t)ir_sweeps * 64 + (int64_t)mixed_thr * 4096 : 0; }
-  bool level_f32(int lv) const { return mixed && lv < mixed_thr; }
 
-  void clear_graphs() {
-    for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
-    graphs.clear();
-  }
-
-  template <class T>
-  T* dalloc(size_t count) {
-    void* p = nullptr;
-    if (count == 0) count = 1;
-    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) throw std::bad_alloc();
-    allocs.push_back(p);
-    return (T*)p;
-  }
-  void dfree(void* p) {
-    if (!p) return;
-    auto it = std::find(allocs.begin(), allocs.end(), p);
-    if (it != allocs.end()) { hipFree(p); allocs.erase(it); }
-  }
-  template <class T>
-  T* upload(const std::vector<T>& v) {
-    T* d = dalloc<T>(v.size());
-    if (!v.empty()) ck(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-    return d;
-  }
-  int64_t N() const { return plan.ndof; }
-};
-
-namespace {
+namespace riga {
+namespace detail {
 
 riga_status run(const std::function<riga_status()>& f) {
   try {
@@ -349,37 +240,7 @@ std::vector<double> upper_inverse(int b, const std::vector<double>& R) {
   return X;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* riga_status_str(riga_status s) {
-  switch (s) {
-    case RIGA_OK: return "ok";
-    case RIGA_ERR_INVALID_ARG: return "invalid argument";
-    case RIGA_ERR_NOT_SPD: return "Q(sigma) is not positive definite";
-    case RIGA_ERR_HIP: return "HIP runtime error";
-    case RIGA_ERR_OOM: return "out of device memory";
-    case RIGA_ERR_STATE: return "call out of order";
-    case RIGA_WARN_NOT_CONVERGED: return "not all requested eigenpairs converged";
-  }
-  return "unknown status";
-}
-
-riga_status riga_create(riga_problem** out, const riga_mesh* mesh, int device, void* hip_stream) {
-  if (!out || !mesh) return RIGA_ERR_INVALID_ARG;
-  *out = nullptr;
-  riga_problem* h = new (std::nothrow) riga_problem();
-  if (!h) return RIGA_ERR_OOM;
-  h->mesh = *mesh;
-  if (h->plan.build(mesh->p, mesh->ne, mesh->hyper_every, mesh->leaf) != 0) {
-    delete h;
-    return RIGA_ERR_INVALID_ARG;
-  }
-  riga_status rc = run([&]() -> riga_status {
-    ck(hipSetDevice(device));
-    h->device = device;
-    h->st = (hipStream_t)hip_stream;
+void setup_device(riga_problem* h) {
     const riga::Plan& P = h->plan;
     const riga::Space1D& S = P.sp;
     h->ds.p = S.p; h->ds.ne = S.ne; h->ds.n = S.n;
@@ -466,6 +327,41 @@ riga_status riga_create(riga_problem** out, const riga_mesh* mesh, int device, v
     ck(hipEventCreate(&h->ev1));
     ck(hipEventCreateWithFlags(&h->ev_fence, hipEventDisableTiming));
     ck(hipStreamCreateWithFlags(&h->own_st, hipStreamNonBlocking));
+}
+
+}  // namespace detail
+}  // namespace riga
+
+extern "C" {
+
+const char* riga_status_str(riga_status s) {
+  switch (s) {
+    case RIGA_OK: return "ok";
+    case RIGA_ERR_INVALID_ARG: return "invalid argument";
+    case RIGA_ERR_NOT_SPD: return "Q(sigma) is not positive definite";
+    case RIGA_ERR_HIP: return "HIP runtime error";
+    case RIGA_ERR_OOM: return "out of device memory";
+    case RIGA_ERR_STATE: return "call out of order";
+    case RIGA_WARN_NOT_CONVERGED: return "not all requested eigenpairs converged";
+  }
+  return "unknown status";
+}
+
+riga_status riga_create(riga_problem** out, const riga_mesh* mesh, int device, void* hip_stream) {
+  if (!out || !mesh) return RIGA_ERR_INVALID_ARG;
+  *out = nullptr;
+  riga_problem* h = new (std::nothrow) riga_problem();
+  if (!h) return RIGA_ERR_OOM;
+  h->mesh = *mesh;
+  if (h->plan.build(mesh->p, mesh->ne, mesh->hyper_every, mesh->leaf) != 0) {
+    delete h;
+    return RIGA_ERR_INVALID_ARG;
+  }
+  riga_status rc = run([&]() -> riga_status {
+    ck(hipSetDevice(device));
+    h->device = device;
+    h->st = (hipStream_t)hip_stream;
+    setup_device(h);
     return RIGA_OK;
   });
   if (rc != RIGA_OK) {
@@ -552,7 +448,8 @@ riga_status riga_export_csr(riga_problem* h, int which, int64_t* rowptr, int32_t
 
 }  // extern "C"
 
-namespace {
+namespace riga {
+namespace detail {
 
 // Factor level lv of the tree (FP32 if the mixed threshold says so).
 void factor_level(riga_problem* h, int lv, double sigma) {
@@ -626,7 +523,8 @@ void ir_history(riga_problem* h, int kmax, std::vector<double>& hist) {
   }
 }
 
-}  // namespace
+}  // namespace detail
+}  // namespace riga
 
 extern "C" {
 
@@ -869,7 +767,8 @@ riga_status riga_adjoint(riga_problem* h, int nev, const double* lam, const doub
 //   <x, y>_B = x_u^T y_u + x_l^T M y_l = x_u^T y_u + (M x_l)^T y_l.
 // The Krylov decomposition is S V_k = V_{k+b} H, with H (k+b) x k.
 // =============================================================================
-namespace {
+namespace riga {
+namespace detail {
 
 struct KrylovRun {
   riga_problem* h;
@@ -1085,7 +984,8 @@ struct KrylovRun {
   }
 };
 
-}  // namespace
+}  // namespace detail
+}  // namespace riga
 
 extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, double* lam, double* X,
                                  double* eta, int* nconv) {
@@ -1123,9 +1023,7 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     KrylovRun kr{h, N, b, m, nev, maxit, ldh, tol};
     int it = 0;
     bool converged = false;
-    std::vector<cplx> T, Z, Y;
-    std::vector<int> wanted;
-    std::vector<cplx> theta;
+    riga::KsCycle cyc;
     uint64_t step_seed = opt->seed * 1000003u + 5;
     // First attempt on the fast path; a breakdown reported by the device sends
     // the solve once more through the host-checked path.
@@ -1176,99 +1074,27 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
         if (flag) { broke = true; break; }
       }
       const int k = kr.k;
-      // Rayleigh--Ritz on H_k (eq. ArnoldiRitz)
-      std::vector<double> Hk((size_t)k * k);
-      for (int c = 0; c < k; ++c)
-        for (int r = 0; r < k; ++r) Hk[r + (size_t)c * k] = kr.Hat(r, c);
-      if (riga::schur_complex(k, Hk.data(), T, Z) != 0) throw HipError{hipErrorUnknown};
-      theta.resize(k);
-      for (int i = 0; i < k; ++i) theta[i] = T[i + (size_t)i * k];
-      // sort by |theta| descending (= |lam - sigma| ascending), clusters kept together
-      std::vector<int> ord(k);
-      std::iota(ord.begin(), ord.end(), 0);
-      std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return std::abs(theta[a]) > std::abs(theta[c]); });
-      auto cluster_end = [&](int pos) {  // extend pos to the end of its |theta| cluster
-        while (pos < k && std::abs(std::abs(theta[ord[pos]]) - std::abs(theta[ord[pos - 1]])) <=
-                              1e-9 * std::abs(theta[ord[pos - 1]]))
-          ++pos;
-        return pos;
-      };
-      int nw = cluster_end(std::min(nev, k));
-      // Ritz vectors and residual estimates ||E y|| (E = rows k..k+b of H)
-      riga::schur_eigvecs(k, T, Z, Y, 1e-11);
-      std::vector<double> res(k);
-      for (int i = 0; i < k; ++i) {
-        double s = 0.0;
-        for (int r = 0; r < b; ++r) {
-          cplx acc = 0.0;
-          for (int c = 0; c < k; ++c) acc += kr.Hat(k + r, c) * Y[c + (size_t)i * k];
-          s += std::norm(acc);
-        }
-        res[i] = std::sqrt(s);
-      }
-      int nc = 0;
-      for (int p = 0; p < nw; ++p)
-        if (res[ord[p]] <= tol * std::abs(theta[ord[p]])) ++nc;
+      if (riga::ks_ritz(kr.H, ldh, k, b, nev, tol, cyc) != 0) throw HipError{hipErrorUnknown};
       ++it;
-      if (nc == nw) { converged = true; wanted.assign(ord.begin(), ord.begin() + nw); break; }
-      if (it >= maxit) { wanted.assign(ord.begin(), ord.begin() + nw); break; }
+      if (cyc.nconv == cyc.nw) { converged = true; break; }
+      if (it >= maxit) break;
       // --- Krylov--Schur restart: keep the nearest Ritz values ------------------
-      int kk = nev + (k - nev) / 2;
-      kk = std::min(kk, m - b);
-      kk = std::max(kk, std::min(nw, m - b));
-      int kend = cluster_end(std::max(1, kk));
-      if (kend + b <= m) kk = kend;
-      else {  // step back to a cluster boundary
-        while (kk > 1 && std::abs(std::abs(theta[ord[kk]]) - std::abs(theta[ord[kk - 1]])) <=
-                             1e-9 * std::abs(theta[ord[kk - 1]]))
-          --kk;
-      }
-      std::vector<int> keep(ord.begin(), ord.begin() + kk);
-      riga::schur_reorder(k, T, Z, keep);
-      std::vector<double> Qk;
-      int r = riga::realify(k, kk, Z, Qk);
-      // T_new = Qk^T H_k Qk, E_new = E Qk
-      std::vector<double> HQ((size_t)k * r, 0.0), Tn((size_t)r * r, 0.0), En((size_t)b * r, 0.0);
-      for (int c = 0; c < r; ++c)
-        for (int t2 = 0; t2 < k; ++t2) {
-          double q = Qk[t2 + (size_t)c * k];
-          if (q == 0.0) continue;
-          for (int rr = 0; rr < k; ++rr) HQ[rr + (size_t)c * k] += Hk[rr + (size_t)t2 * k] * q;
-        }
-      for (int c = 0; c < r; ++c)
-        for (int rr = 0; rr < r; ++rr) {
-          double s = 0.0;
-          for (int t2 = 0; t2 < k; ++t2) s += Qk[t2 + (size_t)rr * k] * HQ[t2 + (size_t)c * k];
-          Tn[rr + (size_t)c * r] = s;
-        }
-      for (int c = 0; c < r; ++c)
-        for (int rr = 0; rr < b; ++rr) {
-          double s = 0.0;
-          for (int t2 = 0; t2 < k; ++t2) s += kr.Hat(k + rr, t2) * Qk[t2 + (size_t)c * k];
-          En[rr + (size_t)c * b] = s;
-        }
+      riga::ks_restart(kr.H, ldh, k, b, m, nev, cyc);
+      const int r = cyc.r;
       // V_new = [V_k Qk, V_{k:k+b}] in the alternate buffers
       const int kin = k + b, kout = r + b;
-      std::vector<double> Qe((size_t)kin * kout, 0.0);
-      for (int c = 0; c < r; ++c)
-        for (int t2 = 0; t2 < k; ++t2) Qe[t2 + (size_t)c * kin] = Qk[t2 + (size_t)c * k];
-      for (int q = 0; q < b; ++q) Qe[(k + q) + (size_t)(r + q) * kin] = 1.0;
       double* dQ = h->d_small;
       {
         double* stage = h->pinned(2 * (size_t)ldh * ldh + 8);
-        std::memcpy(stage, Qe.data(), Qe.size() * sizeof(double));
-        ck(hipMemcpyAsync(dQ, stage, Qe.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
+        std::memcpy(stage, cyc.Qe.data(), cyc.Qe.size() * sizeof(double));
+        ck(hipMemcpyAsync(dQ, stage, cyc.Qe.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
       }
       riga::launch_gemm_tall(N, h->Vu, N, kin, dQ, kout, h->Vu2, 1, N, h->st);
       riga::launch_gemm_tall(N, h->Vl, N, kin, dQ, kout, h->Vl2, 1, N, h->st);
       riga::launch_gemm_tall(N, h->Wl, N, kin, dQ, kout, h->Wl2, 1, N, h->st);
       ck(hipStreamSynchronize(h->st));
       std::swap(h->Vu, h->Vu2); std::swap(h->Vl, h->Vl2); std::swap(h->Wl, h->Wl2);
-      std::fill(kr.H.begin(), kr.H.end(), 0.0);
-      for (int c = 0; c < r; ++c) {
-        for (int rr = 0; rr < r; ++rr) kr.Hat(rr, c) = Tn[rr + (size_t)c * r];
-        for (int rr = 0; rr < b; ++rr) kr.Hat(r + rr, c) = En[rr + (size_t)c * b];
-      }
+      kr.H = cyc.Hn;
       if (kr.fast) {
         // the pinned block is free again: the restart GEMMs were synchronised
         double* stage = h->pinned(2 * (size_t)ldh * ldh + 8);
@@ -1281,11 +1107,12 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     }  // attempts
     // --- eigenpairs: u = V_u y for the wanted Ritz vectors --------------------------
     const int k = kr.k;
+    const std::vector<int>& wanted = cyc.wanted;
     const int nw = (int)wanted.size();
     std::vector<double> Yr((size_t)k * nw), Yi((size_t)k * nw);
     for (int j = 0; j < nw; ++j)
       for (int c = 0; c < k; ++c) {
-        cplx y = Y[c + (size_t)wanted[j] * k];
+        cplx y = cyc.Y[c + (size_t)wanted[j] * k];
         Yr[c + (size_t)j * k] = y.real();
         Yi[c + (size_t)j * k] = y.imag();
       }
@@ -1318,16 +1145,10 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
       double f[11] = {0};
       for (int x = 0; x < nsplit; ++x)
         for (int t2 = 0; t2 < 11; ++t2) f[t2] += part[((size_t)j * nsplit + x) * 11 + t2];
-      // unconjugated forms u^T A u = a^T A a - b^T A b + 2i a^T A b
-      cplx qm(f[0] - f[1], 2 * f[2]), qc(f[3] - f[4], 2 * f[5]), qk(f[6] - f[7], 2 * f[8]);
-      uMu[j] = f[0] + f[1];
-      unorm2[j] = f[9] + f[10];
-      cplx ritz = h->sigma + 1.0 / theta[wanted[j]];
-      // two-sided Rayleigh functional: u^T Q(lam) u = 0, root nearest the Ritz value
-      cplx disc = std::sqrt(qc * qc - 4.0 * qm * qk);
-      cplx r1 = (-qc + disc) / (2.0 * qm), r2 = (-qc - disc) / (2.0 * qm);
-      cplx pick = std::abs(r1 - ritz) < std::abs(r2 - ritz) ? r1 : r2;
-      lam_rq[j] = (std::isfinite(pick.real()) && std::isfinite(pick.imag())) ? pick : ritz;
+      const riga::PairForms pf = riga::pair_forms(f);
+      uMu[j] = pf.uMu;
+      unorm2[j] = pf.unorm2;
+      lam_rq[j] = riga::rayleigh_polish(pf, h->sigma + 1.0 / cyc.theta[wanted[j]]);
     }
     std::vector<double> lamd((size_t)2 * nw);
     for (int j = 0; j < nw; ++j) { lamd[2 * j] = lam_rq[j].real(); lamd[2 * j + 1] = lam_rq[j].imag(); }
@@ -1346,8 +1167,7 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
         s += o[0];
         if (o[1] > best) { best = o[1]; umax[j] = cplx(o[3], o[4]); }
       }
-      double al = std::abs(lam_rq[j]);
-      etav[j] = std::sqrt(s) / ((al * al * h->norms[2] + al * h->norms[1] + h->norms[0]) * std::sqrt(unorm2[j]));
+      etav[j] = riga::scaled_residual(s, lam_rq[j], h->norms, unorm2[j]);
     }
     std::vector<int> order = canonical_order(lam_rq, h->sigma);
     const int nout = std::min(nev, nw);

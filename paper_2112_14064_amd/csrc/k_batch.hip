@@ -1,0 +1,372 @@
+// Batched form: the Krylov building blocks for a forest of independent QEPs
+// of different sizes, run in lockstep (one launch per operation for all of
+// them).  Every problem owns a contiguous range of rows of the forest vectors
+// (dofbase); per-problem state lives on the device (current column k, live
+// flag, small matrices at fixed strides), so one captured block step replays
+// unchanged for every step of every problem.  Row-parallel kernels take a
+// table of row blocks that never straddle two problems:
+//   rb[blk] = {problem, first row, end row, 0}.
+#include "kernels.hpp"
+#include "krylov_dev.hpp"
+
+#include <algorithm>
+
+namespace riga {
+
+constexpr int BT = 256;   // threads per block of the row-parallel kernels
+constexpr int SPB_G = 16; // lanes per row of the sparse product
+
+// Y = a0 s A0 X + a1 A1 X + bz Z and Y2 = A0 X, with s = sigma of the row's
+// problem (a0_sig) or 1; implicit tensor columns of the problem's space.
+template <int NC>
+__global__ __launch_bounds__(BT) void k_spmv_b(const int* __restrict__ rinst, const DevSpace* __restrict__ spaces,
+                                               const int64_t* __restrict__ dofbase, const double* __restrict__ isig,
+                                               const unsigned char* __restrict__ live, int64_t ntot,
+                                               const double* __restrict__ A0, double a0, int a0_sig,
+                                               const double* __restrict__ A1, double a1,
+                                               const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
+                                               int64_t ldy, const double* __restrict__ Z, int64_t ldz, double bz,
+                                               double* __restrict__ Y2, int64_t ldy2) {
+  const int g = threadIdx.x % SPB_G;
+  const int64_t r = ((int64_t)blockIdx.x * BT + threadIdx.x) / SPB_G;
+  const int q0 = r < ntot ? rinst[r] : 0;
+  const bool active = r < ntot && (live == nullptr || live[q0]);
+  double s0[NC], s1[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) { s0[q] = 0.0; s1[q] = 0.0; }
+  if (active) {
+    const DevSpace& sp = spaces[q0];
+    const int64_t base = dofbase[q0];
+    const int n = sp.n;
+    const int64_t rl = r - base;
+    const int i = (int)(rl % n), j = (int)(rl / n);
+    const int lx = sp.lo[i], wx = sp.hi[i] - sp.lo[i] + 1, ly = sp.lo[j];
+    const int64_t k0 = sp.rowptr[rl], len = sp.rowptr[rl + 1] - k0;
+    for (int o = g; o < len; o += SPB_G) {
+      const int64_t col = base + (int64_t)(ly + o / wx) * n + lx + o % wx;
+      const double v0 = A0[k0 + o];
+      const double v1 = A1 ? A1[k0 + o] : 0.0;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const double xv = X[col + q * ldx];
+        s0[q] += v0 * xv;
+        s1[q] += v1 * xv;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NC; ++q)
+#pragma unroll
+    for (int off = SPB_G / 2; off > 0; off >>= 1) {
+      s0[q] += __shfl_xor(s0[q], off, SPB_G);
+      s1[q] += __shfl_xor(s1[q], off, SPB_G);
+    }
+  if (active && g == 0) {
+    const double c0 = a0_sig ? a0 * isig[q0] : a0;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      double val = c0 * s0[q] + a1 * s1[q];
+      if (Z) val += bz * Z[r + q * ldz];
+      Y[r + q * ldy] = val;
+      if (Y2) Y2[r + q * ldy2] = s0[q];
+    }
+  }
+}
+
+void launch_spmv_b(const BatchDev& B, int ncols, const double* A0, double a0, int a0_sig, const double* A1,
+                   double a1, const double* X, int64_t ldx, double* Y, int64_t ldy, const double* Z, int64_t ldz,
+                   double bz, double* Y2, int64_t ldy2, hipStream_t st) {
+  const int64_t blocks = (B.ntot * SPB_G + BT - 1) / BT;
+#define RIGA_SPMVB(NC)                                                                                        \
+  hipLaunchKernelGGL(k_spmv_b<NC>, dim3((unsigned)blocks), dim3(BT), 0, st, B.rinst, B.spaces, B.dofbase, B.sig, \
+                     B.live, B.ntot, A0, a0, a0_sig, A1, a1, X, ldx, Y, ldy, Z, ldz, bz, Y2, ldy2)
+  switch (ncols) {
+    case 1: RIGA_SPMVB(1); break;
+    case 2: RIGA_SPMVB(2); break;
+    case 3: RIGA_SPMVB(3); break;
+    case 4: RIGA_SPMVB(4); break;
+    case 5: RIGA_SPMVB(5); break;
+    case 6: RIGA_SPMVB(6); break;
+    case 7: RIGA_SPMVB(7); break;
+    default: RIGA_SPMVB(8); break;
+  }
+#undef RIGA_SPMVB
+}
+
+// Xu[:, q] = Vu[:, k + q], Xw[:, q] = Wl[:, k + q] with k the problem's current column.
+__global__ __launch_bounds__(BT) void k_gather_b(const int4* __restrict__ rb, const int* __restrict__ kcur,
+                                                 const unsigned char* __restrict__ live, int nq,
+                                                 const double* __restrict__ Vu, const double* __restrict__ Wl,
+                                                 int64_t ld, double* __restrict__ Xu, double* __restrict__ Xw) {
+  const int4 b = rb[blockIdx.x];
+  if (live && !live[b.x]) return;
+  const int64_t r = b.y + threadIdx.x;
+  if (r >= b.z) return;
+  const int k = kcur[b.x];
+  for (int q = 0; q < nq; ++q) {
+    Xu[r + q * ld] = Vu[r + (int64_t)(k + q) * ld];
+    Xw[r + q * ld] = Wl[r + (int64_t)(k + q) * ld];
+  }
+}
+
+void launch_gather_b(const BatchDev& B, int nq, const double* Vu, const double* Wl, double* Xu, double* Xw,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_b, dim3(B.nrb), dim3(BT), 0, st, B.rb, B.kcur, B.live, nq, Vu, Wl, B.ntot, Xu, Xw);
+}
+
+// Partial multi-dots per dot block (rows of one problem):
+// partial[blk * pstride + c * NQ + q] = sum_rows Au[:, c] Xu[:, q] + Al[:, c] Xl[:, q],
+// c < nc = kcur[p] + nc_add (or nc_fixed without kcur).
+template <int NQ>
+__global__ __launch_bounds__(BT) void k_dots_b(const int4* __restrict__ db, const int* __restrict__ kcur,
+                                               int nc_add, int nc_fixed, const unsigned char* __restrict__ live,
+                                               const double* __restrict__ Au, const double* __restrict__ Al,
+                                               int64_t lda, const double* __restrict__ Xu,
+                                               const double* __restrict__ Xl, int64_t ldx,
+                                               double* __restrict__ partial, int pstride) {
+  const int4 b = db[blockIdx.x];
+  if (live && !live[b.x]) return;
+  const int nc = kcur ? kcur[b.x] + nc_add : nc_fixed;
+  const int64_t i0 = b.y, i1 = b.z;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = BT / 64;
+  double* out = partial + (int64_t)blockIdx.x * pstride;
+  for (int c = wave; c < nc; c += 2 * NW) {
+    const int c2 = c + NW;
+    const bool two = c2 < nc;
+    double acc[NQ], acc2[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) { acc[q] = 0.0; acc2[q] = 0.0; }
+    const double* au = Au + (int64_t)c * lda;
+    const double* al = Al ? Al + (int64_t)c * lda : nullptr;
+    const double* bu = Au + (int64_t)(two ? c2 : c) * lda;
+    const double* bl = Al ? Al + (int64_t)(two ? c2 : c) * lda : nullptr;
+    for (int64_t i = i0 + lane; i < i1; i += 64) {
+      const double u = au[i], u2 = bu[i];
+      const double l = al ? al[i] : 0.0, l2 = bl ? bl[i] : 0.0;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const double xu = Xu[i + q * ldx];
+        const double xl = Xl ? Xl[i + q * ldx] : 0.0;
+        acc[q] += u * xu + l * xl;
+        acc2[q] += u2 * xu + l2 * xl;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        acc[q] += __shfl_xor(acc[q], off, 64);
+        acc2[q] += __shfl_xor(acc2[q], off, 64);
+      }
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        out[c * NQ + q] = acc[q];
+        if (two) out[c2 * NQ + q] = acc2[q];
+      }
+    }
+  }
+}
+
+// out[p * ostride + idx] = sum over the problem's dot blocks of the partials
+// (fixed order: deterministic), one workgroup per problem.
+__global__ __launch_bounds__(BT) void k_dots_final_b(const int* __restrict__ dboff, const int* __restrict__ kcur,
+                                                     int nc_add, int nc_fixed, const unsigned char* __restrict__ live,
+                                                     int nq, const double* __restrict__ partial, int pstride,
+                                                     double* __restrict__ out, int ostride) {
+  const int p = blockIdx.x;
+  if (live && !live[p]) return;
+  const int nout = (kcur ? kcur[p] + nc_add : nc_fixed) * nq;
+  const int b0 = dboff[p], b1 = dboff[p + 1];
+  for (int idx = threadIdx.x; idx < nout; idx += BT) {
+    double s = 0.0;
+    for (int b = b0; b < b1; ++b) s += partial[(int64_t)b * pstride + idx];
+    out[(int64_t)p * ostride + idx] = s;
+  }
+}
+
+void launch_dots_b(const BatchDev& B, int nc_add, int nc_fixed, bool use_k, const double* Au, const double* Al,
+                   int nq, const double* Xu, const double* Xl, double* out, int ostride, hipStream_t st) {
+  const int* kc = use_k ? B.kcur : nullptr;
+#define RIGA_DOTSB(NQ)                                                                                        \
+  hipLaunchKernelGGL(k_dots_b<NQ>, dim3(B.ndb), dim3(BT), 0, st, B.db, kc, nc_add, nc_fixed, B.live, Au, Al, \
+                     B.ntot, Xu, Xl, B.ntot, B.partial, B.pstride)
+  switch (nq) {
+    case 1: RIGA_DOTSB(1); break;
+    case 2: RIGA_DOTSB(2); break;
+    case 3: RIGA_DOTSB(3); break;
+    default: RIGA_DOTSB(4); break;
+  }
+#undef RIGA_DOTSB
+  hipLaunchKernelGGL(k_dots_final_b, dim3(B.n), dim3(BT), 0, st, B.dboff, kc, nc_add, nc_fixed, B.live, nq,
+                     B.partial, B.pstride, out, ostride);
+}
+
+// Z[:, q] -= sum_{c < kcur + nc_add} A[:, c] h_p[c * NQ + q] for up to three pairs.
+template <int NQ>
+__global__ __launch_bounds__(BT) void k_cgs_update_b(const int4* __restrict__ rb, const int* __restrict__ kcur,
+                                                     int nc_add, const unsigned char* __restrict__ live,
+                                                     const double* __restrict__ h, int hstride,
+                                                     const double* __restrict__ A0, double* __restrict__ Z0,
+                                                     const double* __restrict__ A1, double* __restrict__ Z1,
+                                                     const double* __restrict__ A2, double* __restrict__ Z2,
+                                                     int64_t ld) {
+  extern __shared__ double hs[];
+  const int4 b = rb[blockIdx.x];
+  if (live && !live[b.x]) return;
+  const int nc = kcur[b.x] + nc_add;
+  const double* hp = h + (int64_t)b.x * hstride;
+  for (int k = threadIdx.x; k < nc * NQ; k += BT) hs[k] = hp[k];
+  __syncthreads();
+  const int64_t i = b.y + threadIdx.x;
+  if (i >= b.z) return;
+  const double* As[3] = {A0, A1, A2};
+  double* Zs[3] = {Z0, Z1, Z2};
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    if (!As[m]) continue;
+    double z[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) z[q] = Zs[m][i + q * ld];
+    for (int c = 0; c < nc; ++c) {
+      const double a = As[m][i + (int64_t)c * ld];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) z[q] -= a * hs[c * NQ + q];
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) Zs[m][i + q * ld] = z[q];
+  }
+}
+
+void launch_cgs_update_b(const BatchDev& B, int nc_add, int nq, const double* h, int hstride, const double* A0,
+                         double* Z0, const double* A1, double* Z1, const double* A2, double* Z2, int max_nc,
+                         hipStream_t st) {
+  const size_t shm = (size_t)max_nc * nq * sizeof(double);
+#define RIGA_UPDB(NQ)                                                                                          \
+  hipLaunchKernelGGL(k_cgs_update_b<NQ>, dim3(B.nrb), dim3(BT), shm, st, B.rb, B.kcur, nc_add, B.live, h, hstride, \
+                     A0, Z0, A1, Z1, A2, Z2, B.ntot)
+  switch (nq) {
+    case 1: RIGA_UPDB(1); break;
+    case 2: RIGA_UPDB(2); break;
+    case 3: RIGA_UPDB(3); break;
+    default: RIGA_UPDB(4); break;
+  }
+#undef RIGA_UPDB
+}
+
+// One workgroup per problem: block_normalize_body with the problem's arrays;
+// nc = kcur + nc_add and H column kcur (use_k), or nc = 0 and no H (start block).
+__global__ __launch_bounds__(BT) void k_block_normalize_b(const int* __restrict__ kcur, int nc_add,
+                                                          const unsigned char* __restrict__ live, int nq,
+                                                          const double* h1, const double* h2, int hstride,
+                                                          const double* G, double* H, int ldh,
+                                                          double* Rinv, int* flag) {
+  __shared__ double hn[4];
+  const int p = blockIdx.x;
+  if (live && !live[p]) return;
+  const int nc = kcur ? kcur[p] + nc_add : 0;
+  const int k = kcur ? kcur[p] : 0;
+  block_normalize_body(nc, nq, nc > 0 ? h1 + (int64_t)p * hstride : nullptr,
+                       nc > 0 ? h2 + (int64_t)p * hstride : nullptr, G + (int64_t)p * nq * nq,
+                       H ? H + (int64_t)p * ldh * ldh : nullptr, ldh, k, Rinv + (int64_t)p * nq * nq, flag + p, hn);
+}
+
+void launch_block_normalize_b(const BatchDev& B, bool use_k, int nc_add, int nq, const double* h1,
+                              const double* h2, int hstride, const double* G, double* H, int ldh, double* Rinv,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_block_normalize_b, dim3(B.n), dim3(BT), 0, st, use_k ? B.kcur : nullptr, nc_add, B.live, nq,
+                     h1, h2, hstride, G, H, ldh, Rinv, B.flag);
+}
+
+// Out_m[:, col + c] = sum_a In_m[:, a] Rinv_p[a][c], col = kcur + col_add (or col_add).
+template <int NQ>
+__global__ __launch_bounds__(BT) void k_gemm3_b(const int4* __restrict__ rb, const int* __restrict__ kcur,
+                                                int col_add, const unsigned char* __restrict__ live,
+                                                const double* __restrict__ Rinv, const double* __restrict__ I0,
+                                                double* __restrict__ O0, const double* __restrict__ I1,
+                                                double* __restrict__ O1, const double* __restrict__ I2,
+                                                double* __restrict__ O2, int64_t ld) {
+  const int4 b = rb[blockIdx.x];
+  if (live && !live[b.x]) return;
+  const int64_t i = b.y + threadIdx.x;
+  if (i >= b.z) return;
+  const int64_t col = (kcur ? kcur[b.x] : 0) + col_add;
+  const double* Q = Rinv + (int64_t)b.x * NQ * NQ;
+  double q[NQ][NQ];
+#pragma unroll
+  for (int a = 0; a < NQ; ++a)
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) q[a][c] = Q[a + c * NQ];
+  const double* Is[3] = {I0, I1, I2};
+  double* Os[3] = {O0, O1, O2};
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    double x[NQ];
+#pragma unroll
+    for (int a = 0; a < NQ; ++a) x[a] = Is[m][i + a * ld];
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < NQ; ++a) acc += x[a] * q[a][c];
+      Os[m][i + (col + c) * ld] = acc;
+    }
+  }
+}
+
+void launch_gemm3_b(const BatchDev& B, bool use_k, int col_add, int nq, const double* Rinv, const double* I0,
+                    double* O0, const double* I1, double* O1, const double* I2, double* O2, hipStream_t st) {
+  const int* kc = use_k ? B.kcur : nullptr;
+#define RIGA_G3B(NQ)                                                                                            \
+  hipLaunchKernelGGL(k_gemm3_b<NQ>, dim3(B.nrb), dim3(BT), 0, st, B.rb, kc, col_add, B.live, Rinv, I0, O0, I1, O1, \
+                     I2, O2, B.ntot)
+  switch (nq) {
+    case 1: RIGA_G3B(1); break;
+    case 2: RIGA_G3B(2); break;
+    case 3: RIGA_G3B(3); break;
+    default: RIGA_G3B(4); break;
+  }
+#undef RIGA_G3B
+}
+
+// End of a block step: live problems move to the next block; a problem stays
+// live while another block fits in the subspace of size m.
+__global__ void k_advance_b(int n, int b, int m, int* __restrict__ kcur, unsigned char* __restrict__ live) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+    if (!live[p]) continue;
+    const int k = kcur[p] + b;
+    kcur[p] = k;
+    live[p] = (k + b <= m) ? 1 : 0;
+  }
+}
+
+void launch_advance_b(const BatchDev& B, int b, int m, hipStream_t st) {
+  hipLaunchKernelGGL(k_advance_b, dim3((B.n + 255) / 256), dim3(256), 0, st, B.n, b, m, B.kcur, B.live);
+}
+
+// Out[:, 0:kout_p] = In[:, 0:kin_p] Q_p per problem (Q_p at Q + qoff[p], kin_p x
+// kout_p column-major); problems with kout_p = 0 are skipped.
+__global__ __launch_bounds__(GEMM_THREADS) void k_gemm_tall_b(const int4* __restrict__ rb,
+                                                              const int* __restrict__ kin,
+                                                              const int* __restrict__ kout,
+                                                              const int64_t* __restrict__ qoff,
+                                                              const double* __restrict__ Q,
+                                                              const double* __restrict__ In, double* __restrict__ Out,
+                                                              int64_t ld) {
+  extern __shared__ double qs[];
+  const int4 b = rb[blockIdx.x];
+  const int ko = kout[b.x];
+  if (ko <= 0) return;
+  const int64_t i = b.y + threadIdx.x;
+  gemm_tall_row(i, i < b.z, In, ld, kin[b.x], Q + qoff[b.x], ko, Out, 1, ld, qs);
+}
+
+void launch_gemm_tall_b(const BatchDev& B, const int* kin, const int* kout, const int64_t* qoff, const double* Q,
+                        int max_kin, const double* In, double* Out, hipStream_t st) {
+  const size_t shm = (size_t)max_kin * GEMM_CHUNK * sizeof(double);
+  hipLaunchKernelGGL(k_gemm_tall_b, dim3(B.nrb), dim3(GEMM_THREADS), shm, st, B.rb, kin, kout, qoff, Q, In, Out,
+                     B.ntot);
+}
+
+}  // namespace riga

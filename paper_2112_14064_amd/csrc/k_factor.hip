@@ -95,7 +95,7 @@ __device__ __forceinline__ int acc_col(int lane, int wave, int tj) {
 // at or below d (formed in FP64, stored in E).
 template <class E>
 __global__ __launch_bounds__(FT) void k_front_assemble(
-    int n, const int* __restrict__ lo, const int* __restrict__ hi, const int64_t* __restrict__ rowptr,
+    int n, const int* lo, const int* hi, const int64_t* rowptr,
     DevTree t, const int* __restrict__ level_nodes, double s2, double s1,
     const double* __restrict__ Kv, const double* __restrict__ Mv, const double* __restrict__ Cv,
     E* __restrict__ Lbuf, E* __restrict__ Ubuf) {
@@ -108,6 +108,15 @@ __global__ __launch_bounds__(FT) void k_front_assemble(
   const int* fd = t.fdofs + t.foff[v];
   const int* fk = t.fkey + t.foff[v];
   const int* fp = t.fpos + t.foff[v];
+  int base = 0;   // forest: the node's problem has its own space, shift and dof range
+  if (t.inst != nullptr) {
+    const int q = t.inst[v];
+    const DevSpace& sp = t.spaces[q];
+    n = sp.n; lo = sp.lo; hi = sp.hi; rowptr = sp.rowptr;
+    base = (int)t.dofbase[q];
+    s1 = t.isig[q];
+    s2 = s1 * s1;
+  }
   for (int c = c0; c < c1; ++c) {
     if (c < no) {
       for (int r = tid; r < nf; r += FT) F.L[(int64_t)c * nf + r] = E(0);
@@ -117,13 +126,13 @@ __global__ __launch_bounds__(FT) void k_front_assemble(
   }
   __syncthreads();
   for (int a = c0 + tid; a < min(c1, no); a += FT) {
-    const int d = fd[a];
+    const int d = fd[a] - base;
     const int i = d % n, j = d / n;
     const int wx = hi[i] - lo[i] + 1;
     const int64_t k0 = rowptr[d], k1 = rowptr[d + 1];
     for (int64_t k = k0; k < k1; ++k) {
       const int o = (int)(k - k0);
-      const int g = (lo[j] + o / wx) * n + lo[i] + o % wx;
+      const int g = (lo[j] + o / wx) * n + lo[i] + o % wx + base;
       int x0 = 0, x1 = nf;  // binary search of g among the sorted front keys
       while (x1 - x0 > 1) {
         const int c = (x0 + x1) >> 1;

@@ -5,6 +5,7 @@
 // vectors) the short one, and every kernel streams each matrix or basis column
 // once with coalesced accesses.
 #include "kernels.hpp"
+#include "krylov_dev.hpp"
 
 #include <algorithm>
 
@@ -236,46 +237,14 @@ void launch_cgs_update(int64_t n, int nc, int nq, const double* h,
 }
 
 // ---------------------------------------------------------------------------
-// Out = In * Q for a tall In (n x kin) and a small Q (kin x kout) held in LDS.
-// Thread per row; 32 output columns per pass kept in registers; the inner
-// loop issues 8 independent coalesced loads of In before using them.
-constexpr int GEMM_THREADS = 256;
-constexpr int GEMM_CHUNK = 32;
-constexpr int GEMM_UNROLL = 8;
-
+// Out = In * Q for a tall In (n x kin) and a small Q (kin x kout) held in LDS,
+// thread per row (body in krylov_dev.hpp).
 __global__ __launch_bounds__(GEMM_THREADS) void k_gemm_tall(
     int64_t n, const double* __restrict__ In, int64_t ldi, int kin, const double* __restrict__ Q,
     int kout, double* __restrict__ Out, int64_t out_rs, int64_t out_cs) {
-  extern __shared__ double qs[];   // qs[tt * GEMM_CHUNK + c] for the current chunk
+  extern __shared__ double qs[];
   const int64_t i = (int64_t)blockIdx.x * GEMM_THREADS + threadIdx.x;
-  const bool live = i < n;
-  for (int c0 = 0; c0 < kout; c0 += GEMM_CHUNK) {
-    const int kc = min(GEMM_CHUNK, kout - c0);
-    __syncthreads();
-    for (int k = threadIdx.x; k < kin * GEMM_CHUNK; k += GEMM_THREADS) {
-      const int tt = k / GEMM_CHUNK, c = k % GEMM_CHUNK;
-      qs[k] = (c < kc) ? Q[(int64_t)(c0 + c) * kin + tt] : 0.0;
-    }
-    __syncthreads();
-    if (!live) continue;
-    double acc[GEMM_CHUNK];
-#pragma unroll
-    for (int c = 0; c < GEMM_CHUNK; ++c) acc[c] = 0.0;
-    for (int t0 = 0; t0 < kin; t0 += GEMM_UNROLL) {
-      double a[GEMM_UNROLL];
-#pragma unroll
-      for (int u = 0; u < GEMM_UNROLL; ++u) a[u] = (t0 + u < kin) ? In[i + (int64_t)(t0 + u) * ldi] : 0.0;
-#pragma unroll
-      for (int u = 0; u < GEMM_UNROLL; ++u) {
-        const int tt = min(t0 + u, kin - 1);
-#pragma unroll
-        for (int c = 0; c < GEMM_CHUNK; ++c) acc[c] += a[u] * qs[tt * GEMM_CHUNK + c];
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < GEMM_CHUNK; ++c)
-      if (c < kc) Out[i * out_rs + (int64_t)(c0 + c) * out_cs] = acc[c];
-  }
+  gemm_tall_row(i, i < n, In, ldi, kin, Q, kout, Out, out_rs, out_cs, qs);
 }
 
 void launch_gemm_tall(int64_t n, const double* In, int64_t ldi, int kin, const double* Q, int kout,
@@ -484,53 +453,8 @@ void launch_combine_q(int64_t nnz, double s2, double s1, const double* K, const 
 __global__ void k_block_normalize(int nc, int nq, const double* __restrict__ h1, const double* __restrict__ h2,
                                   const double* __restrict__ G, double* __restrict__ H, int ldh, int k,
                                   double* __restrict__ Rinv, int* __restrict__ flag) {
-  for (int idx = threadIdx.x; H && idx < nc * nq; idx += blockDim.x) {
-    const int c = idx / nq, q = idx % nq;
-    H[c + (int64_t)(k + q) * ldh] = (h1 ? h1[idx] : 0.0) + (h2 ? h2[idx] : 0.0);
-  }
-  // squared norms of the projection coefficients, one wave per column q
   __shared__ double hn[4];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (wv < nq) {
-    double sacc = 0.0;
-    for (int c = lane; c < nc; c += 64) {
-      const double hv = (h1 ? h1[c * nq + wv] : 0.0) + (h2 ? h2[c * nq + wv] : 0.0);
-      sacc += hv * hv;
-    }
-    for (int off = 32; off > 0; off >>= 1) sacc += __shfl_xor(sacc, off, 64);
-    if (lane == 0) hn[wv] = sacc;
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  double R[4][4] = {{0}}, X[4][4] = {{0}};
-  bool bad = false;
-  for (int j = 0; j < nq; ++j) {
-    const double n0 = G[j * nq + j] + hn[j];
-    for (int i = 0; i <= j; ++i) {
-      double sacc = 0.5 * (G[i * nq + j] + G[j * nq + i]);
-      for (int kk = 0; kk < i; ++kk) sacc -= R[kk][i] * R[kk][j];
-      if (i == j) {
-        if (!(sacc > 1e-24 * n0)) { bad = true; sacc = 1.0; }
-        R[j][j] = sqrt(sacc);
-      } else {
-        R[i][j] = sacc / R[i][i];
-      }
-    }
-  }
-  for (int j = 0; j < nq; ++j) {
-    X[j][j] = 1.0 / R[j][j];
-    for (int i = j - 1; i >= 0; --i) {
-      double sacc = 0.0;
-      for (int kk = i + 1; kk <= j; ++kk) sacc += R[i][kk] * X[kk][j];
-      X[i][j] = -sacc / R[i][i];
-    }
-  }
-  for (int q = 0; q < nq; ++q)
-    for (int c = 0; c < nq; ++c) {
-      if (H) H[nc + c + (int64_t)(k + q) * ldh] = R[c][q];
-      Rinv[c + q * nq] = X[c][q];
-    }
-  if (bad) *flag = 1;
+  block_normalize_body(nc, nq, h1, h2, G, H, ldh, k, Rinv, flag, hn);
 }
 
 void launch_block_normalize(int nc, int nq, const double* h1, const double* h2, const double* G, double* H,

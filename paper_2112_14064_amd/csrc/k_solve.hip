@@ -70,6 +70,7 @@ __global__ __launch_bounds__(ST) void k_fwd(DevTree t, const int4* __restrict__ 
   const int4 tk = tasks[blockIdx.x];
   const int v = tk.x, r0 = tk.y, r1 = tk.z;
   const int nf = t.nf[v], no = t.no[v];
+  if (t.ilive != nullptr && !t.ilive[t.inst[v]]) return;
   double* red = shm + (size_t)nf * NR;   // SW x SR x NR partial sums
   const int* fd = t.fdofs + t.foff[v];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -146,6 +147,8 @@ __global__ __launch_bounds__(ST) void k_bwd(DevTree t, const int4* __restrict__ 
   const int4 tk = tasks[blockIdx.x];
   const int v = tk.x, a0 = tk.y, a1 = tk.z;
   const int nf = t.nf[v], no = t.no[v];
+  if (t.ilive != nullptr && !t.ilive[t.inst[v]]) return;
+  if (t.inst != nullptr) sig = t.isig[t.inst[v]];
   double* red = shm + (size_t)nf * NR;
   const int* fd = t.fdofs + t.foff[v];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;

@@ -26,6 +26,12 @@ struct DevTree {
   const unsigned char* prec;    // per node: 1 = FP32 front (mixed factor), or null (all FP64)
   const int64_t* lpoff;         // per node: sweep layouts of F (multiples of 4 elements):
   const int64_t* tpoff;         //   ceil(no/4)*4*nf and ceil(nf/4)*4*no entries
+  // Forest of independent problems (batched form), all null for one problem:
+  const int* inst;              // per node: its problem
+  const DevSpace* spaces;       // per problem: 1-D space, rowptr into the forest CSR rows
+  const int64_t* dofbase;       // per problem: first dof in the forest numbering
+  const double* isig;           // per problem: shift sigma
+  const unsigned char* ilive;   // per problem: 0 = skip its nodes in the sweeps (may be null)
 };
 
 // --- assembly ---------------------------------------------------------------
@@ -129,5 +135,50 @@ void launch_deinterleave(int64_t n, int nv, const double* X, double* P, hipStrea
 // grad[e] = sum_k Re(w_k u_k^T M_e u_k) for every element e (see k_krylov.hip).
 void launch_adjoint(const DevSpace& s, const double* tabM, int nv, const double* P, int64_t ndof,
                     const double* w, double* grad, hipStream_t st);
+
+// --- batched form (k_batch.hip) ---------------------------------------------
+// Device view of a forest of independent problems run in lockstep.
+struct BatchDev {
+  int n = 0;                        // problems
+  int64_t ntot = 0;                 // forest rows (sum of the problems' dofs)
+  const int* rinst = nullptr;       // per row: its problem
+  const DevSpace* spaces = nullptr; // per problem
+  const int64_t* dofbase = nullptr; // per problem: first row
+  const double* sig = nullptr;      // per problem: shift
+  unsigned char* live = nullptr;    // per problem: takes part in the current step
+  int* kcur = nullptr;              // per problem: first column of the current block
+  int* flag = nullptr;              // per problem: breakdown flag of the normalisation
+  const int4* rb = nullptr;         // row blocks of <= 256 rows, one problem each
+  int nrb = 0;
+  const int4* db = nullptr;         // dot blocks (longer row ranges, one problem each)
+  int ndb = 0;
+  const int* dboff = nullptr;       // per problem: its dot blocks [dboff[p], dboff[p+1])
+  double* partial = nullptr;        // dot partial sums, pstride per dot block
+  int pstride = 0;
+};
+// Y = a0 s A0 X + a1 A1 X + bz Z, Y2 = A0 X (s = the row's sigma if a0_sig);
+// ncols <= 8, every vector ntot x ncols with the given leading dimensions.
+void launch_spmv_b(const BatchDev& B, int ncols, const double* A0, double a0, int a0_sig, const double* A1,
+                   double a1, const double* X, int64_t ldx, double* Y, int64_t ldy, const double* Z, int64_t ldz,
+                   double bz, double* Y2, int64_t ldy2, hipStream_t st);
+// Current block of the bases (columns kcur .. kcur + nq) into Xu, Xw.
+void launch_gather_b(const BatchDev& B, int nq, const double* Vu, const double* Wl, double* Xu, double* Xw,
+                     hipStream_t st);
+// out[p * ostride + c * nq + q] = A_p[:, c]^T X_p[:, q] (u and l parts), c < nc with
+// nc = kcur + nc_add (use_k) or nc_fixed.
+void launch_dots_b(const BatchDev& B, int nc_add, int nc_fixed, bool use_k, const double* Au, const double* Al,
+                   int nq, const double* Xu, const double* Xl, double* out, int ostride, hipStream_t st);
+// Z[:, q] -= A[:, 0:kcur+nc_add] h_p for up to three pairs (max_nc bounds kcur + nc_add).
+void launch_cgs_update_b(const BatchDev& B, int nc_add, int nq, const double* h, int hstride, const double* A0,
+                         double* Z0, const double* A1, double* Z1, const double* A2, double* Z2, int max_nc,
+                         hipStream_t st);
+void launch_block_normalize_b(const BatchDev& B, bool use_k, int nc_add, int nq, const double* h1,
+                              const double* h2, int hstride, const double* G, double* H, int ldh, double* Rinv,
+                              hipStream_t st);
+void launch_gemm3_b(const BatchDev& B, bool use_k, int col_add, int nq, const double* Rinv, const double* I0,
+                    double* O0, const double* I1, double* O1, const double* I2, double* O2, hipStream_t st);
+void launch_advance_b(const BatchDev& B, int b, int m, hipStream_t st);
+void launch_gemm_tall_b(const BatchDev& B, const int* kin, const int* kout, const int64_t* qoff, const double* Q,
+                        int max_kin, const double* In, double* Out, hipStream_t st);
 
 }  // namespace riga

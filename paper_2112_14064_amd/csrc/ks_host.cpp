@@ -1,0 +1,121 @@
+#include "ks_host.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace riga {
+
+int ks_ritz(const std::vector<double>& H, int ldh, int k, int b, int nev, double tol, KsCycle& c) {
+  auto Hat = [&](int r, int col) { return H[r + (size_t)col * ldh]; };
+  std::vector<double> Hk((size_t)k * k);
+  for (int col = 0; col < k; ++col)
+    for (int r = 0; r < k; ++r) Hk[r + (size_t)col * k] = Hat(r, col);
+  if (schur_complex(k, Hk.data(), c.T, c.Z) != 0) return -1;
+  c.theta.resize(k);
+  for (int i = 0; i < k; ++i) c.theta[i] = c.T[i + (size_t)i * k];
+  // sort by |theta| descending (= |lam - sigma| ascending), clusters kept together
+  c.ord.resize(k);
+  std::iota(c.ord.begin(), c.ord.end(), 0);
+  std::stable_sort(c.ord.begin(), c.ord.end(),
+                   [&](int a, int d) { return std::abs(c.theta[a]) > std::abs(c.theta[d]); });
+  int pos = std::min(nev, k);
+  while (pos < k && std::abs(std::abs(c.theta[c.ord[pos]]) - std::abs(c.theta[c.ord[pos - 1]])) <=
+                        1e-9 * std::abs(c.theta[c.ord[pos - 1]]))
+    ++pos;
+  c.nw = pos;
+  // Ritz vectors and residual estimates ||E y|| (E = rows k..k+b of H)
+  schur_eigvecs(k, c.T, c.Z, c.Y, 1e-11);
+  c.nconv = 0;
+  for (int p = 0; p < c.nw; ++p) {
+    const int i = c.ord[p];
+    double s = 0.0;
+    for (int r = 0; r < b; ++r) {
+      cplx acc = 0.0;
+      for (int col = 0; col < k; ++col) acc += Hat(k + r, col) * c.Y[col + (size_t)i * k];
+      s += std::norm(acc);
+    }
+    if (std::sqrt(s) <= tol * std::abs(c.theta[i])) ++c.nconv;
+  }
+  c.wanted.assign(c.ord.begin(), c.ord.begin() + c.nw);
+  return 0;
+}
+
+void ks_restart(const std::vector<double>& H, int ldh, int k, int b, int m, int nev, KsCycle& c) {
+  auto Hat = [&](int r, int col) { return H[r + (size_t)col * ldh]; };
+  auto same = [&](int p) {  // ord[p] continues the |theta| cluster of ord[p-1]
+    return std::abs(std::abs(c.theta[c.ord[p]]) - std::abs(c.theta[c.ord[p - 1]])) <=
+           1e-9 * std::abs(c.theta[c.ord[p - 1]]);
+  };
+  int kk = nev + (k - nev) / 2;
+  kk = std::min(kk, m - b);
+  kk = std::max(kk, std::min(c.nw, m - b));
+  int kend = std::max(1, kk);
+  while (kend < k && same(kend)) ++kend;
+  if (kend + b <= m) {
+    kk = kend;
+  } else {  // step back to a cluster boundary
+    while (kk > 1 && same(kk)) --kk;
+  }
+  std::vector<int> keep(c.ord.begin(), c.ord.begin() + kk);
+  std::vector<cplx> T = c.T, Z = c.Z;
+  schur_reorder(k, T, Z, keep);
+  std::vector<double> Qk;
+  const int r = realify(k, kk, Z, Qk);
+  std::vector<double> Hk((size_t)k * k);
+  for (int col = 0; col < k; ++col)
+    for (int rr = 0; rr < k; ++rr) Hk[rr + (size_t)col * k] = Hat(rr, col);
+  // T_new = Qk^T H_k Qk, E_new = E Qk
+  std::vector<double> HQ((size_t)k * r, 0.0);
+  for (int col = 0; col < r; ++col)
+    for (int t2 = 0; t2 < k; ++t2) {
+      const double q = Qk[t2 + (size_t)col * k];
+      if (q == 0.0) continue;
+      for (int rr = 0; rr < k; ++rr) HQ[rr + (size_t)col * k] += Hk[rr + (size_t)t2 * k] * q;
+    }
+  c.Hn.assign((size_t)ldh * ldh, 0.0);
+  for (int col = 0; col < r; ++col) {
+    for (int rr = 0; rr < r; ++rr) {
+      double s = 0.0;
+      for (int t2 = 0; t2 < k; ++t2) s += Qk[t2 + (size_t)rr * k] * HQ[t2 + (size_t)col * k];
+      c.Hn[rr + (size_t)col * ldh] = s;
+    }
+    for (int rr = 0; rr < b; ++rr) {
+      double s = 0.0;
+      for (int t2 = 0; t2 < k; ++t2) s += Hat(k + rr, t2) * Qk[t2 + (size_t)col * k];
+      c.Hn[r + rr + (size_t)col * ldh] = s;
+    }
+  }
+  // V_new = [V_k Qk, V_{k:k+b}]
+  const int kin = k + b, kout = r + b;
+  c.Qe.assign((size_t)kin * kout, 0.0);
+  for (int col = 0; col < r; ++col)
+    for (int t2 = 0; t2 < k; ++t2) c.Qe[t2 + (size_t)col * kin] = Qk[t2 + (size_t)col * k];
+  for (int q = 0; q < b; ++q) c.Qe[(k + q) + (size_t)(r + q) * kin] = 1.0;
+  c.r = r;
+}
+
+PairForms pair_forms(const double f[11]) {
+  PairForms pf;
+  // unconjugated forms u^T A u = a^T A a - b^T A b + 2i a^T A b
+  pf.qm = cplx(f[0] - f[1], 2 * f[2]);
+  pf.qc = cplx(f[3] - f[4], 2 * f[5]);
+  pf.qk = cplx(f[6] - f[7], 2 * f[8]);
+  pf.uMu = f[0] + f[1];
+  pf.unorm2 = f[9] + f[10];
+  return pf;
+}
+
+cplx rayleigh_polish(const PairForms& pf, cplx ritz) {
+  const cplx disc = std::sqrt(pf.qc * pf.qc - 4.0 * pf.qm * pf.qk);
+  const cplx r1 = (-pf.qc + disc) / (2.0 * pf.qm), r2 = (-pf.qc - disc) / (2.0 * pf.qm);
+  const cplx pick = std::abs(r1 - ritz) < std::abs(r2 - ritz) ? r1 : r2;
+  return (std::isfinite(pick.real()) && std::isfinite(pick.imag())) ? pick : ritz;
+}
+
+double scaled_residual(double resid2, cplx lam, const double norms[3], double unorm2) {
+  const double al = std::abs(lam);
+  return std::sqrt(resid2) / ((al * al * norms[2] + al * norms[1] + norms[0]) * std::sqrt(unorm2));
+}
+
+}  // namespace riga

@@ -248,4 +248,91 @@ int Plan::build(int p, int ne, int s, int leaf) {
   return 0;
 }
 
+void Plan::merge(const std::vector<const Plan*>& parts, std::vector<int64_t>& dof_base,
+                 std::vector<int>& node_base) {
+  *this = Plan();
+  const size_t np = parts.size();
+  dof_base.assign(np + 1, 0);
+  node_base.assign(np + 1, 0);
+  std::vector<int64_t> nnz_base(np + 1, 0), l_base(np + 1, 0), u_base(np + 1, 0);
+  std::vector<int> f_base(np + 1, 0), c_base(np + 1, 0), m_base(np + 1, 0);
+  for (size_t k = 0; k < np; ++k) {
+    const Plan& q = *parts[k];
+    dof_base[k + 1] = dof_base[k] + q.ndof;
+    node_base[k + 1] = node_base[k] + (int)q.nodes.size();
+    nnz_base[k + 1] = nnz_base[k] + q.nnz;
+    l_base[k + 1] = l_base[k] + q.lsize;
+    u_base[k + 1] = u_base[k] + q.usize;
+    f_base[k + 1] = f_base[k] + (int)q.fdofs.size();
+    c_base[k + 1] = c_base[k] + (int)q.clist.size();
+    m_base[k + 1] = m_base[k] + (int)q.maps.size();
+  }
+  ndof = dof_base[np];
+  nnz = nnz_base[np];
+  lsize = l_base[np];
+  usize = u_base[np];
+  const int nn = node_base[np];
+  rowptr.assign(ndof + 1, 0);
+  nodes.resize(nn);
+  node_of_dof.assign(ndof, 0);
+  elim_pos.assign(ndof, 0);
+  nf.resize(nn); no.resize(nn); nb.resize(nn);
+  loff.resize(nn); uoff.resize(nn);
+  foff.assign(nn + 1, 0);
+  fdofs.resize(f_base[np]); fkey.resize(f_base[np]); fpos.resize(f_base[np]);
+  coff.assign(nn + 1, 0);
+  clist.resize(c_base[np]);
+  moff.assign(nn + 1, 0);
+  maps.resize(m_base[np]);
+  for (size_t k = 0; k < np; ++k) {
+    const Plan& q = *parts[k];
+    const int64_t db = dof_base[k];
+    const int nbk = node_base[k];
+    for (int64_t r = 0; r <= q.ndof; ++r) rowptr[db + r] = q.rowptr[r] + nnz_base[k];
+    for (int64_t d = 0; d < q.ndof; ++d) {
+      node_of_dof[db + d] = q.node_of_dof[d] + nbk;
+      elim_pos[db + d] = q.elim_pos[d] + db;
+    }
+    for (size_t v = 0; v < q.nodes.size(); ++v) {
+      Node nd = q.nodes[v];
+      if (nd.parent >= 0) nd.parent += nbk;
+      for (int& c : nd.children) c += nbk;
+      for (int& d : nd.own) d += (int)db;
+      for (int& d : nd.bnd) d += (int)db;
+      nd.post += nbk;
+      nd.first_desc += nbk;
+      const int g = nbk + (int)v;
+      nodes[g] = std::move(nd);
+      nf[g] = q.nf[v]; no[g] = q.no[v]; nb[g] = q.nb[v];
+      loff[g] = q.loff[v] + l_base[k];
+      uoff[g] = q.uoff[v] + u_base[k];
+      foff[g] = q.foff[v] + f_base[k];
+      coff[g] = q.coff[v] + c_base[k];
+      moff[g] = q.moff[v] + m_base[k];
+    }
+    for (size_t t = 0; t < q.fdofs.size(); ++t) {
+      fdofs[f_base[k] + t] = q.fdofs[t] + (int)db;
+      fkey[f_base[k] + t] = q.fkey[t] + (int)db;
+      fpos[f_base[k] + t] = q.fpos[t];
+    }
+    for (size_t t = 0; t < q.clist.size(); ++t) clist[c_base[k] + t] = q.clist[t] + nbk;
+    for (size_t t = 0; t < q.maps.size(); ++t) maps[m_base[k] + t] = q.maps[t];
+    height = std::max(height, q.height);
+    max_front = std::max(max_front, q.max_front);
+    max_own = std::max(max_own, q.max_own);
+    max_nb = std::max(max_nb, q.max_nb);
+    flops_dense += q.flops_dense;
+    solve_bytes += q.solve_bytes;
+  }
+  foff[nn] = f_base[np];
+  coff[nn] = c_base[np];
+  moff[nn] = m_base[np];
+  level_off.assign(height + 1, 0);
+  for (auto& nd : nodes) level_off[nd.height + 1]++;
+  for (int h = 0; h < height; ++h) level_off[h + 1] += level_off[h];
+  level_nodes.assign(nn, 0);
+  std::vector<int> fill(level_off.begin(), level_off.end() - 1);
+  for (auto& nd : nodes) level_nodes[fill[nd.height]++] = nd.post;
+}
+
 }  // namespace riga

@@ -57,6 +57,13 @@ struct Plan {
   double solve_bytes = 0.0;
 
   int build(int p, int ne, int s, int leaf);  // 0 ok, <0 invalid
+
+  // Forest of independent problems: the plans of `parts` side by side, with
+  // dofs, CSR rows, nodes and factor blocks numbered consecutively (part k's
+  // dofs start at dof_base[k], its nodes at node_base[k]) and tree levels
+  // grouped by height across all parts.  The 1-D space stays empty.
+  void merge(const std::vector<const Plan*>& parts, std::vector<int64_t>& dof_base,
+             std::vector<int>& node_base);
 };
 
 }  // namespace riga

@@ -1,0 +1,150 @@
+// Internal state of one solver handle and the host helpers shared by the
+// single-problem and the batched entry points.
+#pragma once
+#include "../../include/riga.h"
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <functional>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "small_eig.hpp"
+
+namespace riga {
+namespace detail {
+
+struct HipError {
+  hipError_t e;
+};
+inline void ck(hipError_t e) {
+  if (e != hipSuccess) throw HipError{e};
+}
+
+}  // namespace detail
+}  // namespace riga
+
+struct riga_problem {
+  int device = 0;
+  hipStream_t st = nullptr;
+  riga_mesh mesh{};
+  riga::Plan plan;
+  std::vector<void*> allocs;
+  riga::DevSpace ds{};
+  riga::DevTree dt{};
+  int* d_level_nodes = nullptr;
+  double *d_gx = nullptr, *d_gw = nullptr, *d_tabM = nullptr, *d_tabK = nullptr;
+  double *d_K = nullptr, *d_M = nullptr, *d_C = nullptr;
+  double *d_L = nullptr, *d_U = nullptr, *d_T = nullptr, *d_upd = nullptr, *d_tmp = nullptr, *d_tmp2 = nullptr;
+  double *d_Lp = nullptr, *d_Tp = nullptr;         // F in the sweep layouts
+  int64_t lpsize = 0, tpsize = 0;
+  int4 *d_ftasks = nullptr, *d_btasks = nullptr;   // solve tasks, grouped by level
+  double* d_D = nullptr;                            // 64x64 diagonal-block inverses
+  std::vector<int> lvl_max_no, lvl_max_nf, lvl_max_cnb;
+  std::vector<int> ftask_off, btask_off;
+  int64_t* d_status = nullptr;
+  double* d_part = nullptr;       // reduction scratch
+  unsigned* d_ticket = nullptr;
+  int64_t upd_len = 0;
+  bool assembled = false, factored = false;
+  double alpha = 0, beta = 0, sigma = 0;
+  const double* c_elem = nullptr;
+  double norms[3] = {-1, -1, -1};  // ||K||_1, ||C||_1, ||M||_1
+  riga_stats_t stats{};
+  // Krylov workspace
+  int64_t kw_cols = 0, kw_b = 0, kw_nev = 0;
+  double *Vu = nullptr, *Vl = nullptr, *Wl = nullptr, *Vu2 = nullptr, *Vl2 = nullptr, *Wl2 = nullptr;
+  double *Ru = nullptr, *Rl = nullptr, *MRl = nullptr, *Tv = nullptr, *Mvu = nullptr;
+  double *d_small = nullptr;      // device staging for h1, h2, G and small matrices
+  double *d_H = nullptr;          // device copy of the projected matrix (fast path)
+  int* d_flag = nullptr;          // breakdown flag of the fast path
+  double *P = nullptr, *MP = nullptr, *CP = nullptr, *KP = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // The Krylov loop runs on a stream of its own (fenced to the caller's stream)
+  // so that its block steps can be captured as HIP graphs and replayed.
+  hipStream_t own_st = nullptr;
+  hipEvent_t ev_fence = nullptr;
+  double* pin = nullptr;            // pinned host staging (projected matrix, small blocks)
+  size_t pin_len = 0;
+  double* pinned(size_t len) {
+    if (pin_len < len) {
+      if (pin) hipHostFree(pin);
+      pin = nullptr;
+      pin_len = 0;
+      if (hipHostMalloc((void**)&pin, len * sizeof(double), 0) != hipSuccess) throw std::bad_alloc();
+      pin_len = len;
+    }
+    return pin;
+  }
+  std::map<std::tuple<int, int, const double*>, hipGraphExec_t> graphs;   // (k, b, V_u)
+  double graph_sigma = 0.0;
+  int64_t graph_key = 0;            // factor mode the captured graphs were recorded for
+  // Mixed-precision factor: nodes of height < mixed_thr are FP32 (same offsets
+  // as the FP64 blocks, in arrays of their own); every solve is refined
+  // ir_sweeps times with FP64 residuals of Q, whose values are kept in d_Q.
+  bool mixed = false;
+  int mixed_thr = 0, ir_sweeps = 0;
+  float *d_L32 = nullptr, *d_T32 = nullptr, *d_U32 = nullptr, *d_D32 = nullptr;
+  float *d_Lp32 = nullptr, *d_Tp32 = nullptr;
+  double *d_Q = nullptr, *d_irX = nullptr, *d_irR = nullptr, *d_irD = nullptr;
+  unsigned char* d_prec = nullptr;
+  int prec_thr = -1;                // threshold d_prec was written for
+  int64_t n_ir = 0;                 // refinement sweeps issued outside the Krylov loop
+  int64_t factor_key() const { return mixed ? 1 + (int64_t)ir_sweeps * 64 + (int64_t)mixed_thr * 4096 : 0; }
+  bool level_f32(int lv) const { return mixed && lv < mixed_thr; }
+
+  void clear_graphs() {
+    for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
+
+  template <class T>
+  T* dalloc(size_t count) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) throw std::bad_alloc();
+    allocs.push_back(p);
+    return (T*)p;
+  }
+  void dfree(void* p) {
+    if (!p) return;
+    auto it = std::find(allocs.begin(), allocs.end(), p);
+    if (it != allocs.end()) { hipFree(p); allocs.erase(it); }
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v) {
+    T* d = dalloc<T>(v.size());
+    if (!v.empty()) riga::detail::ck(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return d;
+  }
+  int64_t N() const { return plan.ndof; }
+};
+
+namespace riga {
+namespace detail {
+
+// Maps the library's exceptions to status codes.
+riga_status run(const std::function<riga_status()>& f);
+// (p+1)-point Gauss--Legendre rule on [-1, 1].
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+// Canonical order: increasing |lam - sigma|, clusters by decreasing Im, then Re.
+std::vector<int> canonical_order(const std::vector<cplx>& lam, double sigma);
+// Upload h->plan and allocate every device array of the handle.
+void setup_device(riga_problem* h);
+// Solves with the factor (see api.cpp).
+void sweep(riga_problem* h, int nrhs, const double* b, int64_t ldb, const riga::BwdOut& o);
+void solve_levels(riga_problem* h, int nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
+                  double* r_l, const double* v_u, int64_t ldv, double sig);
+void factor_level(riga_problem* h, int lv, double sigma);
+// Factor every level; RIGA_ERR_NOT_SPD with *bad_pivot (a dof) on a failed pivot.
+riga_status factor_all(riga_problem* h, double sigma, int64_t* bad_pivot);
+int small_chol(int b, const std::vector<double>& G, std::vector<double>& R, double rel);
+std::vector<double> upper_inverse(int b, const std::vector<double>& R);
+
+}  // namespace detail
+}  // namespace riga

@@ -51,7 +51,8 @@ class riga_stats_t(C.Structure):
 
 
 EXPORTS = ["riga_create", "riga_info", "riga_assemble", "riga_export_csr", "riga_factor", "riga_factor_mixed",
-           "riga_ir_sweeps",
+           "riga_ir_sweeps", "riga_batch_create", "riga_batch_info", "riga_batch_assemble", "riga_batch_factor",
+           "riga_batch_eigs", "riga_batch_stats", "riga_batch_destroy",
            "riga_solve_q", "riga_apply_op", "riga_eigs", "riga_adjoint", "riga_stats", "riga_time_kernel",
            "riga_selftest_small_eig", "riga_status_str", "riga_destroy"]
 
@@ -86,8 +87,16 @@ def load(path: str = LIB_PATH):
     lib.riga_status_str.restype = C.c_char_p
     lib.riga_destroy.argtypes = [P]
     lib.riga_destroy.restype = None
+    lib.riga_batch_create.argtypes = [C.POINTER(P), C.c_int, P, C.c_int, P]
+    lib.riga_batch_info.argtypes = [P, C.POINTER(C.c_int64), P]
+    lib.riga_batch_assemble.argtypes = [P, P]
+    lib.riga_batch_factor.argtypes = [P, P, P]
+    lib.riga_batch_eigs.argtypes = [P, C.POINTER(riga_options), P, P, P, P]
+    lib.riga_batch_stats.argtypes = [P, C.POINTER(riga_stats_t), C.POINTER(C.c_int)]
+    lib.riga_batch_destroy.argtypes = [P]
+    lib.riga_batch_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("riga_status_str", "riga_destroy"):
+        if name not in ("riga_status_str", "riga_destroy", "riga_batch_destroy"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -267,3 +276,100 @@ class Problem:
         s = riga_stats_t()
         _check(self.lib.riga_stats(self.h, C.byref(s)), "riga_stats")
         return {f: getattr(s, f) for f, _ in riga_stats_t._fields_}
+
+
+class Batch:
+    """Many independent problems solved together (riga_batch_* calls).
+
+    meshes: sequence of (p, ne, hyper_every) or (p, ne, hyper_every, leaf)."""
+
+    def __init__(self, meshes, device: int = 0, stream=None):
+        import torch
+
+        self.torch = torch
+        self.lib = load()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self.n = len(meshes)
+        arr = (riga_mesh * self.n)()
+        for i, m in enumerate(meshes):
+            m = tuple(m) + (0,) * (4 - len(m))
+            arr[i] = riga_mesh(*[int(x) for x in m[:4]])
+        self.meshes = [tuple(m) for m in meshes]
+        self.h = C.c_void_p()
+        _check(self.lib.riga_batch_create(C.byref(self.h), self.n, C.cast(arr, C.c_void_p), device,
+                                          C.c_void_p(stream.cuda_stream)), "riga_batch_create")
+        tot = C.c_int64(0)
+        offs = np.zeros(self.n + 1, dtype=np.int64)
+        _check(self.lib.riga_batch_info(self.h, C.byref(tot), offs.ctypes.data_as(C.c_void_p)), "riga_batch_info")
+        self.total = int(tot.value)
+        self.offsets = offs
+        self._c = None
+
+    def close(self):
+        if self.h:
+            self.lib.riga_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def assemble(self, alphas, betas, c_elems=None):
+        """c_elems: None or a list (None or float64 (ne, ne) tensors) per problem."""
+        arr = (riga_damping * self.n)()
+        keep = []
+        for i in range(self.n):
+            c = None if c_elems is None else c_elems[i]
+            if c is not None:
+                c = c.to(device=self.device, dtype=self.torch.float64).contiguous()
+                keep.append(c)
+            arr[i] = riga_damping(float(alphas[i]), float(betas[i]), _ptr(c))
+        self._c = keep
+        _check(self.lib.riga_batch_assemble(self.h, C.cast(arr, C.c_void_p)), "riga_batch_assemble")
+
+    def factor(self, sigmas):
+        sg = np.ascontiguousarray(sigmas, dtype=np.float64)
+        bad = np.full(self.n, -1, dtype=np.int64)
+        st = self.lib.riga_batch_factor(self.h, sg.ctypes.data_as(C.c_void_p), bad.ctypes.data_as(C.c_void_p))
+        if st == RIGA_ERR_NOT_SPD:
+            err = RigaError(st, "riga_batch_factor")
+            err.bad_pivot = bad
+            raise err
+        _check(st, "riga_batch_factor")
+
+    def eigs(self, nev: int, m: int = 0, block: int = 0, tol: float = 0.0, maxit: int = 0, seed: int = 0,
+             vectors: bool = False, flags: int = 0):
+        """Returns (lam complex (n, nev), X list of complex (nev, N_p) tensors or None,
+        eta (n, nev), nconv (n,), status)."""
+        torch = self.torch
+        lam = np.zeros(self.n * 2 * nev)
+        eta = np.zeros(self.n * nev)
+        nconv = np.zeros(self.n, dtype=np.int32)
+        X = torch.empty(2 * nev * self.total, dtype=torch.float64, device=self.device) if vectors else None
+        opt = riga_options(nev, m, maxit, block, tol, seed, None, flags)
+        st = self.lib.riga_batch_eigs(self.h, C.byref(opt), lam.ctypes.data_as(C.c_void_p), _ptr(X),
+                                      eta.ctypes.data_as(C.c_void_p), nconv.ctypes.data_as(C.c_void_p))
+        _check(st, "riga_batch_eigs", allow_warn=True)
+        lam = lam.reshape(self.n, nev, 2)
+        lam = lam[..., 0] + 1j * lam[..., 1]
+        Xs = None
+        if X is not None:
+            Xs = []
+            for i in range(self.n):
+                o, n_i = int(self.offsets[i]), int(self.offsets[i + 1] - self.offsets[i])
+                blk = X[2 * nev * o: 2 * nev * (o + n_i)].view(nev, n_i, 2)
+                Xs.append(torch.view_as_complex(blk))
+        return lam, Xs, eta.reshape(self.n, nev), nconv, st
+
+    def stats(self):
+        s = riga_stats_t()
+        k = C.c_int(0)
+        _check(self.lib.riga_batch_stats(self.h, C.byref(s), C.byref(k)), "riga_batch_stats")
+        out = {f: getattr(s, f) for f, _ in riga_stats_t._fields_}
+        out["n_resolved"] = k.value
+        return out
