@@ -13,9 +13,10 @@ device) before the timed region.  The IGA discretisation and the CPU oracle are
 measured after the timed steps and reported beside it.
 
 The precision form (FP32 fronts + FP64 refinement against the FP64 path on
-the p=4, 1024^2, s=32 workload) is measured last and reported beside it.
+the p=4, 1024^2, s=32 workload) and the batching form (256 uneven problems
+solved together) are measured last and reported beside it.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-iga] [--no-mixed]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-iga] [--no-mixed] [--no-batch]
 """
 from __future__ import annotations
 
@@ -146,6 +147,55 @@ def precision_form(torch, riga, W, ir_tol=1e-9):
     return out
 
 
+def batching_form(torch, riga, W, steps=2):
+    """The batching workload: 256 independent problems (ne in {32..128}, p in
+    {2,3,4}, s=8, seeded damping and shifts, 8 pairs each) assembled, factored
+    and solved together; sweep shapes autotuned on the forest first.  The
+    single-problem path on the first 32 problems is timed beside it."""
+    probs = W.cfg_batch()
+    B = riga.Batch([(P.p, P.ne, P.hyper_every) for P in probs])
+    al, be, sg = [P.alpha for P in probs], [P.beta for P in probs], [P.sigma for P in probs]
+    B.assemble(al, be)
+    B.factor(sg)
+    before, after = B.autotune(2, 5)
+
+    def one():
+        B.assemble(al, be)
+        B.factor(sg)
+        return B.eigs(8, 20, block=2, seed=0)
+
+    one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        lam, _, eta, nconv, st = one()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    s = B.stats()
+    good = int(sum(int(((eta[i][:nconv[i]]) <= 1e-10).sum()) for i in range(len(probs))))
+    out = {"workload": "256 problems, ne in {32,48,64,96,128}, p in {2,3,4}, s=8, Rayleigh alpha~U[0,0.2], "
+                       "beta~U[0,0.02], sigma~U[0.5,4] (seed 1), 8 pairs each, subspace 20",
+           "total_dofs": int(B.total), "ms_per_step": ms, "eigenpairs_per_s": good * 1e3 / ms, "pairs_ok": good,
+           "assemble_ms": s["t_assemble_ms"], "factor_ms": s["t_factor_ms"], "eigs_ms": s["t_eigs_ms"],
+           "lockstep_cycles": int(s["n_it"]), "resolved_one_by_one": int(s["n_resolved"]),
+           "max_eta": float(eta.max()), "autotune_forest_solve_ms": {"before": before, "after": after}}
+    B.close()
+    # the single-problem path, one problem after another
+    t0 = time.perf_counter()
+    cnt = 0
+    for P in probs[:32]:
+        pr = riga.Problem(P.p, P.ne, P.hyper_every)
+        pr.assemble(P.alpha, P.beta)
+        pr.factor(P.sigma)
+        _, _, e1, n1, _ = pr.eigs(8, 20, block=2, seed=0, vectors=False)
+        cnt += int((e1[:n1] <= 1e-10).sum())
+        pr.close()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out["one_by_one_first32_eigenpairs_per_s"] = cnt / t
+    return out
+
+
 def cpu_baseline(P, lam_gpu):
     """The oracle as it stands: SciPy sparse LU of Q(sigma) + ARPACK on the
     shift-and-invert operator, same workload (full solve, ~30 s)."""
@@ -175,6 +225,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-iga", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path",
@@ -225,6 +276,8 @@ def main():
         }
     if not args.no_mixed:
         out["precision_form"] = precision_form(torch, riga, W)
+    if not args.no_batch:
+        out["batching_form"] = batching_form(torch, riga, W)
     if roof is not None:
         out["roofline"] = roof
     if not args.no_cpu:

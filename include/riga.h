@@ -236,6 +236,22 @@ riga_status riga_stats(const riga_problem* h, riga_stats_t* stats);
 riga_status riga_time_kernel(riga_problem* h, int which, int nrhs, int reps, double* avg_ms,
                              double* work_per_launch, int* launches);
 
+/* Autotuner of the sweep tile shapes (waves per 64-row task x 16-byte column
+ * groups each wave keeps in flight; sweep layouts of Sec. 5.2.2's forward and
+ * backward eliminations): every tree level and direction is timed with each
+ * compiled shape on this handle's factor with nrhs right-hand sides (reps
+ * launches each), and the fastest is kept for all later solves.  Choices are
+ * cached in the process per device architecture, tree-level structure,
+ * precision and nrhs, so a second handle of the same shape reuses them.
+ * before_ms / after_ms (host, or NULL): one full forward+backward solve with
+ * the previous and with the chosen shapes.  Requires a factored handle;
+ * synchronises.                                                              */
+riga_status riga_autotune(riga_problem* h, int nrhs, int reps, double* before_ms, double* after_ms);
+
+/* The sweep shape chosen per tree level (host arrays of `height` ints, or
+ * NULL) and the number of levels.                                            */
+riga_status riga_sweep_shapes(const riga_problem* h, int* fwd, int* bwd, int* levels);
+
 /* Host-only self-test of the dense small eigensolver used for the Ritz values
  * (Rayleigh-Ritz on the projected matrix, eq. ArnoldiRitz): a is n x n real
  * column-major (host); on return w holds the n eigenvalues (re, im pairs) and
@@ -284,6 +300,10 @@ riga_status riga_batch_factor(riga_batch* bh, const double* sigmas, int64_t* bad
  * RIGA_WARN_NOT_CONVERGED if any problem has nconv < nev.                     */
 riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam, double* X, double* eta,
                             int* nconv);
+
+/* riga_autotune for the forest of the batch (shapes chosen per tree level
+ * across all problems).                                                      */
+riga_status riga_batch_autotune(riga_batch* bh, int nrhs, int reps, double* before_ms, double* after_ms);
 
 /* Phase times and counters of the last calls (n_it: lockstep cycles; n_fb:
  * vectors through the sweeps summed over problems); n_resolved (or NULL): the

@@ -9,7 +9,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
+#include <string>
 
 using riga::cplx;
 using namespace riga::detail;
@@ -109,13 +111,13 @@ void sweep(riga_problem* h, int nrhs, const double* b, int64_t ldb, const riga::
     int a = h->ftask_off[lv], c = h->ftask_off[lv + 1] - a;
     const bool f32 = h->level_f32(lv);
     riga::launch_fwd_level(h->dt, h->d_ftasks + a, c, nrhs, h->d_Lp, f32 ? h->d_Lp32 : nullptr, b, ldb, h->d_tmp,
-                           h->N(), h->d_upd, P.max_front, h->st);
+                           h->N(), h->d_upd, P.max_front, h->fvar[lv], h->st);
   }
   for (int lv = H - 1; lv >= 0; --lv) {
     int a = h->btask_off[lv], c = h->btask_off[lv + 1] - a;
     const bool f32 = h->level_f32(lv);
     riga::launch_bwd_level(h->dt, h->d_btasks + a, c, nrhs, h->d_Tp, f32 ? h->d_Tp32 : nullptr, h->d_tmp, h->N(), o,
-                           P.max_front, h->st);
+                           P.max_front, h->bvar[lv], h->st);
   }
 }
 
@@ -288,6 +290,8 @@ void setup_device(riga_problem* h) {
       for (size_t v = 0; v < P.nf.size(); ++v) doff[v + 1] = doff[v] + (P.no[v] + 63) / 64;
       h->dt.doff = h->upload(doff);
       h->d_D = h->dalloc<double>((size_t)doff.back() * 4096);
+      h->fvar.assign(P.height, 0);
+      h->bvar.assign(P.height, 0);
       h->lvl_max_no.assign(P.height, 0);
       h->lvl_max_nf.assign(P.height, 0);
       h->lvl_max_cnb.assign(P.height, 0);
@@ -523,6 +527,94 @@ void ir_history(riga_problem* h, int kmax, std::vector<double>& hist) {
   }
 }
 
+// Per-level autotuning of the sweep shapes.  Every (level, direction) is timed
+// with each compiled shape on the handle's own factor and a seeded right-hand
+// side, after one full solve has put every level's inputs in place (a level's
+// launch only reads what lower / higher levels wrote, so repeating it is
+// idempotent).  Choices are cached per device architecture, level structure,
+// precision and number of right-hand sides.
+void autotune_sweeps(riga_problem* h, int nrhs, int reps, double* before_ms, double* after_ms) {
+  static std::mutex mu;
+  static std::map<std::string, std::pair<std::vector<int>, std::vector<int>>> cache;
+  const riga::Plan& P = h->plan;
+  const int H = P.height;
+  const int64_t N = h->N();
+  hipDeviceProp_t prop;
+  ck(hipGetDeviceProperties(&prop, h->device));
+  std::string key = std::string(prop.gcnArchName) + "|" + std::to_string(nrhs);
+  for (int lv = 0; lv < H; ++lv)
+    key += "|" + std::to_string(h->ftask_off[lv + 1] - h->ftask_off[lv]) + "," +
+           std::to_string(h->btask_off[lv + 1] - h->btask_off[lv]) + "," + std::to_string(h->lvl_max_nf[lv]) +
+           (h->level_f32(lv) ? "s" : "d");
+  if (!h->d_tune) h->d_tune = h->dalloc<double>((size_t)N * 4);
+  riga::BwdOut o;
+  o.xs = h->d_tune; o.ldxs = N;
+  auto full = [&]() {
+    float ms = 0;
+    ck(hipEventRecord(h->ev0, h->st));
+    for (int r = 0; r < reps; ++r) sweep(h, nrhs, h->d_tmp2, N, o);
+    ck(hipEventRecord(h->ev1, h->st));
+    ck(hipEventSynchronize(h->ev1));
+    ck(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    return (double)ms / reps;
+  };
+  // inputs: a seeded right-hand side (d_tmp2), solved once so that every
+  // level's inputs are defined; forward results go to d_tmp, backward to d_tune
+  riga::launch_random_fill(h->d_tmp2, N, nrhs, N, 777, h->st);
+  sweep(h, nrhs, h->d_tmp2, N, o);
+  const double t0 = full();
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      h->fvar = it->second.first;
+      h->bvar = it->second.second;
+      if (before_ms) *before_ms = t0;
+      if (after_ms) *after_ms = full();
+      return;
+    }
+  }
+  const int nv = riga::sweep_variants();
+  auto time_level = [&](bool fwd, int lv, int var) {
+    float ms = 0;
+    const bool f32 = h->level_f32(lv);
+    ck(hipEventRecord(h->ev0, h->st));
+    for (int r = 0; r < reps; ++r) {
+      if (fwd) {
+        const int a = h->ftask_off[lv], c = h->ftask_off[lv + 1] - a;
+        riga::launch_fwd_level(h->dt, h->d_ftasks + a, c, nrhs, h->d_Lp, f32 ? h->d_Lp32 : nullptr, h->d_tmp2, N,
+                               h->d_tmp, N, h->d_upd, P.max_front, var, h->st);
+      } else {
+        const int a = h->btask_off[lv], c = h->btask_off[lv + 1] - a;
+        riga::launch_bwd_level(h->dt, h->d_btasks + a, c, nrhs, h->d_Tp, f32 ? h->d_Tp32 : nullptr, h->d_tmp, N, o,
+                               P.max_front, var, h->st);
+      }
+    }
+    ck(hipEventRecord(h->ev1, h->st));
+    ck(hipEventSynchronize(h->ev1));
+    ck(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    return (double)ms;
+  };
+  // forward levels first (they rewrite d_tmp with the same values), then backward
+  for (int dir = 0; dir < 2; ++dir)
+    for (int lv = 0; lv < H; ++lv) {
+      int best = 0;
+      double tb = 1e300;
+      for (int v = 0; v < nv; ++v) {
+        const double t = time_level(dir == 0, lv, v);
+        if (t < tb) { tb = t; best = v; }
+      }
+      (dir == 0 ? h->fvar : h->bvar)[lv] = best;
+    }
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    cache[key] = {h->fvar, h->bvar};
+  }
+  h->clear_graphs();
+  if (before_ms) *before_ms = t0;
+  if (after_ms) *after_ms = full();
+}
+
 }  // namespace detail
 }  // namespace riga
 
@@ -594,6 +686,26 @@ riga_status riga_factor_mixed(riga_problem* h, double sigma, int fp64_levels, in
     h->ir_sweeps = ir_sweeps;
     return RIGA_OK;
   });
+}
+
+riga_status riga_autotune(riga_problem* h, int nrhs, int reps, double* before_ms, double* after_ms) {
+  if (!h || nrhs < 1 || nrhs > 4 || reps < 1) return RIGA_ERR_INVALID_ARG;
+  if (!h->factored) return RIGA_ERR_STATE;
+  return run([&]() -> riga_status {
+    ck(hipSetDevice(h->device));
+    autotune_sweeps(h, nrhs, reps, before_ms, after_ms);
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_sweep_shapes(const riga_problem* h, int* fwd, int* bwd, int* levels) {
+  if (!h) return RIGA_ERR_INVALID_ARG;
+  if (levels) *levels = h->plan.height;
+  for (int lv = 0; lv < h->plan.height; ++lv) {
+    if (fwd) fwd[lv] = h->fvar[lv];
+    if (bwd) bwd[lv] = h->bvar[lv];
+  }
+  return RIGA_OK;
 }
 
 riga_status riga_ir_sweeps(const riga_problem* h, int* sweeps) {
@@ -689,12 +801,12 @@ riga_status riga_time_kernel(riga_problem* h, int which, int nrhs, int reps, dou
         if (which == 0) {
           int a = h->ftask_off[lv], c = h->ftask_off[lv + 1] - a;
           riga::launch_fwd_level(h->dt, h->d_ftasks + a, c, nrhs, h->d_Lp, h->level_f32(lv) ? h->d_Lp32 : nullptr,
-                                 h->d_tmp2, N, h->d_tmp, N, h->d_upd, P.max_front, h->st);
+                                 h->d_tmp2, N, h->d_tmp, N, h->d_upd, P.max_front, h->fvar[lv], h->st);
         } else if (which == 1) {
           int l2 = H - 1 - lv;
           int a = h->btask_off[l2], c = h->btask_off[l2 + 1] - a;
           riga::launch_bwd_level(h->dt, h->d_btasks + a, c, nrhs, h->d_Tp, h->level_f32(l2) ? h->d_Tp32 : nullptr,
-                                 h->d_tmp, N, o, P.max_front, h->st);
+                                 h->d_tmp, N, o, P.max_front, h->bvar[l2], h->st);
         } else {
           factor_level(h, lv, h->sigma);
         }

@@ -667,6 +667,18 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
   });
 }
 
+riga_status riga_batch_autotune(riga_batch* bh, int nrhs, int reps, double* before_ms, double* after_ms) {
+  if (!bh || nrhs < 1 || nrhs > 4 || reps < 1) return RIGA_ERR_INVALID_ARG;
+  if (!bh->factored) return RIGA_ERR_STATE;
+  return run([&]() -> riga_status {
+    ck(hipSetDevice(bh->device));
+    bh->fp->dt.ilive = nullptr;
+    autotune_sweeps(bh->fp, nrhs, reps, before_ms, after_ms);
+    bh->clear_graphs();
+    return RIGA_OK;
+  });
+}
+
 riga_status riga_batch_stats(const riga_batch* bh, riga_stats_t* stats, int* n_resolved) {
   if (!bh || !stats) return RIGA_ERR_INVALID_ARG;
   *stats = bh->stats;

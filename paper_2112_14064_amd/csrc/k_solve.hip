@@ -24,17 +24,13 @@
 
 namespace riga {
 
-constexpr int ST = 512;           // threads per task: 8 waves
 constexpr int SR = 64;            // rows per task: one per lane
-constexpr int SW = ST / 64;       // waves per task
 // Factor blocks are read in the sweep layouts written by the factorization:
 // K = 16 bytes / element consecutive columns (forward) or rows (backward) of
-// F side by side, one 16-byte load per lane and group; each wave keeps SG
-// group loads in flight per round.
-#ifndef RIGA_SWEEP_GROUPS
-#define RIGA_SWEEP_GROUPS 4
-#endif
-constexpr int SG = RIGA_SWEEP_GROUPS;
+// F side by side, one 16-byte load per lane and group.  Tile shape of a task
+// (a template pair, chosen per tree level by the autotuner): NW waves share
+// the columns of the task's 64 rows, each wave keeping SG group loads in
+// flight per round.  sweep_variant() lists the compiled shapes.
 template <class E>
 struct Pack {
   static constexpr int K = 16 / sizeof(E);
@@ -43,7 +39,7 @@ struct Pack {
 
 // acc[q] of row `lane` summed over the waves through LDS; wave 0 ends with the
 // total for its lane.
-template <int NR>
+template <int NR, int NW>
 __device__ __forceinline__ void reduce_waves(double (&acc)[NR], double* red, int lane, int wave) {
 #pragma unroll
   for (int q = 0; q < NR; ++q) red[(wave * SR + lane) * NR + q] = acc[q];
@@ -53,14 +49,14 @@ __device__ __forceinline__ void reduce_waves(double (&acc)[NR], double* red, int
     for (int q = 0; q < NR; ++q) {
       double s2 = 0.0;
 #pragma unroll
-      for (int w2 = 0; w2 < SW; ++w2) s2 += red[(w2 * SR + lane) * NR + q];
+      for (int w2 = 0; w2 < NW; ++w2) s2 += red[(w2 * SR + lane) * NR + q];
       acc[q] = s2;
     }
   }
 }
 
-template <int NR, class E>
-__global__ __launch_bounds__(ST) void k_fwd(DevTree t, const int4* __restrict__ tasks,
+template <int NR, class E, int NW, int SG>
+__global__ __launch_bounds__(NW * 64) void k_fwd(DevTree t, const int4* __restrict__ tasks,
                                             const E* __restrict__ Lp,
                                             const double* __restrict__ b, int64_t ldb,
                                             double* __restrict__ y, int64_t ldy,
@@ -71,11 +67,11 @@ __global__ __launch_bounds__(ST) void k_fwd(DevTree t, const int4* __restrict__ 
   const int v = tk.x, r0 = tk.y, r1 = tk.z;
   const int nf = t.nf[v], no = t.no[v];
   if (t.ilive != nullptr && !t.ilive[t.inst[v]]) return;
-  double* red = shm + (size_t)nf * NR;   // SW x SR x NR partial sums
+  double* red = shm + (size_t)nf * NR;   // NW x SR x NR partial sums
   const int* fd = t.fdofs + t.foff[v];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-  for (int p = tid; p < nf; p += ST)
+  for (int p = tid; p < nf; p += NW * 64)
 #pragma unroll
     for (int q = 0; q < NR; ++q) f[p * NR + q] = (p < no) ? b[fd[p] + q * ldb] : 0.0;
   __syncthreads();
@@ -84,7 +80,7 @@ __global__ __launch_bounds__(ST) void k_fwd(DevTree t, const int4* __restrict__ 
     const int nbc = t.nb[c];
     const int* mp = t.maps + t.moff[c];
     const double* uc = upd + (int64_t)t.voff[c] * NR;
-    for (int k = tid; k < nbc; k += ST)
+    for (int k = tid; k < nbc; k += NW * 64)
 #pragma unroll
       for (int q = 0; q < NR; ++q) f[mp[k] * NR + q] += uc[k * NR + q];
     __syncthreads();
@@ -102,7 +98,7 @@ __global__ __launch_bounds__(ST) void k_fwd(DevTree t, const int4* __restrict__ 
   // group g of row r at col[g * nf]; entries past the diagonal are stored zeros
   const V* col = reinterpret_cast<const V*>(Lp + t.lpoff[v]) + (live ? r : r0);
   const int gend = (jend + K - 1) / K;
-  for (int g0 = wave * SG; g0 < gend; g0 += SW * SG) {
+  for (int g0 = wave * SG; g0 < gend; g0 += NW * SG) {
     V a[SG];
 #pragma unroll
     for (int u = 0; u < SG; ++u) a[u] = (g0 + u < gend) ? col[(int64_t)(g0 + u) * nf] : V{};
@@ -115,7 +111,7 @@ __global__ __launch_bounds__(ST) void k_fwd(DevTree t, const int4* __restrict__ 
         for (int q = 0; q < NR; ++q) acc[q] += (double)a[u][e] * f[j * NR + q];
       }
   }
-  reduce_waves<NR>(acc, red, lane, wave);
+  reduce_waves<NR, NW>(acc, red, lane, wave);
   if (wave == 0 && live) {
     if (r < no) {
 #pragma unroll
@@ -133,8 +129,8 @@ __global__ __launch_bounds__(ST) void k_fwd(DevTree t, const int4* __restrict__ 
 // Optional outputs: ru = scale (x + base) (base may be null; ru may alias
 // base: each entry is read and written by one thread) and
 // rl = sig val + v_u, where val is the ru value or, without ru, the xs value.
-template <int NR, class E>
-__global__ __launch_bounds__(ST) void k_bwd(DevTree t, const int4* __restrict__ tasks,
+template <int NR, class E, int NW, int SG>
+__global__ __launch_bounds__(NW * 64) void k_bwd(DevTree t, const int4* __restrict__ tasks,
                                             const E* __restrict__ Tp,
                                             const double* __restrict__ y, int64_t ldy,
                                             double* __restrict__ xs, int64_t ldxs, int neg,
@@ -153,7 +149,7 @@ __global__ __launch_bounds__(ST) void k_bwd(DevTree t, const int4* __restrict__ 
   const int* fd = t.fdofs + t.foff[v];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-  for (int p = tid; p < nf; p += ST)
+  for (int p = tid; p < nf; p += NW * 64)
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
       double val;
@@ -178,7 +174,7 @@ __global__ __launch_bounds__(ST) void k_bwd(DevTree t, const int4* __restrict__ 
   // above the diagonal are stored zeros, so the block starts at group a0 / K
   const V* row = reinterpret_cast<const V*>(Tp + t.tpoff[v]) + (live ? a : a0);
   const int gbeg = a0 / K, gend = (nf + K - 1) / K;
-  for (int g0 = gbeg + wave * SG; g0 < gend; g0 += SW * SG) {
+  for (int g0 = gbeg + wave * SG; g0 < gend; g0 += NW * SG) {
     V e[SG];
 #pragma unroll
     for (int u = 0; u < SG; ++u) e[u] = (g0 + u < gend) ? row[(int64_t)(g0 + u) * no] : V{};
@@ -191,7 +187,7 @@ __global__ __launch_bounds__(ST) void k_bwd(DevTree t, const int4* __restrict__ 
         for (int q = 0; q < NR; ++q) acc[q] += (double)e[u][k] * w[i * NR + q];
       }
   }
-  reduce_waves<NR>(acc, red, lane, wave);
+  reduce_waves<NR, NW>(acc, red, lane, wave);
   if (wave == 0 && live) {
     const int d = fd[a];
 #pragma unroll
@@ -207,51 +203,95 @@ __global__ __launch_bounds__(ST) void k_bwd(DevTree t, const int4* __restrict__ 
   }
 }
 
+int sweep_variants() { return 6; }
+
+void sweep_variant(int v, int* waves, int* groups) {
+  static const int W[6] = {8, 8, 8, 4, 4, 4}, G[6] = {4, 2, 8, 4, 2, 8};
+  *waves = W[v];
+  *groups = G[v];
+}
+
+namespace {
+
+template <int NR, class E, int NW, int SG>
+void fwd_one(const DevTree& t, const int4* tasks, int count, const E* Lp, const double* b, int64_t ldb, double* y,
+             int64_t ldy, double* upd, int max_front, hipStream_t st) {
+  const size_t shm = ((size_t)max_front + NW * SR) * NR * sizeof(double);
+  hipLaunchKernelGGL((k_fwd<NR, E, NW, SG>), dim3(count), dim3(NW * 64), shm, st, t, tasks, Lp, b, ldb, y, ldy, upd);
+}
+
+template <int NR, class E>
+void fwd_shape(int variant, const DevTree& t, const int4* tasks, int count, const E* Lp, const double* b,
+               int64_t ldb, double* y, int64_t ldy, double* upd, int max_front, hipStream_t st) {
+  switch (variant) {
+    case 1: fwd_one<NR, E, 8, 2>(t, tasks, count, Lp, b, ldb, y, ldy, upd, max_front, st); break;
+    case 2: fwd_one<NR, E, 8, 8>(t, tasks, count, Lp, b, ldb, y, ldy, upd, max_front, st); break;
+    case 3: fwd_one<NR, E, 4, 4>(t, tasks, count, Lp, b, ldb, y, ldy, upd, max_front, st); break;
+    case 4: fwd_one<NR, E, 4, 2>(t, tasks, count, Lp, b, ldb, y, ldy, upd, max_front, st); break;
+    case 5: fwd_one<NR, E, 4, 8>(t, tasks, count, Lp, b, ldb, y, ldy, upd, max_front, st); break;
+    default: fwd_one<NR, E, 8, 4>(t, tasks, count, Lp, b, ldb, y, ldy, upd, max_front, st); break;
+  }
+}
+
+template <class E>
+void fwd_nr(int nrhs, int variant, const DevTree& t, const int4* tasks, int count, const E* Lp, const double* b,
+            int64_t ldb, double* y, int64_t ldy, double* upd, int max_front, hipStream_t st) {
+  switch (nrhs) {
+    case 1: fwd_shape<1, E>(variant, t, tasks, count, Lp, b, ldb, y, ldy, upd, max_front, st); break;
+    case 2: fwd_shape<2, E>(variant, t, tasks, count, Lp, b, ldb, y, ldy, upd, max_front, st); break;
+    case 3: fwd_shape<3, E>(variant, t, tasks, count, Lp, b, ldb, y, ldy, upd, max_front, st); break;
+    default: fwd_shape<4, E>(variant, t, tasks, count, Lp, b, ldb, y, ldy, upd, max_front, st); break;
+  }
+}
+
+template <int NR, class E, int NW, int SG>
+void bwd_one(const DevTree& t, const int4* tasks, int count, const E* Tp, const double* y, int64_t ldy,
+             const BwdOut& o, int max_front, hipStream_t st) {
+  const size_t shm = ((size_t)max_front + NW * SR) * NR * sizeof(double);
+  hipLaunchKernelGGL((k_bwd<NR, E, NW, SG>), dim3(count), dim3(NW * 64), shm, st, t, tasks, Tp, y, ldy, o.xs,
+                     o.ldxs, o.neg, o.base, o.ldbase, o.ru, o.ldr, o.scale, o.rl, o.v_u, o.ldv, o.sig);
+}
+
+template <int NR, class E>
+void bwd_shape(int variant, const DevTree& t, const int4* tasks, int count, const E* Tp, const double* y,
+               int64_t ldy, const BwdOut& o, int max_front, hipStream_t st) {
+  switch (variant) {
+    case 1: bwd_one<NR, E, 8, 2>(t, tasks, count, Tp, y, ldy, o, max_front, st); break;
+    case 2: bwd_one<NR, E, 8, 8>(t, tasks, count, Tp, y, ldy, o, max_front, st); break;
+    case 3: bwd_one<NR, E, 4, 4>(t, tasks, count, Tp, y, ldy, o, max_front, st); break;
+    case 4: bwd_one<NR, E, 4, 2>(t, tasks, count, Tp, y, ldy, o, max_front, st); break;
+    case 5: bwd_one<NR, E, 4, 8>(t, tasks, count, Tp, y, ldy, o, max_front, st); break;
+    default: bwd_one<NR, E, 8, 4>(t, tasks, count, Tp, y, ldy, o, max_front, st); break;
+  }
+}
+
+template <class E>
+void bwd_nr(int nrhs, int variant, const DevTree& t, const int4* tasks, int count, const E* Tp, const double* y,
+            int64_t ldy, const BwdOut& o, int max_front, hipStream_t st) {
+  switch (nrhs) {
+    case 1: bwd_shape<1, E>(variant, t, tasks, count, Tp, y, ldy, o, max_front, st); break;
+    case 2: bwd_shape<2, E>(variant, t, tasks, count, Tp, y, ldy, o, max_front, st); break;
+    case 3: bwd_shape<3, E>(variant, t, tasks, count, Tp, y, ldy, o, max_front, st); break;
+    default: bwd_shape<4, E>(variant, t, tasks, count, Tp, y, ldy, o, max_front, st); break;
+  }
+}
+
+}  // namespace
+
 void launch_fwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* Lp64,
                       const float* Lp32, const double* b, int64_t ldb, double* y, int64_t ldy, double* upd,
-                      int max_front, hipStream_t st) {
+                      int max_front, int variant, hipStream_t st) {
   if (count <= 0) return;
-  size_t shm = ((size_t)max_front + SW * SR) * nrhs * sizeof(double);
-#define RIGA_FWD(NR, E, L) \
-  hipLaunchKernelGGL((k_fwd<NR, E>), dim3(count), dim3(ST), shm, st, t, tasks, L, b, ldb, y, ldy, upd)
-#define RIGA_FWD_NR(E, L)           \
-  switch (nrhs) {                   \
-    case 1: RIGA_FWD(1, E, L); break; \
-    case 2: RIGA_FWD(2, E, L); break; \
-    case 3: RIGA_FWD(3, E, L); break; \
-    default: RIGA_FWD(4, E, L); break; \
-  }
-  if (Lp32 != nullptr) {
-    RIGA_FWD_NR(float, Lp32)
-  } else {
-    RIGA_FWD_NR(double, Lp64)
-  }
-#undef RIGA_FWD_NR
-#undef RIGA_FWD
+  if (Lp32 != nullptr) fwd_nr<float>(nrhs, variant, t, tasks, count, Lp32, b, ldb, y, ldy, upd, max_front, st);
+  else fwd_nr<double>(nrhs, variant, t, tasks, count, Lp64, b, ldb, y, ldy, upd, max_front, st);
 }
 
 void launch_bwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* Tp64,
-                      const float* Tp32, const double* y, int64_t ldy, const BwdOut& o, int max_front,
+                      const float* Tp32, const double* y, int64_t ldy, const BwdOut& o, int max_front, int variant,
                       hipStream_t st) {
   if (count <= 0) return;
-  size_t shm = ((size_t)max_front + SW * SR) * nrhs * sizeof(double);
-#define RIGA_BWD(NR, E, T)                                                                            \
-  hipLaunchKernelGGL((k_bwd<NR, E>), dim3(count), dim3(ST), shm, st, t, tasks, T, y, ldy, o.xs, o.ldxs, \
-                     o.neg, o.base, o.ldbase, o.ru, o.ldr, o.scale, o.rl, o.v_u, o.ldv, o.sig)
-#define RIGA_BWD_NR(E, T)           \
-  switch (nrhs) {                   \
-    case 1: RIGA_BWD(1, E, T); break; \
-    case 2: RIGA_BWD(2, E, T); break; \
-    case 3: RIGA_BWD(3, E, T); break; \
-    default: RIGA_BWD(4, E, T); break; \
-  }
-  if (Tp32 != nullptr) {
-    RIGA_BWD_NR(float, Tp32)
-  } else {
-    RIGA_BWD_NR(double, Tp64)
-  }
-#undef RIGA_BWD_NR
-#undef RIGA_BWD
+  if (Tp32 != nullptr) bwd_nr<float>(nrhs, variant, t, tasks, count, Tp32, y, ldy, o, max_front, st);
+  else bwd_nr<double>(nrhs, variant, t, tasks, count, Tp64, y, ldy, o, max_front, st);
 }
 
 }  // namespace riga

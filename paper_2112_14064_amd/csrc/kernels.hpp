@@ -71,9 +71,13 @@ void launch_combine_q(int64_t nnz, double s2, double s1, const double* K, const 
 // One launch per tree level; tasks[k] = {node, first row, end row, 0}.  The
 // level's factor is read in its sweep layouts, FP64 (Lp64/Tp64) or FP32
 // (Lp32/Tp32 non-null).
+// `variant` selects the task tile shape (0 .. sweep_variants()-1, see sweep_variant).
 void launch_fwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* Lp64,
                       const float* Lp32, const double* b, int64_t ldb, double* y, int64_t ldy, double* upd,
-                      int max_front, hipStream_t st);
+                      int max_front, int variant, hipStream_t st);
+int sweep_variants();
+// Waves per task and column groups per wave and round of a sweep variant.
+void sweep_variant(int v, int* waves, int* groups);
 // Outputs of the backward sweep (see k_bwd): xs holds the sweep's solution
 // (negated if neg), optionally ru = scale (x + base) and rl = sig val + v_u.
 struct BwdOut {
@@ -83,7 +87,7 @@ struct BwdOut {
   double* rl = nullptr; const double* v_u = nullptr; int64_t ldv = 0; double sig = 0.0;
 };
 void launch_bwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* Tp64,
-                      const float* Tp32, const double* y, int64_t ldy, const BwdOut& o, int max_front,
+                      const float* Tp32, const double* y, int64_t ldy, const BwdOut& o, int max_front, int variant,
                       hipStream_t st);
 
 // --- Krylov building blocks -----------------------------------------------------

@@ -46,6 +46,8 @@ struct riga_problem {
   int4 *d_ftasks = nullptr, *d_btasks = nullptr;   // solve tasks, grouped by level
   double* d_D = nullptr;                            // 64x64 diagonal-block inverses
   std::vector<int> lvl_max_no, lvl_max_nf, lvl_max_cnb;
+  std::vector<int> fvar, bvar;                      // sweep tile shape per level (autotuned)
+  double* d_tune = nullptr;                         // autotuner output block (ndof x 4)
   std::vector<int> ftask_off, btask_off;
   int64_t* d_status = nullptr;
   double* d_part = nullptr;       // reduction scratch
@@ -144,6 +146,8 @@ void factor_level(riga_problem* h, int lv, double sigma);
 // Factor every level; RIGA_ERR_NOT_SPD with *bad_pivot (a dof) on a failed pivot.
 riga_status factor_all(riga_problem* h, double sigma, int64_t* bad_pivot);
 int small_chol(int b, const std::vector<double>& G, std::vector<double>& R, double rel);
+// Autotune the per-level sweep shapes of a factored handle (see riga_autotune).
+void autotune_sweeps(riga_problem* h, int nrhs, int reps, double* before_ms, double* after_ms);
 std::vector<double> upper_inverse(int b, const std::vector<double>& R);
 
 }  // namespace detail

@@ -52,7 +52,8 @@ class riga_stats_t(C.Structure):
 
 EXPORTS = ["riga_create", "riga_info", "riga_assemble", "riga_export_csr", "riga_factor", "riga_factor_mixed",
            "riga_ir_sweeps", "riga_batch_create", "riga_batch_info", "riga_batch_assemble", "riga_batch_factor",
-           "riga_batch_eigs", "riga_batch_stats", "riga_batch_destroy",
+           "riga_batch_eigs", "riga_batch_stats", "riga_batch_destroy", "riga_autotune", "riga_sweep_shapes",
+           "riga_batch_autotune",
            "riga_solve_q", "riga_apply_op", "riga_eigs", "riga_adjoint", "riga_stats", "riga_time_kernel",
            "riga_selftest_small_eig", "riga_status_str", "riga_destroy"]
 
@@ -93,6 +94,9 @@ def load(path: str = LIB_PATH):
     lib.riga_batch_factor.argtypes = [P, P, P]
     lib.riga_batch_eigs.argtypes = [P, C.POINTER(riga_options), P, P, P, P]
     lib.riga_batch_stats.argtypes = [P, C.POINTER(riga_stats_t), C.POINTER(C.c_int)]
+    lib.riga_autotune.argtypes = [P, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.riga_batch_autotune.argtypes = [P, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.riga_sweep_shapes.argtypes = [P, P, P, C.POINTER(C.c_int)]
     lib.riga_batch_destroy.argtypes = [P]
     lib.riga_batch_destroy.restype = None
     for name in EXPORTS:
@@ -272,6 +276,23 @@ class Problem:
                                      g_h.ctypes.data_as(C.c_void_p), _ptr(grad)), "riga_adjoint")
         return grad
 
+    def autotune(self, nrhs: int = 2, reps: int = 5):
+        """Choose the sweep tile shape of every tree level (riga_autotune);
+        returns (ms per solve before, after)."""
+        b, a = C.c_double(0), C.c_double(0)
+        _check(self.lib.riga_autotune(self.h, nrhs, reps, C.byref(b), C.byref(a)), "riga_autotune")
+        return b.value, a.value
+
+    def sweep_shapes(self):
+        """(forward, backward) shape index per tree level."""
+        n = int(self.info["height"])
+        f = np.zeros(n, dtype=np.int32)
+        bw = np.zeros(n, dtype=np.int32)
+        lv = C.c_int(0)
+        _check(self.lib.riga_sweep_shapes(self.h, f.ctypes.data_as(C.c_void_p), bw.ctypes.data_as(C.c_void_p),
+                                          C.byref(lv)), "riga_sweep_shapes")
+        return f, bw
+
     def stats(self):
         s = riga_stats_t()
         _check(self.lib.riga_stats(self.h, C.byref(s)), "riga_stats")
@@ -365,6 +386,12 @@ class Batch:
                 blk = X[2 * nev * o: 2 * nev * (o + n_i)].view(nev, n_i, 2)
                 Xs.append(torch.view_as_complex(blk))
         return lam, Xs, eta.reshape(self.n, nev), nconv, st
+
+    def autotune(self, nrhs: int = 2, reps: int = 5):
+        """riga_batch_autotune; returns (ms per forest solve before, after)."""
+        b, a = C.c_double(0), C.c_double(0)
+        _check(self.lib.riga_batch_autotune(self.h, nrhs, reps, C.byref(b), C.byref(a)), "riga_batch_autotune")
+        return b.value, a.value
 
     def stats(self):
         s = riga_stats_t()
