@@ -1239,12 +1239,8 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     for (int c0 = 0; c0 < 2 * nw; c0 += 8) {
       int nc = std::min(8, 2 * nw - c0);
       const double* x = h->P + (size_t)c0 * N;
-      riga::launch_spmv(h->ds, N, nc, h->d_M, 1.0, nullptr, 0, nullptr, 0, x, N, h->MP + (size_t)c0 * N, N,
-                        nullptr, 0, 0.0, nullptr, 0, h->st);
-      riga::launch_spmv(h->ds, N, nc, h->d_C, 1.0, nullptr, 0, nullptr, 0, x, N, h->CP + (size_t)c0 * N, N,
-                        nullptr, 0, 0.0, nullptr, 0, h->st);
-      riga::launch_spmv(h->ds, N, nc, h->d_K, 1.0, nullptr, 0, nullptr, 0, x, N, h->KP + (size_t)c0 * N, N,
-                        nullptr, 0, 0.0, nullptr, 0, h->st);
+      riga::launch_spmv3(h->ds, N, nc, h->d_M, h->d_C, h->d_K, x, N, h->MP + (size_t)c0 * N, h->CP + (size_t)c0 * N,
+                         h->KP + (size_t)c0 * N, N, h->st);
     }
     const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, N / 4096));
     riga::launch_pair_forms(N, nw, h->P, h->MP, h->CP, h->KP, N, h->d_part, nsplit, h->st);

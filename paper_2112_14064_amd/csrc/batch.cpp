@@ -529,12 +529,8 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
       for (int c0 = 0; c0 < 2 * nw; c0 += 8) {
         const int nc = std::min(8, 2 * nw - c0);
         const double* x = bh->P + (size_t)c0 * T + o;
-        riga::launch_spmv(bh->hsp[i], Ni, nc, fp->d_M, 1.0, nullptr, 0, nullptr, 0, x, T, bh->MP + (size_t)c0 * T + o,
-                          T, nullptr, 0, 0.0, nullptr, 0, st);
-        riga::launch_spmv(bh->hsp[i], Ni, nc, fp->d_C, 1.0, nullptr, 0, nullptr, 0, x, T, bh->CP + (size_t)c0 * T + o,
-                          T, nullptr, 0, 0.0, nullptr, 0, st);
-        riga::launch_spmv(bh->hsp[i], Ni, nc, fp->d_K, 1.0, nullptr, 0, nullptr, 0, x, T, bh->KP + (size_t)c0 * T + o,
-                          T, nullptr, 0, 0.0, nullptr, 0, st);
+        riga::launch_spmv3(bh->hsp[i], Ni, nc, fp->d_M, fp->d_C, fp->d_K, x, T, bh->MP + (size_t)c0 * T + o,
+                           bh->CP + (size_t)c0 * T + o, bh->KP + (size_t)c0 * T + o, T, st);
       }
       riga::launch_pair_forms(Ni, nw, bh->P + o, bh->MP + o, bh->CP + o, bh->KP + o, T, bh->part + (size_t)i * pst,
                               nsplit, st);

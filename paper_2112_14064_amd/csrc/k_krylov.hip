@@ -89,6 +89,72 @@ void launch_spmv(const DevSpace& s, int64_t ndof, int ncols,
 #undef RIGA_SPMV
 }
 
+// Three products with one pass over X: Y0 = A0 X, Y1 = A1 X, Y2 = A2 X.
+template <int NC>
+__global__ __launch_bounds__(SPMV_THREADS) void k_spmv3(
+    int n, const int* __restrict__ lo, const int* __restrict__ hi, const int64_t* __restrict__ rowptr,
+    int64_t ndof, const double* __restrict__ A0, const double* __restrict__ A1, const double* __restrict__ A2,
+    const double* __restrict__ X, int64_t ldx, double* __restrict__ Y0, double* __restrict__ Y1,
+    double* __restrict__ Y2, int64_t ldy) {
+  const int g = threadIdx.x % SPMV_G;
+  const int64_t r = ((int64_t)blockIdx.x * SPMV_THREADS + threadIdx.x) / SPMV_G;
+  const bool active = r < ndof;
+  double s0[NC], s1[NC], s2[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) { s0[q] = 0.0; s1[q] = 0.0; s2[q] = 0.0; }
+  if (active) {
+    const int i = (int)(r % n), j = (int)(r / n);
+    const int lx = lo[i], wx = hi[i] - lo[i] + 1, ly = lo[j];
+    const int64_t k0 = rowptr[r], len = rowptr[r + 1] - k0;
+    for (int o = g; o < len; o += SPMV_G) {
+      const int64_t col = (int64_t)(ly + o / wx) * n + lx + o % wx;
+      const double v0 = A0[k0 + o], v1 = A1[k0 + o], v2 = A2[k0 + o];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const double xv = X[col + q * ldx];
+        s0[q] += v0 * xv;
+        s1[q] += v1 * xv;
+        s2[q] += v2 * xv;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NC; ++q)
+#pragma unroll
+    for (int off = SPMV_G / 2; off > 0; off >>= 1) {
+      s0[q] += __shfl_xor(s0[q], off, SPMV_G);
+      s1[q] += __shfl_xor(s1[q], off, SPMV_G);
+      s2[q] += __shfl_xor(s2[q], off, SPMV_G);
+    }
+  if (active && g == 0) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      Y0[r + q * ldy] = s0[q];
+      Y1[r + q * ldy] = s1[q];
+      Y2[r + q * ldy] = s2[q];
+    }
+  }
+}
+
+void launch_spmv3(const DevSpace& s, int64_t ndof, int ncols, const double* A0, const double* A1, const double* A2,
+                  const double* X, int64_t ldx, double* Y0, double* Y1, double* Y2, int64_t ldy, hipStream_t st) {
+  int64_t blocks = (ndof * SPMV_G + SPMV_THREADS - 1) / SPMV_THREADS;
+#define RIGA_SPMV3(NC)                                                                              \
+  hipLaunchKernelGGL(k_spmv3<NC>, dim3((unsigned)blocks), dim3(SPMV_THREADS), 0, st, s.n, s.lo, s.hi, \
+                     s.rowptr, ndof, A0, A1, A2, X, ldx, Y0, Y1, Y2, ldy)
+  switch (ncols) {
+    case 1: RIGA_SPMV3(1); break;
+    case 2: RIGA_SPMV3(2); break;
+    case 3: RIGA_SPMV3(3); break;
+    case 4: RIGA_SPMV3(4); break;
+    case 5: RIGA_SPMV3(5); break;
+    case 6: RIGA_SPMV3(6); break;
+    case 7: RIGA_SPMV3(7); break;
+    default: RIGA_SPMV3(8); break;
+  }
+#undef RIGA_SPMV3
+}
+
 // ---------------------------------------------------------------------------
 // Multi-dot products out[c][q] = sum_i Au[i,c] Xu[i,q] + Al[i,c] Xl[i,q]:
 // each block owns a slice of rows, each wave owns a set of columns c and its

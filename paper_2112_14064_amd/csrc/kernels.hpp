@@ -97,6 +97,9 @@ void launch_spmv(const DevSpace& s, int64_t ndof, int ncols,
                  const double* A0, double a0, const double* A1, double a1, const double* A2, double a2,
                  const double* X, int64_t ldx, double* Y, int64_t ldy,
                  const double* Z, int64_t ldz, double bz, double* Y2, int64_t ldy2, hipStream_t st);
+// Y0 = A0 X, Y1 = A1 X, Y2 = A2 X in one pass over X (ncols <= 8, common ld of the Y).
+void launch_spmv3(const DevSpace& s, int64_t ndof, int ncols, const double* A0, const double* A1, const double* A2,
+                  const double* X, int64_t ldx, double* Y0, double* Y1, double* Y2, int64_t ldy, hipStream_t st);
 // out[c*nq + q] = sum_i Au[i,c] Xu[i,q] + Al[i,c] Xl[i,q]  (Al/Xl may be null),
 // c < nc, q < nq <= 4; deterministic two-stage reduction.  partial: >= nblk*nc*nq
 // doubles of scratch, ticket: one zeroed uint32.

@@ -59,68 +59,165 @@ void hessenberg(int n, std::vector<double>& H, std::vector<double>& Q) {
 
 }  // namespace
 
-int schur_complex(int n, const double* A, std::vector<cplx>& T, std::vector<cplx>& Z) {
-  std::vector<double> H(A, A + (size_t)n * n), Q;
-  hessenberg(n, H, Q);
-  T.assign((size_t)n * n, cplx(0.0));
-  Z.assign((size_t)n * n, cplx(0.0));
-  for (size_t k = 0; k < (size_t)n * n; ++k) { T[k] = H[k]; Z[k] = Q[k]; }
-  auto t = [&](int i, int j) -> cplx& { return T[i + (size_t)j * n]; };
-  auto z = [&](int i, int j) -> cplx& { return Z[i + (size_t)j * n]; };
+namespace {
+
+// Householder vector of a 2- or 3-vector: (I - beta v v^T) x = alpha e_1 with
+// v[0] = 1; returns false (identity) for x = 0.
+inline bool house(int m, const double* x, double* v, double& beta) {
+  double nrm = 0.0;
+  for (int i = 0; i < m; ++i) nrm += x[i] * x[i];
+  nrm = std::sqrt(nrm);
+  if (nrm == 0.0) return false;
+  const double alpha = x[0] > 0 ? -nrm : nrm;
+  const double v0 = x[0] - alpha;
+  v[0] = 1.0;
+  double vv = 1.0;
+  for (int i = 1; i < m; ++i) { v[i] = x[i] / v0; vv += v[i] * v[i]; }
+  beta = 2.0 / vv;
+  return true;
+}
+
+// Real Schur form H = Q T Q^T of an upper Hessenberg H by Francis double-shift
+// QR steps with deflation (the implicit double-shift algorithm in the form
+// of Golub and Van Loan, Alg. 7.5.1-7.5.2), accumulating into Q.  T is quasi
+// upper triangular: 1x1 blocks and 2x2 blocks (subdiagonal nonzero).
+int real_schur(int n, std::vector<double>& H, std::vector<double>& Q) {
+  auto h = [&](int i, int j) -> double& { return H[i + (size_t)j * n]; };
+  auto q = [&](int i, int j) -> double& { return Q[i + (size_t)j * n]; };
   const double eps = std::numeric_limits<double>::epsilon();
   double anorm = 0.0;
   for (int j = 0; j < n; ++j)
-    for (int i = 0; i < n; ++i) anorm = std::max(anorm, abs1(t(i, j)));
+    for (int i = 0; i <= std::min(j + 1, n - 1); ++i) anorm = std::max(anorm, std::abs(h(i, j)));
   if (anorm == 0.0) return 0;
-  int hi = n - 1, iter = 0, total = 0;
-  const int maxtotal = 100 * std::max(n, 10);
-  while (hi > 0) {
-    int l = hi;
+  int i = n - 1, its = 0, total = 0;
+  const int maxtotal = 60 * std::max(n, 10);
+  while (i >= 0) {
+    // deflation point: the last negligible subdiagonal entry above row i
+    int l = i;
     while (l > 0) {
-      double s = abs1(t(l - 1, l - 1)) + abs1(t(l, l));
-      if (s == 0.0) s = anorm;
-      if (abs1(t(l, l - 1)) <= eps * s) { t(l, l - 1) = 0.0; break; }
+      double sc = std::abs(h(l - 1, l - 1)) + std::abs(h(l, l));
+      if (sc == 0.0) sc = anorm;
+      if (std::abs(h(l, l - 1)) <= eps * sc) { h(l, l - 1) = 0.0; break; }
       --l;
     }
-    if (l == hi) { --hi; iter = 0; continue; }
+    if (l == i) { --i; its = 0; continue; }          // 1x1 block
+    if (l == i - 1) { i -= 2; its = 0; continue; }   // 2x2 block
     if (++total > maxtotal) return -1;
-    ++iter;
-    cplx mu;
-    if (iter % 11 == 10) {
-      // exceptional shift to break a possible cycle
-      mu = t(hi, hi) + 0.75 * std::abs(t(hi, hi - 1).real()) + cplx(0.0, 0.43 * std::abs(t(hi, hi - 1)));
+    ++its;
+    // shifts: eigenvalues of the trailing 2x2 block (trace s, determinant t),
+    // replaced by ad hoc values at iterations 10 and 20 to break cycles
+    double sh, th;
+    if (its == 10 || its == 20) {
+      const double w = std::abs(h(i, i - 1)) + std::abs(h(i - 1, i - 2));
+      sh = 1.5 * w;
+      th = w * w;
     } else {
-      cplx a = t(hi - 1, hi - 1), b = t(hi - 1, hi), c = t(hi, hi - 1), d = t(hi, hi);
-      cplx half = 0.5 * (a - d);
-      cplx disc = std::sqrt(half * half + b * c);
-      cplx m1 = d - (b * c) / (half + disc), m2 = d - (b * c) / (half - disc);
-      if (half + disc == cplx(0.0)) m1 = d;
-      if (half - disc == cplx(0.0)) m2 = d;
-      mu = (std::abs(m1 - d) < std::abs(m2 - d)) ? m1 : m2;
+      sh = h(i - 1, i - 1) + h(i, i);
+      th = h(i - 1, i - 1) * h(i, i) - h(i - 1, i) * h(i, i - 1);
     }
-    cplx x = t(l, l) - mu, y = t(l + 1, l);
-    for (int k = l; k < hi; ++k) {
-      if (k > l) { x = t(k, k - 1); y = t(k + 1, k - 1); }
-      double c; cplx s;
-      givens(x, y, c, s);
-      for (int j = (k > l ? k - 1 : l); j < n; ++j) {
-        cplx t1 = t(k, j), t2 = t(k + 1, j);
-        t(k, j) = c * t1 + s * t2;
-        t(k + 1, j) = -std::conj(s) * t1 + c * t2;
+    // first column of (H - s1)(H - s2) on the active block [l, i]
+    double x[3];
+    x[0] = h(l, l) * h(l, l) + h(l, l + 1) * h(l + 1, l) - sh * h(l, l) + th;
+    x[1] = h(l + 1, l) * (h(l, l) + h(l + 1, l + 1) - sh);
+    x[2] = h(l + 1, l) * h(l + 2, l + 1);
+    const int nw = i - l + 1;
+    double v[3], beta;
+    for (int k = 0; k <= nw - 3; ++k) {
+      const int r0 = l + k;
+      if (house(3, x, v, beta)) {
+        const int c0 = (k == 0) ? l : r0 - 1;
+        for (int j = c0; j < n; ++j) {
+          const double sdot = beta * (h(r0, j) + v[1] * h(r0 + 1, j) + v[2] * h(r0 + 2, j));
+          h(r0, j) -= sdot;
+          h(r0 + 1, j) -= sdot * v[1];
+          h(r0 + 2, j) -= sdot * v[2];
+        }
+        const int rmax = std::min(r0 + 3, i);
+        for (int r = 0; r <= rmax; ++r) {
+          const double sdot = beta * (h(r, r0) + v[1] * h(r, r0 + 1) + v[2] * h(r, r0 + 2));
+          h(r, r0) -= sdot;
+          h(r, r0 + 1) -= sdot * v[1];
+          h(r, r0 + 2) -= sdot * v[2];
+        }
+        for (int r = 0; r < n; ++r) {
+          const double sdot = beta * (q(r, r0) + v[1] * q(r, r0 + 1) + v[2] * q(r, r0 + 2));
+          q(r, r0) -= sdot;
+          q(r, r0 + 1) -= sdot * v[1];
+          q(r, r0 + 2) -= sdot * v[2];
+        }
       }
-      if (k > l) t(k + 1, k - 1) = 0.0;
-      const int imax = std::min(k + 2, hi);
-      for (int i = 0; i <= imax; ++i) {
-        cplx t1 = t(i, k), t2 = t(i, k + 1);
-        t(i, k) = c * t1 + std::conj(s) * t2;
-        t(i, k + 1) = -s * t1 + c * t2;
+      if (k > 0) h(r0 + 1, r0 - 1) = h(r0 + 2, r0 - 1) = 0.0;   // the bulge moved on
+      x[0] = h(r0 + 1, r0);
+      x[1] = h(r0 + 2, r0);
+      if (k < nw - 3) x[2] = h(r0 + 3, r0);
+    }
+    // last 2-vector reflection on rows / columns i-1, i
+    if (house(2, x, v, beta)) {
+      for (int j = i - 2; j < n; ++j) {
+        const double sdot = beta * (h(i - 1, j) + v[1] * h(i, j));
+        h(i - 1, j) -= sdot;
+        h(i, j) -= sdot * v[1];
       }
-      for (int i = 0; i < n; ++i) {
-        cplx t1 = z(i, k), t2 = z(i, k + 1);
-        z(i, k) = c * t1 + std::conj(s) * t2;
-        z(i, k + 1) = -s * t1 + c * t2;
+      for (int r = 0; r <= i; ++r) {
+        const double sdot = beta * (h(r, i - 1) + v[1] * h(r, i));
+        h(r, i - 1) -= sdot;
+        h(r, i) -= sdot * v[1];
+      }
+      for (int r = 0; r < n; ++r) {
+        const double sdot = beta * (q(r, i - 1) + v[1] * q(r, i));
+        q(r, i - 1) -= sdot;
+        q(r, i) -= sdot * v[1];
       }
     }
+    h(i, i - 2) = 0.0;
+  }
+  return 0;
+}
+
+}  // namespace
+
+int schur_complex(int n, const double* A, std::vector<cplx>& T, std::vector<cplx>& Z) {
+  std::vector<double> H(A, A + (size_t)n * n), Q;
+  hessenberg(n, H, Q);
+  if (real_schur(n, H, Q) != 0) return -1;
+  T.assign((size_t)n * n, cplx(0.0));
+  Z.assign((size_t)n * n, cplx(0.0));
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i <= std::min(j + 1, n - 1); ++i) T[i + (size_t)j * n] = H[i + (size_t)j * n];
+  for (size_t k = 0; k < (size_t)n * n; ++k) Z[k] = Q[k];
+  auto t = [&](int i, int j) -> cplx& { return T[i + (size_t)j * n]; };
+  auto z = [&](int i, int j) -> cplx& { return Z[i + (size_t)j * n]; };
+  // complex Schur form: triangularise every 2x2 block with the unitary whose
+  // first column is an eigenvector of the block
+  for (int k = 0; k + 1 < n; ++k) {
+    if (t(k + 1, k) == cplx(0.0)) continue;
+    const cplx a = t(k, k), b = t(k, k + 1), c = t(k + 1, k), d = t(k + 1, k + 1);
+    const cplx half = 0.5 * (a - d);
+    const cplx disc = std::sqrt(half * half + b * c);
+    const cplx lam = 0.5 * (a + d) + disc;
+    // eigenvector of [[a, b], [c, d]] for lam: [b; lam - a] or [lam - d; c]
+    cplx v1 = b, v2 = lam - a;
+    if (std::abs(v1) + std::abs(v2) < std::abs(lam - d) + std::abs(c)) { v1 = lam - d; v2 = c; }
+    const double nv = std::sqrt(std::norm(v1) + std::norm(v2));
+    v1 /= nv; v2 /= nv;
+    // G = [v, w] with w = [-conj(v2); conj(v1)]; T <- G^H T G, Z <- Z G
+    for (int j = k; j < n; ++j) {
+      const cplx t1 = t(k, j), t2 = t(k + 1, j);
+      t(k, j) = std::conj(v1) * t1 + std::conj(v2) * t2;
+      t(k + 1, j) = -v2 * t1 + v1 * t2;
+    }
+    for (int r = 0; r <= k + 1; ++r) {
+      const cplx t1 = t(r, k), t2 = t(r, k + 1);
+      t(r, k) = t1 * v1 + t2 * v2;
+      t(r, k + 1) = -t1 * std::conj(v2) + t2 * std::conj(v1);
+    }
+    for (int r = 0; r < n; ++r) {
+      const cplx t1 = z(r, k), t2 = z(r, k + 1);
+      z(r, k) = t1 * v1 + t2 * v2;
+      z(r, k + 1) = -t1 * std::conj(v2) + t2 * std::conj(v1);
+    }
+    t(k + 1, k) = 0.0;
+    ++k;   // the next block starts after this one
   }
   for (int j = 0; j < n; ++j)
     for (int i = j + 1; i < n; ++i) t(i, j) = 0.0;

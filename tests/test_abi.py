@@ -63,3 +63,48 @@ def test_small_dense_eigensolver_semisimple_multiple():
     w, res = riga.riga_selftest_small_eig(a)
     assert res < 1e-13
     assert np.allclose(np.sort(w.real), d, atol=1e-12)
+
+
+def _rotation_blocks(rng, pairs, reals):
+    """Block diagonal with 2x2 rotation-scaling blocks (complex pairs a +- ib)
+    and 1x1 real entries, under a random orthogonal similarity."""
+    n = 2 * len(pairs) + len(reals)
+    D = np.zeros((n, n))
+    k = 0
+    for a, b in pairs:
+        D[k:k + 2, k:k + 2] = [[a, b], [-b, a]]
+        k += 2
+    for r in reals:
+        D[k, k] = r
+        k += 1
+    Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    ev = np.concatenate([[a + 1j * b for a, b in pairs], [a - 1j * b for a, b in pairs], reals])
+    return Q @ D @ Q.T, ev
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_small_dense_eigensolver_complex_pairs(seed):
+    """Known complex-conjugate pairs and real eigenvalues (the structure of the
+    shift-and-invert QEP spectrum): every eigenvalue recovered."""
+    rng = np.random.default_rng(seed)
+    pairs = [(rng.uniform(-1, 1), rng.uniform(0.1, 3)) for _ in range(30)]
+    reals = list(rng.uniform(-2, 2, 20))
+    a, ev = _rotation_blocks(rng, pairs, reals)
+    w, res = riga.riga_selftest_small_eig(a)
+    assert res < 1e-12
+    for x in ev:
+        assert np.min(np.abs(w - x)) < 1e-11
+
+
+def test_small_dense_eigensolver_large_and_triangular():
+    rng = np.random.default_rng(9)
+    a = rng.standard_normal((128, 128))
+    w, res = riga.riga_selftest_small_eig(a)
+    ref = np.linalg.eigvals(a)
+    assert res < 1e-12
+    for x in ref:
+        assert np.min(np.abs(w - x)) < 1e-10 * np.abs(ref).max()
+    t = np.triu(rng.standard_normal((40, 40)))      # already in Schur form
+    w, res = riga.riga_selftest_small_eig(t)
+    assert res < 1e-12
+    assert np.allclose(np.sort(w.real), np.sort(np.diag(t)), atol=1e-12) and np.abs(w.imag).max() == 0.0
