@@ -24,8 +24,9 @@ int ks_ritz(const std::vector<double>& H, int ldh, int k, int b, int nev, double
                         1e-9 * std::abs(c.theta[c.ord[pos - 1]]))
     ++pos;
   c.nw = pos;
-  // Ritz vectors and residual estimates ||E y|| (E = rows k..k+b of H)
-  schur_eigvecs(k, c.T, c.Z, c.Y, 1e-11);
+  c.wanted.assign(c.ord.begin(), c.ord.begin() + c.nw);
+  // Ritz vectors of the wanted values and residual estimates ||E y|| (E = rows k..k+b of H)
+  schur_eigvecs(k, c.T, c.Z, c.Y, 1e-11, &c.wanted);
   c.nconv = 0;
   for (int p = 0; p < c.nw; ++p) {
     const int i = c.ord[p];
@@ -37,7 +38,6 @@ int ks_ritz(const std::vector<double>& H, int ldh, int k, int b, int nev, double
     }
     if (std::sqrt(s) <= tol * std::abs(c.theta[i])) ++c.nconv;
   }
-  c.wanted.assign(c.ord.begin(), c.ord.begin() + c.nw);
   return 0;
 }
 
@@ -57,9 +57,10 @@ void ks_restart(const std::vector<double>& H, int ldh, int k, int b, int m, int 
   } else {  // step back to a cluster boundary
     while (kk > 1 && same(kk)) --kk;
   }
-  std::vector<int> keep(c.ord.begin(), c.ord.begin() + kk);
+  std::vector<char> keep(k, 0);
+  for (int p = 0; p < kk; ++p) keep[c.ord[p]] = 1;
   std::vector<cplx> T = c.T, Z = c.Z;
-  schur_reorder(k, T, Z, keep);
+  schur_select(k, T, Z, keep);
   std::vector<double> Qk;
   const int r = realify(k, kk, Z, Qk);
   std::vector<double> Hk((size_t)k * k);

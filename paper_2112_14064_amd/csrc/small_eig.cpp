@@ -272,8 +272,22 @@ void schur_reorder(int n, std::vector<cplx>& T, std::vector<cplx>& Z, const std:
   }
 }
 
+void schur_select(int n, std::vector<cplx>& T, std::vector<cplx>& Z, const std::vector<char>& keep) {
+  // walk up from the bottom; every entry not kept sinks to the end of the kept block
+  std::vector<char> kp(keep);
+  int end = n;
+  for (int i = n - 1; i >= 0; --i) {
+    if (kp[i]) continue;
+    for (int k = i; k < end - 1; ++k) {
+      swap_adjacent(n, T, Z, k);
+      std::swap(kp[k], kp[k + 1]);
+    }
+    --end;
+  }
+}
+
 void schur_eigvecs(int n, const std::vector<cplx>& T, const std::vector<cplx>& Z,
-                   std::vector<cplx>& Y, double cluster_tol) {
+                   std::vector<cplx>& Y, double cluster_tol, const std::vector<int>* which) {
   auto t = [&](int i, int j) { return T[i + (size_t)j * n]; };
   double scale = 0.0;
   for (int i = 0; i < n; ++i) scale = std::max(scale, std::abs(t(i, i)));
@@ -281,7 +295,9 @@ void schur_eigvecs(int n, const std::vector<cplx>& T, const std::vector<cplx>& Z
   const double tiny = std::numeric_limits<double>::min() / std::numeric_limits<double>::epsilon();
   Y.assign((size_t)n * n, cplx(0.0));
   std::vector<cplx> x(n);
-  for (int k = 0; k < n; ++k) {
+  const int nk = which ? (int)which->size() : n;
+  for (int kk = 0; kk < nk; ++kk) {
+    const int k = which ? (*which)[kk] : kk;
     const cplx lam = t(k, k);
     std::fill(x.begin(), x.end(), cplx(0.0));
     x[k] = 1.0;

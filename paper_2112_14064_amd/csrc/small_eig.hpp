@@ -24,8 +24,15 @@ void schur_reorder(int n, std::vector<cplx>& T, std::vector<cplx>& Z, const std:
 // largest |T_ii|) are treated as one multiple eigenvalue whose eigenvectors
 // are taken from the Schur basis (the coupling of a semisimple multiple
 // eigenvalue vanishes in exact arithmetic).
+// Only the columns listed in `which` are computed when it is not null (the
+// others are left zero).
 void schur_eigvecs(int n, const std::vector<cplx>& T, const std::vector<cplx>& Z,
-                   std::vector<cplx>& Y, double cluster_tol);
+                   std::vector<cplx>& Y, double cluster_tol, const std::vector<int>* which = nullptr);
+
+// Reorder the Schur form so that the diagonal entries with keep[i] != 0 come
+// first (their relative order kept) with the fewest adjacent exchanges: each
+// entry not kept moves down past the kept ones below it.
+void schur_select(int n, std::vector<cplx>& T, std::vector<cplx>& Z, const std::vector<char>& keep);
 
 // Real orthonormal basis Q (n x r, column-major) of span{Re z, Im z} over the
 // first k columns of Z (n x n).  When those columns span a subspace closed
