@@ -72,6 +72,26 @@ def run_config(torch, riga, P, steps, warmup, block):
     return pr, res, lam
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_sweeps_p3_256x256_s16.json")
+
+
+def measured_traffic(kernel, block):
+    """HBM bytes per launch of a sweep kernel from the committed counter record
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the sweep source has
+    changed since the counters were taken or the launch shape differs."""
+    import hashlib
+
+    try:
+        rec = json.load(open(TRAFFIC_RECORD))
+        src = os.path.join(ROOT, rec["source"])
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError, KeyError):
+        return None
+    if sha != rec.get("source_sha256") or block != 2:
+        return None
+    return rec.get("bytes_per_launch", {}).get(kernel)
+
+
 def roofline(pr, res, block):
     """Roofline of the kernel family with the most time in one step, timed live
     with HIP events on the solver's stream (average duration of one launch)."""
@@ -92,7 +112,7 @@ def roofline(pr, res, block):
         achieved = work / (ms * 1e-3) / 1e9
         out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                "frac": achieved / HBM_PEAK_GBS}
-    out.update({"traffic": None, "kernel": name, "avg_launch_us": ms * 1e3,
+    out.update({"traffic": measured_traffic(name, block), "kernel": name, "avg_launch_us": ms * 1e3,
                 "work_per_launch": work,
                 "step_ms_by_kernel": {k: v[2] for k, v in fam.items()}})
     return out
