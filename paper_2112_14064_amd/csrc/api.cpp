@@ -156,13 +156,13 @@ void solve_levels(riga_problem* h, int nrhs, const double* b, int64_t ldb, doubl
 }
 
 // S v for a block of `nb` vectors (eq. BlockOperatorVector):
-//   t = sigma M v_u + C v_u + (M v_l),   r_u = -Q^{-1} t,   r_l = sigma r_u + v_u,
-// with M v_l supplied (Wl) and M v_u returned in Mvu.
+//   t = (sigma M + C) v_u + (M v_l),   r_u = -Q^{-1} t,   r_l = sigma r_u + v_u,
+// with M v_l supplied (Wl) and sigma M + C formed at factor time.
 void apply_block(riga_problem* h, int nb, const double* vu, const double* wl, int64_t ld,
-                 double* ru, double* rl, double* t, double* mvu) {
+                 double* ru, double* rl, double* t) {
   const int64_t N = h->N();
-  riga::launch_spmv(h->ds, N, nb, h->d_M, h->sigma, h->d_C, 1.0, nullptr, 0.0, vu, ld, t, N, wl, ld,
-                    1.0, mvu, N, h->st);
+  riga::launch_spmv(h->ds, N, nb, h->d_A, 1.0, nullptr, 0.0, nullptr, 0.0, vu, ld, t, N, wl, ld, 1.0, nullptr, 0,
+                    h->st);
   solve_levels(h, nb, t, N, ru, N, rl, vu, ld, h->sigma);
 }
 
@@ -185,7 +185,7 @@ void ensure_norms(riga_problem* h) {
 void ensure_krylov(riga_problem* h, int cols, int b) {
   if (h->kw_cols >= cols && h->kw_b >= b) return;
   h->clear_graphs();
-  for (double* p : {h->Vu, h->Vl, h->Wl, h->Vu2, h->Vl2, h->Wl2, h->Ru, h->Rl, h->MRl, h->Tv, h->Mvu,
+  for (double* p : {h->Vu, h->Vl, h->Wl, h->Vu2, h->Vl2, h->Wl2, h->Ru, h->Rl, h->MRl, h->Tv,
                     h->d_small, h->d_H})
     h->dfree(p);
   const int64_t N = h->N();
@@ -194,7 +194,7 @@ void ensure_krylov(riga_problem* h, int cols, int b) {
   h->Vu = h->dalloc<double>(N * cols); h->Vl = h->dalloc<double>(N * cols); h->Wl = h->dalloc<double>(N * cols);
   h->Vu2 = h->dalloc<double>(N * cols); h->Vl2 = h->dalloc<double>(N * cols); h->Wl2 = h->dalloc<double>(N * cols);
   h->Ru = h->dalloc<double>(N * b); h->Rl = h->dalloc<double>(N * b); h->MRl = h->dalloc<double>(N * b);
-  h->Tv = h->dalloc<double>(N * b); h->Mvu = h->dalloc<double>(N * b);
+  h->Tv = h->dalloc<double>(N * b);
   h->d_small = h->dalloc<double>((size_t)4 * cols * cols + 64);
   h->d_H = h->dalloc<double>((size_t)cols * cols);
   if (!h->d_flag) h->d_flag = h->dalloc<int>(4);
@@ -269,6 +269,7 @@ void setup_device(riga_problem* h) {
     h->d_tabM = h->dalloc<double>((size_t)S.ne * np * np);
     h->d_tabK = h->dalloc<double>((size_t)S.ne * np * np);
     h->d_K = h->dalloc<double>(P.nnz); h->d_M = h->dalloc<double>(P.nnz); h->d_C = h->dalloc<double>(P.nnz);
+    h->d_A = h->dalloc<double>(P.nnz);
     h->d_L = h->dalloc<double>(P.lsize); h->d_U = h->dalloc<double>(P.usize);
     h->d_T = h->dalloc<double>(P.lsize);
     {
@@ -477,7 +478,9 @@ riga_status factor_all(riga_problem* h, double sigma, int64_t* bad_pivot) {
   ck(hipMemsetAsync(h->d_status, 0xFF, sizeof(int64_t), h->st));
   ck(hipEventRecord(h->ev0, h->st));
   for (int lv = 0; lv < P.height; ++lv) factor_level(h, lv, sigma);
-  if (h->mixed) riga::launch_combine_q(P.nnz, sigma * sigma, sigma, h->d_K, h->d_M, h->d_C, h->d_Q, h->st);
+  // sigma M + C for the operator, Q(sigma) for the residuals of the mixed factor
+  riga::launch_combine3(P.nnz, sigma, h->d_M, 1.0, h->d_C, 0.0, h->d_K, h->d_A, h->st);
+  if (h->mixed) riga::launch_combine3(P.nnz, sigma * sigma, h->d_M, sigma, h->d_C, 1.0, h->d_K, h->d_Q, h->st);
   ck(hipGetLastError());
   ck(hipEventRecord(h->ev1, h->st));
   int64_t stat = -1;
@@ -737,7 +740,7 @@ riga_status riga_apply_op(riga_problem* h, int nvec, const double* v, double* r)
     double* t = r + N;  // r_l doubles as scratch for t until the backward sweep writes it
     double* mvu = h->d_upd;  // unused here; Y2 not requested
     (void)mvu;
-    riga::launch_spmv(h->ds, N, nvec, h->d_M, h->sigma, h->d_C, 1.0, nullptr, 0.0, v, 2 * N, t, 2 * N,
+    riga::launch_spmv(h->ds, N, nvec, h->d_A, 1.0, nullptr, 0.0, nullptr, 0.0, v, 2 * N, t, 2 * N,
                       h->d_tmp2, N, 1.0, nullptr, 0, h->st);
     solve_levels(h, nvec, t, 2 * N, r, 2 * N, r + N, v, 2 * N, h->sigma);
     ck(hipGetLastError());
@@ -1042,10 +1045,9 @@ struct KrylovRun {
   void enqueue_step_device() {
     const int64_t n = N;
     const size_t o = (size_t)k * n;
-    apply_block(h, b, h->Vu + o, h->Wl + o, n, h->Ru, h->Rl, h->Tv, h->Mvu);
-    // M r_l = sigma M r_u + M v_u
-    riga::launch_spmv(h->ds, n, b, h->d_M, h->sigma, nullptr, 0, nullptr, 0, h->Ru, n, h->MRl, n, h->Mvu, n,
-                      1.0, nullptr, 0, h->st);
+    apply_block(h, b, h->Vu + o, h->Wl + o, n, h->Ru, h->Rl, h->Tv);
+    riga::launch_spmv(h->ds, n, b, h->d_M, 1.0, nullptr, 0, nullptr, 0, h->Rl, n, h->MRl, n, nullptr, 0, 0.0,
+                      nullptr, 0, h->st);
     orthonormalize_device(k + b, h->d_H, k);
   }
 
@@ -1078,10 +1080,9 @@ struct KrylovRun {
       k += b;
       return;
     }
-    apply_block(h, b, h->Vu + o, h->Wl + o, n, h->Ru, h->Rl, h->Tv, h->Mvu);
-    // M r_l = sigma M r_u + M v_u
-    riga::launch_spmv(h->ds, n, b, h->d_M, h->sigma, nullptr, 0, nullptr, 0, h->Ru, n, h->MRl, n, h->Mvu, n,
-                      1.0, nullptr, 0, h->st);
+    apply_block(h, b, h->Vu + o, h->Wl + o, n, h->Ru, h->Rl, h->Tv);
+    riga::launch_spmv(h->ds, n, b, h->d_M, 1.0, nullptr, 0, nullptr, 0, h->Rl, n, h->MRl, n, nullptr, 0, 0.0,
+                      nullptr, 0, h->st);
     n_fb += b;
     n_mv += 3LL * b;
     {

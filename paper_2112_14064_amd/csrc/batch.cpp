@@ -29,6 +29,7 @@ struct riga_batch {
   std::vector<riga::Plan> plans;
   riga_problem* fp = nullptr;            // the forest: CSR values, factor, sweep tasks
   std::vector<int64_t> dof_base;         // n + 1
+  const int64_t* d_nzbase = nullptr;     // per problem: first nonzero of its rows (n + 1)
   std::vector<int> node_base;            // n + 1
   std::vector<riga::DevSpace> hsp;       // per problem (device pointers)
   std::vector<double*> tabM, tabK, gx, gw;
@@ -40,7 +41,7 @@ struct riga_batch {
   // Krylov workspace
   int kw_ldh = 0, kw_b = 0;
   double *Vu = nullptr, *Vl = nullptr, *Wl = nullptr, *Vu2 = nullptr, *Vl2 = nullptr, *Wl2 = nullptr;
-  double *Ru = nullptr, *Rl = nullptr, *MRl = nullptr, *Tv = nullptr, *Mvu = nullptr, *Xu = nullptr, *Xw = nullptr;
+  double *Ru = nullptr, *Rl = nullptr, *MRl = nullptr, *Tv = nullptr, *Xu = nullptr, *Xw = nullptr;
   double *h1 = nullptr, *h2 = nullptr, *G = nullptr, *Rinv = nullptr, *H = nullptr, *Qd = nullptr;
   double *P = nullptr, *MP = nullptr, *CP = nullptr, *KP = nullptr, *part = nullptr, *dlam = nullptr;
   int *kin = nullptr, *kout = nullptr;
@@ -81,7 +82,7 @@ void ensure_workspace(riga_batch* bh, int ldh, int b) {
   if (bh->kw_ldh >= ldh && bh->kw_b >= b) return;
   riga_problem* fp = bh->fp;
   bh->clear_graphs();
-  for (double* p : {bh->Vu, bh->Vl, bh->Wl, bh->Vu2, bh->Vl2, bh->Wl2, bh->Ru, bh->Rl, bh->MRl, bh->Tv, bh->Mvu,
+  for (double* p : {bh->Vu, bh->Vl, bh->Wl, bh->Vu2, bh->Vl2, bh->Wl2, bh->Ru, bh->Rl, bh->MRl, bh->Tv,
                     bh->Xu, bh->Xw, bh->h1, bh->h2, bh->G, bh->Rinv, bh->H, bh->Qd, bh->P, bh->MP, bh->CP, bh->KP,
                     bh->part, bh->dlam, bh->B.partial})
     fp->dfree(p);
@@ -93,7 +94,7 @@ void ensure_workspace(riga_batch* bh, int ldh, int b) {
   bh->Vu = fp->dalloc<double>(T * ldh); bh->Vl = fp->dalloc<double>(T * ldh); bh->Wl = fp->dalloc<double>(T * ldh);
   bh->Vu2 = fp->dalloc<double>(T * ldh); bh->Vl2 = fp->dalloc<double>(T * ldh);
   bh->Wl2 = fp->dalloc<double>(T * ldh);
-  for (double** p : {&bh->Ru, &bh->Rl, &bh->MRl, &bh->Tv, &bh->Mvu, &bh->Xu, &bh->Xw}) *p = fp->dalloc<double>(T * b);
+  for (double** p : {&bh->Ru, &bh->Rl, &bh->MRl, &bh->Tv, &bh->Xu, &bh->Xw}) *p = fp->dalloc<double>(T * b);
   bh->h1 = fp->dalloc<double>((size_t)n * ldh * b);
   bh->h2 = fp->dalloc<double>((size_t)n * ldh * b);
   bh->G = fp->dalloc<double>((size_t)n * b * b);
@@ -119,15 +120,14 @@ void enqueue_step(riga_batch* bh, int b, int m, int ldh, hipStream_t st) {
   const int64_t T = B.ntot;
   const int hs = ldh * b;
   riga::launch_gather_b(B, b, bh->Vu, bh->Wl, bh->Xu, bh->Xw, st);
-  // t = sigma M v_u + C v_u + M v_l, M v_u kept (eq. BlockOperatorVector)
-  riga::launch_spmv_b(B, b, fp->d_M, 1.0, 1, fp->d_C, 1.0, bh->Xu, T, bh->Tv, T, bh->Xw, T, 1.0, bh->Mvu, T, st);
+  // t = (sigma M + C) v_u + M v_l (eq. BlockOperatorVector), sigma M + C formed per problem
+  riga::launch_spmv_b(B, b, fp->d_A, 1.0, 0, nullptr, 0.0, bh->Xu, T, bh->Tv, T, bh->Xw, T, 1.0, nullptr, 0, st);
   // r_u = -Q^{-1} t, r_l = sigma r_u + v_u (sigma of each node's problem)
   riga::BwdOut o;
   o.xs = bh->Ru; o.ldxs = T; o.neg = 1; o.ldr = T;
   o.rl = bh->Rl; o.v_u = bh->Xu; o.ldv = T;
   sweep(fp, b, bh->Tv, T, o);
-  // M r_l = sigma M r_u + M v_u
-  riga::launch_spmv_b(B, b, fp->d_M, 1.0, 1, nullptr, 0.0, bh->Ru, T, bh->MRl, T, bh->Mvu, T, 1.0, nullptr, 0, st);
+  riga::launch_spmv_b(B, b, fp->d_M, 1.0, 0, nullptr, 0.0, bh->Rl, T, bh->MRl, T, nullptr, 0, 0.0, nullptr, 0, st);
   // classical Gram--Schmidt twice against V[:, 0:k+b], B-inner products
   riga::launch_dots_b(B, b, 0, true, bh->Vu, bh->Wl, b, bh->Ru, bh->Rl, bh->h1, hs, st);
   riga::launch_cgs_update_b(B, b, b, bh->h1, hs, bh->Vu, bh->Ru, bh->Vl, bh->Rl, bh->Wl, bh->MRl, m + b, st);
@@ -249,6 +249,9 @@ riga_status riga_batch_create(riga_batch** out, int n, const riga_mesh* meshes, 
     B.db = fp->upload(db);
     B.ndb = (int)db.size();
     B.dboff = fp->upload(dboff);
+    std::vector<int64_t> nzb(n + 1);
+    for (int i = 0; i <= n; ++i) nzb[i] = fp->plan.rowptr[bh->dof_base[i]];
+    bh->d_nzbase = fp->upload(nzb);
     fp->dt.inst = fp->upload(inst);
     fp->dt.spaces = B.spaces;
     fp->dt.dofbase = B.dofbase;
@@ -338,6 +341,7 @@ riga_status riga_batch_factor(riga_batch* bh, const double* sigmas, int64_t* bad
     fp->dt.ilive = nullptr;
     int64_t bad = -1;
     riga_status rc = factor_all(fp, 1.0, &bad);
+    riga::launch_combine_b(bh->n, bh->d_nzbase, fp->plan.nnz, bh->B.sig, fp->d_M, fp->d_C, fp->d_A, bh->user_st);
     bh->stats.t_factor_ms = fp->stats.t_factor_ms;
     if (rc == RIGA_ERR_NOT_SPD && bad >= 0) {
       const int i = (int)(std::upper_bound(bh->dof_base.begin(), bh->dof_base.end(), bad) - bh->dof_base.begin()) - 1;

@@ -93,6 +93,28 @@ void launch_spmv_b(const BatchDev& B, int ncols, const double* A0, double a0, in
 #undef RIGA_SPMVB
 }
 
+// A = sigma_p M + C on every problem's rows (nonzero ranges nzbase[p] .. nzbase[p+1]).
+__global__ __launch_bounds__(BT) void k_combine_b(int n, const int64_t* __restrict__ nzbase,
+                                                  const double* __restrict__ sig, const double* __restrict__ M,
+                                                  const double* __restrict__ C, double* __restrict__ A) {
+  const int64_t nnz = nzbase[n];
+  for (int64_t k = (int64_t)blockIdx.x * BT + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * BT) {
+    int a = 0, b = n;   // nzbase[a] <= k < nzbase[b]
+    while (b - a > 1) {
+      const int c = (a + b) >> 1;
+      if (nzbase[c] <= k) a = c; else b = c;
+    }
+    A[k] = sig[a] * M[k] + C[k];
+  }
+}
+
+void launch_combine_b(int n, const int64_t* nzbase, int64_t nnz, const double* sig, const double* M, const double* C,
+                      double* A, hipStream_t st) {
+  const int64_t blocks = std::min<int64_t>((nnz + BT - 1) / BT, 8192);
+  hipLaunchKernelGGL(k_combine_b, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(BT), 0, st, n, nzbase, sig, M, C,
+                     A);
+}
+
 // Xu[:, q] = Vu[:, k + q], Xw[:, q] = Wl[:, k + q] with k the problem's current column.
 __global__ __launch_bounds__(BT) void k_gather_b(const int4* __restrict__ rb, const int* __restrict__ kcur,
                                                  const unsigned char* __restrict__ live, int nq,

@@ -176,7 +176,11 @@ __global__ __launch_bounds__(FT) void k_front_extend(DevTree t, const int* __res
 
 // ---------------------------------------------------------------------------------
 // Cholesky of the diagonal block [k0, k0+w) and D = its inverse (lower), stored
-// at D + (doff[v] + k0/64) * 4096 as D[r * 64 + c].
+// at D + (doff[v] + k0/64) * 4096 as D[r * 64 + c].  One wave does both in LDS,
+// lane = row for the factorisation (left-looking: column c of every row from
+// the finished columns, the pivot taken from lane c) and lane = column for the
+// inverse (forward substitution row by row); the wave's LDS accesses are in
+// program order, so no workgroup barrier is needed between the columns.
 template <class E>
 __global__ __launch_bounds__(FT) void k_potrf_diag(DevTree t, const int* __restrict__ level_nodes, int k0,
                                                    E* __restrict__ Lbuf, E* __restrict__ Ubuf,
@@ -189,44 +193,39 @@ __global__ __launch_bounds__(FT) void k_potrf_diag(DevTree t, const int* __restr
   const int tid = threadIdx.x;
   __shared__ E S[TB][LDT];
   __shared__ E Dl[TB][LDT];
-  __shared__ E piv_s;
   for (int idx = tid; idx < TB * TB; idx += FT) {
     const int r = idx % TB, c = idx / TB;       // coalesced along the column
     S[r][c] = (r < w && c <= r) ? F.L[(int64_t)(k0 + c) * F.nf + k0 + r] : E(0);
+    Dl[r][c] = E(0);
   }
   __syncthreads();
-  for (int c = 0; c < w; ++c) {
-    if (tid == 0) {
-      double piv = (double)S[c][c];
+  if (tid < TB) {
+    const int r = tid;
+    for (int c = 0; c < w; ++c) {
+      E acc = S[r][c];
+      for (int k = 0; k < c; ++k) acc -= S[r][k] * S[c][k];
+      double piv = (double)__shfl(acc, c, 64);
       if (!(piv > 0.0)) {           // not SPD (or NaN): record, continue with 1
-        atomicCAS((unsigned long long*)status, (unsigned long long)(-1ll),
-                  (unsigned long long)t.fdofs[t.foff[v] + k0 + c]);
+        if (r == c)
+          atomicCAS((unsigned long long*)status, (unsigned long long)(-1ll),
+                    (unsigned long long)t.fdofs[t.foff[v] + k0 + c]);
         piv = 1.0;
       }
-      piv_s = (E)sqrt(piv);
-      S[c][c] = piv_s;
+      const E d = (E)sqrt(piv);
+      if (r == c) S[c][c] = d;
+      else if (r > c && r < w) S[r][c] = acc / d;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    __syncthreads();
-    const E inv = E(1) / piv_s;
-    for (int r = c + 1 + tid; r < w; r += FT) S[r][c] *= inv;
-    __syncthreads();
-    const int m = w - c - 1;   // trailing order
-    for (int idx = tid; idx < m * m; idx += FT) {
-      const int r = c + 1 + idx / m, cc = c + 1 + idx % m;
-      if (cc <= r) S[r][cc] -= S[r][c] * S[cc][c];
-    }
-    __syncthreads();
-  }
-  // inverse of the lower-triangular block, one column per thread
-  if (tid < TB) {
+    // inverse of the lower-triangular block, lane = column
     const int c = tid;
-    for (int r = 0; r < TB; ++r) Dl[r][c] = E(0);
     if (c < w) {
       Dl[c][c] = E(1) / S[c][c];
-      for (int r = c + 1; r < w; ++r) {
+      for (int rr = c + 1; rr < w; ++rr) {
         E sacc = E(0);
-        for (int k = c; k < r; ++k) sacc += S[r][k] * Dl[k][c];
-        Dl[r][c] = -sacc / S[r][r];
+        for (int k = c; k < rr; ++k) sacc += S[rr][k] * Dl[k][c];
+        Dl[rr][c] = -sacc / S[rr][rr];
       }
     }
   }

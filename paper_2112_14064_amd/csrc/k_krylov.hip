@@ -492,20 +492,20 @@ void launch_rowabs(const int64_t* rowptr, int64_t ndof, const double* A, double*
   hipLaunchKernelGGL(k_rowabs, dim3(nblk), dim3(256), 0, st, rowptr, ndof, A, part);
 }
 
-// Values of Q = s2 M + s1 C + K on the common CSR pattern, for the FP64
-// residuals of the refined mixed-precision solves.
-__global__ __launch_bounds__(256) void k_combine_q(int64_t nnz, double s2, double s1, const double* __restrict__ K,
-                                                   const double* __restrict__ M, const double* __restrict__ C,
-                                                   double* __restrict__ Q) {
+// Out = am M + ac C + ak K on the common CSR pattern: Q(sigma) for the FP64
+// residuals of the refined mixed-precision solves, sigma M + C for the operator.
+__global__ __launch_bounds__(256) void k_combine3(int64_t nnz, double am, const double* __restrict__ M, double ac,
+                                                  const double* __restrict__ C, double ak,
+                                                  const double* __restrict__ K, double* __restrict__ Out) {
   for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * 256)
-    Q[k] = s2 * M[k] + s1 * C[k] + K[k];
+    Out[k] = am * M[k] + ac * C[k] + ak * K[k];
 }
 
-void launch_combine_q(int64_t nnz, double s2, double s1, const double* K, const double* M, const double* C,
-                      double* Q, hipStream_t st) {
+void launch_combine3(int64_t nnz, double am, const double* M, double ac, const double* C, double ak,
+                     const double* K, double* Out, hipStream_t st) {
   const int64_t blocks = std::min<int64_t>((nnz + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_combine_q, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, nnz, s2, s1, K,
-                     M, C, Q);
+  hipLaunchKernelGGL(k_combine3, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, nnz, am, M, ac, C,
+                     ak, K, Out);
 }
 
 // ---------------------------------------------------------------------------

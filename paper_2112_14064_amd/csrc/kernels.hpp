@@ -63,9 +63,9 @@ void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_n
                          int max_nf, int max_child_nb, double s2, double s1, const double* K, const double* M,
                          const double* C, float* L, float* U, float* T, float* D, float* Lp, float* Tp,
                          int64_t* status, hipStream_t st);
-// Q = s2 M + s1 C + K on the shared CSR pattern (nnz values).
-void launch_combine_q(int64_t nnz, double s2, double s1, const double* K, const double* M, const double* C,
-                      double* Q, hipStream_t st);
+// Out = am M + ac C + ak K on the shared CSR pattern (nnz values).
+void launch_combine3(int64_t nnz, double am, const double* M, double ac, const double* C, double ak,
+                     const double* K, double* Out, hipStream_t st);
 
 // --- forward / backward solves ------------------------------------------------
 // One launch per tree level; tasks[k] = {node, first row, end row, 0}.  The
@@ -168,6 +168,9 @@ struct BatchDev {
 void launch_spmv_b(const BatchDev& B, int ncols, const double* A0, double a0, int a0_sig, const double* A1,
                    double a1, const double* X, int64_t ldx, double* Y, int64_t ldy, const double* Z, int64_t ldz,
                    double bz, double* Y2, int64_t ldy2, hipStream_t st);
+// A = sigma_p M + C per problem (nonzeros of problem p in [nzbase[p], nzbase[p+1])).
+void launch_combine_b(int n, const int64_t* nzbase, int64_t nnz, const double* sig, const double* M, const double* C,
+                      double* A, hipStream_t st);
 // Current block of the bases (columns kcur .. kcur + nq) into Xu, Xw.
 void launch_gather_b(const BatchDev& B, int nq, const double* Vu, const double* Wl, double* Xu, double* Xw,
                      hipStream_t st);

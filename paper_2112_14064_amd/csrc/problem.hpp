@@ -40,6 +40,7 @@ struct riga_problem {
   int* d_level_nodes = nullptr;
   double *d_gx = nullptr, *d_gw = nullptr, *d_tabM = nullptr, *d_tabK = nullptr;
   double *d_K = nullptr, *d_M = nullptr, *d_C = nullptr;
+  double* d_A = nullptr;                            // sigma M + C (formed at factor time)
   double *d_L = nullptr, *d_U = nullptr, *d_T = nullptr, *d_upd = nullptr, *d_tmp = nullptr, *d_tmp2 = nullptr;
   double *d_Lp = nullptr, *d_Tp = nullptr;         // F in the sweep layouts
   int64_t lpsize = 0, tpsize = 0;
@@ -61,7 +62,7 @@ struct riga_problem {
   // Krylov workspace
   int64_t kw_cols = 0, kw_b = 0, kw_nev = 0;
   double *Vu = nullptr, *Vl = nullptr, *Wl = nullptr, *Vu2 = nullptr, *Vl2 = nullptr, *Wl2 = nullptr;
-  double *Ru = nullptr, *Rl = nullptr, *MRl = nullptr, *Tv = nullptr, *Mvu = nullptr;
+  double *Ru = nullptr, *Rl = nullptr, *MRl = nullptr, *Tv = nullptr;
   double *d_small = nullptr;      // device staging for h1, h2, G and small matrices
   double *d_H = nullptr;          // device copy of the projected matrix (fast path)
   int* d_flag = nullptr;          // breakdown flag of the fast path
