@@ -368,7 +368,8 @@ void launch_advance_b(const BatchDev& B, int b, int m, hipStream_t st) {
 }
 
 // Out[:, 0:kout_p] = In[:, 0:kin_p] Q_p per problem (Q_p at Q + qoff[p], kin_p x
-// kout_p column-major); problems with kout_p = 0 are skipped.
+// kout_p column-major); problems with kout_p = 0 are skipped.  A row block of up
+// to 256 rows is done as 64-row tiles.
 __global__ __launch_bounds__(GEMM_THREADS) void k_gemm_tall_b(const int4* __restrict__ rb,
                                                               const int* __restrict__ kin,
                                                               const int* __restrict__ kout,
@@ -376,17 +377,17 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_gemm_tall_b(const int4* __rest
                                                               const double* __restrict__ Q,
                                                               const double* __restrict__ In, double* __restrict__ Out,
                                                               int64_t ld) {
-  extern __shared__ double qs[];
+  extern __shared__ double tile[];
   const int4 b = rb[blockIdx.x];
   const int ko = kout[b.x];
   if (ko <= 0) return;
-  const int64_t i = b.y + threadIdx.x;
-  gemm_tall_row(i, i < b.z, In, ld, kin[b.x], Q + qoff[b.x], ko, Out, 1, ld, qs);
+  for (int r0 = b.y; r0 < b.z; r0 += GEMM_ROWS)
+    gemm_tile64(r0, min(GEMM_ROWS, b.z - r0), In, ld, kin[b.x], Q + qoff[b.x], ko, Out, 1, ld, tile);
 }
 
 void launch_gemm_tall_b(const BatchDev& B, const int* kin, const int* kout, const int64_t* qoff, const double* Q,
                         int max_kin, const double* In, double* Out, hipStream_t st) {
-  const size_t shm = (size_t)max_kin * GEMM_CHUNK * sizeof(double);
+  const size_t shm = (size_t)max_kin * GEMM_ROWS * sizeof(double);
   hipLaunchKernelGGL(k_gemm_tall_b, dim3(B.nrb), dim3(GEMM_THREADS), shm, st, B.rb, kin, kout, qoff, Q, In, Out,
                      B.ntot);
 }

@@ -303,23 +303,22 @@ void launch_cgs_update(int64_t n, int nc, int nq, const double* h,
 }
 
 // ---------------------------------------------------------------------------
-// Out = In * Q for a tall In (n x kin) and a small Q (kin x kout) held in LDS,
-// thread per row (body in krylov_dev.hpp).
+// Out = In * Q for a tall In (n x kin) and a small Q (kin x kout), one 64-row
+// tile per workgroup (body in krylov_dev.hpp).
 __global__ __launch_bounds__(GEMM_THREADS) void k_gemm_tall(
     int64_t n, const double* __restrict__ In, int64_t ldi, int kin, const double* __restrict__ Q,
     int kout, double* __restrict__ Out, int64_t out_rs, int64_t out_cs) {
-  extern __shared__ double qs[];
-  const int64_t i = (int64_t)blockIdx.x * GEMM_THREADS + threadIdx.x;
-  gemm_tall_row(i, i < n, In, ldi, kin, Q, kout, Out, out_rs, out_cs, qs);
+  extern __shared__ double tile[];
+  const int64_t r0 = (int64_t)blockIdx.x * GEMM_ROWS;
+  gemm_tile64(r0, (int)min((int64_t)GEMM_ROWS, n - r0), In, ldi, kin, Q, kout, Out, out_rs, out_cs, tile);
 }
 
 void launch_gemm_tall(int64_t n, const double* In, int64_t ldi, int kin, const double* Q, int kout,
                       double* Out, int64_t out_rs, int64_t out_cs, hipStream_t st) {
-  if (kout <= 0 || kin <= 0) return;
-  int64_t blocks = (n + GEMM_THREADS - 1) / GEMM_THREADS;
-  // the Q rows in LDS: kin x 32 doubles per pass, at most 64 KB
-  // callers keep kin <= 256 (the subspace size plus one block)
-  size_t shm = (size_t)kin * GEMM_CHUNK * sizeof(double);
+  if (kout <= 0 || kin <= 0 || n <= 0) return;
+  const int64_t blocks = (n + GEMM_ROWS - 1) / GEMM_ROWS;
+  // the In tile in LDS: kin x 64 doubles; callers keep kin <= 256 (128 KiB)
+  const size_t shm = (size_t)kin * GEMM_ROWS * sizeof(double);
   hipLaunchKernelGGL(k_gemm_tall, dim3((unsigned)blocks), dim3(GEMM_THREADS), shm, st, n, In, ldi, kin, Q,
                      kout, Out, out_rs, out_cs);
 }

@@ -60,43 +60,43 @@ __device__ inline void block_normalize_body(int nc, int nq, const double* h1, co
 }
 
 constexpr int GEMM_THREADS = 256;
-constexpr int GEMM_CHUNK = 32;
-constexpr int GEMM_UNROLL = 8;
+constexpr int GEMM_ROWS = 64;     // rows of In per tile
 
-// Row i of Out = In * Q (In n x kin with leading dimension ldi, Q kin x kout
-// column-major) for the rows of one workgroup; every thread of the block
-// calls it (live = false for threads past the rows).  qs: kin * 32 doubles of
-// shared memory.  32 output columns per pass kept in registers; the inner loop
-// issues 8 independent coalesced loads of In before using them.
-__device__ inline void gemm_tall_row(int64_t i, bool live, const double* __restrict__ In, int64_t ldi, int kin,
-                                     const double* __restrict__ Q, int kout, double* __restrict__ Out,
-                                     int64_t out_rs, int64_t out_cs, double* qs) {
-  for (int c0 = 0; c0 < kout; c0 += GEMM_CHUNK) {
-    const int kc = min(GEMM_CHUNK, kout - c0);
-    __syncthreads();
-    for (int k = threadIdx.x; k < kin * GEMM_CHUNK; k += GEMM_THREADS) {
-      const int tt = k / GEMM_CHUNK, c = k % GEMM_CHUNK;
-      qs[k] = (c < kc) ? Q[(int64_t)(c0 + c) * kin + tt] : 0.0;
-    }
-    __syncthreads();
-    if (!live) continue;
-    double acc[GEMM_CHUNK];
+// Rows [r0, r0 + rows) of Out = In * Q (In n x kin with leading dimension ldi,
+// Q kin x kout column-major).  The tile of In is staged in LDS (tile: kin * 64
+// doubles, laid out [t][row] so the lanes of a wave read consecutive words);
+// lane = row, every wave takes four output columns at a time, and the entries
+// of Q are read through the scalar cache (uniform across the wave).  Called by
+// every thread of a 256-thread block.
+__device__ inline void gemm_tile64(int64_t r0, int rows, const double* __restrict__ In, int64_t ldi, int kin,
+                                   const double* __restrict__ Q, int kout, double* __restrict__ Out,
+                                   int64_t out_rs, int64_t out_cs, double* tile) {
+  __syncthreads();   // the previous tile has been consumed
+  for (int idx = threadIdx.x; idx < GEMM_ROWS * kin; idx += GEMM_THREADS) {
+    const int r = idx % GEMM_ROWS, t = idx / GEMM_ROWS;
+    tile[idx] = (r < rows) ? In[r0 + r + (int64_t)t * ldi] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int c0 = wave * 4; c0 < kout; c0 += 16) {
+    const int nc = min(4, kout - c0);
+    const double* q = Q + (int64_t)c0 * kin;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (nc == 4) {
+      for (int t = 0; t < kin; ++t) {
+        const double a = tile[t * GEMM_ROWS + lane];
 #pragma unroll
-    for (int c = 0; c < GEMM_CHUNK; ++c) acc[c] = 0.0;
-    for (int t0 = 0; t0 < kin; t0 += GEMM_UNROLL) {
-      double a[GEMM_UNROLL];
-#pragma unroll
-      for (int u = 0; u < GEMM_UNROLL; ++u) a[u] = (t0 + u < kin) ? In[i + (int64_t)(t0 + u) * ldi] : 0.0;
-#pragma unroll
-      for (int u = 0; u < GEMM_UNROLL; ++u) {
-        const int tt = min(t0 + u, kin - 1);
-#pragma unroll
-        for (int c = 0; c < GEMM_CHUNK; ++c) acc[c] += a[u] * qs[tt * GEMM_CHUNK + c];
+        for (int u = 0; u < 4; ++u) acc[u] += a * q[(int64_t)u * kin + t];
+      }
+    } else {
+      for (int t = 0; t < kin; ++t) {
+        const double a = tile[t * GEMM_ROWS + lane];
+        for (int u = 0; u < nc; ++u) acc[u] += a * q[(int64_t)u * kin + t];
       }
     }
-#pragma unroll
-    for (int c = 0; c < GEMM_CHUNK; ++c)
-      if (c < kc) Out[i * out_rs + (int64_t)(c0 + c) * out_cs] = acc[c];
+    if (lane < rows)
+      for (int u = 0; u < nc; ++u) Out[(r0 + lane) * out_rs + (int64_t)(c0 + u) * out_cs] = acc[u];
   }
 }
 
