@@ -387,7 +387,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_gemm_tall_b(const int4* __rest
 
 void launch_gemm_tall_b(const BatchDev& B, const int* kin, const int* kout, const int64_t* qoff, const double* Q,
                         int max_kin, const double* In, double* Out, hipStream_t st) {
-  const size_t shm = (size_t)max_kin * GEMM_ROWS * sizeof(double);
+  const size_t shm = (size_t)max_kin * (GEMM_ROWS + 16) * sizeof(double);
   hipLaunchKernelGGL(k_gemm_tall_b, dim3(B.nrb), dim3(GEMM_THREADS), shm, st, B.rb, kin, kout, qoff, Q, In, Out,
                      B.ntot);
 }

@@ -202,8 +202,17 @@ __global__ __launch_bounds__(FT) void k_potrf_diag(DevTree t, const int* __restr
   if (tid < TB) {
     const int r = tid;
     for (int c = 0; c < w; ++c) {
-      E acc = S[r][c];
-      for (int k = 0; k < c; ++k) acc -= S[r][k] * S[c][k];
+      // four partial sums keep the FMA chain short
+      E s0 = E(0), s1 = E(0), s2 = E(0), s3 = E(0);
+      int k = 0;
+      for (; k + 4 <= c; k += 4) {
+        s0 += S[r][k] * S[c][k];
+        s1 += S[r][k + 1] * S[c][k + 1];
+        s2 += S[r][k + 2] * S[c][k + 2];
+        s3 += S[r][k + 3] * S[c][k + 3];
+      }
+      for (; k < c; ++k) s0 += S[r][k] * S[c][k];
+      const E acc = S[r][c] - ((s0 + s1) + (s2 + s3));
       double piv = (double)__shfl(acc, c, 64);
       if (!(piv > 0.0)) {           // not SPD (or NaN): record, continue with 1
         if (r == c)
@@ -223,9 +232,16 @@ __global__ __launch_bounds__(FT) void k_potrf_diag(DevTree t, const int* __restr
     if (c < w) {
       Dl[c][c] = E(1) / S[c][c];
       for (int rr = c + 1; rr < w; ++rr) {
-        E sacc = E(0);
-        for (int k = c; k < rr; ++k) sacc += S[rr][k] * Dl[k][c];
-        Dl[rr][c] = -sacc / S[rr][rr];
+        E s0 = E(0), s1 = E(0), s2 = E(0), s3 = E(0);
+        int k = c;
+        for (; k + 4 <= rr; k += 4) {
+          s0 += S[rr][k] * Dl[k][c];
+          s1 += S[rr][k + 1] * Dl[k + 1][c];
+          s2 += S[rr][k + 2] * Dl[k + 2][c];
+          s3 += S[rr][k + 3] * Dl[k + 3][c];
+        }
+        for (; k < rr; ++k) s0 += S[rr][k] * Dl[k][c];
+        Dl[rr][c] = -((s0 + s1) + (s2 + s3)) / S[rr][rr];
       }
     }
   }

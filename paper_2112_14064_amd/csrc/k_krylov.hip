@@ -317,8 +317,8 @@ void launch_gemm_tall(int64_t n, const double* In, int64_t ldi, int kin, const d
                       double* Out, int64_t out_rs, int64_t out_cs, hipStream_t st) {
   if (kout <= 0 || kin <= 0 || n <= 0) return;
   const int64_t blocks = (n + GEMM_ROWS - 1) / GEMM_ROWS;
-  // the In tile in LDS: kin x 64 doubles; callers keep kin <= 256 (128 KiB)
-  const size_t shm = (size_t)kin * GEMM_ROWS * sizeof(double);
+  // the In tile and 16 columns of Q in LDS: kin x 80 doubles; callers keep kin <= 256 (160 KiB)
+  const size_t shm = (size_t)kin * (GEMM_ROWS + 16) * sizeof(double);
   hipLaunchKernelGGL(k_gemm_tall, dim3((unsigned)blocks), dim3(GEMM_THREADS), shm, st, n, In, ldi, kin, Q,
                      kout, Out, out_rs, out_cs);
 }

@@ -63,40 +63,42 @@ constexpr int GEMM_THREADS = 256;
 constexpr int GEMM_ROWS = 64;     // rows of In per tile
 
 // Rows [r0, r0 + rows) of Out = In * Q (In n x kin with leading dimension ldi,
-// Q kin x kout column-major).  The tile of In is staged in LDS (tile: kin * 64
-// doubles, laid out [t][row] so the lanes of a wave read consecutive words);
-// lane = row, every wave takes four output columns at a time, and the entries
-// of Q are read through the scalar cache (uniform across the wave).  Called by
-// every thread of a 256-thread block.
+// Q kin x kout column-major).  The tile of In is staged in LDS (laid out
+// [t][row] so the lanes of a wave read consecutive words), and so are 16
+// columns of Q at a time (read as broadcasts); lane = row, every wave takes four
+// of those columns.  shm: kin * 64 + kin * 16 doubles.  Called by every thread
+// of a 256-thread block.
 __device__ inline void gemm_tile64(int64_t r0, int rows, const double* __restrict__ In, int64_t ldi, int kin,
                                    const double* __restrict__ Q, int kout, double* __restrict__ Out,
-                                   int64_t out_rs, int64_t out_cs, double* tile) {
+                                   int64_t out_rs, int64_t out_cs, double* shm) {
+  double* tile = shm;                         // [t][row]
+  double* qs = shm + (size_t)kin * GEMM_ROWS;  // [c][t], 16 columns
   __syncthreads();   // the previous tile has been consumed
   for (int idx = threadIdx.x; idx < GEMM_ROWS * kin; idx += GEMM_THREADS) {
     const int r = idx % GEMM_ROWS, t = idx / GEMM_ROWS;
     tile[idx] = (r < rows) ? In[r0 + r + (int64_t)t * ldi] : 0.0;
   }
-  __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  for (int c0 = wave * 4; c0 < kout; c0 += 16) {
-    const int nc = min(4, kout - c0);
-    const double* q = Q + (int64_t)c0 * kin;
+  const int wave = threadIdx.x >> 6;
+  for (int p0 = 0; p0 < kout; p0 += 16) {
+    const int np = min(16, kout - p0);
+    if (p0 > 0) __syncthreads();   // the previous columns of Q have been consumed
+    for (int idx = threadIdx.x; idx < 16 * kin; idx += GEMM_THREADS) {
+      const int c = idx / kin, t = idx % kin;
+      qs[idx] = (c < np) ? Q[(int64_t)(p0 + c) * kin + t] : 0.0;
+    }
+    __syncthreads();
+    const int c0 = wave * 4;
+    if (c0 >= np) continue;
+    const double* q = qs + (size_t)c0 * kin;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (nc == 4) {
-      for (int t = 0; t < kin; ++t) {
-        const double a = tile[t * GEMM_ROWS + lane];
+    for (int t = 0; t < kin; ++t) {
+      const double a = tile[t * GEMM_ROWS + lane];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] += a * q[(int64_t)u * kin + t];
-      }
-    } else {
-      for (int t = 0; t < kin; ++t) {
-        const double a = tile[t * GEMM_ROWS + lane];
-        for (int u = 0; u < nc; ++u) acc[u] += a * q[(int64_t)u * kin + t];
-      }
+      for (int u = 0; u < 4; ++u) acc[u] += a * q[u * kin + t];
     }
     if (lane < rows)
-      for (int u = 0; u < nc; ++u) Out[(r0 + lane) * out_rs + (int64_t)(c0 + u) * out_cs] = acc[u];
+      for (int u = 0; u < min(4, np - c0); ++u) Out[(r0 + lane) * out_rs + (int64_t)(p0 + c0 + u) * out_cs] = acc[u];
   }
 }
 
