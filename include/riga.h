@@ -89,13 +89,16 @@ typedef struct {
  *   v0      device, 2N x block column-major start block, or NULL.
  *   flags   bit 0: launch every block step eagerly instead of replaying its
  *           captured HIP graph; bit 1: check every block step on the host (the
- *           path otherwise taken only after a device-detected breakdown).    */
+ *           path otherwise taken only after a device-detected breakdown).
+ *   keep    Ritz values kept at a Krylov-Schur restart (0: nev + (m - nev)/2;
+ *           at least nev, at most m - block; extended to whole clusters).    */
 typedef struct {
   int nev, m, maxit, block;
   double tol;
   uint64_t seed;
   const double* v0;
   int flags;
+  int keep;
 } riga_options;
 
 typedef struct {

@@ -1112,7 +1112,7 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
   const double tol = opt->tol > 0 ? opt->tol : 1e-12;
   if (nev < 1 || b < 1 || b > 4 || (int64_t)nev >= 2 * N) return RIGA_ERR_INVALID_ARG;
   if ((int64_t)m > 2 * N) m = (int)(2 * N);
-  if (m < nev + b || m + 2 * b > 256) return RIGA_ERR_INVALID_ARG;
+  if (m < nev + b || m + 2 * b > 256 || opt->keep < 0 || opt->keep > m - b) return RIGA_ERR_INVALID_ARG;
   // the solve runs on the handle's own stream, fenced to the caller's stream
   hipStream_t user_st = h->st;
   struct Restore {
@@ -1192,7 +1192,7 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
       if (cyc.nconv == cyc.nw) { converged = true; break; }
       if (it >= maxit) break;
       // --- Krylov--Schur restart: keep the nearest Ritz values ------------------
-      riga::ks_restart(kr.H, ldh, k, b, m, nev, cyc);
+      riga::ks_restart(kr.H, ldh, k, b, m, nev, opt->keep, cyc);
       const int r = cyc.r;
       // V_new = [V_k Qk, V_{k:k+b}] in the alternate buffers
       const int kin = k + b, kout = r + b;

@@ -363,7 +363,8 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
   const int m = opt->m > 0 ? opt->m : std::max(2 * nev, 20);
   const int maxit = opt->maxit > 0 ? opt->maxit : 200;
   const double tol = opt->tol > 0 ? opt->tol : 1e-12;
-  if (nev < 1 || b < 1 || b > 4 || m < nev + b || m + 2 * b > 256) return RIGA_ERR_INVALID_ARG;
+  if (nev < 1 || b < 1 || b > 4 || m < nev + b || m + 2 * b > 256 || opt->keep < 0 || opt->keep > m - b)
+    return RIGA_ERR_INVALID_ARG;
   for (int i = 0; i < n; ++i)
     if (2 * bh->N(i) < m) return RIGA_ERR_INVALID_ARG;
   riga_problem* fp = bh->fp;
@@ -457,7 +458,7 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
         ++it[i];
         if (cyc[i].nconv == cyc[i].nw) { newstate[i] = CONVERGED; return; }
         if (it[i] >= maxit) { newstate[i] = MAXIT; return; }
-        riga::ks_restart(Hi, ldh, k, b, m, nev, cyc[i]);
+        riga::ks_restart(Hi, ldh, k, b, m, nev, opt->keep, cyc[i]);
       });
       for (int i = 0; i < n; ++i)
         if (state[i] == ACTIVE) n_fb += (int64_t)b * ((m - kc[i]) / b);

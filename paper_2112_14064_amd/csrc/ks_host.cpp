@@ -41,13 +41,13 @@ int ks_ritz(const std::vector<double>& H, int ldh, int k, int b, int nev, double
   return 0;
 }
 
-void ks_restart(const std::vector<double>& H, int ldh, int k, int b, int m, int nev, KsCycle& c) {
+void ks_restart(const std::vector<double>& H, int ldh, int k, int b, int m, int nev, int keep, KsCycle& c) {
   auto Hat = [&](int r, int col) { return H[r + (size_t)col * ldh]; };
   auto same = [&](int p) {  // ord[p] continues the |theta| cluster of ord[p-1]
     return std::abs(std::abs(c.theta[c.ord[p]]) - std::abs(c.theta[c.ord[p - 1]])) <=
            1e-9 * std::abs(c.theta[c.ord[p - 1]]);
   };
-  int kk = nev + (k - nev) / 2;
+  int kk = keep > 0 ? std::max(keep, nev) : nev + (k - nev) / 2;
   kk = std::min(kk, m - b);
   kk = std::max(kk, std::min(c.nw, m - b));
   int kend = std::max(1, kk);
@@ -57,10 +57,10 @@ void ks_restart(const std::vector<double>& H, int ldh, int k, int b, int m, int 
   } else {  // step back to a cluster boundary
     while (kk > 1 && same(kk)) --kk;
   }
-  std::vector<char> keep(k, 0);
-  for (int p = 0; p < kk; ++p) keep[c.ord[p]] = 1;
+  std::vector<char> kept(k, 0);
+  for (int p = 0; p < kk; ++p) kept[c.ord[p]] = 1;
   std::vector<cplx> T = c.T, Z = c.Z;
-  schur_select(k, T, Z, keep);
+  schur_select(k, T, Z, kept);
   std::vector<double> Qk;
   const int r = realify(k, kk, Z, Qk);
   std::vector<double> Hk((size_t)k * k);

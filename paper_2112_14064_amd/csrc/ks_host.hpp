@@ -27,10 +27,11 @@ struct KsCycle {
 // iteration failed.
 int ks_ritz(const std::vector<double>& H, int ldh, int k, int b, int nev, double tol, KsCycle& c);
 
-// Krylov--Schur restart after ks_ritz: keep the nev + (k - nev)/2 Ritz values
-// nearest the shift (whole clusters), real Schur basis of their span, the new
-// projected matrix [T; E Q] and the combination Qe = [Q 0; 0 I].
-void ks_restart(const std::vector<double>& H, int ldh, int k, int b, int m, int nev, KsCycle& c);
+// Krylov--Schur restart after ks_ritz: keep the `keep` Ritz values nearest the
+// shift (0: nev + (k - nev)/2; never fewer than nev; extended to whole
+// clusters), real Schur basis of their span, the new projected matrix
+// [T; E Q] and the combination Qe = [Q 0; 0 I].
+void ks_restart(const std::vector<double>& H, int ldh, int k, int b, int m, int nev, int keep, KsCycle& c);
 
 // Forms of a complex vector u = a + i b given the 11 sums
 // a^T M a, b^T M b, a^T M b, a^T C a, b^T C b, a^T C b, a^T K a, b^T K b, a^T K b, a^T a, b^T b.

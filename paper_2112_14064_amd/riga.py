@@ -35,7 +35,8 @@ class riga_damping(C.Structure):
 
 class riga_options(C.Structure):
     _fields_ = [("nev", C.c_int), ("m", C.c_int), ("maxit", C.c_int), ("block", C.c_int),
-                ("tol", C.c_double), ("seed", C.c_uint64), ("v0", C.c_void_p), ("flags", C.c_int)]
+                ("tol", C.c_double), ("seed", C.c_uint64), ("v0", C.c_void_p), ("flags", C.c_int),
+                ("keep", C.c_int)]
 
 
 class riga_info_t(C.Structure):
@@ -237,7 +238,7 @@ class Problem:
         return r
 
     def eigs(self, nev: int, m: int = 0, block: int = 0, tol: float = 0.0, maxit: int = 0, seed: int = 0,
-             v0=None, vectors: bool = True, flags: int = 0):
+             v0=None, vectors: bool = True, flags: int = 0, keep: int = 0):
         """Returns (lam complex ndarray, X complex tensor (nev, ndof) or None, eta ndarray, nconv, status)."""
         torch = self.torch
         lam = np.zeros(2 * nev)
@@ -245,7 +246,7 @@ class Problem:
         X = torch.empty((nev, self.ndof, 2), dtype=torch.float64, device=self.device) if vectors else None
         if v0 is not None:
             v0 = v0.to(device=self.device, dtype=torch.float64).contiguous()
-        opt = riga_options(nev, m, maxit, block, tol, seed, _ptr(v0), flags)
+        opt = riga_options(nev, m, maxit, block, tol, seed, _ptr(v0), flags, keep)
         nconv = C.c_int(0)
         st = self.lib.riga_eigs(self.h, C.byref(opt), lam.ctypes.data_as(C.c_void_p), _ptr(X),
                                 eta.ctypes.data_as(C.c_void_p), C.byref(nconv))
@@ -364,7 +365,7 @@ class Batch:
         _check(st, "riga_batch_factor")
 
     def eigs(self, nev: int, m: int = 0, block: int = 0, tol: float = 0.0, maxit: int = 0, seed: int = 0,
-             vectors: bool = False, flags: int = 0):
+             vectors: bool = False, flags: int = 0, keep: int = 0):
         """Returns (lam complex (n, nev), X list of complex (nev, N_p) tensors or None,
         eta (n, nev), nconv (n,), status)."""
         torch = self.torch
@@ -372,7 +373,7 @@ class Batch:
         eta = np.zeros(self.n * nev)
         nconv = np.zeros(self.n, dtype=np.int32)
         X = torch.empty(2 * nev * self.total, dtype=torch.float64, device=self.device) if vectors else None
-        opt = riga_options(nev, m, maxit, block, tol, seed, None, flags)
+        opt = riga_options(nev, m, maxit, block, tol, seed, None, flags, keep)
         st = self.lib.riga_batch_eigs(self.h, C.byref(opt), lam.ctypes.data_as(C.c_void_p), _ptr(X),
                                       eta.ctypes.data_as(C.c_void_p), nconv.ctypes.data_as(C.c_void_p))
         _check(st, "riga_batch_eigs", allow_warn=True)
