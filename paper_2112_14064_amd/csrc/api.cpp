@@ -139,7 +139,7 @@ void solve_levels(riga_problem* h, int nrhs, const double* b, int64_t ldb, doubl
   o.xs = h->d_irX; o.ldxs = N;
   sweep(h, nrhs, b, ldb, o);
   for (int k = 1; k <= K; ++k) {
-    riga::launch_spmv(h->ds, N, nrhs, h->d_Q, -1.0, nullptr, 0.0, nullptr, 0.0, h->d_irX, N, h->d_irR, N, b, ldb,
+    riga::launch_spmv(h->ds, N, nrhs, h->d_Q, -1.0, h->d_irX, N, h->d_irR, N, b, ldb,
                       1.0, nullptr, 0, h->st);
     riga::BwdOut c;
     c.xs = h->d_irD; c.ldxs = N;
@@ -161,7 +161,7 @@ void solve_levels(riga_problem* h, int nrhs, const double* b, int64_t ldb, doubl
 void apply_block(riga_problem* h, int nb, const double* vu, const double* wl, int64_t ld,
                  double* ru, double* rl, double* t) {
   const int64_t N = h->N();
-  riga::launch_spmv(h->ds, N, nb, h->d_A, 1.0, nullptr, 0.0, nullptr, 0.0, vu, ld, t, N, wl, ld, 1.0, nullptr, 0,
+  riga::launch_spmv(h->ds, N, nb, h->d_A, 1.0, vu, ld, t, N, wl, ld, 1.0, nullptr, 0,
                     h->st);
   solve_levels(h, nb, t, N, ru, N, rl, vu, ld, h->sigma);
 }
@@ -261,6 +261,25 @@ void setup_device(riga_problem* h) {
     for (size_t v = 0; v < P.nb.size(); ++v) voff[v + 1] = voff[v] + P.nb[v];
     h->upd_len = voff.back();
     h->dt.voff = h->upload(voff);
+    {
+      // per front position, the children's update rows that land on it, in child order
+      const size_t npos = (size_t)P.foff.back();
+      std::vector<int> gcnt(npos + 1, 0), gptr(npos + 1, 0), gidx((size_t)h->upd_len);
+      for (size_t v = 0; v < P.nf.size(); ++v)
+        for (int ci = P.coff[v]; ci < P.coff[v + 1]; ++ci) {
+          const int c = P.clist[ci];
+          for (int k = 0; k < P.nb[c]; ++k) ++gcnt[P.foff[v] + P.maps[P.moff[c] + k]];
+        }
+      for (size_t q = 0; q < npos; ++q) gptr[q + 1] = gptr[q] + gcnt[q];
+      std::vector<int> fill(gptr.begin(), gptr.end() - 1);
+      for (size_t v = 0; v < P.nf.size(); ++v)
+        for (int ci = P.coff[v]; ci < P.coff[v + 1]; ++ci) {
+          const int c = P.clist[ci];
+          for (int k = 0; k < P.nb[c]; ++k) gidx[fill[P.foff[v] + P.maps[P.moff[c] + k]]++] = voff[c] + k;
+        }
+      h->dt.gptr = h->upload(gptr);
+      h->dt.gidx = h->upload(gidx);
+    }
     h->d_level_nodes = h->upload(P.level_nodes);
     std::vector<double> gx, gw;
     gauss_legendre(S.p + 1, gx, gw);
@@ -272,15 +291,18 @@ void setup_device(riga_problem* h) {
     h->d_A = h->dalloc<double>(P.nnz);
     h->d_L = h->dalloc<double>(P.lsize); h->d_U = h->dalloc<double>(P.usize);
     h->d_T = h->dalloc<double>(P.lsize);
+    // sweep layouts: every node padded to groups of 4 columns / rows
+    std::vector<int64_t> lpoff(P.nf.size() + 1, 0), tpoff(P.nf.size() + 1, 0);
     {
-      // sweep layouts: every node padded to groups of 4 columns / rows
-      std::vector<int64_t> lpoff(P.nf.size() + 1, 0), tpoff(P.nf.size() + 1, 0);
       for (size_t v = 0; v < P.nf.size(); ++v) {
         lpoff[v + 1] = lpoff[v] + (int64_t)((P.no[v] + 3) / 4 * 4) * P.nf[v];
         tpoff[v + 1] = tpoff[v] + (int64_t)((P.nf[v] + 3) / 4 * 4) * P.no[v];
       }
-      h->lpsize = lpoff.back();
-      h->tpsize = tpoff.back();
+      // slack past the last node: a forward task of a node without own dofs
+      // reads (and discards) one round at the node's offset
+      const int64_t slack = ((int64_t)P.max_front + 64) * 4;
+      h->lpsize = lpoff.back() + slack;
+      h->tpsize = tpoff.back() + slack;
       h->dt.lpoff = h->upload(lpoff);
       h->dt.tpoff = h->upload(tpoff);
       h->d_Lp = h->dalloc<double>(h->lpsize);
@@ -305,18 +327,36 @@ void setup_device(riga_problem* h) {
         }
     }
     {
-      // Row tasks of the solve sweeps: blocks of 64 consecutive rows of one node.
-      std::vector<int4> ft, bt;
+      // Row tasks of the solve sweeps: blocks of 64 consecutive rows of one
+      // node.  Within a level the tasks are launched largest first (columns a
+      // forward task reads: up to its last row's diagonal; rows a backward task
+      // reads: from its first column down), so the short ones fill the tail.
+      std::vector<riga::SweepTask> ft, bt;
       h->ftask_off.assign(P.height + 1, 0);
       h->btask_off.assign(P.height + 1, 0);
+      auto task = [&](int v, int r0, int r1, int64_t poff) {
+        riga::SweepTask k{};
+        k.v = v; k.r0 = r0; k.r1 = r1; k.nf = P.nf[v]; k.no = P.no[v]; k.foff = P.foff[v];
+        k.voff = voff[v]; k.inst = h->node_inst.empty() ? 0 : h->node_inst[v]; k.poff = poff;
+        return k;
+      };
       for (int lv = 0; lv < P.height; ++lv) {
+        const size_t f0 = ft.size(), b0 = bt.size();
         for (int k = P.level_off[lv]; k < P.level_off[lv + 1]; ++k) {
           const int v = P.level_nodes[k];
-          for (int r = 0; r < P.nf[v]; r += 64) ft.push_back(int4{v, r, std::min(r + 64, P.nf[v]), 0});
-          for (int r = 0; r < P.no[v]; r += 64) bt.push_back(int4{v, r, std::min(r + 64, P.no[v]), 0});
+          for (int r = 0; r < P.nf[v]; r += 64) ft.push_back(task(v, r, std::min(r + 64, P.nf[v]), lpoff[v]));
+          for (int r = 0; r < P.no[v]; r += 64) bt.push_back(task(v, r, std::min(r + 64, P.no[v]), tpoff[v]));
         }
+        std::stable_sort(ft.begin() + f0, ft.end(), [](const riga::SweepTask& x, const riga::SweepTask& y) {
+          return std::min(x.r1, x.no) > std::min(y.r1, y.no);
+        });
+        std::stable_sort(bt.begin() + b0, bt.end(), [](const riga::SweepTask& x, const riga::SweepTask& y) {
+          return x.nf - x.r0 > y.nf - y.r0;
+        });
         h->ftask_off[lv + 1] = (int)ft.size();
         h->btask_off[lv + 1] = (int)bt.size();
+        h->fvar[lv] = (h->ftask_off[lv + 1] - h->ftask_off[lv] >= 1024) ? riga::SWEEP_WIDE : riga::SWEEP_NARROW;
+        h->bvar[lv] = (h->btask_off[lv + 1] - h->btask_off[lv] >= 1024) ? riga::SWEEP_WIDE : riga::SWEEP_NARROW;
       }
       h->d_ftasks = h->upload(ft);
       h->d_btasks = h->upload(bt);
@@ -520,7 +560,7 @@ void ir_history(riga_problem* h, int kmax, std::vector<double>& hist) {
   sweep(h, 1, b, N, o);
   hist.clear();
   for (int k = 0; k <= kmax; ++k) {
-    riga::launch_spmv(h->ds, N, 1, h->d_Q, -1.0, nullptr, 0.0, nullptr, 0.0, h->d_irX, N, h->d_irR, N, b, N, 1.0,
+    riga::launch_spmv(h->ds, N, 1, h->d_Q, -1.0, h->d_irX, N, h->d_irR, N, b, N, 1.0,
                       nullptr, 0, h->st);
     hist.push_back(norm2(h->d_irR) / nb);
     if (k == kmax) break;
@@ -735,12 +775,12 @@ riga_status riga_apply_op(riga_problem* h, int nvec, const double* v, double* r)
     ck(hipSetDevice(h->device));
     const int64_t N = h->N();
     // M v_l into tmp2, then the common block operator
-    riga::launch_spmv(h->ds, N, nvec, h->d_M, 1.0, nullptr, 0.0, nullptr, 0.0, v + N, 2 * N, h->d_tmp2, N,
+    riga::launch_spmv(h->ds, N, nvec, h->d_M, 1.0, v + N, 2 * N, h->d_tmp2, N,
                       nullptr, 0, 0.0, nullptr, 0, h->st);
     double* t = r + N;  // r_l doubles as scratch for t until the backward sweep writes it
     double* mvu = h->d_upd;  // unused here; Y2 not requested
     (void)mvu;
-    riga::launch_spmv(h->ds, N, nvec, h->d_A, 1.0, nullptr, 0.0, nullptr, 0.0, v, 2 * N, t, 2 * N,
+    riga::launch_spmv(h->ds, N, nvec, h->d_A, 1.0, v, 2 * N, t, 2 * N,
                       h->d_tmp2, N, 1.0, nullptr, 0, h->st);
     solve_levels(h, nvec, t, 2 * N, r, 2 * N, r + N, v, 2 * N, h->sigma);
     ck(hipGetLastError());
@@ -839,9 +879,9 @@ riga_status riga_adjoint(riga_problem* h, int nev, const double* lam, const doub
     for (int c0 = 0; c0 < 2 * nev; c0 += 8) {
       const int nc = std::min(8, 2 * nev - c0);
       const double* x = h->P + (size_t)c0 * N;
-      riga::launch_spmv(h->ds, N, nc, h->d_M, 1.0, nullptr, 0, nullptr, 0, x, N, h->MP + (size_t)c0 * N, N,
+      riga::launch_spmv(h->ds, N, nc, h->d_M, 1.0, x, N, h->MP + (size_t)c0 * N, N,
                         nullptr, 0, 0.0, nullptr, 0, h->st);
-      riga::launch_spmv(h->ds, N, nc, h->d_C, 1.0, nullptr, 0, nullptr, 0, x, N, h->CP + (size_t)c0 * N, N,
+      riga::launch_spmv(h->ds, N, nc, h->d_C, 1.0, x, N, h->CP + (size_t)c0 * N, N,
                         nullptr, 0, 0.0, nullptr, 0, h->st);
     }
     const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, N / 4096));
@@ -1030,7 +1070,7 @@ struct KrylovRun {
       const int nf = b - r;
       riga::launch_random_fill(h->Ru, N, nf, N, seed * 7919u + 17u, h->st);
       riga::launch_random_fill(h->Rl, N, nf, N, seed * 7919u + 29u, h->st);
-      riga::launch_spmv(h->ds, N, nf, h->d_M, 1.0, nullptr, 0, nullptr, 0, h->Rl, N, h->MRl, N, nullptr, 0, 0.0,
+      riga::launch_spmv(h->ds, N, nf, h->d_M, 1.0, h->Rl, N, h->MRl, N, nullptr, 0, 0.0,
                         nullptr, 0, h->st);
       project(nc + r, nf, h->Ru, h->Rl, h->MRl, dh, nullptr);
       std::vector<double> Gf = gram(nf, h->Ru, h->Rl, h->MRl);
@@ -1046,7 +1086,7 @@ struct KrylovRun {
     const int64_t n = N;
     const size_t o = (size_t)k * n;
     apply_block(h, b, h->Vu + o, h->Wl + o, n, h->Ru, h->Rl, h->Tv);
-    riga::launch_spmv(h->ds, n, b, h->d_M, 1.0, nullptr, 0, nullptr, 0, h->Rl, n, h->MRl, n, nullptr, 0, 0.0,
+    riga::launch_spmv(h->ds, n, b, h->d_M, 1.0, h->Rl, n, h->MRl, n, nullptr, 0, 0.0,
                       nullptr, 0, h->st);
     orthonormalize_device(k + b, h->d_H, k);
   }
@@ -1081,7 +1121,7 @@ struct KrylovRun {
       return;
     }
     apply_block(h, b, h->Vu + o, h->Wl + o, n, h->Ru, h->Rl, h->Tv);
-    riga::launch_spmv(h->ds, n, b, h->d_M, 1.0, nullptr, 0, nullptr, 0, h->Rl, n, h->MRl, n, nullptr, 0, 0.0,
+    riga::launch_spmv(h->ds, n, b, h->d_M, 1.0, h->Rl, n, h->MRl, n, nullptr, 0, 0.0,
                       nullptr, 0, h->st);
     n_fb += b;
     n_mv += 3LL * b;
@@ -1163,7 +1203,7 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
       riga::launch_random_fill(h->Ru, N, b, N, opt->seed * 2 + 1, h->st);
       riga::launch_random_fill(h->Rl, N, b, N, opt->seed * 2 + 2, h->st);
     }
-    riga::launch_spmv(h->ds, N, b, h->d_M, 1.0, nullptr, 0, nullptr, 0, h->Rl, N, h->MRl, N, nullptr, 0, 0.0,
+    riga::launch_spmv(h->ds, N, b, h->d_M, 1.0, h->Rl, N, h->MRl, N, nullptr, 0, 0.0,
                       nullptr, 0, h->st);
     if (kr.fast) {
       kr.orthonormalize_device(0, nullptr, 0);

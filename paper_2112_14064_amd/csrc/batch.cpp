@@ -121,13 +121,13 @@ void enqueue_step(riga_batch* bh, int b, int m, int ldh, hipStream_t st) {
   const int hs = ldh * b;
   riga::launch_gather_b(B, b, bh->Vu, bh->Wl, bh->Xu, bh->Xw, st);
   // t = (sigma M + C) v_u + M v_l (eq. BlockOperatorVector), sigma M + C formed per problem
-  riga::launch_spmv_b(B, b, fp->d_A, 1.0, 0, nullptr, 0.0, bh->Xu, T, bh->Tv, T, bh->Xw, T, 1.0, nullptr, 0, st);
+  riga::launch_spmv_b(B, b, fp->d_A, bh->Xu, T, bh->Tv, T, bh->Xw, T, 1.0, st);
   // r_u = -Q^{-1} t, r_l = sigma r_u + v_u (sigma of each node's problem)
   riga::BwdOut o;
   o.xs = bh->Ru; o.ldxs = T; o.neg = 1; o.ldr = T;
   o.rl = bh->Rl; o.v_u = bh->Xu; o.ldv = T;
   sweep(fp, b, bh->Tv, T, o);
-  riga::launch_spmv_b(B, b, fp->d_M, 1.0, 0, nullptr, 0.0, bh->Rl, T, bh->MRl, T, nullptr, 0, 0.0, nullptr, 0, st);
+  riga::launch_spmv_b(B, b, fp->d_M, bh->Rl, T, bh->MRl, T, nullptr, 0, 0.0, st);
   // classical Gram--Schmidt twice against V[:, 0:k+b], B-inner products
   riga::launch_dots_b(B, b, 0, true, bh->Vu, bh->Wl, b, bh->Ru, bh->Rl, bh->h1, hs, st);
   riga::launch_cgs_update_b(B, b, b, bh->h1, hs, bh->Vu, bh->Ru, bh->Vl, bh->Rl, bh->Wl, bh->MRl, m + b, st);
@@ -172,6 +172,9 @@ riga_status riga_batch_create(riga_batch** out, int n, const riga_mesh* meshes, 
     fp->device = device;
     fp->st = bh->user_st;
     fp->mesh = riga_mesh{0, 0, 0, 0};
+    fp->node_inst.assign(fp->plan.nodes.size(), 0);
+    for (int i = 0; i < n; ++i)
+      for (int v = bh->node_base[i]; v < bh->node_base[i + 1]; ++v) fp->node_inst[v] = i;
     setup_device(fp);
     const int64_t T = fp->plan.ndof;
     // per-problem 1-D spaces in shared arrays, rows into the forest CSR
@@ -223,11 +226,10 @@ riga_status riga_batch_create(riga_batch** out, int n, const riga_mesh* meshes, 
       bh->gw[i] = rule[p].second;
     }
     // problem of every node and row; row blocks and dot blocks
-    std::vector<int> inst(fp->plan.nodes.size()), rinst(T);
+    std::vector<int> rinst(T);
     std::vector<int4> rb, db;
     std::vector<int> dboff(n + 1, 0);
     for (int i = 0; i < n; ++i) {
-      for (int v = bh->node_base[i]; v < bh->node_base[i + 1]; ++v) inst[v] = i;
       const int64_t r0 = bh->dof_base[i], r1 = bh->dof_base[i + 1];
       for (int64_t r = r0; r < r1; ++r) rinst[r] = i;
       for (int64_t r = r0; r < r1; r += 256) rb.push_back(int4{i, (int)r, (int)std::min(r + 256, r1), 0});
@@ -252,7 +254,7 @@ riga_status riga_batch_create(riga_batch** out, int n, const riga_mesh* meshes, 
     std::vector<int64_t> nzb(n + 1);
     for (int i = 0; i <= n; ++i) nzb[i] = fp->plan.rowptr[bh->dof_base[i]];
     bh->d_nzbase = fp->upload(nzb);
-    fp->dt.inst = fp->upload(inst);
+    fp->dt.inst = fp->upload(fp->node_inst);
     fp->dt.spaces = B.spaces;
     fp->dt.dofbase = B.dofbase;
     fp->dt.isig = B.sig;
@@ -398,7 +400,7 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
     ck(hipMemsetAsync(bh->H, 0, sizeof(double) * (size_t)n * ldh * ldh, st));
     riga::launch_random_fill(bh->Ru, T, b, T, opt->seed * 2 + 1, st);
     riga::launch_random_fill(bh->Rl, T, b, T, opt->seed * 2 + 2, st);
-    riga::launch_spmv_b(B, b, fp->d_M, 1.0, 0, nullptr, 0.0, bh->Rl, T, bh->MRl, T, nullptr, 0, 0.0, nullptr, 0, st);
+    riga::launch_spmv_b(B, b, fp->d_M, bh->Rl, T, bh->MRl, T, nullptr, 0, 0.0, st);
     riga::launch_dots_b(B, 0, b, false, bh->Ru, bh->MRl, b, bh->Ru, bh->Rl, bh->G, b * b, st);
     riga::launch_block_normalize_b(B, false, 0, b, nullptr, nullptr, 0, bh->G, nullptr, ldh, bh->Rinv, st);
     riga::launch_gemm3_b(B, false, 0, b, bh->Rinv, bh->Ru, bh->Vu, bh->Rl, bh->Vl, bh->MRl, bh->Wl, st);

@@ -14,26 +14,23 @@
 namespace riga {
 
 constexpr int BT = 256;   // threads per block of the row-parallel kernels
-constexpr int SPB_G = 16; // lanes per row of the sparse product
 
-// Y = a0 s A0 X + a1 A1 X + bz Z and Y2 = A0 X, with s = sigma of the row's
-// problem (a0_sig) or 1; implicit tensor columns of the problem's space.
+// Y = A X + bz Z (Z may be null) on every live problem's rows, implicit
+// tensor columns of the row's problem space; 16 lanes per row.
 template <int NC>
 __global__ __launch_bounds__(BT) void k_spmv_b(const int* __restrict__ rinst, const DevSpace* __restrict__ spaces,
-                                               const int64_t* __restrict__ dofbase, const double* __restrict__ isig,
+                                               const int64_t* __restrict__ dofbase,
                                                const unsigned char* __restrict__ live, int64_t ntot,
-                                               const double* __restrict__ A0, double a0, int a0_sig,
-                                               const double* __restrict__ A1, double a1,
-                                               const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
-                                               int64_t ldy, const double* __restrict__ Z, int64_t ldz, double bz,
-                                               double* __restrict__ Y2, int64_t ldy2) {
-  const int g = threadIdx.x % SPB_G;
-  const int64_t r = ((int64_t)blockIdx.x * BT + threadIdx.x) / SPB_G;
+                                               const double* __restrict__ A, const double* __restrict__ X,
+                                               int64_t ldx, double* __restrict__ Y, int64_t ldy,
+                                               const double* __restrict__ Z, int64_t ldz, double bz) {
+  const int g = threadIdx.x % SPMV_G;
+  const int64_t r = ((int64_t)blockIdx.x * BT + threadIdx.x) / SPMV_G;
   const int q0 = r < ntot ? rinst[r] : 0;
   const bool active = r < ntot && (live == nullptr || live[q0]);
-  double s0[NC], s1[NC];
+  double s[NC];
 #pragma unroll
-  for (int q = 0; q < NC; ++q) { s0[q] = 0.0; s1[q] = 0.0; }
+  for (int q = 0; q < NC; ++q) s[q] = 0.0;
   if (active) {
     const DevSpace& sp = spaces[q0];
     const int64_t base = dofbase[q0];
@@ -41,45 +38,29 @@ __global__ __launch_bounds__(BT) void k_spmv_b(const int* __restrict__ rinst, co
     const int64_t rl = r - base;
     const int i = (int)(rl % n), j = (int)(rl / n);
     const int lx = sp.lo[i], wx = sp.hi[i] - sp.lo[i] + 1, ly = sp.lo[j];
-    const int64_t k0 = sp.rowptr[rl], len = sp.rowptr[rl + 1] - k0;
-    for (int o = g; o < len; o += SPB_G) {
-      const int64_t col = base + (int64_t)(ly + o / wx) * n + lx + o % wx;
-      const double v0 = A0[k0 + o];
-      const double v1 = A1 ? A1[k0 + o] : 0.0;
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const double xv = X[col + q * ldx];
-        s0[q] += v0 * xv;
-        s1[q] += v1 * xv;
-      }
-    }
+    const int64_t k0 = sp.rowptr[rl];
+    tensor_row_sum<NC>(A + k0, (int)(sp.rowptr[rl + 1] - k0), X + base + (int64_t)ly * n + lx, ldx, n, wx, g, s);
   }
 #pragma unroll
   for (int q = 0; q < NC; ++q)
 #pragma unroll
-    for (int off = SPB_G / 2; off > 0; off >>= 1) {
-      s0[q] += __shfl_xor(s0[q], off, SPB_G);
-      s1[q] += __shfl_xor(s1[q], off, SPB_G);
-    }
+    for (int off = SPMV_G / 2; off > 0; off >>= 1) s[q] += __shfl_xor(s[q], off, SPMV_G);
   if (active && g == 0) {
-    const double c0 = a0_sig ? a0 * isig[q0] : a0;
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-      double val = c0 * s0[q] + a1 * s1[q];
+      double val = s[q];
       if (Z) val += bz * Z[r + q * ldz];
       Y[r + q * ldy] = val;
-      if (Y2) Y2[r + q * ldy2] = s0[q];
     }
   }
 }
 
-void launch_spmv_b(const BatchDev& B, int ncols, const double* A0, double a0, int a0_sig, const double* A1,
-                   double a1, const double* X, int64_t ldx, double* Y, int64_t ldy, const double* Z, int64_t ldz,
-                   double bz, double* Y2, int64_t ldy2, hipStream_t st) {
-  const int64_t blocks = (B.ntot * SPB_G + BT - 1) / BT;
+void launch_spmv_b(const BatchDev& B, int ncols, const double* A, const double* X, int64_t ldx, double* Y,
+                   int64_t ldy, const double* Z, int64_t ldz, double bz, hipStream_t st) {
+  const int64_t blocks = (B.ntot * SPMV_G + BT - 1) / BT;
 #define RIGA_SPMVB(NC)                                                                                        \
-  hipLaunchKernelGGL(k_spmv_b<NC>, dim3((unsigned)blocks), dim3(BT), 0, st, B.rinst, B.spaces, B.dofbase, B.sig, \
-                     B.live, B.ntot, A0, a0, a0_sig, A1, a1, X, ldx, Y, ldy, Z, ldz, bz, Y2, ldy2)
+  hipLaunchKernelGGL(k_spmv_b<NC>, dim3((unsigned)blocks), dim3(BT), 0, st, B.rinst, B.spaces, B.dofbase, B.live, \
+                     B.ntot, A, X, ldx, Y, ldy, Z, ldz, bz)
   switch (ncols) {
     case 1: RIGA_SPMVB(1); break;
     case 2: RIGA_SPMVB(2); break;
@@ -151,44 +132,9 @@ __global__ __launch_bounds__(BT) void k_dots_b(const int4* __restrict__ db, cons
   const int nc = kcur ? kcur[b.x] + nc_add : nc_fixed;
   const int64_t i0 = b.y, i1 = b.z;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int NW = BT / 64;
   double* out = partial + (int64_t)blockIdx.x * pstride;
-  for (int c = wave; c < nc; c += 2 * NW) {
-    const int c2 = c + NW;
-    const bool two = c2 < nc;
-    double acc[NQ], acc2[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) { acc[q] = 0.0; acc2[q] = 0.0; }
-    const double* au = Au + (int64_t)c * lda;
-    const double* al = Al ? Al + (int64_t)c * lda : nullptr;
-    const double* bu = Au + (int64_t)(two ? c2 : c) * lda;
-    const double* bl = Al ? Al + (int64_t)(two ? c2 : c) * lda : nullptr;
-    for (int64_t i = i0 + lane; i < i1; i += 64) {
-      const double u = au[i], u2 = bu[i];
-      const double l = al ? al[i] : 0.0, l2 = bl ? bl[i] : 0.0;
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const double xu = Xu[i + q * ldx];
-        const double xl = Xl ? Xl[i + q * ldx] : 0.0;
-        acc[q] += u * xu + l * xl;
-        acc2[q] += u2 * xu + l2 * xl;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        acc[q] += __shfl_xor(acc[q], off, 64);
-        acc2[q] += __shfl_xor(acc2[q], off, 64);
-      }
-    if (lane == 0) {
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        out[c * NQ + q] = acc[q];
-        if (two) out[c2 * NQ + q] = acc2[q];
-      }
-    }
-  }
+  dots_body<NQ, BT / 64>(i0, i1, nc, Au, Al, lda, Xu, Xl, ldx, lane, wave,
+                         [&](int c, int q, double v) { out[c * NQ + q] = v; });
 }
 
 // out[p * ostride + idx] = sum over the problem's dot blocks of the partials
@@ -243,22 +189,7 @@ __global__ __launch_bounds__(BT) void k_cgs_update_b(const int4* __restrict__ rb
   __syncthreads();
   const int64_t i = b.y + threadIdx.x;
   if (i >= b.z) return;
-  const double* As[3] = {A0, A1, A2};
-  double* Zs[3] = {Z0, Z1, Z2};
-#pragma unroll
-  for (int m = 0; m < 3; ++m) {
-    if (!As[m]) continue;
-    double z[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) z[q] = Zs[m][i + q * ld];
-    for (int c = 0; c < nc; ++c) {
-      const double a = As[m][i + (int64_t)c * ld];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) z[q] -= a * hs[c * NQ + q];
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) Zs[m][i + q * ld] = z[q];
-  }
+  cgs_update_row<NQ>(i, nc, hs, A0, Z0, A1, Z1, A2, Z2, ld, ld);
 }
 
 void launch_cgs_update_b(const BatchDev& B, int nc_add, int nq, const double* h, int hstride, const double* A0,

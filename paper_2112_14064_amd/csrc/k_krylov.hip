@@ -16,66 +16,47 @@ namespace riga {
 // (ii, jj) with ii in [lo(i), hi(i)], jj in [lo(j), hi(j)], stored row-major
 // in that order, so no column-index array is read.  16 lanes per row.
 constexpr int SPMV_THREADS = 256;
-constexpr int SPMV_G = 16;
 
 template <int NC>
 __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(
     int n, const int* __restrict__ lo, const int* __restrict__ hi, const int64_t* __restrict__ rowptr,
-    int64_t ndof, const double* __restrict__ A0, double a0, const double* __restrict__ A1, double a1,
-    const double* __restrict__ A2, double a2, const double* __restrict__ X, int64_t ldx,
+    int64_t ndof, const double* __restrict__ A, double a, const double* __restrict__ X, int64_t ldx,
     double* __restrict__ Y, int64_t ldy, const double* __restrict__ Z, int64_t ldz, double bz,
     double* __restrict__ Y2, int64_t ldy2) {
   const int g = threadIdx.x % SPMV_G;
   const int64_t r = ((int64_t)blockIdx.x * SPMV_THREADS + threadIdx.x) / SPMV_G;
   const bool active = r < ndof;
-  double s0[NC], s1[NC], s2[NC];
+  double s[NC];
 #pragma unroll
-  for (int q = 0; q < NC; ++q) { s0[q] = 0.0; s1[q] = 0.0; s2[q] = 0.0; }
+  for (int q = 0; q < NC; ++q) s[q] = 0.0;
   if (active) {
     const int i = (int)(r % n), j = (int)(r / n);
     const int lx = lo[i], wx = hi[i] - lo[i] + 1, ly = lo[j];
-    const int64_t k0 = rowptr[r], len = rowptr[r + 1] - k0;
-    for (int o = g; o < len; o += SPMV_G) {
-      const int64_t col = (int64_t)(ly + o / wx) * n + lx + o % wx;
-      const double v0 = A0[k0 + o];
-      const double v1 = A1 ? A1[k0 + o] : 0.0;
-      const double v2 = A2 ? A2[k0 + o] : 0.0;
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const double xv = X[col + q * ldx];
-        s0[q] += v0 * xv;
-        s1[q] += v1 * xv;
-        s2[q] += v2 * xv;
-      }
-    }
+    const int64_t k0 = rowptr[r];
+    tensor_row_sum<NC>(A + k0, (int)(rowptr[r + 1] - k0), X + (int64_t)ly * n + lx, ldx, n, wx, g, s);
   }
 #pragma unroll
   for (int q = 0; q < NC; ++q)
 #pragma unroll
-    for (int off = SPMV_G / 2; off > 0; off >>= 1) {
-      s0[q] += __shfl_xor(s0[q], off, SPMV_G);
-      s1[q] += __shfl_xor(s1[q], off, SPMV_G);
-      s2[q] += __shfl_xor(s2[q], off, SPMV_G);
-    }
+    for (int off = SPMV_G / 2; off > 0; off >>= 1) s[q] += __shfl_xor(s[q], off, SPMV_G);
   if (active && g == 0) {
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-      double val = a0 * s0[q] + a1 * s1[q] + a2 * s2[q];
+      double val = a * s[q];
       if (Z) val += bz * Z[r + q * ldz];
       Y[r + q * ldy] = val;
-      if (Y2) Y2[r + q * ldy2] = s0[q];
+      if (Y2) Y2[r + q * ldy2] = s[q];
     }
   }
 }
 
-void launch_spmv(const DevSpace& s, int64_t ndof, int ncols,
-                 const double* A0, double a0, const double* A1, double a1, const double* A2, double a2,
-                 const double* X, int64_t ldx, double* Y, int64_t ldy,
-                 const double* Z, int64_t ldz, double bz, double* Y2, int64_t ldy2, hipStream_t st) {
+void launch_spmv(const DevSpace& s, int64_t ndof, int ncols, const double* A, double a, const double* X,
+                 int64_t ldx, double* Y, int64_t ldy, const double* Z, int64_t ldz, double bz, double* Y2,
+                 int64_t ldy2, hipStream_t st) {
   int64_t blocks = (ndof * SPMV_G + SPMV_THREADS - 1) / SPMV_THREADS;
 #define RIGA_SPMV(NC)                                                                              \
   hipLaunchKernelGGL(k_spmv<NC>, dim3((unsigned)blocks), dim3(SPMV_THREADS), 0, st, s.n, s.lo, s.hi, \
-                     s.rowptr, ndof, A0, a0, A1, a1, A2, a2, X, ldx, Y, ldy, Z, ldz, bz, Y2, ldy2)
+                     s.rowptr, ndof, A, a, X, ldx, Y, ldy, Z, ldz, bz, Y2, ldy2)
   switch (ncols) {
     case 1: RIGA_SPMV(1); break;
     case 2: RIGA_SPMV(2); break;
@@ -178,43 +159,9 @@ __global__ __launch_bounds__(DOT_THREADS) void k_dots(
   const int64_t i0 = (int64_t)blockIdx.x * per;
   const int64_t i1 = min(n, i0 + per);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int NW = DOT_THREADS / 64;
-  for (int c = wave; c < nc; c += 2 * NW) {
-    const int c2 = c + NW;
-    const bool two = c2 < nc;
-    double acc[NQ], acc2[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) { acc[q] = 0.0; acc2[q] = 0.0; }
-    const double* au = Au + (int64_t)c * lda;
-    const double* al = Al ? Al + (int64_t)c * lda : nullptr;
-    const double* bu = Au + (int64_t)(two ? c2 : c) * lda;
-    const double* bl = Al ? Al + (int64_t)(two ? c2 : c) * lda : nullptr;
-    for (int64_t i = i0 + lane; i < i1; i += 64) {
-      const double u = au[i], u2 = bu[i];
-      const double l = al ? al[i] : 0.0, l2 = bl ? bl[i] : 0.0;
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const double xu = Xu[i + q * ldx];
-        const double xl = Xl ? Xl[i + q * ldx] : 0.0;
-        acc[q] += u * xu + l * xl;
-        acc2[q] += u2 * xu + l2 * xl;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        acc[q] += __shfl_xor(acc[q], off, 64);
-        acc2[q] += __shfl_xor(acc2[q], off, 64);
-      }
-    if (lane == 0) {
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        partial[((int64_t)c * NQ + q) * nblk + blockIdx.x] = acc[q];
-        if (two) partial[((int64_t)c2 * NQ + q) * nblk + blockIdx.x] = acc2[q];
-      }
-    }
-  }
+  const int blk = blockIdx.x;
+  dots_body<NQ, DOT_THREADS / 64>(i0, i1, nc, Au, Al, lda, Xu, Xl, ldx, lane, wave,
+                                  [&](int c, int q, double v) { partial[((int64_t)c * NQ + q) * nblk + blk] = v; });
 }
 
 __global__ __launch_bounds__(256) void k_dots_final(int nout, int nblk, const double* __restrict__ partial,
@@ -223,8 +170,18 @@ __global__ __launch_bounds__(256) void k_dots_final(int nout, int nblk, const do
   const int idx = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (idx >= nout) return;
   const double* p = partial + (int64_t)idx * nblk;
+  // partials lane, lane + 64, ... in that order, eight loads in flight
   double s = 0.0;
-  for (int b = lane; b < nblk; b += 64) s += p[b];
+  for (int b0 = 0; b0 < nblk; b0 += 64 * 8) {
+    double v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int b = b0 + e * 64 + lane;
+      v[e] = b < nblk ? p[b] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s += v[e];
+  }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if (lane == 0) out[idx] = s;
@@ -266,22 +223,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_cgs_update(
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * UPD_THREADS + threadIdx.x;
   if (i >= n) return;
-  const double* As[3] = {A0, A1, A2};
-  double* Zs[3] = {Z0, Z1, Z2};
-#pragma unroll
-  for (int m = 0; m < 3; ++m) {
-    if (!As[m]) continue;
-    double z[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) z[q] = Zs[m][i + q * ldz];
-    for (int c = 0; c < nc; ++c) {
-      const double a = As[m][i + (int64_t)c * lda];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) z[q] -= a * hs[c * NQ + q];
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) Zs[m][i + q * ldz] = z[q];
-  }
+  cgs_update_row<NQ>(i, nc, hs, A0, Z0, A1, Z1, A2, Z2, lda, ldz);
 }
 
 void launch_cgs_update(int64_t n, int nc, int nq, const double* h,

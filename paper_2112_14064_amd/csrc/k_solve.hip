@@ -37,6 +37,17 @@ struct Pack {
   typedef E V __attribute__((ext_vector_type(K)));
 };
 
+// One round of a wave: SG group loads g0 .. g0 + SG - 1.  Groups past the
+// end are clamped to the last group (an address of the node) and masked in
+// fma_round: the loads carry no branch, so the compiler can keep the next
+// round in flight while the current one is used.
+template <int SG, class V>
+__device__ __forceinline__ void load_round(V (&a)[SG], const V* p, int g0, int gend, int64_t stride) {
+  const int glast = max(gend - 1, 0);
+#pragma unroll
+  for (int u = 0; u < SG; ++u) a[u] = p[(int64_t)min(g0 + u, glast) * stride];
+}
+
 // acc[q] of row `lane` summed over the waves through LDS; wave 0 ends with the
 // total for its lane.
 template <int NR, int NW>
@@ -55,82 +66,110 @@ __device__ __forceinline__ void reduce_waves(double (&acc)[NR], double* red, int
   }
 }
 
+// acc[q] += sum over the SG groups of a round (group g0 + u of the wave) of
+// the K entries of each group times the LDS vector entries they multiply;
+// groups at or past gend contribute nothing.
+template <int NR, int SG, int K, class V>
+__device__ __forceinline__ void fma_round(double (&acc)[NR], const V (&a)[SG], int g0, int gend,
+                                          const double* vec, int nlast) {
+#pragma unroll
+  for (int u = 0; u < SG; ++u) {
+    const bool in = g0 + u < gend;
+#pragma unroll
+    for (int e = 0; e < K; ++e) {
+      const int j = min((g0 + u) * K + e, nlast);
+      const double av = in ? (double)a[u][e] : 0.0;
+#pragma unroll
+      for (int q = 0; q < NR; ++q) acc[q] += av * vec[j * NR + q];
+    }
+  }
+}
+
+// Forward sweep of one level, one task (64 rows of F of a node) per workgroup.
+// The factor does not depend on the front vector: two rounds of factor loads
+// are in flight while the front is gathered, and rounds alternate between two
+// register buffers so the next round is always loading.
 template <int NR, class E, int NW, int SG>
-__global__ __launch_bounds__(NW * 64) void k_fwd(DevTree t, const int4* __restrict__ tasks,
+__global__ __launch_bounds__(NW * 64) void k_fwd(DevTree t, const SweepTask* __restrict__ tasks,
                                             const E* __restrict__ Lp,
                                             const double* __restrict__ b, int64_t ldb,
                                             double* __restrict__ y, int64_t ldy,
                                             double* __restrict__ upd) {
   extern __shared__ double shm[];
   double* f = shm;                       // f[pos * NR + q], front vector
-  const int4 tk = tasks[blockIdx.x];
-  const int v = tk.x, r0 = tk.y, r1 = tk.z;
-  const int nf = t.nf[v], no = t.no[v];
-  if (t.ilive != nullptr && !t.ilive[t.inst[v]]) return;
+  const SweepTask tk = tasks[blockIdx.x];
+  if (t.ilive != nullptr && !t.ilive[tk.inst]) return;
+  const int r0 = tk.r0, r1 = tk.r1, nf = tk.nf, no = tk.no;
   double* red = shm + (size_t)nf * NR;   // NW x SR x NR partial sums
-  const int* fd = t.fdofs + t.foff[v];
+  const int* fd = t.fdofs + tk.foff;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-  for (int p = tid; p < nf; p += NW * 64)
-#pragma unroll
-    for (int q = 0; q < NR; ++q) f[p * NR + q] = (p < no) ? b[fd[p] + q * ldb] : 0.0;
-  __syncthreads();
-  for (int ci = t.coff[v]; ci < t.coff[v + 1]; ++ci) {
-    const int c = t.clist[ci];
-    const int nbc = t.nb[c];
-    const int* mp = t.maps + t.moff[c];
-    const double* uc = upd + (int64_t)t.voff[c] * NR;
-    for (int k = tid; k < nbc; k += NW * 64)
-#pragma unroll
-      for (int q = 0; q < NR; ++q) f[mp[k] * NR + q] += uc[k * NR + q];
-    __syncthreads();
-  }
   const int r = r0 + lane;
   const bool live = r < r1;
   // columns past the diagonal of L_oo^{-1} are exact zeros: an own-row block
   // stops at its last row's diagonal
   const int jend = (r1 - 1 < no) ? r1 : no;
+  constexpr int K = Pack<E>::K;
+  constexpr int STEP = NW * SG;
+  typedef typename Pack<E>::V V;
+  // group g of row r at col[g * nf]; entries past the diagonal are stored zeros
+  const V* col = reinterpret_cast<const V*>(Lp + tk.poff) + (live ? r : r0);
+  const int gend = (jend + K - 1) / K;
+  int g = __builtin_amdgcn_readfirstlane(wave) * SG;
+  V A[SG], B[SG];
+  load_round<SG>(A, col, g, gend, nf);
+  load_round<SG>(B, col, g + STEP, gend, nf);
+  const int dst = fd[min(r, nf - 1)];      // used by own rows only
+
+  // front vector: own entries of b plus the children's update rows, added in
+  // child order (one pass, no barrier per child)
+  const int* gp = t.gptr + tk.foff;
+  for (int p = tid; p < nf; p += NW * 64) {
+    double s[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) s[q] = (p < no) ? b[fd[p] + q * ldb] : 0.0;
+    const int k1 = gp[p + 1];
+    for (int k = gp[p]; k < k1; ++k) {
+      const double* uc = upd + (int64_t)t.gidx[k] * NR;
+#pragma unroll
+      for (int q = 0; q < NR; ++q) s[q] += uc[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) f[p * NR + q] = s[q];
+  }
+  __syncthreads();
   double acc[NR];
 #pragma unroll
   for (int q = 0; q < NR; ++q) acc[q] = 0.0;
-  constexpr int K = Pack<E>::K;
-  typedef typename Pack<E>::V V;
-  // group g of row r at col[g * nf]; entries past the diagonal are stored zeros
-  const V* col = reinterpret_cast<const V*>(Lp + t.lpoff[v]) + (live ? r : r0);
-  const int gend = (jend + K - 1) / K;
-  for (int g0 = wave * SG; g0 < gend; g0 += NW * SG) {
-    V a[SG];
-#pragma unroll
-    for (int u = 0; u < SG; ++u) a[u] = (g0 + u < gend) ? col[(int64_t)(g0 + u) * nf] : V{};
-#pragma unroll
-    for (int u = 0; u < SG; ++u)
-#pragma unroll
-      for (int e = 0; e < K; ++e) {
-        const int j = min((g0 + u) * K + e, nf - 1);
-#pragma unroll
-        for (int q = 0; q < NR; ++q) acc[q] += (double)a[u][e] * f[j * NR + q];
-      }
+  while (g < gend) {
+    fma_round<NR, SG, K>(acc, A, g, gend, f, nf - 1);
+    load_round<SG>(A, col, g + 2 * STEP, gend, nf);
+    g += STEP;
+    if (g >= gend) break;
+    fma_round<NR, SG, K>(acc, B, g, gend, f, nf - 1);
+    load_round<SG>(B, col, g + 2 * STEP, gend, nf);
+    g += STEP;
   }
   reduce_waves<NR, NW>(acc, red, lane, wave);
   if (wave == 0 && live) {
     if (r < no) {
 #pragma unroll
-      for (int q = 0; q < NR; ++q) y[fd[r] + q * ldy] = acc[q];
+      for (int q = 0; q < NR; ++q) y[dst + q * ldy] = acc[q];
     } else {
-      double* uv = upd + (int64_t)(t.voff[v] + r - no) * NR;
+      double* uv = upd + (int64_t)(tk.voff + r - no) * NR;
 #pragma unroll
       for (int q = 0; q < NR; ++q) uv[q] = f[r * NR + q] - acc[q];
     }
   }
 }
 
-// Backward sweep of one level.  The sweep's own result x (needed by the
-// descendants as boundary values) is kept in xs, negated when `neg` is set.
-// Optional outputs: ru = scale (x + base) (base may be null; ru may alias
-// base: each entry is read and written by one thread) and
+// Backward sweep of one level, one task (64 own columns of a node) per
+// workgroup, loads pipelined as in the forward sweep.  The sweep's own result
+// x (needed by the descendants as boundary values) is kept in xs, negated
+// when `neg` is set.  Optional outputs: ru = scale (x + base) (base may be
+// null; ru may alias base: each entry is read and written by one thread) and
 // rl = sig val + v_u, where val is the ru value or, without ru, the xs value.
 template <int NR, class E, int NW, int SG>
-__global__ __launch_bounds__(NW * 64) void k_bwd(DevTree t, const int4* __restrict__ tasks,
+__global__ __launch_bounds__(NW * 64) void k_bwd(DevTree t, const SweepTask* __restrict__ tasks,
                                             const E* __restrict__ Tp,
                                             const double* __restrict__ y, int64_t ldy,
                                             double* __restrict__ xs, int64_t ldxs, int neg,
@@ -140,14 +179,28 @@ __global__ __launch_bounds__(NW * 64) void k_bwd(DevTree t, const int4* __restri
                                             int64_t ldv, double sig) {
   extern __shared__ double shm[];
   double* w = shm;                       // [y_own; -x_bnd]
-  const int4 tk = tasks[blockIdx.x];
-  const int v = tk.x, a0 = tk.y, a1 = tk.z;
-  const int nf = t.nf[v], no = t.no[v];
-  if (t.ilive != nullptr && !t.ilive[t.inst[v]]) return;
-  if (t.inst != nullptr) sig = t.isig[t.inst[v]];
+  const SweepTask tk = tasks[blockIdx.x];
+  if (t.ilive != nullptr && !t.ilive[tk.inst]) return;
+  const int a0 = tk.r0, a1 = tk.r1, nf = tk.nf, no = tk.no;
   double* red = shm + (size_t)nf * NR;
-  const int* fd = t.fdofs + t.foff[v];
+  const int* fd = t.fdofs + tk.foff;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int a = a0 + lane;
+  const bool live = a < a1;
+  constexpr int K = Pack<E>::K;
+  constexpr int STEP = NW * SG;
+  typedef typename Pack<E>::V V;
+  // rows of F in groups of K: group g of own column a at row[g * no]; rows
+  // above the diagonal of L_oo^{-T} are stored zeros, so the block starts at
+  // group a0 / K
+  const V* row = reinterpret_cast<const V*>(Tp + tk.poff) + (live ? a : a0);
+  const int gend = (nf + K - 1) / K;
+  int g = a0 / K + __builtin_amdgcn_readfirstlane(wave) * SG;
+  V A[SG], B[SG];
+  load_round<SG>(A, row, g, gend, no);
+  load_round<SG>(B, row, g + STEP, gend, no);
+  const int d = fd[min(a, no - 1)];       // used by live lanes only
+  if (t.inst != nullptr) sig = t.isig[tk.inst];
 
   for (int p = tid; p < nf; p += NW * 64)
 #pragma unroll
@@ -162,34 +215,20 @@ __global__ __launch_bounds__(NW * 64) void k_bwd(DevTree t, const int4* __restri
       w[p * NR + q] = val;
     }
   __syncthreads();
-  const int a = a0 + lane;
-  const bool live = a < a1;
   double acc[NR];
 #pragma unroll
   for (int q = 0; q < NR; ++q) acc[q] = 0.0;
-  // entries above the diagonal of L_oo^{-T} vanish: start at the block's first row
-  constexpr int K = Pack<E>::K;
-  typedef typename Pack<E>::V V;
-  // rows of F in groups of K: group g of own column a at row[g * no]; rows
-  // above the diagonal are stored zeros, so the block starts at group a0 / K
-  const V* row = reinterpret_cast<const V*>(Tp + t.tpoff[v]) + (live ? a : a0);
-  const int gbeg = a0 / K, gend = (nf + K - 1) / K;
-  for (int g0 = gbeg + wave * SG; g0 < gend; g0 += NW * SG) {
-    V e[SG];
-#pragma unroll
-    for (int u = 0; u < SG; ++u) e[u] = (g0 + u < gend) ? row[(int64_t)(g0 + u) * no] : V{};
-#pragma unroll
-    for (int u = 0; u < SG; ++u)
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const int i = min((g0 + u) * K + k, nf - 1);
-#pragma unroll
-        for (int q = 0; q < NR; ++q) acc[q] += (double)e[u][k] * w[i * NR + q];
-      }
+  while (g < gend) {
+    fma_round<NR, SG, K>(acc, A, g, gend, w, nf - 1);
+    load_round<SG>(A, row, g + 2 * STEP, gend, no);
+    g += STEP;
+    if (g >= gend) break;
+    fma_round<NR, SG, K>(acc, B, g, gend, w, nf - 1);
+    load_round<SG>(B, row, g + 2 * STEP, gend, no);
+    g += STEP;
   }
   reduce_waves<NR, NW>(acc, red, lane, wave);
   if (wave == 0 && live) {
-    const int d = fd[a];
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
       double val = neg ? -acc[q] : acc[q];
@@ -214,14 +253,14 @@ void sweep_variant(int v, int* waves, int* groups) {
 namespace {
 
 template <int NR, class E, int NW, int SG>
-void fwd_one(const DevTree& t, const int4* tasks, int count, const E* Lp, const double* b, int64_t ldb, double* y,
+void fwd_one(const DevTree& t, const SweepTask* tasks, int count, const E* Lp, const double* b, int64_t ldb, double* y,
              int64_t ldy, double* upd, int max_front, hipStream_t st) {
   const size_t shm = ((size_t)max_front + NW * SR) * NR * sizeof(double);
   hipLaunchKernelGGL((k_fwd<NR, E, NW, SG>), dim3(count), dim3(NW * 64), shm, st, t, tasks, Lp, b, ldb, y, ldy, upd);
 }
 
 template <int NR, class E>
-void fwd_shape(int variant, const DevTree& t, const int4* tasks, int count, const E* Lp, const double* b,
+void fwd_shape(int variant, const DevTree& t, const SweepTask* tasks, int count, const E* Lp, const double* b,
                int64_t ldb, double* y, int64_t ldy, double* upd, int max_front, hipStream_t st) {
   switch (variant) {
     case 1: fwd_one<NR, E, 8, 2>(t, tasks, count, Lp, b, ldb, y, ldy, upd, max_front, st); break;
@@ -234,7 +273,7 @@ void fwd_shape(int variant, const DevTree& t, const int4* tasks, int count, cons
 }
 
 template <class E>
-void fwd_nr(int nrhs, int variant, const DevTree& t, const int4* tasks, int count, const E* Lp, const double* b,
+void fwd_nr(int nrhs, int variant, const DevTree& t, const SweepTask* tasks, int count, const E* Lp, const double* b,
             int64_t ldb, double* y, int64_t ldy, double* upd, int max_front, hipStream_t st) {
   switch (nrhs) {
     case 1: fwd_shape<1, E>(variant, t, tasks, count, Lp, b, ldb, y, ldy, upd, max_front, st); break;
@@ -245,7 +284,7 @@ void fwd_nr(int nrhs, int variant, const DevTree& t, const int4* tasks, int coun
 }
 
 template <int NR, class E, int NW, int SG>
-void bwd_one(const DevTree& t, const int4* tasks, int count, const E* Tp, const double* y, int64_t ldy,
+void bwd_one(const DevTree& t, const SweepTask* tasks, int count, const E* Tp, const double* y, int64_t ldy,
              const BwdOut& o, int max_front, hipStream_t st) {
   const size_t shm = ((size_t)max_front + NW * SR) * NR * sizeof(double);
   hipLaunchKernelGGL((k_bwd<NR, E, NW, SG>), dim3(count), dim3(NW * 64), shm, st, t, tasks, Tp, y, ldy, o.xs,
@@ -253,7 +292,7 @@ void bwd_one(const DevTree& t, const int4* tasks, int count, const E* Tp, const 
 }
 
 template <int NR, class E>
-void bwd_shape(int variant, const DevTree& t, const int4* tasks, int count, const E* Tp, const double* y,
+void bwd_shape(int variant, const DevTree& t, const SweepTask* tasks, int count, const E* Tp, const double* y,
                int64_t ldy, const BwdOut& o, int max_front, hipStream_t st) {
   switch (variant) {
     case 1: bwd_one<NR, E, 8, 2>(t, tasks, count, Tp, y, ldy, o, max_front, st); break;
@@ -266,7 +305,7 @@ void bwd_shape(int variant, const DevTree& t, const int4* tasks, int count, cons
 }
 
 template <class E>
-void bwd_nr(int nrhs, int variant, const DevTree& t, const int4* tasks, int count, const E* Tp, const double* y,
+void bwd_nr(int nrhs, int variant, const DevTree& t, const SweepTask* tasks, int count, const E* Tp, const double* y,
             int64_t ldy, const BwdOut& o, int max_front, hipStream_t st) {
   switch (nrhs) {
     case 1: bwd_shape<1, E>(variant, t, tasks, count, Tp, y, ldy, o, max_front, st); break;
@@ -278,7 +317,7 @@ void bwd_nr(int nrhs, int variant, const DevTree& t, const int4* tasks, int coun
 
 }  // namespace
 
-void launch_fwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* Lp64,
+void launch_fwd_level(const DevTree& t, const SweepTask* tasks, int count, int nrhs, const double* Lp64,
                       const float* Lp32, const double* b, int64_t ldb, double* y, int64_t ldy, double* upd,
                       int max_front, int variant, hipStream_t st) {
   if (count <= 0) return;
@@ -286,7 +325,7 @@ void launch_fwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, 
   else fwd_nr<double>(nrhs, variant, t, tasks, count, Lp64, b, ldb, y, ldy, upd, max_front, st);
 }
 
-void launch_bwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* Tp64,
+void launch_bwd_level(const DevTree& t, const SweepTask* tasks, int count, int nrhs, const double* Tp64,
                       const float* Tp32, const double* y, int64_t ldy, const BwdOut& o, int max_front, int variant,
                       hipStream_t st) {
   if (count <= 0) return;

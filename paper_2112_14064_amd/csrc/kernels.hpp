@@ -22,6 +22,11 @@ struct DevTree {
   const int* foff; const int* fdofs; const int* fkey; const int* fpos;
   const int* coff; const int* clist; const int* moff; const int* maps;
   const int* voff;              // per node: offset of its solve update vector (nb entries)
+  // Forward-sweep gather lists: front position foff[v] + p receives the update
+  // rows gidx[gptr[foff[v] + p] .. gptr[foff[v] + p + 1]) (rows of the update
+  // array, children in clist order), so a front is assembled without a pass
+  // per child.
+  const int* gptr; const int* gidx;
   const int64_t* doff;          // per node: first 64x64 block of its diagonal inverses
   const unsigned char* prec;    // per node: 1 = FP32 front (mixed factor), or null (all FP64)
   const int64_t* lpoff;         // per node: sweep layouts of F (multiples of 4 elements):
@@ -71,11 +76,24 @@ void launch_combine3(int64_t nnz, double am, const double* M, double ac, const d
 // One launch per tree level; tasks[k] = {node, first row, end row, 0}.  The
 // level's factor is read in its sweep layouts, FP64 (Lp64/Tp64) or FP32
 // (Lp32/Tp32 non-null).
+// One task of a sweep level: rows [r0, r1) of F of node v (forward) or own
+// columns [r0, r1) (backward), with the node fields the workgroup needs, so
+// that it starts from a single load.  poff: the node's lpoff (forward) or
+// tpoff (backward); inst: the node's problem in a forest, else 0.
+struct alignas(16) SweepTask {
+  int v, r0, r1, nf;
+  int no, foff, voff, inst;
+  int64_t poff, unused;
+};
 // `variant` selects the task tile shape (0 .. sweep_variants()-1, see sweep_variant).
-void launch_fwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* Lp64,
+void launch_fwd_level(const DevTree& t, const SweepTask* tasks, int count, int nrhs, const double* Lp64,
                       const float* Lp32, const double* b, int64_t ldb, double* y, int64_t ldy, double* upd,
                       int max_front, int variant, hipStream_t st);
 int sweep_variants();
+// Variants the solver starts from before any autotuning: levels with many
+// tasks (bandwidth-bound) take 4-wave tasks, levels with few tasks
+// (latency-bound) 8 waves with short rounds.
+constexpr int SWEEP_WIDE = 3, SWEEP_NARROW = 1;
 // Waves per task and column groups per wave and round of a sweep variant.
 void sweep_variant(int v, int* waves, int* groups);
 // Outputs of the backward sweep (see k_bwd): xs holds the sweep's solution
@@ -86,17 +104,16 @@ struct BwdOut {
   double* ru = nullptr; int64_t ldr = 0; double scale = 1.0;
   double* rl = nullptr; const double* v_u = nullptr; int64_t ldv = 0; double sig = 0.0;
 };
-void launch_bwd_level(const DevTree& t, const int4* tasks, int count, int nrhs, const double* Tp64,
+void launch_bwd_level(const DevTree& t, const SweepTask* tasks, int count, int nrhs, const double* Tp64,
                       const float* Tp32, const double* y, int64_t ldy, const BwdOut& o, int max_front, int variant,
                       hipStream_t st);
 
 // --- Krylov building blocks -----------------------------------------------------
-// Y = a0 A0 X + a1 A1 X + a2 A2 X + bz Z   (A* share the CSR pattern; A1/A2 may be null)
-// and optionally Y2 = A0 X.  X, Y, Z, Y2: ndof x ncols (ld given), ncols <= 8.
-void launch_spmv(const DevSpace& s, int64_t ndof, int ncols,
-                 const double* A0, double a0, const double* A1, double a1, const double* A2, double a2,
-                 const double* X, int64_t ldx, double* Y, int64_t ldy,
-                 const double* Z, int64_t ldz, double bz, double* Y2, int64_t ldy2, hipStream_t st);
+// Y = a A X + bz Z (Z may be null) and optionally Y2 = A X.  X, Y, Z, Y2:
+// ndof x ncols (ld given), ncols <= 8.
+void launch_spmv(const DevSpace& s, int64_t ndof, int ncols, const double* A, double a, const double* X,
+                 int64_t ldx, double* Y, int64_t ldy, const double* Z, int64_t ldz, double bz, double* Y2,
+                 int64_t ldy2, hipStream_t st);
 // Y0 = A0 X, Y1 = A1 X, Y2 = A2 X in one pass over X (ncols <= 8, common ld of the Y).
 void launch_spmv3(const DevSpace& s, int64_t ndof, int ncols, const double* A0, const double* A1, const double* A2,
                   const double* X, int64_t ldx, double* Y0, double* Y1, double* Y2, int64_t ldy, hipStream_t st);
@@ -163,11 +180,10 @@ struct BatchDev {
   double* partial = nullptr;        // dot partial sums, pstride per dot block
   int pstride = 0;
 };
-// Y = a0 s A0 X + a1 A1 X + bz Z, Y2 = A0 X (s = the row's sigma if a0_sig);
-// ncols <= 8, every vector ntot x ncols with the given leading dimensions.
-void launch_spmv_b(const BatchDev& B, int ncols, const double* A0, double a0, int a0_sig, const double* A1,
-                   double a1, const double* X, int64_t ldx, double* Y, int64_t ldy, const double* Z, int64_t ldz,
-                   double bz, double* Y2, int64_t ldy2, hipStream_t st);
+// Y = A X + bz Z (Z may be null) on every live problem's rows; ncols <= 8,
+// every vector ntot x ncols with the given leading dimensions.
+void launch_spmv_b(const BatchDev& B, int ncols, const double* A, const double* X, int64_t ldx, double* Y,
+                   int64_t ldy, const double* Z, int64_t ldz, double bz, hipStream_t st);
 // A = sigma_p M + C per problem (nonzeros of problem p in [nzbase[p], nzbase[p+1])).
 void launch_combine_b(int n, const int64_t* nzbase, int64_t nnz, const double* sig, const double* M, const double* C,
                       double* A, hipStream_t st);

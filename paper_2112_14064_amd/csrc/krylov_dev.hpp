@@ -5,6 +5,154 @@
 
 namespace riga {
 
+// Sparse rows with the implicit tensor sparsity are summed by groups of
+// SPMV_G lanes; a row of up to SPMV_U * SPMV_G stored entries (every degree
+// up to 4) issues all of its loads before the first product, so a row costs
+// one memory latency instead of one per round of lanes.
+constexpr int SPMV_G = 16;
+constexpr int SPMV_U = 6;
+
+// s[q] += sum_o a[o] x[(o / wx) * n + o % wx + q * ldx] over this lane's
+// entries o = g, g + SPMV_G, ... < len (increasing o: the order of a plain loop).
+template <int NC>
+__device__ __forceinline__ void tensor_row_sum(const double* __restrict__ a, int len,
+                                               const double* __restrict__ x, int64_t ldx, int n, int wx, int g,
+                                               double (&s)[NC]) {
+  for (int o0 = 0; o0 < len; o0 += SPMV_U * SPMV_G) {
+    double av[SPMV_U], xv[SPMV_U][NC];
+#pragma unroll
+    for (int u = 0; u < SPMV_U; ++u) {
+      const int o = o0 + u * SPMV_G + g;
+      if (o < len) {
+        const int dy = o / wx;
+        const double* xp = x + (int64_t)dy * n + (o - dy * wx);
+        av[u] = a[o];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) xv[u][q] = xp[q * ldx];
+      } else {
+        av[u] = 0.0;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) xv[u][q] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < SPMV_U; ++u)
+#pragma unroll
+      for (int q = 0; q < NC; ++q) s[q] += av[u] * xv[u][q];
+  }
+}
+
+// Multi-dot body: for the columns c = wave, wave + 2 NW, ... (and c + NW
+// beside each) of Au/Al, the sums over rows [i0, i1) of
+// Au[i,c] Xu[i,q] + Al[i,c] Xl[i,q] (Al, Xl may be null), reduced over the
+// wave; lane 0 calls put(c, q, value).  DOT_U rows per lane per round, every
+// load of a round issued before the first product.
+constexpr int DOT_U = 4;
+
+template <int NQ, int NW, class Put>
+__device__ __forceinline__ void dots_body(int64_t i0, int64_t i1, int nc, const double* __restrict__ Au,
+                                          const double* __restrict__ Al, int64_t lda,
+                                          const double* __restrict__ Xu, const double* __restrict__ Xl,
+                                          int64_t ldx, int lane, int wave, Put put) {
+  for (int c = wave; c < nc; c += 2 * NW) {
+    const int c2 = c + NW;
+    const bool two = c2 < nc;
+    double acc[NQ], acc2[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) { acc[q] = 0.0; acc2[q] = 0.0; }
+    const double* au = Au + (int64_t)c * lda;
+    const double* al = Al ? Al + (int64_t)c * lda : nullptr;
+    const double* bu = Au + (int64_t)(two ? c2 : c) * lda;
+    const double* bl = Al ? Al + (int64_t)(two ? c2 : c) * lda : nullptr;
+    for (int64_t i0r = i0; i0r < i1; i0r += 64 * DOT_U) {
+      double u[DOT_U], u2[DOT_U], l[DOT_U], l2[DOT_U], xu[DOT_U][NQ], xl[DOT_U][NQ];
+#pragma unroll
+      for (int e = 0; e < DOT_U; ++e) {
+        const int64_t i = i0r + e * 64 + lane;
+        const bool in = i < i1;
+        u[e] = in ? au[i] : 0.0;
+        u2[e] = in ? bu[i] : 0.0;
+        l[e] = (in && al) ? al[i] : 0.0;
+        l2[e] = (in && bl) ? bl[i] : 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          xu[e][q] = in ? Xu[i + q * ldx] : 0.0;
+          xl[e][q] = (in && Xl) ? Xl[i + q * ldx] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < DOT_U; ++e)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          acc[q] += u[e] * xu[e][q] + l[e] * xl[e][q];
+          acc2[q] += u2[e] * xu[e][q] + l2[e] * xl[e][q];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        acc[q] += __shfl_xor(acc[q], off, 64);
+        acc2[q] += __shfl_xor(acc2[q], off, 64);
+      }
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        put(c, q, acc[q]);
+        if (two) put(c2, q, acc2[q]);
+      }
+    }
+  }
+}
+
+// Gram--Schmidt update of row i: Zm[i, q] -= sum_c Am[i, c] hs[c * NQ + q]
+// for m = 0, 1, 2 (A1/Z1 and A2/Z2 may be null), columns in increasing order,
+// UPD_U columns per round with all their loads in flight together.
+constexpr int UPD_U = 8;
+
+template <int NQ>
+__device__ __forceinline__ void cgs_update_row(int64_t i, int nc, const double* hs, const double* __restrict__ A0,
+                                               double* __restrict__ Z0, const double* __restrict__ A1,
+                                               double* __restrict__ Z1, const double* __restrict__ A2,
+                                               double* __restrict__ Z2, int64_t lda, int64_t ldz) {
+  const bool has1 = A1 != nullptr, has2 = A2 != nullptr;
+  double z0[NQ], z1[NQ], z2[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    z0[q] = Z0[i + q * ldz];
+    z1[q] = has1 ? Z1[i + q * ldz] : 0.0;
+    z2[q] = has2 ? Z2[i + q * ldz] : 0.0;
+  }
+  for (int c0 = 0; c0 < nc; c0 += UPD_U) {
+    double a0[UPD_U], a1[UPD_U], a2[UPD_U];
+#pragma unroll
+    for (int e = 0; e < UPD_U; ++e) {
+      const bool in = c0 + e < nc;
+      const int64_t o = i + (int64_t)(c0 + e) * lda;
+      a0[e] = in ? A0[o] : 0.0;
+      a1[e] = (in && has1) ? A1[o] : 0.0;
+      a2[e] = (in && has2) ? A2[o] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < UPD_U; ++e) {
+      if (c0 + e >= nc) break;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const double hv = hs[(c0 + e) * NQ + q];
+        z0[q] -= a0[e] * hv;
+        z1[q] -= a1[e] * hv;
+        z2[q] -= a2[e] * hv;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    Z0[i + q * ldz] = z0[q];
+    if (has1) Z1[i + q * ldz] = z1[q];
+    if (has2) Z2[i + q * ldz] = z2[q];
+  }
+}
+
 // End of a block Gram--Schmidt step for one problem (see k_block_normalize):
 // H[0:nc, k+q] = h1 + h2, G = R^T R, H[nc+c, k+q] = R[c][q], Rinv = R^{-1};
 // *flag = 1 when a column lost its norm.  Called by every thread of a block;

@@ -44,7 +44,8 @@ struct riga_problem {
   double *d_L = nullptr, *d_U = nullptr, *d_T = nullptr, *d_upd = nullptr, *d_tmp = nullptr, *d_tmp2 = nullptr;
   double *d_Lp = nullptr, *d_Tp = nullptr;         // F in the sweep layouts
   int64_t lpsize = 0, tpsize = 0;
-  int4 *d_ftasks = nullptr, *d_btasks = nullptr;   // solve tasks, grouped by level
+  riga::SweepTask *d_ftasks = nullptr, *d_btasks = nullptr;   // solve tasks, grouped by level
+  std::vector<int> node_inst;                     // forest: problem of every node (set before setup)
   double* d_D = nullptr;                            // 64x64 diagonal-block inverses
   std::vector<int> lvl_max_no, lvl_max_nf, lvl_max_cnb;
   std::vector<int> fvar, bvar;                      // sweep tile shape per level (autotuned)
