@@ -36,10 +36,11 @@ __global__ __launch_bounds__(BT) void k_spmv_b(const int* __restrict__ rinst, co
     const int64_t base = dofbase[q0];
     const int n = sp.n;
     const int64_t rl = r - base;
-    const int i = (int)(rl % n), j = (int)(rl / n);
-    const int lx = sp.lo[i], wx = sp.hi[i] - sp.lo[i] + 1, ly = sp.lo[j];
-    const int64_t k0 = sp.rowptr[rl];
-    tensor_row_sum<NC>(A + k0, (int)(sp.rowptr[rl + 1] - k0), X + base + (int64_t)ly * n + lx, ldx, n, wx, g, s);
+    const unsigned ru = (unsigned)rl, j = ru / (unsigned)n, i = ru - j * (unsigned)n;
+    const int lx = sp.lo[i], hx = sp.hi[i], ly = sp.lo[j];
+    const int64_t k0 = sp.rowptr[rl], k1 = sp.rowptr[rl + 1];
+    asm volatile("" ::"v"(lx), "v"(hx), "v"(ly));
+    tensor_row_sum<NC>(A + k0, (int)(k1 - k0), X + base + (int64_t)ly * n + lx, ldx, n, hx - lx + 1, g, s);
   }
 #pragma unroll
   for (int q = 0; q < NC; ++q)

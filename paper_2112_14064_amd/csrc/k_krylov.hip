@@ -30,10 +30,13 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(
 #pragma unroll
   for (int q = 0; q < NC; ++q) s[q] = 0.0;
   if (active) {
-    const int i = (int)(r % n), j = (int)(r / n);
-    const int lx = lo[i], wx = hi[i] - lo[i] + 1, ly = lo[j];
-    const int64_t k0 = rowptr[r];
-    tensor_row_sum<NC>(A + k0, (int)(rowptr[r + 1] - k0), X + (int64_t)ly * n + lx, ldx, n, wx, g, s);
+    // rows fit in 32 bits (far more than a device holds); the index loads are
+    // all issued before the first of them is used
+    const unsigned ru = (unsigned)r, j = ru / (unsigned)n, i = ru - j * (unsigned)n;
+    const int lx = lo[i], hx = hi[i], ly = lo[j];
+    const int64_t k0 = rowptr[r], k1 = rowptr[r + 1];
+    asm volatile("" ::"v"(lx), "v"(hx), "v"(ly));
+    tensor_row_sum<NC>(A + k0, (int)(k1 - k0), X + (int64_t)ly * n + lx, ldx, n, hx - lx + 1, g, s);
   }
 #pragma unroll
   for (int q = 0; q < NC; ++q)
@@ -84,7 +87,7 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv3(
 #pragma unroll
   for (int q = 0; q < NC; ++q) { s0[q] = 0.0; s1[q] = 0.0; s2[q] = 0.0; }
   if (active) {
-    const int i = (int)(r % n), j = (int)(r / n);
+    const unsigned ru = (unsigned)r, j = ru / (unsigned)n, i = ru - j * (unsigned)n;
     const int lx = lo[i], wx = hi[i] - lo[i] + 1, ly = lo[j];
     const int64_t k0 = rowptr[r], len = rowptr[r + 1] - k0;
     for (int o = g; o < len; o += SPMV_G) {

@@ -114,21 +114,27 @@ __global__ __launch_bounds__(NW * 64) void k_fwd(DevTree t, const SweepTask* __r
   // group g of row r at col[g * nf]; entries past the diagonal are stored zeros
   const V* col = reinterpret_cast<const V*>(Lp + tk.poff) + (live ? r : r0);
   const int gend = (jend + K - 1) / K;
+  // front vector: own entries of b plus the children's update rows, added in
+  // child order (one pass, no barrier per child).  The indices of the first
+  // gather round are requested before the factor, so that waiting for them
+  // does not wait for the factor loads.
+  const int* gp = t.gptr + tk.foff;
+  const int pc = min(tid, nf - 1);
+  const int fd0 = fd[pc], gb0 = gp[pc], ge0 = gp[pc + 1];
+  __builtin_amdgcn_sched_barrier(0);      // keep the issue order
   int g = __builtin_amdgcn_readfirstlane(wave) * SG;
   V A[SG], B[SG];
   load_round<SG>(A, col, g, gend, nf);
   load_round<SG>(B, col, g + STEP, gend, nf);
   const int dst = fd[min(r, nf - 1)];      // used by own rows only
 
-  // front vector: own entries of b plus the children's update rows, added in
-  // child order (one pass, no barrier per child)
-  const int* gp = t.gptr + tk.foff;
   for (int p = tid; p < nf; p += NW * 64) {
+    const bool first = p == tid;
     double s[NR];
 #pragma unroll
-    for (int q = 0; q < NR; ++q) s[q] = (p < no) ? b[fd[p] + q * ldb] : 0.0;
-    const int k1 = gp[p + 1];
-    for (int k = gp[p]; k < k1; ++k) {
+    for (int q = 0; q < NR; ++q) s[q] = (p < no) ? b[(first ? fd0 : fd[p]) + q * ldb] : 0.0;
+    const int k1 = first ? ge0 : gp[p + 1];
+    for (int k = first ? gb0 : gp[p]; k < k1; ++k) {
       const double* uc = upd + (int64_t)t.gidx[k] * NR;
 #pragma unroll
       for (int q = 0; q < NR; ++q) s[q] += uc[q];
@@ -195,6 +201,9 @@ __global__ __launch_bounds__(NW * 64) void k_bwd(DevTree t, const SweepTask* __r
   // group a0 / K
   const V* row = reinterpret_cast<const V*>(Tp + tk.poff) + (live ? a : a0);
   const int gend = (nf + K - 1) / K;
+  // indices of the first gather round before the factor loads (see k_fwd)
+  const int fd0 = fd[min(tid, nf - 1)];
+  __builtin_amdgcn_sched_barrier(0);      // keep the issue order
   int g = a0 / K + __builtin_amdgcn_readfirstlane(wave) * SG;
   V A[SG], B[SG];
   load_round<SG>(A, row, g, gend, no);
@@ -202,18 +211,20 @@ __global__ __launch_bounds__(NW * 64) void k_bwd(DevTree t, const SweepTask* __r
   const int d = fd[min(a, no - 1)];       // used by live lanes only
   if (t.inst != nullptr) sig = t.isig[tk.inst];
 
-  for (int p = tid; p < nf; p += NW * 64)
+  for (int p = tid; p < nf; p += NW * 64) {
+    const int fp = (p == tid) ? fd0 : fd[p];
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
       double val;
       if (p < no) {
-        val = y[fd[p] + q * ldy];
+        val = y[fp + q * ldy];
       } else {
-        val = xs[fd[p] + q * ldxs];
+        val = xs[fp + q * ldxs];
         if (!neg) val = -val;
       }
       w[p * NR + q] = val;
     }
+  }
   __syncthreads();
   double acc[NR];
 #pragma unroll
