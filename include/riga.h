@@ -262,6 +262,20 @@ riga_status riga_sweep_shapes(const riga_problem* h, int* fwd, int* bwd, int* le
  * no device.                                                                 */
 riga_status riga_selftest_small_eig(int n, const double* a, double* w, double* resid);
 
+/* Host-only self-test of the Krylov--Schur restart's reordering (Sec. 4.1.3:
+ * the kept Ritz values are moved to the top of the real Schur form by
+ * exchanges of adjacent 1x1 / 2x2 blocks).  a: n x n real column-major
+ * (host).  The nkeep eigenvalues of largest modulus (extended to every value
+ * of equal modulus, so conjugate pairs stay whole) are kept.  On return r is
+ * the kept dimension, w[0 .. 2r) the eigenvalues of the leading r x r block
+ * (re, im pairs), resid the larger of max|a Q_r - Q_r T_rr| / max|a| and
+ * max|Q_r^T Q_r - I|, real_path 1 when the real reordering was used.
+ * RIGA_WARN_NOT_CONVERGED when the Schur iteration failed or an exchange was
+ * ill conditioned (the solver then falls back to the complex form).  Touches
+ * no device.                                                                 */
+riga_status riga_selftest_schur_restart(int n, const double* a, int nkeep, int* r, double* w, double* resid,
+                                        int* real_path);
+
 /* ---- Batched form -----------------------------------------------------------
  * Many independent problems of different sizes (degree, mesh, hyperplane
  * spacing, damping, shift) solved together: the nested-dissection trees are

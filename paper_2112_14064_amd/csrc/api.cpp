@@ -816,6 +816,73 @@ riga_status riga_selftest_small_eig(int n, const double* a, double* w, double* r
   return RIGA_OK;
 }
 
+riga_status riga_selftest_schur_restart(int n, const double* a, int nkeep, int* r, double* w, double* resid,
+                                        int* real_path) {
+  if (n < 1 || !a || nkeep < 1 || nkeep > n || !r || !w) return RIGA_ERR_INVALID_ARG;
+  std::vector<double> T, Q;
+  if (riga::schur_real(n, a, T, Q) != 0) return RIGA_WARN_NOT_CONVERGED;
+  // eigenvalue of every diagonal position of the quasi-triangular form
+  std::vector<cplx> lam(n);
+  for (int i = 0; i < n;) {
+    if (i + 1 < n && T[(i + 1) + (size_t)i * n] != 0.0) {
+      const double p = T[i + (size_t)i * n], q = T[i + (size_t)(i + 1) * n];
+      const double u = T[(i + 1) + (size_t)i * n], v = T[(i + 1) + (size_t)(i + 1) * n];
+      const cplx disc = std::sqrt(cplx(0.25 * (p - v) * (p - v) + q * u));
+      lam[i] = 0.5 * (p + v) + disc;
+      lam[i + 1] = 0.5 * (p + v) - disc;
+      i += 2;
+    } else {
+      lam[i] = T[i + (size_t)i * n];
+      i += 1;
+    }
+  }
+  // keep the nkeep of largest modulus, extended to every equal modulus
+  std::vector<int> ord(n);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return std::abs(lam[x]) > std::abs(lam[y]); });
+  int kk = nkeep;
+  while (kk < n && std::abs(std::abs(lam[ord[kk]]) - std::abs(lam[ord[kk - 1]])) <= 1e-12 * std::abs(lam[ord[kk - 1]]))
+    ++kk;
+  std::vector<char> keep(n, 0);
+  for (int p = 0; p < kk; ++p) keep[ord[p]] = 1;
+  const int rr = riga::schur_select_real(n, T, Q, keep);
+  if (real_path) *real_path = rr > 0;
+  if (rr <= 0) return RIGA_WARN_NOT_CONVERGED;
+  *r = rr;
+  // eigenvalues of the leading block and the invariant-subspace residual
+  for (int i = 0; i < rr;) {
+    if (i + 1 < rr && T[(i + 1) + (size_t)i * n] != 0.0) {
+      const double p = T[i + (size_t)i * n], q = T[i + (size_t)(i + 1) * n];
+      const double u = T[(i + 1) + (size_t)i * n], v = T[(i + 1) + (size_t)(i + 1) * n];
+      const cplx disc = std::sqrt(cplx(0.25 * (p - v) * (p - v) + q * u));
+      const cplx l1 = 0.5 * (p + v) + disc, l2 = 0.5 * (p + v) - disc;
+      w[2 * i] = l1.real(); w[2 * i + 1] = l1.imag();
+      w[2 * i + 2] = l2.real(); w[2 * i + 3] = l2.imag();
+      i += 2;
+    } else {
+      w[2 * i] = T[i + (size_t)i * n]; w[2 * i + 1] = 0.0;
+      i += 1;
+    }
+  }
+  double an = 0.0, worst = 0.0;
+  for (int i = 0; i < n * n; ++i) an = std::max(an, std::abs(a[i]));
+  for (int c = 0; c < rr; ++c)
+    for (int i = 0; i < n; ++i) {
+      double aq = 0.0, qt = 0.0;
+      for (int j = 0; j < n; ++j) aq += a[i + (size_t)j * n] * Q[j + (size_t)c * n];
+      for (int j = 0; j < rr; ++j) qt += Q[i + (size_t)j * n] * T[j + (size_t)c * n];
+      worst = std::max(worst, std::abs(aq - qt) / std::max(an, 1e-300));
+    }
+  for (int c = 0; c < rr; ++c)
+    for (int d = 0; d < rr; ++d) {
+      double s = 0.0;
+      for (int i = 0; i < n; ++i) s += Q[i + (size_t)c * n] * Q[i + (size_t)d * n];
+      worst = std::max(worst, std::abs(s - (c == d ? 1.0 : 0.0)));
+    }
+  if (resid) *resid = worst;
+  return RIGA_OK;
+}
+
 riga_status riga_time_kernel(riga_problem* h, int which, int nrhs, int reps, double* avg_ms,
                              double* work_per_launch, int* launches) {
   if (!h || which < 0 || which > 2 || nrhs < 1 || nrhs > 4 || reps < 1 || !avg_ms || !work_per_launch)

@@ -11,7 +11,8 @@ int ks_ritz(const std::vector<double>& H, int ldh, int k, int b, int nev, double
   std::vector<double> Hk((size_t)k * k);
   for (int col = 0; col < k; ++col)
     for (int r = 0; r < k; ++r) Hk[r + (size_t)col * k] = Hat(r, col);
-  if (schur_complex(k, Hk.data(), c.T, c.Z) != 0) return -1;
+  if (schur_real(k, Hk.data(), c.TR, c.QR) != 0) return -1;
+  schur_complexify(k, c.TR, c.QR, c.T, c.Z);
   c.theta.resize(k);
   for (int i = 0; i < k; ++i) c.theta[i] = c.T[i + (size_t)i * k];
   // sort by |theta| descending (= |lam - sigma| ascending), clusters kept together
@@ -59,6 +60,36 @@ void ks_restart(const std::vector<double>& H, int ldh, int k, int b, int m, int 
   }
   std::vector<char> kept(k, 0);
   for (int p = 0; p < kk; ++p) kept[c.ord[p]] = 1;
+  const int kin = k + b;
+  // Preferred: reorder the real Schur form.  The leading r columns of its
+  // vectors are then a real orthonormal basis of the kept invariant subspace
+  // and the new projected matrix is [T_rr; E Q_r].
+  {
+    std::vector<double> TR = c.TR, QR = c.QR;
+    const int r = schur_select_real(k, TR, QR, kept);
+    if (r > 0) {
+      c.Hn.assign((size_t)ldh * ldh, 0.0);
+      for (int col = 0; col < r; ++col) {
+        for (int rr = 0; rr <= std::min(col + 1, r - 1); ++rr) c.Hn[rr + (size_t)col * ldh] = TR[rr + (size_t)col * k];
+        for (int rr = 0; rr < b; ++rr) {
+          double s = 0.0;
+          for (int t2 = 0; t2 < k; ++t2) s += Hat(k + rr, t2) * QR[t2 + (size_t)col * k];
+          c.Hn[r + rr + (size_t)col * ldh] = s;
+        }
+      }
+      const int kout = r + b;
+      c.Qe.assign((size_t)kin * kout, 0.0);
+      for (int col = 0; col < r; ++col)
+        for (int t2 = 0; t2 < k; ++t2) c.Qe[t2 + (size_t)col * kin] = QR[t2 + (size_t)col * k];
+      for (int q = 0; q < b; ++q) c.Qe[(k + q) + (size_t)(r + q) * kin] = 1.0;
+      c.r = r;
+      c.real_restart = true;
+      return;
+    }
+  }
+  // Fallback (an ill-conditioned exchange): reorder the complex Schur form and
+  // take a real basis of the kept span.
+  c.real_restart = false;
   std::vector<cplx> T = c.T, Z = c.Z;
   schur_select(k, T, Z, kept);
   std::vector<double> Qk;
@@ -88,7 +119,7 @@ void ks_restart(const std::vector<double>& H, int ldh, int k, int b, int m, int 
     }
   }
   // V_new = [V_k Qk, V_{k:k+b}]
-  const int kin = k + b, kout = r + b;
+  const int kout = r + b;
   c.Qe.assign((size_t)kin * kout, 0.0);
   for (int col = 0; col < r; ++col)
     for (int t2 = 0; t2 < k; ++t2) c.Qe[t2 + (size_t)col * kin] = Qk[t2 + (size_t)col * k];

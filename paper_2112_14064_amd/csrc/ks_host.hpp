@@ -10,7 +10,8 @@
 namespace riga {
 
 struct KsCycle {
-  std::vector<cplx> T, Z, Y;       // Schur form of H_k, its vectors, Ritz vectors (k x k)
+  std::vector<double> TR, QR;      // real Schur form of H_k and its vectors (k x k)
+  std::vector<cplx> T, Z, Y;       // complex Schur form, its vectors, Ritz vectors (k x k)
   std::vector<cplx> theta;         // Ritz values of S
   std::vector<int> ord;            // positions by |theta| descending, clusters kept together
   int nw = 0;                      // wanted values: nev extended to the end of its cluster
@@ -19,6 +20,7 @@ struct KsCycle {
   int r = 0;                       // kept dimension after the restart
   std::vector<double> Qe;          // (k+b) x (r+b) combination of the basis, column-major
   std::vector<double> Hn;          // projected matrix after the restart, ldh x ldh
+  bool real_restart = false;       // the last restart reordered the real Schur form
 };
 
 // Rayleigh--Ritz on H_k (eq. ArnoldiRitz): H is ldh x ldh column-major with H_k

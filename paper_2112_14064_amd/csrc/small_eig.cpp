@@ -26,7 +26,7 @@ void hessenberg(int n, std::vector<double>& H, std::vector<double>& Q) {
   auto q = [&](int i, int j) -> double& { return Q[i + (size_t)j * n]; };
   Q.assign((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i) q(i, i) = 1.0;
-  std::vector<double> v(n), w(n);
+  std::vector<double> v(n), w(n), z(n);
   for (int k = 0; k + 2 < n; ++k) {
     double alpha = 0.0;
     for (int i = k + 1; i < n; ++i) alpha += h(i, k) * h(i, k);
@@ -39,19 +39,24 @@ void hessenberg(int n, std::vector<double>& H, std::vector<double>& Q) {
     for (int i = k + 1; i < n; ++i) vv += v[i] * v[i];
     if (vv == 0.0) continue;
     const double beta = 2.0 / vv;
-    // rows k+1..n-1: H -= beta v (v^T H)
-    for (int j = 0; j < n; ++j) {
+    // rows k+1..n-1: H -= beta v (v^T H) (columns before k are already reduced)
+    for (int j = k; j < n; ++j) {
       double s = 0.0;
       for (int i = k + 1; i < n; ++i) s += v[i] * h(i, j);
       s *= beta;
       for (int i = k + 1; i < n; ++i) h(i, j) -= s * v[i];
     }
-    // columns k+1..n-1: H -= beta (H v) v^T, and the same for Q
-    for (int i = 0; i < n; ++i) {
-      double s = 0.0, t = 0.0;
-      for (int j = k + 1; j < n; ++j) { s += h(i, j) * v[j]; t += q(i, j) * v[j]; }
-      s *= beta; t *= beta;
-      for (int j = k + 1; j < n; ++j) { h(i, j) -= s * v[j]; q(i, j) -= t * v[j]; }
+    // columns k+1..n-1: H -= beta (H v) v^T, and the same for Q; both by
+    // whole columns (w = H v, z = Q v first)
+    std::fill(w.begin(), w.end(), 0.0);
+    std::fill(z.begin(), z.end(), 0.0);
+    for (int j = k + 1; j < n; ++j) {
+      const double vj = v[j];
+      for (int i = 0; i < n; ++i) { w[i] += h(i, j) * vj; z[i] += q(i, j) * vj; }
+    }
+    for (int j = k + 1; j < n; ++j) {
+      const double c = beta * v[j];
+      for (int i = 0; i < n; ++i) { h(i, j) -= w[i] * c; q(i, j) -= z[i] * c; }
     }
     for (int i = k + 2; i < n; ++i) h(i, k) = 0.0;
   }
@@ -176,15 +181,22 @@ int real_schur(int n, std::vector<double>& H, std::vector<double>& Q) {
 
 }  // namespace
 
-int schur_complex(int n, const double* A, std::vector<cplx>& T, std::vector<cplx>& Z) {
-  std::vector<double> H(A, A + (size_t)n * n), Q;
-  hessenberg(n, H, Q);
-  if (real_schur(n, H, Q) != 0) return -1;
+int schur_real(int n, const double* A, std::vector<double>& T, std::vector<double>& Q) {
+  T.assign(A, A + (size_t)n * n);
+  hessenberg(n, T, Q);
+  if (real_schur(n, T, Q) != 0) return -1;
+  for (int j = 0; j < n; ++j)
+    for (int i = j + 2; i < n; ++i) T[i + (size_t)j * n] = 0.0;
+  return 0;
+}
+
+void schur_complexify(int n, const std::vector<double>& TR, const std::vector<double>& QR, std::vector<cplx>& T,
+                      std::vector<cplx>& Z) {
   T.assign((size_t)n * n, cplx(0.0));
   Z.assign((size_t)n * n, cplx(0.0));
   for (int j = 0; j < n; ++j)
-    for (int i = 0; i <= std::min(j + 1, n - 1); ++i) T[i + (size_t)j * n] = H[i + (size_t)j * n];
-  for (size_t k = 0; k < (size_t)n * n; ++k) Z[k] = Q[k];
+    for (int i = 0; i <= std::min(j + 1, n - 1); ++i) T[i + (size_t)j * n] = TR[i + (size_t)j * n];
+  for (size_t k = 0; k < (size_t)n * n; ++k) Z[k] = QR[k];
   auto t = [&](int i, int j) -> cplx& { return T[i + (size_t)j * n]; };
   auto z = [&](int i, int j) -> cplx& { return Z[i + (size_t)j * n]; };
   // complex Schur form: triangularise every 2x2 block with the unitary whose
@@ -221,7 +233,151 @@ int schur_complex(int n, const double* A, std::vector<cplx>& T, std::vector<cplx
   }
   for (int j = 0; j < n; ++j)
     for (int i = j + 1; i < n; ++i) t(i, j) = 0.0;
+}
+
+int schur_complex(int n, const double* A, std::vector<cplx>& T, std::vector<cplx>& Z) {
+  std::vector<double> TR, QR;
+  if (schur_real(n, A, TR, QR) != 0) return -1;
+  schur_complexify(n, TR, QR, T, Z);
   return 0;
+}
+
+namespace {
+
+// Exchange of the adjacent diagonal blocks A11 (p x p, at row j) and A22
+// (q x q) of a real quasi-triangular T, p, q in {1, 2}, by the direct method
+// of Bai and Demmel (1993): X with A11 X - X A22 = A12 spans, with the
+// identity below it, the invariant subspace of A22; an orthogonal U whose
+// first q columns span [-X; I] moves A22's eigenvalues to the top.
+// Returns false when the Sylvester equation is (nearly) singular or the
+// block left below the exchanged pair is not negligible; T and Q are then
+// partly updated and must be discarded.
+bool swap_blocks(int n, std::vector<double>& T, std::vector<double>& Q, int j, int p, int q) {
+  auto t = [&](int i, int c) -> double& { return T[i + (size_t)c * n]; };
+  const int w = p + q;
+  const double eps = std::numeric_limits<double>::epsilon();
+  double wnorm = 0.0;
+  for (int c = j; c < j + w; ++c)
+    for (int i = j; i < j + w; ++i) wnorm = std::max(wnorm, std::abs(t(i, c)));
+  // Kronecker system (I_q (x) A11 - A22^T (x) I_p) vec(X) = vec(A12), unknown X[a + p b]
+  const int m = p * q;
+  double M[4][5] = {{0}};
+  for (int b = 0; b < q; ++b)
+    for (int a = 0; a < p; ++a) {
+      const int row = a + p * b;
+      for (int c = 0; c < p; ++c) M[row][c + p * b] += t(j + a, j + c);
+      for (int d = 0; d < q; ++d) M[row][a + p * d] -= t(j + p + d, j + p + b);
+      M[row][m] = t(j + a, j + p + b);
+    }
+  // Gaussian elimination with complete pivoting
+  int colp[4] = {0, 1, 2, 3};
+  for (int k = 0; k < m; ++k) {
+    int br = k, bc = k;
+    double best = -1.0;
+    for (int r = k; r < m; ++r)
+      for (int c = k; c < m; ++c)
+        if (std::abs(M[r][c]) > best) { best = std::abs(M[r][c]); br = r; bc = c; }
+    if (best <= eps * std::max(wnorm, std::numeric_limits<double>::min())) return false;
+    for (int c = 0; c <= m; ++c) std::swap(M[k][c], M[br][c]);
+    for (int r = 0; r < m; ++r) std::swap(M[r][k], M[r][bc]);
+    std::swap(colp[k], colp[bc]);
+    for (int r = k + 1; r < m; ++r) {
+      const double f = M[r][k] / M[k][k];
+      for (int c = k; c <= m; ++c) M[r][c] -= f * M[k][c];
+    }
+  }
+  double y[4], X[4];
+  for (int k = m - 1; k >= 0; --k) {
+    double s = M[k][m];
+    for (int c = k + 1; c < m; ++c) s -= M[k][c] * y[c];
+    y[k] = s / M[k][k];
+  }
+  for (int k = 0; k < m; ++k) X[colp[k]] = y[k];
+  // Householder QR of W = [-X; I_q] (w x q): reflectors (I - beta v v^T)
+  double W[4][2] = {{0}};
+  for (int b = 0; b < q; ++b) {
+    for (int a = 0; a < p; ++a) W[a][b] = -X[a + p * b];
+    W[p + b][b] = 1.0;
+  }
+  double V[2][4] = {{0}}, beta[2] = {0, 0};
+  for (int k = 0; k < q; ++k) {
+    double nrm = 0.0;
+    for (int i = k; i < w; ++i) nrm += W[i][k] * W[i][k];
+    nrm = std::sqrt(nrm);
+    const double alpha = W[k][k] > 0 ? -nrm : nrm;
+    for (int i = 0; i < w; ++i) V[k][i] = (i < k) ? 0.0 : W[i][k];
+    V[k][k] -= alpha;
+    double vv = 0.0;
+    for (int i = k; i < w; ++i) vv += V[k][i] * V[k][i];
+    beta[k] = vv > 0.0 ? 2.0 / vv : 0.0;
+    for (int c = k; c < q; ++c) {
+      double sd = 0.0;
+      for (int i = k; i < w; ++i) sd += V[k][i] * W[i][c];
+      sd *= beta[k];
+      for (int i = k; i < w; ++i) W[i][c] -= sd * V[k][i];
+    }
+  }
+  // T <- U^T T U and Q <- Q U with U = H_0 H_1 (window rows / columns j .. j+w-1)
+  for (int k = 0; k < q; ++k) {
+    const double* v = V[k];
+    for (int c = j; c < n; ++c) {
+      double sd = 0.0;
+      for (int i = 0; i < w; ++i) sd += v[i] * t(j + i, c);
+      sd *= beta[k];
+      for (int i = 0; i < w; ++i) t(j + i, c) -= sd * v[i];
+    }
+    for (int r = 0; r < j + w; ++r) {
+      double sd = 0.0;
+      for (int i = 0; i < w; ++i) sd += t(r, j + i) * v[i];
+      sd *= beta[k];
+      for (int i = 0; i < w; ++i) t(r, j + i) -= sd * v[i];
+    }
+    for (int r = 0; r < n; ++r) {
+      double sd = 0.0;
+      for (int i = 0; i < w; ++i) sd += Q[r + (size_t)(j + i) * n] * v[i];
+      sd *= beta[k];
+      for (int i = 0; i < w; ++i) Q[r + (size_t)(j + i) * n] -= sd * v[i];
+    }
+  }
+  // the p x q block below the new leading q x q block must be negligible
+  double low = 0.0;
+  for (int c = j; c < j + q; ++c)
+    for (int i = j + q; i < j + w; ++i) low = std::max(low, std::abs(t(i, c)));
+  if (low > 10.0 * eps * std::max(wnorm, 1.0)) return false;
+  for (int c = j; c < j + q; ++c)
+    for (int i = j + q; i < j + w; ++i) t(i, c) = 0.0;
+  return true;
+}
+
+}  // namespace
+
+int schur_select_real(int n, std::vector<double>& T, std::vector<double>& Q, const std::vector<char>& keep) {
+  // blocks of the quasi-triangular form: start, size, kept
+  std::vector<int> bs, bz;
+  std::vector<char> bk;
+  for (int i = 0; i < n;) {
+    const int sz = (i + 1 < n && T[(i + 1) + (size_t)i * n] != 0.0) ? 2 : 1;
+    if (sz == 2 && keep[i] != keep[i + 1]) return -1;   // a conjugate pair is kept whole
+    bs.push_back(i); bz.push_back(sz); bk.push_back(keep[i] != 0);
+    i += sz;
+  }
+  // walk up from the bottom; every block not kept sinks to the end of the kept ones
+  const int nb = (int)bs.size();
+  int end = nb;
+  for (int b = nb - 1; b >= 0; --b) {
+    if (bk[b]) continue;
+    for (int k = b; k < end - 1; ++k) {
+      // blocks k (not kept) and k+1 (kept) exchange places
+      if (!swap_blocks(n, T, Q, bs[k], bz[k], bz[k + 1])) return -1;
+      bs[k + 1] = bs[k] + bz[k + 1];
+      std::swap(bz[k], bz[k + 1]);
+      std::swap(bk[k], bk[k + 1]);
+    }
+    --end;
+  }
+  int r = 0;
+  for (int b = 0; b < nb && bk[b]; ++b) r += bz[b];
+  return r;
 }
 
 namespace {

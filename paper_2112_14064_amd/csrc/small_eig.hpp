@@ -15,6 +15,22 @@ using cplx = std::complex<double>;
 // Returns 0, or -1 if the iteration did not converge.
 int schur_complex(int n, const double* A, std::vector<cplx>& T, std::vector<cplx>& Z);
 
+// The real Schur form A = Q T Q^T behind schur_complex: T quasi upper
+// triangular (1x1 blocks and 2x2 blocks of complex-conjugate pairs, nonzero
+// subdiagonal), Q orthogonal.  Returns 0, or -1 if the iteration failed.
+int schur_real(int n, const double* A, std::vector<double>& T, std::vector<double>& Q);
+// The complex Schur form of a real one (each 2x2 block triangularised):
+// diagonal position i of the complex T is position i of the real T.
+void schur_complexify(int n, const std::vector<double>& TR, const std::vector<double>& QR, std::vector<cplx>& T,
+                      std::vector<cplx>& Z);
+// Reorder a real Schur form so that the blocks at positions with keep[i] != 0
+// come first, their relative order kept, by exchanges of adjacent blocks in
+// real arithmetic.  Returns the kept dimension r (the leading r columns of Q
+// span the kept invariant subspace and T[0:r, 0:r] is its quasi-triangular
+// form), or -1 when an exchange is ill conditioned or the mask splits a 2x2
+// block; T and Q are then unusable.
+int schur_select_real(int n, std::vector<double>& T, std::vector<double>& Q, const std::vector<char>& keep);
+
 // Reorder the Schur form so that the eigenvalues at positions order[0..k-1]
 // (positions in the current T) come first, in that order.
 void schur_reorder(int n, std::vector<cplx>& T, std::vector<cplx>& Z, const std::vector<int>& order);

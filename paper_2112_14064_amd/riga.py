@@ -56,7 +56,7 @@ EXPORTS = ["riga_create", "riga_info", "riga_assemble", "riga_export_csr", "riga
            "riga_batch_eigs", "riga_batch_stats", "riga_batch_destroy", "riga_autotune", "riga_sweep_shapes",
            "riga_batch_autotune",
            "riga_solve_q", "riga_apply_op", "riga_eigs", "riga_adjoint", "riga_stats", "riga_time_kernel",
-           "riga_selftest_small_eig", "riga_status_str", "riga_destroy"]
+           "riga_selftest_small_eig", "riga_selftest_schur_restart", "riga_status_str", "riga_destroy"]
 
 _lib = None
 
@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH):
     lib.riga_time_kernel.argtypes = [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.POINTER(C.c_int)]
     lib.riga_selftest_small_eig.argtypes = [C.c_int, P, P, P]
+    lib.riga_selftest_schur_restart.argtypes = [C.c_int, P, C.c_int, P, P, P, P]
     lib.riga_status_str.argtypes = [C.c_int]
     lib.riga_status_str.restype = C.c_char_p
     lib.riga_destroy.argtypes = [P]
@@ -135,6 +136,23 @@ def riga_selftest_small_eig(a: np.ndarray):
     _check(lib.riga_selftest_small_eig(n, a.ctypes.data_as(C.c_void_p), w.ctypes.data_as(C.c_void_p),
                                        C.cast(C.pointer(res), C.c_void_p)), "riga_selftest_small_eig")
     return w[0::2] + 1j * w[1::2], res.value
+
+
+def riga_selftest_schur_restart(a: np.ndarray, nkeep: int):
+    """Restart reordering of the library's real Schur form (host only): the
+    nkeep eigenvalues of largest modulus (whole clusters) moved to the top.
+    Returns (eigenvalues of the leading block, residual, real path used)."""
+    lib = load()
+    a = np.asfortranarray(np.asarray(a, dtype=np.float64))
+    n = a.shape[0]
+    w = np.zeros(2 * n)
+    r, real = C.c_int(0), C.c_int(0)
+    res = C.c_double(0.0)
+    _check(lib.riga_selftest_schur_restart(n, a.ctypes.data_as(C.c_void_p), nkeep, C.cast(C.pointer(r), C.c_void_p),
+                                           w.ctypes.data_as(C.c_void_p), C.cast(C.pointer(res), C.c_void_p),
+                                           C.cast(C.pointer(real), C.c_void_p)), "riga_selftest_schur_restart")
+    k = r.value
+    return w[0:2 * k:2] + 1j * w[1:2 * k:2], res.value, bool(real.value)
 
 
 class Problem:

@@ -108,3 +108,39 @@ def test_small_dense_eigensolver_large_and_triangular():
     w, res = riga.riga_selftest_small_eig(t)
     assert res < 1e-12
     assert np.allclose(np.sort(w.real), np.sort(np.diag(t)), atol=1e-12) and np.abs(w.imag).max() == 0.0
+
+
+@pytest.mark.parametrize("n,nkeep,seed", [(17, 5, 0), (64, 20, 1), (96, 48, 2)])
+def test_restart_reordering_keeps_the_largest(n, nkeep, seed):
+    """Real Schur reordering of the Krylov--Schur restart: the leading block
+    holds exactly the eigenvalues of largest modulus (pairs whole), spans an
+    invariant subspace and has an orthonormal basis."""
+    a = np.random.default_rng(seed).standard_normal((n, n))
+    w, res, real = riga.riga_selftest_schur_restart(a, nkeep)
+    ref = np.linalg.eigvals(a)
+    top = ref[np.argsort(-np.abs(ref), kind="stable")]
+    assert real and res < 1e-13
+    k = len(w)
+    assert nkeep <= k <= nkeep + 1
+    # the same multiset as the k largest in modulus
+    for x in top[:k]:
+        assert np.min(np.abs(w - x)) < 1e-10 * np.abs(ref).max()
+    assert np.abs(np.sort_complex(w).sum() - top[:k].sum()) < 1e-9 * np.abs(ref).max()
+
+
+def test_restart_reordering_conjugate_pairs_and_reals():
+    """The spectrum shape of the shift-and-invert operator (conjugate pairs
+    and real values): pairs are moved as whole 2x2 blocks."""
+    rng = np.random.default_rng(5)
+    pairs = [(rng.uniform(-1, 1), rng.uniform(0.1, 3)) for _ in range(25)]
+    reals = list(rng.uniform(-2, 2, 10))
+    a, ev = _rotation_blocks(rng, pairs, reals)
+    w, res, real = riga.riga_selftest_schur_restart(a, 21)
+    top = ev[np.argsort(-np.abs(ev), kind="stable")]
+    assert real and res < 1e-12
+    assert len(w) in (21, 22)
+    for x in top[:len(w)]:
+        assert np.min(np.abs(w - x)) < 1e-10
+    # closed under conjugation
+    for x in w:
+        assert np.min(np.abs(w - np.conj(x))) < 1e-10
