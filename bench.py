@@ -126,7 +126,7 @@ def precision_form(torch, riga, W, ir_tol=1e-9):
     import numpy as np
 
     P = W.cfg_precision()
-    pr = riga.Problem(P.p, P.ne, P.hyper_every, leaf=16)
+    pr = riga.Problem(P.p, P.ne, P.hyper_every)
     info = pr.info
     c = torch.from_numpy(P.c_elem).to(pr.device)
     out = {"workload": f"p={P.p}, {P.ne}x{P.ne}, s={P.hyper_every}, c_e lognormal(-3,0.5) seed 0, "

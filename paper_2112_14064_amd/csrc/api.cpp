@@ -318,12 +318,14 @@ void setup_device(riga_problem* h) {
       h->lvl_max_no.assign(P.height, 0);
       h->lvl_max_nf.assign(P.height, 0);
       h->lvl_max_cnb.assign(P.height, 0);
+      h->lvl_max_kids.assign(P.height, 0);
       for (int lv = 0; lv < P.height; ++lv)
         for (int k = P.level_off[lv]; k < P.level_off[lv + 1]; ++k) {
           const int v = P.level_nodes[k];
           h->lvl_max_no[lv] = std::max(h->lvl_max_no[lv], P.no[v]);
           h->lvl_max_nf[lv] = std::max(h->lvl_max_nf[lv], P.nf[v]);
           for (int c : P.nodes[v].children) h->lvl_max_cnb[lv] = std::max(h->lvl_max_cnb[lv], P.nb[c]);
+          h->lvl_max_kids[lv] = std::max(h->lvl_max_kids[lv], (int)P.nodes[v].children.size());
         }
     }
     {
@@ -504,11 +506,11 @@ void factor_level(riga_problem* h, int lv, double sigma) {
   if (h->mixed) t.prec = h->d_prec;
   if (h->level_f32(lv))
     riga::launch_front_factor(h->ds, t, h->d_level_nodes + a, c, h->lvl_max_no[lv], h->lvl_max_nf[lv],
-                              h->lvl_max_cnb[lv], sigma * sigma, sigma, h->d_K, h->d_M, h->d_C, h->d_L32, h->d_U32,
+                              h->lvl_max_cnb[lv], h->lvl_max_kids[lv], sigma * sigma, sigma, h->d_K, h->d_M, h->d_C, h->d_L32, h->d_U32,
                               h->d_T32, h->d_D32, h->d_Lp32, h->d_Tp32, h->d_status, h->st);
   else
     riga::launch_front_factor(h->ds, t, h->d_level_nodes + a, c, h->lvl_max_no[lv], h->lvl_max_nf[lv],
-                              h->lvl_max_cnb[lv], sigma * sigma, sigma, h->d_K, h->d_M, h->d_C, h->d_L, h->d_U,
+                              h->lvl_max_cnb[lv], h->lvl_max_kids[lv], sigma * sigma, sigma, h->d_K, h->d_M, h->d_C, h->d_L, h->d_U,
                               h->d_T, h->d_D, h->d_Lp, h->d_Tp, h->d_U32, h->d_status, h->st);
 }
 

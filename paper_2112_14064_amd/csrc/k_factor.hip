@@ -467,7 +467,7 @@ __global__ __launch_bounds__(FT) void k_pack(DevTree t, const int* __restrict__ 
 
 template <class E>
 void front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
-                  int max_nf, int max_child_nb, double s2, double s1, const double* K, const double* M,
+                  int max_nf, int max_child_nb, int max_kids, double s2, double s1, const double* K, const double* M,
                   const double* C, E* L, E* U, E* T, E* D, E* Lp, E* Tp, const float* U32,
                   const double* U64, int64_t* status, hipStream_t st) {
   if (count <= 0) return;
@@ -475,7 +475,7 @@ void front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, i
   hipLaunchKernelGGL(k_front_assemble<E>, dim3(count, ncol), dim3(FT), 0, st, s.n, s.lo, s.hi, s.rowptr, t,
                      level_nodes, s2, s1, K, M, C, L, U);
   if (max_child_nb > 0)
-    for (int slot = 0; slot < 2; ++slot)
+    for (int slot = 0; slot < max_kids; ++slot)
       hipLaunchKernelGGL(k_front_extend<E>, dim3(count, (max_child_nb + TB - 1) / TB), dim3(FT), 0, st, t,
                          level_nodes, slot, L, U, U32, U64);
   for (int k0 = 0; k0 < max_no; k0 += TB) {
@@ -495,19 +495,19 @@ void front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, i
 }
 
 void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
-                         int max_nf, int max_child_nb, double s2, double s1, const double* K, const double* M,
+                         int max_nf, int max_child_nb, int max_kids, double s2, double s1, const double* K, const double* M,
                          const double* C, double* L, double* U, double* T, double* D, double* Lp, double* Tp,
                          const float* U32, int64_t* status, hipStream_t st) {
-  front_factor<double>(s, t, level_nodes, count, max_no, max_nf, max_child_nb, s2, s1, K, M, C, L, U, T, D, Lp, Tp,
+  front_factor<double>(s, t, level_nodes, count, max_no, max_nf, max_child_nb, max_kids, s2, s1, K, M, C, L, U, T, D, Lp, Tp,
                        U32, U, status, st);
 }
 
 void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
-                         int max_nf, int max_child_nb, double s2, double s1, const double* K, const double* M,
+                         int max_nf, int max_child_nb, int max_kids, double s2, double s1, const double* K, const double* M,
                          const double* C, float* L, float* U, float* T, float* D, float* Lp, float* Tp,
                          int64_t* status, hipStream_t st) {
   // FP32 fronts only have FP32 children
-  front_factor<float>(s, t, level_nodes, count, max_no, max_nf, max_child_nb, s2, s1, K, M, C, L, U, T, D, Lp, Tp,
+  front_factor<float>(s, t, level_nodes, count, max_no, max_nf, max_child_nb, max_kids, s2, s1, K, M, C, L, U, T, D, Lp, Tp,
                       U, nullptr, status, st);
 }
 

@@ -57,15 +57,15 @@ void launch_assemble(const DevSpace& s, const double* tabM, const double* tabK,
 // and F in the sweep layouts Lp (lpoff: groups of 16 bytes of columns) and
 // Tp (tpoff: groups of rows); L, U, T are working storage of the
 // factorization.  D holds the 64x64 inverses of the diagonal blocks (doff);
-// max_no / max_nf bound the level.
+// max_no / max_nf bound the level, max_child_nb / max_kids its children.
 // FP64 level: children flagged in t.prec keep their update blocks in U32.
 void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
-                         int max_nf, int max_child_nb, double s2, double s1, const double* K, const double* M,
+                         int max_nf, int max_child_nb, int max_kids, double s2, double s1, const double* K, const double* M,
                          const double* C, double* L, double* U, double* T, double* D, double* Lp, double* Tp,
                          const float* U32, int64_t* status, hipStream_t st);
 // FP32 level (FP32 products and accumulation); all children are FP32.
 void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
-                         int max_nf, int max_child_nb, double s2, double s1, const double* K, const double* M,
+                         int max_nf, int max_child_nb, int max_kids, double s2, double s1, const double* K, const double* M,
                          const double* C, float* L, float* U, float* T, float* D, float* Lp, float* Tp,
                          int64_t* status, hipStream_t st);
 // Out = am M + ac C + ak K on the shared CSR pattern (nnz values).

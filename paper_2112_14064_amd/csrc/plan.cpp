@@ -68,10 +68,101 @@ int pick_cut(int lo, int hi, int s, int leaf) {
 
 }  // namespace
 
+void Plan::amalgamate() {
+  const int nn = (int)nodes.size();
+  if (amalg_group < 2 || nn < 2) return;
+  const int root = nn - 1;
+  // depth from the root and the number of nodes at every depth
+  std::vector<int> depth(nn, 0), count;
+  for (int v = root; v >= 0; --v) {
+    for (int c : nodes[v].children) depth[c] = depth[v] + 1;
+  }
+  for (int v = 0; v < nn; ++v) {
+    if ((int)count.size() <= depth[v]) count.resize(depth[v] + 1, 0);
+    ++count[depth[v]];
+  }
+  // the top depths with at most amalg_max nodes are grouped by amalg_group
+  int dtop = 0;
+  while (dtop < (int)count.size() && count[dtop] <= amalg_max) ++dtop;
+  // group heads: depths that are multiples of amalg_group; a head takes its
+  // group only while the group's own dofs stay within amalg_own (large fronts
+  // near the root of big meshes are bandwidth-bound: merging them only adds
+  // work)
+  std::vector<int> rep(nn), gown(nn, 0);
+  for (int v = 0; v < nn; ++v) {            // postorder: descendants first
+    const int d = depth[v];
+    gown[v] = (int)nodes[v].own.size();
+    if (d < dtop && d % amalg_group != 0) continue;
+    // own dofs of the descendants within the group
+    std::function<int(int)> sum = [&](int u) {
+      int t = 0;
+      for (int c : nodes[u].children)
+        if (depth[c] < dtop && depth[c] % amalg_group != 0) t += (int)nodes[c].own.size() + sum(c);
+      return t;
+    };
+    gown[v] += sum(v);
+  }
+  for (int v = root; v >= 0; --v) {
+    const int d = depth[v];
+    if (d < dtop && d % amalg_group != 0 && rep[nodes[v].parent] == nodes[v].parent &&
+        gown[nodes[v].parent] <= amalg_own)
+      rep[v] = nodes[v].parent;
+    else if (d < dtop && d % amalg_group != 0 && rep[nodes[v].parent] != nodes[v].parent)
+      rep[v] = rep[nodes[v].parent];
+    else
+      rep[v] = v;
+  }
+  bool any = false;
+  for (int v = 0; v < nn; ++v) any |= rep[v] != v;
+  if (!any) return;
+  // the merged tree: own dofs of a group in postorder (children first),
+  // children = the members' children outside the group
+  std::vector<std::vector<int>> kids(nn), owns(nn);
+  for (int v = 0; v < nn; ++v) {           // postorder: members before their group head
+    const int g = rep[v];
+    owns[g].insert(owns[g].end(), nodes[v].own.begin(), nodes[v].own.end());
+    for (int c : nodes[v].children)
+      if (rep[c] == c) kids[g].push_back(c);
+  }
+  std::vector<int> order;
+  std::function<void(int)> dfs = [&](int v) {
+    for (int c : kids[v]) dfs(c);
+    order.push_back(v);
+  };
+  dfs(root);
+  std::vector<int> newid(nn, -1);
+  for (size_t k = 0; k < order.size(); ++k) newid[order[k]] = (int)k;
+  std::vector<Node> out(order.size());
+  for (size_t k = 0; k < order.size(); ++k) {
+    const int v = order[k];
+    Node nd = nodes[v];
+    nd.own = std::move(owns[v]);
+    std::sort(nd.own.begin(), nd.own.end());
+    nd.children.clear();
+    for (int c : kids[v]) nd.children.push_back(newid[c]);
+    nd.parent = -1;
+    nd.post = (int)k;
+    out[k] = std::move(nd);
+  }
+  for (auto& nd : out)
+    for (int c : nd.children) out[c].parent = nd.post;
+  for (auto& nd : out) {
+    nd.first_desc = nd.post;
+    nd.height = 0;
+    for (int c : nd.children) {
+      nd.first_desc = std::min(nd.first_desc, out[c].first_desc);
+      nd.height = std::max(nd.height, out[c].height + 1);
+    }
+  }
+  nodes = std::move(out);
+  height = nodes.back().height + 1;
+  for (int64_t d = 0; d < ndof; ++d) node_of_dof[d] = newid[rep[node_of_dof[d]]];
+}
+
 int Plan::build(int p, int ne, int s, int leaf) {
   if (p < 1 || p > 8 || ne < 2) return -1;
   if (s < 0 || (s > 0 && ne % s != 0)) return -1;
-  if (leaf <= 0) leaf = 16;
+  if (leaf <= 0) leaf = 8;
   sp.build(p, ne, s);
   n1d = sp.n;
   if (n1d < 1) return -1;
@@ -156,6 +247,7 @@ int Plan::build(int p, int ne, int s, int leaf) {
       node_of_dof[d] = v;
       nodes[v].own.push_back(d);  // increasing dof id by construction
     }
+  amalgamate();
   elim_pos.assign(ndof, -1);
   int64_t pos = 0;
   for (auto& nd : nodes)

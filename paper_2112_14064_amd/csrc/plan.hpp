@@ -4,6 +4,16 @@
 #include <cstdint>
 #include <vector>
 
+#ifndef RIGA_AMALG_GROUP
+#define RIGA_AMALG_GROUP 2
+#endif
+#ifndef RIGA_AMALG_MAX
+#define RIGA_AMALG_MAX 256
+#endif
+#ifndef RIGA_AMALG_OWN
+#define RIGA_AMALG_OWN 320
+#endif
+
 namespace riga {
 
 // One direction of the tensor-product space (Sec. 3.1).  Knot positions are
@@ -56,6 +66,13 @@ struct Plan {
   double flops_dense = 0.0;
   double solve_bytes = 0.0;
 
+  // Amalgamation near the root: the depths holding at most amalg_max nodes
+  // are taken amalg_group at a time, each group's top node absorbing the own
+  // dofs of its descendants in the group (<= 1: off) when they number at most
+  // amalg_own.  Those levels hold little data and the solve pays one
+  // dependent step per level.
+  int amalg_group = RIGA_AMALG_GROUP, amalg_max = RIGA_AMALG_MAX, amalg_own = RIGA_AMALG_OWN;
+
   int build(int p, int ne, int s, int leaf);  // 0 ok, <0 invalid
 
   // Forest of independent problems: the plans of `parts` side by side, with
@@ -64,6 +81,9 @@ struct Plan {
   // grouped by height across all parts.  The 1-D space stays empty.
   void merge(const std::vector<const Plan*>& parts, std::vector<int64_t>& dof_base,
              std::vector<int>& node_base);
+
+ private:
+  void amalgamate();
 };
 
 }  // namespace riga

@@ -47,7 +47,7 @@ struct riga_problem {
   riga::SweepTask *d_ftasks = nullptr, *d_btasks = nullptr;   // solve tasks, grouped by level
   std::vector<int> node_inst;                     // forest: problem of every node (set before setup)
   double* d_D = nullptr;                            // 64x64 diagonal-block inverses
-  std::vector<int> lvl_max_no, lvl_max_nf, lvl_max_cnb;
+  std::vector<int> lvl_max_no, lvl_max_nf, lvl_max_cnb, lvl_max_kids;
   std::vector<int> fvar, bvar;                      // sweep tile shape per level (autotuned)
   double* d_tune = nullptr;                         // autotuner output block (ndof x 4)
   std::vector<int> ftask_off, btask_off;

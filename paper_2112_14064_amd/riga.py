@@ -68,6 +68,10 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2112_14064_amd.build`")
+    # torch carries its own HIP runtime; it must be the process's only one, so
+    # it is loaded before the library resolves libamdhip64 (device memory and
+    # streams of the binding come from torch)
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     P = C.c_void_p
     lib.riga_create.argtypes = [C.POINTER(P), C.POINTER(riga_mesh), C.c_int, P]
