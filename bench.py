@@ -77,17 +77,19 @@ TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_sweeps_p3_256x256_s
 
 def measured_traffic(kernel, block):
     """HBM bytes per launch of a sweep kernel from the committed counter record
-    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the sweep source has
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when a source the
+    traffic depends on (sweep kernels, task layout, elimination tree) has
     changed since the counters were taken or the launch shape differs."""
     import hashlib
 
     try:
         rec = json.load(open(TRAFFIC_RECORD))
-        src = os.path.join(ROOT, rec["source"])
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    except (OSError, ValueError, KeyError):
+        for src, want in rec["source_sha256"].items():
+            if hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest() != want:
+                return None
+    except (OSError, ValueError, KeyError, AttributeError):
         return None
-    if sha != rec.get("source_sha256") or block != 2:
+    if block != 2:
         return None
     return rec.get("bytes_per_launch", {}).get(kernel)
 
