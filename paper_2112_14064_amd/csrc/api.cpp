@@ -1056,9 +1056,9 @@ struct KrylovRun {
     double* dQ = h->d_small + (size_t)2 * ldh * b + 32;
     ck(hipMemcpyAsync(dQ, Qm.data(), Qm.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
     const size_t o = (size_t)dst * N;
-    riga::launch_gemm_tall(N, iu, N, kin, dQ, kout, h->Vu + o, 1, N, h->st);
-    riga::launch_gemm_tall(N, il, N, kin, dQ, kout, h->Vl + o, 1, N, h->st);
-    riga::launch_gemm_tall(N, iml, N, kin, dQ, kout, h->Wl + o, 1, N, h->st);
+    riga::launch_gemm_tall(N, iu, N, kin, dQ, kout, h->Vu + o, N, h->st);
+    riga::launch_gemm_tall(N, il, N, kin, dQ, kout, h->Vl + o, N, h->st);
+    riga::launch_gemm_tall(N, iml, N, kin, dQ, kout, h->Wl + o, N, h->st);
     ck(hipStreamSynchronize(h->st));  // dQ is host-staged again by the next call
   }
 
@@ -1311,9 +1311,9 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
         std::memcpy(stage, cyc.Qe.data(), cyc.Qe.size() * sizeof(double));
         ck(hipMemcpyAsync(dQ, stage, cyc.Qe.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
       }
-      riga::launch_gemm_tall(N, h->Vu, N, kin, dQ, kout, h->Vu2, 1, N, h->st);
-      riga::launch_gemm_tall(N, h->Vl, N, kin, dQ, kout, h->Vl2, 1, N, h->st);
-      riga::launch_gemm_tall(N, h->Wl, N, kin, dQ, kout, h->Wl2, 1, N, h->st);
+      riga::launch_gemm_tall(N, h->Vu, N, kin, dQ, kout, h->Vu2, N, h->st);
+      riga::launch_gemm_tall(N, h->Vl, N, kin, dQ, kout, h->Vl2, N, h->st);
+      riga::launch_gemm_tall(N, h->Wl, N, kin, dQ, kout, h->Wl2, N, h->st);
       ck(hipStreamSynchronize(h->st));
       std::swap(h->Vu, h->Vu2); std::swap(h->Vl, h->Vl2); std::swap(h->Wl, h->Wl2);
       kr.H = cyc.Hn;
@@ -1341,10 +1341,10 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     ensure_post(h, nw);
     double* dQ = h->d_small;
     ck(hipMemcpyAsync(dQ, Yr.data(), Yr.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
-    riga::launch_gemm_tall(N, h->Vu, N, k, dQ, nw, h->P, 1, N, h->st);
+    riga::launch_gemm_tall(N, h->Vu, N, k, dQ, nw, h->P, N, h->st);
     ck(hipStreamSynchronize(h->st));
     ck(hipMemcpyAsync(dQ, Yi.data(), Yi.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
-    riga::launch_gemm_tall(N, h->Vu, N, k, dQ, nw, h->P + (size_t)nw * N, 1, N, h->st);
+    riga::launch_gemm_tall(N, h->Vu, N, k, dQ, nw, h->P + (size_t)nw * N, N, h->st);
     // M, C, K times the planar real and imaginary parts
     for (int c0 = 0; c0 < 2 * nw; c0 += 8) {
       int nc = std::min(8, 2 * nw - c0);

@@ -302,25 +302,25 @@ void launch_advance_b(const BatchDev& B, int b, int m, hipStream_t st) {
 // Out[:, 0:kout_p] = In[:, 0:kin_p] Q_p per problem (Q_p at Q + qoff[p], kin_p x
 // kout_p column-major); problems with kout_p = 0 are skipped.  A row block of up
 // to 256 rows is done as 64-row tiles.
-__global__ __launch_bounds__(GEMM_THREADS) void k_gemm_tall_b(const int4* __restrict__ rb,
+__global__ __launch_bounds__(512) void k_gemm_tall_b(const int4* __restrict__ rb,
                                                               const int* __restrict__ kin,
                                                               const int* __restrict__ kout,
                                                               const int64_t* __restrict__ qoff,
                                                               const double* __restrict__ Q,
                                                               const double* __restrict__ In, double* __restrict__ Out,
                                                               int64_t ld) {
-  extern __shared__ double tile[];
+  extern __shared__ double qs[];
   const int4 b = rb[blockIdx.x];
   const int ko = kout[b.x];
   if (ko <= 0) return;
-  for (int r0 = b.y; r0 < b.z; r0 += GEMM_ROWS)
-    gemm_tile64(r0, min(GEMM_ROWS, b.z - r0), In, ld, kin[b.x], Q + qoff[b.x], ko, Out, 1, ld, tile);
+  // a row block holds at most 256 rows: two 16-row slabs for each of 8 waves
+  gemm_rows_mfma<8, 2>(b.y, b.z, In, ld, kin[b.x], Q + qoff[b.x], ko, Out, ld, qs);
 }
 
 void launch_gemm_tall_b(const BatchDev& B, const int* kin, const int* kout, const int64_t* qoff, const double* Q,
                         int max_kin, const double* In, double* Out, hipStream_t st) {
-  const size_t shm = (size_t)max_kin * (GEMM_ROWS + 16) * sizeof(double);
-  hipLaunchKernelGGL(k_gemm_tall_b, dim3(B.nrb), dim3(GEMM_THREADS), shm, st, B.rb, kin, kout, qoff, Q, In, Out,
+  const size_t shm = (size_t)gemm_lds_doubles(max_kin) * sizeof(double);
+  hipLaunchKernelGGL(k_gemm_tall_b, dim3(B.nrb), dim3(512), shm, st, B.rb, kin, kout, qoff, Q, In, Out,
                      B.ntot);
 }
 

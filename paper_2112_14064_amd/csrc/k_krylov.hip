@@ -250,22 +250,24 @@ void launch_cgs_update(int64_t n, int nc, int nq, const double* h,
 // ---------------------------------------------------------------------------
 // Out = In * Q for a tall In (n x kin) and a small Q (kin x kout), one 64-row
 // tile per workgroup (body in krylov_dev.hpp).
-__global__ __launch_bounds__(GEMM_THREADS) void k_gemm_tall(
+constexpr int GEMM_WAVES = 8;   // 128 rows per block, one 16-row slab per wave
+
+__global__ __launch_bounds__(GEMM_WAVES * 64) void k_gemm_tall(
     int64_t n, const double* __restrict__ In, int64_t ldi, int kin, const double* __restrict__ Q,
-    int kout, double* __restrict__ Out, int64_t out_rs, int64_t out_cs) {
-  extern __shared__ double tile[];
-  const int64_t r0 = (int64_t)blockIdx.x * GEMM_ROWS;
-  gemm_tile64(r0, (int)min((int64_t)GEMM_ROWS, n - r0), In, ldi, kin, Q, kout, Out, out_rs, out_cs, tile);
+    int kout, double* __restrict__ Out, int64_t ldo) {
+  extern __shared__ double qs[];
+  const int64_t r0 = (int64_t)blockIdx.x * (16 * GEMM_WAVES);
+  gemm_rows_mfma<GEMM_WAVES, 1>(r0, min(n, r0 + 16 * GEMM_WAVES), In, ldi, kin, Q, kout, Out, ldo, qs);
 }
 
 void launch_gemm_tall(int64_t n, const double* In, int64_t ldi, int kin, const double* Q, int kout,
-                      double* Out, int64_t out_rs, int64_t out_cs, hipStream_t st) {
+                      double* Out, int64_t ldo, hipStream_t st) {
   if (kout <= 0 || kin <= 0 || n <= 0) return;
-  const int64_t blocks = (n + GEMM_ROWS - 1) / GEMM_ROWS;
-  // the In tile and 16 columns of Q in LDS: kin x 80 doubles; callers keep kin <= 256 (160 KiB)
-  const size_t shm = (size_t)kin * (GEMM_ROWS + 16) * sizeof(double);
-  hipLaunchKernelGGL(k_gemm_tall, dim3((unsigned)blocks), dim3(GEMM_THREADS), shm, st, n, In, ldi, kin, Q,
-                     kout, Out, out_rs, out_cs);
+  const int64_t blocks = (n + 16 * GEMM_WAVES - 1) / (16 * GEMM_WAVES);
+  // 64 columns of Q in LDS: at most 64 x 257 doubles (kin <= 254), within the 160 KiB of a CU
+  const size_t shm = (size_t)gemm_lds_doubles(kin) * sizeof(double);
+  hipLaunchKernelGGL(k_gemm_tall, dim3((unsigned)blocks), dim3(GEMM_WAVES * 64), shm, st, n, In, ldi, kin, Q,
+                     kout, Out, ldo);
 }
 
 // ---------------------------------------------------------------------------

@@ -128,9 +128,10 @@ int dots_blocks(int64_t n);
 void launch_cgs_update(int64_t n, int nc, int nq, const double* h,
                        const double* A0, double* Z0, const double* A1, double* Z1,
                        const double* A2, double* Z2, int64_t lda, int64_t ldz, hipStream_t st);
-// Out[i, c] (stride so, co) = sum_t In[i, t] Q[t, c] (Q device, kin x kout col-major).
+// Out[i + c ldo] = sum_t In[i + t ldi] Q[t, c] (Q device, kin x kout col-major,
+// kin <= 254), on the FP64 matrix cores.
 void launch_gemm_tall(int64_t n, const double* In, int64_t ldi, int kin, const double* Q, int kout,
-                      double* Out, int64_t out_rs, int64_t out_cs, hipStream_t st);
+                      double* Out, int64_t ldo, hipStream_t st);
 // Counter-based uniform(-1, 1) fill of a ndof x ncols block (splitmix64 of seed, index).
 void launch_random_fill(double* X, int64_t n, int ncols, int64_t ld, uint64_t seed, hipStream_t st);
 // Eigenvector post-processing on planar complex columns P = [a_1..a_nv | b_1..b_nv]

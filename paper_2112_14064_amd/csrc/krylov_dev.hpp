@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "mfma_layout.hpp"
+
 namespace riga {
 
 // Sparse rows with the implicit tensor sparsity are summed by groups of
@@ -207,46 +209,72 @@ __device__ inline void block_normalize_body(int nc, int nq, const double* h1, co
   if (bad) *flag = 1;
 }
 
-constexpr int GEMM_THREADS = 256;
-constexpr int GEMM_ROWS = 64;     // rows of In per tile
+constexpr int GEMM_COLS = 64;     // columns of Q staged in LDS at a time
+constexpr int GEMM_KCH = 32;      // k-steps of In held in registers at a time
 
-// Rows [r0, r0 + rows) of Out = In * Q (In n x kin with leading dimension ldi,
-// Q kin x kout column-major).  The tile of In is staged in LDS (laid out
-// [t][row] so the lanes of a wave read consecutive words), and so are 16
-// columns of Q at a time (read as broadcasts); lane = row, every wave takes four
-// of those columns.  shm: kin * 64 + kin * 16 doubles.  Called by every thread
-// of a 256-thread block.
-__device__ inline void gemm_tile64(int64_t r0, int rows, const double* __restrict__ In, int64_t ldi, int kin,
-                                   const double* __restrict__ Q, int kout, double* __restrict__ Out,
-                                   int64_t out_rs, int64_t out_cs, double* shm) {
-  double* tile = shm;                         // [t][row]
-  double* qs = shm + (size_t)kin * GEMM_ROWS;  // [c][t], 16 columns
-  __syncthreads();   // the previous tile has been consumed
-  for (int idx = threadIdx.x; idx < GEMM_ROWS * kin; idx += GEMM_THREADS) {
-    const int r = idx % GEMM_ROWS, t = idx / GEMM_ROWS;
-    tile[idx] = (r < rows) ? In[r0 + r + (int64_t)t * ldi] : 0.0;
-  }
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  for (int p0 = 0; p0 < kout; p0 += 16) {
-    const int np = min(16, kout - p0);
-    if (p0 > 0) __syncthreads();   // the previous columns of Q have been consumed
-    for (int idx = threadIdx.x; idx < 16 * kin; idx += GEMM_THREADS) {
-      const int c = idx / kin, t = idx % kin;
-      qs[idx] = (c < np) ? Q[(int64_t)(p0 + c) * kin + t] : 0.0;
+// LDS doubles gemm_rows_mfma needs for a given kin.
+__host__ __device__ inline int gemm_lds_doubles(int kin) { return GEMM_COLS * ((kin + 3) / 4 * 4 + 1); }
+
+// Rows [r0, r1) of Out = In * Q (In with leading dimension ldi and kin
+// columns, Q kin x kout column-major, Out with leading dimension ldo), at most
+// 16 * NWAVES * SLABS rows.  A dense contraction of depth kin: v_mfma_f64_16x16x4_f64,
+// each wave owning SLABS slabs of 16 rows and every output column, 64 columns
+// of Q at a time in LDS (column stride kin rounded up to 4, plus 1).  The In
+// values of GEMM_KCH k-steps are loaded (unconditionally, from clamped
+// addresses, and masked) before their products.  Called by every thread of a
+// block of NWAVES waves; qs: gemm_lds_doubles(kin) doubles of shared memory.
+template <int NWAVES, int SLABS>
+__device__ inline void gemm_rows_mfma(int64_t r0, int64_t r1, const double* __restrict__ In, int64_t ldi, int kin,
+                                      const double* __restrict__ Q, int kout, double* __restrict__ Out,
+                                      int64_t ldo, double* qs) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kr = mfma_ab_k(lane), cl = mfma_b_col(lane);   // A row = B column = lane & 15
+  const int ksteps = (kin + 3) / 4, kp = ksteps * 4 + 1;
+  for (int c0 = 0; c0 < kout; c0 += GEMM_COLS) {
+    const int nc = min(GEMM_COLS, kout - c0);
+    __syncthreads();   // the previous columns of Q have been consumed
+    for (int idx = threadIdx.x; idx < GEMM_COLS * kp; idx += NWAVES * 64) {
+      const int c = idx / kp, t = idx - c * kp;
+      qs[idx] = (c < nc && t < kin) ? Q[(int64_t)(c0 + c) * kin + t] : 0.0;
     }
     __syncthreads();
-    const int c0 = wave * 4;
-    if (c0 >= np) continue;
-    const double* q = qs + (size_t)c0 * kin;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int t = 0; t < kin; ++t) {
-      const double a = tile[t * GEMM_ROWS + lane];
+    const int nj = (nc + 15) / 16;
+    for (int sl = 0; sl < SLABS; ++sl) {
+      const int64_t rb = r0 + (int64_t)(wave * SLABS + sl) * 16;
+      if (rb >= r1) break;
+      const int64_t ra = min(rb + mfma_a_row(lane), r1 - 1);
+      const bool rok = rb + mfma_a_row(lane) < r1;
+      dvec4 acc[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] += a * q[u * kin + t];
+      for (int j = 0; j < 4; ++j) acc[j] = dvec4{0.0, 0.0, 0.0, 0.0};
+      for (int s0 = 0; s0 < ksteps; s0 += GEMM_KCH) {
+        double a[GEMM_KCH];
+#pragma unroll
+        for (int e = 0; e < GEMM_KCH; ++e) {
+          const int t = (s0 + e) * 4 + kr;
+          const double v = In[ra + (int64_t)min(t, kin - 1) * ldi];
+          a[e] = (rok && t < kin) ? v : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < GEMM_KCH; ++e) {
+          if (s0 + e >= ksteps) break;
+          const double* qk = qs + (s0 + e) * 4 + kr;
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (j < nj) acc[j] = Mfma<double>::mma(a[e], qk[(j * 16 + cl) * kp], acc[j]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int c = j * 16 + mfma_d_col(lane);
+        if (j >= nj || c >= nc) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = rb + Mfma<double>::drow(lane, v);
+          if (row < r1) Out[row + (int64_t)(c0 + c) * ldo] = acc[j][v];
+        }
+      }
     }
-    if (lane < rows)
-      for (int u = 0; u < min(4, np - c0); ++u) Out[(r0 + lane) * out_rs + (int64_t)(p0 + c0 + u) * out_cs] = acc[u];
   }
 }
 
