@@ -166,20 +166,21 @@ void apply_block(riga_problem* h, int nb, const double* vu, const double* wl, in
   solve_levels(h, nb, t, N, ru, N, rl, vu, ld, h->sigma);
 }
 
-double host_norm1(riga_problem* h, const double* A) {
-  const int nblk = 512;
-  riga::launch_rowabs(h->plan.rowptr.empty() ? nullptr : h->ds.rowptr, h->N(), A, h->d_part, nblk, h->st);
-  std::vector<double> part(nblk);
-  ck(hipMemcpyAsync(part.data(), h->d_part, nblk * sizeof(double), hipMemcpyDeviceToHost, h->st));
-  ck(hipStreamSynchronize(h->st));
-  return *std::max_element(part.begin(), part.end());
-}
-
+// ||K||_1, ||C||_1, ||M||_1 (largest absolute row sums): one launch, one copy.
 void ensure_norms(riga_problem* h) {
   if (h->norms[0] >= 0) return;
-  h->norms[0] = host_norm1(h, h->d_K);
-  h->norms[1] = host_norm1(h, h->d_C);
-  h->norms[2] = host_norm1(h, h->d_M);
+  const int rows = 1024;
+  const int nblk = (int)((h->N() + rows - 1) / rows);
+  double* part = h->d_part;   // 512 * 400 * 4 doubles: room for 3 per block up to 280M rows
+  riga::launch_rowabs3(nullptr, nblk, h->N(), rows, h->ds.rowptr, h->d_K, h->d_C, h->d_M, part, h->st);
+  std::vector<double> hp((size_t)nblk * 3);
+  ck(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
+  ck(hipStreamSynchronize(h->st));
+  for (int a = 0; a < 3; ++a) {
+    double m = 0.0;
+    for (int b = 0; b < nblk; ++b) m = std::max(m, hp[(size_t)b * 3 + a]);
+    h->norms[a] = m;
+  }
 }
 
 void ensure_krylov(riga_problem* h, int cols, int b) {

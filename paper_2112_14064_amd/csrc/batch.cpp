@@ -36,6 +36,14 @@ struct riga_batch {
   std::vector<double> alpha, beta, sigma;
   std::vector<const double*> celem;
   std::vector<double> norms;             // per problem ||K||_1, ||C||_1, ||M||_1
+  std::vector<int> rb_problem;           // problem of every row block
+  // batched assembly: tables, Gauss rules and damping per problem (device)
+  int max_ne = 0;
+  const int64_t* d_taboff = nullptr;
+  const double* const* d_gx = nullptr;
+  const double* const* d_gw = nullptr;
+  double *d_tabM = nullptr, *d_tabK = nullptr, *d_alpha = nullptr, *d_beta = nullptr;
+  const double** d_celem = nullptr;
   bool assembled = false, factored = false;
   riga::BatchDev B{};
   // Krylov workspace
@@ -225,6 +233,22 @@ riga_status riga_batch_create(riga_batch** out, int n, const riga_mesh* meshes, 
       bh->gx[i] = rule[p].first;
       bh->gw[i] = rule[p].second;
     }
+    // per-problem tables of the batched assembly
+    {
+      std::vector<int64_t> to(n);
+      for (int i = 0; i < n; ++i) {
+        to[i] = (int64_t)taboff[i];
+        bh->max_ne = std::max(bh->max_ne, bh->plans[i].sp.ne);
+      }
+      bh->d_taboff = fp->upload(to);
+      bh->d_gx = fp->upload(std::vector<const double*>(bh->gx.begin(), bh->gx.end()));
+      bh->d_gw = fp->upload(std::vector<const double*>(bh->gw.begin(), bh->gw.end()));
+      bh->d_tabM = dtM;
+      bh->d_tabK = dtK;
+      bh->d_alpha = fp->dalloc<double>(n);
+      bh->d_beta = fp->dalloc<double>(n);
+      bh->d_celem = fp->dalloc<const double*>(n);
+    }
     // problem of every node and row; row blocks and dot blocks
     std::vector<int> rinst(T);
     std::vector<int4> rb, db;
@@ -247,6 +271,8 @@ riga_status riga_batch_create(riga_batch** out, int n, const riga_mesh* meshes, 
     B.kcur = fp->dalloc<int>(n);
     B.flag = fp->dalloc<int>(n);
     B.rb = fp->upload(rb);
+    bh->rb_problem.resize(rb.size());
+    for (size_t b = 0; b < rb.size(); ++b) bh->rb_problem[b] = rb[b].x;
     B.nrb = (int)rb.size();
     B.db = fp->upload(db);
     B.ndb = (int)db.size();
@@ -296,28 +322,31 @@ riga_status riga_batch_assemble(riga_batch* bh, const riga_damping* damping) {
     ck(hipEventRecord(fp->ev0, st));
     bh->alpha.resize(n); bh->beta.resize(n); bh->celem.resize(n);
     for (int i = 0; i < n; ++i) {
-      riga::launch_bspline_tables(bh->hsp[i], bh->gx[i], bh->gw[i], bh->tabM[i], bh->tabK[i], st);
-      riga::launch_assemble(bh->hsp[i], bh->tabM[i], bh->tabK[i], damping[i].alpha, damping[i].beta,
-                            damping[i].c_elem, fp->d_K, fp->d_M, fp->d_C, bh->N(i), st);
       bh->alpha[i] = damping[i].alpha; bh->beta[i] = damping[i].beta; bh->celem[i] = damping[i].c_elem;
     }
+    // the damping of every problem, then tables and entries of all problems in two launches
+    ck(hipMemcpyAsync(bh->d_alpha, bh->alpha.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+    ck(hipMemcpyAsync(bh->d_beta, bh->beta.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+    ck(hipMemcpyAsync((void*)bh->d_celem, bh->celem.data(), n * sizeof(const double*), hipMemcpyHostToDevice, st));
+    riga::launch_assemble_b(bh->B.rb, bh->B.nrb, bh->B.spaces, bh->B.dofbase, bh->d_taboff, bh->d_gx, bh->d_gw, n,
+                            bh->max_ne, bh->d_tabM, bh->d_tabK, bh->d_alpha, bh->d_beta, bh->d_celem, fp->d_K,
+                            fp->d_M, fp->d_C, st);
     ck(hipEventRecord(fp->ev1, st));
-    // 1-norms per problem (largest absolute row sums), one synchronisation
-    const int nblk = 16;
-    double* part = fp->d_part;   // 512 * 400 * 4 doubles: room for 3 * 16 per problem up to n = 1600
-    if ((size_t)n * 3 * nblk > (size_t)512 * 400 * 4) throw std::bad_alloc();
-    const double* mats[3] = {fp->d_K, fp->d_C, fp->d_M};
-    for (int i = 0; i < n; ++i)
-      for (int a = 0; a < 3; ++a)
-        riga::launch_rowabs(bh->hsp[i].rowptr, bh->N(i), mats[a], part + ((size_t)i * 3 + a) * nblk, nblk, st);
-    std::vector<double> h((size_t)n * 3 * nblk);
+    // 1-norms per problem (largest absolute row sums): one launch over the row
+    // blocks of the forest, one synchronisation
+    const int nrb = bh->B.nrb;
+    double* part = fp->d_part;   // 512 * 400 * 4 doubles: room for 3 per row block up to 273,066 blocks
+    if ((size_t)nrb * 3 > (size_t)512 * 400 * 4) throw std::bad_alloc();
+    riga::launch_rowabs3(bh->B.rb, nrb, fp->N(), 0, fp->ds.rowptr, fp->d_K, fp->d_C, fp->d_M, part, st);
+    std::vector<double> h((size_t)nrb * 3);
     ck(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     ck(hipStreamSynchronize(st));
     bh->norms.assign((size_t)n * 3, 0.0);
-    for (int i = 0; i < n; ++i)
-      for (int a = 0; a < 3; ++a)
-        bh->norms[(size_t)i * 3 + a] =
-            *std::max_element(h.begin() + ((size_t)i * 3 + a) * nblk, h.begin() + ((size_t)i * 3 + a + 1) * nblk);
+    for (int b = 0; b < nrb; ++b)
+      for (int a = 0; a < 3; ++a) {
+        double& v = bh->norms[(size_t)bh->rb_problem[b] * 3 + a];
+        v = std::max(v, h[(size_t)b * 3 + a]);
+      }
     float ms = 0;
     ck(hipEventElapsedTime(&ms, fp->ev0, fp->ev1));
     bh->stats.t_assemble_ms = ms;

@@ -33,11 +33,11 @@ __device__ inline void basis_funs(int k, double u, int q, const int* t, double* 
   }
 }
 
-__global__ void k_bspline_tables(int p, int ne, const int* __restrict__ knots, const int* __restrict__ first,
-                                 const double* __restrict__ gx, const double* __restrict__ gw,
-                                 double* __restrict__ tabM, double* __restrict__ tabK) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ne) return;
+// Tables of element e of one 1-D space.
+__device__ inline void element_tables(int e, int p, int ne, const int* __restrict__ knots,
+                                      const int* __restrict__ first, const double* __restrict__ gx,
+                                      const double* __restrict__ gw, double* __restrict__ tabM,
+                                      double* __restrict__ tabK) {
   const int np = p + 1;
   const int k = first[e] + p;  // knot span of the element (knot indices are in element units)
   double m[(MAXP + 1) * (MAXP + 1)], kk[(MAXP + 1) * (MAXP + 1)];
@@ -73,6 +73,25 @@ __global__ void k_bspline_tables(int p, int ne, const int* __restrict__ knots, c
   }
 }
 
+
+__global__ void k_bspline_tables(int p, int ne, const int* __restrict__ knots, const int* __restrict__ first,
+                                 const double* __restrict__ gx, const double* __restrict__ gw,
+                                 double* __restrict__ tabM, double* __restrict__ tabK) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < ne) element_tables(e, p, ne, knots, first, gx, gw, tabM, tabK);
+}
+
+// Every problem of a forest: problem blockIdx.y, its tables at tabM/tabK +
+// taboff[problem], its Gauss rule at gx[problem], gw[problem].
+__global__ void k_bspline_tables_b(const DevSpace* __restrict__ spaces, const int64_t* __restrict__ taboff,
+                                   const double* const* __restrict__ gx, const double* const* __restrict__ gw,
+                                   double* __restrict__ tabM, double* __restrict__ tabK) {
+  const int q = blockIdx.y;
+  const DevSpace sp = spaces[q];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < sp.ne) element_tables(e, sp.p, sp.ne, sp.knots, sp.first, gx[q], gw[q], tabM + taboff[q], tabK + taboff[q]);
+}
+
 void launch_bspline_tables(const DevSpace& s, const double* gx, const double* gw,
                            double* tabM, double* tabK, hipStream_t st) {
   int threads = 64;
@@ -83,18 +102,18 @@ void launch_bspline_tables(const DevSpace& s, const double* gx, const double* gw
 
 constexpr int ASM_ROWS = 64;
 constexpr int ASM_THREADS = 256;
+constexpr int ASM_MAXROWS = 256;   // rows of one block at most (forest row blocks)
 
-__global__ __launch_bounds__(ASM_THREADS) void k_assemble(
-    int p, int ne, int n, const int* __restrict__ sup0, const int* __restrict__ sup1,
-    const int* __restrict__ lo, const int* __restrict__ hi, const int* __restrict__ first,
-    const int64_t* __restrict__ rowptr, int64_t ndof,
-    const double* __restrict__ tabM, const double* __restrict__ tabK,
-    double alpha, double beta, const double* __restrict__ c_elem,
-    double* __restrict__ Ko, double* __restrict__ Mo, double* __restrict__ Co) {
-  __shared__ int64_t rp[ASM_ROWS + 1];
-  const int64_t r0 = (int64_t)blockIdx.x * ASM_ROWS;
-  const int nrows = (int)min((int64_t)ASM_ROWS, ndof - r0);
-  for (int t = threadIdx.x; t <= nrows; t += blockDim.x) rp[t] = rowptr[r0 + t];
+// Entries of rows [r0, r0 + nrows) of one space (row indices local to the
+// space, rowptr its row pointers into the value arrays); rp: nrows + 1 words
+// of shared memory.
+__device__ inline void assemble_rows(const DevSpace& s, int64_t r0, int nrows, const double* __restrict__ tabM,
+                                     const double* __restrict__ tabK, double alpha, double beta,
+                                     const double* __restrict__ c_elem, double* __restrict__ Ko,
+                                     double* __restrict__ Mo, double* __restrict__ Co, int64_t* rp) {
+  const int p = s.p, ne = s.ne, n = s.n;
+  const int *sup0 = s.sup0, *sup1 = s.sup1, *lo = s.lo, *hi = s.hi, *first = s.first;
+  for (int t = threadIdx.x; t <= nrows; t += blockDim.x) rp[t] = s.rowptr[r0 + t];
   __syncthreads();
   const int np = p + 1;
   const int64_t kbeg = rp[0], kend = rp[nrows];
@@ -147,13 +166,51 @@ __global__ __launch_bounds__(ASM_THREADS) void k_assemble(
   }
 }
 
+__global__ __launch_bounds__(ASM_THREADS) void k_assemble(DevSpace s, int64_t ndof, const double* __restrict__ tabM,
+                                                          const double* __restrict__ tabK, double alpha, double beta,
+                                                          const double* __restrict__ c_elem, double* __restrict__ Ko,
+                                                          double* __restrict__ Mo, double* __restrict__ Co) {
+  __shared__ int64_t rp[ASM_ROWS + 1];
+  const int64_t r0 = (int64_t)blockIdx.x * ASM_ROWS;
+  assemble_rows(s, r0, (int)min((int64_t)ASM_ROWS, ndof - r0), tabM, tabK, alpha, beta, c_elem, Ko, Mo, Co, rp);
+}
+
+// Every problem of a forest, one block per row block rb[b] = {problem, first
+// row, end row} (forest rows; the problem's rows start at dofbase).
+__global__ __launch_bounds__(ASM_THREADS) void k_assemble_b(const int4* __restrict__ rb,
+                                                            const DevSpace* __restrict__ spaces,
+                                                            const int64_t* __restrict__ dofbase,
+                                                            const int64_t* __restrict__ taboff,
+                                                            const double* __restrict__ tabM,
+                                                            const double* __restrict__ tabK,
+                                                            const double* __restrict__ alpha,
+                                                            const double* __restrict__ beta,
+                                                            const double* const* __restrict__ c_elem,
+                                                            double* __restrict__ Ko, double* __restrict__ Mo,
+                                                            double* __restrict__ Co) {
+  __shared__ int64_t rp[ASM_MAXROWS + 1];
+  const int4 b = rb[blockIdx.x];
+  const int q = b.x;
+  const DevSpace sp = spaces[q];
+  assemble_rows(sp, b.y - dofbase[q], b.z - b.y, tabM + taboff[q], tabK + taboff[q], alpha[q], beta[q], c_elem[q],
+                Ko, Mo, Co, rp);
+}
+
+void launch_assemble_b(const int4* rb, int nrb, const DevSpace* spaces, const int64_t* dofbase,
+                       const int64_t* taboff, const double* const* gx, const double* const* gw, int n, int max_ne,
+                       double* tabM, double* tabK, const double* alpha, const double* beta,
+                       const double* const* c_elem, double* K, double* M, double* C, hipStream_t st) {
+  hipLaunchKernelGGL(k_bspline_tables_b, dim3((max_ne + 63) / 64, n), dim3(64), 0, st, spaces, taboff, gx, gw, tabM,
+                     tabK);
+  hipLaunchKernelGGL(k_assemble_b, dim3(nrb), dim3(ASM_THREADS), 0, st, rb, spaces, dofbase, taboff, tabM, tabK,
+                     alpha, beta, c_elem, K, M, C);
+}
+
 void launch_assemble(const DevSpace& s, const double* tabM, const double* tabK,
                      double alpha, double beta, const double* c_elem,
                      double* K, double* M, double* C, int64_t ndof, hipStream_t st) {
   int64_t blocks = (ndof + ASM_ROWS - 1) / ASM_ROWS;
-  hipLaunchKernelGGL(k_assemble, dim3((unsigned)blocks), dim3(ASM_THREADS), 0, st,
-                     s.p, s.ne, s.n, s.sup0, s.sup1, s.lo, s.hi, s.first, s.rowptr, ndof,
-                     tabM, tabK, alpha, beta, c_elem, K, M, C);
+  hipLaunchKernelGGL(k_assemble, dim3((unsigned)blocks), dim3(ASM_THREADS), 0, st, s, ndof, tabM, tabK, alpha, beta,
+                     c_elem, K, M, C);
 }
-
 }  // namespace riga

@@ -413,29 +413,58 @@ void launch_finalize(int64_t n, int nv, int nout, const double* P, int64_t ld, c
   hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks), dim3(256), 0, st, n, nv, nout, P, ld, s, X);
 }
 
-// Largest absolute row sum of a CSR value array (the 1-norm of a symmetric
-// matrix); per-block maxima in part[blockIdx.x].
-__global__ __launch_bounds__(256) void k_rowabs(const int64_t* __restrict__ rowptr, int64_t ndof,
-                                                const double* __restrict__ A, double* __restrict__ part) {
-  double best = 0.0;
-  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < ndof; r += (int64_t)gridDim.x * 256) {
-    double s = 0.0;
-    for (int64_t k = rowptr[r]; k < rowptr[r + 1]; ++k) s += fabs(A[k]);
-    best = fmax(best, s);
+// Largest absolute row sums of three CSR value arrays sharing one row-pointer
+// array (the 1-norms of symmetric matrices), per block of rows: block b covers
+// rows rb[b].y .. rb[b].z (or rows b * rows_per_block .. when rb is null) and
+// writes part[3 b + a] for array a.  16 lanes per row, every row's loads of
+// the three arrays in flight together.
+__global__ __launch_bounds__(256) void k_rowabs3(const int4* __restrict__ rb, int64_t ndof, int rows_per_block,
+                                                 const int64_t* __restrict__ rowptr, const double* __restrict__ A0,
+                                                 const double* __restrict__ A1, const double* __restrict__ A2,
+                                                 double* __restrict__ part) {
+  int64_t r0, r1;
+  if (rb != nullptr) {
+    const int4 b = rb[blockIdx.x];
+    r0 = b.y; r1 = b.z;
+  } else {
+    r0 = (int64_t)blockIdx.x * rows_per_block;
+    r1 = min(ndof, r0 + rows_per_block);
   }
-  __shared__ double red[256];
-  red[threadIdx.x] = best;
+  const int g = threadIdx.x % 16;
+  double best[3] = {0.0, 0.0, 0.0};
+  for (int64_t r = r0 + threadIdx.x / 16; r < r1; r += 16) {
+    const int64_t k0 = rowptr[r], k1 = rowptr[r + 1];
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t k = k0 + g; k < k1; k += 16) {
+      s[0] += fabs(A0[k]);
+      s[1] += fabs(A1[k]);
+      s[2] += fabs(A2[k]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) s[a] += __shfl_xor(s[a], off, 16);
+      best[a] = fmax(best[a], s[a]);
+    }
+  }
+  __shared__ double red[3][256];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) red[a][threadIdx.x] = best[a];
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) red[a][threadIdx.x] = fmax(red[a][threadIdx.x], red[a][threadIdx.x + w]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  if (threadIdx.x < 3) part[(int64_t)blockIdx.x * 3 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-void launch_rowabs(const int64_t* rowptr, int64_t ndof, const double* A, double* part, int nblk,
-                   hipStream_t st) {
-  hipLaunchKernelGGL(k_rowabs, dim3(nblk), dim3(256), 0, st, rowptr, ndof, A, part);
+void launch_rowabs3(const int4* rb, int nblocks, int64_t ndof, int rows_per_block, const int64_t* rowptr,
+                    const double* A0, const double* A1, const double* A2, double* part, hipStream_t st) {
+  if (nblocks <= 0) return;
+  hipLaunchKernelGGL(k_rowabs3, dim3(nblocks), dim3(256), 0, st, rb, ndof, rows_per_block, rowptr, A0, A1, A2,
+                     part);
 }
 
 // Out = am M + ac C + ak K on the common CSR pattern: Q(sigma) for the FP64

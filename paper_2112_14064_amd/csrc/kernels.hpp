@@ -48,6 +48,14 @@ void launch_bspline_tables(const DevSpace& s, const double* gx, const double* gw
 void launch_assemble(const DevSpace& s, const double* tabM, const double* tabK,
                      double alpha, double beta, const double* c_elem,
                      double* K, double* M, double* C, int64_t ndof, hipStream_t st);
+// Both steps for every problem of a forest in two launches: per problem q its
+// space spaces[q], first row dofbase[q], tables at tabM/tabK + taboff[q],
+// Gauss rule gx[q]/gw[q] (device pointer arrays), damping alpha[q], beta[q],
+// c_elem[q] (may be null); rb: row blocks of at most 256 rows of one problem.
+void launch_assemble_b(const int4* rb, int nrb, const DevSpace* spaces, const int64_t* dofbase,
+                       const int64_t* taboff, const double* const* gx, const double* const* gw, int n, int max_ne,
+                       double* tabM, double* tabK, const double* alpha, const double* beta,
+                       const double* const* c_elem, double* K, double* M, double* C, hipStream_t st);
 
 // --- factorization ------------------------------------------------------------
 // One tree level: assemble each front (original entries of Q = s2 M + s1 C + K
@@ -143,8 +151,11 @@ void launch_pair_resid(int64_t n, int nv, const double* P, const double* MP, con
                        hipStream_t st);
 void launch_finalize(int64_t n, int nv, int nout, const double* P, int64_t ld, const double* s, double* X,
                      hipStream_t st);
-void launch_rowabs(const int64_t* rowptr, int64_t ndof, const double* A, double* part, int nblk,
-                   hipStream_t st);
+// Largest absolute row sums of A0, A1, A2 (shared rowptr) per block of rows:
+// part[3 b + a].  Blocks are rb[b] = {problem, first row, end row, 0} (forest)
+// or, with rb null, consecutive runs of rows_per_block rows of ndof.
+void launch_rowabs3(const int4* rb, int nblocks, int64_t ndof, int rows_per_block, const int64_t* rowptr,
+                    const double* A0, const double* A1, const double* A2, double* part, hipStream_t st);
 
 // Device-side block normalisation (see k_krylov.hip): H columns k..k+nq from the
 // projection coefficients h1 + h2 and the Cholesky factor of the Gram matrix G;
