@@ -4,6 +4,7 @@
 // keeps only the projected matrix (at most ~100 x 100) and the tree plan.
 #include "problem.hpp"
 #include "ks_host.hpp"
+#include "sweep_plan.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -161,8 +162,8 @@ void solve_levels(riga_problem* h, int nrhs, const double* b, int64_t ldb, doubl
 void apply_block(riga_problem* h, int nb, const double* vu, const double* wl, int64_t ld,
                  double* ru, double* rl, double* t) {
   const int64_t N = h->N();
-  riga::launch_spmv(h->ds, N, nb, h->d_A, 1.0, vu, ld, t, N, wl, ld, 1.0, nullptr, 0,
-                    h->st);
+  riga::launch_spmv_ell(h->d_slabs, h->nslab, h->d_space1, nullptr, nullptr, nb, h->d_Aell, vu, ld, t, N, wl, ld,
+                        1.0, h->st);
   solve_levels(h, nb, t, N, ru, N, rl, vu, ld, h->sigma);
 }
 
@@ -243,6 +244,16 @@ std::vector<double> upper_inverse(int b, const std::vector<double>& R) {
   return X;
 }
 
+void setup_ell(riga_problem* h, const std::vector<int4>& ranges) {
+  std::vector<riga::EllSlab> slabs;
+  const int64_t entries = riga::build_ell_slabs(h->plan.rowptr, ranges, slabs);
+  h->nslab = (int)slabs.size();
+  h->d_slabs = h->upload(slabs);
+  h->d_Aell = h->dalloc<double>(entries);
+  h->d_Mell = h->dalloc<double>(entries);
+  h->d_space1 = h->upload(std::vector<riga::DevSpace>{h->ds});
+}
+
 void setup_device(riga_problem* h) {
     const riga::Plan& P = h->plan;
     const riga::Space1D& S = P.sp;
@@ -258,29 +269,12 @@ void setup_device(riga_problem* h) {
     h->dt.fkey = h->upload(P.fkey); h->dt.fpos = h->upload(P.fpos);
     h->dt.coff = h->upload(P.coff); h->dt.clist = h->upload(P.clist);
     h->dt.moff = h->upload(P.moff); h->dt.maps = h->upload(P.maps);
-    std::vector<int> voff(P.nb.size() + 1, 0);
-    for (size_t v = 0; v < P.nb.size(); ++v) voff[v + 1] = voff[v] + P.nb[v];
-    h->upd_len = voff.back();
-    h->dt.voff = h->upload(voff);
-    {
-      // per front position, the children's update rows that land on it, in child order
-      const size_t npos = (size_t)P.foff.back();
-      std::vector<int> gcnt(npos + 1, 0), gptr(npos + 1, 0), gidx((size_t)h->upd_len);
-      for (size_t v = 0; v < P.nf.size(); ++v)
-        for (int ci = P.coff[v]; ci < P.coff[v + 1]; ++ci) {
-          const int c = P.clist[ci];
-          for (int k = 0; k < P.nb[c]; ++k) ++gcnt[P.foff[v] + P.maps[P.moff[c] + k]];
-        }
-      for (size_t q = 0; q < npos; ++q) gptr[q + 1] = gptr[q] + gcnt[q];
-      std::vector<int> fill(gptr.begin(), gptr.end() - 1);
-      for (size_t v = 0; v < P.nf.size(); ++v)
-        for (int ci = P.coff[v]; ci < P.coff[v + 1]; ++ci) {
-          const int c = P.clist[ci];
-          for (int k = 0; k < P.nb[c]; ++k) gidx[fill[P.foff[v] + P.maps[P.moff[c] + k]]++] = voff[c] + k;
-        }
-      h->dt.gptr = h->upload(gptr);
-      h->dt.gidx = h->upload(gidx);
-    }
+    riga::SweepPlan sw;
+    riga::build_sweep_plan(P, h->node_inst, sw);
+    h->upd_len = sw.voff.back();
+    h->dt.voff = h->upload(sw.voff);
+    h->dt.gptr = h->upload(sw.gptr);
+    h->dt.gidx = h->upload(sw.gidx);
     h->d_level_nodes = h->upload(P.level_nodes);
     std::vector<double> gx, gw;
     gauss_legendre(S.p + 1, gx, gw);
@@ -292,30 +286,17 @@ void setup_device(riga_problem* h) {
     h->d_A = h->dalloc<double>(P.nnz);
     h->d_L = h->dalloc<double>(P.lsize); h->d_U = h->dalloc<double>(P.usize);
     h->d_T = h->dalloc<double>(P.lsize);
-    // sweep layouts: every node padded to groups of 4 columns / rows
-    std::vector<int64_t> lpoff(P.nf.size() + 1, 0), tpoff(P.nf.size() + 1, 0);
-    {
-      for (size_t v = 0; v < P.nf.size(); ++v) {
-        lpoff[v + 1] = lpoff[v] + (int64_t)((P.no[v] + 3) / 4 * 4) * P.nf[v];
-        tpoff[v + 1] = tpoff[v] + (int64_t)((P.nf[v] + 3) / 4 * 4) * P.no[v];
-      }
-      // slack past the last node: a forward task of a node without own dofs
-      // reads (and discards) one round at the node's offset
-      const int64_t slack = ((int64_t)P.max_front + 64) * 4;
-      h->lpsize = lpoff.back() + slack;
-      h->tpsize = tpoff.back() + slack;
-      h->dt.lpoff = h->upload(lpoff);
-      h->dt.tpoff = h->upload(tpoff);
-      h->d_Lp = h->dalloc<double>(h->lpsize);
-      h->d_Tp = h->dalloc<double>(h->tpsize);
-    }
+    h->lpsize = sw.lpsize;
+    h->tpsize = sw.tpsize;
+    h->dt.lpoff = h->upload(sw.lpoff);
+    h->dt.tpoff = h->upload(sw.tpoff);
+    h->d_Lp = h->dalloc<double>(h->lpsize);
+    h->d_Tp = h->dalloc<double>(h->tpsize);
     {
       std::vector<int64_t> doff(P.nf.size() + 1, 0);
       for (size_t v = 0; v < P.nf.size(); ++v) doff[v + 1] = doff[v] + (P.no[v] + 63) / 64;
       h->dt.doff = h->upload(doff);
       h->d_D = h->dalloc<double>((size_t)doff.back() * 4096);
-      h->fvar.assign(P.height, 0);
-      h->bvar.assign(P.height, 0);
       h->lvl_max_no.assign(P.height, 0);
       h->lvl_max_nf.assign(P.height, 0);
       h->lvl_max_cnb.assign(P.height, 0);
@@ -329,41 +310,12 @@ void setup_device(riga_problem* h) {
           h->lvl_max_kids[lv] = std::max(h->lvl_max_kids[lv], (int)P.nodes[v].children.size());
         }
     }
-    {
-      // Row tasks of the solve sweeps: blocks of 64 consecutive rows of one
-      // node.  Within a level the tasks are launched largest first (columns a
-      // forward task reads: up to its last row's diagonal; rows a backward task
-      // reads: from its first column down), so the short ones fill the tail.
-      std::vector<riga::SweepTask> ft, bt;
-      h->ftask_off.assign(P.height + 1, 0);
-      h->btask_off.assign(P.height + 1, 0);
-      auto task = [&](int v, int r0, int r1, int64_t poff) {
-        riga::SweepTask k{};
-        k.v = v; k.r0 = r0; k.r1 = r1; k.nf = P.nf[v]; k.no = P.no[v]; k.foff = P.foff[v];
-        k.voff = voff[v]; k.inst = h->node_inst.empty() ? 0 : h->node_inst[v]; k.poff = poff;
-        return k;
-      };
-      for (int lv = 0; lv < P.height; ++lv) {
-        const size_t f0 = ft.size(), b0 = bt.size();
-        for (int k = P.level_off[lv]; k < P.level_off[lv + 1]; ++k) {
-          const int v = P.level_nodes[k];
-          for (int r = 0; r < P.nf[v]; r += 64) ft.push_back(task(v, r, std::min(r + 64, P.nf[v]), lpoff[v]));
-          for (int r = 0; r < P.no[v]; r += 64) bt.push_back(task(v, r, std::min(r + 64, P.no[v]), tpoff[v]));
-        }
-        std::stable_sort(ft.begin() + f0, ft.end(), [](const riga::SweepTask& x, const riga::SweepTask& y) {
-          return std::min(x.r1, x.no) > std::min(y.r1, y.no);
-        });
-        std::stable_sort(bt.begin() + b0, bt.end(), [](const riga::SweepTask& x, const riga::SweepTask& y) {
-          return x.nf - x.r0 > y.nf - y.r0;
-        });
-        h->ftask_off[lv + 1] = (int)ft.size();
-        h->btask_off[lv + 1] = (int)bt.size();
-        h->fvar[lv] = (h->ftask_off[lv + 1] - h->ftask_off[lv] >= 1024) ? riga::SWEEP_WIDE : riga::SWEEP_NARROW;
-        h->bvar[lv] = (h->btask_off[lv + 1] - h->btask_off[lv] >= 1024) ? riga::SWEEP_WIDE : riga::SWEEP_NARROW;
-      }
-      h->d_ftasks = h->upload(ft);
-      h->d_btasks = h->upload(bt);
-    }
+    h->ftask_off = sw.ftask_off;
+    h->btask_off = sw.btask_off;
+    h->fvar = sw.fvar;
+    h->bvar = sw.bvar;
+    h->d_ftasks = h->upload(sw.ftasks);
+    h->d_btasks = h->upload(sw.btasks);
     h->d_upd = h->dalloc<double>((size_t)h->upd_len * 4);
     h->d_tmp = h->dalloc<double>((size_t)P.ndof * 4);
     h->d_tmp2 = h->dalloc<double>((size_t)P.ndof * 4);
@@ -410,6 +362,7 @@ riga_status riga_create(riga_problem** out, const riga_mesh* mesh, int device, v
     h->device = device;
     h->st = (hipStream_t)hip_stream;
     setup_device(h);
+    setup_ell(h, {int4{0, 0, (int)h->N(), 0}});
     return RIGA_OK;
   });
   if (rc != RIGA_OK) {
@@ -460,6 +413,7 @@ riga_status riga_assemble(riga_problem* h, const riga_damping* damping) {
     riga::launch_bspline_tables(h->ds, h->d_gx, h->d_gw, h->d_tabM, h->d_tabK, h->st);
     riga::launch_assemble(h->ds, h->d_tabM, h->d_tabK, damping->alpha, damping->beta, damping->c_elem,
                           h->d_K, h->d_M, h->d_C, h->N(), h->st);
+    riga::launch_csr_to_ell(h->d_slabs, h->nslab, h->ds.rowptr, h->d_M, h->d_Mell, h->st);
     ck(hipGetLastError());
     ck(hipEventRecord(h->ev1, h->st));
     h->alpha = damping->alpha; h->beta = damping->beta; h->c_elem = damping->c_elem;
@@ -523,6 +477,8 @@ riga_status factor_all(riga_problem* h, double sigma, int64_t* bad_pivot) {
   for (int lv = 0; lv < P.height; ++lv) factor_level(h, lv, sigma);
   // sigma M + C for the operator, Q(sigma) for the residuals of the mixed factor
   riga::launch_combine3(P.nnz, sigma, h->d_M, 1.0, h->d_C, 0.0, h->d_K, h->d_A, h->st);
+  // (a forest combines its per-problem shifts itself and converts then)
+  if (h->node_inst.empty()) riga::launch_csr_to_ell(h->d_slabs, h->nslab, h->ds.rowptr, h->d_A, h->d_Aell, h->st);
   if (h->mixed) riga::launch_combine3(P.nnz, sigma * sigma, h->d_M, sigma, h->d_C, 1.0, h->d_K, h->d_Q, h->st);
   ck(hipGetLastError());
   ck(hipEventRecord(h->ev1, h->st));
@@ -1156,8 +1112,8 @@ struct KrylovRun {
     const int64_t n = N;
     const size_t o = (size_t)k * n;
     apply_block(h, b, h->Vu + o, h->Wl + o, n, h->Ru, h->Rl, h->Tv);
-    riga::launch_spmv(h->ds, n, b, h->d_M, 1.0, h->Rl, n, h->MRl, n, nullptr, 0, 0.0,
-                      nullptr, 0, h->st);
+    riga::launch_spmv_ell(h->d_slabs, h->nslab, h->d_space1, nullptr, nullptr, b, h->d_Mell, h->Rl, n, h->MRl, n,
+                          nullptr, 0, 0.0, h->st);
     orthonormalize_device(k + b, h->d_H, k);
   }
 

@@ -129,13 +129,15 @@ void enqueue_step(riga_batch* bh, int b, int m, int ldh, hipStream_t st) {
   const int hs = ldh * b;
   riga::launch_gather_b(B, b, bh->Vu, bh->Wl, bh->Xu, bh->Xw, st);
   // t = (sigma M + C) v_u + M v_l (eq. BlockOperatorVector), sigma M + C formed per problem
-  riga::launch_spmv_b(B, b, fp->d_A, bh->Xu, T, bh->Tv, T, bh->Xw, T, 1.0, st);
+  riga::launch_spmv_ell(fp->d_slabs, fp->nslab, B.spaces, B.dofbase, B.live, b, fp->d_Aell, bh->Xu, T, bh->Tv, T,
+                        bh->Xw, T, 1.0, st);
   // r_u = -Q^{-1} t, r_l = sigma r_u + v_u (sigma of each node's problem)
   riga::BwdOut o;
   o.xs = bh->Ru; o.ldxs = T; o.neg = 1; o.ldr = T;
   o.rl = bh->Rl; o.v_u = bh->Xu; o.ldv = T;
   sweep(fp, b, bh->Tv, T, o);
-  riga::launch_spmv_b(B, b, fp->d_M, bh->Rl, T, bh->MRl, T, nullptr, 0, 0.0, st);
+  riga::launch_spmv_ell(fp->d_slabs, fp->nslab, B.spaces, B.dofbase, B.live, b, fp->d_Mell, bh->Rl, T, bh->MRl, T,
+                        nullptr, 0, 0.0, st);
   // classical Gram--Schmidt twice against V[:, 0:k+b], B-inner products
   riga::launch_dots_b(B, b, 0, true, bh->Vu, bh->Wl, b, bh->Ru, bh->Rl, bh->h1, hs, st);
   riga::launch_cgs_update_b(B, b, b, bh->h1, hs, bh->Vu, bh->Ru, bh->Vl, bh->Rl, bh->Wl, bh->MRl, m + b, st);
@@ -184,6 +186,11 @@ riga_status riga_batch_create(riga_batch** out, int n, const riga_mesh* meshes, 
     for (int i = 0; i < n; ++i)
       for (int v = bh->node_base[i]; v < bh->node_base[i + 1]; ++v) fp->node_inst[v] = i;
     setup_device(fp);
+    {
+      std::vector<int4> ranges(n);
+      for (int i = 0; i < n; ++i) ranges[i] = int4{i, (int)bh->dof_base[i], (int)bh->dof_base[i + 1], 0};
+      setup_ell(fp, ranges);
+    }
     const int64_t T = fp->plan.ndof;
     // per-problem 1-D spaces in shared arrays, rows into the forest CSR
     std::vector<int> knots, sup0, sup1, lo, hi, first;
@@ -331,6 +338,7 @@ riga_status riga_batch_assemble(riga_batch* bh, const riga_damping* damping) {
     riga::launch_assemble_b(bh->B.rb, bh->B.nrb, bh->B.spaces, bh->B.dofbase, bh->d_taboff, bh->d_gx, bh->d_gw, n,
                             bh->max_ne, bh->d_tabM, bh->d_tabK, bh->d_alpha, bh->d_beta, bh->d_celem, fp->d_K,
                             fp->d_M, fp->d_C, st);
+    riga::launch_csr_to_ell(fp->d_slabs, fp->nslab, fp->ds.rowptr, fp->d_M, fp->d_Mell, st);
     ck(hipEventRecord(fp->ev1, st));
     // 1-norms per problem (largest absolute row sums): one launch over the row
     // blocks of the forest, one synchronisation
@@ -373,6 +381,7 @@ riga_status riga_batch_factor(riga_batch* bh, const double* sigmas, int64_t* bad
     int64_t bad = -1;
     riga_status rc = factor_all(fp, 1.0, &bad);
     riga::launch_combine_b(bh->n, bh->d_nzbase, fp->plan.nnz, bh->B.sig, fp->d_M, fp->d_C, fp->d_A, bh->user_st);
+    riga::launch_csr_to_ell(fp->d_slabs, fp->nslab, fp->ds.rowptr, fp->d_A, fp->d_Aell, bh->user_st);
     bh->stats.t_factor_ms = fp->stats.t_factor_ms;
     if (rc == RIGA_ERR_NOT_SPD && bad >= 0) {
       const int i = (int)(std::upper_bound(bh->dof_base.begin(), bh->dof_base.end(), bad) - bh->dof_base.begin()) - 1;
@@ -429,7 +438,8 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
     ck(hipMemsetAsync(bh->H, 0, sizeof(double) * (size_t)n * ldh * ldh, st));
     riga::launch_random_fill(bh->Ru, T, b, T, opt->seed * 2 + 1, st);
     riga::launch_random_fill(bh->Rl, T, b, T, opt->seed * 2 + 2, st);
-    riga::launch_spmv_b(B, b, fp->d_M, bh->Rl, T, bh->MRl, T, nullptr, 0, 0.0, st);
+    riga::launch_spmv_ell(fp->d_slabs, fp->nslab, B.spaces, B.dofbase, B.live, b, fp->d_Mell, bh->Rl, T, bh->MRl, T,
+                        nullptr, 0, 0.0, st);
     riga::launch_dots_b(B, 0, b, false, bh->Ru, bh->MRl, b, bh->Ru, bh->Rl, bh->G, b * b, st);
     riga::launch_block_normalize_b(B, false, 0, b, nullptr, nullptr, 0, bh->G, nullptr, ldh, bh->Rinv, st);
     riga::launch_gemm3_b(B, false, 0, b, bh->Rinv, bh->Ru, bh->Vu, bh->Rl, bh->Vl, bh->MRl, bh->Wl, st);

@@ -15,66 +15,6 @@ namespace riga {
 
 constexpr int BT = 256;   // threads per block of the row-parallel kernels
 
-// Y = A X + bz Z (Z may be null) on every live problem's rows, implicit
-// tensor columns of the row's problem space; 16 lanes per row.
-template <int NC>
-__global__ __launch_bounds__(BT) void k_spmv_b(const int* __restrict__ rinst, const DevSpace* __restrict__ spaces,
-                                               const int64_t* __restrict__ dofbase,
-                                               const unsigned char* __restrict__ live, int64_t ntot,
-                                               const double* __restrict__ A, const double* __restrict__ X,
-                                               int64_t ldx, double* __restrict__ Y, int64_t ldy,
-                                               const double* __restrict__ Z, int64_t ldz, double bz) {
-  const int g = threadIdx.x % SPMV_G;
-  const int64_t r = ((int64_t)blockIdx.x * BT + threadIdx.x) / SPMV_G;
-  const int q0 = r < ntot ? rinst[r] : 0;
-  const bool active = r < ntot && (live == nullptr || live[q0]);
-  double s[NC];
-#pragma unroll
-  for (int q = 0; q < NC; ++q) s[q] = 0.0;
-  if (active) {
-    const DevSpace& sp = spaces[q0];
-    const int64_t base = dofbase[q0];
-    const int n = sp.n;
-    const int64_t rl = r - base;
-    const unsigned ru = (unsigned)rl, j = ru / (unsigned)n, i = ru - j * (unsigned)n;
-    const int lx = sp.lo[i], hx = sp.hi[i], ly = sp.lo[j];
-    const int64_t k0 = sp.rowptr[rl], k1 = sp.rowptr[rl + 1];
-    asm volatile("" ::"v"(lx), "v"(hx), "v"(ly));
-    tensor_row_sum<NC>(A + k0, (int)(k1 - k0), X + base + (int64_t)ly * n + lx, ldx, n, hx - lx + 1, g, s);
-  }
-#pragma unroll
-  for (int q = 0; q < NC; ++q)
-#pragma unroll
-    for (int off = SPMV_G / 2; off > 0; off >>= 1) s[q] += __shfl_xor(s[q], off, SPMV_G);
-  if (active && g == 0) {
-#pragma unroll
-    for (int q = 0; q < NC; ++q) {
-      double val = s[q];
-      if (Z) val += bz * Z[r + q * ldz];
-      Y[r + q * ldy] = val;
-    }
-  }
-}
-
-void launch_spmv_b(const BatchDev& B, int ncols, const double* A, const double* X, int64_t ldx, double* Y,
-                   int64_t ldy, const double* Z, int64_t ldz, double bz, hipStream_t st) {
-  const int64_t blocks = (B.ntot * SPMV_G + BT - 1) / BT;
-#define RIGA_SPMVB(NC)                                                                                        \
-  hipLaunchKernelGGL(k_spmv_b<NC>, dim3((unsigned)blocks), dim3(BT), 0, st, B.rinst, B.spaces, B.dofbase, B.live, \
-                     B.ntot, A, X, ldx, Y, ldy, Z, ldz, bz)
-  switch (ncols) {
-    case 1: RIGA_SPMVB(1); break;
-    case 2: RIGA_SPMVB(2); break;
-    case 3: RIGA_SPMVB(3); break;
-    case 4: RIGA_SPMVB(4); break;
-    case 5: RIGA_SPMVB(5); break;
-    case 6: RIGA_SPMVB(6); break;
-    case 7: RIGA_SPMVB(7); break;
-    default: RIGA_SPMVB(8); break;
-  }
-#undef RIGA_SPMVB
-}
-
 // A = sigma_p M + C on every problem's rows (nonzero ranges nzbase[p] .. nzbase[p+1]).
 __global__ __launch_bounds__(BT) void k_combine_b(int n, const int64_t* __restrict__ nzbase,
                                                   const double* __restrict__ sig, const double* __restrict__ M,

@@ -73,6 +73,129 @@ void launch_spmv(const DevSpace& s, int64_t ndof, int ncols, const double* A, do
 #undef RIGA_SPMV
 }
 
+// ---------------------------------------------------------------------------
+// Sliced-ELL products: a workgroup per slab of 64 rows, lane = row, its waves
+// taking interleaved rounds of entries (partial sums added in LDS in wave
+// order).  The matrix is read in 512-byte coalesced rows of the slab; the
+// vector entries of a row are
+// the implicit tensor columns, which consecutive rows of a grid line share
+// shifted by one, so the gathers of a wave fall on a few cache lines.
+int64_t build_ell_slabs(const std::vector<int64_t>& rowptr, const std::vector<int4>& ranges,
+                        std::vector<EllSlab>& slabs) {
+  slabs.clear();
+  int64_t off = 0;
+  for (const int4& rg : ranges)
+    for (int64_t r = rg.y; r < rg.z; r += 64) {
+      EllSlab sb{};
+      sb.inst = rg.x;
+      sb.r0 = (int)r;
+      sb.nrows = (int)std::min<int64_t>(64, rg.z - r);
+      int w = 0;
+      for (int l = 0; l < sb.nrows; ++l) w = std::max(w, (int)(rowptr[r + l + 1] - rowptr[r + l]));
+      sb.width = w;
+      sb.off = off;
+      off += (int64_t)w * 64;
+      slabs.push_back(sb);
+    }
+  return off;
+}
+
+__global__ __launch_bounds__(64) void k_csr_to_ell(const EllSlab* __restrict__ slabs,
+                                                   const int64_t* __restrict__ rowptr,
+                                                   const double* __restrict__ V, double* __restrict__ E) {
+  const EllSlab sb = slabs[blockIdx.x];
+  const int l = threadIdx.x;
+  const bool act = l < sb.nrows;
+  int64_t k0 = 0, len = 0;
+  if (act) {
+    k0 = rowptr[sb.r0 + l];
+    len = rowptr[sb.r0 + l + 1] - k0;
+  }
+  for (int o = 0; o < sb.width; ++o) E[sb.off + (int64_t)o * 64 + l] = (o < len) ? V[k0 + o] : 0.0;
+}
+
+void launch_csr_to_ell(const EllSlab* slabs, int nslab, const int64_t* rowptr, const double* V, double* E,
+                       hipStream_t st) {
+  if (nslab <= 0) return;
+  hipLaunchKernelGGL(k_csr_to_ell, dim3(nslab), dim3(64), 0, st, slabs, rowptr, V, E);
+}
+
+constexpr int ELL_U = 7;   // entries per round: one stencil line of a degree-3 row
+constexpr int ELL_W = 4;   // waves per slab, taking interleaved rounds
+
+template <int NC>
+__global__ __launch_bounds__(ELL_W * 64) void k_spmv_ell(const EllSlab* __restrict__ slabs, int nslab,
+                                                         const DevSpace* __restrict__ spaces,
+                                                         const int64_t* __restrict__ dofbase,
+                                                         const unsigned char* __restrict__ live,
+                                                         const double* __restrict__ E, const double* __restrict__ X,
+                                                         int64_t ldx, double* __restrict__ Y, int64_t ldy,
+                                                         const double* __restrict__ Z, int64_t ldz, double bz) {
+  __shared__ double red[ELL_W][64][NC];
+  const EllSlab sb = slabs[blockIdx.x];
+  if (live != nullptr && !live[sb.inst]) return;
+  const DevSpace sp = spaces[sb.inst];
+  const int64_t base = dofbase != nullptr ? dofbase[sb.inst] : 0;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const bool act = l < sb.nrows;
+  const unsigned rl = (unsigned)(sb.r0 - base) + (act ? (unsigned)l : 0u);   // row within its problem
+  const unsigned n = (unsigned)sp.n, j = rl / n, i = rl - j * n;
+  const int lx = sp.lo[i], hx = sp.hi[i], ly = sp.lo[j], hy = sp.hi[j];
+  const int wx = hx - lx + 1, len = wx * (hy - ly + 1);
+  const double* xb = X + base + (int64_t)ly * n + lx;
+  const double* xr = X + base + rl;          // a valid address for padded entries
+  const double* e = E + sb.off + l;
+  double acc[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) acc[q] = 0.0;
+  for (int o0 = w * ELL_U; o0 < sb.width; o0 += ELL_W * ELL_U) {
+    double av[ELL_U], xv[ELL_U][NC];
+#pragma unroll
+    for (int u = 0; u < ELL_U; ++u) {
+      const int o = o0 + u;
+      const double a = e[(int64_t)min(o, sb.width - 1) * 64];
+      av[u] = (o < sb.width) ? a : 0.0;
+      const int dy = o / wx;
+      const double* xp = (o < len) ? xb + (int64_t)dy * n + (o - dy * wx) : xr;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) xv[u][q] = xp[q * ldx];
+    }
+#pragma unroll
+    for (int u = 0; u < ELL_U; ++u)
+#pragma unroll
+      for (int q = 0; q < NC; ++q) acc[q] += av[u] * xv[u][q];
+  }
+#pragma unroll
+  for (int q = 0; q < NC; ++q) red[w][l][q] = acc[q];
+  __syncthreads();
+  if (w == 0 && act) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      double val = 0.0;
+#pragma unroll
+      for (int v = 0; v < ELL_W; ++v) val += red[v][l][q];
+      if (Z) val += bz * Z[base + rl + q * ldz];
+      Y[base + rl + q * ldy] = val;
+    }
+  }
+}
+
+void launch_spmv_ell(const EllSlab* slabs, int nslab, const DevSpace* spaces, const int64_t* dofbase,
+                     const unsigned char* live, int ncols, const double* E, const double* X, int64_t ldx, double* Y,
+                     int64_t ldy, const double* Z, int64_t ldz, double bz, hipStream_t st) {
+  if (nslab <= 0) return;
+#define RIGA_SPMV_ELL(NC)                                                                                        \
+  hipLaunchKernelGGL(k_spmv_ell<NC>, dim3(nslab), dim3(ELL_W * 64), 0, st, slabs, nslab, spaces, dofbase, live, E, X, \
+                     ldx, Y, ldy, Z, ldz, bz)
+  switch (ncols) {
+    case 1: RIGA_SPMV_ELL(1); break;
+    case 2: RIGA_SPMV_ELL(2); break;
+    case 3: RIGA_SPMV_ELL(3); break;
+    default: RIGA_SPMV_ELL(4); break;
+  }
+#undef RIGA_SPMV_ELL
+}
+
 // Three products with one pass over X: Y0 = A0 X, Y1 = A1 X, Y2 = A2 X.
 template <int NC>
 __global__ __launch_bounds__(SPMV_THREADS) void k_spmv3(

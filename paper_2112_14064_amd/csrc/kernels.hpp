@@ -2,6 +2,7 @@
 // unless stated otherwise; every launch is asynchronous on `st`.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <vector>
 #include <cstdint>
 
 namespace riga {
@@ -117,6 +118,27 @@ void launch_bwd_level(const DevTree& t, const SweepTask* tasks, int count, int n
                       hipStream_t st);
 
 // --- Krylov building blocks -----------------------------------------------------
+// Sliced-ELL copy of a CSR value array for the Krylov products: slabs of 64
+// consecutive rows of one problem; entry o of the slab's row r0 + l at
+// E[off + 64 o + l] for o < width (the slab's longest row; shorter rows padded
+// with zeros).  Columns stay implicit in the tensor structure.
+struct alignas(16) EllSlab {
+  int inst, r0, nrows, width;   // problem (0 for one problem), first row (global), rows, entries per row
+  int64_t off;
+};
+// Slabs of the rows [r0, r1) of problem inst for every range; returns the
+// entries of the layout.
+int64_t build_ell_slabs(const std::vector<int64_t>& rowptr, const std::vector<int4>& ranges,
+                        std::vector<EllSlab>& slabs);
+void launch_csr_to_ell(const EllSlab* slabs, int nslab, const int64_t* rowptr, const double* V, double* E,
+                       hipStream_t st);
+// Y = E X + bz Z (Z may be null) on the slabs' rows (of live problems when
+// live is not null): spaces[inst] and dofbase[inst] (null: 0) locate a slab's
+// problem.  ncols <= 4; a workgroup per slab, lane = row, its 4 waves taking
+// interleaved rounds of 7 entries whose loads are in flight together.
+void launch_spmv_ell(const EllSlab* slabs, int nslab, const DevSpace* spaces, const int64_t* dofbase,
+                     const unsigned char* live, int ncols, const double* E, const double* X, int64_t ldx, double* Y,
+                     int64_t ldy, const double* Z, int64_t ldz, double bz, hipStream_t st);
 // Y = a A X + bz Z (Z may be null) and optionally Y2 = A X.  X, Y, Z, Y2:
 // ndof x ncols (ld given), ncols <= 8.
 void launch_spmv(const DevSpace& s, int64_t ndof, int ncols, const double* A, double a, const double* X,
@@ -192,10 +214,6 @@ struct BatchDev {
   double* partial = nullptr;        // dot partial sums, pstride per dot block
   int pstride = 0;
 };
-// Y = A X + bz Z (Z may be null) on every live problem's rows; ncols <= 8,
-// every vector ntot x ncols with the given leading dimensions.
-void launch_spmv_b(const BatchDev& B, int ncols, const double* A, const double* X, int64_t ldx, double* Y,
-                   int64_t ldy, const double* Z, int64_t ldz, double bz, hipStream_t st);
 // A = sigma_p M + C per problem (nonzeros of problem p in [nzbase[p], nzbase[p+1])).
 void launch_combine_b(int n, const int64_t* nzbase, int64_t nnz, const double* sig, const double* M, const double* C,
                       double* A, hipStream_t st);

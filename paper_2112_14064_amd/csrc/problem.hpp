@@ -45,6 +45,11 @@ struct riga_problem {
   double *d_Lp = nullptr, *d_Tp = nullptr;         // F in the sweep layouts
   int64_t lpsize = 0, tpsize = 0;
   riga::SweepTask *d_ftasks = nullptr, *d_btasks = nullptr;   // solve tasks, grouped by level
+  // sliced-ELL copies of sigma M + C and M for the Krylov products
+  riga::EllSlab* d_slabs = nullptr;
+  int nslab = 0;
+  double *d_Aell = nullptr, *d_Mell = nullptr;
+  riga::DevSpace* d_space1 = nullptr;   // the problem's space as a one-entry device table
   std::vector<int> node_inst;                     // forest: problem of every node (set before setup)
   double* d_D = nullptr;                            // 64x64 diagonal-block inverses
   std::vector<int> lvl_max_no, lvl_max_nf, lvl_max_cnb, lvl_max_kids;
@@ -140,6 +145,9 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 std::vector<int> canonical_order(const std::vector<cplx>& lam, double sigma);
 // Upload h->plan and allocate every device array of the handle.
 void setup_device(riga_problem* h);
+// Sliced-ELL slabs over the row ranges {problem, first row, end row} and the
+// two ELL value arrays.
+void setup_ell(riga_problem* h, const std::vector<int4>& ranges);
 // Solves with the factor (see api.cpp).
 void sweep(riga_problem* h, int nrhs, const double* b, int64_t ldb, const riga::BwdOut& o);
 void solve_levels(riga_problem* h, int nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
