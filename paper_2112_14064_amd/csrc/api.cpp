@@ -978,7 +978,7 @@ struct KrylovRun {
     for (int pass = 0; pass < 2; ++pass) {
       riga::launch_dots(n, nc, h->Vu, h->Wl, n, nq, ru, rl, n, h->d_part, h->d_ticket, dh + (size_t)pass * ldh * b,
                         h->st);
-      riga::launch_cgs_update(n, nc, nq, dh + (size_t)pass * ldh * b, h->Vu, ru, h->Vl, rl, h->Wl, mrl, n, n, h->st);
+      riga::launch_cgs_update(n, nc, nq, dh + (size_t)pass * ldh * b, h->Vu, ru, h->Vl, rl, h->Wl, mrl, n, n, nullptr, h->st);
     }
     n_vv += 8LL * nc * nq;
     if (hsum) {
@@ -1026,15 +1026,19 @@ struct KrylovRun {
     double* h2 = h->d_small + (size_t)ldh * b;
     double* dG = h->d_small + (size_t)2 * ldh * b;
     double* dRinv = h->d_small + (size_t)2 * ldh * b + 16;
+    int gblk = 0;
     if (nc > 0) {
       riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, h1, h->st);
-      riga::launch_cgs_update(N, nc, b, h1, h->Vu, h->Ru, h->Vl, h->Rl, h->Wl, h->MRl, N, N, h->st);
+      riga::launch_cgs_update(N, nc, b, h1, h->Vu, h->Ru, h->Vl, h->Rl, h->Wl, h->MRl, N, N, nullptr, h->st);
       riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, h2, h->st);
-      riga::launch_cgs_update(N, nc, b, h2, h->Vu, h->Ru, h->Vl, h->Rl, h->Wl, h->MRl, N, N, h->st);
+      // the second pass also leaves the partial B-Gram sums of the updated block
+      gblk = riga::launch_cgs_update(N, nc, b, h2, h->Vu, h->Ru, h->Vl, h->Rl, h->Wl, h->MRl, N, N, h->d_part,
+                                     h->st);
+    } else {
+      riga::launch_dots(N, b, h->Ru, h->MRl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, dG, h->st);
     }
-    riga::launch_dots(N, b, h->Ru, h->MRl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, dG, h->st);
-    riga::launch_block_normalize(nc, b, nc > 0 ? h1 : nullptr, nc > 0 ? h2 : nullptr, dG, dest, ldh, col, dRinv,
-                                 h->d_flag, h->st);
+    riga::launch_block_normalize(nc, b, nc > 0 ? h1 : nullptr, nc > 0 ? h2 : nullptr, dG, nc > 0 ? h->d_part : nullptr,
+                                 gblk, dest, ldh, col, dRinv, h->d_flag, h->st);
     const size_t o = (size_t)nc * N;
     riga::launch_gemm3(N, b, dRinv, h->Ru, h->Vu + o, h->Rl, h->Vl + o, h->MRl, h->Wl + o, N, h->st);
   }

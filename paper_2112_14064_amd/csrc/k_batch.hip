@@ -130,7 +130,8 @@ __global__ __launch_bounds__(BT) void k_cgs_update_b(const int4* __restrict__ rb
   __syncthreads();
   const int64_t i = b.y + threadIdx.x;
   if (i >= b.z) return;
-  cgs_update_row<NQ>(i, nc, hs, A0, Z0, A1, Z1, A2, Z2, ld, ld);
+  double z0[NQ], z1[NQ], z2[NQ];
+  cgs_update_row<NQ>(i, nc, hs, A0, Z0, A1, Z1, A2, Z2, ld, ld, z0, z1, z2);
 }
 
 void launch_cgs_update_b(const BatchDev& B, int nc_add, int nq, const double* h, int hstride, const double* A0,

@@ -343,24 +343,45 @@ __global__ __launch_bounds__(UPD_THREADS) void k_cgs_update(
     int64_t n, int nc, const double* __restrict__ h,
     const double* __restrict__ A0, double* __restrict__ Z0, const double* __restrict__ A1,
     double* __restrict__ Z1, const double* __restrict__ A2, double* __restrict__ Z2,
-    int64_t lda, int64_t ldz) {
+    int64_t lda, int64_t ldz, double* __restrict__ gpart) {
   extern __shared__ double hs[];
   for (int k = threadIdx.x; k < nc * NQ; k += UPD_THREADS) hs[k] = h[k];
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * UPD_THREADS + threadIdx.x;
-  if (i >= n) return;
-  cgs_update_row<NQ>(i, nc, hs, A0, Z0, A1, Z1, A2, Z2, lda, ldz);
+  double z0[NQ], z1[NQ], z2[NQ];
+  if (i < n) cgs_update_row<NQ>(i, nc, hs, A0, Z0, A1, Z1, A2, Z2, lda, ldz, z0, z1, z2);
+  if (gpart == nullptr) return;
+  // B-Gram of the updated block, Z0^T Z0 + Z2^T Z1 (Z2 = M Z1), summed over
+  // the block's rows: lanes, then waves in order
+  __shared__ double gw[UPD_THREADS / 64][NQ * NQ];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NQ; ++c)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double g = (i < n) ? z0[c] * z0[q] + z2[c] * z1[q] : 0.0;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) g += __shfl_xor(g, off, 64);
+      if (lane == 0) gw[wave][c * NQ + q] = g;
+    }
+  __syncthreads();
+  if (threadIdx.x < NQ * NQ) {
+    double g = 0.0;
+#pragma unroll
+    for (int w = 0; w < UPD_THREADS / 64; ++w) g += gw[w][threadIdx.x];
+    gpart[(int64_t)blockIdx.x * NQ * NQ + threadIdx.x] = g;
+  }
 }
 
-void launch_cgs_update(int64_t n, int nc, int nq, const double* h,
-                       const double* A0, double* Z0, const double* A1, double* Z1,
-                       const double* A2, double* Z2, int64_t lda, int64_t ldz, hipStream_t st) {
-  if (nc <= 0) return;
+int launch_cgs_update(int64_t n, int nc, int nq, const double* h,
+                      const double* A0, double* Z0, const double* A1, double* Z1,
+                      const double* A2, double* Z2, int64_t lda, int64_t ldz, double* gpart, hipStream_t st) {
+  if (nc <= 0) return 0;
   int64_t blocks = (n + UPD_THREADS - 1) / UPD_THREADS;
 #define RIGA_UPD(NQ)                                                                              \
   hipLaunchKernelGGL(k_cgs_update<NQ>, dim3((unsigned)blocks), dim3(UPD_THREADS),                 \
                      (size_t)nc * NQ * sizeof(double), st, n, nc, h,                               \
-                     A0, Z0, A1, Z1, A2, Z2, lda, ldz)
+                     A0, Z0, A1, Z1, A2, Z2, lda, ldz, gpart)
   switch (nq) {
     case 1: RIGA_UPD(1); break;
     case 2: RIGA_UPD(2); break;
@@ -368,6 +389,7 @@ void launch_cgs_update(int64_t n, int nc, int nq, const double* h,
     default: RIGA_UPD(4); break;
   }
 #undef RIGA_UPD
+  return (int)blocks;
 }
 
 // ---------------------------------------------------------------------------
@@ -614,16 +636,32 @@ void launch_combine3(int64_t nnz, double am, const double* M, double ac, const d
 // whose squared B-norm after projection falls below 1e-24 of its norm before
 // projection (an invariant subspace was reached) sets *flag = 1; the caller
 // then redoes the solve on the host-checked path.
+// With gpart, G is first summed from gblk per-block partials (nq x nq each,
+// block order).
 __global__ void k_block_normalize(int nc, int nq, const double* __restrict__ h1, const double* __restrict__ h2,
-                                  const double* __restrict__ G, double* __restrict__ H, int ldh, int k,
-                                  double* __restrict__ Rinv, int* __restrict__ flag) {
+                                  const double* __restrict__ G, const double* __restrict__ gpart, int gblk,
+                                  double* __restrict__ H, int ldh, int k, double* __restrict__ Rinv,
+                                  int* __restrict__ flag) {
   __shared__ double hn[4];
+  __shared__ double gs[16];
+  if (gpart != nullptr) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int idx = wv; idx < nq * nq; idx += blockDim.x / 64) {
+      double s = 0.0;
+      for (int b = lane; b < gblk; b += 64) s += gpart[(int64_t)b * nq * nq + idx];
+      for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+      if (lane == 0) gs[idx] = s;
+    }
+    __syncthreads();
+    G = gs;
+  }
   block_normalize_body(nc, nq, h1, h2, G, H, ldh, k, Rinv, flag, hn);
 }
 
-void launch_block_normalize(int nc, int nq, const double* h1, const double* h2, const double* G, double* H,
-                            int ldh, int k, double* Rinv, int* flag, hipStream_t st) {
-  hipLaunchKernelGGL(k_block_normalize, dim3(1), dim3(256), 0, st, nc, nq, h1, h2, G, H, ldh, k, Rinv, flag);
+void launch_block_normalize(int nc, int nq, const double* h1, const double* h2, const double* G, const double* gpart,
+                            int gblk, double* H, int ldh, int k, double* Rinv, int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_block_normalize, dim3(1), dim3(256), 0, st, nc, nq, h1, h2, G, gpart, gblk, H, ldh, k, Rinv,
+                     flag);
 }
 
 // Out_m[:, 0:nq] = In_m[:, 0:nq] Q for three (In, Out) pairs; Q nq x nq on the device.

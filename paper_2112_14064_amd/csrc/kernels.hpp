@@ -155,9 +155,12 @@ void launch_dots(int64_t n, int nc, const double* Au, const double* Al, int64_t 
                  double* partial, unsigned* ticket, double* out, hipStream_t st);
 int dots_blocks(int64_t n);
 // Z[:, q] -= sum_c A[:, c] h[c*nq+q] for up to three (A, Z) pairs sharing h.
-void launch_cgs_update(int64_t n, int nc, int nq, const double* h,
-                       const double* A0, double* Z0, const double* A1, double* Z1,
-                       const double* A2, double* Z2, int64_t lda, int64_t ldz, hipStream_t st);
+// With gpart (nq <= 4), every block also writes the sum over its rows of the
+// updated Z0^T Z0 + Z2^T Z1 (nq x nq) to gpart[block * nq * nq ...]; returns
+// the number of blocks.
+int launch_cgs_update(int64_t n, int nc, int nq, const double* h,
+                      const double* A0, double* Z0, const double* A1, double* Z1,
+                      const double* A2, double* Z2, int64_t lda, int64_t ldz, double* gpart, hipStream_t st);
 // Out[i + c ldo] = sum_t In[i + t ldi] Q[t, c] (Q device, kin x kout col-major,
 // kin <= 254), on the FP64 matrix cores.
 void launch_gemm_tall(int64_t n, const double* In, int64_t ldi, int kin, const double* Q, int kout,
@@ -180,10 +183,11 @@ void launch_rowabs3(const int4* rb, int nblocks, int64_t ndof, int rows_per_bloc
                     const double* A0, const double* A1, const double* A2, double* part, hipStream_t st);
 
 // Device-side block normalisation (see k_krylov.hip): H columns k..k+nq from the
-// projection coefficients h1 + h2 and the Cholesky factor of the Gram matrix G;
+// projection coefficients h1 + h2 and the Cholesky factor of the Gram matrix G
+// (or, with gpart, of the sum of gblk partial Gram matrices);
 // Rinv = R^{-1}; *flag = 1 when a column was lost (breakdown).
-void launch_block_normalize(int nc, int nq, const double* h1, const double* h2, const double* G, double* H,
-                            int ldh, int k, double* Rinv, int* flag, hipStream_t st);
+void launch_block_normalize(int nc, int nq, const double* h1, const double* h2, const double* G, const double* gpart,
+                            int gblk, double* H, int ldh, int k, double* Rinv, int* flag, hipStream_t st);
 // Out_m = In_m Q (n x nq times nq x nq) for three pairs sharing Q and ld.
 void launch_gemm3(int64_t n, int nq, const double* Q, const double* I0, double* O0, const double* I1, double* O1,
                   const double* I2, double* O2, int64_t ld, hipStream_t st);

@@ -109,16 +109,17 @@ __device__ __forceinline__ void dots_body(int64_t i0, int64_t i1, int nc, const 
 
 // Gram--Schmidt update of row i: Zm[i, q] -= sum_c Am[i, c] hs[c * NQ + q]
 // for m = 0, 1, 2 (A1/Z1 and A2/Z2 may be null), columns in increasing order,
-// UPD_U columns per round with all their loads in flight together.
+// UPD_U columns per round with all their loads in flight together; the
+// updated rows are also left in z0, z1, z2.
 constexpr int UPD_U = 8;
 
 template <int NQ>
 __device__ __forceinline__ void cgs_update_row(int64_t i, int nc, const double* hs, const double* __restrict__ A0,
                                                double* __restrict__ Z0, const double* __restrict__ A1,
                                                double* __restrict__ Z1, const double* __restrict__ A2,
-                                               double* __restrict__ Z2, int64_t lda, int64_t ldz) {
+                                               double* __restrict__ Z2, int64_t lda, int64_t ldz,
+                                               double (&z0)[NQ], double (&z1)[NQ], double (&z2)[NQ]) {
   const bool has1 = A1 != nullptr, has2 = A2 != nullptr;
-  double z0[NQ], z1[NQ], z2[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     z0[q] = Z0[i + q * ldz];
