@@ -512,7 +512,7 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
       }
       if (!fin.empty()) {
         std::fill(hkout.begin(), hkout.end(), 0);
-        int max_kin = 1;
+        int max_kin = 1, max_kout = 1;
         for (int i : fin) {
           const int k = kend[i], nw = cyc[i].nw;
           double* q = Qh.data() + (size_t)i * 2 * hl;
@@ -524,19 +524,20 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
             }
           hkin[i] = k; hkout[i] = 2 * nw; hqoff[i] = (int64_t)i * 2 * hl;
           max_kin = std::max(max_kin, k);
+          max_kout = std::max(max_kout, 2 * nw);
         }
         ck(hipMemcpyAsync(bh->Qd, Qh.data(), sizeof(double) * n * 2 * hl, hipMemcpyHostToDevice, st));
         ck(hipMemcpyAsync(bh->kin, hkin.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
         ck(hipMemcpyAsync(bh->kout, hkout.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
         ck(hipMemcpyAsync(bh->qoff, hqoff.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
-        riga::launch_gemm_tall_b(B, bh->kin, bh->kout, bh->qoff, bh->Qd, max_kin, bh->Vu, bh->P, st);
+        riga::launch_gemm_tall_b(B, bh->kin, bh->kout, bh->qoff, bh->Qd, max_kin, max_kout, bh->Vu, bh->P, st);
         ck(hipStreamSynchronize(st));   // Qh and the small arrays are staged again below
       }
       state = newstate;
       if (rst.empty()) break;
       // restart: V_new = [V_k Qk, V_{k:k+b}] per problem, new H, k = r
       std::fill(hkout.begin(), hkout.end(), 0);
-      int max_kin = 1;
+      int max_kin = 1, max_kout = 1;
       std::fill(Hh.begin(), Hh.end(), 0.0);
       for (int i : rst) {
         const riga::KsCycle& c = cyc[i];
@@ -544,6 +545,7 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
         std::memcpy(Qh.data() + (size_t)i * 2 * hl, c.Qe.data(), c.Qe.size() * sizeof(double));
         hkin[i] = kin; hkout[i] = kout; hqoff[i] = (int64_t)i * 2 * hl;
         max_kin = std::max(max_kin, kin);
+        max_kout = std::max(max_kout, kout);
         std::memcpy(Hh.data() + (size_t)i * hl, c.Hn.data(), hl * sizeof(double));
         kc[i] = c.r;
       }
@@ -552,9 +554,9 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
       ck(hipMemcpyAsync(bh->kin, hkin.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
       ck(hipMemcpyAsync(bh->kout, hkout.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
       ck(hipMemcpyAsync(bh->qoff, hqoff.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
-      riga::launch_gemm_tall_b(B, bh->kin, bh->kout, bh->qoff, bh->Qd, max_kin, bh->Vu, bh->Vu2, st);
-      riga::launch_gemm_tall_b(B, bh->kin, bh->kout, bh->qoff, bh->Qd, max_kin, bh->Vl, bh->Vl2, st);
-      riga::launch_gemm_tall_b(B, bh->kin, bh->kout, bh->qoff, bh->Qd, max_kin, bh->Wl, bh->Wl2, st);
+      riga::launch_gemm_tall_b(B, bh->kin, bh->kout, bh->qoff, bh->Qd, max_kin, max_kout, bh->Vu, bh->Vu2, st);
+      riga::launch_gemm_tall_b(B, bh->kin, bh->kout, bh->qoff, bh->Qd, max_kin, max_kout, bh->Vl, bh->Vl2, st);
+      riga::launch_gemm_tall_b(B, bh->kin, bh->kout, bh->qoff, bh->Qd, max_kin, max_kout, bh->Wl, bh->Wl2, st);
       std::swap(bh->Vu, bh->Vu2); std::swap(bh->Vl, bh->Vl2); std::swap(bh->Wl, bh->Wl2);
       ck(hipMemcpyAsync(bh->H, Hh.data(), sizeof(double) * n * hl, hipMemcpyHostToDevice, st));
       ck(hipMemcpyAsync(B.kcur, kc.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));

@@ -243,26 +243,51 @@ void launch_advance_b(const BatchDev& B, int b, int m, hipStream_t st) {
 // Out[:, 0:kout_p] = In[:, 0:kin_p] Q_p per problem (Q_p at Q + qoff[p], kin_p x
 // kout_p column-major); problems with kout_p = 0 are skipped.  A row block of up
 // to 256 rows is done as 64-row tiles.
-__global__ __launch_bounds__(512) void k_gemm_tall_b(const int4* __restrict__ rb,
-                                                              const int* __restrict__ kin,
-                                                              const int* __restrict__ kout,
-                                                              const int64_t* __restrict__ qoff,
-                                                              const double* __restrict__ Q,
-                                                              const double* __restrict__ In, double* __restrict__ Out,
-                                                              int64_t ld) {
+// Outputs of at most 32 columns from at most 128 inputs in every problem (the
+// usual short bases of the batched form) take the LDS tile, otherwise the
+// matrix cores; separate kernels, so each keeps its own register budget.
+constexpr int GEMM_NARROW_OUT = 32, GEMM_NARROW_IN = 128;
+
+__global__ __launch_bounds__(256) void k_gemm_tall_b_tile(const int4* __restrict__ rb,
+                                                          const int* __restrict__ kin,
+                                                          const int* __restrict__ kout,
+                                                          const int64_t* __restrict__ qoff,
+                                                          const double* __restrict__ Q,
+                                                          const double* __restrict__ In, double* __restrict__ Out,
+                                                          int64_t ld) {
   extern __shared__ double qs[];
   const int4 b = rb[blockIdx.x];
   const int ko = kout[b.x];
   if (ko <= 0) return;
-  // a row block holds at most 256 rows: two 16-row slabs for each of 8 waves
-  gemm_rows_mfma<8, 2>(b.y, b.z, In, ld, kin[b.x], Q + qoff[b.x], ko, Out, ld, qs);
+  for (int r0 = b.y; r0 < b.z; r0 += 64)
+    gemm_tile64(r0, min(64, b.z - r0), In, ld, kin[b.x], Q + qoff[b.x], ko, Out, ld, qs);
+}
+
+__global__ __launch_bounds__(256) void k_gemm_tall_b(const int4* __restrict__ rb,
+                                                     const int* __restrict__ kin,
+                                                     const int* __restrict__ kout,
+                                                     const int64_t* __restrict__ qoff,
+                                                     const double* __restrict__ Q,
+                                                     const double* __restrict__ In, double* __restrict__ Out,
+                                                     int64_t ld) {
+  extern __shared__ double qs[];
+  const int4 b = rb[blockIdx.x];
+  const int ko = kout[b.x];
+  if (ko <= 0) return;
+  // a row block holds at most 256 rows: four 16-row slabs for each of 4 waves
+  gemm_rows_mfma<4, 4>(b.y, b.z, In, ld, kin[b.x], Q + qoff[b.x], ko, Out, ld, qs);
 }
 
 void launch_gemm_tall_b(const BatchDev& B, const int* kin, const int* kout, const int64_t* qoff, const double* Q,
-                        int max_kin, const double* In, double* Out, hipStream_t st) {
-  const size_t shm = (size_t)gemm_lds_doubles(max_kin) * sizeof(double);
-  hipLaunchKernelGGL(k_gemm_tall_b, dim3(B.nrb), dim3(512), shm, st, B.rb, kin, kout, qoff, Q, In, Out,
-                     B.ntot);
+                        int max_kin, int max_kout, const double* In, double* Out, hipStream_t st) {
+  if (max_kout <= GEMM_NARROW_OUT && max_kin <= GEMM_NARROW_IN) {
+    const size_t shm = (size_t)max_kin * 80 * sizeof(double);
+    hipLaunchKernelGGL(k_gemm_tall_b_tile, dim3(B.nrb), dim3(256), shm, st, B.rb, kin, kout, qoff, Q, In, Out,
+                       B.ntot);
+  } else {
+    const size_t shm = (size_t)gemm_lds_doubles(max_kin) * sizeof(double);
+    hipLaunchKernelGGL(k_gemm_tall_b, dim3(B.nrb), dim3(256), shm, st, B.rb, kin, kout, qoff, Q, In, Out, B.ntot);
+  }
 }
 
 }  // namespace riga

@@ -239,6 +239,6 @@ void launch_gemm3_b(const BatchDev& B, bool use_k, int col_add, int nq, const do
                     double* O0, const double* I1, double* O1, const double* I2, double* O2, hipStream_t st);
 void launch_advance_b(const BatchDev& B, int b, int m, hipStream_t st);
 void launch_gemm_tall_b(const BatchDev& B, const int* kin, const int* kout, const int64_t* qoff, const double* Q,
-                        int max_kin, const double* In, double* Out, hipStream_t st);
+                        int max_kin, int max_kout, const double* In, double* Out, hipStream_t st);
 
 }  // namespace riga

@@ -211,7 +211,7 @@ __device__ inline void block_normalize_body(int nc, int nq, const double* h1, co
 }
 
 constexpr int GEMM_COLS = 64;     // columns of Q staged in LDS at a time
-constexpr int GEMM_KCH = 32;      // k-steps of In held in registers at a time
+constexpr int GEMM_KCH = 8;       // k-steps of In held in registers at a time
 
 // LDS doubles gemm_rows_mfma needs for a given kin.
 __host__ __device__ inline int gemm_lds_doubles(int kin) { return GEMM_COLS * ((kin + 3) / 4 * 4 + 1); }
@@ -229,17 +229,17 @@ __device__ inline void gemm_rows_mfma(int64_t r0, int64_t r1, const double* __re
                                       const double* __restrict__ Q, int kout, double* __restrict__ Out,
                                       int64_t ldo, double* qs) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int kr = mfma_ab_k(lane), cl = mfma_b_col(lane);   // A row = B column = lane & 15
+  const int kr = mfma_ab_k(lane), cl = mfma_a_row(lane);   // A row = B column = lane & 15
   const int ksteps = (kin + 3) / 4, kp = ksteps * 4 + 1;
   for (int c0 = 0; c0 < kout; c0 += GEMM_COLS) {
     const int nc = min(GEMM_COLS, kout - c0);
+    const int nj = (nc + 15) / 16;
     __syncthreads();   // the previous columns of Q have been consumed
-    for (int idx = threadIdx.x; idx < GEMM_COLS * kp; idx += NWAVES * 64) {
+    for (int idx = threadIdx.x; idx < nj * 16 * kp; idx += NWAVES * 64) {
       const int c = idx / kp, t = idx - c * kp;
       qs[idx] = (c < nc && t < kin) ? Q[(int64_t)(c0 + c) * kin + t] : 0.0;
     }
     __syncthreads();
-    const int nj = (nc + 15) / 16;
     for (int sl = 0; sl < SLABS; ++sl) {
       const int64_t rb = r0 + (int64_t)(wave * SLABS + sl) * 16;
       if (rb >= r1) break;
@@ -261,21 +261,66 @@ __device__ inline void gemm_rows_mfma(int64_t r0, int64_t r1, const double* __re
           if (s0 + e >= ksteps) break;
           const double* qk = qs + (s0 + e) * 4 + kr;
 #pragma unroll
+          // the transposed product Out^T = Q^T In^T: Q's columns are the rows
+          // of the A operand, the slab's rows the columns of B, so a lane's
+          // accumulator holds one output row and 16 consecutive rows are
+          // stored together
           for (int j = 0; j < 4; ++j)
-            if (j < nj) acc[j] = Mfma<double>::mma(a[e], qk[(j * 16 + cl) * kp], acc[j]);
+            if (j < nj) acc[j] = Mfma<double>::mma(qk[(j * 16 + cl) * kp], a[e], acc[j]);
         }
       }
+      const int64_t row = rb + mfma_d_col(lane);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int c = j * 16 + mfma_d_col(lane);
-        if (j >= nj || c >= nc) continue;
+        if (j >= nj || row >= r1) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int64_t row = rb + Mfma<double>::drow(lane, v);
-          if (row < r1) Out[row + (int64_t)(c0 + c) * ldo] = acc[j][v];
+          const int c = j * 16 + Mfma<double>::drow(lane, v);
+          if (c < nc) Out[row + (int64_t)(c0 + c) * ldo] = acc[j][v];
         }
       }
     }
+  }
+}
+
+
+// Narrow outputs (the batched form's short bases): rows [r0, r0 + rows) of
+// Out = In * Q (rows <= 64, column-major Out with leading dimension ldo) with
+// the In tile staged in LDS ([t][row]: the lanes of a wave read consecutive
+// words) and 16 columns of Q at a time (read as broadcasts); lane = row, each
+// of the 4 waves takes four of those columns.  shm: kin * 80 doubles.  Called
+// by every thread of a 256-thread block.
+__device__ inline void gemm_tile64(int64_t r0, int rows, const double* __restrict__ In, int64_t ldi, int kin,
+                                   const double* __restrict__ Q, int kout, double* __restrict__ Out, int64_t ldo,
+                                   double* shm) {
+  double* tile = shm;                 // [t][row]
+  double* qs = shm + (size_t)kin * 64;  // [c][t], 16 columns
+  __syncthreads();   // the previous tile has been consumed
+  for (int idx = threadIdx.x; idx < 64 * kin; idx += 256) {
+    const int r = idx % 64, t = idx / 64;
+    tile[idx] = (r < rows) ? In[r0 + r + (int64_t)t * ldi] : 0.0;
+  }
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  for (int p0 = 0; p0 < kout; p0 += 16) {
+    const int np = min(16, kout - p0);
+    if (p0 > 0) __syncthreads();   // the previous columns of Q have been consumed
+    for (int idx = threadIdx.x; idx < 16 * kin; idx += 256) {
+      const int c = idx / kin, t = idx % kin;
+      qs[idx] = (c < np) ? Q[(int64_t)(p0 + c) * kin + t] : 0.0;
+    }
+    __syncthreads();
+    const int c0 = wave * 4;
+    if (c0 >= np) continue;
+    const double* q = qs + (size_t)c0 * kin;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < kin; ++t) {
+      const double a = tile[t * 64 + lane];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += a * q[u * kin + t];
+    }
+    if (lane < rows)
+      for (int u = 0; u < min(4, np - c0); ++u) Out[r0 + lane + (int64_t)(p0 + c0 + u) * ldo] = acc[u];
   }
 }
 
