@@ -275,6 +275,7 @@ void setup_device(riga_problem* h) {
     h->dt.voff = h->upload(sw.voff);
     h->dt.gptr = h->upload(sw.gptr);
     h->dt.gidx = h->upload(sw.gidx);
+    h->dt.gsrc = h->upload(sw.gsrc);
     h->d_level_nodes = h->upload(P.level_nodes);
     std::vector<double> gx, gw;
     gauss_legendre(S.p + 1, gx, gw);

@@ -115,12 +115,13 @@ __global__ __launch_bounds__(NW * 64) void k_fwd(DevTree t, const SweepTask* __r
   const V* col = reinterpret_cast<const V*>(Lp + tk.poff) + (live ? r : r0);
   const int gend = (jend + K - 1) / K;
   // front vector: own entries of b plus the children's update rows, added in
-  // child order (one pass, no barrier per child).  The indices of the first
-  // gather round are requested before the factor, so that waiting for them
-  // does not wait for the factor loads.
-  const int* gp = t.gptr + tk.foff;
-  const int pc = min(tid, nf - 1);
-  const int fd0 = fd[pc], gb0 = gp[pc], ge0 = gp[pc + 1];
+  // child order (one pass, no barrier per child).  A position's record
+  // {dof or -1, update rows, first update row, list start} gives the b entry
+  // and the first update row in one load; the record of the first gather
+  // round is requested before the factor, so that waiting for it does not
+  // wait for the factor loads.
+  const int4* gs = t.gsrc + tk.foff;
+  const int4 rec0 = gs[min(tid, nf - 1)];
   __builtin_amdgcn_sched_barrier(0);      // keep the issue order
   int g = __builtin_amdgcn_readfirstlane(wave) * SG;
   V A[SG], B[SG];
@@ -129,15 +130,19 @@ __global__ __launch_bounds__(NW * 64) void k_fwd(DevTree t, const SweepTask* __r
   const int dst = fd[min(r, nf - 1)];      // used by own rows only
 
   for (int p = tid; p < nf; p += NW * 64) {
-    const bool first = p == tid;
+    const int4 rc = (p == tid) ? rec0 : gs[p];
     double s[NR];
 #pragma unroll
-    for (int q = 0; q < NR; ++q) s[q] = (p < no) ? b[(first ? fd0 : fd[p]) + q * ldb] : 0.0;
-    const int k1 = first ? ge0 : gp[p + 1];
-    for (int k = first ? gb0 : gp[p]; k < k1; ++k) {
-      const double* uc = upd + (int64_t)t.gidx[k] * NR;
+    for (int q = 0; q < NR; ++q) s[q] = (rc.x >= 0) ? b[rc.x + q * ldb] : 0.0;
+    if (rc.y > 0) {
+      const double* uc = upd + (int64_t)rc.z * NR;
 #pragma unroll
       for (int q = 0; q < NR; ++q) s[q] += uc[q];
+      for (int k = 1; k < rc.y; ++k) {
+        const double* u2 = upd + (int64_t)t.gidx[rc.w + k] * NR;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) s[q] += u2[q];
+      }
     }
 #pragma unroll
     for (int q = 0; q < NR; ++q) f[p * NR + q] = s[q];
@@ -225,6 +230,14 @@ __global__ __launch_bounds__(NW * 64) void k_bwd(DevTree t, const SweepTask* __r
       w[p * NR + q] = val;
     }
   }
+  // the entries the epilogue adds are requested now: their latency passes
+  // during the product
+  double bpre[NR], vpre[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    bpre[q] = (wave == 0 && ru != nullptr && base != nullptr) ? base[d + q * ldbase] : 0.0;
+    vpre[q] = (wave == 0 && rl != nullptr) ? v_u[d + q * ldv] : 0.0;
+  }
   __syncthreads();
   double acc[NR];
 #pragma unroll
@@ -245,10 +258,10 @@ __global__ __launch_bounds__(NW * 64) void k_bwd(DevTree t, const SweepTask* __r
       double val = neg ? -acc[q] : acc[q];
       xs[d + q * ldxs] = val;
       if (ru != nullptr) {
-        val = scale * (acc[q] + (base != nullptr ? base[d + q * ldbase] : 0.0));
+        val = scale * (acc[q] + bpre[q]);
         ru[d + q * ldr] = val;
       }
-      if (rl != nullptr) rl[d + q * ldr] = sig * val + v_u[d + q * ldv];
+      if (rl != nullptr) rl[d + q * ldr] = sig * val + vpre[q];
     }
   }
 }

@@ -28,6 +28,9 @@ struct DevTree {
   // array, children in clist order), so a front is assembled without a pass
   // per child.
   const int* gptr; const int* gidx;
+  // per front position foff[v] + p: {its dof for p < no, else -1; number of
+  // update rows; the first of them; its index in gidx}
+  const int4* gsrc;
   const int64_t* doff;          // per node: first 64x64 block of its diagonal inverses
   const unsigned char* prec;    // per node: 1 = FP32 front (mixed factor), or null (all FP64)
   const int64_t* lpoff;         // per node: sweep layouts of F (multiples of 4 elements):
