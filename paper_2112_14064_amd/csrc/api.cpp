@@ -1028,7 +1028,16 @@ struct KrylovRun {
     double* dG = h->d_small + (size_t)2 * ldh * b;
     double* dRinv = h->d_small + (size_t)2 * ldh * b + 16;
     int gblk = 0;
-    if (nc > 0) {
+    if (riga::cgs_tile_fits(nc, b)) {
+      // pass 1 products; pass 1 update together with the pass 2 products (one
+      // read of the basis); pass 2 update with the partial B-Gram sums of the
+      // new block
+      riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, h1, h->st);
+      riga::launch_cgs_update_dots(N, nc, b, h1, h->Vu, h->Vl, h->Wl, N, h->Ru, h->Rl, h->MRl, N, h->d_part, h2,
+                                   h->st);
+      gblk = riga::launch_cgs_update(N, nc, b, h2, h->Vu, h->Ru, h->Vl, h->Rl, h->Wl, h->MRl, N, N, h->d_part,
+                                     h->st);
+    } else if (nc > 0) {
       riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, h1, h->st);
       riga::launch_cgs_update(N, nc, b, h1, h->Vu, h->Ru, h->Vl, h->Rl, h->Wl, h->MRl, N, N, nullptr, h->st);
       riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, h2, h->st);

@@ -138,10 +138,17 @@ void enqueue_step(riga_batch* bh, int b, int m, int ldh, hipStream_t st) {
   sweep(fp, b, bh->Tv, T, o);
   riga::launch_spmv_ell(fp->d_slabs, fp->nslab, B.spaces, B.dofbase, B.live, b, fp->d_Mell, bh->Rl, T, bh->MRl, T,
                         nullptr, 0, 0.0, st);
-  // classical Gram--Schmidt twice against V[:, 0:k+b], B-inner products
-  riga::launch_dots_b(B, b, 0, true, bh->Vu, bh->Wl, b, bh->Ru, bh->Rl, bh->h1, hs, st);
-  riga::launch_cgs_update_b(B, b, b, bh->h1, hs, bh->Vu, bh->Ru, bh->Vl, bh->Rl, bh->Wl, bh->MRl, m + b, st);
-  riga::launch_dots_b(B, b, 0, true, bh->Vu, bh->Wl, b, bh->Ru, bh->Rl, bh->h2, hs, st);
+  // classical Gram--Schmidt twice against V[:, 0:k+b], B-inner products; where
+  // the tile kernels fit, the pass 1 update also forms the pass 2 products
+  if (riga::cgs_tile_fits(m + b, b)) {
+    riga::launch_cgs_dots_tile_b(B, b, b, m + b, bh->Vu, bh->Wl, bh->Ru, bh->Rl, bh->h1, hs, st);
+    riga::launch_cgs_update_dots_b(B, b, b, m + b, bh->h1, hs, bh->Vu, bh->Vl, bh->Wl, bh->Ru, bh->Rl, bh->MRl,
+                                   bh->h2, hs, st);
+  } else {
+    riga::launch_dots_b(B, b, 0, true, bh->Vu, bh->Wl, b, bh->Ru, bh->Rl, bh->h1, hs, st);
+    riga::launch_cgs_update_b(B, b, b, bh->h1, hs, bh->Vu, bh->Ru, bh->Vl, bh->Rl, bh->Wl, bh->MRl, m + b, st);
+    riga::launch_dots_b(B, b, 0, true, bh->Vu, bh->Wl, b, bh->Ru, bh->Rl, bh->h2, hs, st);
+  }
   riga::launch_cgs_update_b(B, b, b, bh->h2, hs, bh->Vu, bh->Ru, bh->Vl, bh->Rl, bh->Wl, bh->MRl, m + b, st);
   riga::launch_dots_b(B, 0, b, false, bh->Ru, bh->MRl, b, bh->Ru, bh->Rl, bh->G, b * b, st);
   riga::launch_block_normalize_b(B, true, b, b, bh->h1, bh->h2, hs, bh->G, bh->H, ldh, bh->Rinv, st);

@@ -150,6 +150,145 @@ void launch_cgs_update_b(const BatchDev& B, int nc_add, int nq, const double* h,
 #undef RIGA_UPDB
 }
 
+// Tile passes (bodies in krylov_dev.hpp) per dot block: the block's rows are
+// taken in 64-row tiles with nc = kcur + nc_add columns;
+// partial[blk * pstride + c * NQ + q] receives the block's products for
+// k_dots_final_b.  Products alone: blockIdx.y picks the group of
+// CGS_DOT_W * CPW columns.
+template <int NQ, int CPW>
+__global__ __launch_bounds__(CGS_DOT_W * 64) void k_cgs_dots_b(const int4* __restrict__ db,
+                                                               const int* __restrict__ kcur, int nc_add,
+                                                               const unsigned char* __restrict__ live,
+                                                               const double* __restrict__ Vu,
+                                                               const double* __restrict__ Wl,
+                                                               const double* __restrict__ Xu,
+                                                               const double* __restrict__ Xl, int64_t ld,
+                                                               double* __restrict__ partial, int pstride) {
+  const int4 b = db[blockIdx.x];
+  if (live && !live[b.x]) return;
+  const int nc = kcur[b.x] + nc_add;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c0 = ((int)blockIdx.y * CGS_DOT_W + wave) * CPW;
+  if (c0 >= nc) return;
+  double acc[CPW][NQ];
+#pragma unroll
+  for (int j = 0; j < CPW; ++j)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[j][q] = 0.0;
+  for (int64_t r0 = b.y; r0 < b.z; r0 += 64)
+    cgs_tile_dots<NQ, CPW>(r0, min((int64_t)b.z, r0 + 64), nc, c0, Vu, Wl, ld, Xu, Xl, ld, lane, acc);
+  double* out = partial + (int64_t)blockIdx.x * pstride;
+#pragma unroll
+  for (int j = 0; j < CPW; ++j)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const double v = wave_sum(acc[j][q]);
+      if (lane == 0 && c0 + j < nc) out[(c0 + j) * NQ + q] = v;
+    }
+}
+
+// Update fused with the products: NW waves own NW * CPW columns.
+template <int NQ, int NW, int CPW>
+__global__ __launch_bounds__(NW * 64) void k_cgs_upd_dots_b(const int4* __restrict__ db,
+                                                            const int* __restrict__ kcur, int nc_add,
+                                                            const unsigned char* __restrict__ live,
+                                                            const double* __restrict__ h, int hstride,
+                                                            const double* __restrict__ Vu,
+                                                            const double* __restrict__ Vl,
+                                                            const double* __restrict__ Wl, double* __restrict__ Zu,
+                                                            double* __restrict__ Zl, double* __restrict__ Zw,
+                                                            int64_t ld, double* __restrict__ partial, int pstride) {
+  __shared__ double hs[NW * CPW * NQ];
+  __shared__ double red[NW * 3 * NQ * 64];
+  __shared__ double fin[3 * NQ * 64];
+  const int4 b = db[blockIdx.x];
+  if (live && !live[b.x]) return;   // the whole workgroup leaves together
+  const int nc = kcur[b.x] + nc_add;
+  const double* hp = h + (int64_t)b.x * hstride;
+  for (int k = threadIdx.x; k < NW * CPW * NQ; k += NW * 64) hs[k] = k < nc * NQ ? hp[k] : 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double acc[CPW][NQ];
+#pragma unroll
+  for (int j = 0; j < CPW; ++j)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[j][q] = 0.0;
+  for (int64_t r0 = b.y; r0 < b.z; r0 += 64)
+    cgs_tile_update<NQ, NW, CPW>(r0, min((int64_t)b.z, r0 + 64), nc, hs, Vu, Vl, Wl, ld, Zu, Zl, Zw, ld, red, fin,
+                                 lane, wave, acc);
+  double* out = partial + (int64_t)blockIdx.x * pstride;
+  const int c0 = wave * CPW;
+#pragma unroll
+  for (int j = 0; j < CPW; ++j)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const double v = wave_sum(acc[j][q]);
+      if (lane == 0 && c0 + j < nc) out[(c0 + j) * NQ + q] = v;
+    }
+}
+
+template <int NQ>
+void launch_cgs_dots_b(const BatchDev& B, bool narrow, int gy, int nc_add, const double* Vu, const double* Wl,
+                       const double* Xu, const double* Xl, hipStream_t st) {
+  if (narrow)
+    hipLaunchKernelGGL((k_cgs_dots_b<NQ, CGS_NARROW_C>), dim3(B.ndb, gy), dim3(CGS_DOT_W * 64), 0, st, B.db, B.kcur,
+                       nc_add, B.live, Vu, Wl, Xu, Xl, B.ntot, B.partial, B.pstride);
+  else
+    hipLaunchKernelGGL((k_cgs_dots_b<NQ, CGS_WIDE_C>), dim3(B.ndb, gy), dim3(CGS_DOT_W * 64), 0, st, B.db, B.kcur,
+                       nc_add, B.live, Vu, Wl, Xu, Xl, B.ntot, B.partial, B.pstride);
+}
+
+bool launch_cgs_dots_tile_b(const BatchDev& B, int nc_add, int nq, int max_nc, const double* Vu, const double* Wl,
+                            const double* Xu, const double* Xl, double* out, int ostride, hipStream_t st) {
+  if (!cgs_tile_fits(max_nc, nq)) return false;
+  const bool narrow = max_nc <= CGS_NARROW_W * CGS_NARROW_C;
+  const int cpw = narrow ? CGS_NARROW_C : CGS_WIDE_C;
+  const int gy = (max_nc + CGS_DOT_W * cpw - 1) / (CGS_DOT_W * cpw);
+  switch (nq) {
+    case 1: launch_cgs_dots_b<1>(B, narrow, gy, nc_add, Vu, Wl, Xu, Xl, st); break;
+    case 2: launch_cgs_dots_b<2>(B, narrow, gy, nc_add, Vu, Wl, Xu, Xl, st); break;
+    case 3: launch_cgs_dots_b<3>(B, narrow, gy, nc_add, Vu, Wl, Xu, Xl, st); break;
+    default: launch_cgs_dots_b<4>(B, narrow, gy, nc_add, Vu, Wl, Xu, Xl, st); break;
+  }
+  hipLaunchKernelGGL(k_dots_final_b, dim3(B.n), dim3(BT), 0, st, B.dboff, B.kcur, nc_add, 0, B.live, nq, B.partial,
+                     B.pstride, out, ostride);
+  return true;
+}
+
+// The wide shape only for up to two block columns (register budget).
+template <int NQ>
+void launch_cgs_upd_dots_b(const BatchDev& B, bool narrow, int nc_add, const double* h, int hstride,
+                           const double* Vu, const double* Vl, const double* Wl, double* Zu, double* Zl, double* Zw,
+                           hipStream_t st) {
+  if constexpr (NQ <= 2) {
+    if (!narrow) {
+      hipLaunchKernelGGL((k_cgs_upd_dots_b<NQ, CGS_WIDE_W, CGS_WIDE_C>), dim3(B.ndb), dim3(CGS_WIDE_W * 64), 0, st,
+                         B.db, B.kcur, nc_add, B.live, h, hstride, Vu, Vl, Wl, Zu, Zl, Zw, B.ntot, B.partial,
+                         B.pstride);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_cgs_upd_dots_b<NQ, CGS_NARROW_W, CGS_NARROW_C>), dim3(B.ndb), dim3(CGS_NARROW_W * 64), 0,
+                     st, B.db, B.kcur, nc_add, B.live, h, hstride, Vu, Vl, Wl, Zu, Zl, Zw, B.ntot, B.partial,
+                     B.pstride);
+}
+
+bool launch_cgs_update_dots_b(const BatchDev& B, int nc_add, int nq, int max_nc, const double* h, int hstride,
+                              const double* Vu, const double* Vl, const double* Wl, double* Zu, double* Zl,
+                              double* Zw, double* out, int ostride, hipStream_t st) {
+  if (!cgs_tile_fits(max_nc, nq)) return false;
+  const bool narrow = max_nc <= CGS_NARROW_W * CGS_NARROW_C;
+  switch (nq) {
+    case 1: launch_cgs_upd_dots_b<1>(B, narrow, nc_add, h, hstride, Vu, Vl, Wl, Zu, Zl, Zw, st); break;
+    case 2: launch_cgs_upd_dots_b<2>(B, narrow, nc_add, h, hstride, Vu, Vl, Wl, Zu, Zl, Zw, st); break;
+    case 3: launch_cgs_upd_dots_b<3>(B, narrow, nc_add, h, hstride, Vu, Vl, Wl, Zu, Zl, Zw, st); break;
+    default: launch_cgs_upd_dots_b<4>(B, narrow, nc_add, h, hstride, Vu, Vl, Wl, Zu, Zl, Zw, st); break;
+  }
+  hipLaunchKernelGGL(k_dots_final_b, dim3(B.n), dim3(BT), 0, st, B.dboff, B.kcur, nc_add, 0, B.live, nq, B.partial,
+                     B.pstride, out, ostride);
+  return true;
+}
+
 // One workgroup per problem: block_normalize_body with the problem's arrays;
 // nc = kcur + nc_add and H column kcur (use_k), or nc = 0 and no H (start block).
 __global__ __launch_bounds__(BT) void k_block_normalize_b(const int* __restrict__ kcur, int nc_add,

@@ -393,6 +393,87 @@ int launch_cgs_update(int64_t n, int nc, int nq, const double* h,
 }
 
 // ---------------------------------------------------------------------------
+// Pass 1 update fused with the pass 2 products (cgs_tile_update in
+// krylov_dev.hpp): each workgroup takes every gridDim.x-th 64-row tile and
+// leaves one partial sum per output (c, q) in partial[(c nq + q) nblk + block]
+// for k_dots_final.
+template <int NQ, int NW, int CPW>
+__global__ __launch_bounds__(NW * 64) void k_cgs_upd_dots(int64_t n, int nc, const double* __restrict__ h,
+                                                          const double* __restrict__ Vu,
+                                                          const double* __restrict__ Vl,
+                                                          const double* __restrict__ Wl, int64_t lda,
+                                                          double* __restrict__ Zu, double* __restrict__ Zl,
+                                                          double* __restrict__ Zw, int64_t ldz,
+                                                          double* __restrict__ partial) {
+  __shared__ double hs[NW * CPW * NQ];
+  __shared__ double red[NW * 3 * NQ * 64];
+  __shared__ double fin[3 * NQ * 64];
+  for (int k = threadIdx.x; k < NW * CPW * NQ; k += NW * 64) hs[k] = k < nc * NQ ? h[k] : 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double acc[CPW][NQ];
+#pragma unroll
+  for (int j = 0; j < CPW; ++j)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[j][q] = 0.0;
+  const int64_t ntiles = (n + 63) / 64;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t r0 = t * 64;
+    cgs_tile_update<NQ, NW, CPW>(r0, min(n, r0 + 64), nc, hs, Vu, Vl, Wl, lda, Zu, Zl, Zw, ldz, red, fin, lane,
+                                 wave, acc);
+  }
+  const int nblk = gridDim.x, blk = blockIdx.x;
+  const int c0 = wave * CPW;
+#pragma unroll
+  for (int j = 0; j < CPW; ++j)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const double v = wave_sum(acc[j][q]);
+      if (lane == 0 && c0 + j < nc) partial[((int64_t)(c0 + j) * NQ + q) * nblk + blk] = v;
+    }
+}
+
+bool cgs_tile_fits(int nc, int nq) {
+  return nc > 0 && nq >= 1 && nq <= 4 &&
+         (nc <= CGS_NARROW_W * CGS_NARROW_C || (nq <= 2 && nc <= CGS_WIDE_W * CGS_WIDE_C));
+}
+
+// The wide shape only for up to two block columns (register budget).
+template <int NQ>
+void launch_cgs_upd_dots(bool narrow, int blocks, int64_t n, int nc, const double* h, const double* Vu,
+                         const double* Vl, const double* Wl, int64_t lda, double* Zu, double* Zl, double* Zw,
+                         int64_t ldz, double* partial, hipStream_t st) {
+  if constexpr (NQ <= 2) {
+    if (!narrow) {
+      hipLaunchKernelGGL((k_cgs_upd_dots<NQ, CGS_WIDE_W, CGS_WIDE_C>), dim3(blocks), dim3(CGS_WIDE_W * 64), 0, st,
+                         n, nc, h, Vu, Vl, Wl, lda, Zu, Zl, Zw, ldz, partial);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_cgs_upd_dots<NQ, CGS_NARROW_W, CGS_NARROW_C>), dim3(blocks), dim3(CGS_NARROW_W * 64), 0,
+                     st, n, nc, h, Vu, Vl, Wl, lda, Zu, Zl, Zw, ldz, partial);
+}
+
+int launch_cgs_update_dots(int64_t n, int nc, int nq, const double* h, const double* Vu, const double* Vl,
+                           const double* Wl, int64_t lda, double* Zu, double* Zl, double* Zw, int64_t ldz,
+                           double* partial, double* out, hipStream_t st) {
+  if (!cgs_tile_fits(nc, nq) || n <= 0) return -1;
+  const int64_t ntiles = (n + 63) / 64;
+  const int64_t per = (ntiles + CGS_MAX_BLOCKS - 1) / CGS_MAX_BLOCKS;
+  const int blocks = (int)((ntiles + per - 1) / per);
+  const bool narrow = nc <= CGS_NARROW_W * CGS_NARROW_C;
+  switch (nq) {
+    case 1: launch_cgs_upd_dots<1>(narrow, blocks, n, nc, h, Vu, Vl, Wl, lda, Zu, Zl, Zw, ldz, partial, st); break;
+    case 2: launch_cgs_upd_dots<2>(narrow, blocks, n, nc, h, Vu, Vl, Wl, lda, Zu, Zl, Zw, ldz, partial, st); break;
+    case 3: launch_cgs_upd_dots<3>(narrow, blocks, n, nc, h, Vu, Vl, Wl, lda, Zu, Zl, Zw, ldz, partial, st); break;
+    default: launch_cgs_upd_dots<4>(narrow, blocks, n, nc, h, Vu, Vl, Wl, lda, Zu, Zl, Zw, ldz, partial, st); break;
+  }
+  const int nout = nc * nq;
+  hipLaunchKernelGGL(k_dots_final, dim3((nout + 3) / 4), dim3(256), 0, st, nout, blocks, partial, out);
+  return blocks;
+}
+
+// ---------------------------------------------------------------------------
 // Out = In * Q for a tall In (n x kin) and a small Q (kin x kout), one 64-row
 // tile per workgroup (body in krylov_dev.hpp).
 constexpr int GEMM_WAVES = 8;   // 128 rows per block, one 16-row slab per wave

@@ -164,6 +164,22 @@ int dots_blocks(int64_t n);
 int launch_cgs_update(int64_t n, int nc, int nq, const double* h,
                       const double* A0, double* Z0, const double* A1, double* Z1,
                       const double* A2, double* Z2, int64_t lda, int64_t ldz, double* gpart, hipStream_t st);
+// Pass 1 update of classical Gram--Schmidt fused with the pass 2 products
+// (tile kernel, one read of the basis): for the basis (Vu, Vl, Wl; nc columns,
+// ld lda) and the block (Zu, Zl, Zw = M Zl; nq columns, ld ldz),
+//   Z -= V h for (Vu, Zu), (Vl, Zl), (Wl, Zw), h[c nq + q] on the device, then
+//   out[c nq + q] = Vu[:, c]^T Zu[:, q] + Wl[:, c]^T Zl[:, q] of the updated block.
+// Returns the number of workgroups, or -1 (nothing launched) when
+// cgs_tile_fits(nc, nq) is false.  partial: >= blocks * nc * nq doubles of scratch.
+constexpr int CGS_NARROW_W = 4, CGS_NARROW_C = 8;   // waves, columns per wave: nc <= 32
+constexpr int CGS_WIDE_W = 8, CGS_WIDE_C = 12;      // nc <= 96 (nq <= 2)
+constexpr int CGS_MAX_BLOCKS = 256;   // one workgroup per compute unit, all resident
+constexpr int CGS_DOT_W = 4;          // batched products alone: waves per workgroup
+// nc <= 96 with nq <= 2, or nc <= 32 with nq <= 4 (the register budget)
+bool cgs_tile_fits(int nc, int nq);
+int launch_cgs_update_dots(int64_t n, int nc, int nq, const double* h, const double* Vu, const double* Vl,
+                           const double* Wl, int64_t lda, double* Zu, double* Zl, double* Zw, int64_t ldz,
+                           double* partial, double* out, hipStream_t st);
 // Out[i + c ldo] = sum_t In[i + t ldi] Q[t, c] (Q device, kin x kout col-major,
 // kin <= 254), on the FP64 matrix cores.
 void launch_gemm_tall(int64_t n, const double* In, int64_t ldi, int kin, const double* Q, int kout,
@@ -235,6 +251,18 @@ void launch_dots_b(const BatchDev& B, int nc_add, int nc_fixed, bool use_k, cons
 void launch_cgs_update_b(const BatchDev& B, int nc_add, int nq, const double* h, int hstride, const double* A0,
                          double* Z0, const double* A1, double* Z1, const double* A2, double* Z2, int max_nc,
                          hipStream_t st);
+// Batched tile passes on every live problem's dot blocks with
+// nc = kcur + nc_add <= max_nc columns; out[p * ostride + c * nq + q]:
+//   launch_cgs_dots_tile_b      Vu[:, c]^T Xu[:, q] + Wl[:, c]^T Xl[:, q];
+//   launch_cgs_update_dots_b    the fused update and products of
+//                               launch_cgs_update_dots with the problem's h
+//                               (h + p * hstride).
+// Both return false (nothing launched) when cgs_tile_fits(max_nc, nq) is false.
+bool launch_cgs_dots_tile_b(const BatchDev& B, int nc_add, int nq, int max_nc, const double* Vu, const double* Wl,
+                            const double* Xu, const double* Xl, double* out, int ostride, hipStream_t st);
+bool launch_cgs_update_dots_b(const BatchDev& B, int nc_add, int nq, int max_nc, const double* h, int hstride,
+                              const double* Vu, const double* Vl, const double* Wl, double* Zu, double* Zl,
+                              double* Zw, double* out, int ostride, hipStream_t st);
 void launch_block_normalize_b(const BatchDev& B, bool use_k, int nc_add, int nq, const double* h1,
                               const double* h2, int hstride, const double* G, double* H, int ldh, double* Rinv,
                               hipStream_t st);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "kernels.hpp"
 #include "mfma_layout.hpp"
 
 namespace riga {
@@ -154,6 +155,129 @@ __device__ __forceinline__ void cgs_update_row(int64_t i, int nc, const double* 
     if (has1) Z1[i + q * ldz] = z1[q];
     if (has2) Z2[i + q * ldz] = z2[q];
   }
+}
+
+// Gram--Schmidt tiles over 64 rows (lane = row).  Wave w owns the basis
+// columns [c0, c0 + CPW) and keeps the tile's entries of Vu, Wl (and Vl) in
+// registers, so that one read of the basis serves both the update z -= V h
+// and the B-inner products of the updated z.
+//
+// Products alone (cgs_tile_dots): acc[j][q] += Vu[r, c] Xu[r, q] + Wl[r, c] Xl[r, q].
+template <int NQ, int CPW>
+__device__ __forceinline__ void cgs_tile_dots(int64_t r0, int64_t r1, int nc, int c0,
+                                              const double* __restrict__ Vu, const double* __restrict__ Wl,
+                                              int64_t lda, const double* __restrict__ Xu,
+                                              const double* __restrict__ Xl, int64_t ldx, int lane,
+                                              double (&acc)[CPW][NQ]) {
+  const int64_t r = r0 + lane;
+  const bool in = r < r1;
+  const int64_t rr = in ? r : r1 - 1;   // past-the-end lanes load a valid row, contribute zero
+  double au[CPW], aw[CPW], xu[NQ], xl[NQ];
+#pragma unroll
+  for (int j = 0; j < CPW; ++j) {
+    const int64_t o = rr + (int64_t)min(c0 + j, nc - 1) * lda;
+    au[j] = Vu[o];
+    aw[j] = Wl[o];
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    xu[q] = in ? Xu[rr + q * ldx] : 0.0;
+    xl[q] = in ? Xl[rr + q * ldx] : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < CPW; ++j)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[j][q] += au[j] * xu[q] + aw[j] * xl[q];
+}
+
+// Update with the products (cgs_tile_update): a workgroup of NW waves owns
+// NW CPW columns; z = Z - V h for (Vu, Zu), (Vl, Zl), (Wl, Zw) is stored, then
+// acc[j][q] += Vu[r, c] zu[q] + Wl[r, c] zl[q].  hs: h[c NQ + q] in shared
+// memory, zero from c = nc up to NW CPW.  red (NW 3 NQ 64 doubles) holds the
+// waves' partial products; wave t mod NW sums column t of the block (Z minus
+// the waves' parts in wave order, each part summed over its columns in
+// increasing order), stores it and leaves it in fin (3 NQ 64 doubles).  Every
+// wave of the workgroup calls this for every tile.
+template <int NQ, int NW, int CPW>
+__device__ __forceinline__ void cgs_tile_update(int64_t r0, int64_t r1, int nc, const double* hs,
+                                                const double* __restrict__ Vu, const double* __restrict__ Vl,
+                                                const double* __restrict__ Wl, int64_t lda, double* __restrict__ Zu,
+                                                double* __restrict__ Zl, double* __restrict__ Zw, int64_t ldz,
+                                                double* red, double* fin, int lane, int wave,
+                                                double (&acc)[CPW][NQ]) {
+  constexpr int NS = 3 * NQ;              // updated columns of the block: u, l, w parts
+  constexpr int OWN = (NS + NW - 1) / NW; // block columns summed by one wave
+  const int64_t r = r0 + lane;
+  const bool in = r < r1;
+  const int64_t rr = in ? r : r1 - 1;     // past-the-end lanes load a valid row, contribute zero
+  const int c0 = wave * CPW;
+  const bool has = c0 < nc;               // uniform over the wave
+  double au[CPW], aw[CPW], al[CPW];
+  if (has) {
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int64_t o = rr + (int64_t)min(c0 + j, nc - 1) * lda;
+      au[j] = Vu[o];
+      aw[j] = Wl[o];
+      al[j] = Vl[o];
+    }
+  }
+  // this wave's block columns, requested with the basis
+  double zo[OWN];
+#pragma unroll
+  for (int i = 0; i < OWN; ++i) {
+    const int t = wave + i * NW;
+    const double* Z = t < NQ ? Zu : (t < 2 * NQ ? Zl : Zw);
+    zo[i] = t < NS ? Z[rr + (t % NQ) * ldz] : 0.0;
+  }
+  double p[NS];
+#pragma unroll
+  for (int t = 0; t < NS; ++t) p[t] = 0.0;
+  if (has) {
+#pragma unroll
+    for (int j = 0; j < CPW; ++j)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const double hv = hs[(c0 + j) * NQ + q];
+        p[q] += au[j] * hv;
+        p[NQ + q] += al[j] * hv;
+        p[2 * NQ + q] += aw[j] * hv;
+      }
+  }
+#pragma unroll
+  for (int t = 0; t < NS; ++t) red[(wave * NS + t) * 64 + lane] = p[t];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < OWN; ++i) {
+    const int t = wave + i * NW;
+    if (t < NS) {
+      double v = zo[i];
+#pragma unroll
+      for (int w = 0; w < NW; ++w) v -= red[(w * NS + t) * 64 + lane];
+      double* Z = t < NQ ? Zu : (t < 2 * NQ ? Zl : Zw);
+      if (in) Z[rr + (t % NQ) * ldz] = v;
+      fin[t * 64 + lane] = in ? v : 0.0;
+    }
+  }
+  __syncthreads();
+  if (!has) return;
+  double zu[NQ], zl[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    zu[q] = fin[q * 64 + lane];
+    zl[q] = fin[(NQ + q) * 64 + lane];
+  }
+#pragma unroll
+  for (int j = 0; j < CPW; ++j)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[j][q] += au[j] * zu[q] + aw[j] * zl[q];
+}
+
+// Sum over the wave of every lane's v (lane 0 holds the result).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
 }
 
 // End of a block Gram--Schmidt step for one problem (see k_block_normalize):
