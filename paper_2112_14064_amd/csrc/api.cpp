@@ -1257,7 +1257,7 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
       while (kr.k + b <= m) kr.step(step_seed++);
       if (kr.fast) {
         const size_t hl = (size_t)ldh * ldh;
-        double* stage = h->pinned(2 * hl + 8);
+        double* stage = h->pinned(3 * hl + 8);   // the size the restart stages with
         ck(hipMemcpyAsync(stage, h->d_H, sizeof(double) * hl, hipMemcpyDeviceToHost, h->st));
         ck(hipMemcpyAsync(stage + 2 * hl, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, h->st));
         ck(hipStreamSynchronize(h->st));
@@ -1277,22 +1277,23 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
       // V_new = [V_k Qk, V_{k:k+b}] in the alternate buffers
       const int kin = k + b, kout = r + b;
       double* dQ = h->d_small;
-      {
-        double* stage = h->pinned(2 * (size_t)ldh * ldh + 8);
-        std::memcpy(stage, cyc.Qe.data(), cyc.Qe.size() * sizeof(double));
-        ck(hipMemcpyAsync(dQ, stage, cyc.Qe.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
-      }
+      // pinned staging: the combination in the first 2 ldh^2 doubles, the new
+      // projected matrix after it (both copies complete, in stream order,
+      // before the next cycle's download reuses the block)
+      const size_t hl2 = (size_t)ldh * ldh;
+      double* stage = h->pinned(3 * hl2 + 8);
+      std::memcpy(stage, cyc.Qe.data(), cyc.Qe.size() * sizeof(double));
+      ck(hipMemcpyAsync(dQ, stage, cyc.Qe.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
       riga::launch_gemm_tall(N, h->Vu, N, kin, dQ, kout, h->Vu2, N, h->st);
       riga::launch_gemm_tall(N, h->Vl, N, kin, dQ, kout, h->Vl2, N, h->st);
       riga::launch_gemm_tall(N, h->Wl, N, kin, dQ, kout, h->Wl2, N, h->st);
-      ck(hipStreamSynchronize(h->st));
       std::swap(h->Vu, h->Vu2); std::swap(h->Vl, h->Vl2); std::swap(h->Wl, h->Wl2);
       kr.H = cyc.Hn;
       if (kr.fast) {
-        // the pinned block is free again: the restart GEMMs were synchronised
-        double* stage = h->pinned(2 * (size_t)ldh * ldh + 8);
-        std::memcpy(stage, kr.H.data(), sizeof(double) * (size_t)ldh * ldh);
-        ck(hipMemcpyAsync(h->d_H, stage, sizeof(double) * (size_t)ldh * ldh, hipMemcpyHostToDevice, h->st));
+        std::memcpy(stage + 2 * hl2, kr.H.data(), sizeof(double) * hl2);
+        ck(hipMemcpyAsync(h->d_H, stage + 2 * hl2, sizeof(double) * hl2, hipMemcpyHostToDevice, h->st));
+      } else {
+        ck(hipStreamSynchronize(h->st));   // the host path stages its own copies next
       }
       kr.k = r;
     }

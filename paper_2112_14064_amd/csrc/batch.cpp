@@ -71,7 +71,7 @@ namespace {
 // Run f(i) for i in [0, n) on up to 8 host threads.
 template <class F>
 void parallel_for(int n, F f) {
-  const int nt = std::max(1, std::min<int>({8, n, (int)std::thread::hardware_concurrency()}));
+  const int nt = std::max(1, std::min<int>({16, n, (int)std::thread::hardware_concurrency()}));
   if (nt <= 1) {
     for (int i = 0; i < n; ++i) f(i);
     return;
@@ -456,11 +456,21 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
     std::vector<int> state(n, ACTIVE), it(n, 0), kend(n, 0);
     std::vector<riga::KsCycle> cyc(n);
     const size_t hl = (size_t)ldh * ldh;
-    std::vector<double> Hh((size_t)n * hl);
-    std::vector<int> flags(n);
-    std::vector<int> hkin(n), hkout(n);
-    std::vector<int64_t> hqoff(n);
-    std::vector<double> Qh((size_t)n * 2 * hl);   // per problem a slot of 2 ldh^2
+    // host staging in pinned memory (every copy a direct asynchronous one):
+    // down: projected matrices and breakdown flags; up: per problem a slot of
+    // 2 ldh^2 combination coefficients, the new projected matrices and the
+    // small per-problem arrays
+    const size_t nh = (size_t)n * hl, nq2 = (size_t)n * 2 * hl;
+    double* const pin = fp->pinned(nh + n + nq2 + nh + 4 * (size_t)n + 8);
+    double* const dnH = pin;
+    const int* const dnFlag = reinterpret_cast<const int*>(pin + nh);
+    double* const Qh = pin + nh + n;
+    double* const Hh = Qh + nq2;
+    int* const hkin = reinterpret_cast<int*>(Hh + nh);   // n ints in n / 2 doubles
+    int* const hkout = hkin + n;
+    int64_t* const hqoff = reinterpret_cast<int64_t*>(Hh + nh + n);
+    int* const hkc = reinterpret_cast<int*>(Hh + nh + 2 * (size_t)n);
+    unsigned char* const hlive = reinterpret_cast<unsigned char*>(Hh + nh + 3 * (size_t)n);
     int64_t n_fb = 0;
     int cycles = 0;
     for (;;) {
@@ -488,20 +498,17 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
       }
       ++cycles;
       // projected matrices and breakdown flags of every problem
-      double* stage = fp->pinned((size_t)n * hl + n + 8);
-      ck(hipMemcpyAsync(stage, bh->H, sizeof(double) * n * hl, hipMemcpyDeviceToHost, st));
-      ck(hipMemcpyAsync(stage + (size_t)n * hl, B.flag, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+      ck(hipMemcpyAsync(dnH, bh->H, sizeof(double) * nh, hipMemcpyDeviceToHost, st));
+      ck(hipMemcpyAsync((void*)dnFlag, B.flag, sizeof(int) * n, hipMemcpyDeviceToHost, st));
       ck(hipStreamSynchronize(st));
-      std::memcpy(Hh.data(), stage, sizeof(double) * n * hl);
-      std::memcpy(flags.data(), stage + (size_t)n * hl, sizeof(int) * n);
       std::vector<int> newstate(state);
       parallel_for(n, [&](int i) {
         if (state[i] != ACTIVE) return;
         const int steps_i = (m - kc[i]) / b;
         const int k = kc[i] + steps_i * b;
         kend[i] = k;
-        if (flags[i]) { newstate[i] = BROKE; return; }
-        std::vector<double> Hi(Hh.begin() + (size_t)i * hl, Hh.begin() + (size_t)(i + 1) * hl);
+        if (dnFlag[i]) { newstate[i] = BROKE; return; }
+        std::vector<double> Hi(dnH + (size_t)i * hl, dnH + (size_t)(i + 1) * hl);
         if (riga::ks_ritz(Hi, ldh, k, b, nev, tol, cyc[i]) != 0) { newstate[i] = BROKE; return; }
         ++it[i];
         if (cyc[i].nconv == cyc[i].nw) { newstate[i] = CONVERGED; return; }
@@ -518,11 +525,11 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
         else if (newstate[i] == ACTIVE) rst.push_back(i);
       }
       if (!fin.empty()) {
-        std::fill(hkout.begin(), hkout.end(), 0);
+        std::fill(hkout, hkout + n, 0);
         int max_kin = 1, max_kout = 1;
         for (int i : fin) {
           const int k = kend[i], nw = cyc[i].nw;
-          double* q = Qh.data() + (size_t)i * 2 * hl;
+          double* q = Qh + (size_t)i * 2 * hl;
           for (int j = 0; j < nw; ++j)
             for (int c = 0; c < k; ++c) {
               const cplx y = cyc[i].Y[c + (size_t)cyc[i].wanted[j] * k];
@@ -533,42 +540,44 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
           max_kin = std::max(max_kin, k);
           max_kout = std::max(max_kout, 2 * nw);
         }
-        ck(hipMemcpyAsync(bh->Qd, Qh.data(), sizeof(double) * n * 2 * hl, hipMemcpyHostToDevice, st));
-        ck(hipMemcpyAsync(bh->kin, hkin.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
-        ck(hipMemcpyAsync(bh->kout, hkout.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
-        ck(hipMemcpyAsync(bh->qoff, hqoff.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
+        ck(hipMemcpyAsync(bh->Qd, Qh, sizeof(double) * nq2, hipMemcpyHostToDevice, st));
+        ck(hipMemcpyAsync(bh->kin, hkin, sizeof(int) * n, hipMemcpyHostToDevice, st));
+        ck(hipMemcpyAsync(bh->kout, hkout, sizeof(int) * n, hipMemcpyHostToDevice, st));
+        ck(hipMemcpyAsync(bh->qoff, hqoff, sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
         riga::launch_gemm_tall_b(B, bh->kin, bh->kout, bh->qoff, bh->Qd, max_kin, max_kout, bh->Vu, bh->P, st);
         ck(hipStreamSynchronize(st));   // Qh and the small arrays are staged again below
       }
       state = newstate;
       if (rst.empty()) break;
       // restart: V_new = [V_k Qk, V_{k:k+b}] per problem, new H, k = r
-      std::fill(hkout.begin(), hkout.end(), 0);
+      std::fill(hkout, hkout + n, 0);
       int max_kin = 1, max_kout = 1;
-      std::fill(Hh.begin(), Hh.end(), 0.0);
+      std::fill(Hh, Hh + nh, 0.0);
       for (int i : rst) {
         const riga::KsCycle& c = cyc[i];
         const int kin = kend[i] + b, kout = c.r + b;
-        std::memcpy(Qh.data() + (size_t)i * 2 * hl, c.Qe.data(), c.Qe.size() * sizeof(double));
+        std::memcpy(Qh + (size_t)i * 2 * hl, c.Qe.data(), c.Qe.size() * sizeof(double));
         hkin[i] = kin; hkout[i] = kout; hqoff[i] = (int64_t)i * 2 * hl;
         max_kin = std::max(max_kin, kin);
         max_kout = std::max(max_kout, kout);
-        std::memcpy(Hh.data() + (size_t)i * hl, c.Hn.data(), hl * sizeof(double));
+        std::memcpy(Hh + (size_t)i * hl, c.Hn.data(), hl * sizeof(double));
         kc[i] = c.r;
       }
       for (int i = 0; i < n; ++i) live[i] = state[i] == ACTIVE ? 1 : 0;
-      ck(hipMemcpyAsync(bh->Qd, Qh.data(), sizeof(double) * n * 2 * hl, hipMemcpyHostToDevice, st));
-      ck(hipMemcpyAsync(bh->kin, hkin.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
-      ck(hipMemcpyAsync(bh->kout, hkout.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
-      ck(hipMemcpyAsync(bh->qoff, hqoff.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
+      ck(hipMemcpyAsync(bh->Qd, Qh, sizeof(double) * nq2, hipMemcpyHostToDevice, st));
+      ck(hipMemcpyAsync(bh->kin, hkin, sizeof(int) * n, hipMemcpyHostToDevice, st));
+      ck(hipMemcpyAsync(bh->kout, hkout, sizeof(int) * n, hipMemcpyHostToDevice, st));
+      ck(hipMemcpyAsync(bh->qoff, hqoff, sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
       riga::launch_gemm_tall_b(B, bh->kin, bh->kout, bh->qoff, bh->Qd, max_kin, max_kout, bh->Vu, bh->Vu2, st);
       riga::launch_gemm_tall_b(B, bh->kin, bh->kout, bh->qoff, bh->Qd, max_kin, max_kout, bh->Vl, bh->Vl2, st);
       riga::launch_gemm_tall_b(B, bh->kin, bh->kout, bh->qoff, bh->Qd, max_kin, max_kout, bh->Wl, bh->Wl2, st);
       std::swap(bh->Vu, bh->Vu2); std::swap(bh->Vl, bh->Vl2); std::swap(bh->Wl, bh->Wl2);
-      ck(hipMemcpyAsync(bh->H, Hh.data(), sizeof(double) * n * hl, hipMemcpyHostToDevice, st));
-      ck(hipMemcpyAsync(B.kcur, kc.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
-      ck(hipMemcpyAsync(B.live, live.data(), n, hipMemcpyHostToDevice, st));
-      ck(hipStreamSynchronize(st));   // host staging vectors are rewritten next cycle
+      std::memcpy(hkc, kc.data(), sizeof(int) * n);
+      std::memcpy(hlive, live.data(), n);
+      ck(hipMemcpyAsync(bh->H, Hh, sizeof(double) * nh, hipMemcpyHostToDevice, st));
+      ck(hipMemcpyAsync(B.kcur, hkc, sizeof(int) * n, hipMemcpyHostToDevice, st));
+      ck(hipMemcpyAsync(B.live, hlive, n, hipMemcpyHostToDevice, st));
+      ck(hipStreamSynchronize(st));   // the staging area is rewritten next cycle
     }
     fp->dt.ilive = nullptr;
     // --- eigenpairs of every finished problem ------------------------------------

@@ -12,9 +12,9 @@ int ks_ritz(const std::vector<double>& H, int ldh, int k, int b, int nev, double
   for (int col = 0; col < k; ++col)
     for (int r = 0; r < k; ++r) Hk[r + (size_t)col * k] = Hat(r, col);
   if (schur_real(k, Hk.data(), c.TR, c.QR) != 0) return -1;
-  schur_complexify(k, c.TR, c.QR, c.T, c.Z);
-  c.theta.resize(k);
-  for (int i = 0; i < k; ++i) c.theta[i] = c.T[i + (size_t)i * k];
+  c.T.clear();   // the complex Schur form is formed only if a restart needs it
+  c.Z.clear();
+  schur_real_eigvals(k, c.TR, c.theta);
   // sort by |theta| descending (= |lam - sigma| ascending), clusters kept together
   c.ord.resize(k);
   std::iota(c.ord.begin(), c.ord.end(), 0);
@@ -27,7 +27,7 @@ int ks_ritz(const std::vector<double>& H, int ldh, int k, int b, int nev, double
   c.nw = pos;
   c.wanted.assign(c.ord.begin(), c.ord.begin() + c.nw);
   // Ritz vectors of the wanted values and residual estimates ||E y|| (E = rows k..k+b of H)
-  schur_eigvecs(k, c.T, c.Z, c.Y, 1e-11, &c.wanted);
+  schur_eigvecs_real(k, c.TR, c.QR, c.theta, c.Y, 1e-11, &c.wanted);
   c.nconv = 0;
   for (int p = 0; p < c.nw; ++p) {
     const int i = c.ord[p];
@@ -90,6 +90,7 @@ void ks_restart(const std::vector<double>& H, int ldh, int k, int b, int m, int 
   // Fallback (an ill-conditioned exchange): reorder the complex Schur form and
   // take a real basis of the kept span.
   c.real_restart = false;
+  if (c.T.empty()) schur_complexify(k, c.TR, c.QR, c.T, c.Z);
   std::vector<cplx> T = c.T, Z = c.Z;
   schur_select(k, T, Z, kept);
   std::vector<double> Qk;

@@ -11,7 +11,8 @@ namespace riga {
 
 struct KsCycle {
   std::vector<double> TR, QR;      // real Schur form of H_k and its vectors (k x k)
-  std::vector<cplx> T, Z, Y;       // complex Schur form, its vectors, Ritz vectors (k x k)
+  std::vector<cplx> T, Z, Y;       // complex Schur form and its vectors (formed by the restart
+                                   // only when the real reordering fails), Ritz vectors (k x k)
   std::vector<cplx> theta;         // Ritz values of S
   std::vector<int> ord;            // positions by |theta| descending, clusters kept together
   int nw = 0;                      // wanted values: nev extended to the end of its cluster

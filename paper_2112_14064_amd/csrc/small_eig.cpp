@@ -442,6 +442,155 @@ void schur_select(int n, std::vector<cplx>& T, std::vector<cplx>& Z, const std::
   }
 }
 
+namespace {
+
+// A real 2x2 block B = [[a, b], [c, d]] triangularised by the unitary
+// G = [[v1, -conj(v2)], [v2, conj(v1)]] whose first column is a unit
+// eigenvector of B (the rotation schur_complexify applies):
+// G^H B G = [[m1, beta], [0, m2]].
+struct Block2 {
+  cplx v1, v2, m1, m2, beta;
+  bool pair;   // complex-conjugate eigenvalues: m2 is taken as conj(m1)
+};
+
+Block2 block2(double a, double b, double c, double d) {
+  const cplx half = 0.5 * (a - d);
+  const cplx disc = std::sqrt(half * half + b * c);
+  const cplx lam = 0.5 * (a + d) + disc;
+  cplx v1 = b, v2 = lam - a;
+  if (std::abs(v1) + std::abs(v2) < std::abs(lam - d) + std::abs(c)) { v1 = lam - d; v2 = c; }
+  const double nv = std::sqrt(std::norm(v1) + std::norm(v2));
+  v1 /= nv;
+  v2 /= nv;
+  const cplx g00 = a * v1 + b * v2, g10 = c * v1 + d * v2;   // B times the first column of G
+  const cplx g01 = -a * std::conj(v2) + b * std::conj(v1);    // B times the second column
+  const cplx g11 = -c * std::conj(v2) + d * std::conj(v1);
+  Block2 r;
+  r.v1 = v1;
+  r.v2 = v2;
+  r.m1 = std::conj(v1) * g00 + std::conj(v2) * g10;
+  r.beta = std::conj(v1) * g01 + std::conj(v2) * g11;
+  r.pair = (half * half + b * c).real() < 0.0;
+  r.m2 = r.pair ? std::conj(r.m1) : -v2 * g01 + v1 * g11;
+  return r;
+}
+
+inline bool block_starts2(int n, const std::vector<double>& T, int i) {
+  return i + 1 < n && T[(i + 1) + (size_t)i * n] != 0.0;
+}
+
+}  // namespace
+
+void schur_real_eigvals(int n, const std::vector<double>& T, std::vector<cplx>& theta) {
+  theta.assign(n, cplx(0.0));
+  for (int i = 0; i < n;) {
+    if (block_starts2(n, T, i)) {
+      const Block2 g = block2(T[i + (size_t)i * n], T[i + (size_t)(i + 1) * n], T[(i + 1) + (size_t)i * n],
+                              T[(i + 1) + (size_t)(i + 1) * n]);
+      theta[i] = g.m1;
+      theta[i + 1] = g.m2;
+      i += 2;
+    } else {
+      theta[i] = T[i + (size_t)i * n];
+      i += 1;
+    }
+  }
+}
+
+void schur_eigvecs_real(int n, const std::vector<double>& T, const std::vector<double>& Q,
+                        const std::vector<cplx>& theta, std::vector<cplx>& Y, double cluster_tol,
+                        const std::vector<int>* which) {
+  auto t = [&](int i, int j) { return T[i + (size_t)j * n]; };
+  double scale = 0.0;
+  for (int i = 0; i < n; ++i) scale = std::max(scale, std::abs(theta[i]));
+  if (scale == 0.0) scale = 1.0;
+  const double ctol = cluster_tol * scale;
+  const double tiny = std::numeric_limits<double>::min() / std::numeric_limits<double>::epsilon();
+  auto solve1 = [&](cplx rhs, cplx d) -> cplx {   // x with d x = rhs, clustered diagonal -> 0
+    if (std::abs(d) <= ctol) return 0.0;
+    if (std::abs(d) < tiny) d = tiny;
+    return rhs / d;
+  };
+  // block of every position: its first row and size
+  std::vector<int> bstart(n), bsize(n);
+  for (int i = 0; i < n;) {
+    const int sz = block_starts2(n, T, i) ? 2 : 1;
+    for (int u = 0; u < sz; ++u) { bstart[i + u] = i; bsize[i + u] = sz; }
+    i += sz;
+  }
+  Y.assign((size_t)n * n, cplx(0.0));
+  std::vector<char> done(n, 0);
+  std::vector<cplx> x(n);
+  std::vector<double> yr(n), yi(n);
+  const int nk = which ? (int)which->size() : n;
+  for (int kk = 0; kk < nk; ++kk) {
+    const int k = which ? (*which)[kk] : kk;
+    if (done[k]) continue;
+    const cplx lam = theta[k];
+    const int kb = bstart[k], kend = kb + bsize[k] - 1;
+    std::fill(x.begin(), x.begin() + kend + 1, cplx(0.0));
+    // the eigenvector on its own block (triangularised coordinates w, x = G w)
+    if (bsize[k] == 1) {
+      x[k] = 1.0;
+    } else {
+      const Block2 g = block2(t(kb, kb), t(kb, kb + 1), t(kb + 1, kb), t(kb + 1, kb + 1));
+      cplx w0 = 1.0, w1 = 0.0;
+      if (k == kb + 1) {
+        w1 = 1.0;
+        w0 = solve1(-g.beta, g.m1 - lam);
+      }
+      x[kb] = g.v1 * w0 - std::conj(g.v2) * w1;
+      x[kb + 1] = g.v2 * w0 + std::conj(g.v1) * w1;
+    }
+    // back-substitution through the blocks above, bottom to top
+    for (int i = kb - 1; i >= 0;) {
+      const int i0 = bstart[i];
+      if (bsize[i] == 1) {
+        cplx s = 0.0;
+        for (int j = i + 1; j <= kend; ++j) s += t(i, j) * x[j];
+        x[i] = solve1(-s, t(i, i) - lam);
+      } else {
+        cplx s0 = 0.0, s1 = 0.0;
+        for (int j = i0 + 2; j <= kend; ++j) {
+          s0 += t(i0, j) * x[j];
+          s1 += t(i0 + 1, j) * x[j];
+        }
+        const Block2 g = block2(t(i0, i0), t(i0, i0 + 1), t(i0 + 1, i0), t(i0 + 1, i0 + 1));
+        const cplx r0 = std::conj(g.v1) * s0 + std::conj(g.v2) * s1, r1 = -g.v2 * s0 + g.v1 * s1;
+        const cplx w1 = solve1(-r1, g.m2 - lam);
+        const cplx w0 = solve1(-r0 - g.beta * w1, g.m1 - lam);
+        x[i0] = g.v1 * w0 - std::conj(g.v2) * w1;
+        x[i0 + 1] = g.v2 * w0 + std::conj(g.v1) * w1;
+      }
+      i = i0 - 1;
+    }
+    // y = Q x, unit 2-norm
+    std::fill(yr.begin(), yr.end(), 0.0);
+    std::fill(yi.begin(), yi.end(), 0.0);
+    for (int j = 0; j <= kend; ++j) {
+      const double xr = x[j].real(), xi = x[j].imag();
+      const double* q = &Q[(size_t)j * n];
+      for (int i = 0; i < n; ++i) {
+        yr[i] += q[i] * xr;
+        yi[i] += q[i] * xi;
+      }
+    }
+    double nrm = 0.0;
+    for (int i = 0; i < n; ++i) nrm += yr[i] * yr[i] + yi[i] * yi[i];
+    nrm = std::sqrt(nrm);
+    cplx* y = &Y[(size_t)k * n];
+    for (int i = 0; i < n; ++i) y[i] = cplx(yr[i] / nrm, yi[i] / nrm);
+    done[k] = 1;
+    // the conjugate eigenvalue of a complex pair: the conjugate vector
+    if (bsize[k] == 2 && k == kb &&
+        block2(t(kb, kb), t(kb, kb + 1), t(kb + 1, kb), t(kb + 1, kb + 1)).pair) {
+      cplx* y2 = &Y[(size_t)(kb + 1) * n];
+      for (int i = 0; i < n; ++i) y2[i] = std::conj(y[i]);
+      done[kb + 1] = 1;
+    }
+  }
+}
+
 void schur_eigvecs(int n, const std::vector<cplx>& T, const std::vector<cplx>& Z,
                    std::vector<cplx>& Y, double cluster_tol, const std::vector<int>* which) {
   auto t = [&](int i, int j) { return T[i + (size_t)j * n]; };

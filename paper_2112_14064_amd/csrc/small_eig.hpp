@@ -45,6 +45,19 @@ void schur_reorder(int n, std::vector<cplx>& T, std::vector<cplx>& Z, const std:
 void schur_eigvecs(int n, const std::vector<cplx>& T, const std::vector<cplx>& Z,
                    std::vector<cplx>& Y, double cluster_tol, const std::vector<int>* which = nullptr);
 
+// Eigenvalues of a real Schur form T in the order of its diagonal: a 2x2
+// block gives the diagonal of its triangularised form (the values at the same
+// positions of schur_complexify's T).
+void schur_real_eigvals(int n, const std::vector<double>& T, std::vector<cplx>& theta);
+// The eigenvectors of schur_eigvecs computed from the real Schur form
+// A = Q T Q^T (theta from schur_real_eigvals): back-substitution through the
+// quasi-triangular T with each 2x2 block triangularised on the fly, so the
+// same clustering rule applies per diagonal position; the vector of the
+// second eigenvalue of a complex-conjugate block is the conjugate of the first.
+void schur_eigvecs_real(int n, const std::vector<double>& T, const std::vector<double>& Q,
+                        const std::vector<cplx>& theta, std::vector<cplx>& Y, double cluster_tol,
+                        const std::vector<int>* which = nullptr);
+
 // Reorder the Schur form so that the diagonal entries with keep[i] != 0 come
 // first (their relative order kept) with the fewest adjacent exchanges: each
 // entry not kept moves down past the kept ones below it.
