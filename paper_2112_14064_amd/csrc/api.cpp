@@ -756,14 +756,18 @@ riga_status riga_stats(const riga_problem* h, riga_stats_t* stats) {
 
 riga_status riga_selftest_small_eig(int n, const double* a, double* w, double* resid) {
   if (n < 1 || !a || !w) return RIGA_ERR_INVALID_ARG;
-  std::vector<cplx> T, Z, Y;
-  if (riga::schur_complex(n, a, T, Z) != 0) return RIGA_WARN_NOT_CONVERGED;
-  riga::schur_eigvecs(n, T, Z, Y, 1e-12);
+  // the path of the Ritz step: real Schur form, eigenvalues of its blocks,
+  // eigenvectors by back-substitution through the quasi-triangular form
+  std::vector<double> TR, QR;
+  std::vector<cplx> theta, Y;
+  if (riga::schur_real(n, a, TR, QR) != 0) return RIGA_WARN_NOT_CONVERGED;
+  riga::schur_real_eigvals(n, TR, theta);
+  riga::schur_eigvecs_real(n, TR, QR, theta, Y, 1e-12);
   double an = 0.0;
   for (int i = 0; i < n * n; ++i) an = std::max(an, std::abs(a[i]));
   double worst = 0.0;
   for (int k = 0; k < n; ++k) {
-    cplx lam = T[k + (size_t)k * n];
+    cplx lam = theta[k];
     w[2 * k] = lam.real();
     w[2 * k + 1] = lam.imag();
     for (int i = 0; i < n; ++i) {

@@ -92,19 +92,23 @@ __device__ __forceinline__ int acc_col(int lane, int wave, int tj) {
 // Front assembly, columns [64 y, 64 y + 64) of the front per workgroup: zero
 // them (own columns in the L block, boundary columns in the U block) and add
 // the original entries Q[g, d] for the own dofs d of the chunk and front dofs g
-// at or below d (formed in FP64, stored in E).
+// at or below d (formed in FP64, stored in E).  The node's sorted front keys
+// and their positions are staged in shared memory (2 nf ints); each wave takes
+// one own column at a time, its lanes the stored entries of that row, and
+// finds an entry's front position by binary search in shared memory.
 template <class E>
 __global__ __launch_bounds__(FT) void k_front_assemble(
     int n, const int* lo, const int* hi, const int64_t* rowptr,
     DevTree t, const int* __restrict__ level_nodes, double s2, double s1,
     const double* __restrict__ Kv, const double* __restrict__ Mv, const double* __restrict__ Cv,
     E* __restrict__ Lbuf, E* __restrict__ Ubuf) {
+  extern __shared__ int keys[];   // keys[0, nf): sorted front dofs; keys[nf, 2 nf): their positions
   const int v = level_nodes[blockIdx.x];
   const Front<E> F = front_of(t, v, Lbuf, Ubuf);
   const int nf = F.nf, no = F.no, nb = F.nb;
   const int c0 = TB * blockIdx.y, c1 = min(nf, c0 + TB);
   if (c0 >= nf) return;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int* fd = t.fdofs + t.foff[v];
   const int* fk = t.fkey + t.foff[v];
   const int* fp = t.fpos + t.foff[v];
@@ -117,6 +121,12 @@ __global__ __launch_bounds__(FT) void k_front_assemble(
     s1 = t.isig[q];
     s2 = s1 * s1;
   }
+  const bool own = c0 < no;
+  if (own)
+    for (int x = tid; x < nf; x += FT) {
+      keys[x] = fk[x];
+      keys[nf + x] = fp[x];
+    }
   for (int c = c0; c < c1; ++c) {
     if (c < no) {
       for (int r = tid; r < nf; r += FT) F.L[(int64_t)c * nf + r] = E(0);
@@ -125,21 +135,22 @@ __global__ __launch_bounds__(FT) void k_front_assemble(
     }
   }
   __syncthreads();
-  for (int a = c0 + tid; a < min(c1, no); a += FT) {
+  if (!own) return;
+  for (int a = c0 + wave; a < min(c1, no); a += FT / 64) {
     const int d = fd[a] - base;
     const int i = d % n, j = d / n;
-    const int wx = hi[i] - lo[i] + 1;
+    const int lx = lo[i], wx = hi[i] - lx + 1, ly = lo[j];
     const int64_t k0 = rowptr[d], k1 = rowptr[d + 1];
-    for (int64_t k = k0; k < k1; ++k) {
+    for (int64_t k = k0 + lane; k < k1; k += 64) {
       const int o = (int)(k - k0);
-      const int g = (lo[j] + o / wx) * n + lo[i] + o % wx + base;
+      const int g = (ly + o / wx) * n + lx + o % wx + base;
       int x0 = 0, x1 = nf;  // binary search of g among the sorted front keys
       while (x1 - x0 > 1) {
         const int c = (x0 + x1) >> 1;
-        if (fk[c] <= g) x0 = c; else x1 = c;
+        if (keys[c] <= g) x0 = c; else x1 = c;
       }
-      if (fk[x0] == g) {
-        const int pos = fp[x0];
+      if (keys[x0] == g) {
+        const int pos = keys[nf + x0];
         if (pos >= a) F.L[(int64_t)a * nf + pos] = (E)(s2 * Mv[k] + s1 * Cv[k] + Kv[k]);
       }
     }
@@ -176,11 +187,14 @@ __global__ __launch_bounds__(FT) void k_front_extend(DevTree t, const int* __res
 
 // ---------------------------------------------------------------------------------
 // Cholesky of the diagonal block [k0, k0+w) and D = its inverse (lower), stored
-// at D + (doff[v] + k0/64) * 4096 as D[r * 64 + c].  One wave does both in LDS,
-// lane = row for the factorisation (left-looking: column c of every row from
-// the finished columns, the pivot taken from lane c) and lane = column for the
-// inverse (forward substitution row by row); the wave's LDS accesses are in
-// program order, so no workgroup barrier is needed between the columns.
+// at D + (doff[v] + k0/64) * 4096 as D[r * 64 + c].  One wave does both with
+// the block in registers: lane = row for the factorisation (right-looking:
+// at column c every lane scales its entry and updates the rest of its row
+// from column c of the other rows, broadcast through shared memory), then
+// lane = column for the inverse (forward substitution against the rows of L,
+// broadcast from shared memory, with the reciprocal pivots of the
+// factorisation).  Every loop is unrolled so the row / column stays in
+// registers.
 template <class E>
 __global__ __launch_bounds__(FT) void k_potrf_diag(DevTree t, const int* __restrict__ level_nodes, int k0,
                                                    E* __restrict__ Lbuf, E* __restrict__ Ubuf,
@@ -192,57 +206,68 @@ __global__ __launch_bounds__(FT) void k_potrf_diag(DevTree t, const int* __restr
   const int w = min(TB, F.no - k0);
   const int tid = threadIdx.x;
   __shared__ E S[TB][LDT];
-  __shared__ E Dl[TB][LDT];
+  __shared__ E col[TB];   // column c of the rows, before scaling
+  __shared__ E rd[TB];    // reciprocal pivots
   for (int idx = tid; idx < TB * TB; idx += FT) {
     const int r = idx % TB, c = idx / TB;       // coalesced along the column
     S[r][c] = (r < w && c <= r) ? F.L[(int64_t)(k0 + c) * F.nf + k0 + r] : E(0);
-    Dl[r][c] = E(0);
   }
+  if (tid < TB) rd[tid] = E(0);
   __syncthreads();
+  E* D = Dbuf + ((int64_t)t.doff[v] + k0 / TB) * (TB * TB);
   if (tid < TB) {
     const int r = tid;
-    for (int c = 0; c < w; ++c) {
-      // four partial sums keep the FMA chain short
-      E s0 = E(0), s1 = E(0), s2 = E(0), s3 = E(0);
-      int k = 0;
-      for (; k + 4 <= c; k += 4) {
-        s0 += S[r][k] * S[c][k];
-        s1 += S[r][k + 1] * S[c][k + 1];
-        s2 += S[r][k + 2] * S[c][k + 2];
-        s3 += S[r][k + 3] * S[c][k + 3];
-      }
-      for (; k < c; ++k) s0 += S[r][k] * S[c][k];
-      const E acc = S[r][c] - ((s0 + s1) + (s2 + s3));
-      double piv = (double)__shfl(acc, c, 64);
-      if (!(piv > 0.0)) {           // not SPD (or NaN): record, continue with 1
-        if (r == c)
-          atomicCAS((unsigned long long*)status, (unsigned long long)(-1ll),
-                    (unsigned long long)t.fdofs[t.foff[v] + k0 + c]);
-        piv = 1.0;
-      }
-      const E d = (E)sqrt(piv);
-      if (r == c) S[c][c] = d;
-      else if (r > c && r < w) S[r][c] = acc / d;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    // inverse of the lower-triangular block, lane = column
-    const int c = tid;
-    if (c < w) {
-      Dl[c][c] = E(1) / S[c][c];
-      for (int rr = c + 1; rr < w; ++rr) {
-        E s0 = E(0), s1 = E(0), s2 = E(0), s3 = E(0);
-        int k = c;
-        for (; k + 4 <= rr; k += 4) {
-          s0 += S[rr][k] * Dl[k][c];
-          s1 += S[rr][k + 1] * Dl[k + 1][c];
-          s2 += S[rr][k + 2] * Dl[k + 2][c];
-          s3 += S[rr][k + 3] * Dl[k + 3][c];
+    E row[TB];
+#pragma unroll
+    for (int k = 0; k < TB; ++k) row[k] = S[r][k];
+#pragma unroll
+    for (int c = 0; c < TB; ++c) {
+      if (c < w) {   // uniform
+        col[r] = row[c];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double piv = (double)col[c];
+        if (!(piv > 0.0)) {           // not SPD (or NaN): record, continue with 1
+          if (r == c)
+            atomicCAS((unsigned long long*)status, (unsigned long long)(-1ll),
+                      (unsigned long long)t.fdofs[t.foff[v] + k0 + c]);
+          piv = 1.0;
         }
-        for (; k < rr; ++k) s0 += S[rr][k] * Dl[k][c];
-        Dl[rr][c] = -((s0 + s1) + (s2 + s3)) / S[rr][rr];
+        const E d = (E)sqrt(piv);
+        const E inv = E(1) / d;
+        if (r == c) rd[c] = inv;
+        const E lrc = row[c] * inv;   // L[r][c] (rows below the pivot)
+        const E tc = lrc * inv;
+#pragma unroll
+        for (int j = c + 1; j < TB; ++j) row[j] -= tc * col[j];
+        row[c] = (r == c) ? d : lrc;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();   // col is rewritten at the next column
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
+    }
+#pragma unroll
+    for (int k = 0; k < TB; ++k)
+      if (k <= r) S[r][k] = row[k];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // inverse, lane = column c: D[rr][c] = -(sum_k L[rr][k] D[k][c]) / L[rr][rr]
+    const int c = tid;
+    E dc[TB];
+#pragma unroll
+    for (int rr = 0; rr < TB; ++rr) {
+      E s0 = E(0), s1 = E(0);
+#pragma unroll
+      for (int k = 0; k + 1 < rr; k += 2) {
+        s0 += S[rr][k] * dc[k];
+        s1 += S[rr][k + 1] * dc[k + 1];
+      }
+      if (rr & 1) s0 += S[rr][rr - 1] * dc[rr - 1];
+      const E ri = rd[rr];
+      dc[rr] = (rr < c) ? E(0) : (rr == c ? ri : -(s0 + s1) * ri);
+      D[rr * TB + c] = dc[rr];
     }
   }
   __syncthreads();
@@ -250,8 +275,6 @@ __global__ __launch_bounds__(FT) void k_potrf_diag(DevTree t, const int* __restr
     const int r = idx % TB, c = idx / TB;
     if (r < w && c <= r) F.L[(int64_t)(k0 + c) * F.nf + k0 + r] = S[r][c];
   }
-  E* D = Dbuf + ((int64_t)t.doff[v] + k0 / TB) * (TB * TB);
-  for (int idx = tid; idx < TB * TB; idx += FT) D[idx] = Dl[idx / TB][idx % TB];
 }
 
 // Panel rows [k0 + w + 64 y, +64) of columns [k0, k0 + w): X = A D^T.
@@ -472,8 +495,8 @@ void front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, i
                   const double* U64, int64_t* status, hipStream_t st) {
   if (count <= 0) return;
   const int ncol = (max_nf + TB - 1) / TB;
-  hipLaunchKernelGGL(k_front_assemble<E>, dim3(count, ncol), dim3(FT), 0, st, s.n, s.lo, s.hi, s.rowptr, t,
-                     level_nodes, s2, s1, K, M, C, L, U);
+  hipLaunchKernelGGL(k_front_assemble<E>, dim3(count, ncol), dim3(FT), (size_t)2 * max_nf * sizeof(int), st, s.n,
+                     s.lo, s.hi, s.rowptr, t, level_nodes, s2, s1, K, M, C, L, U);
   if (max_child_nb > 0)
     for (int slot = 0; slot < max_kids; ++slot)
       hipLaunchKernelGGL(k_front_extend<E>, dim3(count, (max_child_nb + TB - 1) / TB), dim3(FT), 0, st, t,

@@ -116,8 +116,8 @@ __global__ __launch_bounds__(NW * 64) void k_fwd(DevTree t, const SweepTask* __r
   const int gend = (jend + K - 1) / K;
   // front vector: own entries of b plus the children's update rows, added in
   // child order (one pass, no barrier per child).  A position's record
-  // {dof or -1, update rows, first update row, list start} gives the b entry
-  // and the first update row in one load; the record of the first gather
+  // {dof or -1, update rows, first update row, second row or list start}
+  // gives the b entry and up to two update rows in one load; the record of the first gather
   // round is requested before the factor, so that waiting for it does not
   // wait for the factor loads.
   const int4* gs = t.gsrc + tk.foff;
@@ -138,10 +138,16 @@ __global__ __launch_bounds__(NW * 64) void k_fwd(DevTree t, const SweepTask* __r
       const double* uc = upd + (int64_t)rc.z * NR;
 #pragma unroll
       for (int q = 0; q < NR; ++q) s[q] += uc[q];
-      for (int k = 1; k < rc.y; ++k) {
-        const double* u2 = upd + (int64_t)t.gidx[rc.w + k] * NR;
+      if (rc.y == 2) {
+        const double* u2 = upd + (int64_t)rc.w * NR;
 #pragma unroll
         for (int q = 0; q < NR; ++q) s[q] += u2[q];
+      } else {
+        for (int k = 1; k < rc.y; ++k) {
+          const double* u2 = upd + (int64_t)t.gidx[rc.w + k] * NR;
+#pragma unroll
+          for (int q = 0; q < NR; ++q) s[q] += u2[q];
+        }
       }
     }
 #pragma unroll

@@ -29,7 +29,8 @@ struct DevTree {
   // per child.
   const int* gptr; const int* gidx;
   // per front position foff[v] + p: {its dof for p < no, else -1; number of
-  // update rows; the first of them; its index in gidx}
+  // update rows; the first of them; the second of them when there are two,
+  // else the list's index in gidx}
   const int4* gsrc;
   const int64_t* doff;          // per node: first 64x64 block of its diagonal inverses
   const unsigned char* prec;    // per node: 1 = FP32 front (mixed factor), or null (all FP64)

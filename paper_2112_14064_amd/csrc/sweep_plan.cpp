@@ -35,7 +35,8 @@ void build_sweep_plan(const Plan& P, const std::vector<int>& node_inst, SweepPla
     for (int p = 0; p < P.nf[v]; ++p) {
       const size_t q = (size_t)P.foff[v] + p;
       const int cnt = S.gptr[q + 1] - S.gptr[q];
-      S.gsrc[q] = int4{p < P.no[v] ? P.fdofs[q] : -1, cnt, cnt > 0 ? S.gidx[S.gptr[q]] : 0, S.gptr[q]};
+      S.gsrc[q] = int4{p < P.no[v] ? P.fdofs[q] : -1, cnt, cnt > 0 ? S.gidx[S.gptr[q]] : 0,
+                       cnt == 2 ? S.gidx[S.gptr[q] + 1] : S.gptr[q]};
     }
   // sweep layouts: every node padded to groups of 4 columns / rows
   S.lpoff.assign(nn + 1, 0);

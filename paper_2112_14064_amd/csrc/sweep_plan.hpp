@@ -11,7 +11,8 @@ namespace riga {
 struct SweepPlan {
   std::vector<int> voff;                 // per node: first row of its update vector (nn + 1)
   std::vector<int> gptr, gidx;           // per front position: update rows added to it
-  std::vector<int4> gsrc;                // per front position: {dof or -1, count, first row, gptr}
+  std::vector<int4> gsrc;                // per front position: {dof or -1, count, first row,
+                                         //  second row (count 2) or gptr (count > 2)}
   std::vector<int64_t> lpoff, tpoff;     // per node: packed forward / backward layouts of F (nn + 1)
   int64_t lpsize = 0, tpsize = 0;        // entries of the layouts, with slack
   std::vector<SweepTask> ftasks, btasks; // 64-row tasks grouped by level

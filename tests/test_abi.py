@@ -96,6 +96,18 @@ def test_small_dense_eigensolver_complex_pairs(seed):
         assert np.min(np.abs(w - x)) < 1e-11
 
 
+def test_small_dense_eigensolver_repeated_complex_pairs():
+    """Semisimple repeated complex-conjugate pairs (the degenerate modes of the
+    square): every copy's eigenvector satisfies the eigen-equation."""
+    rng = np.random.default_rng(4)
+    pairs = [(0.3, 1.7)] * 3 + [(-0.5, 0.9)] * 2 + [(1.1, 0.4)]
+    a, ev = _rotation_blocks(rng, pairs, [0.25, 0.25, -1.5])
+    w, res = riga.riga_selftest_small_eig(a)
+    assert res < 1e-12
+    for x in ev:
+        assert np.min(np.abs(w - x)) < 1e-10
+
+
 def test_small_dense_eigensolver_large_and_triangular():
     rng = np.random.default_rng(9)
     a = rng.standard_normal((128, 128))
