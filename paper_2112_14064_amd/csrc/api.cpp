@@ -112,13 +112,13 @@ void sweep(riga_problem* h, int nrhs, const double* b, int64_t ldb, const riga::
     int a = h->ftask_off[lv], c = h->ftask_off[lv + 1] - a;
     const bool f32 = h->level_f32(lv);
     riga::launch_fwd_level(h->dt, h->d_ftasks + a, c, nrhs, h->d_Lp, f32 ? h->d_Lp32 : nullptr, b, ldb, h->d_tmp,
-                           h->N(), h->d_upd, P.max_front, h->fvar[lv], h->st);
+                           h->N(), h->d_upd, h->lvl_max_nf[lv], h->fvar[lv], h->st);
   }
   for (int lv = H - 1; lv >= 0; --lv) {
     int a = h->btask_off[lv], c = h->btask_off[lv + 1] - a;
     const bool f32 = h->level_f32(lv);
     riga::launch_bwd_level(h->dt, h->d_btasks + a, c, nrhs, h->d_Tp, f32 ? h->d_Tp32 : nullptr, h->d_tmp, h->N(), o,
-                           P.max_front, h->bvar[lv], h->st);
+                           h->lvl_max_nf[lv], h->bvar[lv], h->st);
   }
 }
 
@@ -586,11 +586,11 @@ void autotune_sweeps(riga_problem* h, int nrhs, int reps, double* before_ms, dou
       if (fwd) {
         const int a = h->ftask_off[lv], c = h->ftask_off[lv + 1] - a;
         riga::launch_fwd_level(h->dt, h->d_ftasks + a, c, nrhs, h->d_Lp, f32 ? h->d_Lp32 : nullptr, h->d_tmp2, N,
-                               h->d_tmp, N, h->d_upd, P.max_front, var, h->st);
+                               h->d_tmp, N, h->d_upd, h->lvl_max_nf[lv], var, h->st);
       } else {
         const int a = h->btask_off[lv], c = h->btask_off[lv + 1] - a;
         riga::launch_bwd_level(h->dt, h->d_btasks + a, c, nrhs, h->d_Tp, f32 ? h->d_Tp32 : nullptr, h->d_tmp, N, o,
-                               P.max_front, var, h->st);
+                               h->lvl_max_nf[lv], var, h->st);
       }
     }
     ck(hipEventRecord(h->ev1, h->st));
@@ -875,12 +875,12 @@ riga_status riga_time_kernel(riga_problem* h, int which, int nrhs, int reps, dou
         if (which == 0) {
           int a = h->ftask_off[lv], c = h->ftask_off[lv + 1] - a;
           riga::launch_fwd_level(h->dt, h->d_ftasks + a, c, nrhs, h->d_Lp, h->level_f32(lv) ? h->d_Lp32 : nullptr,
-                                 h->d_tmp2, N, h->d_tmp, N, h->d_upd, P.max_front, h->fvar[lv], h->st);
+                                 h->d_tmp2, N, h->d_tmp, N, h->d_upd, h->lvl_max_nf[lv], h->fvar[lv], h->st);
         } else if (which == 1) {
           int l2 = H - 1 - lv;
           int a = h->btask_off[l2], c = h->btask_off[l2 + 1] - a;
           riga::launch_bwd_level(h->dt, h->d_btasks + a, c, nrhs, h->d_Tp, h->level_f32(l2) ? h->d_Tp32 : nullptr,
-                                 h->d_tmp, N, o, P.max_front, h->bvar[l2], h->st);
+                                 h->d_tmp, N, o, h->lvl_max_nf[l2], h->bvar[l2], h->st);
         } else {
           factor_level(h, lv, h->sigma);
         }

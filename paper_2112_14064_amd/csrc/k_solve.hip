@@ -117,11 +117,15 @@ __global__ __launch_bounds__(NW * 64) void k_fwd(DevTree t, const SweepTask* __r
   // front vector: own entries of b plus the children's update rows, added in
   // child order (one pass, no barrier per child).  A position's record
   // {dof or -1, update rows, first update row, second row or list start}
-  // gives the b entry and up to two update rows in one load; the record of the first gather
-  // round is requested before the factor, so that waiting for it does not
-  // wait for the factor loads.
+  // gives the b entry and up to two update rows in one load; the record of
+  // the first gather round is requested before the factor, so that waiting
+  // for it does not wait for the factor loads.  Only the positions the task
+  // reads are gathered: the columns of its product, [0, nown), and its
+  // boundary rows past them, [rb, r1).
+  const int nown = min(nf, gend * K), rb = max(nown, r0);
+  const int ng = nown + max(0, r1 - rb);
   const int4* gs = t.gsrc + tk.foff;
-  const int4 rec0 = gs[min(tid, nf - 1)];
+  const int4 rec0 = gs[min(tid < nown ? tid : rb + tid - nown, nf - 1)];
   __builtin_amdgcn_sched_barrier(0);      // keep the issue order
   int g = __builtin_amdgcn_readfirstlane(wave) * SG;
   V A[SG], B[SG];
@@ -129,8 +133,9 @@ __global__ __launch_bounds__(NW * 64) void k_fwd(DevTree t, const SweepTask* __r
   load_round<SG>(B, col, g + STEP, gend, nf);
   const int dst = fd[min(r, nf - 1)];      // used by own rows only
 
-  for (int p = tid; p < nf; p += NW * 64) {
-    const int4 rc = (p == tid) ? rec0 : gs[p];
+  for (int i = tid; i < ng; i += NW * 64) {
+    const int p = i < nown ? i : rb + i - nown;
+    const int4 rc = (i == tid) ? rec0 : gs[p];
     double s[NR];
 #pragma unroll
     for (int q = 0; q < NR; ++q) s[q] = (rc.x >= 0) ? b[rc.x + q * ldb] : 0.0;
@@ -158,11 +163,11 @@ __global__ __launch_bounds__(NW * 64) void k_fwd(DevTree t, const SweepTask* __r
 #pragma unroll
   for (int q = 0; q < NR; ++q) acc[q] = 0.0;
   while (g < gend) {
-    fma_round<NR, SG, K>(acc, A, g, gend, f, nf - 1);
+    fma_round<NR, SG, K>(acc, A, g, gend, f, nown - 1);
     load_round<SG>(A, col, g + 2 * STEP, gend, nf);
     g += STEP;
     if (g >= gend) break;
-    fma_round<NR, SG, K>(acc, B, g, gend, f, nf - 1);
+    fma_round<NR, SG, K>(acc, B, g, gend, f, nown - 1);
     load_round<SG>(B, col, g + 2 * STEP, gend, nf);
     g += STEP;
   }

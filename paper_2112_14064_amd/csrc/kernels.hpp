@@ -98,7 +98,9 @@ struct alignas(16) SweepTask {
   int no, foff, voff, inst;
   int64_t poff, unused;
 };
-// `variant` selects the task tile shape (0 .. sweep_variants()-1, see sweep_variant).
+// `variant` selects the task tile shape (0 .. sweep_variants()-1, see sweep_variant);
+// max_front bounds the fronts of the given tasks (it sizes the shared memory of
+// a workgroup, so the level's own largest front keeps occupancy up).
 void launch_fwd_level(const DevTree& t, const SweepTask* tasks, int count, int nrhs, const double* Lp64,
                       const float* Lp32, const double* b, int64_t ldb, double* y, int64_t ldy, double* upd,
                       int max_front, int variant, hipStream_t st);
