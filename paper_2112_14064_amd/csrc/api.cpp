@@ -162,8 +162,12 @@ void solve_levels(riga_problem* h, int nrhs, const double* b, int64_t ldb, doubl
 void apply_block(riga_problem* h, int nb, const double* vu, const double* wl, int64_t ld,
                  double* ru, double* rl, double* t) {
   const int64_t N = h->N();
-  riga::launch_spmv_ell(h->d_slabs, h->nslab, h->d_space1, nullptr, nullptr, nb, h->d_Aell, vu, ld, t, N, wl, ld,
-                        1.0, h->st);
+  if (h->c_elem == nullptr)   // sigma M + C = (sigma + alpha) M + beta K: sum factorisation
+    riga::launch_tensor_mk(h->ds, h->d_M1, h->d_K1, nb, h->sigma + h->alpha, h->beta, vu, ld, t, N, wl, ld, 1.0,
+                           h->st);
+  else
+    riga::launch_spmv_ell(h->d_slabs, h->nslab, h->d_space1, nullptr, nullptr, nb, h->d_Aell, vu, ld, t, N, wl, ld,
+                          1.0, h->st);
   solve_levels(h, nb, t, N, ru, N, rl, vu, ld, h->sigma);
 }
 
@@ -283,6 +287,8 @@ void setup_device(riga_problem* h) {
     const int np = S.p + 1;
     h->d_tabM = h->dalloc<double>((size_t)S.ne * np * np);
     h->d_tabK = h->dalloc<double>((size_t)S.ne * np * np);
+    h->d_M1 = h->dalloc<double>((size_t)S.n * (2 * S.p + 1));
+    h->d_K1 = h->dalloc<double>((size_t)S.n * (2 * S.p + 1));
     h->d_K = h->dalloc<double>(P.nnz); h->d_M = h->dalloc<double>(P.nnz); h->d_C = h->dalloc<double>(P.nnz);
     h->d_A = h->dalloc<double>(P.nnz);
     h->d_L = h->dalloc<double>(P.lsize); h->d_U = h->dalloc<double>(P.usize);
@@ -414,7 +420,7 @@ riga_status riga_assemble(riga_problem* h, const riga_damping* damping) {
     riga::launch_bspline_tables(h->ds, h->d_gx, h->d_gw, h->d_tabM, h->d_tabK, h->st);
     riga::launch_assemble(h->ds, h->d_tabM, h->d_tabK, damping->alpha, damping->beta, damping->c_elem,
                           h->d_K, h->d_M, h->d_C, h->N(), h->st);
-    riga::launch_csr_to_ell(h->d_slabs, h->nslab, h->ds.rowptr, h->d_M, h->d_Mell, h->st);
+    riga::launch_band_1d(h->ds, h->d_tabM, h->d_tabK, h->d_M1, h->d_K1, h->st);
     ck(hipGetLastError());
     ck(hipEventRecord(h->ev1, h->st));
     h->alpha = damping->alpha; h->beta = damping->beta; h->c_elem = damping->c_elem;
@@ -478,8 +484,10 @@ riga_status factor_all(riga_problem* h, double sigma, int64_t* bad_pivot) {
   for (int lv = 0; lv < P.height; ++lv) factor_level(h, lv, sigma);
   // sigma M + C for the operator, Q(sigma) for the residuals of the mixed factor
   riga::launch_combine3(P.nnz, sigma, h->d_M, 1.0, h->d_C, 0.0, h->d_K, h->d_A, h->st);
-  // (a forest combines its per-problem shifts itself and converts then)
-  if (h->node_inst.empty()) riga::launch_csr_to_ell(h->d_slabs, h->nslab, h->ds.rowptr, h->d_A, h->d_Aell, h->st);
+  // (a forest combines its per-problem shifts itself and converts then; without
+  // an element damping field the operator uses the sum-factorised product)
+  if (h->node_inst.empty() && h->c_elem != nullptr)
+    riga::launch_csr_to_ell(h->d_slabs, h->nslab, h->ds.rowptr, h->d_A, h->d_Aell, h->st);
   if (h->mixed) riga::launch_combine3(P.nnz, sigma * sigma, h->d_M, sigma, h->d_C, 1.0, h->d_K, h->d_Q, h->st);
   ck(hipGetLastError());
   ck(hipEventRecord(h->ev1, h->st));
@@ -1130,8 +1138,7 @@ struct KrylovRun {
     const int64_t n = N;
     const size_t o = (size_t)k * n;
     apply_block(h, b, h->Vu + o, h->Wl + o, n, h->Ru, h->Rl, h->Tv);
-    riga::launch_spmv_ell(h->d_slabs, h->nslab, h->d_space1, nullptr, nullptr, b, h->d_Mell, h->Rl, n, h->MRl, n,
-                          nullptr, 0, 0.0, h->st);
+    riga::launch_tensor_mk(h->ds, h->d_M1, h->d_K1, b, 1.0, 0.0, h->Rl, n, h->MRl, n, nullptr, 0, 0.0, h->st);
     orthonormalize_device(k + b, h->d_H, k);
   }
 

@@ -206,6 +206,42 @@ void launch_assemble_b(const int4* rb, int nrb, const DevSpace* spaces, const in
                      alpha, beta, c_elem, K, M, C);
 }
 
+// Banded 1-D mass and stiffness matrices of one space: entry (i, ii), ii in
+// lo[i] .. hi[i], is the sum over the shared elements that assemble_rows forms
+// for its x factor (same terms, same order), stored at i (2p + 1) + ii - i + p;
+// every other slot of the band is zero.  M = M1 (x) M1 and
+// K = K1 (x) M1 + M1 (x) K1 on the tensor grid.
+__device__ inline void band_entry(const DevSpace& s, int i, int o, const double* __restrict__ tabM,
+                                  const double* __restrict__ tabK, double* __restrict__ M1, double* __restrict__ K1) {
+  const int p = s.p, np = p + 1, w = 2 * p + 1;
+  const int ii = i - p + o;
+  double sx = 0.0, kx = 0.0;
+  if (ii >= s.lo[i] && ii <= s.hi[i]) {
+    const int ex0 = max(s.sup0[i], s.sup0[ii]), ex1 = min(s.sup1[i], s.sup1[ii]);
+    for (int ex = ex0; ex < ex1; ++ex) {
+      const int la = i + 1 - s.first[ex], lb = ii + 1 - s.first[ex];
+      const int64_t idx = (int64_t)ex * np * np + la * np + lb;
+      sx += tabM[idx];
+      kx += tabK[idx];
+    }
+  }
+  M1[(int64_t)i * w + o] = sx;
+  K1[(int64_t)i * w + o] = kx;
+}
+
+__global__ void k_band_1d(DevSpace s, const double* __restrict__ tabM, const double* __restrict__ tabK,
+                          double* __restrict__ M1, double* __restrict__ K1) {
+  const int w = 2 * s.p + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < s.n * w) band_entry(s, t / w, t % w, tabM, tabK, M1, K1);
+}
+
+void launch_band_1d(const DevSpace& s, const double* tabM, const double* tabK, double* M1, double* K1,
+                    hipStream_t st) {
+  const int total = s.n * (2 * s.p + 1);
+  hipLaunchKernelGGL(k_band_1d, dim3((total + 255) / 256), dim3(256), 0, st, s, tabM, tabK, M1, K1);
+}
+
 void launch_assemble(const DevSpace& s, const double* tabM, const double* tabK,
                      double alpha, double beta, const double* c_elem,
                      double* K, double* M, double* C, int64_t ndof, hipStream_t st) {

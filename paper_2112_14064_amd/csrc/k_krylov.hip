@@ -334,6 +334,117 @@ void launch_dots(int64_t n, int nc, const double* Au, const double* Al, int64_t 
 }
 
 // ---------------------------------------------------------------------------
+// Sum-factorised products with M = M1 (x) M1 and K = K1 (x) M1 + M1 (x) K1
+// (banded 1-D factors, band width w = 2p + 1, entry (i, ii) at
+// i w + ii - i + p).  A workgroup owns a tile of TT_I x TT_J grid points: it
+// stages X on the tile plus a halo of p in shared memory, forms
+// TM = X M1^T and TK = X K1^T along i for the tile's rows and the halo rows,
+// then Y = M1 (a TM + b TK) + b K1 TM along j.
+constexpr int TT_I = 64, TT_J = 8, TT_THREADS = 256;
+
+template <int NQ, bool HASK>
+__global__ __launch_bounds__(TT_THREADS) void k_tensor_mk(int n, int p, const double* __restrict__ M1,
+                                                          const double* __restrict__ K1, double a, double b,
+                                                          const double* __restrict__ X, int64_t ldx,
+                                                          double* __restrict__ Y, int64_t ldy,
+                                                          const double* __restrict__ Z, int64_t ldz, double c) {
+  extern __shared__ double sm[];
+  const int w = 2 * p + 1;
+  const int hx = TT_I + 2 * p, hy = TT_J + 2 * p;
+  const int i0 = blockIdx.x * TT_I, j0 = blockIdx.y * TT_J;
+  double* xs = sm;                          // [hy][hx][NQ]
+  double* tm = xs + (size_t)hy * hx * NQ;   // [hy][TT_I][NQ]
+  double* tk = tm + (size_t)hy * TT_I * NQ; // [hy][TT_I][NQ] (HASK)
+  for (int idx = threadIdx.x; idx < hy * hx; idx += TT_THREADS) {
+    const int jj = j0 - p + idx / hx, ii = i0 - p + idx % hx;
+    const bool in = jj >= 0 && jj < n && ii >= 0 && ii < n;
+    const int64_t d = (int64_t)jj * n + ii;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) xs[idx * NQ + q] = in ? X[d + q * ldx] : 0.0;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < hy * TT_I; idx += TT_THREADS) {
+    const int r = idx / TT_I, ci = idx % TT_I, i = min(i0 + ci, n - 1);
+    const double* mb = M1 + (int64_t)i * w;
+    const double* kb = K1 + (int64_t)i * w;
+    const double* xr = xs + ((size_t)r * hx + ci) * NQ;   // column i - p of the halo row
+    double sm_[NQ], sk_[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) { sm_[q] = 0.0; sk_[q] = 0.0; }
+    for (int o = 0; o < w; ++o) {
+      const double mv = mb[o], kv = HASK ? kb[o] : 0.0;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        sm_[q] += mv * xr[o * NQ + q];
+        if (HASK) sk_[q] += kv * xr[o * NQ + q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      tm[idx * NQ + q] = sm_[q];
+      if (HASK) tk[idx * NQ + q] = sk_[q];
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < TT_J * TT_I; idx += TT_THREADS) {
+    const int jr = idx / TT_I, ci = idx % TT_I;
+    const int i = i0 + ci, j = j0 + jr;
+    if (i >= n || j >= n) continue;
+    const double* mb = M1 + (int64_t)j * w;
+    const double* kb = K1 + (int64_t)j * w;
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    for (int o = 0; o < w; ++o) {
+      const size_t t = ((size_t)(jr + o) * TT_I + ci) * NQ;   // row j - p + o of the halo
+      const double mv = mb[o];
+      if (HASK) {
+        const double kv = kb[o], am = a * mv + b * kv, bm = b * mv;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] += am * tm[t + q] + bm * tk[t + q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] += mv * tm[t + q];
+      }
+    }
+    const int64_t d = (int64_t)j * n + i;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double v = HASK ? acc[q] : a * acc[q];
+      if (Z) v += c * Z[d + q * ldz];
+      Y[d + q * ldy] = v;
+    }
+  }
+}
+
+void launch_tensor_mk(const DevSpace& s, const double* M1, const double* K1, int nq, double a, double b,
+                      const double* X, int64_t ldx, double* Y, int64_t ldy, const double* Z, int64_t ldz, double c,
+                      hipStream_t st) {
+  const int n = s.n, p = s.p;
+  if (n <= 0) return;
+  const dim3 grid((n + TT_I - 1) / TT_I, (n + TT_J - 1) / TT_J);
+  const bool hask = b != 0.0;
+  const size_t shm_x = (size_t)(TT_J + 2 * p) * (TT_I + 2 * p), shm_t = (size_t)(TT_J + 2 * p) * TT_I;
+#define RIGA_TMK(NQ)                                                                                           \
+  do {                                                                                                         \
+    const size_t shm = (shm_x + (hask ? 2 : 1) * shm_t) * NQ * sizeof(double);                                 \
+    if (hask)                                                                                                  \
+      hipLaunchKernelGGL((k_tensor_mk<NQ, true>), grid, dim3(TT_THREADS), shm, st, n, p, M1, K1, a, b, X, ldx, Y, \
+                         ldy, Z, ldz, c);                                                                      \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_tensor_mk<NQ, false>), grid, dim3(TT_THREADS), shm, st, n, p, M1, K1, a, b, X, ldx,  \
+                         Y, ldy, Z, ldz, c);                                                                   \
+  } while (0)
+  switch (nq) {
+    case 1: RIGA_TMK(1); break;
+    case 2: RIGA_TMK(2); break;
+    case 3: RIGA_TMK(3); break;
+    default: RIGA_TMK(4); break;
+  }
+#undef RIGA_TMK
+}
+
+// ---------------------------------------------------------------------------
 // Gram--Schmidt update Z[:, q] -= sum_c A[:, c] h[c][q] for up to three
 // (A, Z) pairs sharing h (upper part, lower part, and M times the lower part).
 constexpr int UPD_THREADS = 256;

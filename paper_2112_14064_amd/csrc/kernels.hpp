@@ -57,6 +57,10 @@ void launch_assemble(const DevSpace& s, const double* tabM, const double* tabK,
 // space spaces[q], first row dofbase[q], tables at tabM/tabK + taboff[q],
 // Gauss rule gx[q]/gw[q] (device pointer arrays), damping alpha[q], beta[q],
 // c_elem[q] (may be null); rb: row blocks of at most 256 rows of one problem.
+// Banded 1-D factors of M and K of a space (see k_assemble.hip): M1, K1 hold
+// n (2p + 1) doubles, entry (i, ii) at i (2p + 1) + ii - i + p.
+void launch_band_1d(const DevSpace& s, const double* tabM, const double* tabK, double* M1, double* K1,
+                    hipStream_t st);
 void launch_assemble_b(const int4* rb, int nrb, const DevSpace* spaces, const int64_t* dofbase,
                        const int64_t* taboff, const double* const* gx, const double* const* gw, int n, int max_ne,
                        double* tabM, double* tabK, const double* alpha, const double* beta,
@@ -183,6 +187,15 @@ bool cgs_tile_fits(int nc, int nq);
 int launch_cgs_update_dots(int64_t n, int nc, int nq, const double* h, const double* Vu, const double* Vl,
                            const double* Wl, int64_t lda, double* Zu, double* Zl, double* Zw, int64_t ldz,
                            double* partial, double* out, hipStream_t st);
+// Y = a M X + b K X + c Z on the tensor grid of a space (X[j n + i], nq <= 4
+// columns; Z may be null) by sum factorisation with the banded 1-D factors:
+// per 64 x 8 tile of the grid, T = X M1^T and X K1^T along i, then
+// Y = M1 (a T_M + b T_K) + b K1 T_M along j, all in shared memory.  Reads X
+// with a halo of p rows and columns instead of the stored entries of the
+// 2-D matrices.
+void launch_tensor_mk(const DevSpace& s, const double* M1, const double* K1, int nq, double a, double b,
+                      const double* X, int64_t ldx, double* Y, int64_t ldy, const double* Z, int64_t ldz, double c,
+                      hipStream_t st);
 // Out[i + c ldo] = sum_t In[i + t ldi] Q[t, c] (Q device, kin x kout col-major,
 // kin <= 254), on the FP64 matrix cores.
 void launch_gemm_tall(int64_t n, const double* In, int64_t ldi, int kin, const double* Q, int kout,

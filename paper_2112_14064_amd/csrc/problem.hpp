@@ -39,6 +39,7 @@ struct riga_problem {
   riga::DevTree dt{};
   int* d_level_nodes = nullptr;
   double *d_gx = nullptr, *d_gw = nullptr, *d_tabM = nullptr, *d_tabK = nullptr;
+  double *d_M1 = nullptr, *d_K1 = nullptr;          // banded 1-D factors of M and K (launch_band_1d)
   double *d_K = nullptr, *d_M = nullptr, *d_C = nullptr;
   double* d_A = nullptr;                            // sigma M + C (formed at factor time)
   double *d_L = nullptr, *d_U = nullptr, *d_T = nullptr, *d_upd = nullptr, *d_tmp = nullptr, *d_tmp2 = nullptr;
