@@ -44,6 +44,12 @@ struct riga_batch {
   const double* const* d_gw = nullptr;
   double *d_tabM = nullptr, *d_tabK = nullptr, *d_alpha = nullptr, *d_beta = nullptr;
   const double** d_celem = nullptr;
+  // sum-factorised products: grid tiles of every problem, banded 1-D factors
+  const int4* d_ttiles = nullptr;
+  int nttiles = 0, max_p = 0, max_w = 0;
+  const int64_t* d_bandoff = nullptr;
+  double *d_M1 = nullptr, *d_K1 = nullptr;
+  bool any_field = false;                 // some problem has an element damping field
   bool assembled = false, factored = false;
   riga::BatchDev B{};
   // Krylov workspace
@@ -128,16 +134,23 @@ void enqueue_step(riga_batch* bh, int b, int m, int ldh, hipStream_t st) {
   const int64_t T = B.ntot;
   const int hs = ldh * b;
   riga::launch_gather_b(B, b, bh->Vu, bh->Wl, bh->Xu, bh->Xw, st);
-  // t = (sigma M + C) v_u + M v_l (eq. BlockOperatorVector), sigma M + C formed per problem
-  riga::launch_spmv_ell(fp->d_slabs, fp->nslab, B.spaces, B.dofbase, B.live, b, fp->d_Aell, bh->Xu, T, bh->Tv, T,
-                        bh->Xw, T, 1.0, st);
+  // t = (sigma M + C) v_u + M v_l (eq. BlockOperatorVector): sum-factorised with
+  // sigma M + C = (sigma + alpha) M + beta K, or the per-problem sparse copy of
+  // sigma M + C when a problem carries an element damping field
+  if (bh->any_field)
+    riga::launch_spmv_ell(fp->d_slabs, fp->nslab, B.spaces, B.dofbase, B.live, b, fp->d_Aell, bh->Xu, T, bh->Tv, T,
+                          bh->Xw, T, 1.0, st);
+  else
+    riga::launch_tensor_mk_b(bh->d_ttiles, bh->nttiles, B.spaces, B.dofbase, bh->d_bandoff, bh->d_M1, bh->d_K1,
+                             B.live, B.sig, bh->d_alpha, bh->d_beta, b, bh->max_p, bh->Xu, T, bh->Tv, T, bh->Xw, T,
+                             1.0, st);
   // r_u = -Q^{-1} t, r_l = sigma r_u + v_u (sigma of each node's problem)
   riga::BwdOut o;
   o.xs = bh->Ru; o.ldxs = T; o.neg = 1; o.ldr = T;
   o.rl = bh->Rl; o.v_u = bh->Xu; o.ldv = T;
   sweep(fp, b, bh->Tv, T, o);
-  riga::launch_spmv_ell(fp->d_slabs, fp->nslab, B.spaces, B.dofbase, B.live, b, fp->d_Mell, bh->Rl, T, bh->MRl, T,
-                        nullptr, 0, 0.0, st);
+  riga::launch_tensor_mk_b(bh->d_ttiles, bh->nttiles, B.spaces, B.dofbase, bh->d_bandoff, bh->d_M1, bh->d_K1, B.live,
+                           nullptr, nullptr, nullptr, b, bh->max_p, bh->Rl, T, bh->MRl, T, nullptr, 0, 0.0, st);
   // classical Gram--Schmidt twice against V[:, 0:k+b], B-inner products; where
   // the tile kernels fit, the pass 1 update also forms the pass 2 products
   if (riga::cgs_tile_fits(m + b, b)) {
@@ -294,6 +307,25 @@ riga_status riga_batch_create(riga_batch** out, int n, const riga_mesh* meshes, 
     std::vector<int64_t> nzb(n + 1);
     for (int i = 0; i <= n; ++i) nzb[i] = fp->plan.rowptr[bh->dof_base[i]];
     bh->d_nzbase = fp->upload(nzb);
+    {
+      std::vector<int4> tiles;
+      std::vector<int64_t> bo(n);
+      int64_t boff = 0;
+      for (int i = 0; i < n; ++i) {
+        const riga::Space1D& S = bh->plans[i].sp;
+        bo[i] = boff;
+        boff += (int64_t)S.n * (2 * S.p + 1);
+        bh->max_p = std::max(bh->max_p, S.p);
+        bh->max_w = std::max(bh->max_w, S.n * (2 * S.p + 1));
+        for (int j0 = 0; j0 < S.n; j0 += riga::TENSOR_TILE_J)
+          for (int i0 = 0; i0 < S.n; i0 += riga::TENSOR_TILE_I) tiles.push_back(int4{i, i0, j0, 0});
+      }
+      bh->d_ttiles = fp->upload(tiles);
+      bh->nttiles = (int)tiles.size();
+      bh->d_bandoff = fp->upload(bo);
+      bh->d_M1 = fp->dalloc<double>((size_t)boff);
+      bh->d_K1 = fp->dalloc<double>((size_t)boff);
+    }
     fp->dt.inst = fp->upload(fp->node_inst);
     fp->dt.spaces = B.spaces;
     fp->dt.dofbase = B.dofbase;
@@ -345,7 +377,10 @@ riga_status riga_batch_assemble(riga_batch* bh, const riga_damping* damping) {
     riga::launch_assemble_b(bh->B.rb, bh->B.nrb, bh->B.spaces, bh->B.dofbase, bh->d_taboff, bh->d_gx, bh->d_gw, n,
                             bh->max_ne, bh->d_tabM, bh->d_tabK, bh->d_alpha, bh->d_beta, bh->d_celem, fp->d_K,
                             fp->d_M, fp->d_C, st);
-    riga::launch_csr_to_ell(fp->d_slabs, fp->nslab, fp->ds.rowptr, fp->d_M, fp->d_Mell, st);
+    riga::launch_band_1d_b(bh->B.spaces, n, bh->max_w, bh->d_taboff, bh->d_tabM, bh->d_tabK, bh->d_bandoff, bh->d_M1,
+                           bh->d_K1, st);
+    bh->any_field = false;
+    for (int i = 0; i < n; ++i) bh->any_field = bh->any_field || bh->celem[i] != nullptr;
     ck(hipEventRecord(fp->ev1, st));
     // 1-norms per problem (largest absolute row sums): one launch over the row
     // blocks of the forest, one synchronisation
@@ -388,7 +423,9 @@ riga_status riga_batch_factor(riga_batch* bh, const double* sigmas, int64_t* bad
     int64_t bad = -1;
     riga_status rc = factor_all(fp, 1.0, &bad);
     riga::launch_combine_b(bh->n, bh->d_nzbase, fp->plan.nnz, bh->B.sig, fp->d_M, fp->d_C, fp->d_A, bh->user_st);
-    riga::launch_csr_to_ell(fp->d_slabs, fp->nslab, fp->ds.rowptr, fp->d_A, fp->d_Aell, bh->user_st);
+    // the operator's sparse copy is needed only with an element damping field
+    if (bh->any_field)
+      riga::launch_csr_to_ell(fp->d_slabs, fp->nslab, fp->ds.rowptr, fp->d_A, fp->d_Aell, bh->user_st);
     bh->stats.t_factor_ms = fp->stats.t_factor_ms;
     if (rc == RIGA_ERR_NOT_SPD && bad >= 0) {
       const int i = (int)(std::upper_bound(bh->dof_base.begin(), bh->dof_base.end(), bad) - bh->dof_base.begin()) - 1;
@@ -445,8 +482,9 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
     ck(hipMemsetAsync(bh->H, 0, sizeof(double) * (size_t)n * ldh * ldh, st));
     riga::launch_random_fill(bh->Ru, T, b, T, opt->seed * 2 + 1, st);
     riga::launch_random_fill(bh->Rl, T, b, T, opt->seed * 2 + 2, st);
-    riga::launch_spmv_ell(fp->d_slabs, fp->nslab, B.spaces, B.dofbase, B.live, b, fp->d_Mell, bh->Rl, T, bh->MRl, T,
-                        nullptr, 0, 0.0, st);
+    riga::launch_tensor_mk_b(bh->d_ttiles, bh->nttiles, B.spaces, B.dofbase, bh->d_bandoff, bh->d_M1, bh->d_K1,
+                             B.live, nullptr, nullptr, nullptr, b, bh->max_p, bh->Rl, T, bh->MRl, T, nullptr, 0, 0.0,
+                             st);
     riga::launch_dots_b(B, 0, b, false, bh->Ru, bh->MRl, b, bh->Ru, bh->Rl, bh->G, b * b, st);
     riga::launch_block_normalize_b(B, false, 0, b, nullptr, nullptr, 0, bh->G, nullptr, ldh, bh->Rinv, st);
     riga::launch_gemm3_b(B, false, 0, b, bh->Rinv, bh->Ru, bh->Vu, bh->Rl, bh->Vl, bh->MRl, bh->Wl, st);

@@ -242,6 +242,23 @@ void launch_band_1d(const DevSpace& s, const double* tabM, const double* tabK, d
   hipLaunchKernelGGL(k_band_1d, dim3((total + 255) / 256), dim3(256), 0, st, s, tabM, tabK, M1, K1);
 }
 
+__global__ void k_band_1d_b(const DevSpace* __restrict__ spaces, const int64_t* __restrict__ taboff,
+                            const double* __restrict__ tabM, const double* __restrict__ tabK,
+                            const int64_t* __restrict__ bandoff, double* __restrict__ M1, double* __restrict__ K1) {
+  const int q = blockIdx.y;
+  const DevSpace sp = spaces[q];
+  const int w = 2 * sp.p + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < sp.n * w)
+    band_entry(sp, t / w, t % w, tabM + taboff[q], tabK + taboff[q], M1 + bandoff[q], K1 + bandoff[q]);
+}
+
+void launch_band_1d_b(const DevSpace* spaces, int n, int max_w, const int64_t* taboff, const double* tabM,
+                      const double* tabK, const int64_t* bandoff, double* M1, double* K1, hipStream_t st) {
+  hipLaunchKernelGGL(k_band_1d_b, dim3((max_w + 255) / 256, n), dim3(256), 0, st, spaces, taboff, tabM, tabK, bandoff,
+                     M1, K1);
+}
+
 void launch_assemble(const DevSpace& s, const double* tabM, const double* tabK,
                      double alpha, double beta, const double* c_elem,
                      double* K, double* M, double* C, int64_t ndof, hipStream_t st) {

@@ -342,16 +342,16 @@ void launch_dots(int64_t n, int nc, const double* Au, const double* Al, int64_t 
 // then Y = M1 (a TM + b TK) + b K1 TM along j.
 constexpr int TT_I = 64, TT_J = 8, TT_THREADS = 256;
 
+// One tile (i0, j0) of one grid; sm: shared memory for the halo and the
+// partial products (sized for the largest degree of the launch).
 template <int NQ, bool HASK>
-__global__ __launch_bounds__(TT_THREADS) void k_tensor_mk(int n, int p, const double* __restrict__ M1,
-                                                          const double* __restrict__ K1, double a, double b,
-                                                          const double* __restrict__ X, int64_t ldx,
-                                                          double* __restrict__ Y, int64_t ldy,
-                                                          const double* __restrict__ Z, int64_t ldz, double c) {
-  extern __shared__ double sm[];
+__device__ __forceinline__ void tensor_tile(int n, int p, int i0, int j0, const double* __restrict__ M1,
+                                            const double* __restrict__ K1, double a, double b,
+                                            const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
+                                            int64_t ldy, const double* __restrict__ Z, int64_t ldz, double c,
+                                            double* sm) {
   const int w = 2 * p + 1;
   const int hx = TT_I + 2 * p, hy = TT_J + 2 * p;
-  const int i0 = blockIdx.x * TT_I, j0 = blockIdx.y * TT_J;
   double* xs = sm;                          // [hy][hx][NQ]
   double* tm = xs + (size_t)hy * hx * NQ;   // [hy][TT_I][NQ]
   double* tk = tm + (size_t)hy * TT_I * NQ; // [hy][TT_I][NQ] (HASK)
@@ -417,6 +417,75 @@ __global__ __launch_bounds__(TT_THREADS) void k_tensor_mk(int n, int p, const do
   }
 }
 
+template <int NQ, bool HASK>
+__global__ __launch_bounds__(TT_THREADS) void k_tensor_mk(int n, int p, const double* __restrict__ M1,
+                                                          const double* __restrict__ K1, double a, double b,
+                                                          const double* __restrict__ X, int64_t ldx,
+                                                          double* __restrict__ Y, int64_t ldy,
+                                                          const double* __restrict__ Z, int64_t ldz, double c) {
+  extern __shared__ double sm[];
+  tensor_tile<NQ, HASK>(n, p, blockIdx.x * TT_I, blockIdx.y * TT_J, M1, K1, a, b, X, ldx, Y, ldy, Z, ldz, c, sm);
+}
+
+// Every live problem of a forest: tile t = {problem, i0, j0, 0}; the problem's
+// rows start at dofbase, its bands at bandoff; a = sig + alpha, b = beta, or
+// with sig null a = 1, b = 0.
+template <int NQ, bool HASK>
+__global__ __launch_bounds__(TT_THREADS) void k_tensor_mk_b(const int4* __restrict__ tiles,
+                                                            const DevSpace* __restrict__ spaces,
+                                                            const int64_t* __restrict__ dofbase,
+                                                            const int64_t* __restrict__ bandoff,
+                                                            const double* __restrict__ M1,
+                                                            const double* __restrict__ K1,
+                                                            const unsigned char* __restrict__ live,
+                                                            const double* __restrict__ sig,
+                                                            const double* __restrict__ alpha,
+                                                            const double* __restrict__ beta,
+                                                            const double* __restrict__ X, int64_t ldx,
+                                                            double* __restrict__ Y, int64_t ldy,
+                                                            const double* __restrict__ Z, int64_t ldz, double c) {
+  extern __shared__ double sm[];
+  const int4 tl = tiles[blockIdx.x];
+  const int q = tl.x;
+  if (live != nullptr && !live[q]) return;   // the whole workgroup leaves together
+  const int n = spaces[q].n, p = spaces[q].p;
+  const int64_t base = dofbase[q], bo = bandoff[q];
+  const double a = sig ? sig[q] + alpha[q] : 1.0, b = sig ? beta[q] : 0.0;
+  tensor_tile<NQ, HASK>(n, p, tl.y, tl.z, M1 + bo, K1 + bo, a, b, X + base, ldx, Y + base, ldy,
+                        Z ? Z + base : nullptr, ldz, c, sm);
+}
+
+size_t tensor_shm(int max_p, int nq, bool hask) {
+  const size_t shm_x = (size_t)(TT_J + 2 * max_p) * (TT_I + 2 * max_p), shm_t = (size_t)(TT_J + 2 * max_p) * TT_I;
+  return (shm_x + (hask ? 2 : 1) * shm_t) * nq * sizeof(double);
+}
+
+void launch_tensor_mk_b(const int4* tiles, int ntiles, const DevSpace* spaces, const int64_t* dofbase,
+                        const int64_t* bandoff, const double* M1, const double* K1, const unsigned char* live,
+                        const double* sig, const double* alpha, const double* beta, int nq, int max_p,
+                        const double* X, int64_t ldx, double* Y, int64_t ldy, const double* Z, int64_t ldz,
+                        double c, hipStream_t st) {
+  if (ntiles <= 0) return;
+  const bool hask = sig != nullptr;
+#define RIGA_TMKB(NQ)                                                                                          \
+  do {                                                                                                         \
+    const size_t shm = tensor_shm(max_p, NQ, hask);                                                            \
+    if (hask)                                                                                                  \
+      hipLaunchKernelGGL((k_tensor_mk_b<NQ, true>), dim3(ntiles), dim3(TT_THREADS), shm, st, tiles, spaces,      \
+                         dofbase, bandoff, M1, K1, live, sig, alpha, beta, X, ldx, Y, ldy, Z, ldz, c);         \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_tensor_mk_b<NQ, false>), dim3(ntiles), dim3(TT_THREADS), shm, st, tiles, spaces,     \
+                         dofbase, bandoff, M1, K1, live, sig, alpha, beta, X, ldx, Y, ldy, Z, ldz, c);         \
+  } while (0)
+  switch (nq) {
+    case 1: RIGA_TMKB(1); break;
+    case 2: RIGA_TMKB(2); break;
+    case 3: RIGA_TMKB(3); break;
+    default: RIGA_TMKB(4); break;
+  }
+#undef RIGA_TMKB
+}
+
 void launch_tensor_mk(const DevSpace& s, const double* M1, const double* K1, int nq, double a, double b,
                       const double* X, int64_t ldx, double* Y, int64_t ldy, const double* Z, int64_t ldz, double c,
                       hipStream_t st) {
@@ -424,10 +493,9 @@ void launch_tensor_mk(const DevSpace& s, const double* M1, const double* K1, int
   if (n <= 0) return;
   const dim3 grid((n + TT_I - 1) / TT_I, (n + TT_J - 1) / TT_J);
   const bool hask = b != 0.0;
-  const size_t shm_x = (size_t)(TT_J + 2 * p) * (TT_I + 2 * p), shm_t = (size_t)(TT_J + 2 * p) * TT_I;
 #define RIGA_TMK(NQ)                                                                                           \
   do {                                                                                                         \
-    const size_t shm = (shm_x + (hask ? 2 : 1) * shm_t) * NQ * sizeof(double);                                 \
+    const size_t shm = tensor_shm(p, NQ, hask);                                                                \
     if (hask)                                                                                                  \
       hipLaunchKernelGGL((k_tensor_mk<NQ, true>), grid, dim3(TT_THREADS), shm, st, n, p, M1, K1, a, b, X, ldx, Y, \
                          ldy, Z, ldz, c);                                                                      \

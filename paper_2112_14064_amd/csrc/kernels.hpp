@@ -61,6 +61,10 @@ void launch_assemble(const DevSpace& s, const double* tabM, const double* tabK,
 // n (2p + 1) doubles, entry (i, ii) at i (2p + 1) + ii - i + p.
 void launch_band_1d(const DevSpace& s, const double* tabM, const double* tabK, double* M1, double* K1,
                     hipStream_t st);
+// Bands of every problem of a forest: problem q's tables at taboff[q], its
+// bands at bandoff[q] (max_w: the largest n (2p + 1)).
+void launch_band_1d_b(const DevSpace* spaces, int n, int max_w, const int64_t* taboff, const double* tabM,
+                      const double* tabK, const int64_t* bandoff, double* M1, double* K1, hipStream_t st);
 void launch_assemble_b(const int4* rb, int nrb, const DevSpace* spaces, const int64_t* dofbase,
                        const int64_t* taboff, const double* const* gx, const double* const* gw, int n, int max_ne,
                        double* tabM, double* tabK, const double* alpha, const double* beta,
@@ -196,6 +200,18 @@ int launch_cgs_update_dots(int64_t n, int nc, int nq, const double* h, const dou
 void launch_tensor_mk(const DevSpace& s, const double* M1, const double* K1, int nq, double a, double b,
                       const double* X, int64_t ldx, double* Y, int64_t ldy, const double* Z, int64_t ldz, double c,
                       hipStream_t st);
+// Grid tiles of the sum-factorised product (64 along i, 8 along j).
+constexpr int TENSOR_TILE_I = 64, TENSOR_TILE_J = 8;
+// Forest form of launch_tensor_mk: tiles[t] = {problem, i0, j0, 0} over the
+// grids of every problem (problem q's rows start at dofbase[q], its bands at
+// M1 / K1 + bandoff[q]); Y = (sig + alpha) M X + beta K X + c Z per problem, or
+// with sig null Y = M X + c Z.  Problems with live[q] == 0 are skipped; max_p
+// bounds the degrees (shared memory size).
+void launch_tensor_mk_b(const int4* tiles, int ntiles, const DevSpace* spaces, const int64_t* dofbase,
+                        const int64_t* bandoff, const double* M1, const double* K1, const unsigned char* live,
+                        const double* sig, const double* alpha, const double* beta, int nq, int max_p,
+                        const double* X, int64_t ldx, double* Y, int64_t ldy, const double* Z, int64_t ldz,
+                        double c, hipStream_t st);
 // Out[i + c ldo] = sum_t In[i + t ldi] Q[t, c] (Q device, kin x kout col-major,
 // kin <= 254), on the FP64 matrix cores.
 void launch_gemm_tall(int64_t n, const double* In, int64_t ldi, int kin, const double* Q, int kout,
