@@ -63,7 +63,7 @@ def run_config(torch, riga, P, steps, warmup, block):
         "ms_per_step": ms,
         "eigenpairs_per_s": good * 1e3 / ms,
         "pairs_ok": good, "status": int(st),
-        "factor_ms": stats["t_factor_ms"], "eigs_ms": stats["t_eigs_ms"],
+        "factor_ms": stats["t_factor_ms"], "eigs_ms": stats["t_eigs_ms"], "eigs_host_ms": stats["t_host_ms"],
         "factor_gflops_dense": info["factor_flops_dense"] / (stats["t_factor_ms"] * 1e-3) / 1e9,
         "n_it": int(stats["n_it"]), "n_fb": int(stats["n_fb"]), "n_mv": int(stats["n_mv"]),
         "n_vv": int(stats["n_vv"]),
@@ -199,6 +199,7 @@ def batching_form(torch, riga, W, steps=2):
                        "beta~U[0,0.02], sigma~U[0.5,4] (seed 1), 8 pairs each, subspace 20",
            "total_dofs": int(B.total), "ms_per_step": ms, "eigenpairs_per_s": good * 1e3 / ms, "pairs_ok": good,
            "assemble_ms": s["t_assemble_ms"], "factor_ms": s["t_factor_ms"], "eigs_ms": s["t_eigs_ms"],
+           "eigs_host_ms": s["t_host_ms"],
            "lockstep_cycles": int(s["n_it"]), "resolved_one_by_one": int(s["n_resolved"]),
            "max_eta": float(eta.max()), "autotune_forest_solve_ms": {"before": before, "after": after}}
     B.close()

@@ -124,6 +124,9 @@ typedef struct {
   int64_t n_ir;         /* FP64 refinement sweeps of the mixed factor (per vector;
                            each is one residual product and one FP32 solve)    */
   double t_assemble_ms, t_factor_ms, t_eigs_ms;  /* last call, device time     */
+  double t_host_ms;     /* host wall time of the last eigensolve between its
+                           device steps: projected-matrix downloads, Ritz
+                           values and restarts, uploads (the device waits)    */
 } riga_stats_t;
 
 /* Build the discretisation and the nested-dissection plan on the host and

@@ -1227,6 +1227,7 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     KrylovRun kr{h, N, b, m, nev, maxit, ldh, tol};
     int it = 0;
     bool converged = false;
+    double t_host = 0.0;   // host Ritz and restart work, the device idle
     riga::KsCycle cyc;
     uint64_t step_seed = opt->seed * 1000003u + 5;
     // First attempt on the fast path; a breakdown reported by the device sends
@@ -1278,10 +1279,14 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
         if (flag) { broke = true; break; }
       }
       const int k = kr.k;
+      const auto th0 = std::chrono::steady_clock::now();   // the device waits from here
       if (riga::ks_ritz(kr.H, ldh, k, b, nev, tol, cyc) != 0) throw HipError{hipErrorUnknown};
       ++it;
-      if (cyc.nconv == cyc.nw) { converged = true; break; }
-      if (it >= maxit) break;
+      if (cyc.nconv == cyc.nw || it >= maxit) {
+        t_host += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - th0).count();
+        converged = cyc.nconv == cyc.nw;
+        break;
+      }
       // --- Krylov--Schur restart: keep the nearest Ritz values ------------------
       riga::ks_restart(kr.H, ldh, k, b, m, nev, opt->keep, cyc);
       const int r = cyc.r;
@@ -1300,6 +1305,7 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
       riga::launch_gemm_tall(N, h->Wl, N, kin, dQ, kout, h->Wl2, N, h->st);
       std::swap(h->Vu, h->Vu2); std::swap(h->Vl, h->Vl2); std::swap(h->Wl, h->Wl2);
       kr.H = cyc.Hn;
+      t_host += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - th0).count();
       if (kr.fast) {
         std::memcpy(stage + 2 * hl2, kr.H.data(), sizeof(double) * hl2);
         ck(hipMemcpyAsync(h->d_H, stage + 2 * hl2, sizeof(double) * hl2, hipMemcpyHostToDevice, h->st));
@@ -1408,6 +1414,7 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     h->stats.t_eigs_ms = ms;
     h->stats.n_it = it;
     h->stats.n_fb = kr.n_fb;
+    h->stats.t_host_ms = t_host;
     h->stats.n_ir = h->mixed ? kr.n_fb * h->ir_sweeps : 0;
     h->stats.n_mv = kr.n_mv + h->stats.n_ir;   // one residual product per refinement sweep
     h->stats.n_vv = kr.n_vv;

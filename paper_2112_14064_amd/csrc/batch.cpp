@@ -10,6 +10,7 @@
 // the whole cycle; the host only sees the projected matrices at cycle ends,
 // where each problem gets its own Ritz values, convergence test and restart.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -59,6 +60,7 @@ struct riga_batch {
   double *h1 = nullptr, *h2 = nullptr, *G = nullptr, *Rinv = nullptr, *H = nullptr, *Qd = nullptr;
   double *P = nullptr, *MP = nullptr, *CP = nullptr, *KP = nullptr, *part = nullptr, *dlam = nullptr;
   int *kin = nullptr, *kout = nullptr;
+  int *kin_f = nullptr, *kout_f = nullptr;   // Ritz-vector products of the problems that finish
   int64_t* qoff = nullptr;
   std::map<const double*, hipGraphExec_t> graphs;  // one block step per basis buffer
   int graph_b = 0, graph_m = 0;                    // step shape the graphs were captured for
@@ -101,6 +103,7 @@ void ensure_workspace(riga_batch* bh, int ldh, int b) {
                     bh->part, bh->dlam, bh->B.partial})
     fp->dfree(p);
   fp->dfree(bh->kin); fp->dfree(bh->kout); fp->dfree(bh->qoff);
+  fp->dfree(bh->kin_f); fp->dfree(bh->kout_f);
   ldh = std::max(ldh, bh->kw_ldh);
   b = std::max(b, bh->kw_b);
   const int64_t T = bh->B.ntot;
@@ -120,6 +123,8 @@ void ensure_workspace(riga_batch* bh, int ldh, int b) {
   bh->dlam = fp->dalloc<double>((size_t)n * 2 * ldh);
   bh->kin = fp->dalloc<int>(n);
   bh->kout = fp->dalloc<int>(n);
+  bh->kin_f = fp->dalloc<int>(n);
+  bh->kout_f = fp->dalloc<int>(n);
   bh->qoff = fp->dalloc<int64_t>(n);
   bh->B.pstride = ldh * 4;
   bh->B.partial = fp->dalloc<double>((size_t)bh->B.ndb * bh->B.pstride);
@@ -499,7 +504,7 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
     // 2 ldh^2 combination coefficients, the new projected matrices and the
     // small per-problem arrays
     const size_t nh = (size_t)n * hl, nq2 = (size_t)n * 2 * hl;
-    double* const pin = fp->pinned(nh + n + nq2 + nh + 4 * (size_t)n + 8);
+    double* const pin = fp->pinned(nh + n + nq2 + nh + 5 * (size_t)n + 8);
     double* const dnH = pin;
     const int* const dnFlag = reinterpret_cast<const int*>(pin + nh);
     double* const Qh = pin + nh + n;
@@ -509,8 +514,11 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
     int64_t* const hqoff = reinterpret_cast<int64_t*>(Hh + nh + n);
     int* const hkc = reinterpret_cast<int*>(Hh + nh + 2 * (size_t)n);
     unsigned char* const hlive = reinterpret_cast<unsigned char*>(Hh + nh + 3 * (size_t)n);
+    int* const hkin_f = reinterpret_cast<int*>(Hh + nh + 4 * (size_t)n);   // n ints each
+    int* const hkout_f = hkin_f + n;
     int64_t n_fb = 0;
     int cycles = 0;
+    double t_host = 0.0;
     for (;;) {
       int steps = 0;
       for (int i = 0; i < n; ++i)
@@ -539,6 +547,7 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
       ck(hipMemcpyAsync(dnH, bh->H, sizeof(double) * nh, hipMemcpyDeviceToHost, st));
       ck(hipMemcpyAsync((void*)dnFlag, B.flag, sizeof(int) * n, hipMemcpyDeviceToHost, st));
       ck(hipStreamSynchronize(st));
+      const auto th0 = std::chrono::steady_clock::now();   // the device waits from here
       std::vector<int> newstate(state);
       parallel_for(n, [&](int i) {
         if (state[i] != ACTIVE) return;
@@ -562,60 +571,63 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
         if (newstate[i] == CONVERGED || newstate[i] == MAXIT) fin.push_back(i);
         else if (newstate[i] == ACTIVE) rst.push_back(i);
       }
-      if (!fin.empty()) {
-        std::fill(hkout, hkout + n, 0);
-        int max_kin = 1, max_kout = 1;
-        for (int i : fin) {
-          const int k = kend[i], nw = cyc[i].nw;
-          double* q = Qh + (size_t)i * 2 * hl;
-          for (int j = 0; j < nw; ++j)
-            for (int c = 0; c < k; ++c) {
-              const cplx y = cyc[i].Y[c + (size_t)cyc[i].wanted[j] * k];
-              q[c + (size_t)j * k] = y.real();
-              q[c + (size_t)(nw + j) * k] = y.imag();
-            }
-          hkin[i] = k; hkout[i] = 2 * nw; hqoff[i] = (int64_t)i * 2 * hl;
-          max_kin = std::max(max_kin, k);
-          max_kout = std::max(max_kout, 2 * nw);
-        }
-        ck(hipMemcpyAsync(bh->Qd, Qh, sizeof(double) * nq2, hipMemcpyHostToDevice, st));
-        ck(hipMemcpyAsync(bh->kin, hkin, sizeof(int) * n, hipMemcpyHostToDevice, st));
-        ck(hipMemcpyAsync(bh->kout, hkout, sizeof(int) * n, hipMemcpyHostToDevice, st));
-        ck(hipMemcpyAsync(bh->qoff, hqoff, sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
-        riga::launch_gemm_tall_b(B, bh->kin, bh->kout, bh->qoff, bh->Qd, max_kin, max_kout, bh->Vu, bh->P, st);
-        ck(hipStreamSynchronize(st));   // Qh and the small arrays are staged again below
+      // Finished problems' Ritz vectors and the others' restart combinations go to
+      // disjoint per-problem slots of one staging area and one upload; the
+      // problems' products are queued (Ritz vectors first: they read the basis
+      // the restart replaces) and the next cycle follows them in stream order.
+      // The staging area is rewritten only after the next cycle's download has
+      // been waited for, so no wait is needed here.
+      std::fill(hkout_f, hkout_f + n, 0);
+      std::fill(hkout, hkout + n, 0);
+      std::fill(Hh, Hh + nh, 0.0);
+      int max_kin_f = 1, max_kout_f = 1, max_kin = 1, max_kout = 1;
+      for (int i = 0; i < n; ++i) hqoff[i] = (int64_t)i * 2 * hl;
+      for (int i : fin) {
+        const int k = kend[i], nw = cyc[i].nw;
+        double* q = Qh + (size_t)i * 2 * hl;
+        for (int j = 0; j < nw; ++j)
+          for (int c = 0; c < k; ++c) {
+            const cplx y = cyc[i].Y[c + (size_t)cyc[i].wanted[j] * k];
+            q[c + (size_t)j * k] = y.real();
+            q[c + (size_t)(nw + j) * k] = y.imag();
+          }
+        hkin_f[i] = k; hkout_f[i] = 2 * nw;
+        max_kin_f = std::max(max_kin_f, k);
+        max_kout_f = std::max(max_kout_f, 2 * nw);
       }
       state = newstate;
-      if (rst.empty()) break;
       // restart: V_new = [V_k Qk, V_{k:k+b}] per problem, new H, k = r
-      std::fill(hkout, hkout + n, 0);
-      int max_kin = 1, max_kout = 1;
-      std::fill(Hh, Hh + nh, 0.0);
       for (int i : rst) {
         const riga::KsCycle& c = cyc[i];
         const int kin = kend[i] + b, kout = c.r + b;
         std::memcpy(Qh + (size_t)i * 2 * hl, c.Qe.data(), c.Qe.size() * sizeof(double));
-        hkin[i] = kin; hkout[i] = kout; hqoff[i] = (int64_t)i * 2 * hl;
+        hkin[i] = kin; hkout[i] = kout;
         max_kin = std::max(max_kin, kin);
         max_kout = std::max(max_kout, kout);
         std::memcpy(Hh + (size_t)i * hl, c.Hn.data(), hl * sizeof(double));
         kc[i] = c.r;
       }
       for (int i = 0; i < n; ++i) live[i] = state[i] == ACTIVE ? 1 : 0;
+      std::memcpy(hkc, kc.data(), sizeof(int) * n);
+      std::memcpy(hlive, live.data(), n);
+      t_host += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - th0).count();
       ck(hipMemcpyAsync(bh->Qd, Qh, sizeof(double) * nq2, hipMemcpyHostToDevice, st));
+      ck(hipMemcpyAsync(bh->qoff, hqoff, sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
+      if (!fin.empty()) {
+        ck(hipMemcpyAsync(bh->kin_f, hkin_f, sizeof(int) * n, hipMemcpyHostToDevice, st));
+        ck(hipMemcpyAsync(bh->kout_f, hkout_f, sizeof(int) * n, hipMemcpyHostToDevice, st));
+        riga::launch_gemm_tall_b(B, bh->kin_f, bh->kout_f, bh->qoff, bh->Qd, max_kin_f, max_kout_f, bh->Vu, bh->P, st);
+      }
+      if (rst.empty()) break;
       ck(hipMemcpyAsync(bh->kin, hkin, sizeof(int) * n, hipMemcpyHostToDevice, st));
       ck(hipMemcpyAsync(bh->kout, hkout, sizeof(int) * n, hipMemcpyHostToDevice, st));
-      ck(hipMemcpyAsync(bh->qoff, hqoff, sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
       riga::launch_gemm_tall_b(B, bh->kin, bh->kout, bh->qoff, bh->Qd, max_kin, max_kout, bh->Vu, bh->Vu2, st);
       riga::launch_gemm_tall_b(B, bh->kin, bh->kout, bh->qoff, bh->Qd, max_kin, max_kout, bh->Vl, bh->Vl2, st);
       riga::launch_gemm_tall_b(B, bh->kin, bh->kout, bh->qoff, bh->Qd, max_kin, max_kout, bh->Wl, bh->Wl2, st);
       std::swap(bh->Vu, bh->Vu2); std::swap(bh->Vl, bh->Vl2); std::swap(bh->Wl, bh->Wl2);
-      std::memcpy(hkc, kc.data(), sizeof(int) * n);
-      std::memcpy(hlive, live.data(), n);
       ck(hipMemcpyAsync(bh->H, Hh, sizeof(double) * nh, hipMemcpyHostToDevice, st));
       ck(hipMemcpyAsync(B.kcur, hkc, sizeof(int) * n, hipMemcpyHostToDevice, st));
       ck(hipMemcpyAsync(B.live, hlive, n, hipMemcpyHostToDevice, st));
-      ck(hipStreamSynchronize(st));   // the staging area is rewritten next cycle
     }
     fp->dt.ilive = nullptr;
     // --- eigenpairs of every finished problem ------------------------------------
@@ -730,6 +742,7 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
     bh->stats.n_mv = 3 * n_fb;
     bh->stats.n_vv = 0;
     bh->stats.n_ir = 0;
+    bh->stats.t_host_ms = t_host;
     // problems whose block lost rank are solved again one by one on the
     // host-checked path of the single-problem driver
     for (int i = 0; i < n; ++i) {

@@ -48,7 +48,8 @@ class riga_info_t(C.Structure):
 
 class riga_stats_t(C.Structure):
     _fields_ = [("n_it", C.c_int64), ("n_fb", C.c_int64), ("n_mv", C.c_int64), ("n_vv", C.c_int64),
-                ("n_ir", C.c_int64), ("t_assemble_ms", C.c_double), ("t_factor_ms", C.c_double), ("t_eigs_ms", C.c_double)]
+                ("n_ir", C.c_int64), ("t_assemble_ms", C.c_double), ("t_factor_ms", C.c_double), ("t_eigs_ms", C.c_double),
+                ("t_host_ms", C.c_double)]
 
 
 EXPORTS = ["riga_create", "riga_info", "riga_assemble", "riga_export_csr", "riga_factor", "riga_factor_mixed",
