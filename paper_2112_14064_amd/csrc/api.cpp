@@ -973,6 +973,7 @@ struct KrylovRun {
   int k = 0;               // processed columns
   bool fast = true;        // device-resident normalisation, no host round-trip per step
   bool graphs = true;      // replay captured block steps (fast path only)
+  bool pre = false;        // the next step's operator application is already queued
   int64_t n_fb = 0, n_mv = 0, n_vv = 0;
 
   double& Hat(int r, int c) { return H[r + (size_t)c * ldh]; }
@@ -1134,11 +1135,17 @@ struct KrylovRun {
 
   // One block step on the device: S applied to V[:, k:k+b], CGS2 against
   // V[:, 0:k+b], device normalisation into V[:, k+b:k+2b] and H.
-  void enqueue_step_device() {
+  // The operator applied to the basis block at column kb (and M to its lower
+  // part): Ru, Rl, MRl.
+  void enqueue_apply(int kb) {
     const int64_t n = N;
-    const size_t o = (size_t)k * n;
+    const size_t o = (size_t)kb * n;
     apply_block(h, b, h->Vu + o, h->Wl + o, n, h->Ru, h->Rl, h->Tv);
     riga::launch_tensor_mk(h->ds, h->d_M1, h->d_K1, b, 1.0, 0.0, h->Rl, n, h->MRl, n, nullptr, 0, 0.0, h->st);
+  }
+
+  void enqueue_step_device() {
+    if (!pre) enqueue_apply(k);
     orthonormalize_device(k + b, h->d_H, k);
   }
 
@@ -1148,7 +1155,7 @@ struct KrylovRun {
     const int nc = k + b;
     if (fast) {
       if (graphs) {
-        auto key = std::make_tuple(k, b, (const double*)h->Vu);
+        auto key = std::make_tuple(k, b, (const double*)h->Vu, pre ? 1 : 0);
         auto it = h->graphs.find(key);
         if (it == h->graphs.end()) {
           ck(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
@@ -1165,6 +1172,7 @@ struct KrylovRun {
       } else {
         enqueue_step_device();
       }
+      pre = false;
       n_fb += b;
       n_mv += 3LL * b;
       n_vv += 8LL * nc * b + 2LL * b * b;
@@ -1238,6 +1246,7 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     if (!kr.fast && attempt == 0) attempt = 1;
     kr.H.assign((size_t)ldh * ldh, 0.0);
     kr.n_fb = kr.n_mv = kr.n_vv = 0;
+    kr.pre = false;
     it = 0;
     converged = false;
     step_seed = opt->seed * 1000003u + 5;
@@ -1279,6 +1288,15 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
         if (flag) { broke = true; break; }
       }
       const int k = kr.k;
+      // The first step after a restart applies the operator to the last block,
+      // which the restart keeps unchanged (column r of the new basis is column k
+      // of this one): queue that application now, on the current buffers, so
+      // the device computes it while the host forms the Ritz values.  It is
+      // discarded when the iteration stops here.
+      if (kr.fast) {
+        kr.enqueue_apply(k);
+        kr.pre = true;
+      }
       const auto th0 = std::chrono::steady_clock::now();   // the device waits from here
       if (riga::ks_ritz(kr.H, ldh, k, b, nev, tol, cyc) != 0) throw HipError{hipErrorUnknown};
       ++it;

@@ -91,7 +91,8 @@ struct riga_problem {
     }
     return pin;
   }
-  std::map<std::tuple<int, int, const double*>, hipGraphExec_t> graphs;   // (k, b, V_u)
+  // (k, b, V_u, operator already applied): captured block steps
+  std::map<std::tuple<int, int, const double*, int>, hipGraphExec_t> graphs;
   double graph_sigma = 0.0;
   int64_t graph_key = 0;            // factor mode the captured graphs were recorded for
   // Mixed-precision factor: nodes of height < mixed_thr are FP32 (same offsets
