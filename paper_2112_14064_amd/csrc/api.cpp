@@ -297,6 +297,7 @@ void setup_device(riga_problem* h) {
     h->tpsize = sw.tpsize;
     h->dt.lpoff = h->upload(sw.lpoff);
     h->dt.tpoff = h->upload(sw.tpoff);
+    h->dt.ttri = h->upload(sw.ttri);
     h->d_Lp = h->dalloc<double>(h->lpsize);
     h->d_Tp = h->dalloc<double>(h->tpsize);
     {

@@ -448,14 +448,17 @@ __global__ __launch_bounds__(FT) void k_rtrsm(DevTree t, const int* __restrict__
   }
 }
 
-// Sweep layout of F (rows of T, F[r][c] at T[r * no + c]) with K = 16 bytes /
+// Sweep layouts of F (rows of T, F[r][c] at T[r * no + c]) with K = 16 bytes /
 // element consecutive entries side by side, so that one lane reads K of them
-// with a single 16-byte load:
-//   Lp: columns in groups of K, F[r][gK + s] at Lp[(g nf + r) K + s],
-//       g < ceil(no/K) (forward sweep: lane = row);
-//   Tp: rows in groups of K, F[gK + s][a] at Tp[(g no + a) K + s],
-//       g < ceil(nf/K) (backward sweep: lane = own column a).
-// Padding columns / rows are written as zeros.  64 x 64 tiles through LDS.
+// with a single 16-byte load (kernels.hpp: lp_group, tp_group):
+//   Lp: columns in groups of K, F[r][gK + s] at Lp[(lp_group(g) + r - gK) K + s]
+//       for r >= gK, g < ceil(no/K) (forward sweep: lane = row);
+//   Tp: rows in groups of K, F[gK + s][a] at Tp[(tp_group(g) + a) K + s] for
+//       a < tp_width(g), g < ceil(nf/K) (backward sweep: lane = own column a),
+//       or at Tp[(g no + a) K + s] for every a < no where t.ttri marks the node
+//       as keeping the full rectangle.
+// The entries left out are the zeros of L_oo^{-1} above its diagonal blocks of
+// K; padding columns / rows are written as zeros.  64 x 64 tiles through LDS.
 template <class E>
 __global__ __launch_bounds__(FT) void k_pack(DevTree t, const int* __restrict__ level_nodes,
                                              const E* __restrict__ Tbuf, E* __restrict__ Lp, E* __restrict__ Tp) {
@@ -478,13 +481,20 @@ __global__ __launch_bounds__(FT) void k_pack(DevTree t, const int* __restrict__ 
   for (int idx = threadIdx.x; idx < TB * TB; idx += FT) {
     const int gl = idx / (TB * K), rem = idx % (TB * K), r = rem / K, sl = rem % K;
     const int c = gl * K + sl;
-    if (r0 + r < nf && c0 + c < nop) L[((int64_t)((c0 + c) / K) * nf + r0 + r) * K + sl] = S[r * LDT + c];
+    const int rr = r0 + r, g = (c0 + c) / K;
+    if (rr < nf && c0 + c < nop && rr >= g * K) L[(lp_group(g, nf, K) + rr - g * K) * K + sl] = S[r * LDT + c];
   }
   E* Tq = Tp + t.tpoff[v];
+  const bool tri = t.ttri[v] != 0;
   for (int idx = threadIdx.x; idx < TB * TB; idx += FT) {
     const int gl = idx / (TB * K), rem = idx % (TB * K), c = rem / K, sl = rem % K;
     const int r = gl * K + sl;
-    if (r0 + r < nfp && c0 + c < no) Tq[((int64_t)((r0 + r) / K) * no + c0 + c) * K + sl] = S[r * LDT + c];
+    const int g = (r0 + r) / K, cc = c0 + c;
+    if (tri) {
+      if (r0 + r < nfp && cc < tp_width(g, no, K)) Tq[(tp_group(g, no, K) + cc) * K + sl] = S[r * LDT + c];
+    } else {
+      if (r0 + r < nfp && cc < no) Tq[((int64_t)g * no + cc) * K + sl] = S[r * LDT + c];
+    }
   }
 }
 

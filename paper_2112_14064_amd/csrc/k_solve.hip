@@ -37,15 +37,18 @@ struct Pack {
   typedef E V __attribute__((ext_vector_type(K)));
 };
 
-// One round of a wave: SG group loads g0 .. g0 + SG - 1.  Groups past the
-// end are clamped to the last group (an address of the node) and masked in
-// fma_round: the loads carry no branch, so the compiler can keep the next
-// round in flight while the current one is used.
-template <int SG, class V>
-__device__ __forceinline__ void load_round(V (&a)[SG], const V* p, int g0, int gend, int64_t stride) {
+// One round of a wave: SG group loads g0 .. g0 + SG - 1 of the lane's row
+// (forward) or column (backward), at p[off(g)]: p is the lane's entry of group
+// 0 and off(g) the group's offset, the same for every lane.  Groups past the
+// end are clamped to the last group and groups the layout leaves out for a
+// lane (their address then holds a neighbouring group's entries of the node)
+// are masked in fma_round: the loads carry no branch, so the compiler can
+// keep the next round in flight while the current one is used.
+template <int SG, class V, class Off>
+__device__ __forceinline__ void load_round(V (&a)[SG], const V* p, int g0, int gend, Off off) {
   const int glast = max(gend - 1, 0);
 #pragma unroll
-  for (int u = 0; u < SG; ++u) a[u] = p[(int64_t)min(g0 + u, glast) * stride];
+  for (int u = 0; u < SG; ++u) a[u] = p[off(min(g0 + u, glast))];
 }
 
 // acc[q] of row `lane` summed over the waves through LDS; wave 0 ends with the
@@ -68,13 +71,14 @@ __device__ __forceinline__ void reduce_waves(double (&acc)[NR], double* red, int
 
 // acc[q] += sum over the SG groups of a round (group g0 + u of the wave) of
 // the K entries of each group times the LDS vector entries they multiply;
-// groups at or past gend contribute nothing.
-template <int NR, int SG, int K, class V>
+// groups at or past gend, or not stored for the lane (stored(g) false),
+// contribute nothing.
+template <int NR, int SG, int K, class V, class Stored>
 __device__ __forceinline__ void fma_round(double (&acc)[NR], const V (&a)[SG], int g0, int gend,
-                                          const double* vec, int nlast) {
+                                          const double* vec, int nlast, Stored stored) {
 #pragma unroll
   for (int u = 0; u < SG; ++u) {
-    const bool in = g0 + u < gend;
+    const bool in = g0 + u < gend && stored(g0 + u);
 #pragma unroll
     for (int e = 0; e < K; ++e) {
       const int j = min((g0 + u) * K + e, nlast);
@@ -111,8 +115,15 @@ __global__ __launch_bounds__(NW * 64) void k_fwd(DevTree t, const SweepTask* __r
   constexpr int K = Pack<E>::K;
   constexpr int STEP = NW * SG;
   typedef typename Pack<E>::V V;
-  // group g of row r at col[g * nf]; entries past the diagonal are stored zeros
-  const V* col = reinterpret_cast<const V*>(Lp + tk.poff) + (live ? r : r0);
+  // group g of row r at lp[lp_group(g) + r - gK] for r >= gK (the rows above
+  // are not stored: zeros of L_oo^{-1}); entries past the diagonal inside a
+  // stored group are stored zeros
+  // (32-bit offsets within the node: lp_group(g) - gK of kernels.hpp; a lane
+  // above a group's first row reads the previous group's rows, masked)
+  const int rr = live ? r : r0;
+  const V* lp = reinterpret_cast<const V*>(Lp + tk.poff) + rr;
+  auto at = [&](int g) { return g * nf - (K / 2) * g * (g - 1) - g * K; };
+  auto stored = [&](int g) { return rr >= g * K; };
   const int gend = (jend + K - 1) / K;
   // front vector: own entries of b plus the children's update rows, added in
   // child order (one pass, no barrier per child).  A position's record
@@ -129,8 +140,8 @@ __global__ __launch_bounds__(NW * 64) void k_fwd(DevTree t, const SweepTask* __r
   __builtin_amdgcn_sched_barrier(0);      // keep the issue order
   int g = __builtin_amdgcn_readfirstlane(wave) * SG;
   V A[SG], B[SG];
-  load_round<SG>(A, col, g, gend, nf);
-  load_round<SG>(B, col, g + STEP, gend, nf);
+  load_round<SG>(A, lp, g, gend, at);
+  load_round<SG>(B, lp, g + STEP, gend, at);
   const int dst = fd[min(r, nf - 1)];      // used by own rows only
 
   for (int i = tid; i < ng; i += NW * 64) {
@@ -163,12 +174,12 @@ __global__ __launch_bounds__(NW * 64) void k_fwd(DevTree t, const SweepTask* __r
 #pragma unroll
   for (int q = 0; q < NR; ++q) acc[q] = 0.0;
   while (g < gend) {
-    fma_round<NR, SG, K>(acc, A, g, gend, f, nown - 1);
-    load_round<SG>(A, col, g + 2 * STEP, gend, nf);
+    fma_round<NR, SG, K>(acc, A, g, gend, f, nown - 1, stored);
+    load_round<SG>(A, lp, g + 2 * STEP, gend, at);
     g += STEP;
     if (g >= gend) break;
-    fma_round<NR, SG, K>(acc, B, g, gend, f, nown - 1);
-    load_round<SG>(B, col, g + 2 * STEP, gend, nf);
+    fma_round<NR, SG, K>(acc, B, g, gend, f, nown - 1, stored);
+    load_round<SG>(B, lp, g + 2 * STEP, gend, at);
     g += STEP;
   }
   reduce_waves<NR, NW>(acc, red, lane, wave);
@@ -190,7 +201,7 @@ __global__ __launch_bounds__(NW * 64) void k_fwd(DevTree t, const SweepTask* __r
 // when `neg` is set.  Optional outputs: ru = scale (x + base) (base may be
 // null; ru may alias base: each entry is read and written by one thread) and
 // rl = sig val + v_u, where val is the ru value or, without ru, the xs value.
-template <int NR, class E, int NW, int SG>
+template <int NR, class E, int NW, int SG, bool TRI>
 __global__ __launch_bounds__(NW * 64) void k_bwd(DevTree t, const SweepTask* __restrict__ tasks,
                                             const E* __restrict__ Tp,
                                             const double* __restrict__ y, int64_t ldy,
@@ -212,18 +223,32 @@ __global__ __launch_bounds__(NW * 64) void k_bwd(DevTree t, const SweepTask* __r
   constexpr int K = Pack<E>::K;
   constexpr int STEP = NW * SG;
   typedef typename Pack<E>::V V;
-  // rows of F in groups of K: group g of own column a at row[g * no]; rows
-  // above the diagonal of L_oo^{-T} are stored zeros, so the block starts at
-  // group a0 / K
-  const V* row = reinterpret_cast<const V*>(Tp + tk.poff) + (live ? a : a0);
+  // rows of F in groups of K: group g of own column a at tp[tp_group(g) + a]
+  // for a < tp_width(g) (or at tp[g no + a] in the full rectangle); the groups
+  // above the column's diagonal block are zeros, so the task starts at group
+  // a0 / K.  Offsets are 32-bit within the node; a lane right of a group's
+  // width reads the next group's columns, masked.  TRI: the level's nodes
+  // leave out the zero triangle (launch_bwd_level), else the full rectangle.
+  const int aa = live ? a : a0;
+  const V* tp = reinterpret_cast<const V*>(Tp + tk.poff) + aa;
+  // tp_group(g) = g no - (x no - K x (x + 1) / 2), x = min(g, g1 - 1): the
+  // rectangle's offset less the columns the groups before g leave out;
+  // straight-line scalar arithmetic (tri = 0: the full rectangle)
+  const int g1m = (no + K - 1) / K - 1;
+  auto at = [&](int g) {
+    if (!TRI) return g * no;
+    const int x = min(g, g1m);
+    return g * no - (x * no - (K / 2) * x * (x + 1));
+  };
+  auto stored = [&](int g) { return !TRI || aa < (g + 1) * K; };
   const int gend = (nf + K - 1) / K;
   // indices of the first gather round before the factor loads (see k_fwd)
   const int fd0 = fd[min(tid, nf - 1)];
   __builtin_amdgcn_sched_barrier(0);      // keep the issue order
   int g = a0 / K + __builtin_amdgcn_readfirstlane(wave) * SG;
   V A[SG], B[SG];
-  load_round<SG>(A, row, g, gend, no);
-  load_round<SG>(B, row, g + STEP, gend, no);
+  load_round<SG>(A, tp, g, gend, at);
+  load_round<SG>(B, tp, g + STEP, gend, at);
   const int d = fd[min(a, no - 1)];       // used by live lanes only
   if (t.inst != nullptr) sig = t.isig[tk.inst];
 
@@ -254,12 +279,12 @@ __global__ __launch_bounds__(NW * 64) void k_bwd(DevTree t, const SweepTask* __r
 #pragma unroll
   for (int q = 0; q < NR; ++q) acc[q] = 0.0;
   while (g < gend) {
-    fma_round<NR, SG, K>(acc, A, g, gend, w, nf - 1);
-    load_round<SG>(A, row, g + 2 * STEP, gend, no);
+    fma_round<NR, SG, K>(acc, A, g, gend, w, nf - 1, stored);
+    load_round<SG>(A, tp, g + 2 * STEP, gend, at);
     g += STEP;
     if (g >= gend) break;
-    fma_round<NR, SG, K>(acc, B, g, gend, w, nf - 1);
-    load_round<SG>(B, row, g + 2 * STEP, gend, no);
+    fma_round<NR, SG, K>(acc, B, g, gend, w, nf - 1, stored);
+    load_round<SG>(B, tp, g + 2 * STEP, gend, at);
     g += STEP;
   }
   reduce_waves<NR, NW>(acc, red, lane, wave);
@@ -322,8 +347,13 @@ template <int NR, class E, int NW, int SG>
 void bwd_one(const DevTree& t, const SweepTask* tasks, int count, const E* Tp, const double* y, int64_t ldy,
              const BwdOut& o, int max_front, hipStream_t st) {
   const size_t shm = ((size_t)max_front + NW * SR) * NR * sizeof(double);
-  hipLaunchKernelGGL((k_bwd<NR, E, NW, SG>), dim3(count), dim3(NW * 64), shm, st, t, tasks, Tp, y, ldy, o.xs,
-                     o.ldxs, o.neg, o.base, o.ldbase, o.ru, o.ldr, o.scale, o.rl, o.v_u, o.ldv, o.sig);
+  // the level's layout: the rule of build_sweep_plan (its backward task count)
+  if (count >= SWEEP_TRI_TASKS)
+    hipLaunchKernelGGL((k_bwd<NR, E, NW, SG, true>), dim3(count), dim3(NW * 64), shm, st, t, tasks, Tp, y, ldy, o.xs,
+                       o.ldxs, o.neg, o.base, o.ldbase, o.ru, o.ldr, o.scale, o.rl, o.v_u, o.ldv, o.sig);
+  else
+    hipLaunchKernelGGL((k_bwd<NR, E, NW, SG, false>), dim3(count), dim3(NW * 64), shm, st, t, tasks, Tp, y, ldy,
+                       o.xs, o.ldxs, o.neg, o.base, o.ldbase, o.ru, o.ldr, o.scale, o.rl, o.v_u, o.ldv, o.sig);
 }
 
 template <int NR, class E>

@@ -34,8 +34,10 @@ struct DevTree {
   const int4* gsrc;
   const int64_t* doff;          // per node: first 64x64 block of its diagonal inverses
   const unsigned char* prec;    // per node: 1 = FP32 front (mixed factor), or null (all FP64)
-  const int64_t* lpoff;         // per node: sweep layouts of F (multiples of 4 elements):
-  const int64_t* tpoff;         //   ceil(no/4)*4*nf and ceil(nf/4)*4*no entries
+  const int64_t* lpoff;         // per node: sweep layouts of F (see lp_group / tp_group;
+  const int64_t* tpoff;         //   room for groups of 2 and of 4 elements)
+  const unsigned char* ttri;    // per node: 1 = Tp without the zero triangle, 0 = full
+                                //   rectangle (F[gK + s][a] at ((g no + a) K + s))
   // Forest of independent problems (batched form), all null for one problem:
   const int* inst;              // per node: its problem
   const DevSpace* spaces;       // per problem: 1-D space, rowptr into the forest CSR rows
@@ -97,6 +99,28 @@ void launch_combine3(int64_t nnz, double am, const double* M, double ac, const d
 // One launch per tree level; tasks[k] = {node, first row, end row, 0}.  The
 // level's factor is read in its sweep layouts, FP64 (Lp64/Tp64) or FP32
 // (Lp32/Tp32 non-null).
+// Sweep layouts of F = [L_oo^{-1}; L_bo L_oo^{-1}] (nf x no) without the zero
+// triangle of L_oo^{-1}, in groups of K side-by-side entries (one 16-byte load):
+//   forward (Lp): group g of columns gK .. gK+K-1 holds rows gK .. nf-1 (the
+//     rows above are zeros), row r at lp_group(g) + r - gK (in groups);
+//   backward (Tp): group g of rows gK .. gK+K-1 holds columns
+//     0 .. tp_width(g)-1 (the columns right of the diagonal block are zeros),
+//     column a at tp_group(g) + a.  Only nodes of levels with many backward
+//     tasks use it (the leaves, where the triangle is a large share of F and
+//     the sweep is bandwidth-bound); the others keep the full rectangle.
+__host__ __device__ inline int64_t lp_group(int g, int nf, int K) {
+  return (int64_t)g * nf - (int64_t)K * g * (g - 1) / 2;
+}
+__host__ __device__ inline int tp_width(int g, int no, int K) { return (g + 1) * K < no ? (g + 1) * K : no; }
+__host__ __device__ inline int64_t tp_group(int g, int no, int K) {
+  const int g1 = (no + K - 1) / K;   // groups below g1 - 1 are (g + 1) K wide, later ones no
+  if (g < g1) return (int64_t)K * g * (g + 1) / 2;
+  return (int64_t)K * (g1 - 1) * g1 / 2 + (int64_t)(g - g1 + 1) * no;
+}
+// Entries of a node's layouts for groups of K.
+__host__ __device__ inline int64_t lp_size(int nf, int no, int K) { return K * lp_group((no + K - 1) / K, nf, K); }
+__host__ __device__ inline int64_t tp_size(int nf, int no, int K) { return K * tp_group((nf + K - 1) / K, no, K); }
+
 // One task of a sweep level: rows [r0, r1) of F of node v (forward) or own
 // columns [r0, r1) (backward), with the node fields the workgroup needs, so
 // that it starts from a single load.  poff: the node's lpoff (forward) or
@@ -117,6 +141,10 @@ int sweep_variants();
 // tasks (bandwidth-bound) take 4-wave tasks, levels with few tasks
 // (latency-bound) 8 waves with short rounds.
 constexpr int SWEEP_WIDE = 3, SWEEP_NARROW = 1;
+// Levels with at least this many backward tasks keep the backward layout
+// without the zero triangle (build_sweep_plan packs them so, launch_bwd_level
+// reads them so).
+constexpr int SWEEP_TRI_TASKS = 1024;
 // Waves per task and column groups per wave and round of a sweep variant.
 void sweep_variant(int v, int* waves, int* groups);
 // Outputs of the backward sweep (see k_bwd): xs holds the sweep's solution

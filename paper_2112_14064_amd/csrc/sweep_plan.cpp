@@ -38,12 +38,26 @@ void build_sweep_plan(const Plan& P, const std::vector<int>& node_inst, SweepPla
       S.gsrc[q] = int4{p < P.no[v] ? P.fdofs[q] : -1, cnt, cnt > 0 ? S.gidx[S.gptr[q]] : 0,
                        cnt == 2 ? S.gidx[S.gptr[q] + 1] : S.gptr[q]};
     }
-  // sweep layouts: every node padded to groups of 4 columns / rows
+  // sweep layouts, room for FP64 (groups of 2) and FP32 (groups of 4) entries:
+  // the forward one without the zero triangle; the backward one too on levels
+  // with at least SWEEP_TRI_TASKS backward tasks (bandwidth-bound), else the
+  // full rectangle (measured faster where a level is latency-bound)
+  S.ttri.assign(nn, 0);
+  for (int lv = 0; lv < P.height; ++lv) {
+    int64_t bt = 0;
+    for (int k = P.level_off[lv]; k < P.level_off[lv + 1]; ++k) bt += (P.no[P.level_nodes[k]] + 63) / 64;
+    if (bt >= SWEEP_TRI_TASKS)
+      for (int k = P.level_off[lv]; k < P.level_off[lv + 1]; ++k) S.ttri[P.level_nodes[k]] = 1;
+  }
   S.lpoff.assign(nn + 1, 0);
   S.tpoff.assign(nn + 1, 0);
   for (size_t v = 0; v < nn; ++v) {
-    S.lpoff[v + 1] = S.lpoff[v] + (int64_t)((P.no[v] + 3) / 4 * 4) * P.nf[v];
-    S.tpoff[v + 1] = S.tpoff[v] + (int64_t)((P.nf[v] + 3) / 4 * 4) * P.no[v];
+    const int nf = P.nf[v], no = P.no[v];
+    // node starts on 16-element (128-byte FP64) boundaries
+    auto up16 = [](int64_t e) { return (e + 15) / 16 * 16; };
+    S.lpoff[v + 1] = S.lpoff[v] + up16(std::max(lp_size(nf, no, 2), lp_size(nf, no, 4)));
+    S.tpoff[v + 1] = S.tpoff[v] + up16(S.ttri[v] ? std::max(tp_size(nf, no, 2), tp_size(nf, no, 4))
+                                                 : (int64_t)((nf + 3) / 4 * 4) * no);
   }
   // slack past the last node: a forward task of a node without own dofs
   // reads (and discards) one round at the node's offset

@@ -14,6 +14,7 @@ struct SweepPlan {
   std::vector<int4> gsrc;                // per front position: {dof or -1, count, first row,
                                          //  second row (count 2) or gptr (count > 2)}
   std::vector<int64_t> lpoff, tpoff;     // per node: packed forward / backward layouts of F (nn + 1)
+  std::vector<unsigned char> ttri;       // per node: backward layout without the zero triangle
   int64_t lpsize = 0, tpsize = 0;        // entries of the layouts, with slack
   std::vector<SweepTask> ftasks, btasks; // 64-row tasks grouped by level
   std::vector<int> ftask_off, btask_off; // level lv: tasks [off[lv], off[lv + 1])
