@@ -29,6 +29,8 @@ int ks_ritz(const std::vector<double>& H, int ldh, int k, int b, int nev, double
   // Ritz vectors of the wanted values and residual estimates ||E y|| (E = rows k..k+b of H)
   schur_eigvecs_real(k, c.TR, c.QR, c.theta, c.Y, 1e-11, &c.wanted);
   c.nconv = 0;
+  c.tol = tol;
+  c.conv.assign(k, 0);
   for (int p = 0; p < c.nw; ++p) {
     const int i = c.ord[p];
     double s = 0.0;
@@ -37,7 +39,10 @@ int ks_ritz(const std::vector<double>& H, int ldh, int k, int b, int nev, double
       for (int col = 0; col < k; ++col) acc += Hat(k + r, col) * c.Y[col + (size_t)i * k];
       s += std::norm(acc);
     }
-    if (std::sqrt(s) <= tol * std::abs(c.theta[i])) ++c.nconv;
+    if (std::sqrt(s) <= tol * std::abs(c.theta[i])) {
+      ++c.nconv;
+      c.conv[i] = 1;
+    }
   }
   return 0;
 }
@@ -64,9 +69,39 @@ void ks_restart(const std::vector<double>& H, int ldh, int k, int b, int m, int 
   // Preferred: reorder the real Schur form.  The leading r columns of its
   // vectors are then a real orthonormal basis of the kept invariant subspace
   // and the new projected matrix is [T_rr; E Q_r].
+  c.nlock = 0;
   {
     std::vector<double> TR = c.TR, QR = c.QR;
-    const int r = schur_select_real(k, TR, QR, kept);
+    // converged kept values first (a pair counts only if both halves passed)
+    std::vector<int> bst, bsz;
+    for (int i = 0; i < k;) {
+      const int sz = (i + 1 < k && TR[(i + 1) + (size_t)i * k] != 0.0) ? 2 : 1;
+      bst.push_back(i);
+      bsz.push_back(sz);
+      i += sz;
+    }
+    std::vector<char> lock(k, 0), kept2 = kept;
+    int nl = 0;
+    for (size_t q = 0; q < bst.size(); ++q) {
+      bool all = true;
+      for (int u = 0; u < bsz[q]; ++u) all = all && kept[bst[q] + u] && (int)c.conv.size() == k && c.conv[bst[q] + u];
+      if (all)
+        for (int u = 0; u < bsz[q]; ++u) lock[bst[q] + u] = 1;
+      nl += all ? bsz[q] : 0;
+    }
+    if (nl > 0 && schur_select_real(k, TR, QR, lock) == nl) {
+      // the selection is stable: locked blocks in their order, then the rest
+      int pos = 0;
+      for (int pass = 0; pass < 2; ++pass)
+        for (size_t q = 0; q < bst.size(); ++q)
+          if ((lock[bst[q]] != 0) == (pass == 0))
+            for (int u = 0; u < bsz[q]; ++u) kept2[pos++] = kept[bst[q] + u];
+    } else {
+      TR = c.TR;
+      QR = c.QR;
+      nl = 0;
+    }
+    const int r = schur_select_real(k, TR, QR, kept2);
     if (r > 0) {
       c.Hn.assign((size_t)ldh * ldh, 0.0);
       for (int col = 0; col < r; ++col) {
@@ -77,6 +112,27 @@ void ks_restart(const std::vector<double>& H, int ldh, int k, int b, int m, int 
           c.Hn[r + rr + (size_t)col * ldh] = s;
         }
       }
+      // locking: the leading run of converged blocks whose columns of E Q are
+      // at most tol |theta| (|theta|^2 = the block's determinant for a pair)
+      int nlock = 0;
+      for (int i = 0; i < std::min(nl, r);) {
+        const int sz = (i + 1 < r && c.Hn[(i + 1) + (size_t)i * ldh] != 0.0) ? 2 : 1;
+        const double* t0 = &c.Hn[(size_t)i * ldh];
+        const double th = sz == 1 ? std::abs(t0[i])
+                                  : std::sqrt(std::abs(t0[i] * t0[i + 1 + ldh] - t0[i + ldh] * t0[i + 1]));
+        bool small = i + sz <= nl;
+        for (int u = 0; u < sz && small; ++u) {
+          double e2 = 0.0;
+          for (int rr = 0; rr < b; ++rr) e2 += c.Hn[r + rr + (size_t)(i + u) * ldh] * c.Hn[r + rr + (size_t)(i + u) * ldh];
+          small = std::sqrt(e2) <= c.tol * th;
+        }
+        if (!small) break;
+        i += sz;
+        nlock = i;
+      }
+      for (int col = 0; col < nlock; ++col)
+        for (int rr = 0; rr < b; ++rr) c.Hn[r + rr + (size_t)col * ldh] = 0.0;
+      c.nlock = nlock;
       const int kout = r + b;
       c.Qe.assign((size_t)kin * kout, 0.0);
       for (int col = 0; col < r; ++col)

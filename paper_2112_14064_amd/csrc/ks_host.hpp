@@ -18,6 +18,9 @@ struct KsCycle {
   int nw = 0;                      // wanted values: nev extended to the end of its cluster
   int nconv = 0;                   // wanted values whose Ritz residual passes the test
   std::vector<int> wanted;         // ord[0 .. nw)
+  std::vector<char> conv;          // per position of TR: a wanted value that passed the test
+  double tol = 0.0;                // the test's tolerance (kept for the restart's locking)
+  int nlock = 0;                   // leading columns the last restart decoupled (locked)
   int r = 0;                       // kept dimension after the restart
   std::vector<double> Qe;          // (k+b) x (r+b) combination of the basis, column-major
   std::vector<double> Hn;          // projected matrix after the restart, ldh x ldh
@@ -33,7 +36,11 @@ int ks_ritz(const std::vector<double>& H, int ldh, int k, int b, int nev, double
 // Krylov--Schur restart after ks_ritz: keep the `keep` Ritz values nearest the
 // shift (0: nev + (k - nev)/2; never fewer than nev; extended to whole
 // clusters), real Schur basis of their span, the new projected matrix
-// [T; E Q] and the combination Qe = [Q 0; 0 I].
+// [T; E Q] and the combination Qe = [Q 0; 0 I].  Converged values are moved
+// to the front of the kept ones; a leading run of them whose Schur vectors
+// couple to the residual block by at most tol |theta| is locked: that part of
+// E Q is set to zero, so the next projected matrix is block upper triangular
+// and its Schur form only iterates on the trailing block.
 void ks_restart(const std::vector<double>& H, int ldh, int k, int b, int m, int nev, int keep, KsCycle& c);
 
 // Forms of a complex vector u = a + i b given the 11 sums

@@ -20,45 +20,62 @@ inline void givens(cplx x, cplx y, double& c, cplx& s) {
   s = (x / nx) * std::conj(y) / nrm;
 }
 
+// Column kernels of the reductions below; the arguments never overlap, so the
+// loops vectorise.
+inline double dot(int len, const double* __restrict__ a, const double* __restrict__ b) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = 0;
+  for (; i + 3 < len; i += 4) {
+    s0 += a[i] * b[i];
+    s1 += a[i + 1] * b[i + 1];
+    s2 += a[i + 2] * b[i + 2];
+    s3 += a[i + 3] * b[i + 3];
+  }
+  for (; i < len; ++i) s0 += a[i] * b[i];
+  return (s0 + s1) + (s2 + s3);
+}
+
+inline void axpy(int len, double a, const double* __restrict__ x, double* __restrict__ y) {
+  for (int i = 0; i < len; ++i) y[i] += a * x[i];
+}
+
 // Real Householder reduction to upper Hessenberg form: A = Q H Q^T.
 void hessenberg(int n, std::vector<double>& H, std::vector<double>& Q) {
-  auto h = [&](int i, int j) -> double& { return H[i + (size_t)j * n]; };
-  auto q = [&](int i, int j) -> double& { return Q[i + (size_t)j * n]; };
   Q.assign((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) q(i, i) = 1.0;
+  for (int i = 0; i < n; ++i) Q[i + (size_t)i * n] = 1.0;
+  double* h = H.data();
+  double* q = Q.data();
   std::vector<double> v(n), w(n), z(n);
   for (int k = 0; k + 2 < n; ++k) {
-    double alpha = 0.0;
-    for (int i = k + 1; i < n; ++i) alpha += h(i, k) * h(i, k);
-    alpha = std::sqrt(alpha);
-    if (alpha == 0.0) continue;
-    if (h(k + 1, k) > 0) alpha = -alpha;
-    double vv = 0.0;
-    for (int i = k + 1; i < n; ++i) { v[i] = h(i, k); }
-    v[k + 1] -= alpha;
-    for (int i = k + 1; i < n; ++i) vv += v[i] * v[i];
+    const int m = n - k - 1;               // length of the reflector (rows k+1..n-1)
+    double* hk = h + (size_t)k * n + k + 1;
+    const double alpha0 = std::sqrt(dot(m, hk, hk));
+    if (alpha0 == 0.0) continue;
+    const double alpha = hk[0] > 0 ? -alpha0 : alpha0;
+    double* vk = v.data() + k + 1;
+    for (int i = 0; i < m; ++i) vk[i] = hk[i];
+    vk[0] -= alpha;
+    const double vv = dot(m, vk, vk);
     if (vv == 0.0) continue;
     const double beta = 2.0 / vv;
     // rows k+1..n-1: H -= beta v (v^T H) (columns before k are already reduced)
     for (int j = k; j < n; ++j) {
-      double s = 0.0;
-      for (int i = k + 1; i < n; ++i) s += v[i] * h(i, j);
-      s *= beta;
-      for (int i = k + 1; i < n; ++i) h(i, j) -= s * v[i];
+      double* hj = h + (size_t)j * n + k + 1;
+      axpy(m, -beta * dot(m, vk, hj), vk, hj);
     }
     // columns k+1..n-1: H -= beta (H v) v^T, and the same for Q; both by
     // whole columns (w = H v, z = Q v first)
     std::fill(w.begin(), w.end(), 0.0);
     std::fill(z.begin(), z.end(), 0.0);
     for (int j = k + 1; j < n; ++j) {
-      const double vj = v[j];
-      for (int i = 0; i < n; ++i) { w[i] += h(i, j) * vj; z[i] += q(i, j) * vj; }
+      axpy(n, v[j], h + (size_t)j * n, w.data());
+      axpy(n, v[j], q + (size_t)j * n, z.data());
     }
     for (int j = k + 1; j < n; ++j) {
-      const double c = beta * v[j];
-      for (int i = 0; i < n; ++i) { h(i, j) -= w[i] * c; q(i, j) -= z[i] * c; }
+      axpy(n, -beta * v[j], w.data(), h + (size_t)j * n);
+      axpy(n, -beta * v[j], z.data(), q + (size_t)j * n);
     }
-    for (int i = k + 2; i < n; ++i) h(i, k) = 0.0;
+    for (int i = k + 2; i < n; ++i) h[i + (size_t)k * n] = 0.0;
   }
 }
 
@@ -80,6 +97,26 @@ inline bool house(int m, const double* x, double* v, double& beta) {
   for (int i = 1; i < m; ++i) { v[i] = x[i] / v0; vv += v[i] * v[i]; }
   beta = 2.0 / vv;
   return true;
+}
+
+// Reflection (I - beta v v^T), v = (1, v1, v2), applied from the right to
+// rows 0..len-1 of three columns.
+inline void refl3(int len, double* __restrict__ a, double* __restrict__ b, double* __restrict__ c, double beta,
+                  double v1, double v2) {
+  for (int r = 0; r < len; ++r) {
+    const double t = beta * (a[r] + v1 * b[r] + v2 * c[r]);
+    a[r] -= t;
+    b[r] -= t * v1;
+    c[r] -= t * v2;
+  }
+}
+
+inline void refl2(int len, double* __restrict__ a, double* __restrict__ b, double beta, double v1) {
+  for (int r = 0; r < len; ++r) {
+    const double t = beta * (a[r] + v1 * b[r]);
+    a[r] -= t;
+    b[r] -= t * v1;
+  }
 }
 
 // Real Schur form H = Q T Q^T of an upper Hessenberg H by Francis double-shift
@@ -138,18 +175,8 @@ int real_schur(int n, std::vector<double>& H, std::vector<double>& Q) {
           h(r0 + 2, j) -= sdot * v[2];
         }
         const int rmax = std::min(r0 + 3, i);
-        for (int r = 0; r <= rmax; ++r) {
-          const double sdot = beta * (h(r, r0) + v[1] * h(r, r0 + 1) + v[2] * h(r, r0 + 2));
-          h(r, r0) -= sdot;
-          h(r, r0 + 1) -= sdot * v[1];
-          h(r, r0 + 2) -= sdot * v[2];
-        }
-        for (int r = 0; r < n; ++r) {
-          const double sdot = beta * (q(r, r0) + v[1] * q(r, r0 + 1) + v[2] * q(r, r0 + 2));
-          q(r, r0) -= sdot;
-          q(r, r0 + 1) -= sdot * v[1];
-          q(r, r0 + 2) -= sdot * v[2];
-        }
+        refl3(rmax + 1, &h(0, r0), &h(0, r0 + 1), &h(0, r0 + 2), beta, v[1], v[2]);
+        refl3(n, &q(0, r0), &q(0, r0 + 1), &q(0, r0 + 2), beta, v[1], v[2]);
       }
       if (k > 0) h(r0 + 1, r0 - 1) = h(r0 + 2, r0 - 1) = 0.0;   // the bulge moved on
       x[0] = h(r0 + 1, r0);
@@ -163,16 +190,8 @@ int real_schur(int n, std::vector<double>& H, std::vector<double>& Q) {
         h(i - 1, j) -= sdot;
         h(i, j) -= sdot * v[1];
       }
-      for (int r = 0; r <= i; ++r) {
-        const double sdot = beta * (h(r, i - 1) + v[1] * h(r, i));
-        h(r, i - 1) -= sdot;
-        h(r, i) -= sdot * v[1];
-      }
-      for (int r = 0; r < n; ++r) {
-        const double sdot = beta * (q(r, i - 1) + v[1] * q(r, i));
-        q(r, i - 1) -= sdot;
-        q(r, i) -= sdot * v[1];
-      }
+      refl2(i + 1, &h(0, i - 1), &h(0, i), beta, v[1]);
+      refl2(n, &q(0, i - 1), &q(0, i), beta, v[1]);
     }
     h(i, i - 2) = 0.0;
   }
