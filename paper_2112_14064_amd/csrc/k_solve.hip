@@ -302,12 +302,19 @@ __global__ __launch_bounds__(NW * 64) void k_bwd(DevTree t, const SweepTask* __r
   }
 }
 
-int sweep_variants() { return 6; }
+int sweep_variants() { return 8; }
 
 void sweep_variant(int v, int* waves, int* groups) {
-  static const int W[6] = {8, 8, 8, 4, 4, 4}, G[6] = {4, 2, 8, 4, 2, 8};
+  static const int W[8] = {8, 8, 8, 4, 4, 4, 16, 16}, G[8] = {4, 2, 8, 4, 2, 8, 2, 1};
   *waves = W[v];
   *groups = G[v];
+}
+
+int sweep_default_variant(int tasks, bool forward) {
+  // measured per level on the rIGA p=3 256^2 tree (8 levels), FP64, 2 right-hand sides
+  if (tasks >= 1024) return 4;                 // 4 waves x 2 groups
+  if (forward) return tasks >= 64 ? 1 : 7;     // 8 x 2, or 16 x 1
+  return tasks >= 256 ? 1 : 6;                 // 8 x 2, or 16 x 2
 }
 
 namespace {
@@ -328,6 +335,8 @@ void fwd_shape(int variant, const DevTree& t, const SweepTask* tasks, int count,
     case 3: fwd_one<NR, E, 4, 4>(t, tasks, count, Lp, b, ldb, y, ldy, upd, max_front, st); break;
     case 4: fwd_one<NR, E, 4, 2>(t, tasks, count, Lp, b, ldb, y, ldy, upd, max_front, st); break;
     case 5: fwd_one<NR, E, 4, 8>(t, tasks, count, Lp, b, ldb, y, ldy, upd, max_front, st); break;
+    case 6: fwd_one<NR, E, 16, 2>(t, tasks, count, Lp, b, ldb, y, ldy, upd, max_front, st); break;
+    case 7: fwd_one<NR, E, 16, 1>(t, tasks, count, Lp, b, ldb, y, ldy, upd, max_front, st); break;
     default: fwd_one<NR, E, 8, 4>(t, tasks, count, Lp, b, ldb, y, ldy, upd, max_front, st); break;
   }
 }
@@ -365,6 +374,8 @@ void bwd_shape(int variant, const DevTree& t, const SweepTask* tasks, int count,
     case 3: bwd_one<NR, E, 4, 4>(t, tasks, count, Tp, y, ldy, o, max_front, st); break;
     case 4: bwd_one<NR, E, 4, 2>(t, tasks, count, Tp, y, ldy, o, max_front, st); break;
     case 5: bwd_one<NR, E, 4, 8>(t, tasks, count, Tp, y, ldy, o, max_front, st); break;
+    case 6: bwd_one<NR, E, 16, 2>(t, tasks, count, Tp, y, ldy, o, max_front, st); break;
+    case 7: bwd_one<NR, E, 16, 1>(t, tasks, count, Tp, y, ldy, o, max_front, st); break;
     default: bwd_one<NR, E, 8, 4>(t, tasks, count, Tp, y, ldy, o, max_front, st); break;
   }
 }

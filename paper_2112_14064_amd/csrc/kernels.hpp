@@ -137,10 +137,12 @@ void launch_fwd_level(const DevTree& t, const SweepTask* tasks, int count, int n
                       const float* Lp32, const double* b, int64_t ldb, double* y, int64_t ldy, double* upd,
                       int max_front, int variant, hipStream_t st);
 int sweep_variants();
-// Variants the solver starts from before any autotuning: levels with many
-// tasks (bandwidth-bound) take 4-wave tasks, levels with few tasks
-// (latency-bound) 8 waves with short rounds.
-constexpr int SWEEP_WIDE = 3, SWEEP_NARROW = 1;
+// Variant a level starts from before any autotuning, by its task count:
+// levels with many tasks (bandwidth-bound) take 4-wave tasks, middle levels 8
+// waves with short rounds, and the few-task levels near the root (a task's
+// rows stream from one compute unit) 16 waves, so more loads are in flight
+// per task.
+int sweep_default_variant(int tasks, bool forward);
 // Levels with at least this many backward tasks keep the backward layout
 // without the zero triangle (build_sweep_plan packs them so, launch_bwd_level
 // reads them so).

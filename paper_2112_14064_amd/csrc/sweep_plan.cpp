@@ -95,8 +95,8 @@ void build_sweep_plan(const Plan& P, const std::vector<int>& node_inst, SweepPla
     });
     S.ftask_off[lv + 1] = (int)S.ftasks.size();
     S.btask_off[lv + 1] = (int)S.btasks.size();
-    S.fvar[lv] = (S.ftask_off[lv + 1] - S.ftask_off[lv] >= 1024) ? SWEEP_WIDE : SWEEP_NARROW;
-    S.bvar[lv] = (S.btask_off[lv + 1] - S.btask_off[lv] >= 1024) ? SWEEP_WIDE : SWEEP_NARROW;
+    S.fvar[lv] = sweep_default_variant(S.ftask_off[lv + 1] - S.ftask_off[lv], true);
+    S.bvar[lv] = sweep_default_variant(S.btask_off[lv + 1] - S.btask_off[lv], false);
   }
 }
 
