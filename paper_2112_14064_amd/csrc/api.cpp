@@ -1040,7 +1040,6 @@ struct KrylovRun {
     double* h1 = h->d_small;
     double* h2 = h->d_small + (size_t)ldh * b;
     double* dG = h->d_small + (size_t)2 * ldh * b;
-    double* dRinv = h->d_small + (size_t)2 * ldh * b + 16;
     int gblk = 0;
     if (riga::cgs_tile_fits(nc, b)) {
       // pass 1 products; pass 1 update together with the pass 2 products (one
@@ -1061,10 +1060,10 @@ struct KrylovRun {
     } else {
       riga::launch_dots(N, b, h->Ru, h->MRl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, dG, h->st);
     }
-    riga::launch_block_normalize(nc, b, nc > 0 ? h1 : nullptr, nc > 0 ? h2 : nullptr, dG, nc > 0 ? h->d_part : nullptr,
-                                 gblk, dest, ldh, col, dRinv, h->d_flag, h->st);
     const size_t o = (size_t)nc * N;
-    riga::launch_gemm3(N, b, dRinv, h->Ru, h->Vu + o, h->Rl, h->Vl + o, h->MRl, h->Wl + o, N, h->st);
+    riga::launch_normalize_gemm3(N, nc, b, nc > 0 ? h1 : nullptr, nc > 0 ? h2 : nullptr, dG,
+                                 nc > 0 ? h->d_part : nullptr, gblk, dest, ldh, col, h->d_flag, h->Ru, h->Vu + o,
+                                 h->Rl, h->Vl + o, h->MRl, h->Wl + o, N, h->st);
   }
 
   void orthonormalize(int nc, std::vector<double>& hsum, std::vector<double>& R, uint64_t seed) {

@@ -889,55 +889,48 @@ void launch_combine3(int64_t nnz, double am, const double* M, double ac, const d
 }
 
 // ---------------------------------------------------------------------------
-// Device-side end of a block Gram--Schmidt step: with h1, h2 (nc x nq, the two
-// projection passes, output-major c*nq+q) and G (nq x nq, the B-Gram matrix of
-// the projected block), write H[0:nc, k+q] = h1 + h2, factor G = R^T R, write
-// H[nc+c, k+q] = R[c][q] and Rinv = R^{-1} (column-major nq x nq).  A column
-// whose squared B-norm after projection falls below 1e-24 of its norm before
-// projection (an invariant subspace was reached) sets *flag = 1; the caller
-// then redoes the solve on the host-checked path.
-// With gpart, G is first summed from gblk per-block partials (nq x nq each,
-// block order).
-__global__ void k_block_normalize(int nc, int nq, const double* __restrict__ h1, const double* __restrict__ h2,
-                                  const double* __restrict__ G, const double* __restrict__ gpart, int gblk,
-                                  double* __restrict__ H, int ldh, int k, double* __restrict__ Rinv,
-                                  int* __restrict__ flag) {
+// Device-side end of a block Gram--Schmidt step, fused with the new basis
+// block: with h1, h2 (nc x nq, the two projection passes, output-major
+// c*nq+q) and G (nq x nq, the B-Gram matrix of the projected block), factor
+// G = R^T R and form Out_m = In_m R^{-1} for three (In, Out) pairs.  Every
+// workgroup forms R and R^{-1} itself (the same arithmetic in the same order,
+// so all agree) from the few values involved; workgroup 0 also writes
+// H[0:nc, k+q] = h1 + h2 and H[nc+c, k+q] = R[c][q].  A column whose squared
+// B-norm after projection falls below 1e-24 of its norm before projection (an
+// invariant subspace was reached) sets *flag = 1; the caller then redoes the
+// solve on the host-checked path.  With gpart, G is first summed from gblk
+// per-block partials (nq x nq each, block order).
+template <int NQ>
+__global__ __launch_bounds__(256) void k_normalize_gemm3(
+    int64_t n, int nc, const double* __restrict__ h1, const double* __restrict__ h2,
+    const double* __restrict__ G, const double* __restrict__ gpart, int gblk, double* __restrict__ H, int ldh,
+    int k, int* __restrict__ flag, const double* __restrict__ I0, double* __restrict__ O0,
+    const double* __restrict__ I1, double* __restrict__ O1, const double* __restrict__ I2,
+    double* __restrict__ O2, int64_t ld) {
   __shared__ double hn[4];
   __shared__ double gs[16];
+  __shared__ double X[NQ * NQ];
   if (gpart != nullptr) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int idx = wv; idx < nq * nq; idx += blockDim.x / 64) {
+    for (int idx = wv; idx < NQ * NQ; idx += blockDim.x / 64) {
       double s = 0.0;
-      for (int b = lane; b < gblk; b += 64) s += gpart[(int64_t)b * nq * nq + idx];
+      for (int b = lane; b < gblk; b += 64) s += gpart[(int64_t)b * NQ * NQ + idx];
       for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
       if (lane == 0) gs[idx] = s;
     }
     __syncthreads();
     G = gs;
   }
-  block_normalize_body(nc, nq, h1, h2, G, H, ldh, k, Rinv, flag, hn);
-}
-
-void launch_block_normalize(int nc, int nq, const double* h1, const double* h2, const double* G, const double* gpart,
-                            int gblk, double* H, int ldh, int k, double* Rinv, int* flag, hipStream_t st) {
-  hipLaunchKernelGGL(k_block_normalize, dim3(1), dim3(256), 0, st, nc, nq, h1, h2, G, gpart, gblk, H, ldh, k, Rinv,
-                     flag);
-}
-
-// Out_m[:, 0:nq] = In_m[:, 0:nq] Q for three (In, Out) pairs; Q nq x nq on the device.
-template <int NQ>
-__global__ __launch_bounds__(256) void k_gemm3(int64_t n, const double* __restrict__ Q,
-                                               const double* __restrict__ I0, double* __restrict__ O0,
-                                               const double* __restrict__ I1, double* __restrict__ O1,
-                                               const double* __restrict__ I2, double* __restrict__ O2,
-                                               int64_t ld) {
+  const bool first = blockIdx.x == 0;
+  block_normalize_body(nc, NQ, h1, h2, G, first ? H : nullptr, ldh, k, X, first ? flag : nullptr, hn);
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   double q[NQ][NQ];
 #pragma unroll
   for (int a = 0; a < NQ; ++a)
 #pragma unroll
-    for (int c = 0; c < NQ; ++c) q[a][c] = Q[a + c * NQ];
+    for (int c = 0; c < NQ; ++c) q[a][c] = X[a + c * NQ];
   const double* Is[3] = {I0, I1, I2};
   double* Os[3] = {O0, O1, O2};
 #pragma unroll
@@ -955,18 +948,21 @@ __global__ __launch_bounds__(256) void k_gemm3(int64_t n, const double* __restri
   }
 }
 
-void launch_gemm3(int64_t n, int nq, const double* Q, const double* I0, double* O0, const double* I1, double* O1,
-                  const double* I2, double* O2, int64_t ld, hipStream_t st) {
-  int64_t blocks = (n + 255) / 256;
-#define RIGA_G3(NQ) \
-  hipLaunchKernelGGL(k_gemm3<NQ>, dim3((unsigned)blocks), dim3(256), 0, st, n, Q, I0, O0, I1, O1, I2, O2, ld)
+void launch_normalize_gemm3(int64_t n, int nc, int nq, const double* h1, const double* h2, const double* G,
+                            const double* gpart, int gblk, double* H, int ldh, int k, int* flag, const double* I0,
+                            double* O0, const double* I1, double* O1, const double* I2, double* O2, int64_t ld,
+                            hipStream_t st) {
+  const int64_t blocks = std::max<int64_t>(1, (n + 255) / 256);
+#define RIGA_NG3(NQ)                                                                                           \
+  hipLaunchKernelGGL(k_normalize_gemm3<NQ>, dim3((unsigned)blocks), dim3(256), 0, st, n, nc, h1, h2, G, gpart, \
+                     gblk, H, ldh, k, flag, I0, O0, I1, O1, I2, O2, ld)
   switch (nq) {
-    case 1: RIGA_G3(1); break;
-    case 2: RIGA_G3(2); break;
-    case 3: RIGA_G3(3); break;
-    default: RIGA_G3(4); break;
+    case 1: RIGA_NG3(1); break;
+    case 2: RIGA_NG3(2); break;
+    case 3: RIGA_NG3(3); break;
+    default: RIGA_NG3(4); break;
   }
-#undef RIGA_G3
+#undef RIGA_NG3
 }
 
 // ---------------------------------------------------------------------------

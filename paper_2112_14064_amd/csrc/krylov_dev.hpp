@@ -331,7 +331,7 @@ __device__ inline void block_normalize_body(int nc, int nq, const double* h1, co
       if (H) H[nc + c + (int64_t)(k + q) * ldh] = R[c][q];
       Rinv[c + q * nq] = X[c][q];
     }
-  if (bad) *flag = 1;
+  if (bad && flag) *flag = 1;
 }
 
 constexpr int GEMM_COLS = 64;     // columns of Q staged in LDS at a time
