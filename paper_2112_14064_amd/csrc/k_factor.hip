@@ -157,15 +157,48 @@ __global__ __launch_bounds__(FT) void k_front_assemble(
   }
 }
 
+// Columns [l0, l1) of a child's update block U (nbc x nbc, lower triangle)
+// added into the parent front at the mapped positions (mk: the map from child
+// row l0 on, in shared memory).  A lane owns rows k and walks the tile's
+// columns in batches of eight: the eight front entries are distinct (the map
+// is injective), so their loads are all issued before the sums are stored.
+template <class E, class S>
+__device__ __forceinline__ void extend_tile(const Front<E>& F, const S* __restrict__ Uc, int nbc, int l0, int l1,
+                                            const int* mk) {
+  for (int k = l0 + (int)threadIdx.x; k < nbc; k += FT) {
+    const int pk = mk[k - l0];
+    const int lend = min(l1, k + 1);
+    int l = l0;
+    for (; l + 8 <= lend; l += 8) {
+      E* p[8];
+      E f[8];
+      S u[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        p[e] = F.at(pk, mk[l + e - l0]);
+        u[e] = Uc[(int64_t)(l + e) * nbc + k];
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) f[e] = *p[e];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) *p[e] = f[e] + (E)u[e];
+    }
+    for (; l < lend; ++l) *F.at(pk, mk[l - l0]) += (E)Uc[(int64_t)l * nbc + k];
+  }
+}
+
 // Extend-add of child number `slot` of every node: child columns [64 y, +64);
 // the map from child boundary to parent front positions is injective, so the
 // workgroups of one launch write disjoint entries.  A child's update block is
-// FP32 (U32) when t.prec marks the child, else FP64 (U64).
+// FP32 (U32) when t.prec marks the child, else FP64 (U64).  Dynamic shared
+// memory: the child's map from the tile's first row on (at most max_child_nb
+// ints).
 template <class E>
 __global__ __launch_bounds__(FT) void k_front_extend(DevTree t, const int* __restrict__ level_nodes, int slot,
                                                      E* __restrict__ Lbuf, E* __restrict__ Ubuf,
                                                      const float* __restrict__ U32,
                                                      const double* __restrict__ U64) {
+  extern __shared__ int mk[];
   const int v = level_nodes[blockIdx.x];
   if (t.coff[v] + slot >= t.coff[v + 1]) return;
   const Front<E> F = front_of(t, v, Lbuf, Ubuf);
@@ -174,25 +207,47 @@ __global__ __launch_bounds__(FT) void k_front_extend(DevTree t, const int* __res
   const int l0 = TB * blockIdx.y, l1 = min(nbc, l0 + TB);
   if (l0 >= nbc) return;
   const int* mp = t.maps + t.moff[c];
-  if (t.prec != nullptr && t.prec[c]) {
-    const float* Uc = U32 + t.uoff[c];
-    for (int l = l0; l < l1; ++l)
-      for (int k = l + threadIdx.x; k < nbc; k += FT) *F.at(mp[k], mp[l]) += (E)Uc[(int64_t)l * nbc + k];
-  } else {
-    const double* Uc = U64 + t.uoff[c];
-    for (int l = l0; l < l1; ++l)
-      for (int k = l + threadIdx.x; k < nbc; k += FT) *F.at(mp[k], mp[l]) += (E)Uc[(int64_t)l * nbc + k];
-  }
+  for (int k = l0 + (int)threadIdx.x; k < nbc; k += FT) mk[k - l0] = mp[k];
+  __syncthreads();
+  if (t.prec != nullptr && t.prec[c])
+    extend_tile(F, U32 + t.uoff[c], nbc, l0, l1, mk);
+  else
+    extend_tile(F, U64 + t.uoff[c], nbc, l0, l1, mk);
 }
 
 // ---------------------------------------------------------------------------------
+// Entry of register v held by lane l (l uniform), for every lane.
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// 1/sqrt(x) from the hardware estimate refined by Newton steps
+// y <- y + y (1 - x y^2) / 2 (two in FP64, one in FP32); x > 0 and normal.
+__device__ __forceinline__ double rsqrt_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+__device__ __forceinline__ float rsqrt_refined(float x) {
+  const float y = __builtin_amdgcn_rsqf(x);
+  const float e = fmaf(-x * y, y, 1.0f);
+  return fmaf(0.5f * y, e, y);
+}
+
 // Cholesky of the diagonal block [k0, k0+w) and D = its inverse (lower), stored
 // at D + (doff[v] + k0/64) * 4096 as D[r * 64 + c].  One wave does both with
-// the block in registers: lane = row for the factorisation (right-looking:
-// at column c every lane scales its entry and updates the rest of its row
-// from column c of the other rows, broadcast through shared memory), then
-// lane = column for the inverse (forward substitution against the rows of L,
-// broadcast from shared memory, with the reciprocal pivots of the
+// the block in registers: lane = row for the factorisation (right-looking: at
+// column c every lane scales its entry and updates the rest of its row from
+// column c of the other rows, read across lanes), then lane = column for the
+// inverse (forward substitution against the rows of L, broadcast from shared
+// memory, four rows at a time, with the reciprocal pivots of the
 // factorisation).  Every loop is unrolled so the row / column stays in
 // registers.
 template <class E>
@@ -206,7 +261,6 @@ __global__ __launch_bounds__(FT) void k_potrf_diag(DevTree t, const int* __restr
   const int w = min(TB, F.no - k0);
   const int tid = threadIdx.x;
   __shared__ E S[TB][LDT];
-  __shared__ E col[TB];   // column c of the rows, before scaling
   __shared__ E rd[TB];    // reciprocal pivots
   for (int idx = tid; idx < TB * TB; idx += FT) {
     const int r = idx % TB, c = idx / TB;       // coalesced along the column
@@ -223,28 +277,21 @@ __global__ __launch_bounds__(FT) void k_potrf_diag(DevTree t, const int* __restr
 #pragma unroll
     for (int c = 0; c < TB; ++c) {
       if (c < w) {   // uniform
-        col[r] = row[c];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        double piv = (double)col[c];
-        if (!(piv > 0.0)) {           // not SPD (or NaN): record, continue with 1
+        E piv = lane_value(row[c], c);
+        if (!(piv > E(0))) {           // not SPD (or NaN): record, continue with 1
           if (r == c)
             atomicCAS((unsigned long long*)status, (unsigned long long)(-1ll),
                       (unsigned long long)t.fdofs[t.foff[v] + k0 + c]);
-          piv = 1.0;
+          piv = E(1);
         }
-        const E d = (E)sqrt(piv);
-        const E inv = E(1) / d;
+        const E inv = rsqrt_refined(piv);
+        const E d = piv * inv;
         if (r == c) rd[c] = inv;
         const E lrc = row[c] * inv;   // L[r][c] (rows below the pivot)
         const E tc = lrc * inv;
 #pragma unroll
-        for (int j = c + 1; j < TB; ++j) row[j] -= tc * col[j];
+        for (int j = c + 1; j < TB; ++j) row[j] -= tc * lane_value(row[c], j);
         row[c] = (r == c) ? d : lrc;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();   // col is rewritten at the next column
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
 #pragma unroll
@@ -253,21 +300,29 @@ __global__ __launch_bounds__(FT) void k_potrf_diag(DevTree t, const int* __restr
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // inverse, lane = column c: D[rr][c] = -(sum_k L[rr][k] D[k][c]) / L[rr][rr]
+    // inverse, lane = column c: D[rr][c] = -(sum_k L[rr][k] D[k][c]) / L[rr][rr],
+    // the products over the rows already done formed for four rows together
     const int c = tid;
     E dc[TB];
 #pragma unroll
-    for (int rr = 0; rr < TB; ++rr) {
-      E s0 = E(0), s1 = E(0);
+    for (int r0 = 0; r0 < TB; r0 += 4) {
+      E sp[4] = {E(0), E(0), E(0), E(0)};
 #pragma unroll
-      for (int k = 0; k + 1 < rr; k += 2) {
-        s0 += S[rr][k] * dc[k];
-        s1 += S[rr][k + 1] * dc[k + 1];
+      for (int k = 0; k < r0; ++k) {
+        const E x = dc[k];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sp[u] += S[r0 + u][k] * x;
       }
-      if (rr & 1) s0 += S[rr][rr - 1] * dc[rr - 1];
-      const E ri = rd[rr];
-      dc[rr] = (rr < c) ? E(0) : (rr == c ? ri : -(s0 + s1) * ri);
-      D[rr * TB + c] = dc[rr];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int rr = r0 + u;
+        E sum = sp[u];
+#pragma unroll
+        for (int k = r0; k < rr; ++k) sum += S[rr][k] * dc[k];
+        const E ri = rd[rr];
+        dc[rr] = (rr < c) ? E(0) : (rr == c ? ri : -sum * ri);
+        D[rr * TB + c] = dc[rr];
+      }
     }
   }
   __syncthreads();
@@ -509,7 +564,8 @@ void front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, i
                      s.lo, s.hi, s.rowptr, t, level_nodes, s2, s1, K, M, C, L, U);
   if (max_child_nb > 0)
     for (int slot = 0; slot < max_kids; ++slot)
-      hipLaunchKernelGGL(k_front_extend<E>, dim3(count, (max_child_nb + TB - 1) / TB), dim3(FT), 0, st, t,
+      hipLaunchKernelGGL(k_front_extend<E>, dim3(count, (max_child_nb + TB - 1) / TB), dim3(FT),
+                         (size_t)max_child_nb * sizeof(int), st, t,
                          level_nodes, slot, L, U, U32, U64);
   for (int k0 = 0; k0 < max_no; k0 += TB) {
     hipLaunchKernelGGL(k_potrf_diag<E>, dim3(count), dim3(FT), 0, st, t, level_nodes, k0, L, U, D, status);
