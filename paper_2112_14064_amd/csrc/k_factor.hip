@@ -136,11 +136,28 @@ __global__ __launch_bounds__(FT) void k_front_assemble(
   }
   __syncthreads();
   if (!own) return;
-  for (int a = c0 + wave; a < min(c1, no); a += FT / 64) {
-    const int d = fd[a] - base;
+  // the wave's columns a = c0 + wave + 4u (at most 16): lane u fetches the
+  // row description of column u first, so the columns' entry loads do not
+  // wait on one another's index loads
+  const int na = (min(c1, no) - c0 - wave + FT / 64 - 1) / (FT / 64);
+  int m_lx = 0, m_wx = 1, m_ly = 0, m_k0 = 0, m_len = 0;
+  if (lane < na) {
+    const int d = fd[c0 + wave + (FT / 64) * lane] - base;
     const int i = d % n, j = d / n;
-    const int lx = lo[i], wx = hi[i] - lx + 1, ly = lo[j];
-    const int64_t k0 = rowptr[d], k1 = rowptr[d + 1];
+    m_lx = lo[i];
+    m_wx = hi[i] - m_lx + 1;
+    m_ly = lo[j];
+    const int64_t r0 = rowptr[d];
+    m_k0 = (int)(r0 - rowptr[0]);
+    m_len = (int)(rowptr[d + 1] - r0);
+  }
+  const int64_t kbase = rowptr[0];
+  for (int u = 0; u < na; ++u) {
+    const int a = c0 + wave + (FT / 64) * u;
+    const int lx = __builtin_amdgcn_readlane(m_lx, u), wx = __builtin_amdgcn_readlane(m_wx, u);
+    const int ly = __builtin_amdgcn_readlane(m_ly, u);
+    const int64_t k0 = kbase + __builtin_amdgcn_readlane(m_k0, u);
+    const int64_t k1 = k0 + __builtin_amdgcn_readlane(m_len, u);
     for (int64_t k = k0 + lane; k < k1; k += 64) {
       const int o = (int)(k - k0);
       const int g = (ly + o / wx) * n + lx + o % wx + base;
