@@ -1336,6 +1336,7 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     }  // attempts
     // --- eigenpairs: u = V_u y for the wanted Ritz vectors --------------------------
     const int k = kr.k;
+    riga::ks_ritz_vectors(cyc);
     const std::vector<int>& wanted = cyc.wanted;
     const int nw = (int)wanted.size();
     std::vector<double> Yr((size_t)k * nw), Yi((size_t)k * nw);

@@ -648,6 +648,7 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
       for (int i = 0; i < n; ++i) hqoff[i] = (int64_t)i * 2 * hl;
       for (int i : fin) {
         const int k = kend[i], nw = cyc[i].nw;
+        riga::ks_ritz_vectors(cyc[i]);
         double* q = Qh + (size_t)i * 2 * hl;
         for (int j = 0; j < nw; ++j)
           for (int c = 0; c < k; ++c) {

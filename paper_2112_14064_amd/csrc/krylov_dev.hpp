@@ -46,7 +46,8 @@ __device__ __forceinline__ void tensor_row_sum(const double* __restrict__ a, int
 }
 
 // Multi-dot body: for the columns c = wave, wave + 2 NW, ... (and c + NW
-// beside each) of Au/Al, the sums over rows [i0, i1) of
+// beside each; four columns per pass when the rows fit one round) of Au/Al,
+// the sums over rows [i0, i1) of
 // Au[i,c] Xu[i,q] + Al[i,c] Xl[i,q] (Al, Xl may be null), reduced over the
 // wave; lane 0 calls put(c, q, value).  DOT_U rows per lane per round, every
 // load of a round issued before the first product.
@@ -57,6 +58,63 @@ __device__ __forceinline__ void dots_body(int64_t i0, int64_t i1, int nc, const 
                                           const double* __restrict__ Al, int64_t lda,
                                           const double* __restrict__ Xu, const double* __restrict__ Xl,
                                           int64_t ldx, int lane, int wave, Put put) {
+  if (i1 - i0 <= 64 * DOT_U) {
+    // the rows fit one round: the X rows stay in registers and a wave takes
+    // four columns per pass (c, c + NW, c + 2 NW, c + 3 NW), every load of a
+    // pass issued before its first product; the sums are formed in the same
+    // order as below
+    double xu[DOT_U][NQ], xl[DOT_U][NQ];
+    bool in[DOT_U];
+#pragma unroll
+    for (int e = 0; e < DOT_U; ++e) {
+      const int64_t i = i0 + e * 64 + lane;
+      in[e] = i < i1;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        xu[e][q] = in[e] ? Xu[i + q * ldx] : 0.0;
+        xl[e][q] = (in[e] && Xl) ? Xl[i + q * ldx] : 0.0;
+      }
+    }
+    for (int c = wave; c < nc; c += 4 * NW) {
+      double u[4][DOT_U], l[4][DOT_U];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int cm = min(c + m * NW, nc - 1);   // past the end: a repeat, not stored
+        const double* au = Au + (int64_t)cm * lda;
+        const double* al = Al ? Al + (int64_t)cm * lda : nullptr;
+#pragma unroll
+        for (int e = 0; e < DOT_U; ++e) {
+          const int64_t i = i0 + e * 64 + lane;
+          u[m][e] = in[e] ? au[i] : 0.0;
+          l[m][e] = (in[e] && al) ? al[i] : 0.0;
+        }
+      }
+      double acc[4][NQ];
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          double a = 0.0;
+#pragma unroll
+          for (int e = 0; e < DOT_U; ++e) a += u[m][e] * xu[e][q] + l[m][e] * xl[e][q];
+          acc[m][q] = a;
+        }
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) acc[m][q] += __shfl_xor(acc[m][q], off, 64);
+      if (lane == 0) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          if (c + m * NW < nc)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) put(c + m * NW, q, acc[m][q]);
+      }
+    }
+    return;
+  }
   for (int c = wave; c < nc; c += 2 * NW) {
     const int c2 = c + NW;
     const bool two = c2 < nc;

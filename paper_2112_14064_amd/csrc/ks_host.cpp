@@ -26,8 +26,18 @@ int ks_ritz(const std::vector<double>& H, int ldh, int k, int b, int nev, double
     ++pos;
   c.nw = pos;
   c.wanted.assign(c.ord.begin(), c.ord.begin() + c.nw);
-  // Ritz vectors of the wanted values and residual estimates ||E y|| (E = rows k..k+b of H)
-  schur_eigvecs_real(k, c.TR, c.QR, c.theta, c.Y, 1e-11, &c.wanted);
+  // Ritz vectors of the wanted values in the Schur basis (y = Q x) and
+  // residual estimates ||E y|| = ||(E Q) x|| (E = rows k..k+b of H)
+  c.k = k;
+  c.Y.clear();
+  schur_eigvecs_real(k, c.TR, c.QR, c.theta, c.X, 1e-11, &c.wanted, true);
+  std::vector<double> EQ((size_t)b * k, 0.0);
+  for (int col = 0; col < k; ++col)
+    for (int r = 0; r < b; ++r) {
+      double s = 0.0;
+      for (int t2 = 0; t2 < k; ++t2) s += Hat(k + r, t2) * c.QR[t2 + (size_t)col * k];
+      EQ[r + (size_t)col * b] = s;
+    }
   c.nconv = 0;
   c.tol = tol;
   c.conv.assign(k, 0);
@@ -36,7 +46,7 @@ int ks_ritz(const std::vector<double>& H, int ldh, int k, int b, int nev, double
     double s = 0.0;
     for (int r = 0; r < b; ++r) {
       cplx acc = 0.0;
-      for (int col = 0; col < k; ++col) acc += Hat(k + r, col) * c.Y[col + (size_t)i * k];
+      for (int col = 0; col < k; ++col) acc += EQ[r + (size_t)col * b] * c.X[col + (size_t)i * k];
       s += std::norm(acc);
     }
     if (std::sqrt(s) <= tol * std::abs(c.theta[i])) {
@@ -45,6 +55,20 @@ int ks_ritz(const std::vector<double>& H, int ldh, int k, int b, int nev, double
     }
   }
   return 0;
+}
+
+void ks_ritz_vectors(KsCycle& c) {
+  const int k = c.k;
+  c.Y.assign((size_t)k * k, cplx(0.0));
+  for (int i : c.wanted) {
+    const cplx* x = &c.X[(size_t)i * k];
+    cplx* y = &c.Y[(size_t)i * k];
+    for (int j = 0; j < k; ++j) {
+      if (x[j] == cplx(0.0)) continue;
+      const double* q = &c.QR[(size_t)j * k];
+      for (int r = 0; r < k; ++r) y[r] += q[r] * x[j];
+    }
+  }
 }
 
 void ks_restart(const std::vector<double>& H, int ldh, int k, int b, int m, int nev, int keep, KsCycle& c) {

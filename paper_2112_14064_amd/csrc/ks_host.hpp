@@ -12,7 +12,10 @@ namespace riga {
 struct KsCycle {
   std::vector<double> TR, QR;      // real Schur form of H_k and its vectors (k x k)
   std::vector<cplx> T, Z, Y;       // complex Schur form and its vectors (formed by the restart
-                                   // only when the real reordering fails), Ritz vectors (k x k)
+                                   // only when the real reordering fails), Ritz vectors (k x k,
+                                   // formed by ks_ritz_vectors)
+  std::vector<cplx> X;             // the wanted Ritz vectors in the Schur basis (k x k)
+  int k = 0;                       // dimension of the last Rayleigh--Ritz
   std::vector<cplx> theta;         // Ritz values of S
   std::vector<int> ord;            // positions by |theta| descending, clusters kept together
   int nw = 0;                      // wanted values: nev extended to the end of its cluster
@@ -32,6 +35,10 @@ struct KsCycle {
 // counts as converged when ||E y|| <= tol |theta|.  Returns -1 if the Schur
 // iteration failed.
 int ks_ritz(const std::vector<double>& H, int ldh, int k, int b, int nev, double tol, KsCycle& c);
+
+// Ritz vectors Y = Q X of the wanted values of the last ks_ritz (only the
+// final cycle needs them; the convergence test works in the Schur basis).
+void ks_ritz_vectors(KsCycle& c);
 
 // Krylov--Schur restart after ks_ritz: keep the `keep` Ritz values nearest the
 // shift (0: nev + (k - nev)/2; never fewer than nev; extended to whole

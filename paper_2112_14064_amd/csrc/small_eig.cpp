@@ -518,7 +518,7 @@ void schur_real_eigvals(int n, const std::vector<double>& T, std::vector<cplx>& 
 
 void schur_eigvecs_real(int n, const std::vector<double>& T, const std::vector<double>& Q,
                         const std::vector<cplx>& theta, std::vector<cplx>& Y, double cluster_tol,
-                        const std::vector<int>* which) {
+                        const std::vector<int>* which, bool schur_basis) {
   auto t = [&](int i, int j) { return T[i + (size_t)j * n]; };
   double scale = 0.0;
   for (int i = 0; i < n; ++i) scale = std::max(scale, std::abs(theta[i]));
@@ -583,15 +583,22 @@ void schur_eigvecs_real(int n, const std::vector<double>& T, const std::vector<d
       }
       i = i0 - 1;
     }
-    // y = Q x, unit 2-norm
+    // y = Q x (or x itself in the Schur basis), unit 2-norm
     std::fill(yr.begin(), yr.end(), 0.0);
     std::fill(yi.begin(), yi.end(), 0.0);
-    for (int j = 0; j <= kend; ++j) {
-      const double xr = x[j].real(), xi = x[j].imag();
-      const double* q = &Q[(size_t)j * n];
-      for (int i = 0; i < n; ++i) {
-        yr[i] += q[i] * xr;
-        yi[i] += q[i] * xi;
+    if (schur_basis) {
+      for (int j = 0; j <= kend; ++j) {
+        yr[j] = x[j].real();
+        yi[j] = x[j].imag();
+      }
+    } else {
+      for (int j = 0; j <= kend; ++j) {
+        const double xr = x[j].real(), xi = x[j].imag();
+        const double* q = &Q[(size_t)j * n];
+        for (int i = 0; i < n; ++i) {
+          yr[i] += q[i] * xr;
+          yi[i] += q[i] * xi;
+        }
       }
     }
     double nrm = 0.0;

@@ -54,9 +54,12 @@ void schur_real_eigvals(int n, const std::vector<double>& T, std::vector<cplx>& 
 // quasi-triangular T with each 2x2 block triangularised on the fly, so the
 // same clustering rule applies per diagonal position; the vector of the
 // second eigenvalue of a complex-conjugate block is the conjugate of the first.
+// With schur_basis, Y holds the vectors in the coordinates of the Schur basis
+// (the eigenvectors of T, unit 2-norm); Q times them gives the eigenvectors
+// of A.
 void schur_eigvecs_real(int n, const std::vector<double>& T, const std::vector<double>& Q,
                         const std::vector<cplx>& theta, std::vector<cplx>& Y, double cluster_tol,
-                        const std::vector<int>* which = nullptr);
+                        const std::vector<int>* which = nullptr, bool schur_basis = false);
 
 // Reorder the Schur form so that the diagonal entries with keep[i] != 0 come
 // first (their relative order kept) with the fewest adjacent exchanges: each
