@@ -11,7 +11,7 @@
 #define RIGA_AMALG_MAX 256
 #endif
 #ifndef RIGA_AMALG_OWN
-#define RIGA_AMALG_OWN 320
+#define RIGA_AMALG_OWN 640
 #endif
 
 namespace riga {
