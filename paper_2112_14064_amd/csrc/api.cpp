@@ -1061,9 +1061,10 @@ struct KrylovRun {
       riga::launch_dots(N, b, h->Ru, h->MRl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, dG, h->st);
     }
     const size_t o = (size_t)nc * N;
+    double* rbuf = h->d_small + (size_t)2 * ldh * b + 16;   // nq x nq, after G
     riga::launch_normalize_gemm3(N, nc, b, nc > 0 ? h1 : nullptr, nc > 0 ? h2 : nullptr, dG,
-                                 nc > 0 ? h->d_part : nullptr, gblk, dest, ldh, col, h->d_flag, h->Ru, h->Vu + o,
-                                 h->Rl, h->Vl + o, h->MRl, h->Wl + o, N, h->st);
+                                 nc > 0 ? h->d_part : nullptr, gblk, dest, ldh, col, h->d_flag, rbuf, h->Ru,
+                                 h->Vu + o, h->Rl, h->Vl + o, h->MRl, h->Wl + o, N, h->st);
   }
 
   void orthonormalize(int nc, std::vector<double>& hsum, std::vector<double>& R, uint64_t seed) {

@@ -900,16 +900,23 @@ void launch_combine3(int64_t nnz, double am, const double* M, double ac, const d
 // invariant subspace was reached) sets *flag = 1; the caller then redoes the
 // solve on the host-checked path.  With gpart, G is first summed from gblk
 // per-block partials (nq x nq each, block order).
+// With many workgroups (gblk large) the per-workgroup sums of the partials
+// would cost more than they save: then one workgroup forms R^{-1} into rbuf
+// (mode 1, no rows) and the product reads it from there (mode 2).
 template <int NQ>
 __global__ __launch_bounds__(256) void k_normalize_gemm3(
     int64_t n, int nc, const double* __restrict__ h1, const double* __restrict__ h2,
     const double* __restrict__ G, const double* __restrict__ gpart, int gblk, double* __restrict__ H, int ldh,
-    int k, int* __restrict__ flag, const double* __restrict__ I0, double* __restrict__ O0,
-    const double* __restrict__ I1, double* __restrict__ O1, const double* __restrict__ I2,
-    double* __restrict__ O2, int64_t ld) {
+    int k, int* __restrict__ flag, double* __restrict__ rbuf, int mode, const double* __restrict__ I0,
+    double* __restrict__ O0, const double* __restrict__ I1, double* __restrict__ O1,
+    const double* __restrict__ I2, double* __restrict__ O2, int64_t ld) {
   __shared__ double hn[4];
   __shared__ double gs[16];
   __shared__ double X[NQ * NQ];
+  if (mode == 2) {
+    if (threadIdx.x < NQ * NQ) X[threadIdx.x] = rbuf[threadIdx.x];
+    __syncthreads();
+  } else {
   if (gpart != nullptr) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int idx = wv; idx < NQ * NQ; idx += blockDim.x / 64) {
@@ -924,6 +931,11 @@ __global__ __launch_bounds__(256) void k_normalize_gemm3(
   const bool first = blockIdx.x == 0;
   block_normalize_body(nc, NQ, h1, h2, G, first ? H : nullptr, ldh, k, X, first ? flag : nullptr, hn);
   __syncthreads();
+  if (mode == 1) {
+    if (threadIdx.x < NQ * NQ) rbuf[threadIdx.x] = X[threadIdx.x];
+    return;
+  }
+  }
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   double q[NQ][NQ];
@@ -949,19 +961,29 @@ __global__ __launch_bounds__(256) void k_normalize_gemm3(
 }
 
 void launch_normalize_gemm3(int64_t n, int nc, int nq, const double* h1, const double* h2, const double* G,
-                            const double* gpart, int gblk, double* H, int ldh, int k, int* flag, const double* I0,
-                            double* O0, const double* I1, double* O1, const double* I2, double* O2, int64_t ld,
-                            hipStream_t st) {
+                            const double* gpart, int gblk, double* H, int ldh, int k, int* flag, double* rbuf,
+                            const double* I0, double* O0, const double* I1, double* O1, const double* I2,
+                            double* O2, int64_t ld, hipStream_t st) {
   const int64_t blocks = std::max<int64_t>(1, (n + 255) / 256);
-#define RIGA_NG3(NQ)                                                                                           \
-  hipLaunchKernelGGL(k_normalize_gemm3<NQ>, dim3((unsigned)blocks), dim3(256), 0, st, n, nc, h1, h2, G, gpart, \
-                     gblk, H, ldh, k, flag, I0, O0, I1, O1, I2, O2, ld)
-  switch (nq) {
-    case 1: RIGA_NG3(1); break;
-    case 2: RIGA_NG3(2); break;
-    case 3: RIGA_NG3(3); break;
-    default: RIGA_NG3(4); break;
+  // fused while every workgroup's share of the partial sums stays small
+  const bool split = gpart != nullptr && gblk > 512;
+#define RIGA_NG3(NQ, GRID, NROWS, MODE)                                                                      \
+  hipLaunchKernelGGL(k_normalize_gemm3<NQ>, dim3((unsigned)(GRID)), dim3(256), 0, st, (int64_t)(NROWS), nc, h1, \
+                     h2, G, gpart, gblk, H, ldh, k, flag, rbuf, MODE, I0, O0, I1, O1, I2, O2, ld)
+#define RIGA_NG3_ALL(NQ)                                   \
+  if (split) {                                             \
+    RIGA_NG3(NQ, 1, 0, 1);                                 \
+    RIGA_NG3(NQ, blocks, n, 2);                            \
+  } else {                                                 \
+    RIGA_NG3(NQ, blocks, n, 0);                            \
   }
+  switch (nq) {
+    case 1: RIGA_NG3_ALL(1); break;
+    case 2: RIGA_NG3_ALL(2); break;
+    case 3: RIGA_NG3_ALL(3); break;
+    default: RIGA_NG3_ALL(4); break;
+  }
+#undef RIGA_NG3_ALL
 #undef RIGA_NG3
 }
 

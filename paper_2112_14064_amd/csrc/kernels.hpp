@@ -267,11 +267,12 @@ void launch_rowabs3(const int4* rb, int nblocks, int64_t ndof, int rows_per_bloc
 // k_krylov.hip): H columns k..k+nq from the projection coefficients h1 + h2 and
 // the Cholesky factor R of the Gram matrix G (or, with gpart, of the sum of
 // gblk partial Gram matrices); Out_m = In_m R^{-1} (n x nq) for three pairs
-// sharing ld; *flag = 1 when a column was lost (breakdown).
+// sharing ld; *flag = 1 when a column was lost (breakdown).  rbuf: nq x nq
+// device scratch (used when gblk is large).
 void launch_normalize_gemm3(int64_t n, int nc, int nq, const double* h1, const double* h2, const double* G,
-                            const double* gpart, int gblk, double* H, int ldh, int k, int* flag, const double* I0,
-                            double* O0, const double* I1, double* O1, const double* I2, double* O2, int64_t ld,
-                            hipStream_t st);
+                            const double* gpart, int gblk, double* H, int ldh, int k, int* flag, double* rbuf,
+                            const double* I0, double* O0, const double* I1, double* O1, const double* I2,
+                            double* O2, int64_t ld, hipStream_t st);
 
 // Interleaved complex columns -> planar [Re | Im].
 void launch_deinterleave(int64_t n, int nv, const double* X, double* P, hipStream_t st);
