@@ -1036,7 +1036,8 @@ struct KrylovRun {
 
   // Device path of orthonormalize: same arithmetic, the b x b factor computed by
   // a one-workgroup kernel, H written on the device (dest = nullptr: not recorded).
-  void orthonormalize_device(int nc, double* dest, int col) {
+  // mr: MRl = M Rl is formed here, in the launch of the first products
+  void orthonormalize_device(int nc, double* dest, int col, bool mr = false) {
     double* h1 = h->d_small;
     double* h2 = h->d_small + (size_t)ldh * b;
     double* dG = h->d_small + (size_t)2 * ldh * b;
@@ -1045,13 +1046,21 @@ struct KrylovRun {
       // pass 1 products; pass 1 update together with the pass 2 products (one
       // read of the basis); pass 2 update with the partial B-Gram sums of the
       // new block
-      riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, h1, h->st);
+      if (mr)
+        riga::launch_dots_mr(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h1, h->ds, h->d_M1, h->MRl, N,
+                             h->st);
+      else
+        riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, h1, h->st);
       riga::launch_cgs_update_dots(N, nc, b, h1, h->Vu, h->Vl, h->Wl, N, h->Ru, h->Rl, h->MRl, N, h->d_part, h2,
                                    h->st);
       gblk = riga::launch_cgs_update(N, nc, b, h2, h->Vu, h->Ru, h->Vl, h->Rl, h->Wl, h->MRl, N, N, h->d_part,
                                      h->st);
     } else if (nc > 0) {
-      riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, h1, h->st);
+      if (mr)
+        riga::launch_dots_mr(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h1, h->ds, h->d_M1, h->MRl, N,
+                             h->st);
+      else
+        riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, h1, h->st);
       riga::launch_cgs_update(N, nc, b, h1, h->Vu, h->Ru, h->Vl, h->Rl, h->Wl, h->MRl, N, N, nullptr, h->st);
       riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, h2, h->st);
       // the second pass also leaves the partial B-Gram sums of the updated block
@@ -1136,18 +1145,18 @@ struct KrylovRun {
 
   // One block step on the device: S applied to V[:, k:k+b], CGS2 against
   // V[:, 0:k+b], device normalisation into V[:, k+b:k+2b] and H.
-  // The operator applied to the basis block at column kb (and M to its lower
-  // part): Ru, Rl, MRl.
+  // The operator applied to the basis block at column kb: Ru, Rl (M Rl is
+  // formed by orthonormalize_device, with the first products).
   void enqueue_apply(int kb) {
     const int64_t n = N;
     const size_t o = (size_t)kb * n;
     apply_block(h, b, h->Vu + o, h->Wl + o, n, h->Ru, h->Rl, h->Tv);
-    riga::launch_tensor_mk(h->ds, h->d_M1, h->d_K1, b, 1.0, 0.0, h->Rl, n, h->MRl, n, nullptr, 0, 0.0, h->st);
   }
 
+  // (M Rl, which the Gram-Schmidt updates need, is formed with the first products)
   void enqueue_step_device() {
     if (!pre) enqueue_apply(k);
-    orthonormalize_device(k + b, h->d_H, k);
+    orthonormalize_device(k + b, h->d_H, k, true);
   }
 
   void step(uint64_t seed) {

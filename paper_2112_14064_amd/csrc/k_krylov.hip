@@ -512,6 +512,54 @@ void launch_tensor_mk(const DevSpace& s, const double* M1, const double* K1, int
 #undef RIGA_TMK
 }
 
+// Pass 1 products (as launch_dots) and Y = M X (sum-factorised, as
+// launch_tensor_mk with b = 0) in one launch: the first nblk workgroups form
+// the products, the others the tiles of the mass product.  The two read
+// different data and write different outputs.
+template <int NQ>
+__global__ __launch_bounds__(256) void k_dots_mr(int64_t n, int nc, const double* __restrict__ Au,
+                                                 const double* __restrict__ Al, int64_t lda,
+                                                 const double* __restrict__ Xu, const double* __restrict__ Xl,
+                                                 int64_t ldx, double* __restrict__ partial, int nblk, int tn, int p,
+                                                 const double* __restrict__ M1, const double* __restrict__ X2,
+                                                 int64_t ldx2, double* __restrict__ Y2, int64_t ldy2) {
+  extern __shared__ double sm[];
+  const int bx = blockIdx.x;
+  if (bx < nblk) {
+    const int64_t per = (n + nblk - 1) / nblk;
+    const int64_t i0 = (int64_t)bx * per;
+    const int64_t i1 = min(n, i0 + per);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    dots_body<NQ, 4>(i0, i1, nc, Au, Al, lda, Xu, Xl, ldx, lane, wave,
+                     [&](int c, int q, double v) { partial[((int64_t)c * NQ + q) * nblk + bx] = v; });
+  } else {
+    const int t = bx - nblk, gx = (tn + TT_I - 1) / TT_I;
+    tensor_tile<NQ, false>(tn, p, (t % gx) * TT_I, (t / gx) * TT_J, M1, nullptr, 1.0, 0.0, X2, ldx2, Y2, ldy2,
+                           nullptr, 0, 0.0, sm);
+  }
+}
+
+void launch_dots_mr(int64_t n, int nc, const double* Au, const double* Al, int64_t lda, int nq, const double* Xu,
+                    const double* Xl, int64_t ldx, double* partial, double* out, const DevSpace& s,
+                    const double* M1, double* Y2, int64_t ldy2, hipStream_t st) {
+  const int blocks = dots_blocks(n);
+  const int tn = s.n, gx = (tn + TT_I - 1) / TT_I, gy = (tn + TT_J - 1) / TT_J;
+  const unsigned grid = (unsigned)(blocks + gx * gy);
+  const size_t shm = tensor_shm(s.p, nq, false);
+#define RIGA_DMR(NQ)                                                                                        \
+  hipLaunchKernelGGL(k_dots_mr<NQ>, dim3(grid), dim3(256), shm, st, n, nc, Au, Al, lda, Xu, Xl, ldx, partial, \
+                     blocks, tn, s.p, M1, Xl, ldx, Y2, ldy2)
+  switch (nq) {
+    case 1: RIGA_DMR(1); break;
+    case 2: RIGA_DMR(2); break;
+    case 3: RIGA_DMR(3); break;
+    default: RIGA_DMR(4); break;
+  }
+#undef RIGA_DMR
+  const int nout = nc * nq;
+  hipLaunchKernelGGL(k_dots_final, dim3((nout + 3) / 4), dim3(256), 0, st, nout, blocks, partial, out);
+}
+
 // ---------------------------------------------------------------------------
 // Gram--Schmidt update Z[:, q] -= sum_c A[:, c] h[c][q] for up to three
 // (A, Z) pairs sharing h (upper part, lower part, and M times the lower part).

@@ -263,6 +263,11 @@ void launch_finalize(int64_t n, int nv, int nout, const double* P, int64_t ld, c
 void launch_rowabs3(const int4* rb, int nblocks, int64_t ndof, int rows_per_block, const int64_t* rowptr,
                     const double* A0, const double* A1, const double* A2, double* part, hipStream_t st);
 
+// launch_dots (nc > 0) together with M1 (x) M1 applied to the nq columns of
+// Xl (the space s, ldx) into Y2: one launch for both, then the final sums.
+void launch_dots_mr(int64_t n, int nc, const double* Au, const double* Al, int64_t lda, int nq, const double* Xu,
+                    const double* Xl, int64_t ldx, double* partial, double* out, const DevSpace& s,
+                    const double* M1, double* Y2, int64_t ldy2, hipStream_t st);
 // Device-side block normalisation fused with the new basis block (see
 // k_krylov.hip): H columns k..k+nq from the projection coefficients h1 + h2 and
 // the Cholesky factor R of the Gram matrix G (or, with gpart, of the sum of
