@@ -340,7 +340,7 @@ void launch_dots(int64_t n, int nc, const double* Au, const double* Al, int64_t 
 // stages X on the tile plus a halo of p in shared memory, forms
 // TM = X M1^T and TK = X K1^T along i for the tile's rows and the halo rows,
 // then Y = M1 (a TM + b TK) + b K1 TM along j.
-constexpr int TT_I = 64, TT_J = 8, TT_THREADS = 256;
+constexpr int TT_I = TENSOR_TILE_I, TT_J = TENSOR_TILE_J, TT_THREADS = 256;
 
 // One tile (i0, j0) of one grid; sm: shared memory for the halo and the
 // partial products (sized for the largest degree of the launch).
