@@ -341,17 +341,21 @@ void launch_dots(int64_t n, int nc, const double* Au, const double* Al, int64_t 
 // TM = X M1^T and TK = X K1^T along i for the tile's rows and the halo rows,
 // then Y = M1 (a TM + b TK) + b K1 TM along j.
 constexpr int TT_I = TENSOR_TILE_I, TT_J = TENSOR_TILE_J, TT_THREADS = 256;
+// Tile height of the single-problem launches: half the forest's, so a
+// single grid gives twice the workgroups (these launches are latency-bound).
+constexpr int TT_J1 = TENSOR_TILE_J / 2;
 
-// One tile (i0, j0) of one grid; sm: shared memory for the halo and the
-// partial products (sized for the largest degree of the launch).
-template <int NQ, bool HASK>
+// One tile (i0, j0) of TT_I x TJ points of one grid; sm: shared memory for
+// the halo and the partial products (sized for the largest degree of the
+// launch).
+template <int NQ, bool HASK, int TJ = TT_J>
 __device__ __forceinline__ void tensor_tile(int n, int p, int i0, int j0, const double* __restrict__ M1,
                                             const double* __restrict__ K1, double a, double b,
                                             const double* __restrict__ X, int64_t ldx, double* __restrict__ Y,
                                             int64_t ldy, const double* __restrict__ Z, int64_t ldz, double c,
                                             double* sm) {
   const int w = 2 * p + 1;
-  const int hx = TT_I + 2 * p, hy = TT_J + 2 * p;
+  const int hx = TT_I + 2 * p, hy = TJ + 2 * p;
   double* xs = sm;                          // [hy][hx][NQ]
   double* tm = xs + (size_t)hy * hx * NQ;   // [hy][TT_I][NQ]
   double* tk = tm + (size_t)hy * TT_I * NQ; // [hy][TT_I][NQ] (HASK)
@@ -386,7 +390,7 @@ __device__ __forceinline__ void tensor_tile(int n, int p, int i0, int j0, const 
     }
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < TT_J * TT_I; idx += TT_THREADS) {
+  for (int idx = threadIdx.x; idx < TJ * TT_I; idx += TT_THREADS) {
     const int jr = idx / TT_I, ci = idx % TT_I;
     const int i = i0 + ci, j = j0 + jr;
     if (i >= n || j >= n) continue;
@@ -424,7 +428,8 @@ __global__ __launch_bounds__(TT_THREADS) void k_tensor_mk(int n, int p, const do
                                                           double* __restrict__ Y, int64_t ldy,
                                                           const double* __restrict__ Z, int64_t ldz, double c) {
   extern __shared__ double sm[];
-  tensor_tile<NQ, HASK>(n, p, blockIdx.x * TT_I, blockIdx.y * TT_J, M1, K1, a, b, X, ldx, Y, ldy, Z, ldz, c, sm);
+  tensor_tile<NQ, HASK, TT_J1>(n, p, blockIdx.x * TT_I, blockIdx.y * TT_J1, M1, K1, a, b, X, ldx, Y, ldy, Z, ldz, c,
+                               sm);
 }
 
 // Every live problem of a forest: tile t = {problem, i0, j0, 0}; the problem's
@@ -455,8 +460,8 @@ __global__ __launch_bounds__(TT_THREADS) void k_tensor_mk_b(const int4* __restri
                         Z ? Z + base : nullptr, ldz, c, sm);
 }
 
-size_t tensor_shm(int max_p, int nq, bool hask) {
-  const size_t shm_x = (size_t)(TT_J + 2 * max_p) * (TT_I + 2 * max_p), shm_t = (size_t)(TT_J + 2 * max_p) * TT_I;
+size_t tensor_shm(int max_p, int nq, bool hask, int tj) {
+  const size_t shm_x = (size_t)(tj + 2 * max_p) * (TT_I + 2 * max_p), shm_t = (size_t)(tj + 2 * max_p) * TT_I;
   return (shm_x + (hask ? 2 : 1) * shm_t) * nq * sizeof(double);
 }
 
@@ -469,7 +474,7 @@ void launch_tensor_mk_b(const int4* tiles, int ntiles, const DevSpace* spaces, c
   const bool hask = sig != nullptr;
 #define RIGA_TMKB(NQ)                                                                                          \
   do {                                                                                                         \
-    const size_t shm = tensor_shm(max_p, NQ, hask);                                                            \
+    const size_t shm = tensor_shm(max_p, NQ, hask, TT_J);                                                            \
     if (hask)                                                                                                  \
       hipLaunchKernelGGL((k_tensor_mk_b<NQ, true>), dim3(ntiles), dim3(TT_THREADS), shm, st, tiles, spaces,      \
                          dofbase, bandoff, M1, K1, live, sig, alpha, beta, X, ldx, Y, ldy, Z, ldz, c);         \
@@ -491,11 +496,11 @@ void launch_tensor_mk(const DevSpace& s, const double* M1, const double* K1, int
                       hipStream_t st) {
   const int n = s.n, p = s.p;
   if (n <= 0) return;
-  const dim3 grid((n + TT_I - 1) / TT_I, (n + TT_J - 1) / TT_J);
+  const dim3 grid((n + TT_I - 1) / TT_I, (n + TT_J1 - 1) / TT_J1);
   const bool hask = b != 0.0;
 #define RIGA_TMK(NQ)                                                                                           \
   do {                                                                                                         \
-    const size_t shm = tensor_shm(p, NQ, hask);                                                                \
+    const size_t shm = tensor_shm(p, NQ, hask, TT_J1);                                                                \
     if (hask)                                                                                                  \
       hipLaunchKernelGGL((k_tensor_mk<NQ, true>), grid, dim3(TT_THREADS), shm, st, n, p, M1, K1, a, b, X, ldx, Y, \
                          ldy, Z, ldz, c);                                                                      \
@@ -534,7 +539,7 @@ __global__ __launch_bounds__(256) void k_dots_mr(int64_t n, int nc, const double
                      [&](int c, int q, double v) { partial[((int64_t)c * NQ + q) * nblk + bx] = v; });
   } else {
     const int t = bx - nblk, gx = (tn + TT_I - 1) / TT_I;
-    tensor_tile<NQ, false>(tn, p, (t % gx) * TT_I, (t / gx) * TT_J, M1, nullptr, 1.0, 0.0, X2, ldx2, Y2, ldy2,
+    tensor_tile<NQ, false, TT_J1>(tn, p, (t % gx) * TT_I, (t / gx) * TT_J1, M1, nullptr, 1.0, 0.0, X2, ldx2, Y2, ldy2,
                            nullptr, 0, 0.0, sm);
   }
 }
@@ -543,9 +548,9 @@ void launch_dots_mr(int64_t n, int nc, const double* Au, const double* Al, int64
                     const double* Xl, int64_t ldx, double* partial, double* out, const DevSpace& s,
                     const double* M1, double* Y2, int64_t ldy2, hipStream_t st) {
   const int blocks = dots_blocks(n);
-  const int tn = s.n, gx = (tn + TT_I - 1) / TT_I, gy = (tn + TT_J - 1) / TT_J;
+  const int tn = s.n, gx = (tn + TT_I - 1) / TT_I, gy = (tn + TT_J1 - 1) / TT_J1;
   const unsigned grid = (unsigned)(blocks + gx * gy);
-  const size_t shm = tensor_shm(s.p, nq, false);
+  const size_t shm = tensor_shm(s.p, nq, false, TT_J1);
 #define RIGA_DMR(NQ)                                                                                        \
   hipLaunchKernelGGL(k_dots_mr<NQ>, dim3(grid), dim3(256), shm, st, n, nc, Au, Al, lda, Xu, Xl, ldx, partial, \
                      blocks, tn, s.p, M1, Xl, ldx, Y2, ldy2)
