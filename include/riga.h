@@ -50,7 +50,10 @@ typedef enum {
   RIGA_ERR_HIP = -3,           /* a HIP runtime call failed                    */
   RIGA_ERR_OOM = -4,           /* device allocation failed                     */
   RIGA_ERR_STATE = -5,         /* call out of order (e.g. eigs before factor)  */
-  RIGA_WARN_NOT_CONVERGED = 1  /* eigs stopped at maxit with nconv < nev       */
+  RIGA_WARN_NOT_CONVERGED = 1, /* eigs stopped at maxit, or fewer than nev pairs
+                                  meet eta <= 1e-10: nconv < nev               */
+  RIGA_WARN_IR_STAGNATED = 2    /* riga_factor_mixed: the refinement missed its
+                                  target; the handle holds an FP64 factor      */
 } riga_status;
 
 /* Discretisation (Sec. 3.1-3.3).
@@ -114,7 +117,27 @@ typedef struct {
   int64_t factor_entries;   /* stored entries of the factor (dense fronts)      */
   double  factor_flops_dense; /* flops executed by the dense-front factorization */
   double  solve_bytes;  /* bytes of factor read by one forward+backward solve   */
+  int64_t factor_nnz;   /* nnz(L) of the symbolic Cholesky of Q under the
+                           elimination order used (diagonal included; no
+                           dense-front zeros)                                  */
+  double  factor_flops; /* algorithmic factorization flops of that order:
+                           sum_j (c_j^2 + 2 c_j), c_j = off-diagonal nonzeros
+                           of column j of L (the cost C_fa of eq. Cost)        */
 } riga_info_t;
+
+/* Phases of the per-phase counters in riga_stats_t (eq. Cost of Sec. 5.1 and
+ * the operation sets of Alg. 2).                                             */
+enum {
+  RIGA_PHASE_ASSEMBLE = 0,  /* K, M, C values                                    */
+  RIGA_PHASE_FACTOR = 1,    /* factorization of Q(sigma)  (N_fa C_fa)            */
+  RIGA_PHASE_FB = 2,        /* forward/backward eliminations (N_fb C_fb)         */
+  RIGA_PHASE_MV = 3,        /* products with sigma M + C and M (N_mv C_mv)       */
+  RIGA_PHASE_VV = 4,        /* B-orthogonalisation products (N_vv C_vv)          */
+  RIGA_PHASE_RESTART = 5,   /* basis recombination at restarts and Ritz vectors  */
+  RIGA_PHASE_IR = 6,        /* FP64 residual products of the mixed refinement    */
+  RIGA_PHASE_POST = 7,      /* M, C, K products and forms of the returned pairs  */
+  RIGA_NPHASE = 8
+};
 
 typedef struct {
   int64_t n_it;         /* Krylov-Schur restarts performed (N_it)               */
@@ -127,15 +150,51 @@ typedef struct {
   double t_host_ms;     /* host wall time of the last eigensolve between its
                            device steps: projected-matrix downloads, Ritz
                            values and restarts, uploads (the device waits)    */
+  /* Algorithmic work of the last assemble / factor / eigs calls per phase
+   * (RIGA_PHASE_*), not the bytes a profiler counts.  flops follow eq. Cost:
+   * C_fa = the symbolic count of riga_info_t.factor_flops; C_fb = 4 nnz(L)
+   * per vector; C_mv = 2 nnz(Q) per product; C_vv = 2 N per length-N product;
+   * assembly is a lower-order term there and counts 0 flops.  bytes are the
+   * minimum HBM traffic of this library's kernels for that work: assembly
+   * writes the three value arrays (24 B per nonzero, plus 8 B per element of
+   * a damping field); the factorization reads them and writes nnz(L) entries;
+   * a sweep pass reads the stored inverse blocks once per block of
+   * right-hand sides plus 16 B per dof and vector; a sum-factorised product
+   * moves 16 B per dof, a sparse one 8 B per stored entry plus 16 B per dof;
+   * a length-N product reads 8 B per dof; a restart reads and writes the
+   * three bases once.                                                         */
+  double bytes[RIGA_NPHASE];
+  double flops[RIGA_NPHASE];
 } riga_stats_t;
 
-/* Build the discretisation and the nested-dissection plan on the host and
- * allocate device storage on `device` (HIP ordinal).  hip_stream: a
- * hipStream_t, or NULL for the default stream.  *out receives the handle.   */
+/* Build the discretisation (open knot vectors of eq. KnotsX with C^0
+ * hyperplanes of multiplicity p for rIGA, Sec. 3.1-3.3) and the
+ * nested-dissection plan whose separators are the rIGA hyperplanes (the
+ * elimination of Sec. 5.2.1) on the host, and allocate device storage on
+ * `device` (HIP ordinal).  hip_stream: a hipStream_t, or NULL for the default
+ * stream.  *out receives the handle; RIGA_ERR_INVALID_ARG for a mesh outside
+ * the limits of riga_mesh, RIGA_ERR_OOM when device memory runs out.         */
 riga_status riga_create(riga_problem** out, const riga_mesh* mesh, int device, void* hip_stream);
 
-/* Sizes of the discretisation and of the factor plan (host output).          */
+/* Sizes of the discretisation and of the factor plan (host output):
+ * dimensions of the spaces of Sec. 3.2-3.3 and of the nested-dissection tree
+ * whose separators are the rIGA hyperplanes (Sec. 3.3), the stored factor
+ * and the cost C_fa of eq. Cost (Sec. 5.2.1) for the elimination order used.
+ * The symbolic count is computed on the host at the first call.              */
 riga_status riga_info(const riga_problem* h, riga_info_t* info);
+
+/* Host-only symbolic Cholesky of Q(sigma)'s sparsity for a mesh (Sec. 5.2.1,
+ * eq. CostFactIGA / eq. CostFactrIGA are its asymptotics), under the
+ * elimination order this library's plan uses; touches no device.
+ *   ndof:     host, receives N (may be NULL).
+ *   order:    host, N int64 or NULL: order[k] = the dof eliminated k-th.
+ *   colcount: host, N int64 or NULL: nonzeros of column k of L (elimination
+ *             position k; diagonal included).
+ *   nnz_l, flops: host or NULL: sum of colcount, sum_k (c_k^2 + 2 c_k) with
+ *             c_k = colcount[k] - 1.
+ * Call once with order = colcount = NULL to size the arrays.                 */
+riga_status riga_symbolic(const riga_mesh* mesh, int64_t* ndof, int64_t* order, int64_t* colcount,
+                          int64_t* nnz_l, double* flops);
 
 /* Assemble K, M and C on the device (Sec. 3.1; element integrals by the
  * (p+1)^2-point Gauss rule).  Invalidates an existing factorization.         */
@@ -171,7 +230,13 @@ riga_status riga_factor(riga_problem* h, double sigma, int64_t* bad_pivot);
  *              residual ||b - Q x_k|| / ||b|| is <= ir_tol, but never more
  *              than the point after which one more sweep would reduce it by
  *              less than a factor 4 (ir_tol = 0: that point).
- *   ir_tol     >= 0, used with ir_sweeps = -1.
+ *   ir_tol     >= 0: the residual target of that calibration solve.
+ * Stagnation: with ir_sweeps = -1, if the chosen count leaves the calibration
+ * residual above ir_tol (above 1e-10 when ir_tol = 0), or with a fixed
+ * ir_sweeps and ir_tol > 0, if that count leaves it above ir_tol, the FP32
+ * factor is too weak for the refinement: Q(sigma) is factored again in FP64
+ * (as riga_factor) and RIGA_WARN_IR_STAGNATED is returned; riga_ir_sweeps then
+ * reports -1.  A fixed ir_sweeps with ir_tol = 0 is taken as given.
  *   ir_hist    host, RIGA_IR_MAX+1 doubles, or NULL: ||b - Q x_k|| / ||b|| for
  *              k = 0..RIGA_IR_MAX of that calibration solve (written whenever
  *              not NULL).
@@ -281,6 +346,10 @@ riga_status riga_selftest_schur_restart(int n, const double* a, int nkeep, int* 
                                         int* real_path);
 
 /* ---- Batched form -----------------------------------------------------------
+ * The paper solves one problem at a time; every problem here follows the
+ * single-problem method above (Alg. 2 on the pencil of eq. Linearization with
+ * the factorization of Sec. 5.2.1), and the batching is this library's own
+ * execution form.
  * Many independent problems of different sizes (degree, mesh, hyperplane
  * spacing, damping, shift) solved together: the nested-dissection trees are
  * merged into one forest, so each factorization level and each sweep is one

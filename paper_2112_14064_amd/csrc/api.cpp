@@ -351,6 +351,7 @@ const char* riga_status_str(riga_status s) {
     case RIGA_ERR_OOM: return "out of device memory";
     case RIGA_ERR_STATE: return "call out of order";
     case RIGA_WARN_NOT_CONVERGED: return "not all requested eigenpairs converged";
+    case RIGA_WARN_IR_STAGNATED: return "iterative refinement of the mixed factor stagnated; factored in FP64";
   }
   return "unknown status";
 }
@@ -410,7 +411,30 @@ riga_status riga_info(const riga_problem* h, riga_info_t* info) {
   info->factor_entries = P.lsize;
   info->factor_flops_dense = P.flops_dense;
   info->solve_bytes = P.solve_bytes;
+  const_cast<riga::Plan&>(P).ensure_symbolic();   // cached on the handle
+  info->factor_nnz = P.sym_nnz_l;
+  info->factor_flops = P.sym_flops;
   return RIGA_OK;
+}
+
+riga_status riga_symbolic(const riga_mesh* mesh, int64_t* ndof, int64_t* order, int64_t* colcount,
+                          int64_t* nnz_l, double* flops) {
+  if (!mesh) return RIGA_ERR_INVALID_ARG;
+  return run([&]() -> riga_status {
+    riga::Plan P;
+    if (P.build(mesh->p, mesh->ne, mesh->hyper_every, mesh->leaf) != 0) return RIGA_ERR_INVALID_ARG;
+    if (ndof) *ndof = P.ndof;
+    std::vector<int64_t> cc;
+    int64_t nz = 0;
+    double fl = 0.0;
+    P.symbolic(colcount ? &cc : nullptr, nz, fl);
+    if (order)
+      for (int64_t d = 0; d < P.ndof; ++d) order[P.elim_pos[d]] = d;
+    if (colcount) std::copy(cc.begin(), cc.end(), colcount);
+    if (nnz_l) *nnz_l = nz;
+    if (flops) *flops = fl;
+    return RIGA_OK;
+  });
 }
 
 riga_status riga_assemble(riga_problem* h, const riga_damping* damping) {
@@ -425,9 +449,13 @@ riga_status riga_assemble(riga_problem* h, const riga_damping* damping) {
     ck(hipGetLastError());
     ck(hipEventRecord(h->ev1, h->st));
     h->alpha = damping->alpha; h->beta = damping->beta; h->c_elem = damping->c_elem;
+    h->clear_graphs();   // captured block steps hold the old operator coefficients
     h->assembled = true;
     h->factored = false;
     h->norms[0] = h->norms[1] = h->norms[2] = -1;
+    h->stats.flops[RIGA_PHASE_ASSEMBLE] = 0.0;   // a lower-order term of eq. Cost
+    h->stats.bytes[RIGA_PHASE_ASSEMBLE] =
+        24.0 * (double)h->plan.nnz + (damping->c_elem ? 8.0 * h->mesh.ne * (double)h->mesh.ne : 0.0);
     h->stats.t_assemble_ms = -1;  // resolved lazily (the call does not synchronise)
     return RIGA_OK;
   });
@@ -498,6 +526,19 @@ riga_status factor_all(riga_problem* h, double sigma, int64_t* bad_pivot) {
   float ms = 0;
   ck(hipEventElapsedTime(&ms, h->ev0, h->ev1));
   h->stats.t_factor_ms = ms;
+  {
+    riga::Plan& Pm = h->plan;
+    // factor entries read by one forward + backward pass, FP32 levels at 4 B
+    double sb = 0.0;
+    for (size_t v = 0; v < Pm.nodes.size(); ++v) {
+      const double o = Pm.no[v], bb = Pm.nb[v];
+      sb += 2.0 * (h->level_f32(Pm.nodes[v].height) ? 4.0 : 8.0) * (o * (o + 1) / 2 + bb * o);
+    }
+    h->solve_bytes_now = sb;
+    Pm.ensure_symbolic();
+    h->stats.flops[RIGA_PHASE_FACTOR] = Pm.sym_flops;
+    h->stats.bytes[RIGA_PHASE_FACTOR] = 24.0 * (double)Pm.nnz + 8.0 * (double)Pm.sym_nnz_l;
+  }
   if (stat >= 0) {
     if (bad_pivot) *bad_pivot = stat;
     h->factored = false;
@@ -638,6 +679,7 @@ riga_status riga_factor(riga_problem* h, double sigma, int64_t* bad_pivot) {
   if (!h->assembled) return RIGA_ERR_STATE;
   return run([&]() -> riga_status {
     ck(hipSetDevice(h->device));
+    h->clear_graphs();
     h->mixed = false;
     return factor_all(h, sigma, bad_pivot);
   });
@@ -652,6 +694,7 @@ riga_status riga_factor_mixed(riga_problem* h, double sigma, int fp64_levels, in
   if (!h->assembled) return RIGA_ERR_STATE;
   return run([&]() -> riga_status {
     ck(hipSetDevice(h->device));
+    h->clear_graphs();
     const riga::Plan& P = h->plan;
     const int64_t N = h->N();
     if (!h->d_L32) {
@@ -679,7 +722,8 @@ riga_status riga_factor_mixed(riga_problem* h, double sigma, int fp64_levels, in
     h->ir_sweeps = 0;
     riga_status rc = factor_all(h, sigma, bad_pivot);
     if (rc != RIGA_OK) return rc;
-    if (ir_sweeps < 0 || ir_hist) {
+    bool stagnated = false;
+    if (ir_sweeps < 0 || ir_hist || ir_tol > 0.0) {
       std::vector<double> hist;
       ir_history(h, RIGA_IR_MAX, hist);
       if (ir_hist)
@@ -693,7 +737,21 @@ riga_status riga_factor_mixed(riga_problem* h, double sigma, int fp64_levels, in
           best = k;
         }
         ir_sweeps = best;
+        // the refinement stopped gaining before the target (ir_tol, or the
+        // stagnation bound when refining to the floor)
+        const double target = ir_tol > 0.0 ? ir_tol : kIrStagnation;
+        stagnated = !(hist[best] <= target);
+      } else if (ir_tol > 0.0) {
+        // a fixed count must reach the caller's target
+        stagnated = !(hist[std::min<int>(ir_sweeps, (int)hist.size() - 1)] <= ir_tol);
       }
+    }
+    if (stagnated) {
+      // the FP32 factor is too weak for the FP64 refinement: factor in FP64
+      h->mixed = false;
+      h->ir_sweeps = 0;
+      rc = factor_all(h, sigma, bad_pivot);
+      return rc == RIGA_OK ? RIGA_WARN_IR_STAGNATED : rc;
     }
     h->ir_sweeps = ir_sweeps;
     return RIGA_OK;
@@ -1165,7 +1223,7 @@ struct KrylovRun {
     const int nc = k + b;
     if (fast) {
       if (graphs) {
-        auto key = std::make_tuple(k, b, (const double*)h->Vu, pre ? 1 : 0);
+        auto key = std::make_tuple(k, b, (const double*)h->Vu, pre ? 1 : 0, ldh);
         auto it = h->graphs.find(key);
         if (it == h->graphs.end()) {
           ck(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
@@ -1246,6 +1304,7 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     int it = 0;
     bool converged = false;
     double t_host = 0.0;   // host Ritz and restart work, the device idle
+    double rs_bytes = 0.0, rs_flops = 0.0;   // restart recombinations
     riga::KsCycle cyc;
     uint64_t step_seed = opt->seed * 1000003u + 5;
     // First attempt on the fast path; a breakdown reported by the device sends
@@ -1331,6 +1390,8 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
       riga::launch_gemm_tall(N, h->Vu, N, kin, dQ, kout, h->Vu2, N, h->st);
       riga::launch_gemm_tall(N, h->Vl, N, kin, dQ, kout, h->Vl2, N, h->st);
       riga::launch_gemm_tall(N, h->Wl, N, kin, dQ, kout, h->Wl2, N, h->st);
+      rs_bytes += 3.0 * 8.0 * (double)N * (kin + kout);
+      rs_flops += 3.0 * 2.0 * (double)N * kin * kout;
       std::swap(h->Vu, h->Vu2); std::swap(h->Vl, h->Vl2); std::swap(h->Wl, h->Wl2);
       kr.H = cyc.Hn;
       t_host += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - th0).count();
@@ -1407,12 +1468,11 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     }
     std::vector<int> order = canonical_order(lam_rq, h->sigma);
     const int nout = std::min(nev, nw);
-    int conv_out = converged ? nout : 0;
-    if (!converged) {
-      // count converged pairs in canonical order
-      for (int j = 0; j < nout; ++j) {
-        if (etav[order[j]] <= 1e-10) ++conv_out; else break;
-      }
+    // converged pairs: the leading ones in canonical order whose explicit
+    // scaled residual meets the bar (the Ritz estimate alone is not trusted)
+    int conv_out = 0;
+    for (int j = 0; j < nout; ++j) {
+      if (etav[order[j]] <= riga::detail::kEtaConverged) ++conv_out; else break;
     }
     for (int j = 0; j < nout; ++j) {
       lam[2 * j] = lam_rq[order[j]].real();
@@ -1447,7 +1507,30 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     h->stats.n_ir = h->mixed ? kr.n_fb * h->ir_sweeps : 0;
     h->stats.n_mv = kr.n_mv + h->stats.n_ir;   // one residual product per refinement sweep
     h->stats.n_vv = kr.n_vv;
+    {
+      // algorithmic work per phase (eq. Cost; the byte model is stated with riga_stats_t)
+      riga_stats_t& S = h->stats;
+      riga::Plan& Pm = h->plan;
+      Pm.ensure_symbolic();
+      const double Nd = (double)N, nnz = (double)Pm.nnz, irs = h->mixed ? h->ir_sweeps : 0;
+      const double vec = (double)kr.n_fb;                 // vectors through the operator
+      const double passes = vec / b * (1.0 + irs);        // sweep passes over the factor
+      S.bytes[RIGA_PHASE_FB] = passes * h->solve_bytes_now + vec * (1.0 + irs) * 16.0 * Nd;
+      S.flops[RIGA_PHASE_FB] = vec * (1.0 + irs) * 4.0 * (double)Pm.sym_nnz_l;
+      const double mv_bytes = 16.0 * Nd + (h->c_elem ? 8.0 * nnz + 16.0 * Nd : 16.0 * Nd);
+      S.bytes[RIGA_PHASE_MV] = vec * mv_bytes;
+      S.flops[RIGA_PHASE_MV] = (double)kr.n_mv * 2.0 * nnz;
+      S.bytes[RIGA_PHASE_VV] = (double)kr.n_vv * 8.0 * Nd;
+      S.flops[RIGA_PHASE_VV] = (double)kr.n_vv * 2.0 * Nd;
+      S.bytes[RIGA_PHASE_RESTART] = rs_bytes + 2.0 * 8.0 * Nd * (k + nw);
+      S.flops[RIGA_PHASE_RESTART] = rs_flops + 2.0 * 2.0 * Nd * k * nw;
+      S.bytes[RIGA_PHASE_IR] = passes > 0 && irs > 0 ? vec / b * irs * 8.0 * nnz + vec * irs * 24.0 * Nd : 0.0;
+      S.flops[RIGA_PHASE_IR] = vec * irs * 2.0 * nnz;
+      const double pv = 2.0 * nw;                         // planar real / imaginary parts
+      S.bytes[RIGA_PHASE_POST] = std::ceil(pv / 8.0) * 24.0 * nnz + pv * 32.0 * Nd;
+      S.flops[RIGA_PHASE_POST] = pv * 3.0 * 2.0 * nnz;
+    }
     if (nconv) *nconv = conv_out;
-    return converged ? RIGA_OK : RIGA_WARN_NOT_CONVERGED;
+    return (converged && conv_out == nev) ? RIGA_OK : RIGA_WARN_NOT_CONVERGED;
   });
 }

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
+#include <exception>
 #include <functional>
 #include <mutex>
 #include <numeric>
@@ -109,6 +110,12 @@ class HostPool {
     std::unique_lock<std::mutex> lk(mu_);
     done_cv_.wait(lk, [&] { return busy_ == 0; });
     job_ = nullptr;
+    std::exception_ptr e;
+    {
+      std::lock_guard<std::mutex> ek(err_mu_);
+      std::swap(e, err_);
+    }
+    if (e) std::rethrow_exception(e);
   }
 
  private:
@@ -124,8 +131,17 @@ class HostPool {
     cv_.notify_all();
     for (auto& t : th_) t.join();
   }
+  // A job that throws stops nothing else: the first exception is kept and
+  // rethrown on the calling thread once every worker is idle.
   void work() {
-    for (int i = next_.fetch_add(1); i < n_; i = next_.fetch_add(1)) (*job_)(i);
+    for (int i = next_.fetch_add(1); i < n_; i = next_.fetch_add(1)) {
+      try {
+        (*job_)(i);
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(err_mu_);
+        if (!err_) err_ = std::current_exception();
+      }
+    }
   }
   void loop() {
     uint64_t seen = 0;
@@ -142,7 +158,8 @@ class HostPool {
     }
   }
   std::vector<std::thread> th_;
-  std::mutex run_mu_, mu_;
+  std::mutex run_mu_, mu_, err_mu_;
+  std::exception_ptr err_;
   std::condition_variable cv_, done_cv_;
   const std::function<void(int)>* job_ = nullptr;
   int n_ = 0, busy_ = 0;
@@ -255,6 +272,7 @@ riga_status riga_batch_create(riga_batch** out, int n, const riga_mesh* meshes, 
   std::vector<int> bad(n, 0);
   parallel_for(n, [&](int i) {
     bad[i] = bh->plans[i].build(meshes[i].p, meshes[i].ne, meshes[i].hyper_every, meshes[i].leaf);
+    if (bad[i] == 0) bh->plans[i].ensure_symbolic();   // algorithmic factor flops of the forest
   });
   for (int i = 0; i < n; ++i)
     if (bad[i] != 0) {
@@ -435,6 +453,7 @@ riga_status riga_batch_assemble(riga_batch* bh, const riga_damping* damping) {
     const int n = bh->n;
     hipStream_t st = bh->user_st;
     ck(hipEventRecord(fp->ev0, st));
+    bh->clear_graphs();   // captured block steps hold the old operator coefficients
     bh->alpha.resize(n); bh->beta.resize(n); bh->celem.resize(n);
     for (int i = 0; i < n; ++i) {
       bh->alpha[i] = damping[i].alpha; bh->beta[i] = damping[i].beta; bh->celem[i] = damping[i].c_elem;
@@ -769,12 +788,12 @@ riga_status riga_batch_eigs(riga_batch* bh, const riga_options* opt, double* lam
       }
       std::vector<int> order = canonical_order(lrq[i], bh->sigma[i]);
       const int nout = std::min(nev, nw);
+      // leading pairs in canonical order whose explicit residual meets the bar
       int cnt = 0;
-      if (state[i] == CONVERGED) cnt = nout;
-      else
-        for (int j = 0; j < nout; ++j) {
-          if (etav[order[j]] <= 1e-10) ++cnt; else break;
-        }
+      for (int j = 0; j < nout; ++j) {
+        if (etav[order[j]] <= riga::detail::kEtaConverged) ++cnt; else break;
+      }
+      if (cnt < nev) all_conv = false;
       nconv[i] = cnt;
       for (int j = 0; j < nout; ++j) {
         lam[(size_t)i * 2 * nev + 2 * j] = lrq[i][order[j]].real();

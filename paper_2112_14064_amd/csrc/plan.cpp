@@ -68,6 +68,63 @@ int pick_cut(int lo, int hi, int s, int leaf) {
 
 }  // namespace
 
+void Plan::symbolic(std::vector<int64_t>* colcount, int64_t& nnz_l, double& flops) const {
+  const int64_t nd = ndof;
+  const int n = sp.n;
+  std::vector<int64_t> dof_at(nd);
+  for (int64_t d = 0; d < nd; ++d) dof_at[elim_pos[d]] = d;
+  // elimination tree by path compression (Liu): for row i, every earlier
+  // column k coupled to i reaches i through its root
+  std::vector<int64_t> parent(nd, -1), anc(nd, -1), cnt(nd, 1), mark(nd, -1);
+  auto neighbours = [&](int64_t i, auto&& f) {
+    const int64_t d = dof_at[i];
+    const int x = (int)(d % n), y = (int)(d / n);
+    for (int jj = sp.lo[y]; jj <= sp.hi[y]; ++jj)
+      for (int ii = sp.lo[x]; ii <= sp.hi[x]; ++ii) {
+        const int64_t k = elim_pos[(int64_t)jj * n + ii];
+        if (k < i) f(k);
+      }
+  };
+  for (int64_t i = 0; i < nd; ++i) {
+    neighbours(i, [&](int64_t k) {
+      int64_t r = k;
+      while (anc[r] != -1 && anc[r] != i) {
+        const int64_t t = anc[r];
+        anc[r] = i;
+        r = t;
+      }
+      if (anc[r] == -1) {
+        anc[r] = i;
+        parent[r] = i;
+      }
+    });
+  }
+  // row i of L is the union of the etree paths from its coupled columns up to
+  // i (the row subtree): every column met on them gains the entry (i, j)
+  for (int64_t i = 0; i < nd; ++i) {
+    mark[i] = i;
+    neighbours(i, [&](int64_t k) {
+      for (int64_t j = k; mark[j] != i; j = parent[j]) {
+        mark[j] = i;
+        ++cnt[j];
+      }
+    });
+  }
+  nnz_l = 0;
+  flops = 0.0;
+  for (int64_t j = 0; j < nd; ++j) {
+    nnz_l += cnt[j];
+    const double c = (double)(cnt[j] - 1);
+    flops += c * c + 2.0 * c;
+  }
+  if (colcount) *colcount = std::move(cnt);
+}
+
+void Plan::ensure_symbolic() {
+  if (sym_nnz_l >= 0) return;
+  symbolic(nullptr, sym_nnz_l, sym_flops);
+}
+
 void Plan::amalgamate() {
   const int nn = (int)nodes.size();
   if (amalg_group < 2 || nn < 2) return;
@@ -415,6 +472,13 @@ void Plan::merge(const std::vector<const Plan*>& parts, std::vector<int64_t>& do
     max_nb = std::max(max_nb, q.max_nb);
     flops_dense += q.flops_dense;
     solve_bytes += q.solve_bytes;
+    if (q.sym_nnz_l < 0 || (k > 0 && sym_nnz_l < 0)) {
+      sym_nnz_l = -1;
+      sym_flops = -1.0;
+    } else {
+      sym_nnz_l = (k == 0 ? 0 : sym_nnz_l) + q.sym_nnz_l;
+      sym_flops = (k == 0 ? 0.0 : sym_flops) + q.sym_flops;
+    }
   }
   foff[nn] = f_base[np];
   coff[nn] = c_base[np];

@@ -75,6 +75,18 @@ struct Plan {
 
   int build(int p, int ne, int s, int leaf);  // 0 ok, <0 invalid
 
+  // Symbolic Cholesky of the tensor sparsity under the elimination order of
+  // the plan (no dense-front zeros): per elimination position the nonzeros of
+  // its column of L (diagonal included), their sum nnz(L), and the flops
+  // sum_j (c_j^2 + 2 c_j) with c_j the off-diagonal count of column j.
+  // Single-space plans only (a forest sums its parts' totals).
+  void symbolic(std::vector<int64_t>* colcount, int64_t& nnz_l, double& flops) const;
+  // Cached totals of symbolic() (computed on first use; a forest sets them
+  // from its parts in merge()).
+  int64_t sym_nnz_l = -1;
+  double sym_flops = -1.0;
+  void ensure_symbolic();
+
   // Forest of independent problems: the plans of `parts` side by side, with
   // dofs, CSR rows, nodes and factor blocks numbered consecutively (part k's
   // dofs start at dof_base[k], its nodes at node_base[k]) and tree levels

@@ -91,8 +91,11 @@ struct riga_problem {
     }
     return pin;
   }
-  // (k, b, V_u, operator already applied): captured block steps
-  std::map<std::tuple<int, int, const double*, int>, hipGraphExec_t> graphs;
+  // (k, b, V_u, operator already applied, leading dimension of H): captured
+  // block steps.  They bake in the operator's coefficients (sigma, alpha,
+  // beta, the damping branch) and the factor, so assembling or factoring
+  // again drops them.
+  std::map<std::tuple<int, int, const double*, int, int>, hipGraphExec_t> graphs;
   double graph_sigma = 0.0;
   int64_t graph_key = 0;            // factor mode the captured graphs were recorded for
   // Mixed-precision factor: nodes of height < mixed_thr are FP32 (same offsets
@@ -106,6 +109,7 @@ struct riga_problem {
   unsigned char* d_prec = nullptr;
   int prec_thr = -1;                // threshold d_prec was written for
   int64_t n_ir = 0;                 // refinement sweeps issued outside the Krylov loop
+  double solve_bytes_now = 0.0;     // factor bytes one sweep pass reads (current precision)
   int64_t factor_key() const { return mixed ? 1 + (int64_t)ir_sweeps * 64 + (int64_t)mixed_thr * 4096 : 0; }
   bool level_f32(int lv) const { return mixed && lv < mixed_thr; }
 
@@ -138,6 +142,14 @@ struct riga_problem {
 
 namespace riga {
 namespace detail {
+
+// A returned eigenpair counts as converged when its scaled residual (Tisseur's
+// backward error of the QEP, 1-norms of K, C, M) is at most this.
+constexpr double kEtaConverged = 1e-10;
+// Mixed factor, refinement to the floor (ir_tol = 0): the calibration solve
+// must bring ||b - Q x|| / ||b|| to at most this before a sweep gains less
+// than a factor 4, else the refinement has stagnated.
+constexpr double kIrStagnation = 1e-10;
 
 // Maps the library's exceptions to status codes.
 riga_status run(const std::function<riga_status()>& f);

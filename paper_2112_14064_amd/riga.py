@@ -22,6 +22,7 @@ RIGA_ERR_HIP = -3
 RIGA_ERR_OOM = -4
 RIGA_ERR_STATE = -5
 RIGA_WARN_NOT_CONVERGED = 1
+RIGA_WARN_IR_STAGNATED = 2
 RIGA_IR_MAX = 10
 
 
@@ -43,13 +44,16 @@ class riga_info_t(C.Structure):
     _fields_ = [("n1d", C.c_int64), ("ndof", C.c_int64), ("nnz", C.c_int64), ("nnodes", C.c_int64),
                 ("nleaves", C.c_int64), ("height", C.c_int64), ("max_front", C.c_int64),
                 ("leaf_own", C.c_int64), ("factor_entries", C.c_int64),
-                ("factor_flops_dense", C.c_double), ("solve_bytes", C.c_double)]
+                ("factor_flops_dense", C.c_double), ("solve_bytes", C.c_double),
+                ("factor_nnz", C.c_int64), ("factor_flops", C.c_double)]
+
+PHASES = ("assemble", "factor", "fb", "mv", "vv", "restart", "ir", "post")
 
 
 class riga_stats_t(C.Structure):
     _fields_ = [("n_it", C.c_int64), ("n_fb", C.c_int64), ("n_mv", C.c_int64), ("n_vv", C.c_int64),
                 ("n_ir", C.c_int64), ("t_assemble_ms", C.c_double), ("t_factor_ms", C.c_double), ("t_eigs_ms", C.c_double),
-                ("t_host_ms", C.c_double)]
+                ("t_host_ms", C.c_double), ("bytes", C.c_double * 8), ("flops", C.c_double * 8)]
 
 
 EXPORTS = ["riga_create", "riga_info", "riga_assemble", "riga_export_csr", "riga_factor", "riga_factor_mixed",
@@ -57,7 +61,7 @@ EXPORTS = ["riga_create", "riga_info", "riga_assemble", "riga_export_csr", "riga
            "riga_batch_eigs", "riga_batch_stats", "riga_batch_destroy", "riga_autotune", "riga_sweep_shapes",
            "riga_batch_autotune",
            "riga_solve_q", "riga_apply_op", "riga_eigs", "riga_adjoint", "riga_stats", "riga_time_kernel",
-           "riga_selftest_small_eig", "riga_selftest_schur_restart", "riga_status_str", "riga_destroy"]
+           "riga_selftest_small_eig", "riga_selftest_schur_restart", "riga_symbolic", "riga_status_str", "riga_destroy"]
 
 _lib = None
 
@@ -91,6 +95,7 @@ def load(path: str = LIB_PATH):
                                      C.POINTER(C.c_double), C.POINTER(C.c_int)]
     lib.riga_selftest_small_eig.argtypes = [C.c_int, P, P, P]
     lib.riga_selftest_schur_restart.argtypes = [C.c_int, P, C.c_int, P, P, P, P]
+    lib.riga_symbolic.argtypes = [C.POINTER(riga_mesh), P, P, P, P, P]
     lib.riga_status_str.argtypes = [C.c_int]
     lib.riga_status_str.restype = C.c_char_p
     lib.riga_destroy.argtypes = [P]
@@ -124,6 +129,30 @@ def _check(status: int, where: str, allow_warn: bool = False) -> int:
     if status < 0 or (status > 0 and not allow_warn):
         raise RigaError(status, where)
     return status
+
+
+def _stats_dict(s) -> dict:
+    out = {f: getattr(s, f) for f, _ in riga_stats_t._fields_ if f not in ("bytes", "flops")}
+    out["bytes"] = {ph: float(s.bytes[i]) for i, ph in enumerate(PHASES)}
+    out["flops"] = {ph: float(s.flops[i]) for i, ph in enumerate(PHASES)}
+    return out
+
+
+def riga_symbolic(p: int, ne: int, hyper_every: int, leaf: int = 0):
+    """Host-only symbolic Cholesky of Q's sparsity under the library's
+    elimination order: (order, colcount, nnz_l, flops), order[k] the dof
+    eliminated k-th and colcount[k] the nonzeros of column k of L."""
+    lib = load()
+    mesh = riga_mesh(p, ne, hyper_every, leaf)
+    n = C.c_int64(0)
+    _check(lib.riga_symbolic(C.byref(mesh), C.byref(n), None, None, None, None), "riga_symbolic")
+    order = np.zeros(n.value, dtype=np.int64)
+    cc = np.zeros(n.value, dtype=np.int64)
+    nz = C.c_int64(0)
+    fl = C.c_double(0.0)
+    _check(lib.riga_symbolic(C.byref(mesh), None, order.ctypes.data_as(C.c_void_p), cc.ctypes.data_as(C.c_void_p),
+                             C.byref(nz), C.byref(fl)), "riga_symbolic")
+    return order, cc, nz.value, fl.value
 
 
 def _ptr(t):
@@ -237,7 +266,8 @@ class Problem:
             err = RigaError(st, where)
             err.bad_pivot = bad.value
             raise err
-        _check(st, where)
+        _check(st, where, allow_warn=(st == RIGA_WARN_IR_STAGNATED))
+        self.factor_status = st
         return hist
 
     def ir_sweeps(self) -> int:
@@ -320,7 +350,7 @@ class Problem:
     def stats(self):
         s = riga_stats_t()
         _check(self.lib.riga_stats(self.h, C.byref(s)), "riga_stats")
-        return {f: getattr(s, f) for f, _ in riga_stats_t._fields_}
+        return _stats_dict(s)
 
 
 class Batch:
@@ -421,6 +451,6 @@ class Batch:
         s = riga_stats_t()
         k = C.c_int(0)
         _check(self.lib.riga_batch_stats(self.h, C.byref(s), C.byref(k)), "riga_batch_stats")
-        out = {f: getattr(s, f) for f, _ in riga_stats_t._fields_}
+        out = _stats_dict(s)
         out["n_resolved"] = k.value
         return out

@@ -156,3 +156,52 @@ def test_restart_reordering_conjugate_pairs_and_reals():
     # closed under conjugation
     for x in w:
         assert np.min(np.abs(w - np.conj(x))) < 1e-10
+
+
+# --- algorithmic factorization flops (the cost C_fa of eq. Cost) --------------------
+
+@pytest.mark.parametrize("p,ne,s,leaf", [(2, 8, 4, 0), (3, 12, 4, 0), (2, 10, 0, 2), (3, 8, 0, 2), (2, 16, 4, 2)])
+def test_symbolic_counts_match_dense_cholesky(p, ne, s, leaf):
+    """The library's symbolic column counts under its own elimination order
+    equal the nonzero counts of a dense Cholesky of a matrix with Q(sigma)'s
+    pattern (taken from the oracle's assembly) permuted to that order: random
+    values on the pattern make numerical cancellation a measure-zero event."""
+    from oracle import assemble as oasm
+    order, cc, nnz_l, flops = riga.riga_symbolic(p, ne, s, leaf)
+    K, M, C_ = oasm.assemble(p, ne, s)
+    pat = (abs(K) + abs(M)).tocoo()
+    N = K.shape[0]
+    assert len(order) == N and sorted(order) == list(range(N))
+    rng = np.random.default_rng(p * 100 + ne)
+    A = np.zeros((N, N))
+    v = rng.uniform(0.5, 1.0, pat.nnz)
+    A[pat.row, pat.col] = v
+    A = A + A.T
+    A += np.diag(np.abs(A).sum(axis=1) + 1.0)           # SPD by diagonal dominance
+    L = np.linalg.cholesky(A[np.ix_(order, order)])
+    nzc = (np.abs(L) > 1e-13 * np.abs(L).max()).sum(axis=0)
+    assert np.array_equal(nzc, cc)
+    assert nnz_l == int(cc.sum())
+    c = cc - 1.0
+    assert flops == pytest.approx(float((c * c + 2 * c).sum()), rel=1e-15)
+    # fill-in happened (the count is not the pattern of A's lower triangle)
+    assert nnz_l > (pat.nnz + N) // 2
+
+
+def test_symbolic_riga_cheaper_than_iga():
+    """Sec. 5.2.1: at p = 3 the C^0 hyperplanes cut the factorization cost
+    (eq. CostFactIGA vs eq. CostFactrIGA) on a mesh large enough to show it."""
+    _, _, nz_i, fl_i = riga.riga_symbolic(3, 64, 0)
+    _, _, nz_r, fl_r = riga.riga_symbolic(3, 64, 16)
+    assert fl_r < 0.6 * fl_i and nz_r < nz_i
+
+
+def test_pins_catch_symbolic_without_fill():
+    """Planted mistake: counting only the pattern of A (no fill) fails the
+    dense-Cholesky pin above."""
+    from oracle import assemble as oasm
+    order, cc, _, _ = riga.riga_symbolic(2, 8, 4, 0)
+    K, M, _ = oasm.assemble(2, 8, 4)
+    A = (abs(K) + abs(M)).toarray()[np.ix_(order, order)]
+    nofill = (np.tril(A) != 0).sum(axis=0)
+    assert not np.array_equal(nofill, cc)

@@ -333,3 +333,126 @@ def test_pins_catch_transposed_derivative_sign():
     h = 1e-6
     fd = (obs.basis(kv, p, x + h) - obs.basis(kv, p, x - h)) / (2 * h)
     assert not np.allclose(bad, fd, atol=1e-3)
+
+
+# --- element mass, Q(lambda) and the scaled residual ---------------------------------
+
+def _scatter_element_masses(p, ne, s, elem_fn):
+    """sum_e M_e scattered to the Dirichlet dofs, with M_e from elem_fn."""
+    N = ospace.scalar_counts(p, ne, s)[0]
+    out = np.zeros((N, N))
+    for ey in range(ne):
+        for ex in range(ne):
+            dofs, Me = elem_fn(p, ne, s, ex, ey)
+            ok = np.flatnonzero((dofs >= 0) & (dofs < N))
+            out[np.ix_(dofs[ok], dofs[ok])] += Me[np.ix_(ok, ok)]
+    return out
+
+
+def _element_mass_swapped_xy(p, ne, s, ex, ey):
+    """Planted mistake: the y factor of the tensor basis taken from element ex."""
+    kv, first, B, D, w = oasm._element_tables(p, ne, s)
+    n1 = obs.n_functions(kv, p) - 2
+    nl = p + 1
+    Phi = np.einsum("yb,xa->yxba", B[ex], B[ey]).reshape(nl * nl, nl * nl)
+    Me = np.einsum("q,qa,qb->ab", np.outer(w, w).reshape(-1), Phi, Phi)
+    dofs = [(first[ey] + ly - 1) * n1 + (first[ex] + lx - 1)
+            if (1 <= first[ex] + lx <= n1 and 1 <= first[ey] + ly <= n1) else -1
+            for ly in range(nl) for lx in range(nl)]
+    return np.array(dofs), Me
+
+
+def _element_mass_no_dirichlet_mask(p, ne, s, ex, ey):
+    """Planted mistake: boundary functions are not dropped from the dof map."""
+    dofs, Me = oasm.element_mass_2d(p, ne, s, ex, ey)
+    kv, first, B, D, w = oasm._element_tables(p, ne, s)
+    n1 = obs.n_functions(kv, p) - 2
+    nl = p + 1
+    bad = np.array([(first[ey] + ly - 1) * n1 + (first[ex] + lx - 1) for ly in range(nl) for lx in range(nl)])
+    return bad, Me
+
+
+@pytest.mark.parametrize("p,ne,s", [(3, 8, 4), (2, 6, 0), (4, 8, 4)])
+def test_element_mass_2d_scatters_to_assembled_mass(p, ne, s):
+    """sum_e M_e = M (the mass form is additive over elements, Sec. 3.1): the
+    element matrices of element_mass_2d, scattered to their dofs, rebuild the
+    assembled M; and u^T M_e u agrees with the 1-D Kronecker route of the
+    adjoint's element forms (M_e = M1_ey (x) M1_ex on the tensor basis)."""
+    _, M, _ = oasm.assemble(p, ne, s)
+    Md = M.toarray()
+    S = _scatter_element_masses(p, ne, s, oasm.element_mass_2d)
+    assert np.abs(S - Md).max() <= 1e-15 * np.abs(Md).max()
+    u = np.random.default_rng(11).standard_normal(M.shape[0])
+    q = oadj.element_quadratic_forms(p, ne, s, u)[0]
+    for ex, ey in [(0, 0), (ne - 1, 1), (ne // 2, ne // 2 - 1), (1, ne - 1)]:
+        dofs, Me = oasm.element_mass_2d(p, ne, s, ex, ey)
+        ok = dofs >= 0
+        ue = u[dofs[ok]]
+        assert abs(ue @ Me[np.ix_(ok, ok)] @ ue - q[ey, ex]) <= 1e-14 * abs(q[ey, ex]) + 1e-18
+
+
+@pytest.mark.parametrize("bad", [_element_mass_swapped_xy, _element_mass_no_dirichlet_mask])
+def test_pins_catch_element_mass_mistakes(bad):
+    """A swapped tensor factor (elements differ in x and y near the
+    hyperplanes and the boundary) or a missing Dirichlet mask breaks the
+    scatter pin."""
+    p, ne, s = 3, 8, 4
+    Md = oasm.assemble(p, ne, s)[1].toarray()
+    S = _scatter_element_masses(p, ne, s, bad)
+    assert np.abs(S - Md).max() > 1e-6 * np.abs(Md).max()
+
+
+def test_q_matrix_annihilates_qz_eigenvectors():
+    """Q(lam) u = 0 for eigenpairs of the companion pencil (eq. QuadEig /
+    eq. Linearization), at complex lam: q_matrix is lam^2 M + lam C + K."""
+    K, M, C = oasm.assemble(2, 8, 4, 0.1, 0.01, np.random.default_rng(4).lognormal(-3, 0.5, (8, 8)))
+    lam, U = oeig.dense_qep(K, C, M)
+    scale = oeig.onenorm(K)
+    for k in oeig.canonical_order(lam, 1.0)[:8]:
+        assert abs(lam[k].imag) > 0.1
+        r = oasm.q_matrix(K, M, C, lam[k]) @ U[:, k]
+        assert np.linalg.norm(r) <= 1e-11 * scale * np.linalg.norm(U[:, k])
+
+
+def test_pins_catch_q_matrix_mistakes():
+    """sigma M for sigma^2 M, or C and M exchanged, leave a large residual."""
+    K, M, C = oasm.assemble(2, 8, 4, 0.1, 0.01)
+    lam, U = oeig.dense_qep(K, C, M)
+    k = oeig.canonical_order(lam, 1.0)[0]
+    u = U[:, k]
+    scale = oeig.onenorm(K) * np.linalg.norm(u)
+    for bad in (lam[k] * M + lam[k] * C + K, lam[k] ** 2 * C + lam[k] * M + K):
+        assert np.linalg.norm(bad @ u) > 1e-4 * scale
+
+
+_ETA_K = np.array([[4.0, 0.0], [3.0, 9.0]])    # column sums 7, 9; row sums 4, 12
+_ETA_C = np.array([[1.0, 2.0], [0.0, 0.5]])    # column sums 1, 2.5
+_ETA_M = np.array([[1.0, 0.0], [1.0, 2.0]])    # column sums 2, 2; row sums 1, 3
+_ETA_LAM = 1.0 + 1.0j
+_ETA_U = np.array([1.0, 1.0])
+
+
+def test_residual_hand_computed():
+    """eta for 2 x 2 coefficients worked by hand: lam = 1 + i, lam^2 = 2i,
+    Q(lam) u = K u + lam C u + lam^2 M u = [4 + 3 (1+i) + 2i, 12 + 0.5 (1+i) + 6i]
+    = [7 + 5i, 12.5 + 6.5i]; ||Q u||_2 = sqrt(49 + 25 + 156.25 + 42.25) = sqrt(272.5);
+    |lam|^2 ||M||_1 + |lam| ||C||_1 + ||K||_1 = 2*2 + sqrt(2)*2.5 + 9; ||u||_2 = sqrt(2)."""
+    eta = oeig.residual(_ETA_K, _ETA_C, _ETA_M, _ETA_LAM, _ETA_U)
+    want = math.sqrt(272.5) / ((4.0 + 2.5 * math.sqrt(2.0) + 9.0) * math.sqrt(2.0))
+    assert eta == pytest.approx(want, rel=1e-15)
+
+
+def test_pins_catch_residual_normalisation_mistakes():
+    """A dropped |lam|^2, the infinity norm or an unnormalised u give other values."""
+    want = math.sqrt(272.5) / ((4.0 + 2.5 * math.sqrt(2.0) + 9.0) * math.sqrt(2.0))
+    num = math.sqrt(272.5)
+    bads = [
+        num / ((2.0 * 2.0 ** 0.5 + 2.5 * math.sqrt(2.0) + 9.0) * math.sqrt(2.0)),   # |lam| for |lam|^2
+        num / ((2.0 * 3.0 + math.sqrt(2.0) * 3.0 + 12.0) * math.sqrt(2.0)),         # infinity norms
+        num / (4.0 + 2.5 * math.sqrt(2.0) + 9.0),                                   # ||u|| dropped
+    ]
+    for b in bads:
+        assert abs(b - want) > 1e-3 * want
+    # and the oracle's own value is not any of them
+    eta = oeig.residual(_ETA_K, _ETA_C, _ETA_M, _ETA_LAM, _ETA_U)
+    assert all(abs(eta - b) > 1e-3 * want for b in bads)
