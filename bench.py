@@ -239,6 +239,22 @@ def cpu_baseline(P, lam_gpu):
                       f"{t:.1f} s"}, rel_gpu
 
 
+COPY_BYTES = 512 * 1024 * 1024
+
+
+def copy_calibration(torch):
+    """A plain device-to-device copy of COPY_BYTES, three times: the HBM byte
+    counters a profiler reads for it, against the 2 x COPY_BYTES it must move,
+    scale the counters of the solver's kernels."""
+    a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": COPY_BYTES, "copies": 3}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +265,9 @@ def main():
     ap.add_argument("--no-iga", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 512 MiB device-to-device copy three times (the known-size "
+                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path",
@@ -256,6 +275,10 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
 
     from paper_2112_14064_amd import riga
     from paper_2112_14064_amd import workloads as W

@@ -142,3 +142,89 @@ def test_adjoint_full_size():
     ga = np.array([grad[divmod(int(e), P.ne)] for e in els])
     print("adjoint vs FD: max abs diff", np.abs(ga - fd).max(), "max |fd|", np.abs(fd).max(), flush=True)
     assert np.abs(ga - fd).max() <= 1e-5 * np.abs(fd).max() + 4e-13 / h
+
+
+def _secant_quotients(lp, Xp, lm, Xm, M, C0, dofs, Me, dc_minus):
+    """(lam_k(c + h e) - lam_k(c - h e)) / (2h) for every k, from the two
+    perturbed eigenpairs, without subtracting the eigenvalues.
+
+    With Q_pm(lam) = lam^2 M + lam C_pm + K and C_+ - C_- = 2h M_e:
+    x_-^T Q_+(lam_+) x_+ = 0 and x_-^T Q_-(lam_-) = 0 (complex-symmetric pencil)
+    give, after Q_-(lam_+) - Q_-(lam_-) = (lam_+ - lam_-) [(lam_+ + lam_-) M + C_-],
+        lam_+ - lam_- = -2h lam_+ x_-^T M_e x_+ / x_-^T [(lam_+ + lam_-) M + C_-] x_+,
+    an exact identity for exact pairs.  C_- = C0 + dc_minus M_e."""
+    MX = M @ Xp
+    CX = C0 @ Xp
+    out = np.zeros(len(lp), dtype=complex)
+    ok = dofs >= 0
+    d = dofs[ok]
+    Mee = Me[np.ix_(ok, ok)]
+    for k in range(len(lp)):
+        xm, xp = Xm[:, k], Xp[:, k]
+        num = xm[d] @ Mee @ xp[d]
+        den = xm @ ((lp[k] + lm[k]) * MX[:, k] + CX[:, k]) + dc_minus * num
+        out[k] = -lp[k] * num / den
+    return out
+
+
+@pytest.mark.timeout(900)
+def test_adjoint_full_size_central_differences_h1e6():
+    """The configured check of the p=3 512x512 workload: central differences
+    with h = 1e-6 on 32 seeded elements of L = sum Re lam over the 20
+    eigenvalues nearest sigma = 2, each L(c +- h e) from a full GPU solve.  The
+    difference of the two solves' eigenvalues is taken through the two-pencil
+    identity of _secant_quotients (oracle M, C and M_e), which is the central
+    quotient itself without the cancellation that limits a plain subtraction
+    to ~eps |lam| / h.  The identity is first checked against plain subtraction
+    at h = 1e-2, where both are resolved."""
+    from oracle.assemble import element_mass_2d
+    P = W.cfg_adjoint()
+    pr, lam, X = _solve(P.p, P.ne, P.hyper_every, P.c_elem, P.sigma, P.nev, m=P.m)
+    grad = pr.adjoint(lam, X, np.ones(P.nev, dtype=complex)).cpu().numpy()
+    pr.close()
+    print("[full] oracle assembly of M and C", flush=True)
+    K, M, C0 = oasm.assemble(P.p, P.ne, P.hyper_every, 0.0, 0.0, P.c_elem)
+    del K
+
+    def solve(cc):
+        pr2, l2, X2 = _solve(P.p, P.ne, P.hyper_every, cc, P.sigma, P.nev, m=P.m)
+        U2 = X2.cpu().numpy().T
+        pr2.close()
+        return l2, U2
+
+    def quotients(e, h):
+        ey, ex = divmod(int(e), P.ne)
+        cp, cm = P.c_elem.copy(), P.c_elem.copy()
+        cp[ey, ex] += h
+        cm[ey, ex] -= h
+        two_h = cp[ey, ex] - cm[ey, ex]          # exact spacing of the two FP64 inputs
+        lp, Xp = solve(cp)
+        lm, Xm = solve(cm)
+        dofs, Me = element_mass_2d(P.p, P.ne, P.hyper_every, ex, ey)
+        q = _secant_quotients(lp, Xp, lm, Xm, M, C0, dofs, Me, cm[ey, ex] - P.c_elem[ey, ex])
+        plain = (np.sum(lp.real) - np.sum(lm.real)) / two_h
+        return float(np.sum(q.real)), float(plain), float(abs(np.sum(lp.real)))
+
+    els = W.fd_elements(P.ne, 32, seed=2)
+    # the identity against plain subtraction where both are resolved
+    for e in els[:4]:
+        qi, qp, _ = quotients(e, 1e-2)
+        print(f"[full] h=1e-2 element {int(e)}: identity {qi:.12e} plain {qp:.12e}", flush=True)
+        assert abs(qi - qp) <= 1e-8 * abs(qp) + 1e-12
+    # the configured step
+    h = 1e-6
+    fd, plain, Ls = [], [], []
+    for e in els:
+        qi, qp, Lv = quotients(e, h)
+        fd.append(qi)
+        plain.append(qp)
+        Ls.append(Lv)
+        print(f"[full] h=1e-6 element {int(e)}: fd {qi:.6e} (plain subtraction {qp:.6e})", flush=True)
+    fd = np.array(fd)
+    ga = np.array([grad[divmod(int(e), P.ne)] for e in els])
+    eps = np.finfo(float).eps
+    bound = 1e-5 * np.abs(fd).max() + 4 * eps * max(Ls) / h
+    print(f"adjoint vs central differences (h=1e-6): max abs diff {np.abs(ga - fd).max():.3e}, "
+          f"max |fd| {np.abs(fd).max():.3e}, bound {bound:.3e}; plain subtraction max diff "
+          f"{np.abs(ga - np.array(plain)).max():.3e}", flush=True)
+    assert np.abs(ga - fd).max() <= bound

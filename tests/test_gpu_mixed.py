@@ -214,3 +214,26 @@ def test_precision_workload_full_size():
     print("[full] sampled row residuals", res.max(), flush=True)
     assert res.max() <= 1e-8
     pr.close()
+
+
+def test_stagnated_refinement_falls_back_to_fp64():
+    """A refinement target the FP32 factor cannot reach (below the FP64
+    residual floor) or a fixed sweep count that misses the caller's target
+    gives RIGA_WARN_IR_STAGNATED and leaves an FP64 factor: its solves equal
+    those of riga_factor bitwise.  Reachable targets keep the mixed factor."""
+    riga = _riga()
+    pr = _problem(4, 64, 32, 0.0, 0.0, W.lognormal_field(64, 0))
+    b = torch.from_numpy(np.random.default_rng(3).standard_normal((2, pr.ndof)))
+    pr.factor(5.0)
+    x64 = pr.solve_q(b)
+    for sweeps, tol in ((-1, 1e-30), (0, 1e-8), (1, 1e-12)):
+        print(f"[case] stagnation sweeps={sweeps} tol={tol}", flush=True)
+        pr.factor(5.0, "mixed", fp64_levels=1, ir_sweeps=sweeps, ir_tol=tol)
+        assert pr.factor_status == riga.RIGA_WARN_IR_STAGNATED
+        assert pr.ir_sweeps() == -1
+        assert torch.equal(pr.solve_q(b), x64)
+    for sweeps, tol in ((-1, 1e-9), (3, 1e-9), (2, 0.0)):
+        pr.factor(5.0, "mixed", fp64_levels=1, ir_sweeps=sweeps, ir_tol=tol)
+        assert pr.factor_status == riga.RIGA_OK
+        assert pr.ir_sweeps() >= 0
+    pr.close()

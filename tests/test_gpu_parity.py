@@ -223,3 +223,88 @@ def test_host_checked_path_matches_closed_form():
     K, M, C = oasm.assemble(P.p, P.ne, P.hyper_every, P.alpha, P.beta)
     _check_pairs(pr, lam, X, eta, K, C, M, ref, P.nev, P.sigma)
     pr.close()
+
+
+@pytest.mark.parametrize("s", [16, 0])
+def test_headline_workload_full_size(s):
+    """p=3 on 256x256, rIGA with C^0 hyperplanes every 16 elements (82,369 dofs)
+    and IGA (66,049 dofs), Rayleigh 0.05 M + 0.005 K, the 40 eigenpairs nearest
+    sigma = 2 with subspace 80: every eigenvalue against the closed form
+    (Kronecker sum of the 1-D pencil), the library's eta for all pairs and the
+    oracle's eta, M-normalisation and phase for sampled eigenvectors."""
+    P = W.cfg_riga_vs_iga(s)
+    pr = _problem(P.p, P.ne, P.hyper_every, P.alpha, P.beta)
+    assert pr.ndof == (82369 if s else 66049)
+    pr.factor(P.sigma)
+    lam, X, eta, nconv, st = pr.eigs(P.nev, P.m, block=2, seed=0)
+    assert st == 0 and nconv == P.nev
+    ref, _ = oeig.rayleigh_closed(P.p, P.ne, P.hyper_every, P.alpha, P.beta, P.sigma, P.nev)
+    rel = np.abs(lam - ref) / np.abs(ref)
+    print(f"[full] {P.name}: max rel err {rel.max():.2e}, max eta {eta.max():.2e}", flush=True)
+    assert rel.max() <= 1e-10
+    assert eta.max() <= 1e-10
+    K, M, C = oasm.assemble(P.p, P.ne, P.hyper_every, P.alpha, P.beta)
+    norms = (oeig.onenorm(K), oeig.onenorm(C), oeig.onenorm(M))
+    U = X.cpu().numpy().T
+    for k in np.random.default_rng(2).choice(P.nev, 6, replace=False):
+        u = U[:, k]
+        assert oeig.residual(K, C, M, lam[k], u, norms) <= 1e-10
+        assert abs(np.vdot(u, M @ u) - 1.0) < 1e-10
+    pr.close()
+
+
+def test_reassembly_and_subspace_change_on_one_handle():
+    """Captured block steps must not outlive the operator they were recorded
+    for: on one handle, a smaller subspace after a larger one, new Rayleigh
+    coefficients at the same shift, and a switch between Rayleigh and element
+    damping at the same shift each give the closed form / dense QZ."""
+    p, ne, s, sigma, nev = 2, 16, 4, 1.0, 6
+    pr = _problem(p, ne, s, 0.1, 0.01)
+    pr.factor(sigma)
+    for m in (40, 20):
+        lam, X, eta, nconv, st = pr.eigs(nev, m, block=2, seed=3)
+        ref, _ = oeig.rayleigh_closed(p, ne, s, 0.1, 0.01, sigma, nev)
+        print(f"[case] m={m} max rel err {np.max(np.abs(lam - ref) / np.abs(ref)):.2e}", flush=True)
+        assert st == 0 and np.max(np.abs(lam - ref) / np.abs(ref)) <= 1e-10
+    for a, b in ((0.3, 0.002), (0.02, 0.03)):
+        pr.assemble(a, b)
+        pr.factor(sigma)
+        lam, X, eta, nconv, st = pr.eigs(nev, 20, block=2, seed=3)
+        ref, _ = oeig.rayleigh_closed(p, ne, s, a, b, sigma, nev)
+        print(f"[case] alpha={a} beta={b} max rel err {np.max(np.abs(lam - ref) / np.abs(ref)):.2e}", flush=True)
+        assert st == 0 and np.max(np.abs(lam - ref) / np.abs(ref)) <= 1e-10
+    c = W.lognormal_field(ne, 21)
+    pr.assemble(0.0, 0.0, torch.from_numpy(c))
+    pr.factor(sigma)
+    lam, X, eta, nconv, st = pr.eigs(nev, 20, block=2, seed=3)
+    K, M, C = oasm.assemble(p, ne, s, 0.0, 0.0, c)
+    ref = oeig.nearest(oeig.dense_qep(K, C, M)[0], sigma, nev)
+    assert st == 0 and np.max(np.abs(lam - ref) / np.abs(ref)) <= 1e-10
+    pr.assemble(0.1, 0.01)
+    pr.factor(sigma)
+    lam, X, eta, nconv, st = pr.eigs(nev, 20, block=2, seed=3)
+    ref, _ = oeig.rayleigh_closed(p, ne, s, 0.1, 0.01, sigma, nev)
+    assert st == 0 and np.max(np.abs(lam - ref) / np.abs(ref)) <= 1e-10
+    pr.close()
+
+
+def test_stats_follow_the_cost_model():
+    """Per-phase counters of riga_stats (eq. Cost): the factorization flops are
+    the symbolic count, the eliminations 4 nnz(L) per vector, the products
+    2 nnz per product, and every phase that ran has work."""
+    P = W.cfg_small()
+    pr = _problem(P.p, P.ne, P.hyper_every, P.alpha, P.beta)
+    pr.factor(P.sigma)
+    lam, X, eta, nconv, st = pr.eigs(P.nev, P.m, block=2, seed=0)
+    s_ = pr.stats()
+    inf = pr.info
+    _, cc, nz, fl = _riga().riga_symbolic(P.p, P.ne, P.hyper_every)
+    assert inf["factor_nnz"] == nz and inf["factor_flops"] == fl
+    assert s_["flops"]["factor"] == fl
+    assert s_["flops"]["fb"] == pytest.approx(s_["n_fb"] * 4.0 * nz)
+    assert s_["flops"]["mv"] == pytest.approx(s_["n_mv"] * 2.0 * inf["nnz"])
+    assert s_["flops"]["vv"] == pytest.approx(s_["n_vv"] * 2.0 * pr.ndof)
+    for ph in ("assemble", "factor", "fb", "mv", "vv", "restart", "post"):
+        assert s_["bytes"][ph] > 0, ph
+    assert s_["bytes"]["ir"] == 0 and s_["flops"]["ir"] == 0
+    pr.close()
