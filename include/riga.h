@@ -50,6 +50,8 @@ typedef enum {
   RIGA_ERR_HIP = -3,           /* a HIP runtime call failed                    */
   RIGA_ERR_OOM = -4,           /* device allocation failed                     */
   RIGA_ERR_STATE = -5,         /* call out of order (e.g. eigs before factor)  */
+  RIGA_ERR_SCRATCH = -6,       /* riga_solve_q_noalloc: the solve needs more
+                                  than RIGA_NOALLOC_SCRATCH_BYTES of workspace */
   RIGA_WARN_NOT_CONVERGED = 1, /* eigs stopped at maxit, or fewer than nev pairs
                                   meet eta <= 1e-10: nconv < nev               */
   RIGA_WARN_IR_STAGNATED = 2    /* riga_factor_mixed: the refinement missed its
@@ -123,6 +125,8 @@ typedef struct {
   double  factor_flops; /* algorithmic factorization flops of that order:
                            sum_j (c_j^2 + 2 c_j), c_j = off-diagonal nonzeros
                            of column j of L (the cost C_fa of eq. Cost)        */
+  int64_t upd_len;      /* entries of the update vectors one right-hand side
+                           passes up the tree in a forward sweep              */
 } riga_info_t;
 
 /* Phases of the per-phase counters in riga_stats_t (eq. Cost of Sec. 5.1 and
@@ -254,6 +258,24 @@ riga_status riga_ir_sweeps(const riga_problem* h, int* sweeps);
  * (Sec. 5.2.2).  b, x: device, ndof x nrhs column-major, 1 <= nrhs <= 4;
  * x may alias b.                                                             */
 riga_status riga_solve_q(riga_problem* h, int nrhs, const double* b, double* x);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): riga_solve_q
+ * with the same kernels, whose workspace (the forward sweep's result, the
+ * update vectors passed up the tree and, for a mixed factor, the refinement's
+ * iterate, residual and correction) lives in one static device array of
+ * RIGA_NOALLOC_SCRATCH_BYTES per GPU instead of the handle's buffers.  The
+ * call allocates nothing and queues its work like riga_solve_q.
+ *   Needed workspace: 8 nrhs (ndof + upd_len) bytes for an FP64 factor and
+ *   8 nrhs (4 ndof + upd_len) for a mixed one (ndof, upd_len from riga_info);
+ *   a larger need returns RIGA_ERR_SCRATCH before anything is queued.
+ * The array of a GPU is shared by every call on it and keeps the last call's
+ * contents (a solve writes every entry before reading it): calls that overlap
+ * on one GPU (several host threads, or several streams in flight) race.  The
+ * device address of the array is looked up once per GPU, on the first call
+ * there; the array lives until the process ends.                           */
+#define RIGA_NOALLOC_SCRATCH_BYTES (64ull << 20)
+riga_status riga_solve_q_noalloc(riga_problem* h, int nrhs, const double* b, double* x);
 
 /* r = (A - sigma B)^{-1} B v for the companion pencil of eq. Linearization,
  * applied blockwise as in eq. BlockOperatorVector:

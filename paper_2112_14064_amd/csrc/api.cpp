@@ -105,19 +105,25 @@ riga_status run(const std::function<riga_status()>& f) {
 // ---- forward / backward solve -------------------------------------------------
 // One forward and one backward sweep over all levels, each level with the
 // precision its factor blocks were computed in.
-void sweep(riga_problem* h, int nrhs, const double* b, int64_t ldb, const riga::BwdOut& o) {
+SolveWork handle_work(const riga_problem* h) {
+  return SolveWork{h->d_tmp, h->d_upd, h->d_irX, h->d_irR, h->d_irD};
+}
+
+void sweep(riga_problem* h, int nrhs, const double* b, int64_t ldb, const riga::BwdOut& o, const SolveWork* w) {
+  const SolveWork hw = handle_work(h);
+  if (w == nullptr) w = &hw;
   const riga::Plan& P = h->plan;
   const int H = P.height;
   for (int lv = 0; lv < H; ++lv) {
     int a = h->ftask_off[lv], c = h->ftask_off[lv + 1] - a;
     const bool f32 = h->level_f32(lv);
-    riga::launch_fwd_level(h->dt, h->d_ftasks + a, c, nrhs, h->d_Lp, f32 ? h->d_Lp32 : nullptr, b, ldb, h->d_tmp,
-                           h->N(), h->d_upd, h->lvl_max_nf[lv], h->fvar[lv], h->st);
+    riga::launch_fwd_level(h->dt, h->d_ftasks + a, c, nrhs, h->d_Lp, f32 ? h->d_Lp32 : nullptr, b, ldb, w->tmp,
+                           h->N(), w->upd, h->lvl_max_nf[lv], h->fvar[lv], h->st);
   }
   for (int lv = H - 1; lv >= 0; --lv) {
     int a = h->btask_off[lv], c = h->btask_off[lv + 1] - a;
     const bool f32 = h->level_f32(lv);
-    riga::launch_bwd_level(h->dt, h->d_btasks + a, c, nrhs, h->d_Tp, f32 ? h->d_Tp32 : nullptr, h->d_tmp, h->N(), o,
+    riga::launch_bwd_level(h->dt, h->d_btasks + a, c, nrhs, h->d_Tp, f32 ? h->d_Tp32 : nullptr, w->tmp, h->N(), o,
                            h->lvl_max_nf[lv], h->bvar[lv], h->st);
   }
 }
@@ -127,32 +133,34 @@ void sweep(riga_problem* h, int nrhs, const double* b, int64_t ldb, const riga::
 // FP64 residuals: x_0 = Q~^{-1} b, x_k = x_{k-1} + Q~^{-1}(b - Q x_{k-1}).
 // b is read for the last time before x or r_l is written, so either may alias it.
 void solve_levels(riga_problem* h, int nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
-                  double* r_l, const double* v_u, int64_t ldv, double sig) {
+                  double* r_l, const double* v_u, int64_t ldv, double sig, const SolveWork* w) {
+  const SolveWork hw = handle_work(h);
+  if (w == nullptr) w = &hw;
   const int K = h->mixed ? h->ir_sweeps : 0;
   riga::BwdOut o;
   if (K == 0) {
     o.xs = x; o.ldxs = ldx; o.neg = r_l != nullptr ? 1 : 0;
     o.rl = r_l; o.v_u = v_u; o.ldv = ldv; o.ldr = ldx; o.sig = sig;
-    sweep(h, nrhs, b, ldb, o);
+    sweep(h, nrhs, b, ldb, o, w);
     return;
   }
   const int64_t N = h->N();
-  o.xs = h->d_irX; o.ldxs = N;
-  sweep(h, nrhs, b, ldb, o);
+  o.xs = w->irX; o.ldxs = N;
+  sweep(h, nrhs, b, ldb, o, w);
   for (int k = 1; k <= K; ++k) {
-    riga::launch_spmv(h->ds, N, nrhs, h->d_Q, -1.0, h->d_irX, N, h->d_irR, N, b, ldb,
+    riga::launch_spmv(h->ds, N, nrhs, h->d_Q, -1.0, w->irX, N, w->irR, N, b, ldb,
                       1.0, nullptr, 0, h->st);
     riga::BwdOut c;
-    c.xs = h->d_irD; c.ldxs = N;
-    c.base = h->d_irX; c.ldbase = N;
+    c.xs = w->irD; c.ldxs = N;
+    c.base = w->irX; c.ldbase = N;
     if (k < K) {
-      c.ru = h->d_irX; c.ldr = N;
+      c.ru = w->irX; c.ldr = N;
     } else {
       c.ru = x; c.ldr = ldx;
       c.scale = r_l != nullptr ? -1.0 : 1.0;
       c.rl = r_l; c.v_u = v_u; c.ldv = ldv; c.sig = sig;
     }
-    sweep(h, nrhs, h->d_irR, N, c);
+    sweep(h, nrhs, w->irR, N, c, w);
   }
 }
 
@@ -350,6 +358,7 @@ const char* riga_status_str(riga_status s) {
     case RIGA_ERR_HIP: return "HIP runtime error";
     case RIGA_ERR_OOM: return "out of device memory";
     case RIGA_ERR_STATE: return "call out of order";
+    case RIGA_ERR_SCRATCH: return "the solve needs more workspace than the static scratch array holds (RIGA_NOALLOC_SCRATCH_BYTES)";
     case RIGA_WARN_NOT_CONVERGED: return "not all requested eigenpairs converged";
     case RIGA_WARN_IR_STAGNATED: return "iterative refinement of the mixed factor stagnated; factored in FP64";
   }
@@ -414,6 +423,7 @@ riga_status riga_info(const riga_problem* h, riga_info_t* info) {
   const_cast<riga::Plan&>(P).ensure_symbolic();   // cached on the handle
   info->factor_nnz = P.sym_nnz_l;
   info->factor_flops = P.sym_flops;
+  info->upd_len = h->upd_len;
   return RIGA_OK;
 }
 

@@ -162,10 +162,21 @@ void setup_device(riga_problem* h);
 // Sliced-ELL slabs over the row ranges {problem, first row, end row} and the
 // two ELL value arrays.
 void setup_ell(riga_problem* h, const std::vector<int4>& ranges);
-// Solves with the factor (see api.cpp).
-void sweep(riga_problem* h, int nrhs, const double* b, int64_t ldb, const riga::BwdOut& o);
+// Device workspace of a solve: the forward sweep's result (tmp, ndof x nrhs),
+// the update vectors passed up the tree (upd, upd_len x nrhs) and, for a mixed
+// factor, the refinement's iterate, residual and correction (ndof x nrhs
+// each).  Every entry a solve reads from it was written earlier in the same
+// solve, so the contents between solves do not matter.
+struct SolveWork {
+  double *tmp, *upd, *irX, *irR, *irD;
+};
+// The handle's own workspace (allocated with the handle and the mixed factor).
+SolveWork handle_work(const riga_problem* h);
+// Solves with the factor (see api.cpp); w = nullptr takes the handle's workspace.
+void sweep(riga_problem* h, int nrhs, const double* b, int64_t ldb, const riga::BwdOut& o,
+           const SolveWork* w = nullptr);
 void solve_levels(riga_problem* h, int nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
-                  double* r_l, const double* v_u, int64_t ldv, double sig);
+                  double* r_l, const double* v_u, int64_t ldv, double sig, const SolveWork* w = nullptr);
 void factor_level(riga_problem* h, int lv, double sigma);
 // Factor every level; RIGA_ERR_NOT_SPD with *bad_pivot (a dof) on a failed pivot.
 riga_status factor_all(riga_problem* h, double sigma, int64_t* bad_pivot);

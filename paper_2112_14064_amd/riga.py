@@ -21,6 +21,7 @@ RIGA_ERR_NOT_SPD = -2
 RIGA_ERR_HIP = -3
 RIGA_ERR_OOM = -4
 RIGA_ERR_STATE = -5
+RIGA_ERR_SCRATCH = -6
 RIGA_WARN_NOT_CONVERGED = 1
 RIGA_WARN_IR_STAGNATED = 2
 RIGA_IR_MAX = 10
@@ -45,7 +46,7 @@ class riga_info_t(C.Structure):
                 ("nleaves", C.c_int64), ("height", C.c_int64), ("max_front", C.c_int64),
                 ("leaf_own", C.c_int64), ("factor_entries", C.c_int64),
                 ("factor_flops_dense", C.c_double), ("solve_bytes", C.c_double),
-                ("factor_nnz", C.c_int64), ("factor_flops", C.c_double)]
+                ("factor_nnz", C.c_int64), ("factor_flops", C.c_double), ("upd_len", C.c_int64)]
 
 PHASES = ("assemble", "factor", "fb", "mv", "vv", "restart", "ir", "post")
 
@@ -60,7 +61,7 @@ EXPORTS = ["riga_create", "riga_info", "riga_assemble", "riga_export_csr", "riga
            "riga_ir_sweeps", "riga_batch_create", "riga_batch_info", "riga_batch_assemble", "riga_batch_factor",
            "riga_batch_eigs", "riga_batch_stats", "riga_batch_destroy", "riga_autotune", "riga_sweep_shapes",
            "riga_batch_autotune",
-           "riga_solve_q", "riga_apply_op", "riga_eigs", "riga_adjoint", "riga_stats", "riga_time_kernel",
+           "riga_solve_q", "riga_solve_q_noalloc", "riga_apply_op", "riga_eigs", "riga_adjoint", "riga_stats", "riga_time_kernel",
            "riga_selftest_small_eig", "riga_selftest_schur_restart", "riga_symbolic", "riga_status_str", "riga_destroy"]
 
 _lib = None
@@ -87,6 +88,7 @@ def load(path: str = LIB_PATH):
     lib.riga_factor_mixed.argtypes = [P, C.c_double, C.c_int, C.c_int, C.c_double, P, C.POINTER(C.c_int64)]
     lib.riga_ir_sweeps.argtypes = [P, C.POINTER(C.c_int)]
     lib.riga_solve_q.argtypes = [P, C.c_int, P, P]
+    lib.riga_solve_q_noalloc.argtypes = [P, C.c_int, P, P]
     lib.riga_apply_op.argtypes = [P, C.c_int, P, P]
     lib.riga_eigs.argtypes = [P, C.POINTER(riga_options), P, P, P, C.POINTER(C.c_int)]
     lib.riga_adjoint.argtypes = [P, C.c_int, P, P, P, P]
@@ -282,6 +284,14 @@ class Problem:
         x = self.torch.empty_like(b)
         _check(self.lib.riga_solve_q(self.h, b.shape[0], _ptr(b), _ptr(x)), "riga_solve_q")
         return x
+
+    def solve_q_noalloc(self, b, x):
+        """riga_solve_q_noalloc: x = Q(sigma)^{-1} b with the library's static
+        workspace; b, x: caller-allocated (nrhs, ndof) tensors on the device."""
+        assert b.is_contiguous() and x.is_contiguous() and b.shape == x.shape
+        assert b.dtype == self.torch.float64 and x.dtype == self.torch.float64
+        return _check(self.lib.riga_solve_q_noalloc(self.h, b.shape[0], _ptr(b), _ptr(x)),
+                      "riga_solve_q_noalloc")
 
     def apply_op(self, v):
         """r = (A - sigma B)^{-1} B v for v of shape (nvec, 2*ndof)."""
