@@ -21,4 +21,6 @@ Modules
               form, sparse shift-and-invert (eq. BlockOperatorVector), residual,
               canonical ordering
     adjoint   d lam / d c_e for a per-element damping field
+    gep       the undamped pencil K u = mu M u: closed-form eigenvalues in an interval,
+              dense solver, inertia counts (Sec. 4.1.4, spectrum slicing), residual
 """
