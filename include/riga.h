@@ -367,6 +367,53 @@ riga_status riga_selftest_small_eig(int n, const double* a, double* w, double* r
 riga_status riga_selftest_schur_restart(int n, const double* a, int nkeep, int* r, double* w, double* resid,
                                         int* real_path);
 
+/* ---- Undamped problem: K u = mu M u with spectrum slicing --------------------
+ * With C = 0 the QEP of eq. QuadEig reduces to the Hermitian definite pencil
+ * K u = mu M u (lam^2 = -mu, the non-conductive case), whose eigenvalues are
+ * real and positive.  Sec. 4.1.4 (spectrum slicing): for K - s M = L D L^T,
+ * Sylvester's law of inertia makes the number of negative pivots the number of
+ * eigenvalues below s, so an interval splits into slices of known counts; each
+ * slice is solved by the Lanczos recurrence (the Lanczos remark of Sec. 4.1.2:
+ * the projected matrix of this operator is symmetric) on the shift-and-invert
+ * operator (K - s M)^{-1} M of a shift inside it, with Krylov--Schur (thick)
+ * restarts (Sec. 4.1.3).  Requires riga_assemble; its damping is ignored.   */
+
+/* Factor K - shift M over the nested-dissection tree in the signed form
+ * L S L^T (LDL^T without pivoting, S = diag(+-1) folded into L; any real
+ * shift) and return *neg_count = the number of negative pivots = the number of
+ * eigenvalues mu < shift, with multiplicity (neg_count host, or NULL).
+ * RIGA_ERR_NOT_SPD when a pivot is zero or NaN (shift on an eigenvalue to
+ * working precision), with *bad_pivot (host, or NULL) as for riga_factor.
+ * Synchronises.  Afterwards riga_solve_q and riga_solve_q_noalloc solve with
+ * K - shift M; riga_eigs and riga_apply_op return RIGA_ERR_STATE until
+ * riga_factor or riga_factor_mixed factors Q(sigma) again.                   */
+riga_status riga_factor_gep(riga_problem* h, double shift, int64_t* neg_count, int64_t* bad_pivot);
+
+/* Every eigenvalue of K u = mu M u in [a, b) (a < b) with its eigenvector, by
+ * spectrum slicing:
+ *   1. count = nu(b) - nu(a) from two signed factorizations;
+ *   2. a slice holding more than max_slice eigenvalues (0: 40; >= 2) is
+ *      bisected at its midpoint, whose count costs one factorization;
+ *   3. each slice [l, r) with k > 0 eigenvalues is factored at its midpoint s
+ *      (moved by 1e-9 relative if a pivot vanishes) and solved by block Lanczos
+ *      (opt->block, 0: 2; opt->tol, opt->maxit, opt->seed as for riga_eigs;
+ *      opt->nev, opt->m and opt->keep are chosen per slice: the k + 2 values of
+ *      theta = 1/(mu - s) of largest modulus, subspace max(2 (k + 2), 20)); the
+ *      converged values with mu in [l, r) are returned.
+ *   cap    room (pairs) in mu / U / resid; count > cap gives RIGA_ERR_INVALID_ARG
+ *          with *count written.
+ *   mu     host, cap doubles: the eigenvalues, ascending.
+ *   U      device, ndof x cap column-major, or NULL: M-orthonormal eigenvectors.
+ *   resid  host, cap doubles, or NULL (needs U): ||K u - mu M u||_2 /
+ *          ((||K||_1 + |mu| ||M||_1) ||u||_2).
+ *   count  host: nu(b) - nu(a).   found: host: pairs returned.
+ *   stats  host, 4 int64 or NULL: factorizations, slices, operator applications,
+ *          restarts.
+ * RIGA_WARN_NOT_CONVERGED when a slice returns fewer pairs than its count.
+ * Synchronises; leaves the handle factored at the last slice's shift.        */
+riga_status riga_gep_slice(riga_problem* h, double a, double b, int max_slice, const riga_options* opt, int cap,
+                           double* mu, double* U, double* resid, int64_t* count, int* found, int64_t* stats);
+
 /* ---- Batched form -----------------------------------------------------------
  * The paper solves one problem at a time; every problem here follows the
  * single-problem method above (Alg. 2 on the pencil of eq. Linearization with

@@ -335,10 +335,8 @@ void setup_device(riga_problem* h) {
     h->d_upd = h->dalloc<double>((size_t)h->upd_len * 4);
     h->d_tmp = h->dalloc<double>((size_t)P.ndof * 4);
     h->d_tmp2 = h->dalloc<double>((size_t)P.ndof * 4);
-    h->d_status = h->dalloc<int64_t>(1);
+    h->d_status = h->dalloc<int64_t>(2);
     h->d_part = h->dalloc<double>((size_t)512 * 400 * 4 + 64);
-    h->d_ticket = h->dalloc<unsigned>(4);
-    ck(hipMemset(h->d_ticket, 0, 4 * sizeof(unsigned)));
     ck(hipEventCreate(&h->ev0));
     ck(hipEventCreate(&h->ev1));
     ck(hipEventCreateWithFlags(&h->ev_fence, hipEventDisableTiming));
@@ -453,9 +451,9 @@ riga_status riga_assemble(riga_problem* h, const riga_damping* damping) {
     ck(hipSetDevice(h->device));
     ck(hipEventRecord(h->ev0, h->st));
     riga::launch_bspline_tables(h->ds, h->d_gx, h->d_gw, h->d_tabM, h->d_tabK, h->st);
-    riga::launch_assemble(h->ds, h->d_tabM, h->d_tabK, damping->alpha, damping->beta, damping->c_elem,
-                          h->d_K, h->d_M, h->d_C, h->N(), h->st);
     riga::launch_band_1d(h->ds, h->d_tabM, h->d_tabK, h->d_M1, h->d_K1, h->st);
+    riga::launch_assemble(h->ds, h->d_tabM, h->d_M1, h->d_K1, damping->alpha, damping->beta, damping->c_elem,
+                          h->d_K, h->d_M, h->d_C, h->N(), h->st);
     ck(hipGetLastError());
     ck(hipEventRecord(h->ev1, h->st));
     h->alpha = damping->alpha; h->beta = damping->beta; h->c_elem = damping->c_elem;
@@ -499,28 +497,31 @@ riga_status riga_export_csr(riga_problem* h, int which, int64_t* rowptr, int32_t
 namespace riga {
 namespace detail {
 
-// Factor level lv of the tree (FP32 if the mixed threshold says so).
-void factor_level(riga_problem* h, int lv, double sigma) {
+// Factor level lv of the tree (FP32 if the mixed threshold says so): the
+// fronts of s2 M + s1 C + K.
+void factor_level(riga_problem* h, int lv, double s2, double s1) {
   const riga::Plan& P = h->plan;
   int a = P.level_off[lv], c = P.level_off[lv + 1] - a;
   riga::DevTree t = h->dt;
   if (h->mixed) t.prec = h->d_prec;
   if (h->level_f32(lv))
     riga::launch_front_factor(h->ds, t, h->d_level_nodes + a, c, h->lvl_max_no[lv], h->lvl_max_nf[lv],
-                              h->lvl_max_cnb[lv], h->lvl_max_kids[lv], sigma * sigma, sigma, h->d_K, h->d_M, h->d_C, h->d_L32, h->d_U32,
+                              h->lvl_max_cnb[lv], h->lvl_max_kids[lv], s2, s1, h->d_K, h->d_M, h->d_C, h->d_L32, h->d_U32,
                               h->d_T32, h->d_D32, h->d_Lp32, h->d_Tp32, h->d_status, h->st);
   else
     riga::launch_front_factor(h->ds, t, h->d_level_nodes + a, c, h->lvl_max_no[lv], h->lvl_max_nf[lv],
-                              h->lvl_max_cnb[lv], h->lvl_max_kids[lv], sigma * sigma, sigma, h->d_K, h->d_M, h->d_C, h->d_L, h->d_U,
+                              h->lvl_max_cnb[lv], h->lvl_max_kids[lv], s2, s1, h->d_K, h->d_M, h->d_C, h->d_L, h->d_U,
                               h->d_T, h->d_D, h->d_Lp, h->d_Tp, h->d_U32, h->d_status, h->st);
 }
 
 // Factor every level; RIGA_ERR_NOT_SPD with *bad_pivot on a failed pivot.
 riga_status factor_all(riga_problem* h, double sigma, int64_t* bad_pivot) {
   const riga::Plan& P = h->plan;
+  h->dt.sgn = nullptr;
+  h->gep = false;
   ck(hipMemsetAsync(h->d_status, 0xFF, sizeof(int64_t), h->st));
   ck(hipEventRecord(h->ev0, h->st));
-  for (int lv = 0; lv < P.height; ++lv) factor_level(h, lv, sigma);
+  for (int lv = 0; lv < P.height; ++lv) factor_level(h, lv, sigma * sigma, sigma);
   // sigma M + C for the operator, Q(sigma) for the residuals of the mixed factor
   riga::launch_combine3(P.nnz, sigma, h->d_M, 1.0, h->d_C, 0.0, h->d_K, h->d_A, h->st);
   // (a forest combines its per-problem shifts itself and converts then; without
@@ -559,6 +560,36 @@ riga_status factor_all(riga_problem* h, double sigma, int64_t* bad_pivot) {
   return RIGA_OK;
 }
 
+riga_status factor_gep_all(riga_problem* h, double shift, int64_t* bad_pivot, int64_t* negs) {
+  const riga::Plan& P = h->plan;
+  h->clear_graphs();
+  h->mixed = false;
+  h->factored = false;
+  if (h->d_sgn == nullptr) h->d_sgn = h->dalloc<double>((size_t)h->N());
+  h->dt.sgn = h->d_sgn;
+  h->gep = true;
+  ck(hipMemsetAsync(h->d_status, 0xFF, sizeof(int64_t), h->st));   // no failed pivot
+  ck(hipMemsetAsync(h->d_status + 1, 0, sizeof(int64_t), h->st));   // no negative pivot
+  ck(hipEventRecord(h->ev0, h->st));
+  for (int lv = 0; lv < P.height; ++lv) factor_level(h, lv, -shift, 0.0);
+  ck(hipGetLastError());
+  ck(hipEventRecord(h->ev1, h->st));
+  int64_t stat[2] = {-1, 0};
+  ck(hipMemcpyAsync(stat, h->d_status, sizeof(stat), hipMemcpyDeviceToHost, h->st));
+  ck(hipStreamSynchronize(h->st));
+  float ms = 0;
+  ck(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+  h->stats.t_factor_ms = ms;
+  if (negs) *negs = stat[1];
+  if (stat[0] >= 0) {
+    if (bad_pivot) *bad_pivot = stat[0];
+    return RIGA_ERR_NOT_SPD;
+  }
+  h->sigma = shift;
+  h->factored = true;
+  return RIGA_OK;
+}
+
 // ||b - Q x|| / ||b|| history of a refined solve of one seeded right-hand side
 // (hist[0] after the unrefined solve, hist[k] after k refinement sweeps).
 void ir_history(riga_problem* h, int kmax, std::vector<double>& hist) {
@@ -568,7 +599,7 @@ void ir_history(riga_problem* h, int kmax, std::vector<double>& hist) {
   const int nblk = riga::dots_blocks(N);
   double* out = h->d_part + nblk + 8;
   auto norm2 = [&](const double* v) {
-    riga::launch_dots(N, 1, v, nullptr, N, 1, v, nullptr, N, h->d_part, h->d_ticket, out, h->st);
+    riga::launch_dots(N, 1, v, nullptr, N, 1, v, nullptr, N, h->d_part, out, h->st);
     double r = 0;
     ck(hipMemcpyAsync(&r, out, sizeof(double), hipMemcpyDeviceToHost, h->st));
     ck(hipStreamSynchronize(h->st));
@@ -807,7 +838,7 @@ riga_status riga_solve_q(riga_problem* h, int nrhs, const double* b, double* x) 
 
 riga_status riga_apply_op(riga_problem* h, int nvec, const double* v, double* r) {
   if (!h || nvec < 1 || nvec > 4 || !v || !r || v == r) return RIGA_ERR_INVALID_ARG;
-  if (!h->factored) return RIGA_ERR_STATE;
+  if (!h->factored || h->gep) return RIGA_ERR_STATE;
   return run([&]() -> riga_status {
     ck(hipSetDevice(h->device));
     const int64_t N = h->N();
@@ -959,7 +990,8 @@ riga_status riga_time_kernel(riga_problem* h, int which, int nrhs, int reps, dou
           riga::launch_bwd_level(h->dt, h->d_btasks + a, c, nrhs, h->d_Tp, h->level_f32(l2) ? h->d_Tp32 : nullptr,
                                  h->d_tmp, N, o, h->lvl_max_nf[l2], h->bvar[l2], h->st);
         } else {
-          factor_level(h, lv, h->sigma);
+          if (h->gep) factor_level(h, lv, -h->sigma, 0.0);
+          else factor_level(h, lv, h->sigma * h->sigma, h->sigma);
         }
       }
     }
@@ -1059,7 +1091,7 @@ struct KrylovRun {
   void project(int nc, int nq, double* ru, double* rl, double* mrl, double* dh, std::vector<double>* hsum) {
     const int64_t n = N;
     for (int pass = 0; pass < 2; ++pass) {
-      riga::launch_dots(n, nc, h->Vu, h->Wl, n, nq, ru, rl, n, h->d_part, h->d_ticket, dh + (size_t)pass * ldh * b,
+      riga::launch_dots(n, nc, h->Vu, h->Wl, n, nq, ru, rl, n, h->d_part, dh + (size_t)pass * ldh * b,
                         h->st);
       riga::launch_cgs_update(n, nc, nq, dh + (size_t)pass * ldh * b, h->Vu, ru, h->Vl, rl, h->Wl, mrl, n, n, nullptr, h->st);
     }
@@ -1077,7 +1109,7 @@ struct KrylovRun {
 
   std::vector<double> gram(int nq, double* ru, double* rl, double* mrl) {
     double* dG = h->d_small + (size_t)2 * ldh * b;
-    riga::launch_dots(N, nq, ru, mrl, N, nq, ru, rl, N, h->d_part, h->d_ticket, dG, h->st);
+    riga::launch_dots(N, nq, ru, mrl, N, nq, ru, rl, N, h->d_part, dG, h->st);
     n_vv += 2LL * nq * nq;
     std::vector<double> G((size_t)nq * nq);
     ck(hipMemcpyAsync(G.data(), dG, G.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
@@ -1118,7 +1150,7 @@ struct KrylovRun {
         riga::launch_dots_mr(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h1, h->ds, h->d_M1, h->MRl, N,
                              h->st);
       else
-        riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, h1, h->st);
+        riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h1, h->st);
       riga::launch_cgs_update_dots(N, nc, b, h1, h->Vu, h->Vl, h->Wl, N, h->Ru, h->Rl, h->MRl, N, h->d_part, h2,
                                    h->st);
       gblk = riga::launch_cgs_update(N, nc, b, h2, h->Vu, h->Ru, h->Vl, h->Rl, h->Wl, h->MRl, N, N, h->d_part,
@@ -1128,14 +1160,14 @@ struct KrylovRun {
         riga::launch_dots_mr(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h1, h->ds, h->d_M1, h->MRl, N,
                              h->st);
       else
-        riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, h1, h->st);
+        riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h1, h->st);
       riga::launch_cgs_update(N, nc, b, h1, h->Vu, h->Ru, h->Vl, h->Rl, h->Wl, h->MRl, N, N, nullptr, h->st);
-      riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, h2, h->st);
+      riga::launch_dots(N, nc, h->Vu, h->Wl, N, b, h->Ru, h->Rl, N, h->d_part, h2, h->st);
       // the second pass also leaves the partial B-Gram sums of the updated block
       gblk = riga::launch_cgs_update(N, nc, b, h2, h->Vu, h->Ru, h->Vl, h->Rl, h->Wl, h->MRl, N, N, h->d_part,
                                      h->st);
     } else {
-      riga::launch_dots(N, b, h->Ru, h->MRl, N, b, h->Ru, h->Rl, N, h->d_part, h->d_ticket, dG, h->st);
+      riga::launch_dots(N, b, h->Ru, h->MRl, N, b, h->Ru, h->Rl, N, h->d_part, dG, h->st);
     }
     const size_t o = (size_t)nc * N;
     double* rbuf = h->d_small + (size_t)2 * ldh * b + 16;   // nq x nq, after G
@@ -1280,7 +1312,7 @@ struct KrylovRun {
 extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, double* lam, double* X,
                                  double* eta, int* nconv) {
   if (!h || !opt || !lam) return RIGA_ERR_INVALID_ARG;
-  if (!h->factored) return RIGA_ERR_STATE;
+  if (!h->factored || h->gep) return RIGA_ERR_STATE;
   const int64_t N = h->N();
   const int nev = opt->nev;
   const int b = opt->block > 0 ? opt->block : 2;

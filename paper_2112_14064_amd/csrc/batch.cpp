@@ -372,15 +372,13 @@ riga_status riga_batch_assemble(riga_batch* bh, const riga_damping* damping) {
     for (int i = 0; i < n; ++i) {
       bh->alpha[i] = damping[i].alpha; bh->beta[i] = damping[i].beta; bh->celem[i] = damping[i].c_elem;
     }
-    // the damping of every problem, then tables and entries of all problems in two launches
+    // the damping of every problem, then tables, bands and entries of all problems in three launches
     ck(hipMemcpyAsync(bh->d_alpha, bh->alpha.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
     ck(hipMemcpyAsync(bh->d_beta, bh->beta.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
     ck(hipMemcpyAsync((void*)bh->d_celem, bh->celem.data(), n * sizeof(const double*), hipMemcpyHostToDevice, st));
     riga::launch_assemble_b(bh->B.rb, bh->B.nrb, bh->B.spaces, bh->B.dofbase, bh->d_taboff, bh->d_gx, bh->d_gw, n,
-                            bh->max_ne, bh->d_tabM, bh->d_tabK, bh->d_alpha, bh->d_beta, bh->d_celem, fp->d_K,
-                            fp->d_M, fp->d_C, st);
-    riga::launch_band_1d_b(bh->B.spaces, n, bh->max_w, bh->d_taboff, bh->d_tabM, bh->d_tabK, bh->d_bandoff, bh->d_M1,
-                           bh->d_K1, st);
+                            bh->max_ne, bh->d_tabM, bh->d_tabK, bh->max_w, bh->d_bandoff, bh->d_M1, bh->d_K1,
+                            bh->d_alpha, bh->d_beta, bh->d_celem, fp->d_K, fp->d_M, fp->d_C, st);
     bh->any_field = false;
     for (int i = 0; i < n; ++i) bh->any_field = bh->any_field || bh->celem[i] != nullptr;
     ck(hipEventRecord(fp->ev1, st));

@@ -5,9 +5,14 @@
 // a = (ax, ay), b = (bx, by) and element (ex, ey)
 //   M_e[a,b] = m_ex[ax,bx] m_ey[ay,by],
 //   K_e[a,b] = k_ex[ax,bx] m_ey[ay,by] + m_ex[ax,bx] k_ey[ay,by].
-// Each CSR entry is produced by one thread that sums over the (at most
-// (p+1)^2) elements shared by the two supports: a pure gather, no atomics, so
-// the result is bitwise reproducible.
+// The 1-D factors are assembled first as bands (k_band_1d: m_x and k_x summed
+// over the elements two supports share), and every CSR row of M, K, C is then
+// written by one wave from the two band rows of its dof, lane = stored entry:
+//   M = M1[i][ii] M1[j][jj],  K = K1[i][ii] M1[j][jj] + M1[i][ii] K1[j][jj],
+// consecutive lanes writing consecutive entries.  A per-element damping field
+// adds sum_{ey, ex} c[ey][ex] m_ex[i, ii] m_ey[j, jj], formed per row through
+// the table T[ey][ii] = sum_ex c[ey][ex] m_ex[i, ii] (in LDS).  A pure gather,
+// no atomics, so the result is bitwise reproducible.
 #include "kernels.hpp"
 
 namespace riga {
@@ -100,115 +105,124 @@ void launch_bspline_tables(const DevSpace& s, const double* gx, const double* gw
                      s.p, s.ne, s.knots, s.first, gx, gw, tabM, tabK);
 }
 
-constexpr int ASM_ROWS = 64;
 constexpr int ASM_THREADS = 256;
-constexpr int ASM_MAXROWS = 256;   // rows of one block at most (forest row blocks)
+constexpr int ASM_WAVES = ASM_THREADS / 64;
+constexpr int ASM_ROWS_PER_WAVE = 4;
+constexpr int ASM_TMAX = (MAXP + 1) * (2 * MAXP + 1);   // T[ey][ii] entries per row
 
-// Entries of rows [r0, r0 + nrows) of one space (row indices local to the
-// space, rowptr its row pointers into the value arrays); rp: nrows + 1 words
-// of shared memory.
-__device__ inline void assemble_rows(const DevSpace& s, int64_t r0, int nrows, const double* __restrict__ tabM,
-                                     const double* __restrict__ tabK, double alpha, double beta,
-                                     const double* __restrict__ c_elem, double* __restrict__ Ko,
-                                     double* __restrict__ Mo, double* __restrict__ Co, int64_t* rp) {
-  const int p = s.p, ne = s.ne, n = s.n;
-  const int *sup0 = s.sup0, *sup1 = s.sup1, *lo = s.lo, *hi = s.hi, *first = s.first;
-  for (int t = threadIdx.x; t <= nrows; t += blockDim.x) rp[t] = s.rowptr[r0 + t];
-  __syncthreads();
-  const int np = p + 1;
-  const int64_t kbeg = rp[0], kend = rp[nrows];
-  for (int64_t k = kbeg + threadIdx.x; k < kend; k += blockDim.x) {
-    // row of entry k: last row whose start is <= k
-    int a = 0, b = nrows;  // invariant rp[a] <= k < rp[b]
-    while (b - a > 1) {
-      int c = (a + b) >> 1;
-      if (rp[c] <= k) a = c; else b = c;
+// Row r (local to the space, uniform in the wave) of K, M, C from the bands
+// M1, K1 (row i at i (2p + 1), column ii at + ii - i + p); T: ASM_TMAX doubles
+// of this wave's shared memory.
+__device__ inline void assemble_row(const DevSpace& s, int64_t r, const double* __restrict__ tabM,
+                                    const double* __restrict__ M1, const double* __restrict__ K1, double alpha,
+                                    double beta, const double* __restrict__ c_elem, double* __restrict__ Ko,
+                                    double* __restrict__ Mo, double* __restrict__ Co, double* T, int lane) {
+  const int p = s.p, n = s.n, ne = s.ne, w = 2 * p + 1, np = p + 1;
+  const int i = (int)(r % n), j = (int)(r / n);
+  const int lox = s.lo[i], wx = s.hi[i] - lox + 1, loy = s.lo[j];
+  const int64_t k0 = s.rowptr[r];
+  const int len = (int)(s.rowptr[r + 1] - k0);
+  const double* mxr = M1 + (int64_t)i * w - i + p;   // mxr[ii] = M1[i][ii]
+  const double* kxr = K1 + (int64_t)i * w - i + p;
+  const double* myr = M1 + (int64_t)j * w - j + p;
+  const double* kyr = K1 + (int64_t)j * w - j + p;
+  const int sy0 = s.sup0[j], sy1 = s.sup1[j];
+  if (c_elem != nullptr) {
+    // T[ey - sy0][ii - lox] over the elements ey of j's support and the
+    // coupled functions ii of i
+    const int nt = (sy1 - sy0) * wx;
+    for (int t = lane; t < nt; t += 64) {
+      const int ey = sy0 + t / wx, ii = lox + t % wx;
+      const int ex0 = max(s.sup0[i], s.sup0[ii]), ex1 = min(s.sup1[i], s.sup1[ii]);
+      double acc = 0.0;
+      for (int ex = ex0; ex < ex1; ++ex) {
+        const int fx = s.first[ex];
+        acc += c_elem[(int64_t)ey * ne + ex] * tabM[((int64_t)ex * np + i + 1 - fx) * np + ii + 1 - fx];
+      }
+      T[t] = acc;
     }
-    const int64_t r = r0 + a;
-    const int i = (int)(r % n), j = (int)(r / n);
-    const int o = (int)(k - rp[a]);
-    const int wx = hi[i] - lo[i] + 1;
-    const int jj = lo[j] + o / wx, ii = lo[i] + o % wx;
-    // x factor: elements shared by the supports of functions i and ii
-    double mx[MAXP + 1], my[MAXP + 1];
-    double sx = 0.0, kx = 0.0, sy = 0.0, ky = 0.0;
-    const int ex0 = max(sup0[i], sup0[ii]), ex1 = min(sup1[i], sup1[ii]);
-    for (int ex = ex0; ex < ex1; ++ex) {
-      int la = i + 1 - first[ex], lb = ii + 1 - first[ex];
-      int64_t idx = (int64_t)ex * np * np + la * np + lb;
-      mx[ex - ex0] = tabM[idx];
-      sx += tabM[idx];
-      kx += tabK[idx];
-    }
-    const int ey0 = max(sup0[j], sup0[jj]), ey1 = min(sup1[j], sup1[jj]);
-    for (int ey = ey0; ey < ey1; ++ey) {
-      int la = j + 1 - first[ey], lb = jj + 1 - first[ey];
-      int64_t idx = (int64_t)ey * np * np + la * np + lb;
-      my[ey - ey0] = tabM[idx];
-      sy += tabM[idx];
-      ky += tabK[idx];
-    }
-    const double mval = sx * sy;
-    const double kval = kx * sy + sx * ky;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  for (int o = lane; o < len; o += 64) {
+    const int jj = loy + o / wx, ii = lox + o % wx;
+    const double mx = mxr[ii], kx = kxr[ii], my = myr[jj], ky = kyr[jj];
+    const double mval = mx * my;
+    const double kval = kx * my + mx * ky;
     double cval = alpha * mval + beta * kval;
-    if (c_elem) {
+    if (c_elem != nullptr) {
+      const int ey0 = max(sy0, s.sup0[jj]), ey1 = min(sy1, s.sup1[jj]);
       double acc = 0.0;
       for (int ey = ey0; ey < ey1; ++ey) {
-        double rowacc = 0.0;
-        for (int ex = ex0; ex < ex1; ++ex) rowacc += c_elem[(int64_t)ey * ne + ex] * mx[ex - ex0];
-        acc += rowacc * my[ey - ey0];
+        const int fy = s.first[ey];
+        acc += tabM[((int64_t)ey * np + j + 1 - fy) * np + jj + 1 - fy] * T[(ey - sy0) * wx + ii - lox];
       }
       cval += acc;
     }
-    Ko[k] = kval;
-    Mo[k] = mval;
-    Co[k] = cval;
+    Ko[k0 + o] = kval;
+    Mo[k0 + o] = mval;
+    Co[k0 + o] = cval;
   }
 }
 
 __global__ __launch_bounds__(ASM_THREADS) void k_assemble(DevSpace s, int64_t ndof, const double* __restrict__ tabM,
-                                                          const double* __restrict__ tabK, double alpha, double beta,
+                                                          const double* __restrict__ M1, const double* __restrict__ K1,
+                                                          double alpha, double beta,
                                                           const double* __restrict__ c_elem, double* __restrict__ Ko,
                                                           double* __restrict__ Mo, double* __restrict__ Co) {
-  __shared__ int64_t rp[ASM_ROWS + 1];
-  const int64_t r0 = (int64_t)blockIdx.x * ASM_ROWS;
-  assemble_rows(s, r0, (int)min((int64_t)ASM_ROWS, ndof - r0), tabM, tabK, alpha, beta, c_elem, Ko, Mo, Co, rp);
+  __shared__ double T[ASM_WAVES][ASM_TMAX];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r0 = ((int64_t)blockIdx.x * ASM_WAVES + wave) * ASM_ROWS_PER_WAVE;
+  for (int q = 0; q < ASM_ROWS_PER_WAVE; ++q) {
+    const int64_t r = r0 + q;
+    if (r >= ndof) break;
+    assemble_row(s, r, tabM, M1, K1, alpha, beta, c_elem, Ko, Mo, Co, T[wave], lane);
+  }
 }
 
 // Every problem of a forest, one block per row block rb[b] = {problem, first
-// row, end row} (forest rows; the problem's rows start at dofbase).
+// row, end row} (forest rows; the problem's rows start at dofbase), the waves
+// taking its rows in turn; bands at M1 / K1 + bandoff[q].
 __global__ __launch_bounds__(ASM_THREADS) void k_assemble_b(const int4* __restrict__ rb,
                                                             const DevSpace* __restrict__ spaces,
                                                             const int64_t* __restrict__ dofbase,
                                                             const int64_t* __restrict__ taboff,
                                                             const double* __restrict__ tabM,
-                                                            const double* __restrict__ tabK,
+                                                            const int64_t* __restrict__ bandoff,
+                                                            const double* __restrict__ M1,
+                                                            const double* __restrict__ K1,
                                                             const double* __restrict__ alpha,
                                                             const double* __restrict__ beta,
                                                             const double* const* __restrict__ c_elem,
                                                             double* __restrict__ Ko, double* __restrict__ Mo,
                                                             double* __restrict__ Co) {
-  __shared__ int64_t rp[ASM_MAXROWS + 1];
+  __shared__ double T[ASM_WAVES][ASM_TMAX];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int4 b = rb[blockIdx.x];
   const int q = b.x;
   const DevSpace sp = spaces[q];
-  assemble_rows(sp, b.y - dofbase[q], b.z - b.y, tabM + taboff[q], tabK + taboff[q], alpha[q], beta[q], c_elem[q],
-                Ko, Mo, Co, rp);
+  const int64_t base = dofbase[q];
+  for (int64_t row = b.y + wave; row < b.z; row += ASM_WAVES)
+    assemble_row(sp, row - base, tabM + taboff[q], M1 + bandoff[q], K1 + bandoff[q], alpha[q], beta[q], c_elem[q], Ko,
+                 Mo, Co, T[wave], lane);
 }
 
 void launch_assemble_b(const int4* rb, int nrb, const DevSpace* spaces, const int64_t* dofbase,
                        const int64_t* taboff, const double* const* gx, const double* const* gw, int n, int max_ne,
-                       double* tabM, double* tabK, const double* alpha, const double* beta,
-                       const double* const* c_elem, double* K, double* M, double* C, hipStream_t st) {
+                       double* tabM, double* tabK, int max_w, const int64_t* bandoff, double* M1, double* K1,
+                       const double* alpha, const double* beta, const double* const* c_elem, double* K, double* M,
+                       double* C, hipStream_t st) {
   hipLaunchKernelGGL(k_bspline_tables_b, dim3((max_ne + 63) / 64, n), dim3(64), 0, st, spaces, taboff, gx, gw, tabM,
                      tabK);
-  hipLaunchKernelGGL(k_assemble_b, dim3(nrb), dim3(ASM_THREADS), 0, st, rb, spaces, dofbase, taboff, tabM, tabK,
-                     alpha, beta, c_elem, K, M, C);
+  launch_band_1d_b(spaces, n, max_w, taboff, tabM, tabK, bandoff, M1, K1, st);
+  hipLaunchKernelGGL(k_assemble_b, dim3(nrb), dim3(ASM_THREADS), 0, st, rb, spaces, dofbase, taboff, tabM, bandoff,
+                     M1, K1, alpha, beta, c_elem, K, M, C);
 }
 
 // Banded 1-D mass and stiffness matrices of one space: entry (i, ii), ii in
-// lo[i] .. hi[i], is the sum over the shared elements that assemble_rows forms
-// for its x factor (same terms, same order), stored at i (2p + 1) + ii - i + p;
+// lo[i] .. hi[i], is the sum of the element blocks over the elements the two
+// supports share, stored at i (2p + 1) + ii - i + p;
 // every other slot of the band is zero.  M = M1 (x) M1 and
 // K = K1 (x) M1 + M1 (x) K1 on the tensor grid.
 __device__ inline void band_entry(const DevSpace& s, int i, int o, const double* __restrict__ tabM,
@@ -259,11 +273,12 @@ void launch_band_1d_b(const DevSpace* spaces, int n, int max_w, const int64_t* t
                      M1, K1);
 }
 
-void launch_assemble(const DevSpace& s, const double* tabM, const double* tabK,
+void launch_assemble(const DevSpace& s, const double* tabM, const double* M1, const double* K1,
                      double alpha, double beta, const double* c_elem,
                      double* K, double* M, double* C, int64_t ndof, hipStream_t st) {
-  int64_t blocks = (ndof + ASM_ROWS - 1) / ASM_ROWS;
-  hipLaunchKernelGGL(k_assemble, dim3((unsigned)blocks), dim3(ASM_THREADS), 0, st, s, ndof, tabM, tabK, alpha, beta,
+  const int64_t rows = (int64_t)ASM_WAVES * ASM_ROWS_PER_WAVE;
+  const int64_t blocks = (ndof + rows - 1) / rows;
+  hipLaunchKernelGGL(k_assemble, dim3((unsigned)blocks), dim3(ASM_THREADS), 0, st, s, ndof, tabM, M1, K1, alpha, beta,
                      c_elem, K, M, C);
 }
 }  // namespace riga

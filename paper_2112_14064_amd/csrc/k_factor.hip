@@ -3,11 +3,18 @@
 // Sec. 5.2.1: one factorization per shift).
 //
 // A front of node v holds its own dofs (eliminated here) followed by its
-// boundary dofs (ancestors coupled to the subtree).  Storage per node:
-//   L block  nf x no, column-major (ld nf): the own columns of the front;
-//   U block  nb x nb, column-major: the update (Schur complement) matrix that
-//            the parent adds into its front ("extend-add");
-//   T block  no x nf, column-major (same offset as L): F^T, the rows of F.
+// boundary dofs (ancestors coupled to the subtree).  Storage per node, at the
+// same offset in two buffers of nf x no entries (the front buffer and the
+// factor buffer) plus the update block:
+//   front   nf x no, column-major (ld nf): the own columns of the assembled
+//           front, updated in place by the panels; after the factorization it
+//           receives F (row r of F at r * no), the matrix the sweeps use;
+//   factor  nf x no, column-major: L (the own columns of the Cholesky factor),
+//           written panel by panel (kept apart from the front so that a
+//           panel's rows are read by every workgroup of its update launch
+//           while the factor rows are written);
+//   U       nb x nb, column-major: the update (Schur complement) matrix that
+//           the parent adds into its front ("extend-add").
 // A tree level is processed by a pipeline of batched kernels whose grids span
 // every node of the level:
 //   k_front_assemble   zero the front and add the original entries of Q
@@ -16,13 +23,15 @@
 //                      launch (64 child columns per workgroup);
 //   per 64-wide panel of own columns:
 //     k_potrf_diag     Cholesky of the 64x64 diagonal block and its inverse
-//                      D_k = L_kk^{-1} (one workgroup per node, in LDS);
-//     k_trsm_panel     panel rows below the block: X = A D_k^T   (MFMA)
-//     k_syrk_update    trailing lower triangle, own and update parts:
-//                      C -= P_I P_J^T on 64x64 tiles             (MFMA)
+//                      D_k = L_kk^{-1}, both blocked by 16 over four waves
+//                      (one workgroup per node, in LDS);
+//     k_panel_update   per pair of 64-row tiles (I, J), J <= I, below the
+//                      block: the panel rows X_I = A_I D_k^T and X_J (MFMA),
+//                      X_I stored as factor rows by the diagonal pair, and
+//                      the trailing tile C_IJ -= X_I X_J^T (MFMA);
 //   k_rtrsm            rows of F = [L_oo^{-1}; L_bo L_oo^{-1}] from
 //                      X L_oo = [I; L_bo], block column by block column from
-//                      the right with the stored D_k               (MFMA)
+//                      the right with the stored D_k (MFMA, 16 waves);
 //   k_pack             F in the two sweep layouts Lp / Tp (16-byte groups of
 //                      columns / rows).
 // With F, each forward/backward sweep is one matrix-vector product per node.
@@ -30,8 +39,9 @@
 // double (v_mfma_f64_16x16x4_f64) or float (v_mfma_f32_16x16x4_f32, FP32
 // products and accumulation) for the mixed-precision factorization, where the
 // lower tree levels are FP32 and the top levels FP64.  Products run on 64x64
-// tiles staged in LDS; each of the four waves owns a 32x32 quadrant (2x2 MFMA
-// tiles).
+// tiles staged in LDS; a tile is split over the waves of the workgroup (4
+// waves: 32x32 quadrants of 2x2 MFMA tiles; 16 waves: one 16x16 MFMA tile
+// each).
 #include "kernels.hpp"
 #include "mfma_layout.hpp"
 
@@ -39,7 +49,7 @@
 
 namespace riga {
 
-constexpr int FT = 256;     // threads per workgroup
+constexpr int FT = 256;     // threads per workgroup (four waves)
 constexpr int TB = 64;      // panel / tile width
 constexpr int LDT = TB + 1; // LDS row stride (elements)
 
@@ -58,35 +68,75 @@ __device__ __forceinline__ Front<E> front_of(const DevTree& t, int v, E* Lbuf, E
 
 template <class E> using acc_t = typename Mfma<E>::acc_t;
 
-// acc += sign * A (64 x kw) B (kw x 64), A at As[i * LDT + k], B at Bs[k * LDT + j];
-// wave w owns rows 32 (w >> 1) .. and columns 32 (w & 1) .., as 2 x 2 MFMA tiles.
-template <class E>
-__device__ __forceinline__ void mma64(const E* As, const E* Bs, int kw, acc_t<E> (&acc)[2][2],
-                                      int lane, int wave, E sign) {
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  for (int k0 = 0; k0 < kw; k0 += 4) {
-    const int k = k0 + mfma_ab_k(lane);
-    E a[2], b[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      a[t] = (k < kw) ? sign * As[(wr + 16 * t + mfma_a_row(lane)) * LDT + k] : E(0);
-      b[t] = (k < kw) ? Bs[k * LDT + wc + 16 * t + mfma_b_col(lane)] : E(0);
-    }
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < 2; ++tj)
-        acc[ti][tj] = Mfma<E>::mma(a[ti], b[tj], acc[ti][tj]);
+// A 64 x 64 product tile split over the NW waves of a workgroup: a WR x WC
+// grid of wave regions, each TI x TJ MFMA tiles of 16 x 16.
+template <class E, int NW>
+struct Tile64 {
+  static constexpr int WC = NW == 16 ? 4 : 2, WR = NW / WC;
+  static constexpr int TI = TB / WR / 16, TJ = TB / WC / 16;
+  struct Acc { acc_t<E> a[TI][TJ]; };
+  static __device__ __forceinline__ int row(int lane, int wave, int ti, int v) {
+    return (wave / WC) * (TB / WR) + 16 * ti + Mfma<E>::drow(lane, v);
   }
-}
-
-template <class E>
-__device__ __forceinline__ int acc_row(int lane, int wave, int ti, int v) {
-  return (wave >> 1) * 32 + 16 * ti + Mfma<E>::drow(lane, v);
-}
-__device__ __forceinline__ int acc_col(int lane, int wave, int tj) {
-  return (wave & 1) * 32 + 16 * tj + mfma_d_col(lane);
-}
+  static __device__ __forceinline__ int col(int lane, int wave, int tj) {
+    return (wave % WC) * (TB / WC) + 16 * tj + mfma_d_col(lane);
+  }
+  static __device__ __forceinline__ void zero(Acc& c) {
+#pragma unroll
+    for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < TJ; ++tj) c.a[ti][tj] = acc_t<E>{0, 0, 0, 0};
+  }
+  // acc += A (64 x kw) B (kw x 64) with both operands read from global memory:
+  // A(i, k) at A[k * lda + i] for i < nrows (rows past nrows are zero), B(k, j)
+  // at B[k * ldb + j]; k < kw.  Lanes 0..15 of a k row read 16 consecutive
+  // entries, and the unrolled k loop keeps several rounds of loads in flight
+  // (masked lanes read a valid address and select zero).
+  static __device__ __forceinline__ void mma_global(const E* __restrict__ A, int64_t lda, int nrows,
+                                                    const E* __restrict__ B, int ldb, int kw, Acc& c, int lane,
+                                                    int wave) {
+    const int wr = (wave / WC) * (TB / WR), wc = (wave % WC) * (TB / WC);
+#pragma unroll 4
+    for (int k0 = 0; k0 < TB; k0 += 4) {
+      const int k = k0 + mfma_ab_k(lane);
+      const bool kin = k < kw;
+      E a[TI], b[TJ];
+#pragma unroll
+      for (int t = 0; t < TI; ++t) {
+        const int i = wr + 16 * t + mfma_a_row(lane);
+        const bool in = kin && i < nrows;
+        const E x = A[in ? (int64_t)k * lda + i : 0];
+        a[t] = in ? x : E(0);
+      }
+#pragma unroll
+      for (int t = 0; t < TJ; ++t) {
+        const E x = B[kin ? k * ldb + wc + 16 * t + mfma_b_col(lane) : 0];
+        b[t] = kin ? x : E(0);
+      }
+#pragma unroll
+      for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < TJ; ++tj) c.a[ti][tj] = Mfma<E>::mma(a[ti], b[tj], c.a[ti][tj]);
+    }
+  }
+  // acc += sign * A (64 x kw) B (kw x 64), A at As[i * LDT + k], B at Bs[k * LDT + j]
+  static __device__ __forceinline__ void mma(const E* As, const E* Bs, int kw, Acc& c, int lane, int wave,
+                                             E sign) {
+    const int wr = (wave / WC) * (TB / WR), wc = (wave % WC) * (TB / WC);
+    for (int k0 = 0; k0 < kw; k0 += 4) {
+      const int k = k0 + mfma_ab_k(lane);
+      E a[TI], b[TJ];
+#pragma unroll
+      for (int t = 0; t < TI; ++t) a[t] = (k < kw) ? sign * As[(wr + 16 * t + mfma_a_row(lane)) * LDT + k] : E(0);
+#pragma unroll
+      for (int t = 0; t < TJ; ++t) b[t] = (k < kw) ? Bs[k * LDT + wc + 16 * t + mfma_b_col(lane)] : E(0);
+#pragma unroll
+      for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < TJ; ++tj) c.a[ti][tj] = Mfma<E>::mma(a[ti], b[tj], c.a[ti][tj]);
+    }
+  }
+};
 
 // ---------------------------------------------------------------------------------
 // Front assembly, columns [64 y, 64 y + 64) of the front per workgroup: zero
@@ -152,23 +202,42 @@ __global__ __launch_bounds__(FT) void k_front_assemble(
     m_len = (int)(rowptr[d + 1] - r0);
   }
   const int64_t kbase = rowptr[0];
-  for (int u = 0; u < na; ++u) {
-    const int a = c0 + wave + (FT / 64) * u;
-    const int lx = __builtin_amdgcn_readlane(m_lx, u), wx = __builtin_amdgcn_readlane(m_wx, u);
-    const int ly = __builtin_amdgcn_readlane(m_ly, u);
-    const int64_t k0 = kbase + __builtin_amdgcn_readlane(m_k0, u);
-    const int64_t k1 = k0 + __builtin_amdgcn_readlane(m_len, u);
-    for (int64_t k = k0 + lane; k < k1; k += 64) {
-      const int o = (int)(k - k0);
-      const int g = (ly + o / wx) * n + lx + o % wx + base;
-      int x0 = 0, x1 = nf;  // binary search of g among the sorted front keys
-      while (x1 - x0 > 1) {
-        const int c = (x0 + x1) >> 1;
-        if (keys[c] <= g) x0 = c; else x1 = c;
+  int mlen = m_len;   // longest row of the wave's columns
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mlen = max(mlen, __shfl_xor(mlen, off, 64));
+  // chunks of 64 stored entries per row (lane = entry); per batch of eight
+  // columns every value load is issued before the first search, so their
+  // latencies overlap (lanes past a row's end read the row's first entry)
+  constexpr int UB = 8;
+  for (int ch = 0; ch * 64 < mlen; ++ch) {
+    const int o = ch * 64 + lane;
+    for (int u0 = 0; u0 < na; u0 += UB) {
+      double q[UB];
+#pragma unroll
+      for (int uu = 0; uu < UB; ++uu) {
+        const int u = min(u0 + uu, 15);
+        const int len = u0 + uu < na ? __builtin_amdgcn_readlane(m_len, u) : 0;
+        const int64_t k = kbase + __builtin_amdgcn_readlane(m_k0, u) + (o < len ? o : 0);
+        q[uu] = s2 * Mv[k] + s1 * Cv[k] + Kv[k];
       }
-      if (keys[x0] == g) {
-        const int pos = keys[nf + x0];
-        if (pos >= a) F.L[(int64_t)a * nf + pos] = (E)(s2 * Mv[k] + s1 * Cv[k] + Kv[k]);
+#pragma unroll
+      for (int uu = 0; uu < UB; ++uu) {
+        const int u = u0 + uu;
+        if (u >= na) break;
+        if (o >= __builtin_amdgcn_readlane(m_len, u)) continue;
+        const int a = c0 + wave + (FT / 64) * u;
+        const int lx = __builtin_amdgcn_readlane(m_lx, u), wx = __builtin_amdgcn_readlane(m_wx, u);
+        const int ly = __builtin_amdgcn_readlane(m_ly, u);
+        const int g = (ly + o / wx) * n + lx + o % wx + base;
+        int x0 = 0, x1 = nf;  // binary search of g among the sorted front keys
+        while (x1 - x0 > 1) {
+          const int c = (x0 + x1) >> 1;
+          if (keys[c] <= g) x0 = c; else x1 = c;
+        }
+        if (keys[x0] == g) {
+          const int pos = keys[nf + x0];
+          if (pos >= a) F.L[(int64_t)a * nf + pos] = (E)q[uu];
+        }
       }
     }
   }
@@ -177,30 +246,32 @@ __global__ __launch_bounds__(FT) void k_front_assemble(
 // Columns [l0, l1) of a child's update block U (nbc x nbc, lower triangle)
 // added into the parent front at the mapped positions (mk: the map from child
 // row l0 on, in shared memory).  A lane owns rows k and walks the tile's
-// columns in batches of eight: the eight front entries are distinct (the map
-// is injective), so their loads are all issued before the sums are stored.
+// columns in batches of sixteen: the front entries are distinct (the map is
+// injective), so their loads are all issued before the sums are stored.
 template <class E, class S>
 __device__ __forceinline__ void extend_tile(const Front<E>& F, const S* __restrict__ Uc, int nbc, int l0, int l1,
                                             const int* mk) {
+  constexpr int B = 16;
   for (int k = l0 + (int)threadIdx.x; k < nbc; k += FT) {
     const int pk = mk[k - l0];
     const int lend = min(l1, k + 1);
-    int l = l0;
-    for (; l + 8 <= lend; l += 8) {
-      E* p[8];
-      E f[8];
-      S u[8];
+    for (int l = l0; l < lend; l += B) {
+      // columns past lend read the batch's first entry and store nothing
+      E* p[B];
+      E f[B];
+      S u[B];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        p[e] = F.at(pk, mk[l + e - l0]);
-        u[e] = Uc[(int64_t)(l + e) * nbc + k];
+      for (int e = 0; e < B; ++e) {
+        const int le = l + e < lend ? l + e : l;
+        p[e] = F.at(pk, mk[le - l0]);
+        u[e] = Uc[(int64_t)le * nbc + k];
       }
 #pragma unroll
-      for (int e = 0; e < 8; ++e) f[e] = *p[e];
+      for (int e = 0; e < B; ++e) f[e] = *p[e];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) *p[e] = f[e] + (E)u[e];
+      for (int e = 0; e < B; ++e)
+        if (l + e < lend) *p[e] = f[e] + (E)u[e];
     }
-    for (; l < lend; ++l) *F.at(pk, mk[l - l0]) += (E)Uc[(int64_t)l * nbc + k];
   }
 }
 
@@ -257,143 +328,199 @@ __device__ __forceinline__ float rsqrt_refined(float x) {
   const float e = fmaf(-x * y, y, 1.0f);
   return fmaf(0.5f * y, e, y);
 }
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-// Cholesky of the diagonal block [k0, k0+w) and D = its inverse (lower), stored
-// at D + (doff[v] + k0/64) * 4096 as D[r * 64 + c].  One wave does both with
-// the block in registers: lane = row for the factorisation (right-looking: at
-// column c every lane scales its entry and updates the rest of its row from
-// column c of the other rows, read across lanes), then lane = column for the
-// inverse (forward substitution against the rows of L, broadcast from shared
-// memory, four rows at a time, with the reciprocal pivots of the
-// factorisation).  Every loop is unrolled so the row / column stays in
-// registers.
+// Cholesky of the diagonal block [k0, k0+w) of the front and D = its inverse
+// (lower), stored transposed at D + (doff[v] + k0/64) * 4096 as Dt[c * 64 + r]
+// = D[r][c] (zero outside the w x w block), L_kk into the factor buffer.  The block sits in
+// LDS, padded to 64 x 64 with the identity.  Both are blocked by 16:
+//   factorisation: wave 0 factors a 16-column block column (lane = row: at
+//   column c every lane scales its entry, the column is written to LDS, and
+//   every lane updates the rest of its row from broadcast reads of it), then
+//   all four waves subtract its product from the trailing lower triangle;
+//   inverse: wave b inverts diagonal block b by forward substitution (lane =
+//   column), then wave j forms the blocks below it in block column j,
+//   D_ij = -D_ii sum_k L_ik D_kj, one block row after the other.
+// A pivot that is not positive (or NaN) is recorded in *status (the front's
+// dof, first one wins) and replaced by 1 so that the kernel completes.
+// Signed form (t.sgn not null; an indefinite K - s M, Sec. 4.1.4): the
+// factorization is A = L S L^T with S = diag(+-1) the signs of the pivots
+// (LDL^T with D = S |D| folded into L, no pivoting): l_cc = sqrt|a_cc|,
+// l_rc = a_rc / (s_c l_cc), and the Schur complement keeps a_rj - a_rc a_jc /
+// a_cc; the signs go to t.sgn[dof] and their negative count (the inertia of
+// Sylvester's law) is added to *negs.  Only a zero or NaN pivot is an error.
 template <class E>
 __global__ __launch_bounds__(FT) void k_potrf_diag(DevTree t, const int* __restrict__ level_nodes, int k0,
-                                                   E* __restrict__ Lbuf, E* __restrict__ Ubuf,
-                                                   E* __restrict__ Dbuf,
-                                                   int64_t* __restrict__ status) {
+                                                   const E* __restrict__ Lbuf, E* __restrict__ Fbuf,
+                                                   E* __restrict__ Dbuf, int64_t* __restrict__ status,
+                                                   unsigned long long* __restrict__ negs) {
   const int v = level_nodes[blockIdx.x];
-  const Front<E> F = front_of(t, v, Lbuf, Ubuf);
-  if (F.no <= k0) return;
-  const int w = min(TB, F.no - k0);
-  const int tid = threadIdx.x;
+  const int nf = t.nf[v], no = t.no[v];
+  if (no <= k0) return;
+  const int w = min(TB, no - k0);
+  const E* L = Lbuf + t.loff[v];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ E S[TB][LDT];
-  __shared__ E rd[TB];    // reciprocal pivots
-  for (int idx = tid; idx < TB * TB; idx += FT) {
-    const int r = idx % TB, c = idx / TB;       // coalesced along the column
-    S[r][c] = (r < w && c <= r) ? F.L[(int64_t)(k0 + c) * F.nf + k0 + r] : E(0);
+  __shared__ E Dm[TB][LDT];
+  __shared__ E Tx[3][16][17];   // per wave: the product sum_k L_ik D_kj of one block
+  __shared__ E rd[TB];          // reciprocal pivots
+  __shared__ E sg[TB];          // pivot signs
+  const bool sgd = t.sgn != nullptr;
+  {
+    // every load of the block issued before the first LDS store (coalesced
+    // along the column; entries outside the w x w lower triangle read the
+    // block's first entry and are replaced)
+    constexpr int U = TB * TB / FT;
+    E x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = tid + u * FT, r = idx % TB, c = idx / TB;
+      const bool in = c <= r && r < w;
+      x[u] = L[in ? (int64_t)(k0 + c) * nf + k0 + r : (int64_t)k0 * nf + k0];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = tid + u * FT, r = idx % TB, c = idx / TB;
+      const bool in = c <= r && r < w;
+      S[r][c] = in ? x[u] : ((c == r && r >= w) ? E(1) : E(0));
+      Dm[r][c] = E(0);
+    }
   }
-  if (tid < TB) rd[tid] = E(0);
   __syncthreads();
-  E* D = Dbuf + ((int64_t)t.doff[v] + k0 / TB) * (TB * TB);
-  if (tid < TB) {
-    const int r = tid;
-    E row[TB];
+  for (int c0 = 0; c0 < TB; c0 += 16) {
+    if (wave == 0) {
+      const int r = lane;
+      E row[16];
 #pragma unroll
-    for (int k = 0; k < TB; ++k) row[k] = S[r][k];
+      for (int j = 0; j < 16; ++j) row[j] = S[r][c0 + j];
 #pragma unroll
-    for (int c = 0; c < TB; ++c) {
-      if (c < w) {   // uniform
-        E piv = lane_value(row[c], c);
-        if (!(piv > E(0))) {           // not SPD (or NaN): record, continue with 1
-          if (r == c)
+      for (int c = 0; c < 16; ++c) {
+        const int cc = c0 + c;
+        E piv = lane_value(row[c], cc);
+        E s = E(1);
+        if (sgd && piv < E(0)) {
+          s = E(-1);
+          piv = -piv;
+        }
+        if (!(piv > E(0))) {           // not SPD (signed form: zero) or NaN: record, continue with 1
+          if (r == cc && cc < w)
             atomicCAS((unsigned long long*)status, (unsigned long long)(-1ll),
-                      (unsigned long long)t.fdofs[t.foff[v] + k0 + c]);
+                      (unsigned long long)t.fdofs[t.foff[v] + k0 + cc]);
           piv = E(1);
         }
         const E inv = rsqrt_refined(piv);
         const E d = piv * inv;
-        if (r == c) rd[c] = inv;
-        const E lrc = row[c] * inv;   // L[r][c] (rows below the pivot)
-        const E tc = lrc * inv;
+        if (r == cc) {
+          rd[cc] = inv;
+          sg[cc] = s;
+        }
+        const E lrc = row[c] * inv * s;   // L[r][cc] (rows below the pivot)
+        row[c] = (r == cc) ? d : lrc;
+        // column cc published in LDS; the rest of the block column is
+        // updated with a_rj - a_rc a_jc / a_cc = a_rj - s l_rc l_jc, the l_jc
+        // read as broadcasts
+        if (r >= cc) S[r][cc] = row[c];
+        wave_sync();
+        const E t = lrc * s;
 #pragma unroll
-        for (int j = c + 1; j < TB; ++j) row[j] -= tc * lane_value(row[c], j);
-        row[c] = (r == c) ? d : lrc;
+        for (int j = c + 1; j < 16; ++j) row[j] -= t * S[c0 + j][cc];
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (r >= c0 + j) S[r][c0 + j] = row[j];
+    }
+    __syncthreads();
+    const int n = TB - c0 - 16;   // trailing rows / columns
+    for (int idx = tid; idx < n * n; idx += FT) {
+      const int i = idx / n, j = idx % n;
+      if (j <= i) {
+        const int ri = c0 + 16 + i, rj = c0 + 16 + j;
+        E s = S[ri][rj];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) s -= S[ri][c0 + c] * sg[c0 + c] * S[rj][c0 + c];
+        S[ri][rj] = s;
       }
     }
+    __syncthreads();
+  }
+  // inverse: diagonal blocks, wave b takes block b, lane = column (16 lanes)
+  if (lane < 16) {
+    const int base = 16 * wave, c = lane;
+    E dc[16];
 #pragma unroll
-    for (int k = 0; k < TB; ++k)
-      if (k <= r) S[r][k] = row[k];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // inverse, lane = column c: D[rr][c] = -(sum_k L[rr][k] D[k][c]) / L[rr][rr],
-    // the products over the rows already done formed for four rows together
-    const int c = tid;
-    E dc[TB];
+    for (int rr = 0; rr < 16; ++rr) {
+      E sum = E(0);
 #pragma unroll
-    for (int r0 = 0; r0 < TB; r0 += 4) {
-      E sp[4] = {E(0), E(0), E(0), E(0)};
+      for (int k = 0; k < rr; ++k) sum += S[base + rr][base + k] * dc[k];
+      const E ri = rd[base + rr];
+      dc[rr] = (rr < c) ? E(0) : (rr == c ? ri : -sum * ri);
+      Dm[base + rr][base + c] = dc[rr];
+    }
+  }
+  __syncthreads();
+  // blocks below the diagonal: wave j takes block column j; lane = column c
+  // of the block and four consecutive rows 4 rg .. 4 rg + 3
+  if (wave < 3) {
+    const int j = wave, c = lane & 15, rg = lane >> 4;
+    for (int i = j + 1; i < 4; ++i) {
+      E tv[4] = {E(0), E(0), E(0), E(0)};
+      for (int k = 16 * j; k < 16 * i; ++k) {
+        const E dk = Dm[k][16 * j + c];
 #pragma unroll
-      for (int k = 0; k < r0; ++k) {
-        const E x = dc[k];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) sp[u] += S[r0 + u][k] * x;
+        for (int u = 0; u < 4; ++u) tv[u] += S[16 * i + 4 * rg + u][k] * dk;
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) Tx[j][4 * rg + u][c] = tv[u];
+      wave_sync();
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int rr = r0 + u;
-        E sum = sp[u];
+        const int r = 4 * rg + u;
+        E s = E(0);
 #pragma unroll
-        for (int k = r0; k < rr; ++k) sum += S[rr][k] * dc[k];
-        const E ri = rd[rr];
-        dc[rr] = (rr < c) ? E(0) : (rr == c ? ri : -sum * ri);
-        D[rr * TB + c] = dc[rr];
+        for (int q = 0; q < 16; ++q) s += Dm[16 * i + r][16 * i + q] * Tx[j][q][c];
+        Dm[16 * i + r][16 * j + c] = -s;
       }
+      wave_sync();
     }
   }
   __syncthreads();
+  E* Lf = Fbuf + t.loff[v];
   for (int idx = tid; idx < TB * TB; idx += FT) {
     const int r = idx % TB, c = idx / TB;
-    if (r < w && c <= r) F.L[(int64_t)(k0 + c) * F.nf + k0 + r] = S[r][c];
+    if (r < w && c <= r) Lf[(int64_t)(k0 + c) * nf + k0 + r] = S[r][c];
   }
-}
-
-// Panel rows [k0 + w + 64 y, +64) of columns [k0, k0 + w): X = A D^T.
-template <class E>
-__global__ __launch_bounds__(FT) void k_trsm_panel(DevTree t, const int* __restrict__ level_nodes, int k0,
-                                                   E* __restrict__ Lbuf, E* __restrict__ Ubuf,
-                                                   const E* __restrict__ Dbuf) {
-  const int v = level_nodes[blockIdx.x];
-  const Front<E> F = front_of(t, v, Lbuf, Ubuf);
-  if (F.no <= k0) return;
-  const int w = min(TB, F.no - k0);
-  const int r0 = k0 + w + TB * blockIdx.y;
-  if (r0 >= F.nf) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ E As[TB * LDT];
-  __shared__ E Bs[TB * LDT];
-  const E* D = Dbuf + ((int64_t)t.doff[v] + k0 / TB) * (TB * TB);
+  // D stored transposed: Dt[c * 64 + r] = D[r][c]
+  E* Dt = Dbuf + ((int64_t)t.doff[v] + k0 / TB) * (TB * TB);
   for (int idx = tid; idx < TB * TB; idx += FT) {
-    const int i = idx % TB, k = idx / TB;        // row i of the tile, column k (coalesced in i)
-    const int r = r0 + i;
-    As[i * LDT + k] = (r < F.nf && k < w) ? F.L[(int64_t)(k0 + k) * F.nf + r] : E(0);
-    const int kk = idx / TB, j = idx % TB;        // Bs[k][j] = D[j][k]
-    Bs[kk * LDT + j] = D[j * TB + kk];
+    const int c = idx / TB, r = idx % TB;
+    Dt[idx] = (r < w && c < w) ? Dm[r][c] : E(0);
   }
-  __syncthreads();
-  acc_t<E> acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = acc_t<E>{0, 0, 0, 0};
-  mma64<E>(As, Bs, w, acc, lane, wave, E(1));
-#pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-      for (int vv = 0; vv < 4; ++vv) {
-        const int r = r0 + acc_row<E>(lane, wave, ti, vv), c = acc_col(lane, wave, tj);
-        if (r < F.nf && c < w) F.L[(int64_t)(k0 + c) * F.nf + r] = acc[ti][tj][vv];
-      }
+  if (sgd && wave == 0) {
+    const bool neg = lane < w && sg[lane] < E(0);
+    if (lane < w) t.sgn[t.fdofs[t.foff[v] + k0 + lane]] = (double)sg[lane];
+    const unsigned long long cnt = __builtin_popcountll(__ballot(neg));
+    if (lane == 0 && cnt > 0) atomicAdd(negs, cnt);
+  }
 }
 
-// Trailing update below the panel [k0, k0 + w): tiles (I, J), J <= I, of the
-// front rows/columns from s0 = k0 + w, pair index in blockIdx.y.
+// Panel rows and trailing update below the panel [k0, k0 + w), one workgroup
+// per pair (I, J), J <= I, of 64-row tiles from s0 = k0 + w (pair index in
+// blockIdx.y): X_I = A_I D^T and X_J = A_J D^T from the panel rows A of the
+// front (MFMA; the diagonal pair writes X_I into the factor buffer), then
+// C_IJ -= X_I X_J^T on the front's lower triangle (MFMA).  Signed form: the
+// factor rows are X_I S and the update C_IJ -= X_I S X_J^T (S the panel's
+// pivot signs).  No workgroup writes
+// what another one reads: the panel is read from the front, X goes to the
+// factor buffer, and the C tiles are disjoint.
 template <class E>
-__global__ __launch_bounds__(FT) void k_syrk_update(DevTree t, const int* __restrict__ level_nodes, int k0,
-                                                    E* __restrict__ Lbuf, E* __restrict__ Ubuf) {
+__global__ __launch_bounds__(FT) void k_panel_update(DevTree t, const int* __restrict__ level_nodes, int k0,
+                                                     E* __restrict__ Lbuf, E* __restrict__ Ubuf,
+                                                     E* __restrict__ Fbuf, const E* __restrict__ Dbuf) {
+  typedef Tile64<E, 4> TL;
   const int v = level_nodes[blockIdx.x];
   const Front<E> F = front_of(t, v, Lbuf, Ubuf);
   if (F.no <= k0) return;
@@ -406,49 +533,87 @@ __global__ __launch_bounds__(FT) void k_syrk_update(DevTree t, const int* __rest
   const int J = pidx - I * (I + 1) / 2;
   const int rI = s0 + TB * I, rJ = s0 + TB * J;
   if (rI >= F.nf) return;
+  const int nf = F.nf;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ E As[TB * LDT];
-  __shared__ E Bs[TB * LDT];
-  for (int idx = tid; idx < TB * TB; idx += FT) {
-    const int i = idx % TB, k = idx / TB;
-    const int ra = rI + i, rb = rJ + i;
-    As[i * LDT + k] = (ra < F.nf && k < w) ? F.L[(int64_t)(k0 + k) * F.nf + ra] : E(0);
-    Bs[k * LDT + i] = (rb < F.nf && k < w) ? F.L[(int64_t)(k0 + k) * F.nf + rb] : E(0);
+  __shared__ E Xi[TB * LDT];   // X_I S (A operand; S the panel's pivot signs)
+  __shared__ E Xj[TB * LDT];   // X_J^T (B operand)
+  __shared__ E ps[TB];
+  if (tid < TB) ps[tid] = (t.sgn != nullptr && tid < w) ? (E)t.sgn[t.fdofs[t.foff[v] + k0 + tid]] : E(1);
+  // B operand of X = A D^T: D^T(k, j) = Dt[k * 64 + j], row-major in global memory
+  const E* Dt = Dbuf + ((int64_t)t.doff[v] + k0 / TB) * (TB * TB);
+  // the C tile's current values, loaded before the products so that their
+  // latency overlaps them (entries outside the lower triangle read the tile's
+  // corner and are not used)
+  typename TL::Acc c;
+  E* cp[TL::TI][TL::TJ][4];
+#pragma unroll
+  for (int ti = 0; ti < TL::TI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TL::TJ; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = rI + TL::row(lane, wave, ti, e), cc = rJ + TL::col(lane, wave, tj);
+        const bool in = r < nf && cc < nf && r >= cc;
+        cp[ti][tj][e] = in ? F.at(r, cc) : nullptr;
+        c.a[ti][tj][e] = *(in ? cp[ti][tj][e] : F.at(rI, rJ));
+      }
+  typename TL::Acc x;
+  TL::zero(x);
+  TL::mma_global(F.L + (int64_t)k0 * nf + rI, nf, nf - rI, Dt, TB, w, x, lane, wave);
+  E* Lf = Fbuf + t.loff[v];
+  __syncthreads();   // ps
+#pragma unroll
+  for (int ti = 0; ti < TL::TI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TL::TJ; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = TL::row(lane, wave, ti, e), cl = TL::col(lane, wave, tj);
+        const E val = x.a[ti][tj][e];
+        Xi[r * LDT + cl] = val * ps[cl];
+        if (I == J) {
+          Xj[cl * LDT + r] = val;
+          if (rI + r < nf && cl < w) Lf[(int64_t)(k0 + cl) * nf + rI + r] = val * ps[cl];
+        }
+      }
+  if (I != J) {
+    typename TL::Acc y;
+    TL::zero(y);
+    TL::mma_global(F.L + (int64_t)k0 * nf + rJ, nf, nf - rJ, Dt, TB, w, y, lane, wave);
+#pragma unroll
+    for (int ti = 0; ti < TL::TI; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < TL::TJ; ++tj)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          Xj[TL::col(lane, wave, tj) * LDT + TL::row(lane, wave, ti, e)] = y.a[ti][tj][e];
   }
   __syncthreads();
-  acc_t<E> acc[2][2];
+  TL::mma(Xi, Xj, w, c, lane, wave, E(-1));
 #pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
+  for (int ti = 0; ti < TL::TI; ++ti)
 #pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
+    for (int tj = 0; tj < TL::TJ; ++tj)
 #pragma unroll
-      for (int vv = 0; vv < 4; ++vv) {
-        const int r = rI + acc_row<E>(lane, wave, ti, vv), c = rJ + acc_col(lane, wave, tj);
-        acc[ti][tj][vv] = (r < F.nf && c < F.nf && r >= c) ? *F.at(r, c) : E(0);
-      }
-  mma64<E>(As, Bs, w, acc, lane, wave, E(-1));
-#pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-      for (int vv = 0; vv < 4; ++vv) {
-        const int r = rI + acc_row<E>(lane, wave, ti, vv), c = rJ + acc_col(lane, wave, tj);
-        if (r < F.nf && c < F.nf && r >= c) *F.at(r, c) = acc[ti][tj][vv];
-      }
+      for (int e = 0; e < 4; ++e)
+        if (cp[ti][tj][e] != nullptr) *cp[ti][tj][e] = c.a[ti][tj][e];
 }
 
-// Rows [64 y, +64) of X with X L_oo = [I; L_bo]; X row r at T[r * no + ...].
+// Rows [64 y, +64) of X with X L_oo = [I; L_bo] (L from the factor buffer);
+// X row r at Fout[r * no + ...] (the front buffer's block of the node).
+// Sixteen waves: each takes one 16 x 16 MFMA tile of a 64 x 64 product.
+constexpr int RT_THREADS = 1024;
 template <class E>
-__global__ __launch_bounds__(FT) void k_rtrsm(DevTree t, const int* __restrict__ level_nodes,
-                                              E* __restrict__ Lbuf, E* __restrict__ Ubuf,
-                                              E* __restrict__ Tbuf, const E* __restrict__ Dbuf) {
+__global__ __launch_bounds__(RT_THREADS) void k_rtrsm(DevTree t, const int* __restrict__ level_nodes,
+                                                      const E* __restrict__ Lfac, E* __restrict__ Fout,
+                                                      const E* __restrict__ Dbuf) {
+  typedef Tile64<E, RT_THREADS / 64> TL;
   const int v = level_nodes[blockIdx.x];
-  const Front<E> F = front_of(t, v, Lbuf, Ubuf);
-  const int nf = F.nf, no = F.no;
+  const int nf = t.nf[v], no = t.no[v];
   const int r0 = TB * blockIdx.y;
   if (r0 >= nf || no == 0) return;
-  E* T = Tbuf + t.loff[v];
+  const E* L = Lfac + t.loff[v];
+  E* T = Fout + t.loff[v];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ E As[TB * LDT];
   __shared__ E Bs[TB * LDT];
@@ -457,64 +622,83 @@ __global__ __launch_bounds__(FT) void k_rtrsm(DevTree t, const int* __restrict__
   for (int P = npan - 1; P >= 0; --P) {
     const int c0 = P * TB, w = min(TB, no - c0);
     if (top && r0 + TB - 1 < c0) {               // X[r][c] = 0 for c > r < no
-      for (int idx = tid; idx < TB * TB; idx += FT) {
+      for (int idx = tid; idx < TB * TB; idx += RT_THREADS) {
         const int i = idx / TB, j = idx % TB;
         if (j < w) T[(int64_t)(r0 + i) * no + c0 + j] = E(0);
       }
       continue;
     }
-    acc_t<E> acc[2][2];
+    typename TL::Acc acc;
 #pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
+    for (int ti = 0; ti < TL::TI; ++ti)
 #pragma unroll
-      for (int tj = 0; tj < 2; ++tj)
+      for (int tj = 0; tj < TL::TJ; ++tj)
 #pragma unroll
-        for (int vv = 0; vv < 4; ++vv) {
-          const int r = r0 + acc_row<E>(lane, wave, ti, vv), c = c0 + acc_col(lane, wave, tj);
-          E val = E(0);
-          if (r < nf && c < c0 + w) val = (r < no) ? (r == c ? E(1) : E(0)) : F.L[(int64_t)c * nf + r];
-          acc[ti][tj][vv] = val;
+        for (int e = 0; e < 4; ++e) {
+          const int r = r0 + TL::row(lane, wave, ti, e), c = c0 + TL::col(lane, wave, tj);
+          const bool bnd = r < nf && c < c0 + w && r >= no;
+          const E lv = L[bnd ? (int64_t)c * nf + r : 0];
+          acc.a[ti][tj][e] = bnd ? lv : ((r < nf && c < c0 + w && r == c) ? E(1) : E(0));
         }
     // minus X[:, kb] L[kb, P] over solved block columns kb > P (X vanishes past the diagonal for top rows)
     const int kbmax = top ? min(npan - 1, (r0 + TB - 1) / TB) : npan - 1;
     for (int kb = P + 1; kb <= kbmax; ++kb) {
       const int cb = kb * TB, wb = min(TB, no - cb);
-      __syncthreads();
-      for (int idx = tid; idx < TB * TB; idx += FT) {
-        const int k = idx % TB, i = idx / TB;      // As[i][k] = X[r0 + i][cb + k], coalesced in k
-        As[i * LDT + k] = (r0 + i < nf && k < wb) ? T[(int64_t)(r0 + i) * no + cb + k] : E(0);
-        const int j = idx / TB, kk = idx % TB;     // Bs[k][j] = L[cb + k][c0 + j], coalesced in k
-        Bs[kk * LDT + j] = (kk < wb && j < w) ? F.L[(int64_t)(c0 + j) * nf + cb + kk] : E(0);
+      // every load of both tiles issued before the first LDS store
+      constexpr int U = TB * TB / RT_THREADS;
+      E xa[U], xb[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = tid + u * RT_THREADS, k = idx % TB, i = idx / TB;
+        const bool ina = r0 + i < nf && k < wb;   // As[i][k] = X[r0 + i][cb + k], coalesced in k
+        const bool inb = k < wb && i < w;          // Bs[k][i] = L[cb + k][c0 + i], coalesced in k
+        xa[u] = T[ina ? (int64_t)(r0 + i) * no + cb + k : 0];
+        xb[u] = L[inb ? (int64_t)(c0 + i) * nf + cb + k : 0];
       }
       __syncthreads();
-      mma64<E>(As, Bs, wb, acc, lane, wave, E(-1));
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = tid + u * RT_THREADS, k = idx % TB, i = idx / TB;
+        As[i * LDT + k] = (r0 + i < nf && k < wb) ? xa[u] : E(0);
+        Bs[k * LDT + i] = (k < wb && i < w) ? xb[u] : E(0);
+      }
+      __syncthreads();
+      TL::mma(As, Bs, wb, acc, lane, wave, E(-1));
     }
     // X[:, P] = acc D_P
     __syncthreads();
-    const E* D = Dbuf + ((int64_t)t.doff[v] + P) * (TB * TB);
+    // D_P (stored transposed: Dt[j * 64 + k] = D[k][j]) as the B operand
+    const E* Dt = Dbuf + ((int64_t)t.doff[v] + P) * (TB * TB);
+    {
+      constexpr int U = TB * TB / RT_THREADS;
+      E xd[U];
 #pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
+      for (int u = 0; u < U; ++u) xd[u] = Dt[tid + u * RT_THREADS];
 #pragma unroll
-      for (int tj = 0; tj < 2; ++tj)
+      for (int ti = 0; ti < TL::TI; ++ti)
 #pragma unroll
-        for (int vv = 0; vv < 4; ++vv)
-          As[acc_row<E>(lane, wave, ti, vv) * LDT + acc_col(lane, wave, tj)] = acc[ti][tj][vv];
-    for (int idx = tid; idx < TB * TB; idx += FT) Bs[(idx / TB) * LDT + idx % TB] = D[idx];
+        for (int tj = 0; tj < TL::TJ; ++tj)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            As[TL::row(lane, wave, ti, e) * LDT + TL::col(lane, wave, tj)] = acc.a[ti][tj][e];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = tid + u * RT_THREADS;
+        Bs[(idx % TB) * LDT + idx / TB] = xd[u];
+      }
+    }
     __syncthreads();
-    acc_t<E> x[2][2];
+    typename TL::Acc x;
+    TL::zero(x);
+    TL::mma(As, Bs, w, x, lane, wave, E(1));
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int ti = 0; ti < TL::TI; ++ti)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) x[a][b] = acc_t<E>{0, 0, 0, 0};
-    mma64<E>(As, Bs, w, x, lane, wave, E(1));
+      for (int tj = 0; tj < TL::TJ; ++tj)
 #pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-        for (int vv = 0; vv < 4; ++vv) {
-          const int r = r0 + acc_row<E>(lane, wave, ti, vv), c = acc_col(lane, wave, tj);
-          if (r < nf && c < w) T[(int64_t)r * no + c0 + c] = x[ti][tj][vv];
+        for (int e = 0; e < 4; ++e) {
+          const int r = r0 + TL::row(lane, wave, ti, e), c = TL::col(lane, wave, tj);
+          if (r < nf && c < w) T[(int64_t)r * no + c0 + c] = x.a[ti][tj][e];
         }
     __syncthreads();   // T of this block column is read as the next panel's A operand
   }
@@ -544,9 +728,20 @@ __global__ __launch_bounds__(FT) void k_pack(DevTree t, const int* __restrict__ 
   if (r0 >= nfp || c0 >= nop) return;
   const E* T = Tbuf + t.loff[v];
   __shared__ E S[TB * LDT];
-  for (int idx = threadIdx.x; idx < TB * TB; idx += FT) {
-    const int i = idx / TB, c = idx % TB;         // row r0 + i, contiguous in c
-    S[i * LDT + c] = (r0 + i < nf && c0 + c < no) ? T[(int64_t)(r0 + i) * no + c0 + c] : E(0);
+  {
+    constexpr int U = TB * TB / FT;
+    E x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = threadIdx.x + u * FT, i = idx / TB, c = idx % TB;   // row r0 + i, contiguous in c
+      const bool in = r0 + i < nf && c0 + c < no;
+      x[u] = T[in ? (int64_t)(r0 + i) * no + c0 + c : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = threadIdx.x + u * FT, i = idx / TB, c = idx % TB;
+      S[i * LDT + c] = (r0 + i < nf && c0 + c < no) ? x[u] : E(0);
+    }
   }
   __syncthreads();
   E* L = Lp + t.lpoff[v];
@@ -569,35 +764,37 @@ __global__ __launch_bounds__(FT) void k_pack(DevTree t, const int* __restrict__ 
     }
   }
 }
-
+// One tree level.  Lf: the front buffer (assembled front, updated in place;
+// receives F), Lx: the factor buffer (L), U: update blocks, D: diagonal-block
+// inverses.
 template <class E>
 void front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
                   int max_nf, int max_child_nb, int max_kids, double s2, double s1, const double* K, const double* M,
-                  const double* C, E* L, E* U, E* T, E* D, E* Lp, E* Tp, const float* U32,
+                  const double* C, E* Lf, E* U, E* Lx, E* D, E* Lp, E* Tp, const float* U32,
                   const double* U64, int64_t* status, hipStream_t st) {
   if (count <= 0) return;
   const int ncol = (max_nf + TB - 1) / TB;
   hipLaunchKernelGGL(k_front_assemble<E>, dim3(count, ncol), dim3(FT), (size_t)2 * max_nf * sizeof(int), st, s.n,
-                     s.lo, s.hi, s.rowptr, t, level_nodes, s2, s1, K, M, C, L, U);
+                     s.lo, s.hi, s.rowptr, t, level_nodes, s2, s1, K, M, C, Lf, U);
   if (max_child_nb > 0)
     for (int slot = 0; slot < max_kids; ++slot)
       hipLaunchKernelGGL(k_front_extend<E>, dim3(count, (max_child_nb + TB - 1) / TB), dim3(FT),
                          (size_t)max_child_nb * sizeof(int), st, t,
-                         level_nodes, slot, L, U, U32, U64);
+                         level_nodes, slot, Lf, U, U32, U64);
   for (int k0 = 0; k0 < max_no; k0 += TB) {
-    hipLaunchKernelGGL(k_potrf_diag<E>, dim3(count), dim3(FT), 0, st, t, level_nodes, k0, L, U, D, status);
-    // rows and trailing tiles below a block that is at least one column wide
+    hipLaunchKernelGGL(k_potrf_diag<E>, dim3(count), dim3(FT), 0, st, t, level_nodes, k0, (const E*)Lf, Lx, D,
+                       status, (unsigned long long*)(status + 1));
+    // row tiles below a block that is at least one column wide; one workgroup per tile pair
     const int below = std::max(1, max_nf - k0 - 1);
     const int nrc = (below + TB - 1) / TB;
-    hipLaunchKernelGGL(k_trsm_panel<E>, dim3(count, nrc), dim3(FT), 0, st, t, level_nodes, k0, L, U,
-                       (const E*)D);
-    hipLaunchKernelGGL(k_syrk_update<E>, dim3(count, nrc * (nrc + 1) / 2), dim3(FT), 0, st, t, level_nodes,
-                       k0, L, U);
+    hipLaunchKernelGGL(k_panel_update<E>, dim3(count, nrc * (nrc + 1) / 2), dim3(FT), 0, st, t, level_nodes, k0,
+                       Lf, U, Lx, (const E*)D);
   }
   const int nrt = (max_nf + TB - 1) / TB;
-  hipLaunchKernelGGL(k_rtrsm<E>, dim3(count, nrt), dim3(FT), 0, st, t, level_nodes, L, U, T, (const E*)D);
+  hipLaunchKernelGGL(k_rtrsm<E>, dim3(count, nrt), dim3(RT_THREADS), 0, st, t, level_nodes, (const E*)Lx, Lf,
+                     (const E*)D);
   const int nct = (max_no + 3 + TB - 1) / TB, nrp = (max_nf + 3 + TB - 1) / TB;
-  hipLaunchKernelGGL(k_pack<E>, dim3(count, nrp * nct), dim3(FT), 0, st, t, level_nodes, (const E*)T, Lp, Tp);
+  hipLaunchKernelGGL(k_pack<E>, dim3(count, nrp * nct), dim3(FT), 0, st, t, level_nodes, (const E*)Lf, Lp, Tp);
 }
 
 void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,

@@ -315,8 +315,7 @@ __global__ __launch_bounds__(256) void k_dots_final(int nout, int nblk, const do
 
 void launch_dots(int64_t n, int nc, const double* Au, const double* Al, int64_t lda,
                  int nq, const double* Xu, const double* Xl, int64_t ldx,
-                 double* partial, unsigned* ticket, double* out, hipStream_t st) {
-  (void)ticket;
+                 double* partial, double* out, hipStream_t st) {
   if (nc <= 0) return;
   int blocks = dots_blocks(n);
 #define RIGA_DOTS(NQ)                                                                          \

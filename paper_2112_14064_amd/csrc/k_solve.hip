@@ -185,8 +185,10 @@ __global__ __launch_bounds__(NW * 64) void k_fwd(DevTree t, const SweepTask* __r
   reduce_waves<NR, NW>(acc, red, lane, wave);
   if (wave == 0 && live) {
     if (r < no) {
+      // signed factor L S L^T: the backward sweep starts from S L^{-1} b
+      const double sg = t.sgn != nullptr ? t.sgn[dst] : 1.0;
 #pragma unroll
-      for (int q = 0; q < NR; ++q) y[dst + q * ldy] = acc[q];
+      for (int q = 0; q < NR; ++q) y[dst + q * ldy] = acc[q] * sg;
     } else {
       double* uv = upd + (int64_t)(tk.voff + r - no) * NR;
 #pragma unroll

@@ -36,6 +36,8 @@ struct DevTree {
   const unsigned char* prec;    // per node: 1 = FP32 front (mixed factor), or null (all FP64)
   const int64_t* lpoff;         // per node: sweep layouts of F (see lp_group / tp_group;
   const int64_t* tpoff;         //   room for groups of 2 and of 4 elements)
+  double* sgn;                  // per dof: sign of its pivot in the signed factorization
+                                //   K - s M = L S L^T (null: Cholesky, every sign +1)
   const unsigned char* ttri;    // per node: 1 = Tp without the zero triangle, 0 = full
                                 //   rectangle (F[gK + s][a] at ((g no + a) K + s))
   // Forest of independent problems (batched form), all null for one problem:
@@ -51,26 +53,29 @@ struct DevTree {
 // the Cox--de Boor values at the (p+1)-point Gauss rule (gx, gw on [-1, 1]).
 void launch_bspline_tables(const DevSpace& s, const double* gx, const double* gw,
                            double* tabM, double* tabK, hipStream_t st);
-// CSR values of K, M and C = alpha M + beta K + sum_e c_e M_e by gather.
-void launch_assemble(const DevSpace& s, const double* tabM, const double* tabK,
-                     double alpha, double beta, const double* c_elem,
-                     double* K, double* M, double* C, int64_t ndof, hipStream_t st);
-// Both steps for every problem of a forest in two launches: per problem q its
-// space spaces[q], first row dofbase[q], tables at tabM/tabK + taboff[q],
-// Gauss rule gx[q]/gw[q] (device pointer arrays), damping alpha[q], beta[q],
-// c_elem[q] (may be null); rb: row blocks of at most 256 rows of one problem.
 // Banded 1-D factors of M and K of a space (see k_assemble.hip): M1, K1 hold
 // n (2p + 1) doubles, entry (i, ii) at i (2p + 1) + ii - i + p.
 void launch_band_1d(const DevSpace& s, const double* tabM, const double* tabK, double* M1, double* K1,
                     hipStream_t st);
+// CSR values of K, M and C = alpha M + beta K + sum_e c_e M_e from the bands
+// (launch_band_1d first) and, for c_elem, the element tables: one wave per row.
+void launch_assemble(const DevSpace& s, const double* tabM, const double* M1, const double* K1,
+                     double alpha, double beta, const double* c_elem,
+                     double* K, double* M, double* C, int64_t ndof, hipStream_t st);
 // Bands of every problem of a forest: problem q's tables at taboff[q], its
 // bands at bandoff[q] (max_w: the largest n (2p + 1)).
 void launch_band_1d_b(const DevSpace* spaces, int n, int max_w, const int64_t* taboff, const double* tabM,
                       const double* tabK, const int64_t* bandoff, double* M1, double* K1, hipStream_t st);
+// Tables, bands and entries for every problem of a forest in three launches:
+// per problem q its space spaces[q], first row dofbase[q], tables at tabM/tabK
+// + taboff[q], bands at M1/K1 + bandoff[q], Gauss rule gx[q]/gw[q] (device
+// pointer arrays), damping alpha[q], beta[q], c_elem[q] (may be null); rb: row
+// blocks of at most 256 rows of one problem.
 void launch_assemble_b(const int4* rb, int nrb, const DevSpace* spaces, const int64_t* dofbase,
                        const int64_t* taboff, const double* const* gx, const double* const* gw, int n, int max_ne,
-                       double* tabM, double* tabK, const double* alpha, const double* beta,
-                       const double* const* c_elem, double* K, double* M, double* C, hipStream_t st);
+                       double* tabM, double* tabK, int max_w, const int64_t* bandoff, double* M1, double* K1,
+                       const double* alpha, const double* beta, const double* const* c_elem, double* K, double* M,
+                       double* C, hipStream_t st);
 
 // --- factorization ------------------------------------------------------------
 // One tree level: assemble each front (original entries of Q = s2 M + s1 C + K
@@ -193,10 +198,10 @@ void launch_spmv3(const DevSpace& s, int64_t ndof, int ncols, const double* A0, 
                   const double* X, int64_t ldx, double* Y0, double* Y1, double* Y2, int64_t ldy, hipStream_t st);
 // out[c*nq + q] = sum_i Au[i,c] Xu[i,q] + Al[i,c] Xl[i,q]  (Al/Xl may be null),
 // c < nc, q < nq <= 4; deterministic two-stage reduction.  partial: >= nblk*nc*nq
-// doubles of scratch, ticket: one zeroed uint32.
+// doubles of scratch.
 void launch_dots(int64_t n, int nc, const double* Au, const double* Al, int64_t lda,
                  int nq, const double* Xu, const double* Xl, int64_t ldx,
-                 double* partial, unsigned* ticket, double* out, hipStream_t st);
+                 double* partial, double* out, hipStream_t st);
 int dots_blocks(int64_t n);
 // Z[:, q] -= sum_c A[:, c] h[c*nq+q] for up to three (A, Z) pairs sharing h.
 // With gpart (nq <= 4), every block also writes the sum over its rows of the

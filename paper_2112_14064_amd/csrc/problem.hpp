@@ -57,9 +57,10 @@ struct riga_problem {
   std::vector<int> fvar, bvar;                      // sweep tile shape per level (autotuned)
   double* d_tune = nullptr;                         // autotuner output block (ndof x 4)
   std::vector<int> ftask_off, btask_off;
-  int64_t* d_status = nullptr;
+  int64_t* d_status = nullptr;      // [0] first failed pivot (-1: none), [1] negative pivots
+  double* d_sgn = nullptr;          // pivot signs of the signed factorization (ndof)
+  bool gep = false;                 // the factor is K - s M (signed form), not Q(sigma)
   double* d_part = nullptr;       // reduction scratch
-  unsigned* d_ticket = nullptr;
   int64_t upd_len = 0;
   bool assembled = false, factored = false;
   double alpha = 0, beta = 0, sigma = 0;
@@ -177,9 +178,14 @@ void sweep(riga_problem* h, int nrhs, const double* b, int64_t ldb, const riga::
            const SolveWork* w = nullptr);
 void solve_levels(riga_problem* h, int nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
                   double* r_l, const double* v_u, int64_t ldv, double sig, const SolveWork* w = nullptr);
-void factor_level(riga_problem* h, int lv, double sigma);
+void factor_level(riga_problem* h, int lv, double s2, double s1);
 // Factor every level; RIGA_ERR_NOT_SPD with *bad_pivot (a dof) on a failed pivot.
 riga_status factor_all(riga_problem* h, double sigma, int64_t* bad_pivot);
+// K - shift M in the signed form L S L^T; *negs = negative pivots (the number
+// of eigenvalues of K u = mu M u below shift).
+riga_status factor_gep_all(riga_problem* h, double shift, int64_t* bad_pivot, int64_t* negs);
+void ensure_norms(riga_problem* h);
+void ensure_krylov(riga_problem* h, int cols, int b);
 int small_chol(int b, const std::vector<double>& G, std::vector<double>& R, double rel);
 // Autotune the per-level sweep shapes of a factored handle (see riga_autotune).
 void autotune_sweeps(riga_problem* h, int nrhs, int reps, double* before_ms, double* after_ms);

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <limits>
+#include <numeric>
 
 namespace riga {
 
@@ -718,6 +719,67 @@ int realify(int n, int k, const std::vector<cplx>& Z, std::vector<double>& Q) {
     }
   }
   return rank;
+}
+
+int sym_eig_jacobi(int n, const double* Ain, std::vector<double>& w, std::vector<double>& Z) {
+  std::vector<double> A((size_t)n * n);
+  for (int j = 0; j < n; ++j)
+    for (int i = j; i < n; ++i) A[i + (size_t)j * n] = A[j + (size_t)i * n] = Ain[i + (size_t)j * n];
+  Z.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Z[i + (size_t)i * n] = 1.0;
+  double fro = 0.0;
+  for (double x : A) fro += x * x;
+  const double eps = std::numeric_limits<double>::epsilon();
+  const double floor_abs = eps * eps * std::sqrt(fro);
+  // a pair is rotated only while |a_pq| exceeds eps sqrt(|a_pp a_qq|) (below
+  // that it no longer moves the diagonal in working precision); a sweep with
+  // no rotation ends the iteration
+  int sweeps = 0;
+  bool rotated = true;
+  for (; sweeps < 50 && rotated; ++sweeps) {
+    rotated = false;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p + (size_t)q * n];
+        const double app = A[p + (size_t)p * n], aqq = A[q + (size_t)q * n];
+        if (std::abs(apq) <= std::max(eps * std::sqrt(std::abs(app * aqq)), floor_abs)) continue;
+        rotated = true;
+        // rotation [c s; -s c] with tan = t the smaller root of t^2 + 2 tau t - 1 = 0
+        const double tau = (aqq - app) / (2.0 * apq);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::abs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+        // A <- J^T A J on rows / columns p and q
+        for (int k = 0; k < n; ++k) {
+          const double akp = A[k + (size_t)p * n], akq = A[k + (size_t)q * n];
+          A[k + (size_t)p * n] = c * akp - s * akq;
+          A[k + (size_t)q * n] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A[p + (size_t)k * n], aqk = A[q + (size_t)k * n];
+          A[p + (size_t)k * n] = c * apk - s * aqk;
+          A[q + (size_t)k * n] = s * apk + c * aqk;
+        }
+        A[p + (size_t)q * n] = A[q + (size_t)p * n] = 0.0;
+        for (int k = 0; k < n; ++k) {
+          const double zkp = Z[k + (size_t)p * n], zkq = Z[k + (size_t)q * n];
+          Z[k + (size_t)p * n] = c * zkp - s * zkq;
+          Z[k + (size_t)q * n] = s * zkp + c * zkq;
+        }
+      }
+  }
+  if (rotated) return -1;
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(),
+                   [&](int a, int b) { return A[a + (size_t)a * n] < A[b + (size_t)b * n]; });
+  w.resize(n);
+  std::vector<double> Zs((size_t)n * n);
+  for (int i = 0; i < n; ++i) {
+    w[i] = A[idx[i] + (size_t)idx[i] * n];
+    for (int k = 0; k < n; ++k) Zs[k + (size_t)i * n] = Z[k + (size_t)idx[i] * n];
+  }
+  Z.swap(Zs);
+  return sweeps;
 }
 
 }  // namespace riga

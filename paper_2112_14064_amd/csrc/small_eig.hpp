@@ -66,6 +66,14 @@ void schur_eigvecs_real(int n, const std::vector<double>& T, const std::vector<d
 // entry not kept moves down past the kept ones below it.
 void schur_select(int n, std::vector<cplx>& T, std::vector<cplx>& Z, const std::vector<char>& keep);
 
+// Eigenvalues w (ascending) and orthonormal eigenvectors Z (n x n,
+// column-major, column i for w[i]) of a real symmetric n x n column-major A
+// (only its lower triangle is read) by the cyclic Jacobi method: plane
+// rotations that annihilate one off-diagonal pair at a time, swept row by row
+// until no pair exceeds eps sqrt(|a_pp a_qq|) (Golub and Van Loan, Sec. 8.5).
+// Returns the number of sweeps, or -1 without convergence in 50 sweeps.
+int sym_eig_jacobi(int n, const double* A, std::vector<double>& w, std::vector<double>& Z);
+
 // Real orthonormal basis Q (n x r, column-major) of span{Re z, Im z} over the
 // first k columns of Z (n x n).  When those columns span a subspace closed
 // under conjugation, r == k.  Returns r.

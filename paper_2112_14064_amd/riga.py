@@ -61,6 +61,7 @@ EXPORTS = ["riga_create", "riga_info", "riga_assemble", "riga_export_csr", "riga
            "riga_ir_sweeps", "riga_batch_create", "riga_batch_info", "riga_batch_assemble", "riga_batch_factor",
            "riga_batch_eigs", "riga_batch_stats", "riga_batch_destroy", "riga_autotune", "riga_sweep_shapes",
            "riga_batch_autotune",
+           "riga_factor_gep", "riga_gep_slice",
            "riga_solve_q", "riga_solve_q_noalloc", "riga_apply_op", "riga_eigs", "riga_adjoint", "riga_stats", "riga_time_kernel",
            "riga_selftest_small_eig", "riga_selftest_schur_restart", "riga_symbolic", "riga_status_str", "riga_destroy"]
 
@@ -89,6 +90,9 @@ def load(path: str = LIB_PATH):
     lib.riga_ir_sweeps.argtypes = [P, C.POINTER(C.c_int)]
     lib.riga_solve_q.argtypes = [P, C.c_int, P, P]
     lib.riga_solve_q_noalloc.argtypes = [P, C.c_int, P, P]
+    lib.riga_factor_gep.argtypes = [P, C.c_double, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.riga_gep_slice.argtypes = [P, C.c_double, C.c_double, C.c_int, C.POINTER(riga_options), C.c_int, P, P, P,
+                                   C.POINTER(C.c_int64), C.POINTER(C.c_int), P]
     lib.riga_apply_op.argtypes = [P, C.c_int, P, P]
     lib.riga_eigs.argtypes = [P, C.POINTER(riga_options), P, P, P, C.POINTER(C.c_int)]
     lib.riga_adjoint.argtypes = [P, C.c_int, P, P, P, P]
@@ -284,6 +288,42 @@ class Problem:
         x = self.torch.empty_like(b)
         _check(self.lib.riga_solve_q(self.h, b.shape[0], _ptr(b), _ptr(x)), "riga_solve_q")
         return x
+
+    def factor_gep(self, shift: float) -> int:
+        """riga_factor_gep: signed factorization of K - shift M; returns the
+        number of eigenvalues of K u = mu M u below shift (its inertia)."""
+        neg = C.c_int64(-1)
+        bad = C.c_int64(-1)
+        st = self.lib.riga_factor_gep(self.h, shift, C.byref(neg), C.byref(bad))
+        if st == RIGA_ERR_NOT_SPD:
+            err = RigaError(st, "riga_factor_gep")
+            err.bad_pivot = int(bad.value)
+            raise err
+        _check(st, "riga_factor_gep")
+        return int(neg.value)
+
+    def gep_slice(self, a: float, b: float, max_slice: int = 0, block: int = 0, tol: float = 0.0,
+                  maxit: int = 0, seed: int = 0, cap: int = 512, vectors: bool = True):
+        """riga_gep_slice: every eigenvalue of K u = mu M u in [a, b).  Returns
+        (mu ndarray, U tensor (found, ndof) or None, resid ndarray or None,
+        count, status, stats dict)."""
+        opt = riga_options(0, 0, maxit, block, tol, seed, None, 0, 0)
+        mu = np.zeros(cap)
+        res = np.zeros(cap)
+        U = self.torch.empty((cap, self.ndof), dtype=self.torch.float64, device=self.device) if vectors else None
+        cnt = C.c_int64(0)
+        fnd = C.c_int(0)
+        stats = np.zeros(4, dtype=np.int64)
+        st = self.lib.riga_gep_slice(self.h, a, b, max_slice, C.byref(opt), cap, mu.ctypes.data_as(C.c_void_p),
+                                     _ptr(U) if vectors else None,
+                                     res.ctypes.data_as(C.c_void_p) if vectors else None,
+                                     C.byref(cnt), C.byref(fnd), stats.ctypes.data_as(C.c_void_p))
+        _check(st, "riga_gep_slice", allow_warn=True)
+        n = int(fnd.value)
+        st_d = {"factorizations": int(stats[0]), "slices": int(stats[1]), "operator_columns": int(stats[2]),
+                "restarts": int(stats[3])}
+        return (mu[:n].copy(), U[:n] if vectors else None, res[:n].copy() if vectors else None, int(cnt.value),
+                st, st_d)
 
     def solve_q_noalloc(self, b, x):
         """riga_solve_q_noalloc: x = Q(sigma)^{-1} b with the library's static

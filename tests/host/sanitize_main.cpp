@@ -5,9 +5,11 @@
 //     symbolic Cholesky and the forest merge of the batched form;
 //   - the dense real Schur form of a projected matrix (eq. ArnoldiRitz) and
 //     the reordering of the Krylov--Schur restart (Sec. 4.1.3);
+//   - the symmetric Jacobi eigensolver of the Lanczos slices (Sec. 4.1.2);
 //   - one Rayleigh--Ritz + restart cycle on a random block Hessenberg matrix;
 //   - the host worker pool, including a job that throws.
 // Exit status 0 when every check passes; a sanitizer report fails the run.
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -147,6 +149,54 @@ void pool() {
   P.run(64, [&](int) { ++cnt; });
   check(cnt.load() == 64, "the pool runs again after an exception");
 }
+// The symmetric eigensolver of the Lanczos slices: A = Q diag(d) Q^T with a
+// known spectrum spread over eight decades, both signs and a double value
+// (Q a product of random Householder reflectors); the computed values must
+// match d sorted and the vectors must be orthonormal with small residuals.
+void symmetric_eig(std::mt19937_64& rng) {
+  std::normal_distribution<double> g;
+  for (int n : {1, 2, 9, 40, 84, 160}) {
+    std::vector<double> d(n), Q((size_t)n * n, 0.0), A((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) d[i] = (i % 2 ? -1.0 : 1.0) * std::pow(10.0, -4.0 + 8.0 * i / std::max(1, n - 1));
+    if (n > 3) d[3] = d[2];
+    for (int i = 0; i < n; ++i) Q[i + (size_t)i * n] = 1.0;
+    for (int r = 0; r < 3; ++r) {
+      std::vector<double> v(n);
+      double vv = 0.0;
+      for (auto& x : v) { x = g(rng); vv += x * x; }
+      for (int i = 0; i < n; ++i) {   // Q <- Q (I - 2 v v^T / v^T v)
+        double qv = 0.0;
+        for (int k = 0; k < n; ++k) qv += Q[i + (size_t)k * n] * v[k];
+        for (int k = 0; k < n; ++k) Q[i + (size_t)k * n] -= 2.0 * qv * v[k] / vv;
+      }
+    }
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s += Q[i + (size_t)k * n] * d[k] * Q[j + (size_t)k * n];
+        A[i + (size_t)j * n] = s;
+      }
+    std::vector<double> w, Z;
+    check(riga::sym_eig_jacobi(n, A.data(), w, Z) >= 0, "Jacobi converges");
+    std::vector<double> ds = d;
+    std::sort(ds.begin(), ds.end());
+    double ev = 0.0, orth = 0.0, res = 0.0;
+    for (int i = 0; i < n; ++i) ev = std::max(ev, std::abs(w[i] - ds[i]));
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) {
+        double s = 0.0, r = 0.0;
+        for (int k = 0; k < n; ++k) s += Z[k + (size_t)a * n] * Z[k + (size_t)b * n];
+        orth = std::max(orth, std::abs(s - (a == b ? 1.0 : 0.0)));
+        for (int k = 0; k < n; ++k) r += A[a + (size_t)k * n] * Z[k + (size_t)b * n];
+        res = std::max(res, std::abs(r - w[b] * Z[a + (size_t)b * n]));
+      }
+    // A itself carries the rounding of Q diag(d) Q^T, about n eps max|d|
+    const double scale = 1e-4 * std::pow(10.0, 8.0);
+    check(ev <= 1e-14 * n * scale, "Jacobi eigenvalues");
+    check(orth <= 1e-13 * n, "Jacobi vectors orthonormal");
+    check(res <= 1e-14 * n * scale, "Jacobi residuals");
+  }
+}
 
 }  // namespace
 
@@ -156,6 +206,7 @@ int main(int argc, char** argv) {
   if (!tsan) {
     plans();
     dense_eig(rng);
+    symmetric_eig(rng);
     krylov_schur_cycle(rng);
   }
   pool();
