@@ -16,7 +16,11 @@ The precision form (FP32 fronts + FP64 refinement against the FP64 path on
 the p=4, 1024^2, s=32 workload) and the batching form (256 uneven problems
 solved together) are measured last and reported beside it.
 
+The undamped case (C = 0: all eigenvalues of K u = mu M u in an interval by
+spectrum slicing) on the same mesh, rIGA and IGA, is reported last.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-iga] [--no-mixed] [--no-batch]
+                       [--no-undamped]
 """
 from __future__ import annotations
 
@@ -249,6 +253,54 @@ def oracle_check(P, lam_gpu):
     return float(rel.max()), int((rel <= 1e-10).sum())
 
 
+def undamped_form(torch, riga, W):
+    """The undamped case (C = 0) on the headline mesh, rIGA and IGA: every
+    eigenvalue of K u = mu M u in [0, 1500) by spectrum slicing (inertia of
+    signed factorizations, block Lanczos per slice), one warm-up and one timed
+    call each; eigenpairs/s counts the returned pairs with scaled residual
+    <= 1e-10."""
+    out, mus = {}, {}
+    for s in (16, 0):
+        P = W.cfg_undamped(s)
+        a, b = P.extra["interval"]
+        pr = riga.Problem(P.p, P.ne, P.hyper_every)
+        pr.assemble(0.0, 0.0)
+        pr.gep_slice(a, b, max_slice=P.extra["max_slice"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mu, U, eta, count, st, stats = pr.gep_slice(a, b, max_slice=P.extra["max_slice"])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        good = int(sum(1 for e in eta if e <= 1e-10))
+        st_h = pr.stats()
+        out["riga" if s else "iga"] = {
+            "workload": f"p={P.p}, {P.ne}x{P.ne}, " + (f"rIGA s={s}" if s else "IGA") +
+                        f", all mu in [{a:g}, {b:g}), slices of <= {P.extra['max_slice']}",
+            "ndof": int(pr.ndof), "count": int(count), "found": int(len(mu)), "status": int(st),
+            "ms": ms, "eigenpairs_per_s": good * 1e3 / ms, "pairs_ok": good,
+            "factor_ms_total": st_h["t_factor_ms"], "max_eta": float(max(eta)) if len(eta) else None,
+            **stats}
+        mus["riga" if s else "iga"] = (P, mu)
+        pr.close()
+    return out, mus
+
+
+def oracle_check_undamped(mus):
+    """Count and eigenvalues of the undamped leg against the oracle's closed
+    form (Kronecker sums of the 1-D pencil): part of the CPU-baseline leg."""
+    import numpy as np
+
+    from oracle import gep as ogep
+
+    res = {}
+    for k, (P, mu) in mus.items():
+        a, b = P.extra["interval"]
+        ref = ogep.gep_closed(P.p, P.ne, P.hyper_every, a, b)
+        rel = float(np.max(np.abs(mu - ref) / np.abs(ref))) if len(ref) == len(mu) and len(mu) else None
+        res[k] = (len(ref), rel)
+    return res
+
+
 def cpu_baseline(P, lam_gpu):
     """The oracle as it stands: SciPy sparse LU of Q(sigma) + ARPACK on the
     shift-and-invert operator, same workload (full solve, ~30 s)."""
@@ -298,6 +350,7 @@ def main():
     ap.add_argument("--no-iga", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-undamped", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy three times (the known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -357,6 +410,9 @@ def main():
         out["precision_form"] = precision_form(torch, riga, W)
     if not args.no_batch:
         out["batching_form"] = batching_form(torch, riga, W)
+    mus = None
+    if not args.no_undamped:
+        out["undamped_form"], mus = undamped_form(torch, riga, W)
     if roof is not None:
         out["roofline"] = roof
     if not args.no_cpu:
@@ -368,6 +424,10 @@ def main():
         if iga is not None:
             out["iga_fp64"]["max_rel_err_vs_oracle"], out["iga_fp64"]["pairs_within_1e-10_of_oracle"] = \
                 oracle_check(Pi, lam_iga)
+        if mus is not None:
+            for k, (n_ref, rel) in oracle_check_undamped(mus).items():
+                out["undamped_form"][k]["oracle_count"] = n_ref
+                out["undamped_form"][k]["max_rel_err_vs_oracle"] = rel
     print(json.dumps(out))
 
 

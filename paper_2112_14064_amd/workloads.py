@@ -85,6 +85,16 @@ def cfg_riga_vs_iga(hyper_every: int = 16) -> Problem:
                    sigma=2.0, nev=40, m=80, name=f"p3_256x256_{tag}")
 
 
+def cfg_undamped(hyper_every: int = 16) -> Problem:
+    """The undamped case (C = 0: K u = mu M u) on the headline mesh, p=3 on
+    256x256, rIGA (C^0 every 16 elements) or IGA (hyper_every=0): every
+    eigenvalue in [0, 1500) (108 with multiplicity) by spectrum slicing
+    with at most 40 eigenvalues per slice."""
+    tag = f"s{hyper_every}" if hyper_every else "iga"
+    return Problem(p=3, ne=256, hyper_every=hyper_every, name=f"p3_256x256_{tag}_undamped",
+                   extra={"interval": (0.0, 1500.0), "max_slice": 40})
+
+
 def cfg_precision() -> Problem:
     """p=4 on 1024x1024, C^0 every 32 elements, c_e ~ lognormal(-3,0.5) seed 0,
     20 eigenpairs near sigma=5."""
