@@ -402,7 +402,10 @@ riga_status riga_factor_gep(riga_problem* h, double shift, int64_t* neg_count, i
  *      converged values with mu in [l, r) are returned.
  *   cap    room (pairs) in mu / U / resid; count > cap gives RIGA_ERR_INVALID_ARG
  *          with *count written.
- *   mu     host, cap doubles: the eigenvalues, ascending.
+ *   mu     host, cap doubles: the eigenvalues, ascending: with U, the Rayleigh
+ *          quotients u^T K u / u^T M u of the returned vectors (error quadratic
+ *          in theirs); without, the Ritz values s + 1/theta, whose error grows
+ *          as (mu - s)^2 away from the slice's shift.
  *   U      device, ndof x cap column-major, or NULL: M-orthonormal eigenvectors.
  *   resid  host, cap doubles, or NULL (needs U): ||K u - mu M u||_2 /
  *          ((||K||_1 + |mu| ||M||_1) ||u||_2).

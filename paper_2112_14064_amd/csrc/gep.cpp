@@ -247,6 +247,68 @@ int solve_slice(riga_problem* h, double s, double lo, double hi, int want, int r
   return 0;
 }
 
+// mu[j] = u_j^T K u_j / u_j^T M u_j for the n columns of U.  A Ritz value
+// s + 1/theta far from its slice's shift carries the rounding of the shifted
+// solves amplified by (mu - s)^2 |theta_max|; the Rayleigh quotient's error is
+// quadratic in the eigenvector's.  Two columns per pass: K u and M u side by
+// side in d_tmp2 (N x 4), the four products of each column with them in one
+// reduction; one synchronisation per group that d_small holds.
+void rayleigh_quotients(riga_problem* h, int n, const double* U, double* mu) {
+  const int64_t N = h->N();
+  double* T = h->d_tmp2;
+  const int per_group = std::max(1, (int)((4 * h->kw_cols * h->kw_cols + 64) / 8));
+  for (int g0 = 0; g0 < n; g0 += 2 * per_group) {
+    const int g1 = std::min(n, g0 + 2 * per_group);
+    for (int j = g0; j < g1; j += 2) {
+      const int c = std::min(2, g1 - j);
+      const double* u = U + (size_t)j * N;
+      // K u_c at T + 2cN, M u_c at T + (2c + 1)N
+      riga::launch_spmv(h->ds, N, c, h->d_K, 1.0, u, N, T, 2 * N, nullptr, 0, 0.0, nullptr, 0, h->st);
+      riga::launch_spmv(h->ds, N, c, h->d_M, 1.0, u, N, T + N, 2 * N, nullptr, 0, 0.0, nullptr, 0, h->st);
+      riga::launch_dots(N, c, u, nullptr, N, 2 * c, T, nullptr, N, h->d_part, h->d_small + 4 * (j - g0), h->st);
+    }
+    std::vector<double> out((size_t)4 * (g1 - g0 + 1));
+    ck(hipMemcpyAsync(out.data(), h->d_small, (size_t)4 * (g1 - g0) * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    ck(hipStreamSynchronize(h->st));
+    for (int jc = g0; jc < g1; jc += 2) {
+      const int cc = std::min(2, g1 - jc), nq = 2 * cc;
+      const double* o = out.data() + 4 * (jc - g0);   // o[c nq + q]: column c times T column q
+      for (int c = 0; c < cc; ++c) {
+        const double uku = o[c * nq + 2 * c], umu = o[c * nq + 2 * c + 1];
+        if (umu > 0.0 && std::isfinite(uku)) mu[jc + c] = uku / umu;
+      }
+    }
+  }
+}
+
+// Ascending order of the n values, the columns of U permuted with them (a
+// polished value can pass a neighbour it was within rounding of).
+void order_pairs(riga_problem* h, int n, double* U, double* mu) {
+  std::vector<int> perm(n);
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int c) { return mu[a] < mu[c]; });
+  const int64_t N = h->N();
+  const size_t bytes = (size_t)N * sizeof(double);
+  std::vector<double> sorted(n);
+  std::vector<char> seen(n, 0);
+  for (int i = 0; i < n; ++i) sorted[i] = mu[perm[i]];
+  // column i of the result is column perm[i]: follow each cycle once through
+  // one spare column
+  for (int i = 0; i < n; ++i) {
+    if (seen[i] || perm[i] == i) { seen[i] = 1; continue; }
+    ck(hipMemcpyAsync(h->d_tmp, U + (size_t)i * N, bytes, hipMemcpyDeviceToDevice, h->st));
+    int j = i;
+    while (perm[j] != i) {
+      ck(hipMemcpyAsync(U + (size_t)j * N, U + (size_t)perm[j] * N, bytes, hipMemcpyDeviceToDevice, h->st));
+      seen[j] = 1;
+      j = perm[j];
+    }
+    ck(hipMemcpyAsync(U + (size_t)j * N, h->d_tmp, bytes, hipMemcpyDeviceToDevice, h->st));
+    seen[j] = 1;
+  }
+  for (int i = 0; i < n; ++i) mu[i] = sorted[i];
+}
+
 }  // namespace
 
 extern "C" {
@@ -346,6 +408,10 @@ riga_status riga_gep_slice(riga_problem* h, double a, double b, int max_slice, c
       nout += nf;
     }
     *found = nout;
+    if (U != nullptr && nout > 0) {
+      rayleigh_quotients(h, nout, U, mu);
+      order_pairs(h, nout, U, mu);
+    }
     if (resid != nullptr && U != nullptr && nout > 0) {
       ensure_norms(h);
       const double nk = h->norms[0], nm = h->norms[2];
