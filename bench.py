@@ -17,10 +17,12 @@ the p=4, 1024^2, s=32 workload) and the batching form (256 uneven problems
 solved together) are measured last and reported beside it.
 
 The undamped case (C = 0: all eigenvalues of K u = mu M u in an interval by
-spectrum slicing) on the same mesh, rIGA and IGA, is reported last.
+spectrum slicing) on the same mesh, rIGA and IGA, is reported last, and the
+headline step with the Krylov basis in compact two-level (TOAR) form beside
+the full basis.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-iga] [--no-mixed] [--no-batch]
-                       [--no-undamped]
+                       [--no-undamped] [--no-toar] [--basis full|toar]
 """
 from __future__ import annotations
 
@@ -38,14 +40,14 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 
 
-def run_config(torch, riga, P, steps, warmup, block):
+def run_config(torch, riga, P, steps, warmup, block, flags=0):
     pr = riga.Problem(P.p, P.ne, P.hyper_every)
     info = pr.info
 
     def one():
         pr.assemble(P.alpha, P.beta)
         pr.factor(P.sigma)
-        return pr.eigs(P.nev, P.m, block=block, seed=0, vectors=True)
+        return pr.eigs(P.nev, P.m, block=block, seed=0, vectors=True, flags=flags)
 
     for _ in range(warmup):
         one()
@@ -130,6 +132,24 @@ def roofline(pr, res, block):
                 # last-level cache (MALL), so the sweeps of this workload can hit it
                 "solve_factor_mb": res["solve_factor_mb"], "mall_resident": res["solve_factor_mb"] < 256.0})
     return out
+
+
+def compact_basis_form(torch, riga, W, steps, block):
+    """The headline workload (rIGA and IGA) with the Krylov basis in compact
+    two-level form (RIGA_EIGS_TOAR): the same step, timed the same way, and
+    the N-long Krylov storage of both forms."""
+    out, lams = {}, {}
+    for s in (16, 0):
+        P = W.cfg_riga_vs_iga(s)
+        pr, res, lam = run_config(torch, riga, P, steps, 1, block, flags=riga.RIGA_EIGS_TOAR)
+        ldh = P.m + 2 * block
+        res["krylov_storage_mb"] = 2 * res["ndof"] * ldh * 8 / 1e6          # U and its restart copy
+        res["full_basis_storage_mb"] = 6 * res["ndof"] * ldh * 8 / 1e6       # V_u, V_l, M V_l and copies
+        res["toar_drop"] = pr.stats()["toar_drop"]
+        out["riga" if s else "iga"] = res
+        lams["riga" if s else "iga"] = (P, lam)
+        pr.close()
+    return out, lams
 
 
 def precision_form(torch, riga, W, ir_tol=1e-9):
@@ -351,6 +371,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-undamped", action="store_true")
+    ap.add_argument("--no-toar", action="store_true")
+    ap.add_argument("--basis", choices=("full", "toar"), default="full",
+                    help="Krylov basis of the timed headline steps: the full 2N-long basis (default) or the "
+                         "compact two-level form")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy three times (the known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -371,13 +395,14 @@ def main():
 
     riga.load()
     P = W.cfg_riga_vs_iga(16)
-    pr, res, lam = run_config(torch, riga, P, args.steps, args.warmup, args.block)
+    main_flags = riga.RIGA_EIGS_TOAR if args.basis == "toar" else 0
+    pr, res, lam = run_config(torch, riga, P, args.steps, args.warmup, args.block, flags=main_flags)
     roof = roofline(pr, res, args.block)
     pr.close()
     iga = None
     if not args.no_iga:
         Pi = W.cfg_riga_vs_iga(0)
-        pri, iga, lam_iga = run_config(torch, riga, Pi, 1, 1, args.block)
+        pri, iga, lam_iga = run_config(torch, riga, Pi, 1, 1, args.block, flags=main_flags)
         pri.close()
     out = {
         "metric": METRIC,
@@ -396,7 +421,7 @@ def main():
                                "hyperplanes every 16 elements, Rayleigh 0.05M+0.005K, 40 eigenpairs "
                                "nearest sigma=2, subspace 80",
                    "p": P.p, "ne": P.ne, "hyper_every": P.hyper_every, "nev": P.nev, "m": P.m,
-                   "block": args.block, "ndof": res["ndof"]},
+                   "block": args.block, "ndof": res["ndof"], "basis": args.basis},
         "riga_fp64": res,
     }
     if iga is not None:
@@ -406,6 +431,9 @@ def main():
             "eigs": iga["eigs_ms"] / res["eigs_ms"],
             "step": iga["ms_per_step"] / res["ms_per_step"],
         }
+    toar_lams = None
+    if not args.no_toar:
+        out["compact_basis_form"], toar_lams = compact_basis_form(torch, riga, W, args.steps, args.block)
     if not args.no_mixed:
         out["precision_form"] = precision_form(torch, riga, W)
     if not args.no_batch:
@@ -424,6 +452,10 @@ def main():
         if iga is not None:
             out["iga_fp64"]["max_rel_err_vs_oracle"], out["iga_fp64"]["pairs_within_1e-10_of_oracle"] = \
                 oracle_check(Pi, lam_iga)
+        if toar_lams is not None:
+            for k, (Pt, lt) in toar_lams.items():
+                out["compact_basis_form"][k]["max_rel_err_vs_oracle"], \
+                    out["compact_basis_form"][k]["pairs_within_1e-10_of_oracle"] = oracle_check(Pt, lt)
         if mus is not None:
             for k, (n_ref, rel) in oracle_check_undamped(mus).items():
                 out["undamped_form"][k]["oracle_count"] = n_ref

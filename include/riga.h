@@ -95,7 +95,9 @@ typedef struct {
  *   v0      device, 2N x block column-major start block, or NULL.
  *   flags   bit 0: launch every block step eagerly instead of replaying its
  *           captured HIP graph; bit 1: check every block step on the host (the
- *           path otherwise taken only after a device-detected breakdown).
+ *           path otherwise taken only after a device-detected breakdown);
+ *           RIGA_EIGS_TOAR (bit 2): keep the Krylov basis in compact two-level
+ *           form (see riga_eigs).
  *   keep    Ritz values kept at a Krylov-Schur restart (0: nev + (m - nev)/2;
  *           at least nev, at most m - block; extended to whole clusters).    */
 typedef struct {
@@ -106,6 +108,7 @@ typedef struct {
   int flags;
   int keep;
 } riga_options;
+#define RIGA_EIGS_TOAR 4
 
 typedef struct {
   int64_t n1d;          /* 1-D functions per direction after Dirichlet          */
@@ -169,6 +172,10 @@ typedef struct {
    * three bases once.                                                         */
   double bytes[RIGA_NPHASE];
   double flops[RIGA_NPHASE];
+  double toar_drop;     /* compact basis (RIGA_EIGS_TOAR): the largest norm a
+                           restart's compression of U left out, relative to
+                           the compact basis (rounding level when the
+                           compression is exact); 0 for the full basis        */
 } riga_stats_t;
 
 /* Build the discretisation (open knot vectors of eq. KnotsX with C^0
@@ -286,6 +293,16 @@ riga_status riga_apply_op(riga_problem* h, int nvec, const double* v, double* r)
 
 /* The nev eigenpairs of the QEP nearest sigma (Alg. 2): block Krylov-Schur on
  * the shift-and-invert operator with B-orthogonal (CGS2) bases.
+ * With opt->flags & RIGA_EIGS_TOAR the basis is kept in the compact two-level
+ * form V = [U Q1; U Q2] of the second-order Arnoldi methods (SOAR, cited in
+ * Sec. 4.2.1): the lower block of the operator's image is sigma r_u + v_u
+ * (eq. BlockOperatorVector), so every upper and lower block lies in the span
+ * of one N x r orthonormal U (r = basis columns + block), and the long-vector
+ * work of a step reads U alone (one N x r array instead of three N x k ones).
+ * The inner product is then the Euclidean one of the 2N-space; the returned
+ * pairs are computed, polished and checked as above.  m + 2 block <= 254.  A
+ * case the compact form cannot run (a start block without full rank, a
+ * breakdown) is solved with the full basis instead.
  *   lam: host, 2*nev doubles (re, im) in canonical order: increasing
  *        |lam - sigma|, ties (relative 1e-9) by decreasing Im, then Re.
  *   X:   device, ndof x nev complex (interleaved re, im), column k the
@@ -366,6 +383,14 @@ riga_status riga_selftest_small_eig(int n, const double* a, double* w, double* r
  * no device.                                                                 */
 riga_status riga_selftest_schur_restart(int n, const double* a, int nkeep, int* r, double* w, double* resid,
                                         int* real_path);
+
+/* Host-only self-test of the compression of the compact (TOAR) basis at a
+ * restart: an orthonormal W (r x rp) whose range holds the columns of A (r x
+ * nc, column-major, host) by Householder QR with column pivoting.  On return
+ * W (host, r x rp) and *drop = the largest norm left outside range(W) after
+ * rp pivots relative to the largest column norm of A (rounding level when
+ * rank(A) <= rp).  Touches no device.                                        */
+riga_status riga_selftest_range_basis(int r, int nc, const double* a, int rp, double* w, double* drop);
 
 /* ---- Undamped problem: K u = mu M u with spectrum slicing --------------------
  * With C = 0 the QEP of eq. QuadEig reduces to the Hermitian definite pencil

@@ -1306,6 +1306,93 @@ struct KrylovRun {
   }
 };
 
+// Eigenpairs from the planar Ritz vectors of the wanted values in h->P
+// (N x 2 nw: real parts, then imaginary parts; nw = cyc.wanted.size()):
+// Rayleigh polish of each value (the root of u^T Q(lam) u = 0 nearest the
+// Ritz value), explicit scaled residuals, canonical order, and the normalised
+// eigenvectors written to X.  dsmall: device scratch of >= 3 nev + 2 nw + 16
+// doubles.  Returns the number of leading pairs (canonical order) whose
+// residual meets kEtaConverged.
+int finish_pairs(riga_problem* h, const riga::KsCycle& cyc, int nev, double* dsmall, double* lam, double* X,
+                 double* eta) {
+  const int64_t N = h->N();
+  const std::vector<int>& wanted = cyc.wanted;
+  const int nw = (int)wanted.size();
+    // M, C, K times the planar real and imaginary parts
+    for (int c0 = 0; c0 < 2 * nw; c0 += 8) {
+      int nc = std::min(8, 2 * nw - c0);
+      const double* x = h->P + (size_t)c0 * N;
+      riga::launch_spmv3(h->ds, N, nc, h->d_M, h->d_C, h->d_K, x, N, h->MP + (size_t)c0 * N, h->CP + (size_t)c0 * N,
+                         h->KP + (size_t)c0 * N, N, h->st);
+    }
+    const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, N / 4096));
+    riga::launch_pair_forms(N, nw, h->P, h->MP, h->CP, h->KP, N, h->d_part, nsplit, h->st);
+    std::vector<double> part((size_t)nw * nsplit * 11);
+    ck(hipMemcpyAsync(part.data(), h->d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    ck(hipStreamSynchronize(h->st));
+    std::vector<cplx> lam_rq(nw);
+    std::vector<double> uMu(nw), unorm2(nw);
+    for (int j = 0; j < nw; ++j) {
+      double f[11] = {0};
+      for (int x = 0; x < nsplit; ++x)
+        for (int t2 = 0; t2 < 11; ++t2) f[t2] += part[((size_t)j * nsplit + x) * 11 + t2];
+      const riga::PairForms pf = riga::pair_forms(f);
+      uMu[j] = pf.uMu;
+      unorm2[j] = pf.unorm2;
+      lam_rq[j] = riga::rayleigh_polish(pf, h->sigma + 1.0 / cyc.theta[wanted[j]]);
+    }
+    std::vector<double> lamd((size_t)2 * nw);
+    for (int j = 0; j < nw; ++j) { lamd[2 * j] = lam_rq[j].real(); lamd[2 * j + 1] = lam_rq[j].imag(); }
+    double* dlam = dsmall + 8;
+    ck(hipMemcpyAsync(dlam, lamd.data(), lamd.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
+    riga::launch_pair_resid(N, nw, h->P, h->MP, h->CP, h->KP, N, dlam, h->d_part, nsplit, h->st);
+    std::vector<double> rpart((size_t)nw * nsplit * 5);
+    ck(hipMemcpyAsync(rpart.data(), h->d_part, rpart.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
+    ck(hipStreamSynchronize(h->st));
+    std::vector<double> etav(nw);
+    std::vector<cplx> umax(nw);
+    for (int j = 0; j < nw; ++j) {
+      double s = 0.0, best = -1.0;
+      for (int x = 0; x < nsplit; ++x) {
+        const double* o = &rpart[((size_t)j * nsplit + x) * 5];
+        s += o[0];
+        if (o[1] > best) { best = o[1]; umax[j] = cplx(o[3], o[4]); }
+      }
+      etav[j] = riga::scaled_residual(s, lam_rq[j], h->norms, unorm2[j]);
+    }
+    std::vector<int> order = canonical_order(lam_rq, h->sigma);
+    const int nout = std::min(nev, nw);
+    // converged pairs: the leading ones in canonical order whose explicit
+    // scaled residual meets the bar (the Ritz estimate alone is not trusted)
+    int conv_out = 0;
+    for (int j = 0; j < nout; ++j) {
+      if (etav[order[j]] <= riga::detail::kEtaConverged) ++conv_out; else break;
+    }
+    for (int j = 0; j < nout; ++j) {
+      lam[2 * j] = lam_rq[order[j]].real();
+      lam[2 * j + 1] = lam_rq[order[j]].imag();
+      if (eta) eta[j] = etav[order[j]];
+    }
+    if (X) {
+      // scale u^H M u = 1 with an entry of largest modulus real positive, in output order
+      std::vector<double> sc((size_t)3 * nout);
+      for (int j = 0; j < nout; ++j) {
+        const int src = order[j];
+        const cplx ph = std::conj(umax[src]) / std::abs(umax[src]);
+        const cplx s = ph / std::sqrt(uMu[src]);
+        sc[3 * j] = s.real();
+        sc[3 * j + 1] = s.imag();
+        sc[3 * j + 2] = (double)src;
+      }
+      double* dsc = dsmall + 8;
+      double* stage = h->pinned(sc.size() + 8);
+      std::memcpy(stage, sc.data(), sc.size() * sizeof(double));
+      ck(hipMemcpyAsync(dsc, stage, sc.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
+      riga::launch_finalize(N, nw, nout, h->P, N, dsc, X, h->st);
+    }
+  return conv_out;
+}
+
 }  // namespace detail
 }  // namespace riga
 
@@ -1339,6 +1426,13 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
       h->graph_key = h->factor_key();
     }
     ensure_norms(h);
+    h->stats.toar_drop = 0.0;
+    if (opt->flags & RIGA_EIGS_TOAR) {
+      bool fallback = false;
+      const riga_status rs = eigs_toar(h, opt, nev, b, m, maxit, tol, lam, X, eta, nconv, &fallback);
+      if (!fallback) return rs;
+      h->stats.toar_drop = 0.0;
+    }
     const int ldh = m + 2 * b;
     ensure_krylov(h, ldh, b);
     ck(hipEventRecord(h->ev0, h->st));
@@ -1466,78 +1560,7 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     ck(hipStreamSynchronize(h->st));
     ck(hipMemcpyAsync(dQ, Yi.data(), Yi.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
     riga::launch_gemm_tall(N, h->Vu, N, k, dQ, nw, h->P + (size_t)nw * N, N, h->st);
-    // M, C, K times the planar real and imaginary parts
-    for (int c0 = 0; c0 < 2 * nw; c0 += 8) {
-      int nc = std::min(8, 2 * nw - c0);
-      const double* x = h->P + (size_t)c0 * N;
-      riga::launch_spmv3(h->ds, N, nc, h->d_M, h->d_C, h->d_K, x, N, h->MP + (size_t)c0 * N, h->CP + (size_t)c0 * N,
-                         h->KP + (size_t)c0 * N, N, h->st);
-    }
-    const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, N / 4096));
-    riga::launch_pair_forms(N, nw, h->P, h->MP, h->CP, h->KP, N, h->d_part, nsplit, h->st);
-    std::vector<double> part((size_t)nw * nsplit * 11);
-    ck(hipMemcpyAsync(part.data(), h->d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
-    ck(hipStreamSynchronize(h->st));
-    std::vector<cplx> lam_rq(nw);
-    std::vector<double> uMu(nw), unorm2(nw);
-    for (int j = 0; j < nw; ++j) {
-      double f[11] = {0};
-      for (int x = 0; x < nsplit; ++x)
-        for (int t2 = 0; t2 < 11; ++t2) f[t2] += part[((size_t)j * nsplit + x) * 11 + t2];
-      const riga::PairForms pf = riga::pair_forms(f);
-      uMu[j] = pf.uMu;
-      unorm2[j] = pf.unorm2;
-      lam_rq[j] = riga::rayleigh_polish(pf, h->sigma + 1.0 / cyc.theta[wanted[j]]);
-    }
-    std::vector<double> lamd((size_t)2 * nw);
-    for (int j = 0; j < nw; ++j) { lamd[2 * j] = lam_rq[j].real(); lamd[2 * j + 1] = lam_rq[j].imag(); }
-    double* dlam = h->d_small + 8;
-    ck(hipMemcpyAsync(dlam, lamd.data(), lamd.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
-    riga::launch_pair_resid(N, nw, h->P, h->MP, h->CP, h->KP, N, dlam, h->d_part, nsplit, h->st);
-    std::vector<double> rpart((size_t)nw * nsplit * 5);
-    ck(hipMemcpyAsync(rpart.data(), h->d_part, rpart.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
-    ck(hipStreamSynchronize(h->st));
-    std::vector<double> etav(nw);
-    std::vector<cplx> umax(nw);
-    for (int j = 0; j < nw; ++j) {
-      double s = 0.0, best = -1.0;
-      for (int x = 0; x < nsplit; ++x) {
-        const double* o = &rpart[((size_t)j * nsplit + x) * 5];
-        s += o[0];
-        if (o[1] > best) { best = o[1]; umax[j] = cplx(o[3], o[4]); }
-      }
-      etav[j] = riga::scaled_residual(s, lam_rq[j], h->norms, unorm2[j]);
-    }
-    std::vector<int> order = canonical_order(lam_rq, h->sigma);
-    const int nout = std::min(nev, nw);
-    // converged pairs: the leading ones in canonical order whose explicit
-    // scaled residual meets the bar (the Ritz estimate alone is not trusted)
-    int conv_out = 0;
-    for (int j = 0; j < nout; ++j) {
-      if (etav[order[j]] <= riga::detail::kEtaConverged) ++conv_out; else break;
-    }
-    for (int j = 0; j < nout; ++j) {
-      lam[2 * j] = lam_rq[order[j]].real();
-      lam[2 * j + 1] = lam_rq[order[j]].imag();
-      if (eta) eta[j] = etav[order[j]];
-    }
-    if (X) {
-      // scale u^H M u = 1 with an entry of largest modulus real positive, in output order
-      std::vector<double> sc((size_t)3 * nout);
-      for (int j = 0; j < nout; ++j) {
-        const int src = order[j];
-        const cplx ph = std::conj(umax[src]) / std::abs(umax[src]);
-        const cplx s = ph / std::sqrt(uMu[src]);
-        sc[3 * j] = s.real();
-        sc[3 * j + 1] = s.imag();
-        sc[3 * j + 2] = (double)src;
-      }
-      double* dsc = h->d_small + 8;
-      double* stage = h->pinned(sc.size() + 8);
-      std::memcpy(stage, sc.data(), sc.size() * sizeof(double));
-      ck(hipMemcpyAsync(dsc, stage, sc.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
-      riga::launch_finalize(N, nw, nout, h->P, N, dsc, X, h->st);
-    }
+    const int conv_out = finish_pairs(h, cyc, nev, h->d_small, lam, X, eta);
     ck(hipEventRecord(h->ev1, h->st));
     ck(hipStreamSynchronize(h->st));
     float ms = 0;

@@ -313,6 +313,10 @@ __global__ __launch_bounds__(256) void k_dots_final(int nout, int nblk, const do
   if (lane == 0) out[idx] = s;
 }
 
+void launch_dots_final(int nout, int nblk, const double* partial, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_dots_final, dim3((nout + 3) / 4), dim3(256), 0, st, nout, nblk, partial, out);
+}
+
 void launch_dots(int64_t n, int nc, const double* Au, const double* Al, int64_t lda,
                  int nq, const double* Xu, const double* Xl, int64_t ldx,
                  double* partial, double* out, hipStream_t st) {
@@ -999,6 +1003,7 @@ __global__ __launch_bounds__(256) void k_normalize_gemm3(
   double* Os[3] = {O0, O1, O2};
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
+    if (Is[m] == nullptr) continue;   // fewer than three pairs (uniform branch)
     double x[NQ];
 #pragma unroll
     for (int a = 0; a < NQ; ++a) x[a] = Is[m][i + a * ld];

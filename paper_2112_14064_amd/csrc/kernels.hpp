@@ -203,6 +203,9 @@ void launch_dots(int64_t n, int nc, const double* Au, const double* Al, int64_t 
                  int nq, const double* Xu, const double* Xl, int64_t ldx,
                  double* partial, double* out, hipStream_t st);
 int dots_blocks(int64_t n);
+// out[o] = sum over the nblk partial sums partial[o nblk + b] (second stage of
+// the products above, one wave per output, fixed order).
+void launch_dots_final(int nout, int nblk, const double* partial, double* out, hipStream_t st);
 // Z[:, q] -= sum_c A[:, c] h[c*nq+q] for up to three (A, Z) pairs sharing h.
 // With gpart (nq <= 4), every block also writes the sum over its rows of the
 // updated Z0^T Z0 + Z2^T Z1 (nq x nq) to gpart[block * nq * nq ...]; returns
@@ -276,9 +279,9 @@ void launch_dots_mr(int64_t n, int nc, const double* Au, const double* Al, int64
 // Device-side block normalisation fused with the new basis block (see
 // k_krylov.hip): H columns k..k+nq from the projection coefficients h1 + h2 and
 // the Cholesky factor R of the Gram matrix G (or, with gpart, of the sum of
-// gblk partial Gram matrices); Out_m = In_m R^{-1} (n x nq) for three pairs
-// sharing ld; *flag = 1 when a column was lost (breakdown).  rbuf: nq x nq
-// device scratch (used when gblk is large).
+// gblk partial Gram matrices); Out_m = In_m R^{-1} (n x nq) for up to three
+// pairs sharing ld (I1/O1 and I2/O2 may be null); *flag = 1 when a column was
+// lost (breakdown).  rbuf: nq x nq device scratch (used when gblk is large).
 void launch_normalize_gemm3(int64_t n, int nc, int nq, const double* h1, const double* h2, const double* G,
                             const double* gpart, int gblk, double* H, int ldh, int k, int* flag, double* rbuf,
                             const double* I0, double* O0, const double* I1, double* O1, const double* I2,
@@ -344,5 +347,21 @@ void launch_gemm3_b(const BatchDev& B, bool use_k, int col_add, int nq, const do
 void launch_advance_b(const BatchDev& B, int b, int m, hipStream_t st);
 void launch_gemm_tall_b(const BatchDev& B, const int* kin, const int* kout, const int64_t* qoff, const double* Q,
                         int max_kin, int max_kout, const double* In, double* Out, hipStream_t st);
+
+// --- compact (TOAR) basis (k_toar.hip) ----------------------------------------
+// Z -= U h (n x nq, h[c nq + q] on the device, c < nc) fused with
+// out[c nq + q] = U[:, c]^T Z[:, q] of the updated block: one read of U.
+// Returns the number of workgroups, or -1 (nothing launched) when
+// toar_tile_fits(nc, nq) is false.  partial: >= blocks nc nq doubles.
+bool toar_tile_fits(int nc, int nq);
+int launch_toar_update_dots(int64_t n, int nc, int nq, const double* h, const double* U, int64_t ldu, double* Z,
+                            int64_t ldz, double* partial, double* out, hipStream_t st);
+// The compact step of one block (see k_toar.hip): orthogonalise the
+// coordinates of the operator's image against the compact basis (Q1, Q2;
+// ldq rows), write H's column block k..k+nq, the new basis columns and their
+// packed copy P.  false (nothing launched) when the sizes exceed the kernel's
+// shared-memory tables (r + nq <= 264, k + nq <= 260, r + nq <= ldq).
+bool launch_toar_compact(int r, int k, int nq, double sig, const double* S, int lds, double* Q1, double* Q2, int ldq,
+                         double* H, int ldh, int* flag, double* P, hipStream_t st);
 
 }  // namespace riga

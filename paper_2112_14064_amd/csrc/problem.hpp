@@ -75,6 +75,15 @@ struct riga_problem {
   double *d_H = nullptr;          // device copy of the projected matrix (fast path)
   int* d_flag = nullptr;          // breakdown flag of the fast path
   double *P = nullptr, *MP = nullptr, *CP = nullptr, *KP = nullptr;
+  // Compact (TOAR) Krylov workspace: U and its restart copy (N x cols), the
+  // operator input [v_u | v_l] (N x 2b) and M v_l, the operator's output, the
+  // compact basis [Q1; Q2] (2 x cols x cols), the coordinates of the
+  // orthonormalised upper block (cols x 4), the packed next block (cols x 8),
+  // small device scratch, the projected matrix and the breakdown flag.
+  int64_t tw_cols = 0, tw_b = 0;
+  double *tU = nullptr, *tU2 = nullptr, *tX = nullptr, *tW = nullptr, *tRu = nullptr, *tRl = nullptr, *tTv = nullptr;
+  double *tQ = nullptr, *tS = nullptr, *tP = nullptr, *tsmall = nullptr, *tH = nullptr;
+  int* tflag = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // The Krylov loop runs on a stream of its own (fenced to the caller's stream)
   // so that its block steps can be captured as HIP graphs and replayed.
@@ -142,6 +151,7 @@ struct riga_problem {
 };
 
 namespace riga {
+struct KsCycle;
 namespace detail {
 
 // A returned eigenpair counts as converged when its scaled residual (Tisseur's
@@ -186,6 +196,20 @@ riga_status factor_all(riga_problem* h, double sigma, int64_t* bad_pivot);
 riga_status factor_gep_all(riga_problem* h, double shift, int64_t* bad_pivot, int64_t* negs);
 void ensure_norms(riga_problem* h);
 void ensure_krylov(riga_problem* h, int cols, int b);
+void ensure_post(riga_problem* h, int nev);
+// S v for a block of nb vectors (eq. BlockOperatorVector) with M v_l supplied:
+// ru = -Q(sigma)^{-1} ((sigma M + C) vu + wl), rl = sigma ru + vu; t: N x nb scratch.
+void apply_block(riga_problem* h, int nb, const double* vu, const double* wl, int64_t ld,
+                 double* ru, double* rl, double* t);
+// Eigenpairs from the planar Ritz vectors of cyc's wanted values in h->P (see api.cpp).
+int finish_pairs(riga_problem* h, const riga::KsCycle& cyc, int nev, double* dsmall, double* lam, double* X,
+                 double* eta);
+// The nev eigenpairs nearest sigma by block Krylov--Schur with the compact
+// (TOAR) basis (see toar.cpp).  Sets *fallback (and returns RIGA_OK, nothing
+// written) when the compact form cannot run the case; the caller then runs
+// the full-basis iteration.
+riga_status eigs_toar(riga_problem* h, const riga_options* opt, int nev, int b, int m, int maxit, double tol,
+                      double* lam, double* X, double* eta, int* nconv, bool* fallback);
 int small_chol(int b, const std::vector<double>& G, std::vector<double>& R, double rel);
 // Autotune the per-level sweep shapes of a factored handle (see riga_autotune).
 void autotune_sweeps(riga_problem* h, int nrhs, int reps, double* before_ms, double* after_ms);

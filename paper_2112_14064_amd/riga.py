@@ -25,6 +25,7 @@ RIGA_ERR_SCRATCH = -6
 RIGA_WARN_NOT_CONVERGED = 1
 RIGA_WARN_IR_STAGNATED = 2
 RIGA_IR_MAX = 10
+RIGA_EIGS_TOAR = 4   # riga_options.flags: compact two-level Krylov basis
 
 
 class riga_mesh(C.Structure):
@@ -54,7 +55,8 @@ PHASES = ("assemble", "factor", "fb", "mv", "vv", "restart", "ir", "post")
 class riga_stats_t(C.Structure):
     _fields_ = [("n_it", C.c_int64), ("n_fb", C.c_int64), ("n_mv", C.c_int64), ("n_vv", C.c_int64),
                 ("n_ir", C.c_int64), ("t_assemble_ms", C.c_double), ("t_factor_ms", C.c_double), ("t_eigs_ms", C.c_double),
-                ("t_host_ms", C.c_double), ("bytes", C.c_double * 8), ("flops", C.c_double * 8)]
+                ("t_host_ms", C.c_double), ("bytes", C.c_double * 8), ("flops", C.c_double * 8),
+                ("toar_drop", C.c_double)]
 
 
 EXPORTS = ["riga_create", "riga_info", "riga_assemble", "riga_export_csr", "riga_factor", "riga_factor_mixed",
@@ -63,7 +65,7 @@ EXPORTS = ["riga_create", "riga_info", "riga_assemble", "riga_export_csr", "riga
            "riga_batch_autotune",
            "riga_factor_gep", "riga_gep_slice",
            "riga_solve_q", "riga_solve_q_noalloc", "riga_apply_op", "riga_eigs", "riga_adjoint", "riga_stats", "riga_time_kernel",
-           "riga_selftest_small_eig", "riga_selftest_schur_restart", "riga_symbolic", "riga_status_str", "riga_destroy"]
+           "riga_selftest_small_eig", "riga_selftest_schur_restart", "riga_symbolic", "riga_status_str", "riga_destroy", "riga_selftest_range_basis"]
 
 _lib = None
 
@@ -101,6 +103,7 @@ def load(path: str = LIB_PATH):
                                      C.POINTER(C.c_double), C.POINTER(C.c_int)]
     lib.riga_selftest_small_eig.argtypes = [C.c_int, P, P, P]
     lib.riga_selftest_schur_restart.argtypes = [C.c_int, P, C.c_int, P, P, P, P]
+    lib.riga_selftest_range_basis.argtypes = [C.c_int, C.c_int, P, C.c_int, P, P]
     lib.riga_symbolic.argtypes = [C.POINTER(riga_mesh), P, P, P, P, P]
     lib.riga_status_str.argtypes = [C.c_int]
     lib.riga_status_str.restype = C.c_char_p
@@ -176,6 +179,20 @@ def riga_selftest_small_eig(a: np.ndarray):
     _check(lib.riga_selftest_small_eig(n, a.ctypes.data_as(C.c_void_p), w.ctypes.data_as(C.c_void_p),
                                        C.cast(C.pointer(res), C.c_void_p)), "riga_selftest_small_eig")
     return w[0::2] + 1j * w[1::2], res.value
+
+
+def riga_selftest_range_basis(a: np.ndarray, rp: int):
+    """Compression of the compact Krylov basis (host only): an orthonormal
+    basis W (r x rp) of the range of a (r x nc) by pivoted Householder QR.
+    Returns (W, relative norm left outside range(W))."""
+    lib = load()
+    a = np.asfortranarray(np.asarray(a, dtype=np.float64))
+    r, nc = a.shape
+    w = np.zeros((rp, r))   # column-major r x rp
+    drop = C.c_double(0.0)
+    _check(lib.riga_selftest_range_basis(r, nc, a.ctypes.data_as(C.c_void_p), rp, w.ctypes.data_as(C.c_void_p),
+                                         C.cast(C.pointer(drop), C.c_void_p)), "riga_selftest_range_basis")
+    return w.T.copy(), drop.value
 
 
 def riga_selftest_schur_restart(a: np.ndarray, nkeep: int):

@@ -205,3 +205,26 @@ def test_pins_catch_symbolic_without_fill():
     A = (abs(K) + abs(M)).toarray()[np.ix_(order, order)]
     nofill = (np.tril(A) != 0).sum(axis=0)
     assert not np.array_equal(nofill, cc)
+
+
+@pytest.mark.parametrize("r,nc,rank,rp,seed", [(30, 40, 12, 14, 0), (84, 124, 64, 64, 1), (20, 8, 8, 10, 2)])
+def test_compact_basis_compression(r, nc, rank, rp, seed):
+    """The restart compression of the compact Krylov basis: W has orthonormal
+    columns and its range holds every column of a matrix of rank <= rp
+    (rounding-level drop); a matrix of larger rank leaves its (rp+1)-th
+    singular value outside (within the pivoted QR's bounds)."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((r, rank)) @ rng.standard_normal((rank, nc))
+    W, drop = riga.riga_selftest_range_basis(A, rp)
+    assert W.shape == (r, rp)
+    assert np.abs(W.T @ W - np.eye(rp)).max() < 1e-14 * r
+    assert np.abs(W @ (W.T @ A) - A).max() <= 1e-13 * np.abs(A).max() * r
+    assert drop < 1e-14 * r
+    # full rank, rp below it: what is left is of the size of the next singular values
+    B = rng.standard_normal((r, nc))
+    rq = min(r, nc) - 2
+    W2, drop2 = riga.riga_selftest_range_basis(B, rq)
+    sv = np.linalg.svd(B, compute_uv=False)
+    res = np.linalg.norm(B - W2 @ (W2.T @ B), axis=0).max() / np.linalg.norm(B, axis=0).max()
+    assert drop2 > 0.0 and abs(drop2 - res) <= 1e-12
+    assert res >= 0.1 * sv[rq] / np.linalg.norm(B, axis=0).max()
