@@ -19,10 +19,11 @@ solved together) are measured last and reported beside it.
 The undamped case (C = 0: all eigenvalues of K u = mu M u in an interval by
 spectrum slicing) on the same mesh, rIGA and IGA, is reported last, and the
 headline step with the Krylov basis in compact two-level (TOAR) form beside
-the full basis.
+the full basis, and the headline mesh with a gyroscopic (skew) part in the
+damping, factored by LU.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-iga] [--no-mixed] [--no-batch]
-                       [--no-undamped] [--no-toar] [--basis full|toar]
+                       [--no-undamped] [--no-toar] [--no-gyro] [--basis full|toar]
 """
 from __future__ import annotations
 
@@ -132,6 +133,63 @@ def roofline(pr, res, block):
                 # last-level cache (MALL), so the sweeps of this workload can hit it
                 "solve_factor_mb": res["solve_factor_mb"], "mall_resident": res["solve_factor_mb"] < 256.0})
     return out
+
+
+def gyroscopic_form(torch, riga, W, steps, block):
+    """The headline mesh (rIGA and IGA) with a skew-symmetric part in the
+    damping: LU factorisation of the nonsymmetric Q(sigma) and the eigensolve,
+    timed like the headline step (assemble + factor + eigs per step)."""
+    import numpy as np
+
+    out, lams = {}, {}
+    for s in (16, 0):
+        P = W.cfg_gyro(s)
+        pr = riga.Problem(P.p, P.ne, P.hyper_every)
+        info = pr.info
+
+        def one():
+            pr.assemble(P.alpha, P.beta, gyro=P.extra["gyro"])
+            pr.factor(P.sigma)
+            return pr.eigs(P.nev, P.m, block=block, seed=0, vectors=True)
+
+        one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            lam, X, eta, nconv, st = one()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        stats = pr.stats()
+        good = int(sum(1 for e in eta[:nconv] if e <= 1e-10))
+        out["riga" if s else "iga"] = {
+            "workload": f"p={P.p}, {P.ne}x{P.ne}, " + (f"rIGA s={s}" if s else "IGA") +
+                        f", C = {P.alpha}M + {P.beta}K + G(g={P.extra['gyro']}), {P.nev} pairs nearest "
+                        f"sigma={P.sigma}, subspace {P.m}",
+            "ndof": int(info["ndof"]), "ms_per_step": ms, "eigenpairs_per_s": good * 1e3 / ms, "pairs_ok": good,
+            "status": int(st), "factor_ms": stats["t_factor_ms"], "eigs_ms": stats["t_eigs_ms"],
+            # an LU without pivoting does twice the work of the Cholesky of the same pattern
+            "factor_gflops_algorithmic": 2.0 * info["factor_flops"] / (stats["t_factor_ms"] * 1e-3) / 1e9,
+            "n_it": int(stats["n_it"]), "n_fb": int(stats["n_fb"]), "max_eta": float(max(eta)),
+            "max_abs_re_over_abs": float(np.max(np.abs(np.real(lam)) / np.abs(lam))),
+        }
+        lams["riga" if s else "iga"] = (P, lam)
+        pr.close()
+    return out, lams
+
+
+def oracle_check_gyro(lams):
+    """Eigenvalues of the gyroscopic leg against the oracle's 1-D y-mode
+    closed form: part of the CPU-baseline leg."""
+    import numpy as np
+
+    from oracle import gyro as ogyro
+
+    res = {}
+    for k, (P, lam) in lams.items():
+        ref = ogyro.gyro_closed(P.p, P.ne, P.hyper_every, P.alpha, P.beta, P.extra["gyro"][0], P.sigma, P.nev)
+        rel = np.abs(np.asarray(lam) - ref) / np.abs(ref)
+        res[k] = (float(rel.max()), int((rel <= 1e-10).sum()))
+    return res
 
 
 def compact_basis_form(torch, riga, W, steps, block):
@@ -372,6 +430,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-undamped", action="store_true")
     ap.add_argument("--no-toar", action="store_true")
+    ap.add_argument("--no-gyro", action="store_true")
     ap.add_argument("--basis", choices=("full", "toar"), default="full",
                     help="Krylov basis of the timed headline steps: the full 2N-long basis (default) or the "
                          "compact two-level form")
@@ -431,6 +490,9 @@ def main():
             "eigs": iga["eigs_ms"] / res["eigs_ms"],
             "step": iga["ms_per_step"] / res["ms_per_step"],
         }
+    gyro_lams = None
+    if not args.no_gyro:
+        out["gyroscopic_form"], gyro_lams = gyroscopic_form(torch, riga, W, min(args.steps, 3), args.block)
     toar_lams = None
     if not args.no_toar:
         out["compact_basis_form"], toar_lams = compact_basis_form(torch, riga, W, args.steps, args.block)
@@ -452,6 +514,10 @@ def main():
         if iga is not None:
             out["iga_fp64"]["max_rel_err_vs_oracle"], out["iga_fp64"]["pairs_within_1e-10_of_oracle"] = \
                 oracle_check(Pi, lam_iga)
+        if gyro_lams is not None:
+            for k, (rel, ok) in oracle_check_gyro(gyro_lams).items():
+                out["gyroscopic_form"][k]["max_rel_err_vs_oracle"] = rel
+                out["gyroscopic_form"][k]["pairs_within_1e-10_of_oracle"] = ok
         if toar_lams is not None:
             for k, (Pt, lt) in toar_lams.items():
                 out["compact_basis_form"][k]["max_rel_err_vs_oracle"], \

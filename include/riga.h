@@ -211,7 +211,26 @@ riga_status riga_symbolic(const riga_mesh* mesh, int64_t* ndof, int64_t* order, 
  * (p+1)^2-point Gauss rule).  Invalidates an existing factorization.         */
 riga_status riga_assemble(riga_problem* h, const riga_damping* damping);
 
-/* Copy one assembled matrix out in CSR form: which = 0 K, 1 M, 2 C.
+/* As riga_assemble, with a skew-symmetric (gyroscopic) part added to the
+ * damping: the model-problem remark after eq. HcurlQuadEig (Sec. 2.1) takes a
+ * skew-Hermitian damping matrix, C = -C^T, whose QEP is gyroscopic with a
+ * spectrum symmetric with respect to the imaginary axis.  Here the skew part
+ * is real, the form of a constant vector g = (gx, gy):
+ *   C = alpha M + beta K + sum_e c_e M_e + G,   G_ab = int B_a (g . grad B_b),
+ * skew-symmetric on the Dirichlet space (on the identity geometry
+ * G = gx M1 (x) S1 + gy S1 (x) M1 with s_ij = int B_i B_j', x fastest).
+ * Q(sigma) is then nonsymmetric with a positive definite symmetric part for
+ * sigma > 0: riga_factor factors it by LU without pivoting on the same tree
+ * (two triangles per front, twice the factor storage), and riga_eigs polishes
+ * each eigenvalue as the root of u^H Q(lam) u = 0 (the pencil is not
+ * complex-symmetric).  gx = gy = 0 is riga_assemble.  Not with
+ * riga_factor_mixed or riga_adjoint (RIGA_ERR_INVALID_ARG); a forest's
+ * problems cannot take it.  gx, gy finite.                                   */
+riga_status riga_assemble_gyroscopic(riga_problem* h, const riga_damping* damping, double gx, double gy);
+
+/* Copy one assembled matrix out in CSR form: which = 0 K, 1 M, 2 C, 3 C^T
+ * (values of the transpose on the same pattern; only after
+ * riga_assemble_gyroscopic with a nonzero g, else RIGA_ERR_STATE).
  *   rowptr: host, ndof+1 int64;  col: host, nnz int32;  val: device, nnz
  *   doubles.  Rows are dofs, columns ascend within a row.  Any of the three
  *   pointers may be NULL to skip it.                                         */

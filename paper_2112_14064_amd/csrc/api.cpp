@@ -170,7 +170,7 @@ void solve_levels(riga_problem* h, int nrhs, const double* b, int64_t ldb, doubl
 void apply_block(riga_problem* h, int nb, const double* vu, const double* wl, int64_t ld,
                  double* ru, double* rl, double* t) {
   const int64_t N = h->N();
-  if (h->c_elem == nullptr)   // sigma M + C = (sigma + alpha) M + beta K: sum factorisation
+  if (h->c_elem == nullptr && !h->gyro)   // sigma M + C = (sigma + alpha) M + beta K: sum factorisation
     riga::launch_tensor_mk(h->ds, h->d_M1, h->d_K1, nb, h->sigma + h->alpha, h->beta, vu, ld, t, N, wl, ld, 1.0,
                            h->st);
   else
@@ -179,13 +179,16 @@ void apply_block(riga_problem* h, int nb, const double* vu, const double* wl, in
   solve_levels(h, nb, t, N, ru, N, rl, vu, ld, h->sigma);
 }
 
-// ||K||_1, ||C||_1, ||M||_1 (largest absolute row sums): one launch, one copy.
+// ||K||_1, ||C||_1, ||M||_1 (largest absolute column sums): one launch, one copy.
 void ensure_norms(riga_problem* h) {
   if (h->norms[0] >= 0) return;
   const int rows = 1024;
   const int nblk = (int)((h->N() + rows - 1) / rows);
   double* part = h->d_part;   // 512 * 400 * 4 doubles: room for 3 per block up to 280M rows
-  riga::launch_rowabs3(nullptr, nblk, h->N(), rows, h->ds.rowptr, h->d_K, h->d_C, h->d_M, part, h->st);
+  // largest absolute column sums: the row sums of the symmetric K and M, and
+  // of C^T when the damping has a skew part
+  riga::launch_rowabs3(nullptr, nblk, h->N(), rows, h->ds.rowptr, h->d_K, h->gyro ? h->d_Ct : h->d_C, h->d_M, part,
+                       h->st);
   std::vector<double> hp((size_t)nblk * 3);
   ck(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
   ck(hipStreamSynchronize(h->st));
@@ -297,6 +300,8 @@ void setup_device(riga_problem* h) {
     h->d_tabK = h->dalloc<double>((size_t)S.ne * np * np);
     h->d_M1 = h->dalloc<double>((size_t)S.n * (2 * S.p + 1));
     h->d_K1 = h->dalloc<double>((size_t)S.n * (2 * S.p + 1));
+    h->d_tabS = h->dalloc<double>((size_t)S.ne * np * np);
+    h->d_S1 = h->dalloc<double>((size_t)S.n * (2 * S.p + 1));
     h->d_K = h->dalloc<double>(P.nnz); h->d_M = h->dalloc<double>(P.nnz); h->d_C = h->dalloc<double>(P.nnz);
     h->d_A = h->dalloc<double>(P.nnz);
     h->d_L = h->dalloc<double>(P.lsize); h->d_U = h->dalloc<double>(P.usize);
@@ -445,17 +450,34 @@ riga_status riga_symbolic(const riga_mesh* mesh, int64_t* ndof, int64_t* order, 
   });
 }
 
-riga_status riga_assemble(riga_problem* h, const riga_damping* damping) {
-  if (!h || !damping) return RIGA_ERR_INVALID_ARG;
+namespace {
+
+riga_status assemble_impl(riga_problem* h, const riga_damping* damping, double gx, double gy) {
+  if (!h || !damping || !std::isfinite(gx) || !std::isfinite(gy)) return RIGA_ERR_INVALID_ARG;
+  if ((gx != 0.0 || gy != 0.0) && !h->node_inst.empty()) return RIGA_ERR_INVALID_ARG;
   return run([&]() -> riga_status {
     ck(hipSetDevice(h->device));
+    const bool gyro = gx != 0.0 || gy != 0.0;
+    if (gyro && h->d_Ct == nullptr) {
+      const riga::Plan& P = h->plan;
+      h->d_Ct = h->dalloc<double>(P.nnz);
+      h->d_LR = h->dalloc<double>(P.lsize);
+      h->d_UR = h->dalloc<double>(P.usize);
+      h->d_TR = h->dalloc<double>(P.lsize);
+      int64_t dblocks = 0;
+      for (size_t v = 0; v < P.nf.size(); ++v) dblocks += (P.no[v] + 63) / 64;
+      h->d_DR = h->dalloc<double>((size_t)dblocks * 4096);
+    }
     ck(hipEventRecord(h->ev0, h->st));
-    riga::launch_bspline_tables(h->ds, h->d_gx, h->d_gw, h->d_tabM, h->d_tabK, h->st);
+    riga::launch_bspline_tables(h->ds, h->d_gx, h->d_gw, h->d_tabM, h->d_tabK, gyro ? h->d_tabS : nullptr, h->st);
     riga::launch_band_1d(h->ds, h->d_tabM, h->d_tabK, h->d_M1, h->d_K1, h->st);
+    if (gyro) riga::launch_band_skew(h->ds, h->d_tabS, h->d_S1, h->st);
     riga::launch_assemble(h->ds, h->d_tabM, h->d_M1, h->d_K1, damping->alpha, damping->beta, damping->c_elem,
-                          h->d_K, h->d_M, h->d_C, h->N(), h->st);
+                          h->d_K, h->d_M, h->d_C, h->N(), h->st, gyro ? h->d_S1 : nullptr, gx, gy,
+                          gyro ? h->d_Ct : nullptr);
     ck(hipGetLastError());
     ck(hipEventRecord(h->ev1, h->st));
+    h->gyro = gyro; h->gx = gx; h->gy = gy;
     h->alpha = damping->alpha; h->beta = damping->beta; h->c_elem = damping->c_elem;
     h->clear_graphs();   // captured block steps hold the old operator coefficients
     h->assembled = true;
@@ -469,9 +491,20 @@ riga_status riga_assemble(riga_problem* h, const riga_damping* damping) {
   });
 }
 
+}  // namespace
+
+riga_status riga_assemble(riga_problem* h, const riga_damping* damping) {
+  return assemble_impl(h, damping, 0.0, 0.0);
+}
+
+riga_status riga_assemble_gyroscopic(riga_problem* h, const riga_damping* damping, double gx, double gy) {
+  return assemble_impl(h, damping, gx, gy);
+}
+
 riga_status riga_export_csr(riga_problem* h, int which, int64_t* rowptr, int32_t* col, double* val) {
-  if (!h || which < 0 || which > 2) return RIGA_ERR_INVALID_ARG;
+  if (!h || which < 0 || which > 3) return RIGA_ERR_INVALID_ARG;
   if (val && !h->assembled) return RIGA_ERR_STATE;
+  if (val && which == 3 && !h->gyro) return RIGA_ERR_STATE;
   return run([&]() -> riga_status {
     const riga::Plan& P = h->plan;
     const riga::Space1D& S = P.sp;
@@ -485,7 +518,7 @@ riga_status riga_export_csr(riga_problem* h, int which, int64_t* rowptr, int32_t
             for (int ii = S.lo[i]; ii <= S.hi[i]; ++ii) col[k++] = jj * n + ii;
     }
     if (val) {
-      const double* src = which == 0 ? h->d_K : which == 1 ? h->d_M : h->d_C;
+      const double* src = which == 0 ? h->d_K : which == 1 ? h->d_M : which == 2 ? h->d_C : h->d_Ct;
       ck(hipMemcpyAsync(val, src, P.nnz * sizeof(double), hipMemcpyDeviceToDevice, h->st));
     }
     return RIGA_OK;
@@ -503,6 +536,13 @@ void factor_level(riga_problem* h, int lv, double s2, double s1) {
   const riga::Plan& P = h->plan;
   int a = P.level_off[lv], c = P.level_off[lv + 1] - a;
   riga::DevTree t = h->dt;
+  if (h->gyro && !h->gep) {   // nonsymmetric Q: LU fronts (FP64)
+    riga::launch_front_factor_lu(h->ds, t, h->d_level_nodes + a, c, h->lvl_max_no[lv], h->lvl_max_nf[lv],
+                                 h->lvl_max_cnb[lv], h->lvl_max_kids[lv], s2, s1, h->d_K, h->d_M, h->d_C, h->d_Ct,
+                                 h->d_L, h->d_U, h->d_T, h->d_D, h->d_LR, h->d_UR, h->d_TR, h->d_DR, h->d_Lp, h->d_Tp,
+                                 h->d_status, h->st);
+    return;
+  }
   if (h->mixed) t.prec = h->d_prec;
   if (h->level_f32(lv))
     riga::launch_front_factor(h->ds, t, h->d_level_nodes + a, c, h->lvl_max_no[lv], h->lvl_max_nf[lv],
@@ -526,7 +566,7 @@ riga_status factor_all(riga_problem* h, double sigma, int64_t* bad_pivot) {
   riga::launch_combine3(P.nnz, sigma, h->d_M, 1.0, h->d_C, 0.0, h->d_K, h->d_A, h->st);
   // (a forest combines its per-problem shifts itself and converts then; without
   // an element damping field the operator uses the sum-factorised product)
-  if (h->node_inst.empty() && h->c_elem != nullptr)
+  if (h->node_inst.empty() && (h->c_elem != nullptr || h->gyro))
     riga::launch_csr_to_ell(h->d_slabs, h->nslab, h->ds.rowptr, h->d_A, h->d_Aell, h->st);
   if (h->mixed) riga::launch_combine3(P.nnz, sigma * sigma, h->d_M, sigma, h->d_C, 1.0, h->d_K, h->d_Q, h->st);
   ck(hipGetLastError());
@@ -733,6 +773,7 @@ riga_status riga_factor_mixed(riga_problem* h, double sigma, int fp64_levels, in
       ir_sweeps > RIGA_IR_MAX || !(ir_tol >= 0.0))
     return RIGA_ERR_INVALID_ARG;
   if (!h->assembled) return RIGA_ERR_STATE;
+  if (h->gyro) return RIGA_ERR_INVALID_ARG;   // LU fronts are FP64 only
   return run([&]() -> riga_status {
     ck(hipSetDevice(h->device));
     h->clear_graphs();
@@ -1011,6 +1052,7 @@ riga_status riga_adjoint(riga_problem* h, int nev, const double* lam, const doub
                          double* grad_c) {
   if (!h || nev < 1 || !lam || !X || !dL_dlam || !grad_c) return RIGA_ERR_INVALID_ARG;
   if (!h->assembled) return RIGA_ERR_STATE;
+  if (h->gyro) return RIGA_ERR_INVALID_ARG;   // the formula needs the complex-symmetric pencil
   return run([&]() -> riga_status {
     ck(hipSetDevice(h->device));
     const int64_t N = h->N();
@@ -1330,15 +1372,32 @@ int finish_pairs(riga_problem* h, const riga::KsCycle& cyc, int nev, double* dsm
     std::vector<double> part((size_t)nw * nsplit * 11);
     ck(hipMemcpyAsync(part.data(), h->d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
     ck(hipStreamSynchronize(h->st));
+    // with a skew part in C the pencil is not complex-symmetric: the polish
+    // takes the root of u^H Q(lam) u = 0 instead, which needs b^T C a besides
+    std::vector<double> cross;
+    if (h->gyro) {
+      riga::launch_cross_form(N, nw, h->P, h->CP, N, h->d_part + (size_t)nw * nsplit * 11, nsplit, h->st);
+      cross.resize((size_t)nw * nsplit);
+      ck(hipMemcpyAsync(cross.data(), h->d_part + (size_t)nw * nsplit * 11, cross.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, h->st));
+      ck(hipStreamSynchronize(h->st));
+    }
     std::vector<cplx> lam_rq(nw);
     std::vector<double> uMu(nw), unorm2(nw);
     for (int j = 0; j < nw; ++j) {
       double f[11] = {0};
       for (int x = 0; x < nsplit; ++x)
         for (int t2 = 0; t2 < 11; ++t2) f[t2] += part[((size_t)j * nsplit + x) * 11 + t2];
-      const riga::PairForms pf = riga::pair_forms(f);
+      riga::PairForms pf = riga::pair_forms(f);
       uMu[j] = pf.uMu;
       unorm2[j] = pf.unorm2;
+      if (h->gyro) {
+        double g = 0.0;
+        for (int x = 0; x < nsplit; ++x) g += cross[(size_t)j * nsplit + x];
+        pf.qm = cplx(f[0] + f[1], 0.0);          // u^H M u
+        pf.qc = cplx(f[3] + f[4], f[5] - g);     // u^H C u
+        pf.qk = cplx(f[6] + f[7], 0.0);          // u^H K u
+      }
       lam_rq[j] = riga::rayleigh_polish(pf, h->sigma + 1.0 / cyc.theta[wanted[j]]);
     }
     std::vector<double> lamd((size_t)2 * nw);

@@ -39,14 +39,16 @@ __device__ inline void basis_funs(int k, double u, int q, const int* t, double* 
 }
 
 // Tables of element e of one 1-D space.
+// tabS (may be null): the element integrals of B_a dB_b/dx (the skew form of
+// a gyroscopic damping).
 __device__ inline void element_tables(int e, int p, int ne, const int* __restrict__ knots,
                                       const int* __restrict__ first, const double* __restrict__ gx,
                                       const double* __restrict__ gw, double* __restrict__ tabM,
-                                      double* __restrict__ tabK) {
+                                      double* __restrict__ tabK, double* __restrict__ tabS = nullptr) {
   const int np = p + 1;
   const int k = first[e] + p;  // knot span of the element (knot indices are in element units)
-  double m[(MAXP + 1) * (MAXP + 1)], kk[(MAXP + 1) * (MAXP + 1)];
-  for (int a = 0; a < np * np; ++a) { m[a] = 0.0; kk[a] = 0.0; }
+  double m[(MAXP + 1) * (MAXP + 1)], kk[(MAXP + 1) * (MAXP + 1)], sk[(MAXP + 1) * (MAXP + 1)];
+  for (int a = 0; a < np * np; ++a) { m[a] = 0.0; kk[a] = 0.0; sk[a] = 0.0; }
   for (int q = 0; q < np; ++q) {
     double u = (double)e + 0.5 * (gx[q] + 1.0);
     double w = 0.5 * gw[q];
@@ -68,22 +70,24 @@ __device__ inline void element_tables(int e, int p, int ne, const int* __restric
       for (int b = 0; b < np; ++b) {
         m[a * np + b] += w * N[a] * N[b];
         kk[a * np + b] += w * D[a] * D[b];
+        sk[a * np + b] += w * N[a] * D[b];
       }
   }
-  // u = ne * x: dx = du / ne and d/dx = ne d/du
+  // u = ne * x: dx = du / ne and d/dx = ne d/du (B dB/dx dx = B dB/du du)
   const double h = 1.0 / (double)ne;
   for (int a = 0; a < np * np; ++a) {
     tabM[(int64_t)e * np * np + a] = m[a] * h;
     tabK[(int64_t)e * np * np + a] = kk[a] * (double)ne;
+    if (tabS != nullptr) tabS[(int64_t)e * np * np + a] = sk[a];
   }
 }
 
 
 __global__ void k_bspline_tables(int p, int ne, const int* __restrict__ knots, const int* __restrict__ first,
                                  const double* __restrict__ gx, const double* __restrict__ gw,
-                                 double* __restrict__ tabM, double* __restrict__ tabK) {
+                                 double* __restrict__ tabM, double* __restrict__ tabK, double* __restrict__ tabS) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < ne) element_tables(e, p, ne, knots, first, gx, gw, tabM, tabK);
+  if (e < ne) element_tables(e, p, ne, knots, first, gx, gw, tabM, tabK, tabS);
 }
 
 // Every problem of a forest: problem blockIdx.y, its tables at tabM/tabK +
@@ -98,11 +102,11 @@ __global__ void k_bspline_tables_b(const DevSpace* __restrict__ spaces, const in
 }
 
 void launch_bspline_tables(const DevSpace& s, const double* gx, const double* gw,
-                           double* tabM, double* tabK, hipStream_t st) {
+                           double* tabM, double* tabK, double* tabS, hipStream_t st) {
   int threads = 64;
   int blocks = (s.ne + threads - 1) / threads;
   hipLaunchKernelGGL(k_bspline_tables, dim3(blocks), dim3(threads), 0, st,
-                     s.p, s.ne, s.knots, s.first, gx, gw, tabM, tabK);
+                     s.p, s.ne, s.knots, s.first, gx, gw, tabM, tabK, tabS);
 }
 
 constexpr int ASM_THREADS = 256;
@@ -113,10 +117,15 @@ constexpr int ASM_TMAX = (MAXP + 1) * (2 * MAXP + 1);   // T[ey][ii] entries per
 // Row r (local to the space, uniform in the wave) of K, M, C from the bands
 // M1, K1 (row i at i (2p + 1), column ii at + ii - i + p); T: ASM_TMAX doubles
 // of this wave's shared memory.
+// With S1 (the band of s_ij = int B_i B_j', null otherwise) C gains the skew
+// gyroscopic part g = gx S1[i][ii] M1[j][jj] + gy M1[i][ii] S1[j][jj] and Cto
+// receives the transpose's values on the same pattern (C^T = sym - g).
 __device__ inline void assemble_row(const DevSpace& s, int64_t r, const double* __restrict__ tabM,
                                     const double* __restrict__ M1, const double* __restrict__ K1, double alpha,
                                     double beta, const double* __restrict__ c_elem, double* __restrict__ Ko,
-                                    double* __restrict__ Mo, double* __restrict__ Co, double* T, int lane) {
+                                    double* __restrict__ Mo, double* __restrict__ Co, double* T, int lane,
+                                    const double* __restrict__ S1 = nullptr, double gxs = 0.0, double gys = 0.0,
+                                    double* __restrict__ Cto = nullptr) {
   const int p = s.p, n = s.n, ne = s.ne, w = 2 * p + 1, np = p + 1;
   const int i = (int)(r % n), j = (int)(r / n);
   const int lox = s.lo[i], wx = s.hi[i] - lox + 1, loy = s.lo[j];
@@ -126,6 +135,8 @@ __device__ inline void assemble_row(const DevSpace& s, int64_t r, const double* 
   const double* kxr = K1 + (int64_t)i * w - i + p;
   const double* myr = M1 + (int64_t)j * w - j + p;
   const double* kyr = K1 + (int64_t)j * w - j + p;
+  const double* sxr = S1 ? S1 + (int64_t)i * w - i + p : nullptr;
+  const double* syr = S1 ? S1 + (int64_t)j * w - j + p : nullptr;
   const int sy0 = s.sup0[j], sy1 = s.sup1[j];
   if (c_elem != nullptr) {
     // T[ey - sy0][ii - lox] over the elements ey of j's support and the
@@ -162,7 +173,13 @@ __device__ inline void assemble_row(const DevSpace& s, int64_t r, const double* 
     }
     Ko[k0 + o] = kval;
     Mo[k0 + o] = mval;
-    Co[k0 + o] = cval;
+    if (S1 != nullptr) {
+      const double g = gxs * sxr[ii] * my + gys * mx * syr[jj];
+      Co[k0 + o] = cval + g;
+      Cto[k0 + o] = cval - g;
+    } else {
+      Co[k0 + o] = cval;
+    }
   }
 }
 
@@ -170,14 +187,16 @@ __global__ __launch_bounds__(ASM_THREADS) void k_assemble(DevSpace s, int64_t nd
                                                           const double* __restrict__ M1, const double* __restrict__ K1,
                                                           double alpha, double beta,
                                                           const double* __restrict__ c_elem, double* __restrict__ Ko,
-                                                          double* __restrict__ Mo, double* __restrict__ Co) {
+                                                          double* __restrict__ Mo, double* __restrict__ Co,
+                                                          const double* __restrict__ S1, double gxs, double gys,
+                                                          double* __restrict__ Cto) {
   __shared__ double T[ASM_WAVES][ASM_TMAX];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t r0 = ((int64_t)blockIdx.x * ASM_WAVES + wave) * ASM_ROWS_PER_WAVE;
   for (int q = 0; q < ASM_ROWS_PER_WAVE; ++q) {
     const int64_t r = r0 + q;
     if (r >= ndof) break;
-    assemble_row(s, r, tabM, M1, K1, alpha, beta, c_elem, Ko, Mo, Co, T[wave], lane);
+    assemble_row(s, r, tabM, M1, K1, alpha, beta, c_elem, Ko, Mo, Co, T[wave], lane, S1, gxs, gys, Cto);
   }
 }
 
@@ -273,12 +292,35 @@ void launch_band_1d_b(const DevSpace* spaces, int n, int max_w, const int64_t* t
                      M1, K1);
 }
 
+// Band of the 1-D skew matrix s_ij = int B_i B_j' (same layout as M1, K1).
+__global__ void k_band_skew(DevSpace s, const double* __restrict__ tabS, double* __restrict__ S1) {
+  const int p = s.p, np = p + 1, w = 2 * p + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= s.n * w) return;
+  const int i = t / w, ii = i - p + t % w;
+  double v = 0.0;
+  if (ii >= s.lo[i] && ii <= s.hi[i]) {
+    const int ex0 = max(s.sup0[i], s.sup0[ii]), ex1 = min(s.sup1[i], s.sup1[ii]);
+    for (int ex = ex0; ex < ex1; ++ex) {
+      const int la = i + 1 - s.first[ex], lb = ii + 1 - s.first[ex];
+      v += tabS[(int64_t)ex * np * np + la * np + lb];
+    }
+  }
+  S1[t] = v;
+}
+
+void launch_band_skew(const DevSpace& s, const double* tabS, double* S1, hipStream_t st) {
+  const int total = s.n * (2 * s.p + 1);
+  hipLaunchKernelGGL(k_band_skew, dim3((total + 255) / 256), dim3(256), 0, st, s, tabS, S1);
+}
+
 void launch_assemble(const DevSpace& s, const double* tabM, const double* M1, const double* K1,
                      double alpha, double beta, const double* c_elem,
-                     double* K, double* M, double* C, int64_t ndof, hipStream_t st) {
+                     double* K, double* M, double* C, int64_t ndof, hipStream_t st,
+                     const double* S1, double gx, double gy, double* Ct) {
   const int64_t rows = (int64_t)ASM_WAVES * ASM_ROWS_PER_WAVE;
   const int64_t blocks = (ndof + rows - 1) / rows;
   hipLaunchKernelGGL(k_assemble, dim3((unsigned)blocks), dim3(ASM_THREADS), 0, st, s, ndof, tabM, M1, K1, alpha, beta,
-                     c_elem, K, M, C);
+                     c_elem, K, M, C, S1, gx, gy, Ct);
 }
 }  // namespace riga

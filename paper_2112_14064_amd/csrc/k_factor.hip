@@ -599,6 +599,302 @@ __global__ __launch_bounds__(FT) void k_panel_update(DevTree t, const int* __res
         if (cp[ti][tj][e] != nullptr) *cp[ti][tj][e] = c.a[ti][tj][e];
 }
 
+// ---------------------------------------------------------------------------------
+// Nonsymmetric fronts (a damping matrix with a skew part makes Q(sigma)
+// nonsymmetric; its symmetric part sigma^2 M + sigma C_sym + K stays positive
+// definite, so Gaussian elimination without pivoting has positive pivots).
+// A front is kept as two lower triangles at the same offsets: the front of A
+// (Lbuf / Ubuf) and the front of A^T (Rbuf / URbuf).  The factorisation is
+// A = L Ut^T with L and Ut lower triangular sharing the diagonal sqrt(a_cc):
+// per pivot c,  d = sqrt(a_cc),  l_rc = a_rc / d,  ut_rc = a_cr / d,  and the
+// Schur complement a_rj -= l_rc ut_jc in both triangles (in the front of A^T:
+// a_jr -= ut_rc l_jc).  Every kernel of the Cholesky path then runs on each
+// side with the other side's panel as its second operand: the forward sweep
+// uses F of L, the backward sweep F of Ut.
+
+// Inverse of the lower block S (64 x 64 in LDS, reciprocal diagonal rd) into
+// Dm, blocked by 16 as in k_potrf_diag (diagonal blocks by forward
+// substitution, one wave each; the blocks below, block column by block
+// column).  Called by every thread; Dm must be zero on entry.
+template <class E>
+__device__ __forceinline__ void lower_inverse(E (*S)[LDT], const E* rd, E (*Dm)[LDT], E (*Tx)[16][17], int lane,
+                                              int wave) {
+  if (lane < 16) {
+    const int base = 16 * wave, c = lane;
+    E dc[16];
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+      E sum = E(0);
+#pragma unroll
+      for (int k = 0; k < rr; ++k) sum += S[base + rr][base + k] * dc[k];
+      const E ri = rd[base + rr];
+      dc[rr] = (rr < c) ? E(0) : (rr == c ? ri : -sum * ri);
+      Dm[base + rr][base + c] = dc[rr];
+    }
+  }
+  __syncthreads();
+  if (wave < 3) {
+    const int j = wave, c = lane & 15, rg = lane >> 4;
+    for (int i = j + 1; i < 4; ++i) {
+      E tv[4] = {E(0), E(0), E(0), E(0)};
+      for (int k = 16 * j; k < 16 * i; ++k) {
+        const E dk = Dm[k][16 * j + c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) tv[u] += S[16 * i + 4 * rg + u][k] * dk;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) Tx[j][4 * rg + u][c] = tv[u];
+      wave_sync();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = 4 * rg + u;
+        E s = E(0);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) s += Dm[16 * i + r][16 * i + q] * Tx[j][q][c];
+        Dm[16 * i + r][16 * j + c] = -s;
+      }
+      wave_sync();
+    }
+  }
+  __syncthreads();
+}
+
+// LU of the diagonal block [k0, k0 + w): L_kk into Lfac, Ut_kk into Rfac,
+// their inverses stored transposed at DLbuf / DUbuf (layout of k_potrf_diag).
+// A pivot that is not positive (or NaN) is recorded in *status (the front's
+// dof, first one wins) and replaced by 1 so that the kernel completes.
+template <class E>
+__global__ __launch_bounds__(FT) void k_getrf_diag(DevTree t, const int* __restrict__ level_nodes, int k0,
+                                                   const E* __restrict__ Lbuf, const E* __restrict__ Rbuf,
+                                                   E* __restrict__ Lfac, E* __restrict__ Rfac,
+                                                   E* __restrict__ DLbuf, E* __restrict__ DUbuf,
+                                                   int64_t* __restrict__ status) {
+  const int v = level_nodes[blockIdx.x];
+  const int nf = t.nf[v], no = t.no[v];
+  if (no <= k0) return;
+  const int w = min(TB, no - k0);
+  const E* LA = Lbuf + t.loff[v];
+  const E* RA = Rbuf + t.loff[v];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ E SL[TB][LDT];
+  __shared__ E SR[TB][LDT];
+  __shared__ E Dm[TB][LDT];
+  __shared__ E Tx[3][16][17];
+  __shared__ E rd[TB];
+  {
+    constexpr int U = TB * TB / FT;
+    E xl[U], xr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = tid + u * FT, r = idx % TB, c = idx / TB;
+      const bool in = c <= r && r < w;
+      const int64_t o = in ? (int64_t)(k0 + c) * nf + k0 + r : (int64_t)k0 * nf + k0;
+      xl[u] = LA[o];
+      xr[u] = RA[o];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = tid + u * FT, r = idx % TB, c = idx / TB;
+      const bool in = c <= r && r < w;
+      const E pad = (c == r && r >= w) ? E(1) : E(0);
+      SL[r][c] = in ? xl[u] : pad;
+      SR[r][c] = in ? xr[u] : pad;
+      Dm[r][c] = E(0);
+    }
+  }
+  __syncthreads();
+  for (int c0 = 0; c0 < TB; c0 += 16) {
+    if (wave == 0) {
+      const int r = lane;
+      E rl[16], rr_[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        rl[j] = SL[r][c0 + j];
+        rr_[j] = SR[r][c0 + j];
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const int cc = c0 + c;
+        E piv = lane_value(rl[c], cc);
+        if (!(piv > E(0))) {
+          if (r == cc && cc < w)
+            atomicCAS((unsigned long long*)status, (unsigned long long)(-1ll),
+                      (unsigned long long)t.fdofs[t.foff[v] + k0 + cc]);
+          piv = E(1);
+        }
+        const E inv = rsqrt_refined(piv);
+        const E d = piv * inv;
+        if (r == cc) rd[cc] = inv;
+        const E l = rl[c] * inv, u = rr_[c] * inv;   // l_r,cc and ut_r,cc (rows below the pivot)
+        rl[c] = (r == cc) ? d : l;
+        rr_[c] = (r == cc) ? d : u;
+        if (r >= cc) {
+          SL[r][cc] = rl[c];
+          SR[r][cc] = rr_[c];
+        }
+        wave_sync();
+#pragma unroll
+        for (int j = c + 1; j < 16; ++j) {
+          rl[j] -= l * SR[c0 + j][cc];
+          rr_[j] -= u * SL[c0 + j][cc];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (r >= c0 + j) {
+          SL[r][c0 + j] = rl[j];
+          SR[r][c0 + j] = rr_[j];
+        }
+    }
+    __syncthreads();
+    const int n = TB - c0 - 16;
+    for (int idx = tid; idx < n * n; idx += FT) {
+      const int i = idx / n, j = idx % n;
+      if (j <= i) {
+        const int ri = c0 + 16 + i, rj = c0 + 16 + j;
+        E a = SL[ri][rj], b = SR[ri][rj];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          a -= SL[ri][c0 + c] * SR[rj][c0 + c];
+          b -= SR[ri][c0 + c] * SL[rj][c0 + c];
+        }
+        SL[ri][rj] = a;
+        SR[ri][rj] = b;
+      }
+    }
+    __syncthreads();
+  }
+  E* Lf = Lfac + t.loff[v];
+  E* Rf = Rfac + t.loff[v];
+  for (int idx = tid; idx < TB * TB; idx += FT) {
+    const int r = idx % TB, c = idx / TB;
+    if (r < w && c <= r) {
+      Lf[(int64_t)(k0 + c) * nf + k0 + r] = SL[r][c];
+      Rf[(int64_t)(k0 + c) * nf + k0 + r] = SR[r][c];
+    }
+  }
+  const int64_t dblk = ((int64_t)t.doff[v] + k0 / TB) * (TB * TB);
+  lower_inverse<E>(SL, rd, Dm, Tx, lane, wave);
+  for (int idx = tid; idx < TB * TB; idx += FT) {
+    const int c = idx / TB, r = idx % TB;
+    DLbuf[dblk + idx] = (r < w && c < w) ? Dm[r][c] : E(0);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < TB * TB; idx += FT) Dm[idx / TB][idx % TB] = E(0);
+  __syncthreads();
+  lower_inverse<E>(SR, rd, Dm, Tx, lane, wave);
+  for (int idx = tid; idx < TB * TB; idx += FT) {
+    const int c = idx / TB, r = idx % TB;
+    DUbuf[dblk + idx] = (r < w && c < w) ? Dm[r][c] : E(0);
+  }
+}
+
+// Panel rows and trailing updates of both triangles below the panel
+// [k0, k0 + w), one workgroup per tile pair (I, J), J <= I (as
+// k_panel_update): X = A_panel D_U^T (rows of L), Y = At_panel D_L^T (rows of
+// Ut), C^A_IJ -= X_I Y_J^T on the front of A and C^At_IJ -= Y_I X_J^T on the
+// front of A^T; the diagonal pair writes X_I and Y_I as factor rows.
+template <class E>
+__global__ __launch_bounds__(FT) void k_panel_update_lu(DevTree t, const int* __restrict__ level_nodes, int k0,
+                                                        E* __restrict__ Lbuf, E* __restrict__ Ubuf,
+                                                        E* __restrict__ Rbuf, E* __restrict__ URbuf,
+                                                        E* __restrict__ Lfac, E* __restrict__ Rfac,
+                                                        const E* __restrict__ DLbuf, const E* __restrict__ DUbuf) {
+  typedef Tile64<E, 4> TL;
+  const int v = level_nodes[blockIdx.x];
+  const Front<E> FA = front_of(t, v, Lbuf, Ubuf);
+  const Front<E> FT_ = front_of(t, v, Rbuf, URbuf);
+  if (FA.no <= k0) return;
+  const int w = min(TB, FA.no - k0);
+  const int s0 = k0 + w;
+  const int pidx = blockIdx.y;
+  int I = (int)((sqrt(8.0 * pidx + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= pidx) ++I;
+  while (I * (I + 1) / 2 > pidx) --I;
+  const int J = pidx - I * (I + 1) / 2;
+  const int rI = s0 + TB * I, rJ = s0 + TB * J;
+  if (rI >= FA.nf) return;
+  const int nf = FA.nf;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ E Xa[TB * LDT];   // A operand (row panel of one side)
+  __shared__ E Xb[TB * LDT];   // B operand (transposed row panel of the other side)
+  const int64_t dblk = ((int64_t)t.doff[v] + k0 / TB) * (TB * TB);
+  const E* DtL = DLbuf + dblk;
+  const E* DtU = DUbuf + dblk;
+  E* Lf = Lfac + t.loff[v];
+  E* Rf = Rfac + t.loff[v];
+  // the C tiles' current values of both sides, loaded before the products
+  typename TL::Acc ca, ct;
+  E* pa[TL::TI][TL::TJ][4];
+  E* pt[TL::TI][TL::TJ][4];
+#pragma unroll
+  for (int ti = 0; ti < TL::TI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TL::TJ; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = rI + TL::row(lane, wave, ti, e), cc = rJ + TL::col(lane, wave, tj);
+        const bool in = r < nf && cc < nf && r >= cc;
+        pa[ti][tj][e] = in ? FA.at(r, cc) : nullptr;
+        pt[ti][tj][e] = in ? FT_.at(r, cc) : nullptr;
+        ca.a[ti][tj][e] = *(in ? pa[ti][tj][e] : FA.at(rI, rJ));
+        ct.a[ti][tj][e] = *(in ? pt[ti][tj][e] : FT_.at(rI, rJ));
+      }
+  typename TL::Acc xi, yi, xj, yj;
+  TL::zero(xi);
+  TL::zero(yi);
+  TL::mma_global(FA.L + (int64_t)k0 * nf + rI, nf, nf - rI, DtU, TB, w, xi, lane, wave);
+  TL::mma_global(FT_.L + (int64_t)k0 * nf + rI, nf, nf - rI, DtL, TB, w, yi, lane, wave);
+  if (I != J) {
+    TL::zero(xj);
+    TL::zero(yj);
+    TL::mma_global(FA.L + (int64_t)k0 * nf + rJ, nf, nf - rJ, DtU, TB, w, xj, lane, wave);
+    TL::mma_global(FT_.L + (int64_t)k0 * nf + rJ, nf, nf - rJ, DtL, TB, w, yj, lane, wave);
+  }
+  // front of A: C -= X_I Y_J^T
+#pragma unroll
+  for (int ti = 0; ti < TL::TI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TL::TJ; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = TL::row(lane, wave, ti, e), cl = TL::col(lane, wave, tj);
+        const E xv = xi.a[ti][tj][e], yv = (I == J) ? yi.a[ti][tj][e] : yj.a[ti][tj][e];
+        Xa[r * LDT + cl] = xv;
+        Xb[cl * LDT + r] = yv;
+        if (I == J && rI + r < nf && cl < w) {
+          Lf[(int64_t)(k0 + cl) * nf + rI + r] = xv;
+          Rf[(int64_t)(k0 + cl) * nf + rI + r] = yi.a[ti][tj][e];
+        }
+      }
+  __syncthreads();
+  TL::mma(Xa, Xb, w, ca, lane, wave, E(-1));
+  __syncthreads();
+  // front of A^T: C -= Y_I X_J^T
+#pragma unroll
+  for (int ti = 0; ti < TL::TI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TL::TJ; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = TL::row(lane, wave, ti, e), cl = TL::col(lane, wave, tj);
+        Xa[r * LDT + cl] = yi.a[ti][tj][e];
+        Xb[cl * LDT + r] = (I == J) ? xi.a[ti][tj][e] : xj.a[ti][tj][e];
+      }
+  __syncthreads();
+  TL::mma(Xa, Xb, w, ct, lane, wave, E(-1));
+#pragma unroll
+  for (int ti = 0; ti < TL::TI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TL::TJ; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (pa[ti][tj][e] != nullptr) {
+          *pa[ti][tj][e] = ca.a[ti][tj][e];
+          *pt[ti][tj][e] = ct.a[ti][tj][e];
+        }
+}
+
 // Rows [64 y, +64) of X with X L_oo = [I; L_bo] (L from the factor buffer);
 // X row r at Fout[r * no + ...] (the front buffer's block of the node).
 // Sixteen waves: each takes one 16 x 16 MFMA tile of a 64 x 64 product.
@@ -715,9 +1011,12 @@ __global__ __launch_bounds__(RT_THREADS) void k_rtrsm(DevTree t, const int* __re
 //       as keeping the full rectangle.
 // The entries left out are the zeros of L_oo^{-1} above its diagonal blocks of
 // K; padding columns / rows are written as zeros.  64 x 64 tiles through LDS.
+// (For an LU factor the forward layout comes from F of L and the backward one
+// from F of Ut, the transposed upper factor: TbufT; TbufT = Tbuf otherwise.)
 template <class E>
 __global__ __launch_bounds__(FT) void k_pack(DevTree t, const int* __restrict__ level_nodes,
-                                             const E* __restrict__ Tbuf, E* __restrict__ Lp, E* __restrict__ Tp) {
+                                             const E* __restrict__ Tbuf, const E* __restrict__ TbufT,
+                                             E* __restrict__ Lp, E* __restrict__ Tp) {
   constexpr int K = 16 / sizeof(E);
   const int v = level_nodes[blockIdx.x];
   const int nf = t.nf[v], no = t.no[v];
@@ -726,9 +1025,8 @@ __global__ __launch_bounds__(FT) void k_pack(DevTree t, const int* __restrict__ 
   const int tr = blockIdx.y % ntr, tc = blockIdx.y / ntr;
   const int r0 = tr * TB, c0 = tc * TB;
   if (r0 >= nfp || c0 >= nop) return;
-  const E* T = Tbuf + t.loff[v];
   __shared__ E S[TB * LDT];
-  {
+  auto stage = [&](const E* __restrict__ T) {
     constexpr int U = TB * TB / FT;
     E x[U];
 #pragma unroll
@@ -742,7 +1040,8 @@ __global__ __launch_bounds__(FT) void k_pack(DevTree t, const int* __restrict__ 
       const int idx = threadIdx.x + u * FT, i = idx / TB, c = idx % TB;
       S[i * LDT + c] = (r0 + i < nf && c0 + c < no) ? x[u] : E(0);
     }
-  }
+  };
+  stage(Tbuf + t.loff[v]);
   __syncthreads();
   E* L = Lp + t.lpoff[v];
   for (int idx = threadIdx.x; idx < TB * TB; idx += FT) {
@@ -750,6 +1049,11 @@ __global__ __launch_bounds__(FT) void k_pack(DevTree t, const int* __restrict__ 
     const int c = gl * K + sl;
     const int rr = r0 + r, g = (c0 + c) / K;
     if (rr < nf && c0 + c < nop && rr >= g * K) L[(lp_group(g, nf, K) + rr - g * K) * K + sl] = S[r * LDT + c];
+  }
+  if (TbufT != Tbuf) {
+    __syncthreads();
+    stage(TbufT + t.loff[v]);
+    __syncthreads();
   }
   E* Tq = Tp + t.tpoff[v];
   const bool tri = t.ttri[v] != 0;
@@ -794,7 +1098,49 @@ void front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, i
   hipLaunchKernelGGL(k_rtrsm<E>, dim3(count, nrt), dim3(RT_THREADS), 0, st, t, level_nodes, (const E*)Lx, Lf,
                      (const E*)D);
   const int nct = (max_no + 3 + TB - 1) / TB, nrp = (max_nf + 3 + TB - 1) / TB;
-  hipLaunchKernelGGL(k_pack<E>, dim3(count, nrp * nct), dim3(FT), 0, st, t, level_nodes, (const E*)Lf, Lp, Tp);
+  hipLaunchKernelGGL(k_pack<E>, dim3(count, nrp * nct), dim3(FT), 0, st, t, level_nodes, (const E*)Lf, (const E*)Lf,
+                     Lp, Tp);
+}
+
+void launch_front_factor_lu(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
+                            int max_nf, int max_child_nb, int max_kids, double s2, double s1, const double* K,
+                            const double* M, const double* C, const double* Ct, double* L, double* U, double* Lx,
+                            double* D, double* R, double* UR, double* Rx, double* DR, double* Lp, double* Tp,
+                            int64_t* status, hipStream_t st) {
+  if (count <= 0) return;
+  typedef double E;
+  const int ncol = (max_nf + TB - 1) / TB;
+  // a front holds the transpose of the rows it is assembled from: the front
+  // of A takes the rows of A^T (C^T values), the front of A^T those of A
+  hipLaunchKernelGGL(k_front_assemble<E>, dim3(count, ncol), dim3(FT), (size_t)2 * max_nf * sizeof(int), st, s.n,
+                     s.lo, s.hi, s.rowptr, t, level_nodes, s2, s1, K, M, Ct, L, U);
+  hipLaunchKernelGGL(k_front_assemble<E>, dim3(count, ncol), dim3(FT), (size_t)2 * max_nf * sizeof(int), st, s.n,
+                     s.lo, s.hi, s.rowptr, t, level_nodes, s2, s1, K, M, C, R, UR);
+  if (max_child_nb > 0)
+    for (int slot = 0; slot < max_kids; ++slot) {
+      hipLaunchKernelGGL(k_front_extend<E>, dim3(count, (max_child_nb + TB - 1) / TB), dim3(FT),
+                         (size_t)max_child_nb * sizeof(int), st, t, level_nodes, slot, L, U, (const float*)nullptr,
+                         (const double*)U);
+      hipLaunchKernelGGL(k_front_extend<E>, dim3(count, (max_child_nb + TB - 1) / TB), dim3(FT),
+                         (size_t)max_child_nb * sizeof(int), st, t, level_nodes, slot, R, UR, (const float*)nullptr,
+                         (const double*)UR);
+    }
+  for (int k0 = 0; k0 < max_no; k0 += TB) {
+    hipLaunchKernelGGL(k_getrf_diag<E>, dim3(count), dim3(FT), 0, st, t, level_nodes, k0, (const E*)L, (const E*)R,
+                       Lx, Rx, D, DR, status);
+    const int below = std::max(1, max_nf - k0 - 1);
+    const int nrc = (below + TB - 1) / TB;
+    hipLaunchKernelGGL(k_panel_update_lu<E>, dim3(count, nrc * (nrc + 1) / 2), dim3(FT), 0, st, t, level_nodes, k0,
+                       L, U, R, UR, Lx, Rx, (const E*)D, (const E*)DR);
+  }
+  const int nrt = (max_nf + TB - 1) / TB;
+  hipLaunchKernelGGL(k_rtrsm<E>, dim3(count, nrt), dim3(RT_THREADS), 0, st, t, level_nodes, (const E*)Lx, L,
+                     (const E*)D);
+  hipLaunchKernelGGL(k_rtrsm<E>, dim3(count, nrt), dim3(RT_THREADS), 0, st, t, level_nodes, (const E*)Rx, R,
+                     (const E*)DR);
+  const int nct = (max_no + 3 + TB - 1) / TB, nrp = (max_nf + 3 + TB - 1) / TB;
+  hipLaunchKernelGGL(k_pack<E>, dim3(count, nrp * nct), dim3(FT), 0, st, t, level_nodes, (const E*)L, (const E*)R,
+                     Lp, Tp);
 }
 
 void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,

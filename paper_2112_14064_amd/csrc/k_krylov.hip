@@ -798,6 +798,32 @@ void launch_pair_forms(int64_t n, int nv, const double* P, const double* MP, con
   hipLaunchKernelGGL(k_pair_forms, dim3(nsplit, nv), dim3(256), 0, st, n, nv, P, MP, CP, KP, ld, part);
 }
 
+// b_k^T (C a_k) per pair (a_k = P column k, b_k = column nv + k, CP = C P):
+// part[k * nsplit + x] for split x, summed in a fixed order.
+__global__ __launch_bounds__(256) void k_cross_form(int64_t n, int nv, const double* __restrict__ P,
+                                                    const double* __restrict__ CP, int64_t ld,
+                                                    double* __restrict__ part) {
+  const int k = blockIdx.y, nsplit = gridDim.x;
+  const int64_t per = (n + nsplit - 1) / nsplit;
+  const int64_t i0 = (int64_t)blockIdx.x * per, i1 = min(n, i0 + per);
+  const int64_t ca = (int64_t)k * ld, cb = (int64_t)(nv + k) * ld;
+  double f = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) f += P[cb + i] * CP[ca + i];
+  __shared__ double red[256];
+  red[threadIdx.x] = f;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(int64_t)k * nsplit + blockIdx.x] = red[0];
+}
+
+void launch_cross_form(int64_t n, int nv, const double* P, const double* CP, int64_t ld, double* part, int nsplit,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_cross_form, dim3(nsplit, nv), dim3(256), 0, st, n, nv, P, CP, ld, part);
+}
+
 // ||K u + lam C u + lam^2 M u||^2 per pair (lam[2k], lam[2k+1] = re, im) and
 // max |u_i|^2 with its index and value:
 // part[(k * nsplit + x) * 5 + {0: sum, 1: max, 2: index, 3: re u_i, 4: im u_i}]

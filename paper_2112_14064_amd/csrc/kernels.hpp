@@ -50,18 +50,24 @@ struct DevTree {
 
 // --- assembly ---------------------------------------------------------------
 // 1-D element mass / stiffness blocks tabM/tabK[e][a][b], a,b in 0..p, from
-// the Cox--de Boor values at the (p+1)-point Gauss rule (gx, gw on [-1, 1]).
+// the Cox--de Boor values at the (p+1)-point Gauss rule (gx, gw on [-1, 1]);
+// tabS (may be null) the blocks of int B_a dB_b/dx.
 void launch_bspline_tables(const DevSpace& s, const double* gx, const double* gw,
-                           double* tabM, double* tabK, hipStream_t st);
+                           double* tabM, double* tabK, double* tabS, hipStream_t st);
+// Band of the 1-D skew matrix s_ij = int B_i B_j' from tabS (layout of M1).
+void launch_band_skew(const DevSpace& s, const double* tabS, double* S1, hipStream_t st);
 // Banded 1-D factors of M and K of a space (see k_assemble.hip): M1, K1 hold
 // n (2p + 1) doubles, entry (i, ii) at i (2p + 1) + ii - i + p.
 void launch_band_1d(const DevSpace& s, const double* tabM, const double* tabK, double* M1, double* K1,
                     hipStream_t st);
 // CSR values of K, M and C = alpha M + beta K + sum_e c_e M_e from the bands
 // (launch_band_1d first) and, for c_elem, the element tables: one wave per row.
+// With S1 (launch_band_skew) C also gets the gyroscopic part
+// gx M1 (x) S1 + gy S1 (x) M1 (x fastest) and Ct the values of C^T.
 void launch_assemble(const DevSpace& s, const double* tabM, const double* M1, const double* K1,
                      double alpha, double beta, const double* c_elem,
-                     double* K, double* M, double* C, int64_t ndof, hipStream_t st);
+                     double* K, double* M, double* C, int64_t ndof, hipStream_t st,
+                     const double* S1 = nullptr, double gx = 0.0, double gy = 0.0, double* Ct = nullptr);
 // Bands of every problem of a forest: problem q's tables at taboff[q], its
 // bands at bandoff[q] (max_w: the largest n (2p + 1)).
 void launch_band_1d_b(const DevSpace* spaces, int n, int max_w, const int64_t* taboff, const double* tabM,
@@ -87,6 +93,17 @@ void launch_assemble_b(const int4* rb, int nrb, const DevSpace* spaces, const in
 // factorization.  D holds the 64x64 inverses of the diagonal blocks (doff);
 // max_no / max_nf bound the level, max_child_nb / max_kids its children.
 // FP64 level: children flagged in t.prec keep their update blocks in U32.
+// One tree level of the LU factorisation of a nonsymmetric Q = s2 M + s1 C + K
+// (C with a skew part; Ct: the values of C^T on the same pattern) without
+// pivoting (see k_factor.hip): the front of A in L / U with the factor L in Lx
+// and its diagonal-block inverses in D, the front of A^T in R / UR with the
+// transposed upper factor in Rx and inverses in DR; the forward sweep layout
+// Lp from L's F and the backward layout Tp from Ut's F.  FP64 only.
+void launch_front_factor_lu(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
+                            int max_nf, int max_child_nb, int max_kids, double s2, double s1, const double* K,
+                            const double* M, const double* C, const double* Ct, double* L, double* U, double* Lx,
+                            double* D, double* R, double* UR, double* Rx, double* DR, double* Lp, double* Tp,
+                            int64_t* status, hipStream_t st);
 void launch_front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, int count, int max_no,
                          int max_nf, int max_child_nb, int max_kids, double s2, double s1, const double* K, const double* M,
                          const double* C, double* L, double* U, double* T, double* D, double* Lp, double* Tp,
@@ -260,6 +277,9 @@ void launch_random_fill(double* X, int64_t n, int ncols, int64_t ld, uint64_t se
 // (ld rows each) with MP = M P, CP = C P, KP = K P; see k_krylov.hip.
 void launch_pair_forms(int64_t n, int nv, const double* P, const double* MP, const double* CP,
                        const double* KP, int64_t ld, double* part, int nsplit, hipStream_t st);
+// b_k^T (C a_k) of every planar pair (see k_krylov.hip): part[k nsplit + x].
+void launch_cross_form(int64_t n, int nv, const double* P, const double* CP, int64_t ld, double* part, int nsplit,
+                       hipStream_t st);
 void launch_pair_resid(int64_t n, int nv, const double* P, const double* MP, const double* CP,
                        const double* KP, int64_t ld, const double* lam, double* part, int nsplit,
                        hipStream_t st);

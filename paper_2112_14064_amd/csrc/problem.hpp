@@ -42,6 +42,13 @@ struct riga_problem {
   double *d_M1 = nullptr, *d_K1 = nullptr;          // banded 1-D factors of M and K (launch_band_1d)
   double *d_K = nullptr, *d_M = nullptr, *d_C = nullptr;
   double* d_A = nullptr;                            // sigma M + C (formed at factor time)
+  // Gyroscopic damping (C = alpha M + beta K + G, G skew): element tables and
+  // band of int B_i B_j', the values of C^T on C's pattern, and the second
+  // triangle of every nonsymmetric front (front, update, factor, inverses).
+  bool gyro = false;
+  double gx = 0.0, gy = 0.0;
+  double *d_tabS = nullptr, *d_S1 = nullptr, *d_Ct = nullptr;
+  double *d_LR = nullptr, *d_UR = nullptr, *d_TR = nullptr, *d_DR = nullptr;
   double *d_L = nullptr, *d_U = nullptr, *d_T = nullptr, *d_upd = nullptr, *d_tmp = nullptr, *d_tmp2 = nullptr;
   double *d_Lp = nullptr, *d_Tp = nullptr;         // F in the sweep layouts
   int64_t lpsize = 0, tpsize = 0;

@@ -65,7 +65,7 @@ EXPORTS = ["riga_create", "riga_info", "riga_assemble", "riga_export_csr", "riga
            "riga_batch_autotune",
            "riga_factor_gep", "riga_gep_slice",
            "riga_solve_q", "riga_solve_q_noalloc", "riga_apply_op", "riga_eigs", "riga_adjoint", "riga_stats", "riga_time_kernel",
-           "riga_selftest_small_eig", "riga_selftest_schur_restart", "riga_symbolic", "riga_status_str", "riga_destroy", "riga_selftest_range_basis"]
+           "riga_selftest_small_eig", "riga_selftest_schur_restart", "riga_symbolic", "riga_status_str", "riga_destroy", "riga_selftest_range_basis", "riga_assemble_gyroscopic"]
 
 _lib = None
 
@@ -86,6 +86,7 @@ def load(path: str = LIB_PATH):
     lib.riga_create.argtypes = [C.POINTER(P), C.POINTER(riga_mesh), C.c_int, P]
     lib.riga_info.argtypes = [P, C.POINTER(riga_info_t)]
     lib.riga_assemble.argtypes = [P, C.POINTER(riga_damping)]
+    lib.riga_assemble_gyroscopic.argtypes = [P, C.POINTER(riga_damping), C.c_double, C.c_double]
     lib.riga_export_csr.argtypes = [P, C.c_int, P, P, P]
     lib.riga_factor.argtypes = [P, C.c_double, C.POINTER(C.c_int64)]
     lib.riga_factor_mixed.argtypes = [P, C.c_double, C.c_int, C.c_int, C.c_double, P, C.POINTER(C.c_int64)]
@@ -248,13 +249,18 @@ class Problem:
         except Exception:
             pass
 
-    def assemble(self, alpha: float = 0.0, beta: float = 0.0, c_elem=None):
-        """c_elem: None or a float64 tensor (ne, ne) [ey, ex] on this device."""
+    def assemble(self, alpha: float = 0.0, beta: float = 0.0, c_elem=None, gyro=None):
+        """c_elem: None or a float64 tensor (ne, ne) [ey, ex] on this device;
+        gyro: None or (gx, gy), the skew part of riga_assemble_gyroscopic."""
         if c_elem is not None:
             c_elem = c_elem.to(device=self.device, dtype=self.torch.float64).contiguous()
         self._c_elem = c_elem  # kept alive while the handle may read it
         d = riga_damping(alpha, beta, _ptr(c_elem))
-        _check(self.lib.riga_assemble(self.h, C.byref(d)), "riga_assemble")
+        if gyro is None:
+            _check(self.lib.riga_assemble(self.h, C.byref(d)), "riga_assemble")
+        else:
+            _check(self.lib.riga_assemble_gyroscopic(self.h, C.byref(d), float(gyro[0]), float(gyro[1])),
+                   "riga_assemble_gyroscopic")
 
     def export_csr(self, which: int):
         torch = self.torch

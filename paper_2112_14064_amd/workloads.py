@@ -95,6 +95,16 @@ def cfg_undamped(hyper_every: int = 16) -> Problem:
                    extra={"interval": (0.0, 1500.0), "max_slice": 40})
 
 
+def cfg_gyro(hyper_every: int = 16) -> Problem:
+    """The headline mesh with a gyroscopic damping: p=3 on 256x256, rIGA (C^0
+    every 16 elements) or IGA (hyper_every=0), C = 0.05 M + 0.005 K + G with
+    the skew form of g = (0.5, 0), the 40 eigenpairs nearest sigma=2 with
+    subspace 80."""
+    tag = f"s{hyper_every}" if hyper_every else "iga"
+    return Problem(p=3, ne=256, hyper_every=hyper_every, alpha=0.05, beta=0.005, sigma=2.0, nev=40, m=80,
+                   name=f"p3_256x256_{tag}_gyro", extra={"gyro": (0.5, 0.0)})
+
+
 def cfg_precision() -> Problem:
     """p=4 on 1024x1024, C^0 every 32 elements, c_e ~ lognormal(-3,0.5) seed 0,
     20 eigenpairs near sigma=5."""
