@@ -23,6 +23,9 @@ Modules
     adjoint   d lam / d c_e for a per-element damping field
     gep       the undamped pencil K u = mu M u: closed-form eigenvalues in an interval,
               dense solver, inertia counts (Sec. 4.1.4, spectrum slicing), residual
+    hcurl     the curl-conforming space S^{p-1,p} x S^{p,p-1} (Sec. 3.2-3.3): element assembly
+              of the curl-curl and mass matrices, the discrete gradient, the Maxwell
+              eigenvalues as sums of 1-D values
     gyro      damping with a skew-symmetric (gyroscopic) part G_ab = int B_a (g . grad B_b):
               element assembly, the 1-D skew matrix, eigenvalues from the 1-D QEPs
               of the y-modes (gy = 0)
