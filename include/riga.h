@@ -69,10 +69,31 @@ typedef enum {
  *                bisected at element interfaces until both sides are <= leaf
  *                elements (0 = default 8: measured fastest for the factor and
  *                the sweeps at degrees 3-4).  With s <= leaf the rIGA leaves
- *                are the macroelements.                                         */
+ *                are the macroelements.
+ *   space        RIGA_SPACE_H1 (0): the scalar space S^{p,p} with homogeneous
+ *                Dirichlet conditions (the first and last function removed
+ *                in each direction).  RIGA_SPACE_HCURL (1): the curl-conforming
+ *                space S^{p-1,p} x S^{p,p-1} of eq. HcurlBasis (Sec. 3.2), dofs
+ *                [E_x..., E_y...] as in eq. HcurlControlVariables; rIGA
+ *                hyperplanes reduce the continuity by k-1 = p-2 (knot
+ *                multiplicity p-1: C^1 in degree p, C^0 in degree p-1; eq.
+ *                DiscreteSpacesrIGA); the tangential component vanishes on
+ *                the boundary (the degree-p factor loses its end functions).
+ *                RIGA_SPACE_HCURL_FREE (2): the same space without boundary
+ *                condition (the matrices of fig. MatPatterns).  Vector spaces
+ *                need p >= 2 and are assembled with K = int rot u rot v,
+ *                M = int u . v (rot u = du_y/dx - du_x/dy), C = alpha M +
+ *                beta K; they support riga_factor, the solves and the
+ *                undamped case (riga_factor_gep, riga_gep_slice), not
+ *                riga_eigs, riga_apply_op, riga_factor_mixed, an element
+ *                damping field, a gyroscopic part, the adjoint or a forest. */
 typedef struct {
   int p, ne, hyper_every, leaf;
+  int space;
 } riga_mesh;
+#define RIGA_SPACE_H1 0
+#define RIGA_SPACE_HCURL 1
+#define RIGA_SPACE_HCURL_FREE 2
 
 /* Damping C = alpha M + beta K + sum_e c_e M_e (Rayleigh part plus an optional
  * per-element viscous field).  c_elem: device, ne*ne doubles indexed
@@ -437,7 +458,12 @@ riga_status riga_factor_gep(riga_problem* h, double shift, int64_t* neg_count, i
  * spectrum slicing:
  *   1. count = nu(b) - nu(a) from two signed factorizations;
  *   2. a slice holding more than max_slice eigenvalues (0: 40; >= 2) is
- *      bisected at its midpoint, whose count costs one factorization;
+ *      bisected at its midpoint, whose count costs one factorization; on a
+ *      vector space (whose gradients are a null space of large multiplicity)
+ *      a slice [l, r) holding eigenvalues is also bisected until
+ *      r - l <= l / 2, so that the null space's operator value -1/s stays
+ *      well below the slice's own (a > 0 there: a <= 0 counts the whole null
+ *      space);
  *   3. each slice [l, r) with k > 0 eigenvalues is factored at its midpoint s
  *      (moved by 1e-9 relative if a pivot vanishes) and solved by block Lanczos
  *      (opt->block, 0: 2; opt->tol, opt->maxit, opt->seed as for riga_eigs;

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libriga.so")
 
-SOURCES = ["plan.cpp", "sweep_plan.cpp", "small_eig.cpp", "ks_host.cpp", "api.cpp", "toar.cpp", "k_assemble.hip", "k_factor.hip", "k_solve.hip",
+SOURCES = ["plan.cpp", "sweep_plan.cpp", "small_eig.cpp", "ks_host.cpp", "api.cpp", "toar.cpp", "hcurl.cpp", "k_assemble.hip", "k_factor.hip", "k_solve.hip",
            "k_krylov.hip", "k_toar.hip", "k_batch.hip", "batch.cpp", "noalloc.hip", "gep.cpp"]
 
 ARCH = "gfx950"

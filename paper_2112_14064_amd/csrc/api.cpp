@@ -179,6 +179,14 @@ void apply_block(riga_problem* h, int nb, const double* vu, const double* wl, in
   solve_levels(h, nb, t, N, ru, N, rl, vu, ld, h->sigma);
 }
 
+void mass_product(riga_problem* h, int nq, const double* X, double* Y) {
+  const int64_t N = h->N();
+  if (h->plan.kind == riga::SPACE_H1)
+    riga::launch_tensor_mk(h->ds, h->d_M1, h->d_K1, nq, 1.0, 0.0, X, N, Y, N, nullptr, 0, 0.0, h->st);
+  else
+    riga::launch_spmv(h->ds, N, nq, h->d_M, 1.0, X, N, Y, N, nullptr, 0, 0.0, nullptr, 0, h->st);
+}
+
 // ||K||_1, ||C||_1, ||M||_1 (largest absolute column sums): one launch, one copy.
 void ensure_norms(riga_problem* h) {
   if (h->norms[0] >= 0) return;
@@ -278,6 +286,13 @@ void setup_device(riga_problem* h) {
     h->ds.lo = h->upload(S.lo); h->ds.hi = h->upload(S.hi);
     h->ds.first = h->upload(S.first);
     h->ds.rowptr = h->upload(P.rowptr);
+    h->ds.col = nullptr;
+    if (P.kind != riga::SPACE_H1) {
+      h->ds.col = h->upload(P.col);
+      std::vector<double> MA, MB, KB, D;
+      hcurl_1d(P.cx[0], P.cy[0], MA, MB, KB, D);   // A = S^{p-1} (x of component 0), B = S^p
+      h->d_hMA = h->upload(MA); h->d_hMB = h->upload(MB); h->d_hKB = h->upload(KB); h->d_hD = h->upload(D);
+    }
     h->dt.nf = h->upload(P.nf); h->dt.no = h->upload(P.no); h->dt.nb = h->upload(P.nb);
     h->dt.loff = h->upload(P.loff); h->dt.uoff = h->upload(P.uoff);
     h->dt.foff = h->upload(P.foff); h->dt.fdofs = h->upload(P.fdofs);
@@ -374,7 +389,14 @@ riga_status riga_create(riga_problem** out, const riga_mesh* mesh, int device, v
   riga_problem* h = new (std::nothrow) riga_problem();
   if (!h) return RIGA_ERR_OOM;
   h->mesh = *mesh;
-  if (h->plan.build(mesh->p, mesh->ne, mesh->hyper_every, mesh->leaf) != 0) {
+  const int kind = mesh->space;
+  const int built = kind == RIGA_SPACE_H1
+                        ? h->plan.build(mesh->p, mesh->ne, mesh->hyper_every, mesh->leaf)
+                        : (kind == RIGA_SPACE_HCURL || kind == RIGA_SPACE_HCURL_FREE)
+                              ? h->plan.build_hcurl(mesh->p, mesh->ne, mesh->hyper_every, mesh->leaf,
+                                                    kind == RIGA_SPACE_HCURL)
+                              : -1;
+  if (built != 0) {
     delete h;
     return RIGA_ERR_INVALID_ARG;
   }
@@ -383,7 +405,7 @@ riga_status riga_create(riga_problem** out, const riga_mesh* mesh, int device, v
     h->device = device;
     h->st = (hipStream_t)hip_stream;
     setup_device(h);
-    setup_ell(h, {int4{0, 0, (int)h->N(), 0}});
+    if (h->plan.kind == riga::SPACE_H1) setup_ell(h, {int4{0, 0, (int)h->N(), 0}});
     return RIGA_OK;
   });
   if (rc != RIGA_OK) {
@@ -435,7 +457,12 @@ riga_status riga_symbolic(const riga_mesh* mesh, int64_t* ndof, int64_t* order, 
   if (!mesh) return RIGA_ERR_INVALID_ARG;
   return run([&]() -> riga_status {
     riga::Plan P;
-    if (P.build(mesh->p, mesh->ne, mesh->hyper_every, mesh->leaf) != 0) return RIGA_ERR_INVALID_ARG;
+    const int kind = mesh->space;
+    const int built = kind == RIGA_SPACE_H1 ? P.build(mesh->p, mesh->ne, mesh->hyper_every, mesh->leaf)
+                      : (kind == RIGA_SPACE_HCURL || kind == RIGA_SPACE_HCURL_FREE)
+                          ? P.build_hcurl(mesh->p, mesh->ne, mesh->hyper_every, mesh->leaf, kind == RIGA_SPACE_HCURL)
+                          : -1;
+    if (built != 0) return RIGA_ERR_INVALID_ARG;
     if (ndof) *ndof = P.ndof;
     std::vector<int64_t> cc;
     int64_t nz = 0;
@@ -455,8 +482,29 @@ namespace {
 riga_status assemble_impl(riga_problem* h, const riga_damping* damping, double gx, double gy) {
   if (!h || !damping || !std::isfinite(gx) || !std::isfinite(gy)) return RIGA_ERR_INVALID_ARG;
   if ((gx != 0.0 || gy != 0.0) && !h->node_inst.empty()) return RIGA_ERR_INVALID_ARG;
+  if (h->plan.kind != riga::SPACE_H1 && (gx != 0.0 || gy != 0.0 || damping->c_elem != nullptr))
+    return RIGA_ERR_INVALID_ARG;
   return run([&]() -> riga_status {
     ck(hipSetDevice(h->device));
+    if (h->plan.kind != riga::SPACE_H1) {
+      const riga::Plan& P = h->plan;
+      ck(hipEventRecord(h->ev0, h->st));
+      riga::launch_assemble_hcurl(P.cx[0].n, P.cx[1].n, P.cbase[1], P.ndof, h->ds.rowptr, h->ds.col, h->d_hMA,
+                                  h->d_hMB, h->d_hKB, h->d_hD, damping->alpha, damping->beta, h->d_K, h->d_M,
+                                  h->d_C, h->st);
+      ck(hipGetLastError());
+      ck(hipEventRecord(h->ev1, h->st));
+      h->gyro = false; h->gx = h->gy = 0.0;
+      h->alpha = damping->alpha; h->beta = damping->beta; h->c_elem = nullptr;
+      h->clear_graphs();
+      h->assembled = true;
+      h->factored = false;
+      h->norms[0] = h->norms[1] = h->norms[2] = -1;
+      h->stats.flops[RIGA_PHASE_ASSEMBLE] = 0.0;
+      h->stats.bytes[RIGA_PHASE_ASSEMBLE] = 24.0 * (double)P.nnz;
+      h->stats.t_assemble_ms = -1;
+      return RIGA_OK;
+    }
     const bool gyro = gx != 0.0 || gy != 0.0;
     if (gyro && h->d_Ct == nullptr) {
       const riga::Plan& P = h->plan;
@@ -509,7 +557,9 @@ riga_status riga_export_csr(riga_problem* h, int which, int64_t* rowptr, int32_t
     const riga::Plan& P = h->plan;
     const riga::Space1D& S = P.sp;
     if (rowptr) std::memcpy(rowptr, P.rowptr.data(), (P.ndof + 1) * sizeof(int64_t));
-    if (col) {
+    if (col && !P.col.empty()) {
+      std::copy(P.col.begin(), P.col.end(), col);
+    } else if (col) {
       const int n = S.n;
       int64_t k = 0;
       for (int j = 0; j < n; ++j)
@@ -773,7 +823,7 @@ riga_status riga_factor_mixed(riga_problem* h, double sigma, int fp64_levels, in
       ir_sweeps > RIGA_IR_MAX || !(ir_tol >= 0.0))
     return RIGA_ERR_INVALID_ARG;
   if (!h->assembled) return RIGA_ERR_STATE;
-  if (h->gyro) return RIGA_ERR_INVALID_ARG;   // LU fronts are FP64 only
+  if (h->gyro || h->plan.kind != riga::SPACE_H1) return RIGA_ERR_INVALID_ARG;   // FP64 LU / vector space
   return run([&]() -> riga_status {
     ck(hipSetDevice(h->device));
     h->clear_graphs();
@@ -879,6 +929,7 @@ riga_status riga_solve_q(riga_problem* h, int nrhs, const double* b, double* x) 
 
 riga_status riga_apply_op(riga_problem* h, int nvec, const double* v, double* r) {
   if (!h || nvec < 1 || nvec > 4 || !v || !r || v == r) return RIGA_ERR_INVALID_ARG;
+  if (h->plan.kind != riga::SPACE_H1) return RIGA_ERR_INVALID_ARG;
   if (!h->factored || h->gep) return RIGA_ERR_STATE;
   return run([&]() -> riga_status {
     ck(hipSetDevice(h->device));
@@ -1052,7 +1103,8 @@ riga_status riga_adjoint(riga_problem* h, int nev, const double* lam, const doub
                          double* grad_c) {
   if (!h || nev < 1 || !lam || !X || !dL_dlam || !grad_c) return RIGA_ERR_INVALID_ARG;
   if (!h->assembled) return RIGA_ERR_STATE;
-  if (h->gyro) return RIGA_ERR_INVALID_ARG;   // the formula needs the complex-symmetric pencil
+  // the formula needs the complex-symmetric pencil of the scalar space
+  if (h->gyro || h->plan.kind != riga::SPACE_H1) return RIGA_ERR_INVALID_ARG;
   return run([&]() -> riga_status {
     ck(hipSetDevice(h->device));
     const int64_t N = h->N();
@@ -1458,6 +1510,7 @@ int finish_pairs(riga_problem* h, const riga::KsCycle& cyc, int nev, double* dsm
 extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, double* lam, double* X,
                                  double* eta, int* nconv) {
   if (!h || !opt || !lam) return RIGA_ERR_INVALID_ARG;
+  if (h->plan.kind != riga::SPACE_H1) return RIGA_ERR_INVALID_ARG;   // tensor products of the scalar space
   if (!h->factored || h->gep) return RIGA_ERR_STATE;
   const int64_t N = h->N();
   const int nev = opt->nev;

@@ -185,7 +185,9 @@ riga_status riga_batch_create(riga_batch** out, int n, const riga_mesh* meshes, 
   bh->plans.resize(n);
   std::vector<int> bad(n, 0);
   parallel_for(n, [&](int i) {
-    bad[i] = bh->plans[i].build(meshes[i].p, meshes[i].ne, meshes[i].hyper_every, meshes[i].leaf);
+    bad[i] = meshes[i].space != RIGA_SPACE_H1
+                 ? -1
+                 : bh->plans[i].build(meshes[i].p, meshes[i].ne, meshes[i].hyper_every, meshes[i].leaf);
     if (bad[i] == 0) bh->plans[i].ensure_symbolic();   // algorithmic factor flops of the forest
   });
   for (int i = 0; i < n; ++i)

@@ -107,14 +107,14 @@ struct Lanczos {
   // R = (K - s M)^{-1} W[:, k:k+b] = S V[:, k:k+b]; MR = M R.
   void apply(int k) {
     solve_levels(h, b, h->Wl + (size_t)k * N, N, h->Ru, N, nullptr, nullptr, 0, 0.0);
-    riga::launch_tensor_mk(h->ds, h->d_M1, h->d_K1, b, 1.0, 0.0, h->Ru, N, h->MRl, N, nullptr, 0, 0.0, h->st);
+    mass_product(h, b, h->Ru, h->MRl);
     n_op += b;
   }
 
   // Start block: the library's counter-based generator, M-orthonormalised.
   bool start(uint64_t seed) {
     riga::launch_random_fill(h->Ru, N, b, N, seed, h->st);
-    riga::launch_tensor_mk(h->ds, h->d_M1, h->d_K1, b, 1.0, 0.0, h->Ru, N, h->MRl, N, nullptr, 0, 0.0, h->st);
+    mass_product(h, b, h->Ru, h->MRl);
     std::vector<double> hs, Rb;
     return orthonormalize(0, hs, Rb);
   }
@@ -334,6 +334,7 @@ riga_status riga_gep_slice(riga_problem* h, double a, double b, int max_slice, c
     return RIGA_ERR_INVALID_ARG;
   if (max_slice == 0) max_slice = 40;
   if (max_slice < 2 || opt->block < 0 || opt->block > 4 || opt->v0 != nullptr) return RIGA_ERR_INVALID_ARG;
+  if (h->plan.kind != riga::SPACE_H1 && !(a > 0.0)) return RIGA_ERR_INVALID_ARG;   // the null space
   if (!h->assembled) return RIGA_ERR_STATE;
   return run([&]() -> riga_status {
     ck(hipSetDevice(h->device));
@@ -363,14 +364,22 @@ riga_status riga_gep_slice(riga_problem* h, double a, double b, int max_slice, c
     if (rc != RIGA_OK) return rc;
     *count = nhi - nlo;
     if (*count > cap) return RIGA_ERR_INVALID_ARG;
-    // bisect until every slice holds at most max_slice eigenvalues
+    // bisect until every slice holds at most max_slice eigenvalues.  A vector
+    // space's pencil has the gradients as a null space of huge multiplicity:
+    // seen from the midpoint s of a slice [l, r) they are the value
+    // theta = -1/s, against |theta| >= 2/(r - l) for the slice's own values,
+    // so its slices are also halved until r - l <= l / 2 (the null cluster
+    // then stays below a fifth of every wanted |theta|)
+    const double rho = h->plan.kind != riga::SPACE_H1 ? 0.5 : 0.0;
     std::vector<Slice> todo{{lo, hi, nlo, nhi}}, done;
     while (!todo.empty()) {
       Slice sl = todo.back();
       todo.pop_back();
+      const bool narrow = rho == 0.0 || (sl.lo > 0.0 && sl.hi - sl.lo <= rho * sl.lo);
       // a slice narrower than 1e-10 relative (a cluster of more than max_slice
       // equal eigenvalues) is solved as it is
-      if (sl.nhi - sl.nlo <= max_slice || sl.hi - sl.lo <= 1e-10 * std::max(std::abs(sl.hi), 1e-300)) {
+      if (sl.nhi == sl.nlo || (sl.nhi - sl.nlo <= max_slice && narrow) ||
+          sl.hi - sl.lo <= 1e-10 * std::max(std::abs(sl.hi), 1e-300)) {
         if (sl.nhi > sl.nlo) done.push_back(sl);
         continue;
       }

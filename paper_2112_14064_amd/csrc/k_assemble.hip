@@ -323,4 +323,71 @@ void launch_assemble(const DevSpace& s, const double* tabM, const double* M1, co
   hipLaunchKernelGGL(k_assemble, dim3((unsigned)blocks), dim3(ASM_THREADS), 0, st, s, ndof, tabM, M1, K1, alpha, beta,
                      c_elem, K, M, C, S1, gx, gy, Ct);
 }
+
+// ---------------------------------------------------------------------------
+// H(curl) space S^{p-1,p} x S^{p,p-1} (Sec. 3.2, eq. HcurlBasis): component 0
+// dofs (i, j) = A_i(x) B_j(y) first, component 1 dofs B_i(x) A_j(y) from base1
+// on (x fastest within a component), with A the degree-(p-1) and B the
+// degree-p 1-D space.  With rot u = d u_2/dx - d u_1/dy,
+//   K00 = MA[i][ii] KB[j][jj],   K11 = KB[i][ii] MA[j][jj],
+//   K01 = -D[i][ii] D[jj][j],    K10 = -D[ii][i] D[j][jj],
+//   M00 = MA[i][ii] MB[j][jj],   M11 = MB[i][ii] MA[j][jj],   M01 = M10 = 0,
+// with MA, MB, KB, D the dense 1-D matrices (hcurl_1d on the host); C =
+// alpha M + beta K.  One wave per row, lanes over its stored entries
+// (explicit column indices).
+__global__ __launch_bounds__(ASM_THREADS) void k_assemble_hcurl(int na, int nb, int64_t base1, int64_t ndof,
+                                                                const int64_t* __restrict__ rowptr,
+                                                                const int* __restrict__ col,
+                                                                const double* __restrict__ MA,
+                                                                const double* __restrict__ MB,
+                                                                const double* __restrict__ KB,
+                                                                const double* __restrict__ D, double alpha,
+                                                                double beta, double* __restrict__ Ko,
+                                                                double* __restrict__ Mo, double* __restrict__ Co) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r0 = ((int64_t)blockIdx.x * ASM_WAVES + wave) * ASM_ROWS_PER_WAVE;
+  for (int qr = 0; qr < ASM_ROWS_PER_WAVE; ++qr) {
+    const int64_t r = r0 + qr;
+    if (r >= ndof) break;
+    const int c = r >= base1 ? 1 : 0;
+    const int64_t rr = r - (c ? base1 : 0);
+    const int nx = c ? nb : na;
+    const int i = (int)(rr % nx), j = (int)(rr / nx);
+    const int64_t k0 = rowptr[r], k1 = rowptr[r + 1];
+    for (int64_t k = k0 + lane; k < k1; k += 64) {
+      const int64_t cc = col[k];
+      const int b = cc >= base1 ? 1 : 0;
+      const int64_t cr = cc - (b ? base1 : 0);
+      const int mx = b ? nb : na;
+      const int ii = (int)(cr % mx), jj = (int)(cr / mx);
+      double kv, mv;
+      if (c == 0 && b == 0) {
+        kv = MA[(int64_t)i * na + ii] * KB[(int64_t)j * nb + jj];
+        mv = MA[(int64_t)i * na + ii] * MB[(int64_t)j * nb + jj];
+      } else if (c == 1 && b == 1) {
+        kv = KB[(int64_t)i * nb + ii] * MA[(int64_t)j * na + jj];
+        mv = MB[(int64_t)i * nb + ii] * MA[(int64_t)j * na + jj];
+      } else if (c == 0) {
+        kv = -D[(int64_t)i * nb + ii] * D[(int64_t)jj * nb + j];
+        mv = 0.0;
+      } else {
+        kv = -D[(int64_t)ii * nb + i] * D[(int64_t)j * nb + jj];
+        mv = 0.0;
+      }
+      Ko[k] = kv;
+      Mo[k] = mv;
+      Co[k] = alpha * mv + beta * kv;
+    }
+  }
+}
+
+void launch_assemble_hcurl(int na, int nb, int64_t base1, int64_t ndof, const int64_t* rowptr, const int* col,
+                           const double* MA, const double* MB, const double* KB, const double* D, double alpha,
+                           double beta, double* K, double* M, double* C, hipStream_t st) {
+  const int64_t rows = (int64_t)ASM_WAVES * ASM_ROWS_PER_WAVE;
+  const int64_t blocks = (ndof + rows - 1) / rows;
+  hipLaunchKernelGGL(k_assemble_hcurl, dim3((unsigned)blocks), dim3(ASM_THREADS), 0, st, na, nb, base1, ndof, rowptr,
+                     col, MA, MB, KB, D, alpha, beta, K, M, C);
+}
+
 }  // namespace riga

@@ -148,7 +148,7 @@ struct Tile64 {
 // finds an entry's front position by binary search in shared memory.
 template <class E>
 __global__ __launch_bounds__(FT) void k_front_assemble(
-    int n, const int* lo, const int* hi, const int64_t* rowptr,
+    int n, const int* lo, const int* hi, const int64_t* rowptr, const int* __restrict__ col,
     DevTree t, const int* __restrict__ level_nodes, double s2, double s1,
     const double* __restrict__ Kv, const double* __restrict__ Mv, const double* __restrict__ Cv,
     E* __restrict__ Lbuf, E* __restrict__ Ubuf) {
@@ -193,10 +193,12 @@ __global__ __launch_bounds__(FT) void k_front_assemble(
   int m_lx = 0, m_wx = 1, m_ly = 0, m_k0 = 0, m_len = 0;
   if (lane < na) {
     const int d = fd[c0 + wave + (FT / 64) * lane] - base;
-    const int i = d % n, j = d / n;
-    m_lx = lo[i];
-    m_wx = hi[i] - m_lx + 1;
-    m_ly = lo[j];
+    if (col == nullptr) {
+      const int i = d % n, j = d / n;
+      m_lx = lo[i];
+      m_wx = hi[i] - m_lx + 1;
+      m_ly = lo[j];
+    }
     const int64_t r0 = rowptr[d];
     m_k0 = (int)(r0 - rowptr[0]);
     m_len = (int)(rowptr[d + 1] - r0);
@@ -226,9 +228,14 @@ __global__ __launch_bounds__(FT) void k_front_assemble(
         if (u >= na) break;
         if (o >= __builtin_amdgcn_readlane(m_len, u)) continue;
         const int a = c0 + wave + (FT / 64) * u;
-        const int lx = __builtin_amdgcn_readlane(m_lx, u), wx = __builtin_amdgcn_readlane(m_wx, u);
-        const int ly = __builtin_amdgcn_readlane(m_ly, u);
-        const int g = (ly + o / wx) * n + lx + o % wx + base;
+        int g;
+        if (col != nullptr) {
+          g = col[kbase + __builtin_amdgcn_readlane(m_k0, u) + o] + base;
+        } else {
+          const int lx = __builtin_amdgcn_readlane(m_lx, u), wx = __builtin_amdgcn_readlane(m_wx, u);
+          const int ly = __builtin_amdgcn_readlane(m_ly, u);
+          g = (ly + o / wx) * n + lx + o % wx + base;
+        }
         int x0 = 0, x1 = nf;  // binary search of g among the sorted front keys
         while (x1 - x0 > 1) {
           const int c = (x0 + x1) >> 1;
@@ -1079,7 +1086,7 @@ void front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, i
   if (count <= 0) return;
   const int ncol = (max_nf + TB - 1) / TB;
   hipLaunchKernelGGL(k_front_assemble<E>, dim3(count, ncol), dim3(FT), (size_t)2 * max_nf * sizeof(int), st, s.n,
-                     s.lo, s.hi, s.rowptr, t, level_nodes, s2, s1, K, M, C, Lf, U);
+                     s.lo, s.hi, s.rowptr, s.col, t, level_nodes, s2, s1, K, M, C, Lf, U);
   if (max_child_nb > 0)
     for (int slot = 0; slot < max_kids; ++slot)
       hipLaunchKernelGGL(k_front_extend<E>, dim3(count, (max_child_nb + TB - 1) / TB), dim3(FT),
@@ -1113,9 +1120,9 @@ void launch_front_factor_lu(const DevSpace& s, const DevTree& t, const int* leve
   // a front holds the transpose of the rows it is assembled from: the front
   // of A takes the rows of A^T (C^T values), the front of A^T those of A
   hipLaunchKernelGGL(k_front_assemble<E>, dim3(count, ncol), dim3(FT), (size_t)2 * max_nf * sizeof(int), st, s.n,
-                     s.lo, s.hi, s.rowptr, t, level_nodes, s2, s1, K, M, Ct, L, U);
+                     s.lo, s.hi, s.rowptr, s.col, t, level_nodes, s2, s1, K, M, Ct, L, U);
   hipLaunchKernelGGL(k_front_assemble<E>, dim3(count, ncol), dim3(FT), (size_t)2 * max_nf * sizeof(int), st, s.n,
-                     s.lo, s.hi, s.rowptr, t, level_nodes, s2, s1, K, M, C, R, UR);
+                     s.lo, s.hi, s.rowptr, s.col, t, level_nodes, s2, s1, K, M, C, R, UR);
   if (max_child_nb > 0)
     for (int slot = 0; slot < max_kids; ++slot) {
       hipLaunchKernelGGL(k_front_extend<E>, dim3(count, (max_child_nb + TB - 1) / TB), dim3(FT),

@@ -53,10 +53,64 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(
   }
 }
 
+// The same product with explicit column indices (vector spaces): SPMV_G
+// lanes per row, entries strided by SPMV_G.
+template <int NC>
+__global__ __launch_bounds__(SPMV_THREADS) void k_spmv_csr(
+    const int* __restrict__ col, const int64_t* __restrict__ rowptr, int64_t ndof, const double* __restrict__ A,
+    double a, const double* __restrict__ X, int64_t ldx, double* __restrict__ Y, int64_t ldy,
+    const double* __restrict__ Z, int64_t ldz, double bz, double* __restrict__ Y2, int64_t ldy2) {
+  const int g = threadIdx.x % SPMV_G;
+  const int64_t r = ((int64_t)blockIdx.x * SPMV_THREADS + threadIdx.x) / SPMV_G;
+  const bool active = r < ndof;
+  double s[NC];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) s[q] = 0.0;
+  if (active) {
+    const int64_t k1 = rowptr[r + 1];
+    for (int64_t k = rowptr[r] + g; k < k1; k += SPMV_G) {
+      const double av = A[k];
+      const int64_t c = col[k];
+#pragma unroll
+      for (int q = 0; q < NC; ++q) s[q] += av * X[c + q * ldx];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NC; ++q)
+#pragma unroll
+    for (int off = SPMV_G / 2; off > 0; off >>= 1) s[q] += __shfl_xor(s[q], off, SPMV_G);
+  if (active && g == 0) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      double val = a * s[q];
+      if (Z) val += bz * Z[r + q * ldz];
+      Y[r + q * ldy] = val;
+      if (Y2) Y2[r + q * ldy2] = s[q];
+    }
+  }
+}
+
 void launch_spmv(const DevSpace& s, int64_t ndof, int ncols, const double* A, double a, const double* X,
                  int64_t ldx, double* Y, int64_t ldy, const double* Z, int64_t ldz, double bz, double* Y2,
                  int64_t ldy2, hipStream_t st) {
   int64_t blocks = (ndof * SPMV_G + SPMV_THREADS - 1) / SPMV_THREADS;
+  if (s.col != nullptr) {
+#define RIGA_SPMVC(NC)                                                                                      \
+  hipLaunchKernelGGL(k_spmv_csr<NC>, dim3((unsigned)blocks), dim3(SPMV_THREADS), 0, st, s.col, s.rowptr, ndof, A, a, \
+                     X, ldx, Y, ldy, Z, ldz, bz, Y2, ldy2)
+    switch (ncols) {
+      case 1: RIGA_SPMVC(1); break;
+      case 2: RIGA_SPMVC(2); break;
+      case 3: RIGA_SPMVC(3); break;
+      case 4: RIGA_SPMVC(4); break;
+      case 5: RIGA_SPMVC(5); break;
+      case 6: RIGA_SPMVC(6); break;
+      case 7: RIGA_SPMVC(7); break;
+      default: RIGA_SPMVC(8); break;
+    }
+#undef RIGA_SPMVC
+    return;
+  }
 #define RIGA_SPMV(NC)                                                                              \
   hipLaunchKernelGGL(k_spmv<NC>, dim3((unsigned)blocks), dim3(SPMV_THREADS), 0, st, s.n, s.lo, s.hi, \
                      s.rowptr, ndof, A, a, X, ldx, Y, ldy, Z, ldz, bz, Y2, ldy2)

@@ -15,6 +15,9 @@ struct DevSpace {
   const int* lo; const int* hi;
   const int* first;             // per element
   const int64_t* rowptr;        // CSR row pointers (ndof + 1)
+  // explicit CSR column indices (vector spaces), or null: the scalar space's
+  // columns are implicit in lo / hi (tensor pattern)
+  const int* col;
 };
 
 struct DevTree {
@@ -68,6 +71,12 @@ void launch_assemble(const DevSpace& s, const double* tabM, const double* M1, co
                      double alpha, double beta, const double* c_elem,
                      double* K, double* M, double* C, int64_t ndof, hipStream_t st,
                      const double* S1 = nullptr, double gx = 0.0, double gy = 0.0, double* Ct = nullptr);
+// K, M, C = alpha M + beta K of the H(curl) space (see k_assemble.hip) from
+// the dense 1-D matrices MA (na x na), MB, KB (nb x nb), D (na x nb); rows
+// from base1 on are component 1.
+void launch_assemble_hcurl(int na, int nb, int64_t base1, int64_t ndof, const int64_t* rowptr, const int* col,
+                           const double* MA, const double* MB, const double* KB, const double* D, double alpha,
+                           double beta, double* K, double* M, double* C, hipStream_t st);
 // Bands of every problem of a forest: problem q's tables at taboff[q], its
 // bands at bandoff[q] (max_w: the largest n (2p + 1)).
 void launch_band_1d_b(const DevSpace* spaces, int n, int max_w, const int64_t* taboff, const double* tabM,

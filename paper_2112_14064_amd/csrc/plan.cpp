@@ -15,21 +15,23 @@
 
 namespace riga {
 
-void Space1D::build(int p_, int ne_, int s_) {
+void Space1D::build(int p_, int ne_, int s_, int mult_, bool dirichlet) {
   p = p_; ne = ne_; s = s_;
+  mult = mult_ < 0 ? p : mult_;
+  off = dirichlet ? 1 : 0;
   knots.clear();
   for (int i = 0; i <= p; ++i) knots.push_back(0);
   for (int k = 1; k < ne; ++k) {
-    int mult = (s > 0 && k % s == 0) ? p : 1;
-    for (int r = 0; r < mult; ++r) knots.push_back(k);
+    int m = (s > 0 && k % s == 0) ? mult : 1;
+    for (int r = 0; r < m; ++r) knots.push_back(k);
   }
   for (int i = 0; i <= p; ++i) knots.push_back(ne);
   nall = (int)knots.size() - p - 1;
-  n = nall - 2;
+  n = nall - 2 * off;
   sup0.resize(n); sup1.resize(n);
   for (int d = 0; d < n; ++d) {
-    sup0[d] = knots[d + 1];
-    sup1[d] = knots[d + 1 + p + 1];
+    sup0[d] = knots[d + off];
+    sup1[d] = knots[d + off + p + 1];
   }
   lo.resize(n); hi.resize(n);
   for (int d = 0; d < n; ++d) {
@@ -78,6 +80,13 @@ void Plan::symbolic(std::vector<int64_t>* colcount, int64_t& nnz_l, double& flop
   std::vector<int64_t> parent(nd, -1), anc(nd, -1), cnt(nd, 1), mark(nd, -1);
   auto neighbours = [&](int64_t i, auto&& f) {
     const int64_t d = dof_at[i];
+    if (!col.empty()) {
+      for (int64_t q = rowptr[d]; q < rowptr[d + 1]; ++q) {
+        const int64_t k = elim_pos[col[q]];
+        if (k < i) f(k);
+      }
+      return;
+    }
     const int x = (int)(d % n), y = (int)(d / n);
     for (int jj = sp.lo[y]; jj <= sp.hi[y]; ++jj)
       for (int ii = sp.lo[x]; ii <= sp.hi[x]; ++ii) {
@@ -234,6 +243,97 @@ int Plan::build(int p, int ne, int s, int leaf) {
     }
   nnz = rowptr[ndof];
 
+  return finish(ne, s, leaf,
+                [&](int64_t d, int& x0, int& x1, int& y0, int& y1) {
+                  const int i = (int)(d % n), j = (int)(d / n);
+                  x0 = sp.sup0[i]; x1 = sp.sup1[i]; y0 = sp.sup0[j]; y1 = sp.sup1[j];
+                },
+                [&](int64_t d, auto&& f) {
+                  const int i = (int)(d % n), j = (int)(d / n);
+                  for (int jj = sp.lo[j]; jj <= sp.hi[j]; ++jj)
+                    for (int ii = sp.lo[i]; ii <= sp.hi[i]; ++ii) f((int64_t)jj * n + ii);
+                });
+}
+
+int Plan::build_hcurl(int p, int ne, int s, int leaf, bool pec) {
+  if (p < 2 || p > 8 || ne < 2) return -1;
+  if (s < 0 || (s > 0 && ne % s != 0)) return -1;
+  if (leaf <= 0) leaf = 8;
+  kind = pec ? SPACE_HCURL : SPACE_HCURL_FREE;
+  // component 0: S^{p-1} (x) S^p (eq. HcurlBasis), component 1: S^p (x) S^{p-1};
+  // both degrees carry the hyperplane knots with multiplicity p - 1
+  cx[0].build(p - 1, ne, s, p - 1, false);
+  cy[0].build(p, ne, s, p - 1, pec);
+  cx[1].build(p, ne, s, p - 1, pec);
+  cy[1].build(p - 1, ne, s, p - 1, false);
+  for (int c = 0; c < 2; ++c)
+    if (cx[c].n < 1 || cy[c].n < 1) return -1;
+  cbase[0] = 0;
+  cbase[1] = (int64_t)cx[0].n * cy[0].n;
+  cbase[2] = cbase[1] + (int64_t)cx[1].n * cy[1].n;
+  ndof = cbase[2];
+  n1d = cx[1].n;
+  sp = cx[1];
+  // coupled functions of space b for every function of space a: supports
+  // overlapping on a set of positive length, a contiguous range (supports
+  // ordered by their starts and ends)
+  auto cross = [](const Space1D& a, const Space1D& b, std::vector<int>& lo, std::vector<int>& hi) {
+    lo.assign(a.n, 0);
+    hi.assign(a.n, -1);
+    int k0 = 0;
+    for (int i = 0; i < a.n; ++i) {
+      while (k0 < b.n && b.sup1[k0] <= a.sup0[i]) ++k0;
+      int k1 = k0;
+      while (k1 < b.n && b.sup0[k1] < a.sup1[i]) ++k1;
+      lo[i] = k0;
+      hi[i] = k1 - 1;
+    }
+  };
+  std::vector<int> xlo[2][2], xhi[2][2], ylo[2][2], yhi[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      cross(cx[a], cx[b], xlo[a][b], xhi[a][b]);
+      cross(cy[a], cy[b], ylo[a][b], yhi[a][b]);
+    }
+  auto locate = [&](int64_t d, int& c, int& i, int& j) {
+    c = d >= cbase[1] ? 1 : 0;
+    const int64_t r = d - cbase[c];
+    i = (int)(r % cx[c].n);
+    j = (int)(r / cx[c].n);
+  };
+  rowptr.assign(ndof + 1, 0);
+  for (int64_t d = 0; d < ndof; ++d) {
+    int c, i, j;
+    locate(d, c, i, j);
+    int64_t cnt = 0;
+    for (int b = 0; b < 2; ++b)
+      cnt += (int64_t)std::max(0, xhi[c][b][i] - xlo[c][b][i] + 1) * std::max(0, yhi[c][b][j] - ylo[c][b][j] + 1);
+    rowptr[d + 1] = rowptr[d] + cnt;
+  }
+  nnz = rowptr[ndof];
+  if (nnz > (int64_t)0x7fffffff) return -1;
+  col.assign(nnz, 0);
+  for (int64_t d = 0; d < ndof; ++d) {
+    int c, i, j;
+    locate(d, c, i, j);
+    int64_t q = rowptr[d];
+    for (int b = 0; b < 2; ++b)   // component-major, then y, then x: increasing dof ids
+      for (int jj = ylo[c][b][j]; jj <= yhi[c][b][j]; ++jj)
+        for (int ii = xlo[c][b][i]; ii <= xhi[c][b][i]; ++ii) col[q++] = (int)(cbase[b] + (int64_t)jj * cx[b].n + ii);
+  }
+  return finish(ne, s, leaf,
+                [&](int64_t d, int& x0, int& x1, int& y0, int& y1) {
+                  int c, i, j;
+                  locate(d, c, i, j);
+                  x0 = cx[c].sup0[i]; x1 = cx[c].sup1[i]; y0 = cy[c].sup0[j]; y1 = cy[c].sup1[j];
+                },
+                [&](int64_t d, auto&& f) {
+                  for (int64_t q = rowptr[d]; q < rowptr[d + 1]; ++q) f((int64_t)col[q]);
+                });
+}
+
+template <class Sup, class Nb>
+int Plan::finish(int ne, int s, int leaf, Sup support, Nb neighbours) {
   // --- tree of boxes -------------------------------------------------------
   std::vector<Node> tmp;
   std::function<int(int, int, int, int)> make = [&](int x0, int x1, int y0, int y1) -> int {
@@ -289,21 +389,21 @@ int Plan::build(int p, int ne, int s, int leaf) {
 
   // --- assign dofs -----------------------------------------------------------
   node_of_dof.assign(ndof, -1);
-  for (int j = 0; j < n; ++j)
-    for (int i = 0; i < n; ++i) {
-      int v = root;
-      for (;;) {
-        const Node& nd = nodes[v];
-        if (nd.dir < 0) break;
-        int a0 = nd.dir == 0 ? sp.sup0[i] : sp.sup0[j];
-        int a1 = nd.dir == 0 ? sp.sup1[i] : sp.sup1[j];
-        if (a0 < nd.cut && nd.cut < a1) break;
-        v = (a1 <= nd.cut) ? nd.children[0] : nd.children[1];
-      }
-      int d = j * n + i;
-      node_of_dof[d] = v;
-      nodes[v].own.push_back(d);  // increasing dof id by construction
+  for (int64_t d = 0; d < ndof; ++d) {
+    int x0, x1, y0, y1;
+    support(d, x0, x1, y0, y1);
+    int v = root;
+    for (;;) {
+      const Node& nd = nodes[v];
+      if (nd.dir < 0) break;
+      int a0 = nd.dir == 0 ? x0 : y0;
+      int a1 = nd.dir == 0 ? x1 : y1;
+      if (a0 < nd.cut && nd.cut < a1) break;
+      v = (a1 <= nd.cut) ? nd.children[0] : nd.children[1];
     }
+    node_of_dof[d] = v;
+    nodes[v].own.push_back((int)d);  // increasing dof id by construction
+  }
   amalgamate();
   elim_pos.assign(ndof, -1);
   int64_t pos = 0;
@@ -322,13 +422,11 @@ int Plan::build(int p, int ne, int s, int leaf) {
       for (int g : nodes[c].bnd)
         if (node_of_dof[g] != nd.post && stamp[g] != nd.post) { stamp[g] = nd.post; S.push_back(g); }
     for (int d : nd.own) {
-      int i = d % n, j = d / n;
-      for (int jj = sp.lo[j]; jj <= sp.hi[j]; ++jj)
-        for (int ii = sp.lo[i]; ii <= sp.hi[i]; ++ii) {
-          int g = jj * n + ii;
-          int w = node_of_dof[g];
-          if (w != nd.post && is_anc(w) && stamp[g] != nd.post) { stamp[g] = nd.post; S.push_back(g); }
-        }
+      neighbours((int64_t)d, [&](int64_t g64) {
+        const int g = (int)g64;
+        int w = node_of_dof[g];
+        if (w != nd.post && is_anc(w) && stamp[g] != nd.post) { stamp[g] = nd.post; S.push_back(g); }
+      });
     }
     std::sort(S.begin(), S.end(), [&](int a, int b) { return elim_pos[a] < elim_pos[b]; });
     nd.bnd = std::move(S);

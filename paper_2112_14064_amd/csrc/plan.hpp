@@ -22,14 +22,20 @@ namespace riga {
 // element boundary (rIGA with C^0 hyperplanes, Sec. 3.3).
 struct Space1D {
   int p = 0, ne = 0, s = 0;
+  int mult = 0;                // knot multiplicity at the hyperplanes
+  int off = 1;                 // full index of function 0 (1: the end functions are removed)
   std::vector<int> knots;      // element-boundary indices 0..ne
   int nall = 0;                // functions before boundary elimination
-  int n = 0;                   // Dirichlet functions: full indices 1..nall-2
-  std::vector<int> sup0, sup1; // support [sup0, sup1) in elements, per Dirichlet function
-  std::vector<int> lo, hi;     // coupled Dirichlet functions form the range [lo, hi]
+  int n = 0;                   // functions kept: full indices off .. off + n - 1
+  std::vector<int> sup0, sup1; // support [sup0, sup1) in elements, per kept function
+  std::vector<int> lo, hi;     // coupled kept functions form the range [lo, hi]
   std::vector<int> first;      // per element: full index of its first nonzero function
-  void build(int p_, int ne_, int s_);
+  // mult_ < 0: p (C^0 hyperplanes); dirichlet: remove the first and last function
+  void build(int p_, int ne_, int s_, int mult_ = -1, bool dirichlet = true);
 };
+
+// Kinds of discrete space (riga_mesh.space).
+enum SpaceKind { SPACE_H1 = 0, SPACE_HCURL = 1, SPACE_HCURL_FREE = 2 };
 
 struct Node {
   int x0, x1, y0, y1;          // box in element units
@@ -44,9 +50,16 @@ struct Node {
 };
 
 struct Plan {
-  Space1D sp;                  // identical in x and y
+  Space1D sp;                  // identical in x and y (scalar space)
   int64_t n1d = 0, ndof = 0, nnz = 0;
   std::vector<int64_t> rowptr; // CSR row pointers of the tensor sparsity
+  // Vector space (H(curl), Sec. 3.2 eq. HcurlBasis / Sec. 3.3): component c
+  // has the tensor space cx[c] (x) cy[c], its dofs at cbase[c] + j n_x + i;
+  // the CSR column indices are explicit (col).  Empty for the scalar space.
+  int kind = SPACE_H1;
+  Space1D cx[2], cy[2];
+  int64_t cbase[3] = {0, 0, 0};
+  std::vector<int> col;
   std::vector<Node> nodes;     // in postorder
   int height = 0;
   std::vector<int> level_nodes;    // node ids grouped by height
@@ -74,6 +87,12 @@ struct Plan {
   int amalg_group = RIGA_AMALG_GROUP, amalg_max = RIGA_AMALG_MAX, amalg_own = RIGA_AMALG_OWN;
 
   int build(int p, int ne, int s, int leaf);  // 0 ok, <0 invalid
+  // H(curl) space S^{p-1,p} x S^{p,p-1} (eq. HcurlBasis), rIGA hyperplanes of
+  // multiplicity p-1 (C^1 in degree p, C^0 in degree p-1; eq.
+  // DiscreteSpacesrIGA), every s elements; pec: tangential components vanish
+  // on the boundary (the degree-p factor loses its end functions), else no
+  // boundary condition.  p >= 2.
+  int build_hcurl(int p, int ne, int s, int leaf, bool pec);
 
   // Symbolic Cholesky of the tensor sparsity under the elimination order of
   // the plan (no dense-front zeros): per elimination position the nonzeros of
@@ -96,6 +115,10 @@ struct Plan {
 
  private:
   void amalgamate();
+  // Tree, dof assignment, amalgamation, boundary sets and frontal data, given
+  // ndof, rowptr and the dofs' supports and neighbours.
+  template <class Sup, class Nb>
+  int finish(int ne, int s, int leaf, Sup support, Nb neighbours);
 };
 
 }  // namespace riga

@@ -45,6 +45,9 @@ struct riga_problem {
   // Gyroscopic damping (C = alpha M + beta K + G, G skew): element tables and
   // band of int B_i B_j', the values of C^T on C's pattern, and the second
   // triangle of every nonsymmetric front (front, update, factor, inverses).
+  // H(curl) space: dense 1-D matrices of the degree-(p-1) space A and the
+  // degree-p space B (MA, MB, KB, D = int A_a B_b')
+  double *d_hMA = nullptr, *d_hMB = nullptr, *d_hKB = nullptr, *d_hD = nullptr;
   bool gyro = false;
   double gx = 0.0, gy = 0.0;
   double *d_tabS = nullptr, *d_S1 = nullptr, *d_Ct = nullptr;
@@ -218,6 +221,12 @@ int finish_pairs(riga_problem* h, const riga::KsCycle& cyc, int nev, double* dsm
 riga_status eigs_toar(riga_problem* h, const riga_options* opt, int nev, int b, int m, int maxit, double tol,
                       double* lam, double* X, double* eta, int* nconv, bool* fallback);
 int small_chol(int b, const std::vector<double>& G, std::vector<double>& R, double rel);
+// Dense 1-D matrices of the H(curl) space (see hcurl.cpp).
+void hcurl_1d(const riga::Space1D& A, const riga::Space1D& B, std::vector<double>& MA, std::vector<double>& MB,
+              std::vector<double>& KB, std::vector<double>& D);
+// M X for nq columns (ld N): the sum-factorised product on the scalar space,
+// the sparse product with explicit columns on a vector space.
+void mass_product(riga_problem* h, int nq, const double* X, double* Y);
 // Autotune the per-level sweep shapes of a factored handle (see riga_autotune).
 void autotune_sweeps(riga_problem* h, int nrhs, int reps, double* before_ms, double* after_ms);
 std::vector<double> upper_inverse(int b, const std::vector<double>& R);

@@ -26,10 +26,11 @@ RIGA_WARN_NOT_CONVERGED = 1
 RIGA_WARN_IR_STAGNATED = 2
 RIGA_IR_MAX = 10
 RIGA_EIGS_TOAR = 4   # riga_options.flags: compact two-level Krylov basis
+RIGA_SPACE_H1, RIGA_SPACE_HCURL, RIGA_SPACE_HCURL_FREE = 0, 1, 2   # riga_mesh.space
 
 
 class riga_mesh(C.Structure):
-    _fields_ = [("p", C.c_int), ("ne", C.c_int), ("hyper_every", C.c_int), ("leaf", C.c_int)]
+    _fields_ = [("p", C.c_int), ("ne", C.c_int), ("hyper_every", C.c_int), ("leaf", C.c_int), ("space", C.c_int)]
 
 
 class riga_damping(C.Structure):
@@ -148,12 +149,12 @@ def _stats_dict(s) -> dict:
     return out
 
 
-def riga_symbolic(p: int, ne: int, hyper_every: int, leaf: int = 0):
+def riga_symbolic(p: int, ne: int, hyper_every: int, leaf: int = 0, space: int = 0):
     """Host-only symbolic Cholesky of Q's sparsity under the library's
     elimination order: (order, colcount, nnz_l, flops), order[k] the dof
     eliminated k-th and colcount[k] the nonzeros of column k of L."""
     lib = load()
-    mesh = riga_mesh(p, ne, hyper_every, leaf)
+    mesh = riga_mesh(p, ne, hyper_every, leaf, space)
     n = C.c_int64(0)
     _check(lib.riga_symbolic(C.byref(mesh), C.byref(n), None, None, None, None), "riga_symbolic")
     order = np.zeros(n.value, dtype=np.int64)
@@ -216,7 +217,8 @@ def riga_selftest_schur_restart(a: np.ndarray, nkeep: int):
 class Problem:
     """One discretised QEP on one device (owns a riga_problem handle)."""
 
-    def __init__(self, p: int, ne: int, hyper_every: int, leaf: int = 0, device: int = 0, stream=None):
+    def __init__(self, p: int, ne: int, hyper_every: int, leaf: int = 0, device: int = 0, stream=None,
+                 space: int = 0):
         import torch
 
         self.torch = torch
@@ -226,8 +228,8 @@ class Problem:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
         self.h = C.c_void_p()
-        mesh = riga_mesh(p, ne, hyper_every, leaf)
-        self.p, self.ne, self.hyper_every = p, ne, hyper_every
+        mesh = riga_mesh(p, ne, hyper_every, leaf, space)
+        self.p, self.ne, self.hyper_every, self.space = p, ne, hyper_every, space
         _check(self.lib.riga_create(C.byref(self.h), C.byref(mesh), device, C.c_void_p(stream.cuda_stream)),
                "riga_create")
         self._c_elem = None
@@ -444,7 +446,7 @@ class Batch:
         arr = (riga_mesh * self.n)()
         for i, m in enumerate(meshes):
             m = tuple(m) + (0,) * (4 - len(m))
-            arr[i] = riga_mesh(*[int(x) for x in m[:4]])
+            arr[i] = riga_mesh(*[int(x) for x in m[:4]], 0)
         self.meshes = [tuple(m) for m in meshes]
         self.h = C.c_void_p()
         _check(self.lib.riga_batch_create(C.byref(self.h), self.n, C.cast(arr, C.c_void_p), device,
