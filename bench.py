@@ -20,10 +20,14 @@ The undamped case (C = 0: all eigenvalues of K u = mu M u in an interval by
 spectrum slicing) on the same mesh, rIGA and IGA, is reported last, and the
 headline step with the Krylov basis in compact two-level (TOAR) form beside
 the full basis, and the headline mesh with a gyroscopic (skew) part in the
-damping, factored by LU.
+damping, factored by LU.  The curl-conforming vector space (p=3, 256^2, perfect
+conductor) closes the run: factorization, FB elimination and Maxwell spectrum
+slicing, rIGA against IGA.  `--flop-table` prints the host-side symbolic cost
+ratios of that space for p = 3..6 (the quantities of tab:FlopTest) and exits.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-iga] [--no-mixed] [--no-batch]
-                       [--no-undamped] [--no-toar] [--no-gyro] [--basis full|toar]
+                       [--no-undamped] [--no-toar] [--no-gyro] [--no-hcurl] [--basis full|toar]
+                       [--flop-table]
 """
 from __future__ import annotations
 
@@ -379,6 +383,102 @@ def oracle_check_undamped(mus):
     return res
 
 
+def vector_space_form(torch, riga, W, reps=10):
+    """The curl-conforming space (p=3, 256x256, perfect conductor), rIGA and
+    IGA: the conductive form C = 0.05 M + 0.005 K factored at sigma=2 (one
+    warm-up and one timed factorization; GFLOP/s from the symbolic count of
+    the elimination order used), the solve of two right-hand sides (FB
+    elimination, mean of `reps`), and the Maxwell form K u = mu M u with
+    every eigenvalue in [1, 150) by spectrum slicing.  The cost ratios IGA /
+    rIGA are the quantities of tab:FlopTest measured on the device."""
+    out, mus = {}, {}
+    for s in (16, 0):
+        P = W.cfg_hcurl(s)
+        space = P.extra["space"]
+        a, b = P.extra["interval"]
+        pr = riga.Problem(P.p, P.ne, P.hyper_every, space=space)
+        info = pr.info
+        pr.assemble(P.alpha, P.beta)
+        pr.factor(P.sigma)
+        pr.factor(P.sigma)
+        t_fac = pr.stats()["t_factor_ms"]
+        rhs = torch.randn((2, pr.ndof), dtype=torch.float64, device="cuda")
+        pr.solve_q(rhs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            pr.solve_q(rhs)
+        torch.cuda.synchronize()
+        t_fb = (time.perf_counter() - t0) * 1e3 / reps
+        pr.assemble(0.0, 0.0)
+        pr.gep_slice(a, b, max_slice=P.extra["max_slice"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mu, U, eta, count, st, stats = pr.gep_slice(a, b, max_slice=P.extra["max_slice"])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        good = int(sum(1 for e in eta if e <= 1e-10))
+        k = "riga" if s else "iga"
+        out[k] = {
+            "workload": f"H(curl) p={P.p}, {P.ne}x{P.ne}, perfect conductor, " +
+                        (f"rIGA s={s}" if s else "IGA"),
+            "ndof": int(pr.ndof), "nnz": int(pr.nnz), "max_front": int(info["max_front"]),
+            "factor_gflop_algorithmic": info["factor_flops"] / 1e9, "factor_ms": t_fac,
+            "factor_gflops": info["factor_flops"] / (t_fac * 1e-3) / 1e9,
+            "solve_2rhs_ms": t_fb, "solve_factor_mb": info["solve_bytes"] / 1e6,
+            "maxwell": {"interval": [a, b], "count": int(count), "found": int(len(mu)), "status": int(st),
+                        "ms": ms, "eigenpairs_per_s": good * 1e3 / ms, "pairs_ok": good,
+                        "max_eta": float(max(eta)) if len(eta) else None, **stats},
+        }
+        mus[k] = (P, mu)
+        pr.close()
+    r, i = out["riga"], out["iga"]
+    out["iga_over_riga"] = {
+        "factor_flops": i["factor_gflop_algorithmic"] / r["factor_gflop_algorithmic"],
+        "factor_time": i["factor_ms"] / r["factor_ms"],
+        "fb_bytes": i["solve_factor_mb"] / r["solve_factor_mb"],
+        "fb_time": i["solve_2rhs_ms"] / r["solve_2rhs_ms"],
+        "mat_vec_nnz": i["nnz"] / r["nnz"], "vec_vec_ndof": i["ndof"] / r["ndof"],
+        "maxwell_time": i["maxwell"]["ms"] / r["maxwell"]["ms"],
+    }
+    return out, mus
+
+
+def flop_table(riga, nes=(256, 1024), degrees=(3, 4, 5, 6)):
+    """Host-only analog of tab:FlopTest for the curl-conforming space with the
+    perfect-conductor condition: symbolic factorization flops and nnz(L) of
+    the library's elimination order, IGA over rIGA (16 x 16 macroelements),
+    and the matrix and vector size ratios."""
+    rows = []
+    for ne in nes:
+        for p in degrees:
+            c = {}
+            for s in (16, 0):
+                order, cc, nz, fl = riga.riga_symbolic(p, ne, s, space=riga.RIGA_SPACE_HCURL)
+                c[s] = (len(order), int(nz), fl)
+            rows.append({"p": p, "ne": ne, "ndof_riga": c[16][0], "ndof_iga": c[0][0],
+                         "factorization": c[0][2] / c[16][2], "fb_elimination": c[0][1] / c[16][1],
+                         "vec_vec": c[0][0] / c[16][0]})
+            print(json.dumps(rows[-1]), flush=True)
+    return rows
+
+
+def oracle_check_hcurl(mus):
+    """Count and eigenvalues of the Maxwell slices of the vector-space leg
+    against the oracle's closed form (sums of 1-D values)."""
+    import numpy as np
+
+    from oracle import hcurl as ohc
+
+    res = {}
+    for k, (P, mu) in mus.items():
+        a, b = P.extra["interval"]
+        ref = ohc.maxwell_closed(P.p, P.ne, P.hyper_every, True, a, b)
+        rel = float(np.max(np.abs(mu - ref) / np.abs(ref))) if len(ref) == len(mu) and len(mu) else None
+        res[k] = (len(ref), rel)
+    return res
+
+
 def cpu_baseline(P, lam_gpu):
     """The oracle as it stands: SciPy sparse LU of Q(sigma) + ARPACK on the
     shift-and-invert operator, same workload (full solve, ~30 s)."""
@@ -431,6 +531,10 @@ def main():
     ap.add_argument("--no-undamped", action="store_true")
     ap.add_argument("--no-toar", action="store_true")
     ap.add_argument("--no-gyro", action="store_true")
+    ap.add_argument("--no-hcurl", action="store_true")
+    ap.add_argument("--flop-table", action="store_true",
+                    help="only print the host-side symbolic cost ratios IGA / rIGA of the curl-conforming space "
+                         "(p = 3..6, 256^2 and 1024^2 elements) and exit")
     ap.add_argument("--basis", choices=("full", "toar"), default="full",
                     help="Krylov basis of the timed headline steps: the full 2N-long basis (default) or the "
                          "compact two-level form")
@@ -447,6 +551,10 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(torch)
+        return
+    if args.flop_table:
+        from paper_2112_14064_amd import riga
+        flop_table(riga)
         return
 
     from paper_2112_14064_amd import riga
@@ -503,6 +611,9 @@ def main():
     mus = None
     if not args.no_undamped:
         out["undamped_form"], mus = undamped_form(torch, riga, W)
+    hc = None
+    if not args.no_hcurl:
+        out["vector_space_form"], hc = vector_space_form(torch, riga, W)
     if roof is not None:
         out["roofline"] = roof
     if not args.no_cpu:
@@ -526,6 +637,10 @@ def main():
             for k, (n_ref, rel) in oracle_check_undamped(mus).items():
                 out["undamped_form"][k]["oracle_count"] = n_ref
                 out["undamped_form"][k]["max_rel_err_vs_oracle"] = rel
+        if hc is not None:
+            for k, (n_ref, rel) in oracle_check_hcurl(hc).items():
+                out["vector_space_form"][k]["maxwell"]["oracle_count"] = n_ref
+                out["vector_space_form"][k]["maxwell"]["max_rel_err_vs_oracle"] = rel
     print(json.dumps(out))
 
 

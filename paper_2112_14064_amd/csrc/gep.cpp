@@ -178,6 +178,16 @@ int solve_slice(riga_problem* h, double s, double lo, double hi, int want, int r
     order.resize(m);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return std::abs(theta[a]) > std::abs(theta[c]); });
+    // On a curl-conforming space the gradients form the eigenvalue mu = 0 of
+    // huge multiplicity (theta = -1/s).  No slice contains it, yet from a
+    // shift s below the next eigenvalue's distance its |theta| ranks among
+    // the values asked for beyond the slice's own; its Ritz values, which
+    // rounding keeps replenishing, go last: they are neither waited for nor
+    // kept at a restart (the cluster rule would keep them all and leave one
+    // block step per restart).
+    if (h->plan.kind != riga::SPACE_H1)
+      std::stable_partition(order.begin(), order.end(),
+                            [&](int j) { return std::abs(s + 1.0 / theta[j]) > 1e-6 * std::abs(s); });
     // residual estimates ||E y|| with E = H[m:m+b, m-b:m]
     auto resid = [&](int j) {
       double r2 = 0.0;
@@ -367,9 +377,12 @@ riga_status riga_gep_slice(riga_problem* h, double a, double b, int max_slice, c
     // bisect until every slice holds at most max_slice eigenvalues.  A vector
     // space's pencil has the gradients as a null space of huge multiplicity:
     // seen from the midpoint s of a slice [l, r) they are the value
-    // theta = -1/s, against |theta| >= 2/(r - l) for the slice's own values,
-    // so its slices are also halved until r - l <= l / 2 (the null cluster
-    // then stays below a fifth of every wanted |theta|)
+    // theta = -1/s, against |theta| >= 2/(r - l) for the slice's own values.
+    // The slice solver sets converged null Ritz values aside, but Ritz values
+    // that still mix the null space with the slice's vectors would compete
+    // with its smallest |theta|; its slices are therefore also halved until
+    // r - l <= l / 2 (the null cluster then stays below a fifth of every
+    // wanted |theta|)
     const double rho = h->plan.kind != riga::SPACE_H1 ? 0.5 : 0.0;
     std::vector<Slice> todo{{lo, hi, nlo, nhi}}, done;
     while (!todo.empty()) {

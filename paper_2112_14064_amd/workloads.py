@@ -140,3 +140,15 @@ def fd_elements(ne: int, count: int = 32, seed: int = 2) -> np.ndarray:
     rng = np.random.default_rng(seed)
     rng.lognormal(-3.0, 0.5, size=(ne, ne))  # same stream position as the field draw
     return rng.choice(ne * ne, size=count, replace=False)
+
+
+def cfg_hcurl(hyper_every: int = 16) -> Problem:
+    """The curl-conforming space S^{2,3} x S^{3,2} (p=3) on 256x256 with the
+    perfect-conductor condition, rIGA (C^1/C^0 hyperplanes every 16 elements,
+    148,512 dofs) or IGA (hyper_every=0, 132,612 dofs): the conductive form
+    C = 0.05 M + 0.005 K factored at sigma=2 and solved with two right-hand
+    sides, and the non-conductive (Maxwell) form K u = mu M u with every
+    eigenvalue in [1, 150) by spectrum slicing, at most 40 per slice."""
+    tag = f"s{hyper_every}" if hyper_every else "iga"
+    return Problem(p=3, ne=256, hyper_every=hyper_every, alpha=0.05, beta=0.005, sigma=2.0,
+                   name=f"p3_256x256_{tag}_hcurl", extra={"space": 1, "interval": (1.0, 150.0), "max_slice": 40})
