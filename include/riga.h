@@ -469,7 +469,9 @@ riga_status riga_factor_gep(riga_problem* h, double shift, int64_t* neg_count, i
  *      (opt->block, 0: 2; opt->tol, opt->maxit, opt->seed as for riga_eigs;
  *      opt->nev, opt->m and opt->keep are chosen per slice: the k + 2 values of
  *      theta = 1/(mu - s) of largest modulus, subspace max(2 (k + 2), 20)); the
- *      converged values with mu in [l, r) are returned.
+ *      converged values with mu in [l, r) are returned.  On a vector space
+ *      Ritz values with |mu| <= 1e-6 |s| (the null space) are neither counted
+ *      among the k + 2 nor kept at restarts.
  *   cap    room (pairs) in mu / U / resid; count > cap gives RIGA_ERR_INVALID_ARG
  *          with *count written.
  *   mu     host, cap doubles: the eigenvalues, ascending: with U, the Rayleigh
