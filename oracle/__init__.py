@@ -29,4 +29,7 @@ Modules
     gyro      damping with a skew-symmetric (gyroscopic) part G_ab = int B_a (g . grad B_b):
               element assembly, the 1-D skew matrix, eigenvalues from the 1-D QEPs
               of the y-modes (gy = 0)
+    cshift    a complex target shift: the eigenvalues of largest |psi| for the real
+              part of the shift-and-invert operator (closed forms on the scalar and
+              curl-conforming spaces, ARPACK's real-part mode)
 """
