@@ -83,10 +83,12 @@ typedef enum {
  *                condition (the matrices of fig. MatPatterns).  Vector spaces
  *                need p >= 2 and are assembled with K = int rot u rot v,
  *                M = int u . v (rot u = du_y/dx - du_x/dy), C = alpha M +
- *                beta K; they support riga_factor, the solves and the
- *                undamped case (riga_factor_gep, riga_gep_slice), not
- *                riga_eigs, riga_apply_op, riga_factor_mixed, an element
- *                damping field, a gyroscopic part, the adjoint or a forest. */
+ *                beta K; they support riga_factor, the solves, the
+ *                undamped case (riga_factor_gep, riga_gep_slice) and
+ *                riga_eigs at a complex target (riga_factor_complex), not
+ *                riga_eigs at a real shift, riga_apply_op, riga_factor_mixed,
+ *                an element damping field, a gyroscopic part, the adjoint
+ *                or a forest. */
 typedef struct {
   int p, ne, hyper_every, leaf;
   int space;
@@ -264,6 +266,43 @@ riga_status riga_export_csr(riga_problem* h, int which, int64_t* rowptr, int32_t
  * failed, else -1.                                                           */
 riga_status riga_factor(riga_problem* h, double sigma, int64_t* bad_pivot);
 
+/* A complex target sigma = sigma_re + i sigma_im (sigma_im > 0) inside the
+ * complex spectrum region of interest (the target shift of Alg. 2, Sec. 4.1.1
+ * with a complex shift).  Q(sigma) = R + iJ with R = (a^2 - b^2) M + a C + K,
+ * J = b (2a M + C) (a = sigma_re, b = sigma_im) is factored in the real form
+ * of -i Q(sigma) = J - iR on two unknowns per dof,
+ *   [[J, R], [-R, J]]  (dof d: unknowns 2d = Re, 2d + 1 = Im),
+ * by Gaussian elimination without pivoting on the same nested-dissection tree
+ * (each front holds a dof's two unknowns together; the LU fronts of
+ * riga_assemble_gyroscopic).  Its symmetric part is J (x) I, so the pivots are
+ * positive when J is positive definite: C symmetric positive semidefinite
+ * and 2a M + C positive definite (e.g. a >= 0 with alpha > 0).  Requires a
+ * symmetric damping (riga_assemble), one problem (not a forest); any space,
+ * including the curl-conforming ones, whose QEP riga_eigs then solves.
+ * Afterwards riga_eigs runs on the real part of the shift-and-invert operator
+ * (Parlett and Saad's real-part operator), Re S(sigma) = (S(sigma) +
+ * S(conj sigma)) / 2, whose eigenvectors are the pencil's with the values
+ *   psi(lam) = (1/(lam - sigma) + 1/(lam - conj sigma)) / 2,
+ * and returns the nev eigenvalues of largest |psi| (near sigma or conj sigma,
+ * in conjugate pairs); each is the root of u^T Q(lam) u = 0 whose psi is
+ * nearest the Ritz value.  An eigenvalue on the circle |lam - a| = b has a
+ * real psi shared with its conjugate and is resolved only as a pair.
+ * Not with RIGA_EIGS_TOAR, riga_solve_q, riga_apply_op or riga_adjoint
+ * (RIGA_ERR_INVALID_ARG / RIGA_ERR_STATE); riga_solve_q_complex solves with the
+ * complex factor.  The second factor (four times the entries of a real
+ * Cholesky factor of the space, two triangles) and its workspace are
+ * allocated at the first call and kept.  On RIGA_ERR_NOT_SPD, *bad_pivot
+ * receives the dof of the failed pivot.  Synchronises.  riga_assemble,
+ * riga_factor and riga_factor_gep end the complex mode.                     */
+riga_status riga_factor_complex(riga_problem* h, double sigma_re, double sigma_im, int64_t* bad_pivot);
+
+/* Q(sigma) x = b with the complex factor of riga_factor_complex.
+ *   b, x: device, ndof x nrhs complex, interleaved (re, im), column-major
+ *         (column stride 2 ndof doubles); nrhs >= 1; x must not alias b.
+ * RIGA_ERR_STATE without a complex factor.  Asynchronous on the handle's
+ * stream.                                                                   */
+riga_status riga_solve_q_complex(riga_problem* h, int nrhs, const double* b, double* x);
+
 /* Largest number of refinement sweeps per solve of a mixed factor.          */
 #define RIGA_IR_MAX 10
 
@@ -332,7 +371,10 @@ riga_status riga_solve_q_noalloc(riga_problem* h, int nrhs, const double* b, dou
 riga_status riga_apply_op(riga_problem* h, int nvec, const double* v, double* r);
 
 /* The nev eigenpairs of the QEP nearest sigma (Alg. 2): block Krylov-Schur on
- * the shift-and-invert operator with B-orthogonal (CGS2) bases.
+ * the shift-and-invert operator with B-orthogonal (CGS2) bases.  After
+ * riga_factor_complex: the nev of largest |psi| on the real part of the
+ * operator, in psi order (decreasing |psi|, ties by decreasing Im, then Re);
+ * on a vector space only then.
  * With opt->flags & RIGA_EIGS_TOAR the basis is kept in the compact two-level
  * form V = [U Q1; U Q2] of the second-order Arnoldi methods (SOAR, cited in
  * Sec. 4.2.1): the lower block of the operator's image is sigma r_u + v_u

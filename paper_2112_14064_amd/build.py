@@ -16,7 +16,7 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libriga.so")
 
 SOURCES = ["plan.cpp", "sweep_plan.cpp", "small_eig.cpp", "ks_host.cpp", "api.cpp", "toar.cpp", "hcurl.cpp", "k_assemble.hip", "k_factor.hip", "k_solve.hip",
-           "k_krylov.hip", "k_toar.hip", "k_batch.hip", "batch.cpp", "noalloc.hip", "gep.cpp"]
+           "k_krylov.hip", "k_toar.hip", "k_cshift.hip", "k_batch.hip", "batch.cpp", "noalloc.hip", "gep.cpp"]
 
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

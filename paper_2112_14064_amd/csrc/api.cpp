@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -170,6 +171,21 @@ void solve_levels(riga_problem* h, int nrhs, const double* b, int64_t ldb, doubl
 void apply_block(riga_problem* h, int nb, const double* vu, const double* wl, int64_t ld,
                  double* ru, double* rl, double* t) {
   const int64_t N = h->N();
+  if (h->cmode) {
+    // the real part of the operator at sigma = a + ib: t = (a M + C) v_u + M v_l
+    // + i b M v_u, x = -Q(sigma)^{-1} t by the real form on the second
+    // handle (same stream), r_u = Re x, r_l = Re(sigma x) + v_u
+    riga_problem* sh = h->cshadow;
+    sh->st = h->st;
+    double* MX = h->d_cw;
+    double* CW = h->d_cw + (size_t)4 * N;
+    riga::launch_spmv(h->ds, N, nb, h->d_M, 1.0, vu, ld, MX, N, nullptr, 0, 0.0, nullptr, 0, h->st);
+    riga::launch_spmv(h->ds, N, nb, h->d_C, 1.0, vu, ld, CW, N, wl, ld, 1.0, nullptr, 0, h->st);
+    riga::launch_cshift_rhs(N, nb, MX, CW, N, h->sigma, h->csig_im, h->d_cb, 2 * N, h->st);
+    solve_levels(sh, nb, h->d_cb, 2 * N, h->d_cx, 2 * N, nullptr, nullptr, 0, 0.0);
+    riga::launch_cshift_out(N, nb, h->d_cx, 2 * N, h->sigma, h->csig_im, vu, ld, ru, rl, N, h->st);
+    return;
+  }
   if (h->c_elem == nullptr && !h->gyro)   // sigma M + C = (sigma + alpha) M + beta K: sum factorisation
     riga::launch_tensor_mk(h->ds, h->d_M1, h->d_K1, nb, h->sigma + h->alpha, h->beta, vu, ld, t, N, wl, ld, 1.0,
                            h->st);
@@ -289,9 +305,11 @@ void setup_device(riga_problem* h) {
     h->ds.col = nullptr;
     if (P.kind != riga::SPACE_H1) {
       h->ds.col = h->upload(P.col);
-      std::vector<double> MA, MB, KB, D;
-      hcurl_1d(P.cx[0], P.cy[0], MA, MB, KB, D);   // A = S^{p-1} (x of component 0), B = S^p
-      h->d_hMA = h->upload(MA); h->d_hMB = h->upload(MB); h->d_hKB = h->upload(KB); h->d_hD = h->upload(D);
+      if (P.kind == riga::SPACE_HCURL || P.kind == riga::SPACE_HCURL_FREE) {
+        std::vector<double> MA, MB, KB, D;
+        hcurl_1d(P.cx[0], P.cy[0], MA, MB, KB, D);   // A = S^{p-1} (x of component 0), B = S^p
+        h->d_hMA = h->upload(MA); h->d_hMB = h->upload(MB); h->d_hKB = h->upload(KB); h->d_hD = h->upload(D);
+      }
     }
     h->dt.nf = h->upload(P.nf); h->dt.no = h->upload(P.no); h->dt.nb = h->upload(P.nb);
     h->dt.loff = h->upload(P.loff); h->dt.uoff = h->upload(P.uoff);
@@ -363,6 +381,58 @@ void setup_device(riga_problem* h) {
     ck(hipStreamCreateWithFlags(&h->own_st, hipStreamNonBlocking));
 }
 
+
+// psi(lam) = (1/(lam - sigma) + 1/(lam - conj sigma)) / 2 for sigma = a + ib:
+// the eigenvalue of the real part of the shift-and-invert operator.
+cplx cshift_psi(cplx lam, double a, double b) {
+  const cplx w = lam - a;
+  return w / (w * w + b * b);
+}
+
+// Order by decreasing |psi|; values whose |psi| agree to 1e-9 relative form a
+// cluster (a conjugate pair), ordered by decreasing Im, then increasing Re.
+std::vector<int> psi_order(const std::vector<cplx>& lam, double a, double b) {
+  std::vector<double> g(lam.size());
+  for (size_t k = 0; k < lam.size(); ++k) g[k] = std::abs(cshift_psi(lam[k], a, b));
+  std::vector<int> idx(lam.size());
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return g[x] > g[y]; });
+  std::vector<int> out;
+  size_t i = 0;
+  while (i < idx.size()) {
+    const double g0 = g[idx[i]];
+    size_t j = i + 1;
+    while (j < idx.size() && g0 - g[idx[j]] <= 1e-9 * g0) ++j;
+    std::vector<int> grp(idx.begin() + i, idx.begin() + j);
+    std::stable_sort(grp.begin(), grp.end(), [&](int x, int y) {
+      if (lam[x].imag() != lam[y].imag()) return lam[x].imag() > lam[y].imag();
+      return lam[x].real() < lam[y].real();
+    });
+    out.insert(out.end(), grp.begin(), grp.end());
+    i = j;
+  }
+  return out;
+}
+
+// The eigenvalue of a Ritz pair of the real part of the operator: of the two
+// roots of u^T Q(lam) u = 0 the one whose psi is nearest the Ritz value (the
+// other is, for a mode of the symmetric pencil, the conjugate, whose psi is
+// the conjugate Ritz value).
+cplx cshift_polish(const PairForms& pf, cplx theta, double a, double b) {
+  const cplx disc = std::sqrt(pf.qc * pf.qc - 4.0 * pf.qm * pf.qk);
+  const cplx r1 = (-pf.qc + disc) / (2.0 * pf.qm), r2 = (-pf.qc - disc) / (2.0 * pf.qm);
+  const bool ok1 = std::isfinite(r1.real()) && std::isfinite(r1.imag());
+  const bool ok2 = std::isfinite(r2.real()) && std::isfinite(r2.imag());
+  if (!ok1 && !ok2) {
+    // no quadratic: invert psi on the branch |lam - a| >= b
+    const cplx sq = std::sqrt(1.0 - 4.0 * theta * theta * b * b);
+    return a + (1.0 + sq) / (2.0 * theta);
+  }
+  if (!ok2) return r1;
+  if (!ok1) return r2;
+  return std::abs(cshift_psi(r1, a, b) - theta) <= std::abs(cshift_psi(r2, a, b) - theta) ? r1 : r2;
+}
+
 }  // namespace detail
 }  // namespace riga
 
@@ -418,6 +488,12 @@ riga_status riga_create(riga_problem** out, const riga_mesh* mesh, int device, v
 
 void riga_destroy(riga_problem* h) {
   if (!h) return;
+  if (h->cshadow) {
+    riga_problem* sh = h->cshadow;
+    h->cshadow = nullptr;
+    sh->st = nullptr;   // h's stream: h synchronises it below
+    riga_destroy(sh);
+  }
   hipSetDevice(h->device);
   if (h->st) hipStreamSynchronize(h->st); else hipDeviceSynchronize();
   if (h->own_st) hipStreamSynchronize(h->own_st);
@@ -499,6 +575,7 @@ riga_status assemble_impl(riga_problem* h, const riga_damping* damping, double g
       h->clear_graphs();
       h->assembled = true;
       h->factored = false;
+      h->cmode = false;
       h->norms[0] = h->norms[1] = h->norms[2] = -1;
       h->stats.flops[RIGA_PHASE_ASSEMBLE] = 0.0;
       h->stats.bytes[RIGA_PHASE_ASSEMBLE] = 24.0 * (double)P.nnz;
@@ -530,6 +607,7 @@ riga_status assemble_impl(riga_problem* h, const riga_damping* damping, double g
     h->clear_graphs();   // captured block steps hold the old operator coefficients
     h->assembled = true;
     h->factored = false;
+    h->cmode = false;
     h->norms[0] = h->norms[1] = h->norms[2] = -1;
     h->stats.flops[RIGA_PHASE_ASSEMBLE] = 0.0;   // a lower-order term of eq. Cost
     h->stats.bytes[RIGA_PHASE_ASSEMBLE] =
@@ -609,6 +687,7 @@ riga_status factor_all(riga_problem* h, double sigma, int64_t* bad_pivot) {
   const riga::Plan& P = h->plan;
   h->dt.sgn = nullptr;
   h->gep = false;
+  h->cmode = false;
   ck(hipMemsetAsync(h->d_status, 0xFF, sizeof(int64_t), h->st));
   ck(hipEventRecord(h->ev0, h->st));
   for (int lv = 0; lv < P.height; ++lv) factor_level(h, lv, sigma * sigma, sigma);
@@ -655,6 +734,7 @@ riga_status factor_gep_all(riga_problem* h, double shift, int64_t* bad_pivot, in
   h->clear_graphs();
   h->mixed = false;
   h->factored = false;
+  h->cmode = false;
   if (h->d_sgn == nullptr) h->d_sgn = h->dalloc<double>((size_t)h->N());
   h->dt.sgn = h->d_sgn;
   h->gep = true;
@@ -813,6 +893,99 @@ riga_status riga_factor(riga_problem* h, double sigma, int64_t* bad_pivot) {
     h->clear_graphs();
     h->mixed = false;
     return factor_all(h, sigma, bad_pivot);
+  });
+}
+
+riga_status riga_factor_complex(riga_problem* h, double sigma_re, double sigma_im, int64_t* bad_pivot) {
+  if (bad_pivot) *bad_pivot = -1;
+  if (!h || !std::isfinite(sigma_re) || !std::isfinite(sigma_im) || !(sigma_im > 0.0)) return RIGA_ERR_INVALID_ARG;
+  if (!h->assembled) return RIGA_ERR_STATE;
+  if (h->gyro || !h->node_inst.empty()) return RIGA_ERR_INVALID_ARG;   // symmetric damping, one problem
+  return run([&]() -> riga_status {
+    ck(hipSetDevice(h->device));
+    h->clear_graphs();
+    h->mixed = false;
+    h->gep = false;
+    h->factored = false;
+    h->cmode = false;
+    const int64_t N = h->N();
+    if (h->cshadow == nullptr) {
+      riga_problem* sh = new riga_problem();
+      sh->mesh = h->mesh;
+      if (sh->plan.build_realform(h->plan) != 0) {
+        delete sh;
+        return RIGA_ERR_INVALID_ARG;
+      }
+      h->cshadow = sh;   // owned by h from here (riga_destroy)
+      sh->device = h->device;
+      sh->st = h->st;
+      setup_device(sh);
+      const riga::Plan& P = sh->plan;
+      sh->gyro = true;   // nonsymmetric: the LU fronts
+      sh->d_Ct = sh->dalloc<double>(P.nnz);
+      sh->d_LR = sh->dalloc<double>(P.lsize);
+      sh->d_UR = sh->dalloc<double>(P.usize);
+      sh->d_TR = sh->dalloc<double>(P.lsize);
+      int64_t dblocks = 0;
+      for (size_t v = 0; v < P.nf.size(); ++v) dblocks += (P.no[v] + 63) / 64;
+      sh->d_DR = sh->dalloc<double>((size_t)dblocks * 4096);
+      // the real form has no mass term: the fronts read M with coefficient 0
+      ck(hipMemsetAsync(sh->d_M, 0, (size_t)P.nnz * sizeof(double), h->st));
+      h->d_cw = h->dalloc<double>((size_t)8 * N);
+      h->d_cb = h->dalloc<double>((size_t)8 * N);
+      h->d_cx = h->dalloc<double>((size_t)8 * N);
+    }
+    riga_problem* sh = h->cshadow;
+    sh->st = h->st;
+    const riga::Plan& P = sh->plan;
+    ck(hipMemsetAsync(sh->d_status, 0xFF, sizeof(int64_t), h->st));
+    ck(hipEventRecord(h->ev0, h->st));
+    riga::launch_realform_values(N, h->ds.rowptr, h->d_K, h->d_M, h->d_C, sigma_re, sigma_im, sh->d_K, sh->d_C,
+                                 sh->d_Ct, h->st);
+    for (int lv = 0; lv < P.height; ++lv) factor_level(sh, lv, 0.0, 1.0);
+    ck(hipGetLastError());
+    ck(hipEventRecord(h->ev1, h->st));
+    int64_t stat = -1;
+    ck(hipMemcpyAsync(&stat, sh->d_status, sizeof(int64_t), hipMemcpyDeviceToHost, h->st));
+    ck(hipStreamSynchronize(h->st));
+    float ms = 0;
+    ck(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    h->stats.t_factor_ms = ms;
+    double sb = 0.0;
+    for (size_t v = 0; v < P.nodes.size(); ++v) {
+      const double o = P.no[v], bb = P.nb[v];
+      sb += 2.0 * 8.0 * (o * (o + 1) / 2 + bb * o);
+    }
+    h->solve_bytes_now = sb;
+    h->stats.flops[RIGA_PHASE_FACTOR] = P.flops_dense * 2.0;   // two triangles
+    h->stats.bytes[RIGA_PHASE_FACTOR] = 24.0 * (double)P.nnz + 16.0 * (double)P.lsize;
+    if (stat >= 0) {
+      if (bad_pivot) *bad_pivot = stat / 2;   // the dof of the failed unknown
+      return RIGA_ERR_NOT_SPD;
+    }
+    h->sigma = sigma_re;
+    h->csig_im = sigma_im;
+    h->cmode = true;
+    h->graph_sigma = std::numeric_limits<double>::quiet_NaN();   // captured steps hold the old shift
+    return RIGA_OK;
+  });
+}
+
+riga_status riga_solve_q_complex(riga_problem* h, int nrhs, const double* b, double* x) {
+  if (!h || nrhs < 1 || !b || !x) return RIGA_ERR_INVALID_ARG;
+  if (!h->cmode) return RIGA_ERR_STATE;
+  return run([&]() -> riga_status {
+    ck(hipSetDevice(h->device));
+    const int64_t N = h->N();
+    riga_problem* sh = h->cshadow;
+    sh->st = h->st;
+    for (int c0 = 0; c0 < nrhs; c0 += 4) {
+      const int nc = std::min(4, nrhs - c0);
+      riga::launch_times_minus_i(N * nc, b + (size_t)c0 * 2 * N, h->d_cb, h->st);
+      solve_levels(sh, nc, h->d_cb, 2 * N, x + (size_t)c0 * 2 * N, 2 * N, nullptr, nullptr, 0, 0.0);
+    }
+    ck(hipGetLastError());
+    return RIGA_OK;
   });
 }
 
@@ -1350,7 +1523,10 @@ struct KrylovRun {
   // (M Rl, which the Gram-Schmidt updates need, is formed with the first products)
   void enqueue_step_device() {
     if (!pre) enqueue_apply(k);
-    orthonormalize_device(k + b, h->d_H, k, true);
+    const bool tensor = h->plan.kind == riga::SPACE_H1;
+    if (!tensor)
+      riga::launch_spmv(h->ds, N, b, h->d_M, 1.0, h->Rl, N, h->MRl, N, nullptr, 0, 0.0, nullptr, 0, h->st);
+    orthonormalize_device(k + b, h->d_H, k, tensor);
   }
 
   void step(uint64_t seed) {
@@ -1450,7 +1626,8 @@ int finish_pairs(riga_problem* h, const riga::KsCycle& cyc, int nev, double* dsm
         pf.qc = cplx(f[3] + f[4], f[5] - g);     // u^H C u
         pf.qk = cplx(f[6] + f[7], 0.0);          // u^H K u
       }
-      lam_rq[j] = riga::rayleigh_polish(pf, h->sigma + 1.0 / cyc.theta[wanted[j]]);
+      lam_rq[j] = h->cmode ? cshift_polish(pf, cyc.theta[wanted[j]], h->sigma, h->csig_im)
+                           : riga::rayleigh_polish(pf, h->sigma + 1.0 / cyc.theta[wanted[j]]);
     }
     std::vector<double> lamd((size_t)2 * nw);
     for (int j = 0; j < nw; ++j) { lamd[2 * j] = lam_rq[j].real(); lamd[2 * j + 1] = lam_rq[j].imag(); }
@@ -1471,7 +1648,7 @@ int finish_pairs(riga_problem* h, const riga::KsCycle& cyc, int nev, double* dsm
       }
       etav[j] = riga::scaled_residual(s, lam_rq[j], h->norms, unorm2[j]);
     }
-    std::vector<int> order = canonical_order(lam_rq, h->sigma);
+    std::vector<int> order = h->cmode ? psi_order(lam_rq, h->sigma, h->csig_im) : canonical_order(lam_rq, h->sigma);
     const int nout = std::min(nev, nw);
     // converged pairs: the leading ones in canonical order whose explicit
     // scaled residual meets the bar (the Ritz estimate alone is not trusted)
@@ -1510,8 +1687,11 @@ int finish_pairs(riga_problem* h, const riga::KsCycle& cyc, int nev, double* dsm
 extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, double* lam, double* X,
                                  double* eta, int* nconv) {
   if (!h || !opt || !lam) return RIGA_ERR_INVALID_ARG;
-  if (h->plan.kind != riga::SPACE_H1) return RIGA_ERR_INVALID_ARG;   // tensor products of the scalar space
-  if (!h->factored || h->gep) return RIGA_ERR_STATE;
+  // a real shift on a vector space would return its gradients (lam = 0 and
+  // -alpha are nearest every positive shift); a complex target is taken
+  if (h->plan.kind != riga::SPACE_H1 && !h->cmode) return RIGA_ERR_INVALID_ARG;
+  if ((!h->factored || h->gep) && !h->cmode) return RIGA_ERR_STATE;
+  if (h->cmode && (opt->flags & RIGA_EIGS_TOAR)) return RIGA_ERR_INVALID_ARG;
   const int64_t N = h->N();
   const int nev = opt->nev;
   const int b = opt->block > 0 ? opt->block : 2;

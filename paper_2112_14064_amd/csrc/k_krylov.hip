@@ -253,10 +253,10 @@ void launch_spmv_ell(const EllSlab* slabs, int nslab, const DevSpace* spaces, co
 // Three products with one pass over X: Y0 = A0 X, Y1 = A1 X, Y2 = A2 X.
 template <int NC>
 __global__ __launch_bounds__(SPMV_THREADS) void k_spmv3(
-    int n, const int* __restrict__ lo, const int* __restrict__ hi, const int64_t* __restrict__ rowptr,
-    int64_t ndof, const double* __restrict__ A0, const double* __restrict__ A1, const double* __restrict__ A2,
-    const double* __restrict__ X, int64_t ldx, double* __restrict__ Y0, double* __restrict__ Y1,
-    double* __restrict__ Y2, int64_t ldy) {
+    int n, const int* __restrict__ lo, const int* __restrict__ hi, const int* __restrict__ colidx,
+    const int64_t* __restrict__ rowptr, int64_t ndof, const double* __restrict__ A0, const double* __restrict__ A1,
+    const double* __restrict__ A2, const double* __restrict__ X, int64_t ldx, double* __restrict__ Y0,
+    double* __restrict__ Y1, double* __restrict__ Y2, int64_t ldy) {
   const int g = threadIdx.x % SPMV_G;
   const int64_t r = ((int64_t)blockIdx.x * SPMV_THREADS + threadIdx.x) / SPMV_G;
   const bool active = r < ndof;
@@ -264,11 +264,15 @@ __global__ __launch_bounds__(SPMV_THREADS) void k_spmv3(
 #pragma unroll
   for (int q = 0; q < NC; ++q) { s0[q] = 0.0; s1[q] = 0.0; s2[q] = 0.0; }
   if (active) {
-    const unsigned ru = (unsigned)r, j = ru / (unsigned)n, i = ru - j * (unsigned)n;
-    const int lx = lo[i], wx = hi[i] - lo[i] + 1, ly = lo[j];
+    // explicit columns (vector spaces), else the tensor pattern of the scalar space
+    int lx = 0, wx = 1, ly = 0;
+    if (colidx == nullptr) {
+      const unsigned ru = (unsigned)r, j = ru / (unsigned)n, i = ru - j * (unsigned)n;
+      lx = lo[i]; wx = hi[i] - lo[i] + 1; ly = lo[j];
+    }
     const int64_t k0 = rowptr[r], len = rowptr[r + 1] - k0;
     for (int o = g; o < len; o += SPMV_G) {
-      const int64_t col = (int64_t)(ly + o / wx) * n + lx + o % wx;
+      const int64_t col = colidx != nullptr ? (int64_t)colidx[k0 + o] : (int64_t)(ly + o / wx) * n + lx + o % wx;
       const double v0 = A0[k0 + o], v1 = A1[k0 + o], v2 = A2[k0 + o];
 #pragma unroll
       for (int q = 0; q < NC; ++q) {
@@ -301,7 +305,7 @@ void launch_spmv3(const DevSpace& s, int64_t ndof, int ncols, const double* A0, 
                   const double* X, int64_t ldx, double* Y0, double* Y1, double* Y2, int64_t ldy, hipStream_t st) {
   int64_t blocks = (ndof * SPMV_G + SPMV_THREADS - 1) / SPMV_THREADS;
 #define RIGA_SPMV3(NC)                                                                              \
-  hipLaunchKernelGGL(k_spmv3<NC>, dim3((unsigned)blocks), dim3(SPMV_THREADS), 0, st, s.n, s.lo, s.hi, \
+  hipLaunchKernelGGL(k_spmv3<NC>, dim3((unsigned)blocks), dim3(SPMV_THREADS), 0, st, s.n, s.lo, s.hi, s.col, \
                      s.rowptr, ndof, A0, A1, A2, X, ldx, Y0, Y1, Y2, ldy)
   switch (ncols) {
     case 1: RIGA_SPMV3(1); break;

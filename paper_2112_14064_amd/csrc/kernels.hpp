@@ -219,7 +219,8 @@ void launch_spmv_ell(const EllSlab* slabs, int nslab, const DevSpace* spaces, co
 void launch_spmv(const DevSpace& s, int64_t ndof, int ncols, const double* A, double a, const double* X,
                  int64_t ldx, double* Y, int64_t ldy, const double* Z, int64_t ldz, double bz, double* Y2,
                  int64_t ldy2, hipStream_t st);
-// Y0 = A0 X, Y1 = A1 X, Y2 = A2 X in one pass over X (ncols <= 8, common ld of the Y).
+// Y0 = A0 X, Y1 = A1 X, Y2 = A2 X in one pass over X (ncols <= 8, common ld of the Y);
+// explicit columns when s.col is set (vector spaces), else the tensor pattern.
 void launch_spmv3(const DevSpace& s, int64_t ndof, int ncols, const double* A0, const double* A1, const double* A2,
                   const double* X, int64_t ldx, double* Y0, double* Y1, double* Y2, int64_t ldy, hipStream_t st);
 // out[c*nq + q] = sum_i Au[i,c] Xu[i,q] + Al[i,c] Xl[i,q]  (Al/Xl may be null),
@@ -392,5 +393,20 @@ int launch_toar_update_dots(int64_t n, int nc, int nq, const double* h, const do
 // shared-memory tables (r + nq <= 264, k + nq <= 260, r + nq <= ldq).
 bool launch_toar_compact(int r, int k, int nq, double sig, const double* S, int lds, double* Q1, double* Q2, int ldq,
                          double* H, int ldh, int* flag, double* P, hipStream_t st);
+
+// Complex target shift sigma = a + ib (see k_cshift.hip).  Real form of
+// -i Q(sigma) on the doubled pattern of Plan::build_realform from the base
+// CSR values (n base rows): Kr = J (x) I, Cr = R (x) E, Ctr = -Cr.
+void launch_realform_values(int64_t n, const int64_t* rowptr, const double* K, const double* M, const double* C,
+                            double a, double b, double* Kr, double* Cr, double* Ctr, hipStream_t st);
+// Real-form right-hand sides (2n x nb, ld ldo) of x = -Q^{-1} t from MX = M v_u
+// and CW = C v_u + M v_l (n x nb, ld ld).
+void launch_cshift_rhs(int64_t n, int nb, const double* MX, const double* CW, int64_t ld, double a, double b,
+                       double* out, int64_t ldo, hipStream_t st);
+// r_u = Re x, r_l = a Re x - b Im x + v_u from the interleaved complex x.
+void launch_cshift_out(int64_t n, int nb, const double* x, int64_t ldx, double a, double b, const double* vu,
+                       int64_t ldv, double* ru, double* rl, int64_t ldr, hipStream_t st);
+// out = -i in for m interleaved complex values.
+void launch_times_minus_i(int64_t m, const double* in, double* out, hipStream_t st);
 
 }  // namespace riga

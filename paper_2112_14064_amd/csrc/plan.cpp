@@ -229,6 +229,7 @@ int Plan::build(int p, int ne, int s, int leaf) {
   if (p < 1 || p > 8 || ne < 2) return -1;
   if (s < 0 || (s > 0 && ne % s != 0)) return -1;
   if (leaf <= 0) leaf = 8;
+  leaf_size = leaf;
   sp.build(p, ne, s);
   n1d = sp.n;
   if (n1d < 1) return -1;
@@ -259,6 +260,7 @@ int Plan::build_hcurl(int p, int ne, int s, int leaf, bool pec) {
   if (p < 2 || p > 8 || ne < 2) return -1;
   if (s < 0 || (s > 0 && ne % s != 0)) return -1;
   if (leaf <= 0) leaf = 8;
+  leaf_size = leaf;
   kind = pec ? SPACE_HCURL : SPACE_HCURL_FREE;
   // component 0: S^{p-1} (x) S^p (eq. HcurlBasis), component 1: S^p (x) S^{p-1};
   // both degrees carry the hyperplane knots with multiplicity p - 1
@@ -327,6 +329,67 @@ int Plan::build_hcurl(int p, int ne, int s, int leaf, bool pec) {
                   locate(d, c, i, j);
                   x0 = cx[c].sup0[i]; x1 = cx[c].sup1[i]; y0 = cy[c].sup0[j]; y1 = cy[c].sup1[j];
                 },
+                [&](int64_t d, auto&& f) {
+                  for (int64_t q = rowptr[d]; q < rowptr[d + 1]; ++q) f((int64_t)col[q]);
+                });
+}
+
+void Plan::dof_support(int64_t d, int& x0, int& x1, int& y0, int& y1) const {
+  if (kind == SPACE_H1) {
+    const int n = sp.n, i = (int)(d % n), j = (int)(d / n);
+    x0 = sp.sup0[i]; x1 = sp.sup1[i]; y0 = sp.sup0[j]; y1 = sp.sup1[j];
+    return;
+  }
+  const int c = d >= cbase[1] ? 1 : 0;
+  const int64_t r = d - cbase[c];
+  const int i = (int)(r % cx[c].n), j = (int)(r / cx[c].n);
+  x0 = cx[c].sup0[i]; x1 = cx[c].sup1[i]; y0 = cy[c].sup0[j]; y1 = cy[c].sup1[j];
+}
+
+int Plan::build_realform(const Plan& base) {
+  if (base.ndof < 1 || base.nodes.empty() || base.kind == SPACE_REALFORM || (base.kind == SPACE_H1 && base.sp.n < 1))
+    return -1;   // a forest has no single space
+  kind = SPACE_REALFORM;
+  sp = base.sp;
+  leaf_size = base.leaf_size;
+  // the same amalgamated tree: a node's own unknowns are twice its dofs
+  amalg_group = base.amalg_group;
+  amalg_max = base.amalg_max;
+  amalg_own = 2 * base.amalg_own;
+  n1d = base.n1d;
+  ndof = 2 * base.ndof;
+  if (ndof > (int64_t)0x3fffffff) return -1;
+  // base's couplings of dof d, increasing
+  std::vector<int64_t> nb_list;
+  auto base_neighbours = [&](int64_t d) {
+    nb_list.clear();
+    if (!base.col.empty()) {
+      for (int64_t q = base.rowptr[d]; q < base.rowptr[d + 1]; ++q) nb_list.push_back(base.col[q]);
+      return;
+    }
+    const Space1D& S = base.sp;
+    const int n = S.n, i = (int)(d % n), j = (int)(d / n);
+    for (int jj = S.lo[j]; jj <= S.hi[j]; ++jj)
+      for (int ii = S.lo[i]; ii <= S.hi[i]; ++ii) nb_list.push_back((int64_t)jj * n + ii);
+  };
+  rowptr.assign(ndof + 1, 0);
+  for (int64_t d = 0; d < base.ndof; ++d) {
+    const int64_t len = base.rowptr[d + 1] - base.rowptr[d];
+    rowptr[2 * d + 1] = rowptr[2 * d] + 2 * len;
+    rowptr[2 * d + 2] = rowptr[2 * d + 1] + 2 * len;
+  }
+  nnz = rowptr[ndof];
+  if (nnz > (int64_t)0x7fffffff) return -1;
+  col.assign(nnz, 0);
+  for (int64_t d = 0; d < base.ndof; ++d) {
+    base_neighbours(d);
+    if ((int64_t)nb_list.size() * 2 != rowptr[2 * d + 1] - rowptr[2 * d]) return -1;
+    int64_t q = rowptr[2 * d];
+    for (int64_t j : nb_list) { col[q++] = (int)(2 * j); col[q++] = (int)(2 * j + 1); }
+    std::copy(col.begin() + rowptr[2 * d], col.begin() + rowptr[2 * d + 1], col.begin() + rowptr[2 * d + 1]);
+  }
+  return finish(base.sp.ne, base.sp.s, leaf_size,
+                [&](int64_t d, int& x0, int& x1, int& y0, int& y1) { base.dof_support(d / 2, x0, x1, y0, y1); },
                 [&](int64_t d, auto&& f) {
                   for (int64_t q = rowptr[d]; q < rowptr[d + 1]; ++q) f((int64_t)col[q]);
                 });

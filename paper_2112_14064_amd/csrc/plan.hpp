@@ -34,8 +34,10 @@ struct Space1D {
   void build(int p_, int ne_, int s_, int mult_ = -1, bool dirichlet = true);
 };
 
-// Kinds of discrete space (riga_mesh.space).
-enum SpaceKind { SPACE_H1 = 0, SPACE_HCURL = 1, SPACE_HCURL_FREE = 2 };
+// Kinds of discrete space (riga_mesh.space).  SPACE_REALFORM is internal: the
+// real form of a complex system on another plan's space (two unknowns per
+// dof, see Plan::build_realform).
+enum SpaceKind { SPACE_H1 = 0, SPACE_HCURL = 1, SPACE_HCURL_FREE = 2, SPACE_REALFORM = 3 };
 
 struct Node {
   int x0, x1, y0, y1;          // box in element units
@@ -57,6 +59,7 @@ struct Plan {
   // has the tensor space cx[c] (x) cy[c], its dofs at cbase[c] + j n_x + i;
   // the CSR column indices are explicit (col).  Empty for the scalar space.
   int kind = SPACE_H1;
+  int leaf_size = 8;           // the leaf length the tree was built with
   Space1D cx[2], cy[2];
   int64_t cbase[3] = {0, 0, 0};
   std::vector<int> col;
@@ -93,6 +96,13 @@ struct Plan {
   // on the boundary (the degree-p factor loses its end functions), else no
   // boundary condition.  p >= 2.
   int build_hcurl(int p, int ne, int s, int leaf, bool pec);
+  // The real form of a complex system on base's space: dof d of base becomes
+  // the unknowns 2d (real part) and 2d + 1 (imaginary part), every coupling
+  // of base a full 2 x 2 block; explicit columns; the same tree of boxes
+  // (a dof's two unknowns are eliminated together).  Single-space bases only.
+  int build_realform(const Plan& base);
+  // Support box of a dof of a single-space plan, in elements.
+  void dof_support(int64_t d, int& x0, int& x1, int& y0, int& y1) const;
 
   // Symbolic Cholesky of the tensor sparsity under the elimination order of
   // the plan (no dense-front zeros): per elimination position the nonzeros of

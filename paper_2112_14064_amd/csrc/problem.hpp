@@ -50,6 +50,15 @@ struct riga_problem {
   double *d_hMA = nullptr, *d_hMB = nullptr, *d_hKB = nullptr, *d_hD = nullptr;
   bool gyro = false;
   double gx = 0.0, gy = 0.0;
+  // Complex target shift sigma + i csig_im (riga_factor_complex; then
+  // factored is false and cmode true): the real form of -i Q(sigma) factored
+  // on a second handle over the doubled plan, and the operator's scratch
+  // (d_cw: M v_u | C v_u + M v_l, N x 4 each; d_cb, d_cx: right-hand sides
+  // and solutions of the real form, 2N x 4 each).
+  bool cmode = false;
+  double csig_im = 0.0;
+  riga_problem* cshadow = nullptr;
+  double *d_cw = nullptr, *d_cb = nullptr, *d_cx = nullptr;
   double *d_tabS = nullptr, *d_S1 = nullptr, *d_Ct = nullptr;
   double *d_LR = nullptr, *d_UR = nullptr, *d_TR = nullptr, *d_DR = nullptr;
   double *d_L = nullptr, *d_U = nullptr, *d_T = nullptr, *d_upd = nullptr, *d_tmp = nullptr, *d_tmp2 = nullptr;

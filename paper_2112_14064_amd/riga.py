@@ -66,7 +66,8 @@ EXPORTS = ["riga_create", "riga_info", "riga_assemble", "riga_export_csr", "riga
            "riga_batch_autotune",
            "riga_factor_gep", "riga_gep_slice",
            "riga_solve_q", "riga_solve_q_noalloc", "riga_apply_op", "riga_eigs", "riga_adjoint", "riga_stats", "riga_time_kernel",
-           "riga_selftest_small_eig", "riga_selftest_schur_restart", "riga_symbolic", "riga_status_str", "riga_destroy", "riga_selftest_range_basis", "riga_assemble_gyroscopic"]
+           "riga_selftest_small_eig", "riga_selftest_schur_restart", "riga_symbolic", "riga_status_str", "riga_destroy", "riga_selftest_range_basis", "riga_assemble_gyroscopic",
+           "riga_factor_complex", "riga_solve_q_complex"]
 
 _lib = None
 
@@ -91,6 +92,8 @@ def load(path: str = LIB_PATH):
     lib.riga_export_csr.argtypes = [P, C.c_int, P, P, P]
     lib.riga_factor.argtypes = [P, C.c_double, C.POINTER(C.c_int64)]
     lib.riga_factor_mixed.argtypes = [P, C.c_double, C.c_int, C.c_int, C.c_double, P, C.POINTER(C.c_int64)]
+    lib.riga_factor_complex.argtypes = [P, C.c_double, C.c_double, C.POINTER(C.c_int64)]
+    lib.riga_solve_q_complex.argtypes = [P, C.c_int, P, P]
     lib.riga_ir_sweeps.argtypes = [P, C.POINTER(C.c_int)]
     lib.riga_solve_q.argtypes = [P, C.c_int, P, P]
     lib.riga_solve_q_noalloc.argtypes = [P, C.c_int, P, P]
@@ -276,15 +279,22 @@ class Problem:
 
     def factor(self, sigma: float, precision: str = "fp64", fp64_levels: int = 1, ir_sweeps: int = -1,
                ir_tol: float = 0.0):
-        """Factor Q(sigma).  precision "fp64" (riga_factor) or "mixed"
+        """Factor Q(sigma).  A complex sigma with a positive imaginary part is a
+        complex target (riga_factor_complex).  precision "fp64" (riga_factor) or "mixed"
         (riga_factor_mixed: FP32 fronts below the top fp64_levels levels, FP64
         refinement of every solve; ir_sweeps -1 lets the library choose, with
         the residual target ir_tol).  For "mixed" returns the calibration
         residual history (RIGA_IR_MAX+1 values)."""
         bad = C.c_int64(-1)
         hist = None
-        if precision == "fp64":
-            st = self.lib.riga_factor(self.h, sigma, C.byref(bad))
+        if isinstance(sigma, complex) and sigma.imag != 0.0:
+            if precision != "fp64":
+                raise ValueError("a complex target is factored in FP64 only")
+            st = self.lib.riga_factor_complex(self.h, sigma.real, sigma.imag, C.byref(bad))
+            where = "riga_factor_complex"
+        elif precision == "fp64":
+            st = self.lib.riga_factor(self.h, float(sigma.real if isinstance(sigma, complex) else sigma),
+                                      C.byref(bad))
             where = "riga_factor"
         elif precision == "mixed":
             hist = np.full(RIGA_IR_MAX + 1, -1.0)
@@ -312,6 +322,14 @@ class Problem:
         b = b.to(device=self.device, dtype=self.torch.float64).contiguous()
         x = self.torch.empty_like(b)
         _check(self.lib.riga_solve_q(self.h, b.shape[0], _ptr(b), _ptr(x)), "riga_solve_q")
+        return x
+
+    def solve_q_complex(self, b):
+        """x = Q(sigma)^{-1} b with the complex factor, b complex of shape
+        (nrhs, ndof)."""
+        b = b.to(device=self.device, dtype=self.torch.complex128).contiguous()
+        x = self.torch.empty_like(b)
+        _check(self.lib.riga_solve_q_complex(self.h, b.shape[0], _ptr(b), _ptr(x)), "riga_solve_q_complex")
         return x
 
     def factor_gep(self, shift: float) -> int:
