@@ -22,11 +22,12 @@ headline step with the Krylov basis in compact two-level (TOAR) form beside
 the full basis, and the headline mesh with a gyroscopic (skew) part in the
 damping, factored by LU.  The curl-conforming vector space (p=3, 256^2, perfect
 conductor) closes the run: factorization, FB elimination and Maxwell spectrum
-slicing, rIGA against IGA.  `--flop-table` prints the host-side symbolic cost
+slicing, rIGA against IGA, and its conductive QEP at the complex target 7i
+(the real part of the shift-and-invert operator).  `--flop-table` prints the host-side symbolic cost
 ratios of that space for p = 3..6 (the quantities of tab:FlopTest) and exits.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-iga] [--no-mixed] [--no-batch]
-                       [--no-undamped] [--no-toar] [--no-gyro] [--no-hcurl] [--basis full|toar]
+                       [--no-undamped] [--no-toar] [--no-gyro] [--no-hcurl] [--no-em] [--basis full|toar]
                        [--flop-table]
 """
 from __future__ import annotations
@@ -463,6 +464,67 @@ def flop_table(riga, nes=(256, 1024), degrees=(3, 4, 5, 6)):
     return rows
 
 
+def complex_target_form(torch, riga, W, steps, block):
+    """The conductive electromagnetic QEP on the curl-conforming space (p=3,
+    256^2, perfect conductor), rIGA and IGA, at the complex target 7i: the
+    real form of Q(sigma) factored by LU, the eigensolve on the real part of
+    the operator; one step = assemble + factor + eigensolve, timed like the
+    headline step."""
+    out, lams = {}, {}
+    for s in (16, 0):
+        P = W.cfg_em_qep(s)
+        pr = riga.Problem(P.p, P.ne, P.hyper_every, space=P.extra["space"])
+        info = pr.info
+        sig = P.extra["sigma_c"]
+
+        def one():
+            pr.assemble(P.alpha, P.beta)
+            pr.factor(sig)
+            return pr.eigs(P.nev, P.m, block=block, seed=0, vectors=True)
+
+        one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            lam, X, eta, nconv, st = one()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        stats = pr.stats()
+        good = int(sum(1 for e in eta[:nconv] if e <= 1e-10))
+        out["riga" if s else "iga"] = {
+            "workload": f"H(curl) p={P.p}, {P.ne}x{P.ne}, perfect conductor, " + (f"rIGA s={s}" if s else "IGA") +
+                        f", C = {P.alpha}M + {P.beta}K, {P.nev} pairs of largest |psi| at sigma={sig}, "
+                        f"subspace {P.m}",
+            "ndof": int(info["ndof"]), "ms_per_step": ms, "eigenpairs_per_s": good * 1e3 / ms, "pairs_ok": good,
+            "status": int(st), "factor_ms": stats["t_factor_ms"], "eigs_ms": stats["t_eigs_ms"],
+            # the real form: twice the unknowns, LU (two triangles) of the doubled fronts
+            "factor_gflop_dense": stats["flops"]["factor"] / 1e9,
+            "factor_gflops_dense": stats["flops"]["factor"] / (stats["t_factor_ms"] * 1e-3) / 1e9,
+            "n_it": int(stats["n_it"]), "n_fb": int(stats["n_fb"]), "max_eta": float(max(eta)),
+        }
+        lams["riga" if s else "iga"] = (P, lam)
+        pr.close()
+    r, i = out["riga"], out["iga"]
+    out["iga_over_riga"] = {"factor_time": i["factor_ms"] / r["factor_ms"], "eigs_time": i["eigs_ms"] / r["eigs_ms"],
+                            "step_time": i["ms_per_step"] / r["ms_per_step"]}
+    return out, lams
+
+
+def oracle_check_em(lams):
+    """Eigenvalues of the complex-target leg against the oracle's Maxwell
+    closed form with the null space, selected by |psi|."""
+    import numpy as np
+
+    from oracle import cshift
+
+    res = {}
+    for k, (P, lam) in lams.items():
+        ref = cshift.maxwell_cshift(P.p, P.ne, P.hyper_every, P.alpha, P.beta, P.extra["sigma_c"], P.nev)
+        rel = np.abs(lam - ref) / np.abs(ref) if len(ref) == len(lam) else np.array([np.inf])
+        res[k] = (float(rel.max()), int(np.sum(rel <= 1e-10)))
+    return res
+
+
 def oracle_check_hcurl(mus):
     """Count and eigenvalues of the Maxwell slices of the vector-space leg
     against the oracle's closed form (sums of 1-D values)."""
@@ -532,6 +594,7 @@ def main():
     ap.add_argument("--no-toar", action="store_true")
     ap.add_argument("--no-gyro", action="store_true")
     ap.add_argument("--no-hcurl", action="store_true")
+    ap.add_argument("--no-em", action="store_true")
     ap.add_argument("--flop-table", action="store_true",
                     help="only print the host-side symbolic cost ratios IGA / rIGA of the curl-conforming space "
                          "(p = 3..6, 256^2 and 1024^2 elements) and exit")
@@ -614,6 +677,9 @@ def main():
     hc = None
     if not args.no_hcurl:
         out["vector_space_form"], hc = vector_space_form(torch, riga, W)
+    em = None
+    if not args.no_em:
+        out["complex_target_form"], em = complex_target_form(torch, riga, W, min(args.steps, 2), args.block)
     if roof is not None:
         out["roofline"] = roof
     if not args.no_cpu:
@@ -637,6 +703,10 @@ def main():
             for k, (n_ref, rel) in oracle_check_undamped(mus).items():
                 out["undamped_form"][k]["oracle_count"] = n_ref
                 out["undamped_form"][k]["max_rel_err_vs_oracle"] = rel
+        if em is not None:
+            for k, (rel, ok) in oracle_check_em(em).items():
+                out["complex_target_form"][k]["max_rel_err_vs_oracle"] = rel
+                out["complex_target_form"][k]["pairs_within_1e-10_of_oracle"] = ok
         if hc is not None:
             for k, (n_ref, rel) in oracle_check_hcurl(hc).items():
                 out["vector_space_form"][k]["maxwell"]["oracle_count"] = n_ref

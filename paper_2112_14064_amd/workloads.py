@@ -152,3 +152,14 @@ def cfg_hcurl(hyper_every: int = 16) -> Problem:
     tag = f"s{hyper_every}" if hyper_every else "iga"
     return Problem(p=3, ne=256, hyper_every=hyper_every, alpha=0.05, beta=0.005, sigma=2.0,
                    name=f"p3_256x256_{tag}_hcurl", extra={"space": 1, "interval": (1.0, 150.0), "max_slice": 40})
+
+
+def cfg_em_qep(hyper_every: int = 16) -> Problem:
+    """The conductive electromagnetic QEP on the curl-conforming space S^{2,3} x
+    S^{3,2} (p=3) on 256x256 with the perfect conductor, rIGA (C^1/C^0
+    hyperplanes every 16 elements) or IGA (hyper_every=0): C = 0.05 M +
+    0.005 K, complex target sigma = 7i, the 38 pairs of largest |psi| (a gap
+    of the spectrum: no conjugate cluster is split), subspace 80."""
+    tag = f"s{hyper_every}" if hyper_every else "iga"
+    return Problem(p=3, ne=256, hyper_every=hyper_every, alpha=0.05, beta=0.005, sigma=7.0, nev=38, m=80,
+                   name=f"p3_256x256_{tag}_em_qep", extra={"space": 1, "sigma_c": 7.0j})
