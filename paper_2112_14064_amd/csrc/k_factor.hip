@@ -52,6 +52,11 @@ namespace riga {
 constexpr int FT = 256;     // threads per workgroup (four waves)
 constexpr int TB = 64;      // panel / tile width
 constexpr int LDT = TB + 1; // LDS row stride (elements)
+// LU fronts with at least this many row tiles below a panel form the panel
+// rows once (k_panel_rows_lu + k_panel_trail_lu) instead of per tile pair
+#ifndef LU_SPLIT_TILES
+#define LU_SPLIT_TILES 8
+#endif
 
 template <class E>
 struct Front {
@@ -902,6 +907,121 @@ __global__ __launch_bounds__(FT) void k_panel_update_lu(DevTree t, const int* __
         }
 }
 
+// Large LU fronts in two launches per panel, so that no panel row is formed
+// twice (the fused kernel above forms X_I, Y_I and X_J, Y_J for every tile
+// pair, i.e. each row tile once per pair it takes part in):
+// k_panel_rows_lu, one workgroup per row tile I below the panel: X_I =
+// A_panel D_U^T and Y_I = At_panel D_L^T written as factor rows;
+// k_panel_trail_lu, one workgroup per tile pair (I, J), J <= I: the stored
+// rows staged in LDS, C^A_IJ -= X_I Y_J^T and C^At_IJ -= Y_I X_J^T.
+template <class E>
+__global__ __launch_bounds__(FT) void k_panel_rows_lu(DevTree t, const int* __restrict__ level_nodes, int k0,
+                                                      E* __restrict__ Lbuf, E* __restrict__ Ubuf,
+                                                      E* __restrict__ Rbuf, E* __restrict__ URbuf,
+                                                      E* __restrict__ Lfac, E* __restrict__ Rfac,
+                                                      const E* __restrict__ DLbuf, const E* __restrict__ DUbuf) {
+  typedef Tile64<E, 4> TL;
+  const int v = level_nodes[blockIdx.x];
+  const Front<E> FA = front_of(t, v, Lbuf, Ubuf);
+  const Front<E> FT_ = front_of(t, v, Rbuf, URbuf);
+  if (FA.no <= k0) return;
+  const int w = min(TB, FA.no - k0);
+  const int rI = k0 + w + TB * (int)blockIdx.y;
+  const int nf = FA.nf;
+  if (rI >= nf) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t dblk = ((int64_t)t.doff[v] + k0 / TB) * (TB * TB);
+  typename TL::Acc xi, yi;
+  TL::zero(xi);
+  TL::zero(yi);
+  TL::mma_global(FA.L + (int64_t)k0 * nf + rI, nf, nf - rI, DUbuf + dblk, TB, w, xi, lane, wave);
+  TL::mma_global(FT_.L + (int64_t)k0 * nf + rI, nf, nf - rI, DLbuf + dblk, TB, w, yi, lane, wave);
+  E* Lf = Lfac + t.loff[v];
+  E* Rf = Rfac + t.loff[v];
+#pragma unroll
+  for (int ti = 0; ti < TL::TI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TL::TJ; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = TL::row(lane, wave, ti, e), cl = TL::col(lane, wave, tj);
+        if (rI + r < nf && cl < w) {
+          Lf[(int64_t)(k0 + cl) * nf + rI + r] = xi.a[ti][tj][e];
+          Rf[(int64_t)(k0 + cl) * nf + rI + r] = yi.a[ti][tj][e];
+        }
+      }
+}
+
+template <class E>
+__global__ __launch_bounds__(FT) void k_panel_trail_lu(DevTree t, const int* __restrict__ level_nodes, int k0,
+                                                       E* __restrict__ Lbuf, E* __restrict__ Ubuf,
+                                                       E* __restrict__ Rbuf, E* __restrict__ URbuf,
+                                                       const E* __restrict__ Lfac, const E* __restrict__ Rfac) {
+  typedef Tile64<E, 4> TL;
+  const int v = level_nodes[blockIdx.x];
+  const Front<E> FA = front_of(t, v, Lbuf, Ubuf);
+  const Front<E> FT_ = front_of(t, v, Rbuf, URbuf);
+  if (FA.no <= k0) return;
+  const int w = min(TB, FA.no - k0);
+  const int s0 = k0 + w;
+  const int pidx = blockIdx.y;
+  int I = (int)((sqrt(8.0 * pidx + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= pidx) ++I;
+  while (I * (I + 1) / 2 > pidx) --I;
+  const int J = pidx - I * (I + 1) / 2;
+  const int rI = s0 + TB * I, rJ = s0 + TB * J;
+  const int nf = FA.nf;
+  if (rI >= nf) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ E Xa[TB * LDT];
+  __shared__ E Xb[TB * LDT];
+  const E* Lf = Lfac + t.loff[v];
+  const E* Rf = Rfac + t.loff[v];
+  typename TL::Acc ca, ct;
+  E* pa[TL::TI][TL::TJ][4];
+  E* pt[TL::TI][TL::TJ][4];
+#pragma unroll
+  for (int ti = 0; ti < TL::TI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TL::TJ; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = rI + TL::row(lane, wave, ti, e), cc = rJ + TL::col(lane, wave, tj);
+        const bool in = r < nf && cc < nf && r >= cc;
+        pa[ti][tj][e] = in ? FA.at(r, cc) : nullptr;
+        pt[ti][tj][e] = in ? FT_.at(r, cc) : nullptr;
+        ca.a[ti][tj][e] = *(in ? pa[ti][tj][e] : FA.at(rI, rJ));
+        ct.a[ti][tj][e] = *(in ? pt[ti][tj][e] : FT_.at(rI, rJ));
+      }
+  // stored rows: lane-consecutive rows of one panel column per pass (coalesced);
+  // rows past the front and columns past the panel are zeros
+  auto stage = [&](const E* Pi, const E* Pj) {
+    for (int idx = tid; idx < TB * TB; idx += FT) {
+      const int r = idx % TB, c = idx / TB;
+      const bool cin = c < w;
+      Xa[r * LDT + c] = (cin && rI + r < nf) ? Pi[(int64_t)(k0 + c) * nf + rI + r] : E(0);
+      Xb[c * LDT + r] = (cin && rJ + r < nf) ? Pj[(int64_t)(k0 + c) * nf + rJ + r] : E(0);
+    }
+  };
+  stage(Lf, Rf);   // X_I, Y_J^T
+  __syncthreads();
+  TL::mma(Xa, Xb, w, ca, lane, wave, E(-1));
+  __syncthreads();
+  stage(Rf, Lf);   // Y_I, X_J^T
+  __syncthreads();
+  TL::mma(Xa, Xb, w, ct, lane, wave, E(-1));
+#pragma unroll
+  for (int ti = 0; ti < TL::TI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TL::TJ; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (pa[ti][tj][e] != nullptr) {
+          *pa[ti][tj][e] = ca.a[ti][tj][e];
+          *pt[ti][tj][e] = ct.a[ti][tj][e];
+        }
+}
+
 // Rows [64 y, +64) of X with X L_oo = [I; L_bo] (L from the factor buffer);
 // X row r at Fout[r * no + ...] (the front buffer's block of the node).
 // Sixteen waves: each takes one 16 x 16 MFMA tile of a 64 x 64 product.
@@ -1137,8 +1257,15 @@ void launch_front_factor_lu(const DevSpace& s, const DevTree& t, const int* leve
                        Lx, Rx, D, DR, status);
     const int below = std::max(1, max_nf - k0 - 1);
     const int nrc = (below + TB - 1) / TB;
-    hipLaunchKernelGGL(k_panel_update_lu<E>, dim3(count, nrc * (nrc + 1) / 2), dim3(FT), 0, st, t, level_nodes, k0,
-                       L, U, R, UR, Lx, Rx, (const E*)D, (const E*)DR);
+    if (nrc >= LU_SPLIT_TILES) {
+      hipLaunchKernelGGL(k_panel_rows_lu<E>, dim3(count, nrc), dim3(FT), 0, st, t, level_nodes, k0, L, U, R, UR, Lx,
+                         Rx, (const E*)D, (const E*)DR);
+      hipLaunchKernelGGL(k_panel_trail_lu<E>, dim3(count, nrc * (nrc + 1) / 2), dim3(FT), 0, st, t, level_nodes, k0,
+                         L, U, R, UR, (const E*)Lx, (const E*)Rx);
+    } else {
+      hipLaunchKernelGGL(k_panel_update_lu<E>, dim3(count, nrc * (nrc + 1) / 2), dim3(FT), 0, st, t, level_nodes,
+                         k0, L, U, R, UR, Lx, Rx, (const E*)D, (const E*)DR);
+    }
   }
   const int nrt = (max_nf + TB - 1) / TB;
   hipLaunchKernelGGL(k_rtrsm<E>, dim3(count, nrt), dim3(RT_THREADS), 0, st, t, level_nodes, (const E*)Lx, L,
