@@ -24,11 +24,13 @@ damping, factored by LU.  The curl-conforming vector space (p=3, 256^2, perfect
 conductor) closes the run: factorization, FB elimination and Maxwell spectrum
 slicing, rIGA against IGA, and its conductive QEP at the complex target 7i
 (the real part of the shift-and-invert operator).  `--flop-table` prints the host-side symbolic cost
-ratios of that space for p = 3..6 (the quantities of tab:FlopTest) and exits.
+ratios of that space for p = 3..6 (the quantities of tab:FlopTest) and exits;
+`--flop-test` runs that space's conductive QEP at the target 7i for p = 3..5 on
+the device (100 pairs) and prints the same ratios from the runs' counts and times.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-iga] [--no-mixed] [--no-batch]
                        [--no-undamped] [--no-toar] [--no-gyro] [--no-hcurl] [--no-em] [--basis full|toar]
-                       [--flop-table]
+                       [--flop-table] [--flop-test]
 """
 from __future__ import annotations
 
@@ -510,6 +512,49 @@ def complex_target_form(torch, riga, W, steps, block):
     return out, lams
 
 
+def flop_test(torch, riga, degrees=(3, 4, 5), ne=256, nev=100, m=220, block=2):
+    """tab:FlopTest on the device: the conductive QEP on the curl-conforming
+    space with the perfect conductor (C = 0.05 M + 0.005 K, target 7i, nev
+    pairs, subspace m), rIGA (16 x 16-element macroelements) against IGA for
+    each degree.  Per operation of eq. Cost the ratio IGA / rIGA of the
+    library's counts (factorization: the symbolic flops of the elimination
+    order; FB elimination: nnz(L) x solves; mat-vec: nnz x products; vec-vec:
+    N x products) and of the measured factorization, eigensolve and total
+    times (one warm-up, one timed call each)."""
+    rows = []
+    for p in degrees:
+        res = {}
+        for s in (16, 0):
+            pr = riga.Problem(p, ne, s, space=riga.RIGA_SPACE_HCURL)
+            info = pr.info
+            _, _, nnz_l, sym_flops = riga.riga_symbolic(p, ne, s, space=riga.RIGA_SPACE_HCURL)
+            for rep in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                pr.assemble(0.05, 0.005)
+                pr.factor(7.0j)
+                lam, X, eta, nconv, st = pr.eigs(nev, m, block=block, seed=0, vectors=False)
+                torch.cuda.synchronize()
+                total = (time.perf_counter() - t0) * 1e3
+            S = pr.stats()
+            res[s] = {"ndof": int(info["ndof"]), "nnz": int(info["nnz"]), "nnz_l": int(nnz_l), "sym_flops": sym_flops,
+                      "factor_ms": S["t_factor_ms"], "eigs_ms": S["t_eigs_ms"], "total_ms": total,
+                      "n_fb": int(S["n_fb"]), "n_mv": int(S["n_mv"]), "n_vv": int(S["n_vv"]), "status": int(st),
+                      "nconv": int(nconv), "max_eta": float(max(eta[:max(nconv, 1)]))}
+            pr.close()
+        r, i = res[16], res[0]
+        row = {"p": p, "ne": ne, "nev": nev, "m": m, "riga": r, "iga": i, "iga_over_riga": {
+            "factorization_flops": i["sym_flops"] / r["sym_flops"],
+            "fb_elimination": (i["nnz_l"] * i["n_fb"]) / (r["nnz_l"] * r["n_fb"]),
+            "mat_vec": (i["nnz"] * i["n_mv"]) / (r["nnz"] * r["n_mv"]),
+            "vec_vec": (i["ndof"] * i["n_vv"]) / (r["ndof"] * r["n_vv"]),
+            "factor_time": i["factor_ms"] / r["factor_ms"], "eigs_time": i["eigs_ms"] / r["eigs_ms"],
+            "total_time": i["total_ms"] / r["total_ms"]}}
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    return rows
+
+
 def oracle_check_em(lams):
     """Eigenvalues of the complex-target leg against the oracle's Maxwell
     closed form with the null space, selected by |psi|."""
@@ -595,6 +640,9 @@ def main():
     ap.add_argument("--no-gyro", action="store_true")
     ap.add_argument("--no-hcurl", action="store_true")
     ap.add_argument("--no-em", action="store_true")
+    ap.add_argument("--flop-test", action="store_true",
+                    help="only run the device analog of tab:FlopTest (the conductive QEP on the curl-conforming "
+                         "space at the target 7i, 100 pairs, p = 3..5 on 256^2, rIGA against IGA) and exit")
     ap.add_argument("--flop-table", action="store_true",
                     help="only print the host-side symbolic cost ratios IGA / rIGA of the curl-conforming space "
                          "(p = 3..6, 256^2 and 1024^2 elements) and exit")
@@ -618,6 +666,11 @@ def main():
     if args.flop_table:
         from paper_2112_14064_amd import riga
         flop_table(riga)
+        return
+    if args.flop_test:
+        from paper_2112_14064_amd import riga
+        riga.load()
+        flop_test(torch, riga)
         return
 
     from paper_2112_14064_amd import riga

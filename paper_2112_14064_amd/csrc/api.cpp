@@ -1873,7 +1873,9 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
       const double vec = (double)kr.n_fb;                 // vectors through the operator
       const double passes = vec / b * (1.0 + irs);        // sweep passes over the factor
       S.bytes[RIGA_PHASE_FB] = passes * h->solve_bytes_now + vec * (1.0 + irs) * 16.0 * Nd;
-      S.flops[RIGA_PHASE_FB] = vec * (1.0 + irs) * 4.0 * (double)Pm.sym_nnz_l;
+      // (a complex target: the real form's two dense triangles, 2 flops per entry and vector)
+      S.flops[RIGA_PHASE_FB] = h->cmode ? vec * 2.0 * h->solve_bytes_now / 8.0
+                                        : vec * (1.0 + irs) * 4.0 * (double)Pm.sym_nnz_l;
       const double mv_bytes = 16.0 * Nd + (h->c_elem ? 8.0 * nnz + 16.0 * Nd : 16.0 * Nd);
       S.bytes[RIGA_PHASE_MV] = vec * mv_bytes;
       S.flops[RIGA_PHASE_MV] = (double)kr.n_mv * 2.0 * nnz;
