@@ -2,7 +2,8 @@
 // tests/test_host_sanitizers.py with the address + undefined-behaviour
 // sanitizers ("asan") or the thread sanitizer ("tsan"):
 //   - the nested-dissection plan (Sec. 3.3 hyperplanes as separators), its
-//     symbolic Cholesky and the forest merge of the batched form;
+//     symbolic Cholesky and the forest merge of the batched form; the
+//     curl-conforming plan and the real form of a complex system;
 //   - the dense real Schur form of a projected matrix (eq. ArnoldiRitz) and
 //     the reordering of the Krylov--Schur restart (Sec. 4.1.3);
 //   - the symmetric Jacobi eigensolver of the Lanczos slices (Sec. 4.1.2);
@@ -73,6 +74,35 @@ void plans() {
   }
   check(F.ndof == tot && db.back() == tot, "forest dofs");
   check(F.sym_nnz_l == nzs, "forest symbolic total");
+}
+
+// The curl-conforming plan (explicit columns) and the real form of a complex
+// system on a plan (two unknowns per dof): every coupling a full 2 x 2 block,
+// the same tree with fronts exactly twice as large, a dof's two unknowns
+// eliminated at the same node.
+void realform_plans() {
+  riga::Plan bases[3];
+  check(bases[0].build(2, 16, 4, 0) == 0, "scalar plan");
+  check(bases[1].build(3, 24, 0, 8) == 0, "scalar IGA plan");
+  check(bases[2].build_hcurl(3, 16, 8, 0, true) == 0, "curl-conforming plan");
+  for (const riga::Plan& b : bases) {
+    riga::Plan r;
+    check(r.build_realform(b) == 0, "real-form plan");
+    check(r.ndof == 2 * b.ndof && r.nnz == 4 * b.nnz, "real-form sizes");
+    check(r.nodes.size() == b.nodes.size(), "real-form tree");
+    for (size_t v = 0; v < b.nodes.size() && v < r.nodes.size(); ++v)
+      check(r.no[v] == 2 * b.no[v] && r.nb[v] == 2 * b.nb[v], "real-form fronts");
+    for (int64_t d = 0; d < b.ndof; ++d) {
+      check(r.node_of_dof[2 * d] == r.node_of_dof[2 * d + 1], "unknowns of a dof together");
+      const int64_t len = b.rowptr[d + 1] - b.rowptr[d];
+      check(r.rowptr[2 * d] == 4 * b.rowptr[d] && r.rowptr[2 * d + 1] - r.rowptr[2 * d] == 2 * len,
+            "real-form rows");
+    }
+    for (int64_t i = 0; i < r.ndof; ++i)
+      for (int64_t q = r.rowptr[i] + 1; q < r.rowptr[i + 1]; ++q) check(r.col[q] > r.col[q - 1], "columns ascend");
+    riga::Plan twice;
+    check(twice.build_realform(r) != 0, "no real form of a real form");
+  }
 }
 
 void dense_eig(std::mt19937_64& rng) {
@@ -205,6 +235,7 @@ int main(int argc, char** argv) {
   std::mt19937_64 rng(12345);
   if (!tsan) {
     plans();
+    realform_plans();
     dense_eig(rng);
     symmetric_eig(rng);
     krylov_schur_cycle(rng);
