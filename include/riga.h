@@ -287,9 +287,10 @@ riga_status riga_factor(riga_problem* h, double sigma, int64_t* bad_pivot);
  * in conjugate pairs); each is the root of u^T Q(lam) u = 0 whose psi is
  * nearest the Ritz value.  An eigenvalue on the circle |lam - a| = b has a
  * real psi shared with its conjugate and is resolved only as a pair.
- * Not with RIGA_EIGS_TOAR, riga_solve_q, riga_apply_op or riga_adjoint
- * (RIGA_ERR_INVALID_ARG / RIGA_ERR_STATE); riga_solve_q_complex solves with the
- * complex factor.  The second factor (four times the entries of a real
+ * Not with RIGA_EIGS_TOAR (RIGA_ERR_INVALID_ARG), riga_solve_q, riga_solve_q_noalloc,
+ * riga_apply_op, riga_autotune or riga_time_kernel (RIGA_ERR_STATE: they use a real
+ * factor); riga_solve_q_complex solves with the complex factor.  riga_adjoint
+ * takes the returned pairs like any others.  The second factor (four times the entries of a real
  * Cholesky factor of the space, two triangles) and its workspace are
  * allocated at the first call and kept.  On RIGA_ERR_NOT_SPD, *bad_pivot
  * receives the dof of the failed pivot.  Synchronises.  riga_assemble,
