@@ -29,6 +29,9 @@ Modules
     gyro      damping with a skew-symmetric (gyroscopic) part G_ab = int B_a (g . grad B_b):
               element assembly, the 1-D skew matrix, eigenvalues from the 1-D QEPs
               of the y-modes (gy = 0)
+    hdiv      the divergence-conforming space S^{p,p-1} x S^{p-1,p} and the vibroacoustic QEP
+              (Sec. 2.2): element assembly of div-div and mass matrices, the absorbing-wall
+              integrals, the rotation to the curl-conforming space
     cshift    a complex target shift: the eigenvalues of largest |psi| for the real
               part of the shift-and-invert operator (closed forms on the scalar and
               curl-conforming spaces, ARPACK's real-part mode)
