@@ -80,7 +80,18 @@ typedef enum {
  *                DiscreteSpacesrIGA); the tangential component vanishes on
  *                the boundary (the degree-p factor loses its end functions).
  *                RIGA_SPACE_HCURL_FREE (2): the same space without boundary
- *                condition (the matrices of fig. MatPatterns).  Vector spaces
+ *                condition (the matrices of fig. MatPatterns).
+ *                RIGA_SPACE_HDIV (3): the divergence-conforming space
+ *                S^{p,p-1} x S^{p-1,p} of eq. HdivBasis (the curl-conforming
+ *                one rotated by 90 degrees), the same hyperplanes and dof
+ *                layout, for the vibroacoustic model of Sec. 2.2: a rigid
+ *                wall (u.n = 0) removes the degree-p function of the normal
+ *                direction that is nonzero on it, an absorbing wall (a bit of
+ *                `walls`) keeps it; riga_assemble then forms, with rho = c =
+ *                1 and damping->alpha, damping->beta the wall coefficients of
+ *                eq. HdivStrong, K = int div u div v + alpha G, M = int u . v,
+ *                C = beta G, G = int over the absorbing walls of (u.n)(v.n)
+ *                (eq. HdivWeak).  Vector spaces
  *                need p >= 2 and are assembled with K = int rot u rot v,
  *                M = int u . v (rot u = du_y/dx - du_x/dy), C = alpha M +
  *                beta K; they support riga_factor, the solves, the
@@ -92,10 +103,16 @@ typedef enum {
 typedef struct {
   int p, ne, hyper_every, leaf;
   int space;
+  int walls;   /* RIGA_SPACE_HDIV: absorbing walls, RIGA_WALL_* bits; 0 otherwise */
 } riga_mesh;
 #define RIGA_SPACE_H1 0
 #define RIGA_SPACE_HCURL 1
 #define RIGA_SPACE_HCURL_FREE 2
+#define RIGA_SPACE_HDIV 3
+#define RIGA_WALL_LEFT 1     /* x = 0 */
+#define RIGA_WALL_RIGHT 2    /* x = 1 */
+#define RIGA_WALL_BOTTOM 4   /* y = 0 */
+#define RIGA_WALL_TOP 8      /* y = 1 */
 
 /* Damping C = alpha M + beta K + sum_e c_e M_e (Rayleigh part plus an optional
  * per-element viscous field).  c_elem: device, ne*ne doubles indexed

@@ -293,6 +293,19 @@ void setup_ell(riga_problem* h, const std::vector<int4>& ranges) {
   h->d_space1 = h->upload(std::vector<riga::DevSpace>{h->ds});
 }
 
+// The plan of a mesh: the scalar space, the curl-conforming or the
+// divergence-conforming one (riga_mesh.space); 0 on success.
+int build_plan(riga::Plan& P, const riga_mesh& m) {
+  switch (m.space) {
+    case RIGA_SPACE_H1: return m.walls == 0 ? P.build(m.p, m.ne, m.hyper_every, m.leaf) : -1;
+    case RIGA_SPACE_HCURL:
+    case RIGA_SPACE_HCURL_FREE:
+      return m.walls == 0 ? P.build_hcurl(m.p, m.ne, m.hyper_every, m.leaf, m.space == RIGA_SPACE_HCURL) : -1;
+    case RIGA_SPACE_HDIV: return P.build_hdiv(m.p, m.ne, m.hyper_every, m.leaf, m.walls);
+    default: return -1;
+  }
+}
+
 void setup_device(riga_problem* h) {
     const riga::Plan& P = h->plan;
     const riga::Space1D& S = P.sp;
@@ -309,6 +322,13 @@ void setup_device(riga_problem* h) {
         std::vector<double> MA, MB, KB, D;
         hcurl_1d(P.cx[0], P.cy[0], MA, MB, KB, D);   // A = S^{p-1} (x of component 0), B = S^p
         h->d_hMA = h->upload(MA); h->d_hMB = h->upload(MB); h->d_hKB = h->upload(KB); h->d_hD = h->upload(D);
+      } else if (P.kind == riga::SPACE_HDIV) {
+        // A = S^{p-1} (y of component 0); B = S^p of x (component 0) and of y (component 1)
+        std::vector<double> MA, MB, KB, D;
+        hcurl_1d(P.cy[0], P.cx[0], MA, MB, KB, D);
+        h->d_hMA = h->upload(MA); h->d_hMB = h->upload(MB); h->d_hKB = h->upload(KB); h->d_hD = h->upload(D);
+        hcurl_1d(P.cx[1], P.cy[1], MA, MB, KB, D);
+        h->d_hMBy = h->upload(MB); h->d_hKBy = h->upload(KB); h->d_hDy = h->upload(D);
       }
     }
     h->dt.nf = h->upload(P.nf); h->dt.no = h->upload(P.no); h->dt.nb = h->upload(P.nb);
@@ -459,13 +479,7 @@ riga_status riga_create(riga_problem** out, const riga_mesh* mesh, int device, v
   riga_problem* h = new (std::nothrow) riga_problem();
   if (!h) return RIGA_ERR_OOM;
   h->mesh = *mesh;
-  const int kind = mesh->space;
-  const int built = kind == RIGA_SPACE_H1
-                        ? h->plan.build(mesh->p, mesh->ne, mesh->hyper_every, mesh->leaf)
-                        : (kind == RIGA_SPACE_HCURL || kind == RIGA_SPACE_HCURL_FREE)
-                              ? h->plan.build_hcurl(mesh->p, mesh->ne, mesh->hyper_every, mesh->leaf,
-                                                    kind == RIGA_SPACE_HCURL)
-                              : -1;
+  const int built = build_plan(h->plan, *mesh);
   if (built != 0) {
     delete h;
     return RIGA_ERR_INVALID_ARG;
@@ -533,11 +547,7 @@ riga_status riga_symbolic(const riga_mesh* mesh, int64_t* ndof, int64_t* order, 
   if (!mesh) return RIGA_ERR_INVALID_ARG;
   return run([&]() -> riga_status {
     riga::Plan P;
-    const int kind = mesh->space;
-    const int built = kind == RIGA_SPACE_H1 ? P.build(mesh->p, mesh->ne, mesh->hyper_every, mesh->leaf)
-                      : (kind == RIGA_SPACE_HCURL || kind == RIGA_SPACE_HCURL_FREE)
-                          ? P.build_hcurl(mesh->p, mesh->ne, mesh->hyper_every, mesh->leaf, kind == RIGA_SPACE_HCURL)
-                          : -1;
+    const int built = build_plan(P, *mesh);
     if (built != 0) return RIGA_ERR_INVALID_ARG;
     if (ndof) *ndof = P.ndof;
     std::vector<int64_t> cc;
@@ -565,9 +575,14 @@ riga_status assemble_impl(riga_problem* h, const riga_damping* damping, double g
     if (h->plan.kind != riga::SPACE_H1) {
       const riga::Plan& P = h->plan;
       ck(hipEventRecord(h->ev0, h->st));
-      riga::launch_assemble_hcurl(P.cx[0].n, P.cx[1].n, P.cbase[1], P.ndof, h->ds.rowptr, h->ds.col, h->d_hMA,
-                                  h->d_hMB, h->d_hKB, h->d_hD, damping->alpha, damping->beta, h->d_K, h->d_M,
-                                  h->d_C, h->st);
+      if (P.kind == riga::SPACE_HDIV)
+        riga::launch_assemble_hdiv(P.cy[0].n, P.cx[0].n, P.cy[1].n, P.cbase[1], P.ndof, h->ds.rowptr, h->ds.col,
+                                   h->d_hMA, h->d_hMB, h->d_hKB, h->d_hD, h->d_hMBy, h->d_hKBy, h->d_hDy, P.walls,
+                                   damping->alpha, damping->beta, h->d_K, h->d_M, h->d_C, h->st);
+      else
+        riga::launch_assemble_hcurl(P.cx[0].n, P.cx[1].n, P.cbase[1], P.ndof, h->ds.rowptr, h->ds.col, h->d_hMA,
+                                    h->d_hMB, h->d_hKB, h->d_hD, damping->alpha, damping->beta, h->d_K, h->d_M,
+                                    h->d_C, h->st);
       ck(hipGetLastError());
       ck(hipEventRecord(h->ev1, h->st));
       h->gyro = false; h->gx = h->gy = 0.0;

@@ -381,6 +381,75 @@ __global__ __launch_bounds__(ASM_THREADS) void k_assemble_hcurl(int na, int nb, 
   }
 }
 
+// Rows of the divergence-conforming space S^{p,p-1} x S^{p-1,p} (eq.
+// HdivBasis) and the vibroacoustic forms of Sec. 2.2 (rho = c = 1): component 0
+// is Bx_i(x) A_j(y), component 1 is A_i(x) By_j(y), div u = d/dx of component
+// 0 plus d/dy of component 1, so on the identity geometry
+//   K00 = KBx (x) MA,  K11 = MA (x) KBy,
+//   K01 = Dx[ii][i] Dy[j][jj],  K10 = Dx[i][ii] Dy[jj][j]   (D = int A B'),
+//   M00 = MBx (x) MA,  M11 = MA (x) MBy,  M01 = M10 = 0,
+// plus the absorbing walls' G = int (u.n)(v.n): on an x wall the end function
+// of Bx (1 there) times MA in y, on a y wall MA in x times the end function of
+// By; K = Kdiv + alpha G, M, C = beta G.  One wave per row (see k_assemble).
+__global__ __launch_bounds__(ASM_THREADS) void k_assemble_hdiv(
+    int na, int nbx, int nby, int64_t base1, int64_t ndof, const int64_t* __restrict__ rowptr,
+    const int* __restrict__ col, const double* __restrict__ MA, const double* __restrict__ MBx,
+    const double* __restrict__ KBx, const double* __restrict__ Dx, const double* __restrict__ MBy,
+    const double* __restrict__ KBy, const double* __restrict__ Dy, int wl, int wr, int wb, int wt, double alpha,
+    double beta, double* __restrict__ Ko, double* __restrict__ Mo, double* __restrict__ Co) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r0 = ((int64_t)blockIdx.x * ASM_WAVES + wave) * ASM_ROWS_PER_WAVE;
+  for (int qr = 0; qr < ASM_ROWS_PER_WAVE; ++qr) {
+    const int64_t r = r0 + qr;
+    if (r >= ndof) break;
+    const int c = r >= base1 ? 1 : 0;
+    const int64_t rr = r - (c ? base1 : 0);
+    const int nx = c ? na : nbx;
+    const int i = (int)(rr % nx), j = (int)(rr / nx);
+    const int64_t k0 = rowptr[r], k1 = rowptr[r + 1];
+    for (int64_t k = k0 + lane; k < k1; k += 64) {
+      const int64_t cc = col[k];
+      const int b = cc >= base1 ? 1 : 0;
+      const int64_t cr = cc - (b ? base1 : 0);
+      const int mx = b ? na : nbx;
+      const int ii = (int)(cr % mx), jj = (int)(cr / mx);
+      double kv, mv, gv = 0.0;
+      if (c == 0 && b == 0) {
+        kv = KBx[(int64_t)i * nbx + ii] * MA[(int64_t)j * na + jj];
+        mv = MBx[(int64_t)i * nbx + ii] * MA[(int64_t)j * na + jj];
+        // x walls: the first (left) or last (right) kept function of Bx
+        const bool lw = wl && i == 0 && ii == 0, rw = wr && i == nbx - 1 && ii == nbx - 1;
+        if (lw || rw) gv = MA[(int64_t)j * na + jj] * ((lw ? 1.0 : 0.0) + (rw ? 1.0 : 0.0));
+      } else if (c == 1 && b == 1) {
+        kv = MA[(int64_t)i * na + ii] * KBy[(int64_t)j * nby + jj];
+        mv = MA[(int64_t)i * na + ii] * MBy[(int64_t)j * nby + jj];
+        const bool bw = wb && j == 0 && jj == 0, tw = wt && j == nby - 1 && jj == nby - 1;
+        if (bw || tw) gv = MA[(int64_t)i * na + ii] * ((bw ? 1.0 : 0.0) + (tw ? 1.0 : 0.0));
+      } else if (c == 0) {
+        kv = Dx[(int64_t)ii * nbx + i] * Dy[(int64_t)j * nby + jj];
+        mv = 0.0;
+      } else {
+        kv = Dx[(int64_t)i * nbx + ii] * Dy[(int64_t)jj * nby + j];
+        mv = 0.0;
+      }
+      Ko[k] = kv + alpha * gv;
+      Mo[k] = mv;
+      Co[k] = beta * gv;
+    }
+  }
+}
+
+void launch_assemble_hdiv(int na, int nbx, int nby, int64_t base1, int64_t ndof, const int64_t* rowptr,
+                          const int* col, const double* MA, const double* MBx, const double* KBx, const double* Dx,
+                          const double* MBy, const double* KBy, const double* Dy, int walls, double alpha,
+                          double beta, double* K, double* M, double* C, hipStream_t st) {
+  const int64_t rows = (int64_t)ASM_WAVES * ASM_ROWS_PER_WAVE;
+  const int64_t blocks = (ndof + rows - 1) / rows;
+  hipLaunchKernelGGL(k_assemble_hdiv, dim3((unsigned)blocks), dim3(ASM_THREADS), 0, st, na, nbx, nby, base1, ndof,
+                     rowptr, col, MA, MBx, KBx, Dx, MBy, KBy, Dy, walls & 1, (walls >> 1) & 1, (walls >> 2) & 1,
+                     (walls >> 3) & 1, alpha, beta, K, M, C);
+}
+
 void launch_assemble_hcurl(int na, int nb, int64_t base1, int64_t ndof, const int64_t* rowptr, const int* col,
                            const double* MA, const double* MB, const double* KB, const double* D, double alpha,
                            double beta, double* K, double* M, double* C, hipStream_t st) {

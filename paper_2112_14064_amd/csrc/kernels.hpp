@@ -77,6 +77,14 @@ void launch_assemble(const DevSpace& s, const double* tabM, const double* M1, co
 void launch_assemble_hcurl(int na, int nb, int64_t base1, int64_t ndof, const int64_t* rowptr, const int* col,
                            const double* MA, const double* MB, const double* KB, const double* D, double alpha,
                            double beta, double* K, double* M, double* C, hipStream_t st);
+// Divergence-conforming space (see k_assemble.hip): K = div-div + alpha G,
+// M, C = beta G with G the absorbing walls' normal-component integral (walls:
+// bits left, right, bottom, top); 1-D matrices of A (na) and of the x / y
+// degree-p spaces (nbx, nby kept functions).
+void launch_assemble_hdiv(int na, int nbx, int nby, int64_t base1, int64_t ndof, const int64_t* rowptr,
+                          const int* col, const double* MA, const double* MBx, const double* KBx, const double* Dx,
+                          const double* MBy, const double* KBy, const double* Dy, int walls, double alpha,
+                          double beta, double* K, double* M, double* C, hipStream_t st);
 // Bands of every problem of a forest: problem q's tables at taboff[q], its
 // bands at bandoff[q] (max_w: the largest n (2p + 1)).
 void launch_band_1d_b(const DevSpace* spaces, int n, int max_w, const int64_t* taboff, const double* tabM,

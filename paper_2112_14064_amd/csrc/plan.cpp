@@ -16,9 +16,13 @@
 namespace riga {
 
 void Space1D::build(int p_, int ne_, int s_, int mult_, bool dirichlet) {
+  build_ends(p_, ne_, s_, mult_, dirichlet, dirichlet);
+}
+
+void Space1D::build_ends(int p_, int ne_, int s_, int mult_, bool drop_first, bool drop_last) {
   p = p_; ne = ne_; s = s_;
   mult = mult_ < 0 ? p : mult_;
-  off = dirichlet ? 1 : 0;
+  off = drop_first ? 1 : 0;
   knots.clear();
   for (int i = 0; i <= p; ++i) knots.push_back(0);
   for (int k = 1; k < ne; ++k) {
@@ -27,7 +31,7 @@ void Space1D::build(int p_, int ne_, int s_, int mult_, bool dirichlet) {
   }
   for (int i = 0; i <= p; ++i) knots.push_back(ne);
   nall = (int)knots.size() - p - 1;
-  n = nall - 2 * off;
+  n = nall - off - (drop_last ? 1 : 0);
   sup0.resize(n); sup1.resize(n);
   for (int d = 0; d < n; ++d) {
     sup0[d] = knots[d + off];
@@ -259,8 +263,6 @@ int Plan::build(int p, int ne, int s, int leaf) {
 int Plan::build_hcurl(int p, int ne, int s, int leaf, bool pec) {
   if (p < 2 || p > 8 || ne < 2) return -1;
   if (s < 0 || (s > 0 && ne % s != 0)) return -1;
-  if (leaf <= 0) leaf = 8;
-  leaf_size = leaf;
   kind = pec ? SPACE_HCURL : SPACE_HCURL_FREE;
   // component 0: S^{p-1} (x) S^p (eq. HcurlBasis), component 1: S^p (x) S^{p-1};
   // both degrees carry the hyperplane knots with multiplicity p - 1
@@ -268,14 +270,35 @@ int Plan::build_hcurl(int p, int ne, int s, int leaf, bool pec) {
   cy[0].build(p, ne, s, p - 1, pec);
   cx[1].build(p, ne, s, p - 1, pec);
   cy[1].build(p - 1, ne, s, p - 1, false);
+  return build_vector(ne, s, leaf);
+}
+
+int Plan::build_hdiv(int p, int ne, int s, int leaf, int absorbing) {
+  if (p < 2 || p > 8 || ne < 2 || absorbing < 0 || absorbing > 15) return -1;
+  if (s < 0 || (s > 0 && ne % s != 0)) return -1;
+  kind = SPACE_HDIV;
+  walls = absorbing;
+  // component 0: S^p (x) S^{p-1} (eq. HdivBasis), component 1: S^{p-1} (x) S^p;
+  // the normal direction's end functions go with the rigid walls
+  cx[0].build_ends(p, ne, s, p - 1, !(absorbing & WALL_LEFT), !(absorbing & WALL_RIGHT));
+  cy[0].build(p - 1, ne, s, p - 1, false);
+  cx[1].build(p - 1, ne, s, p - 1, false);
+  cy[1].build_ends(p, ne, s, p - 1, !(absorbing & WALL_BOTTOM), !(absorbing & WALL_TOP));
+  return build_vector(ne, s, leaf);
+}
+
+int Plan::build_vector(int ne, int s, int leaf) {
+  if (leaf <= 0) leaf = 8;
+  leaf_size = leaf;
   for (int c = 0; c < 2; ++c)
     if (cx[c].n < 1 || cy[c].n < 1) return -1;
   cbase[0] = 0;
   cbase[1] = (int64_t)cx[0].n * cy[0].n;
   cbase[2] = cbase[1] + (int64_t)cx[1].n * cy[1].n;
   ndof = cbase[2];
-  n1d = cx[1].n;
-  sp = cx[1];
+  // the degree-p space of the x direction stands for the mesh (sp.ne, sp.s)
+  sp = kind == SPACE_HDIV ? cx[0] : cx[1];
+  n1d = sp.n;
   // coupled functions of space b for every function of space a: supports
   // overlapping on a set of positive length, a contiguous range (supports
   // ordered by their starts and ends)

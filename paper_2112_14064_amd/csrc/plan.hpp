@@ -32,12 +32,17 @@ struct Space1D {
   std::vector<int> first;      // per element: full index of its first nonzero function
   // mult_ < 0: p (C^0 hyperplanes); dirichlet: remove the first and last function
   void build(int p_, int ne_, int s_, int mult_ = -1, bool dirichlet = true);
+  // the same with each end function removed or kept on its own
+  void build_ends(int p_, int ne_, int s_, int mult_, bool drop_first, bool drop_last);
 };
 
 // Kinds of discrete space (riga_mesh.space).  SPACE_REALFORM is internal: the
 // real form of a complex system on another plan's space (two unknowns per
 // dof, see Plan::build_realform).
-enum SpaceKind { SPACE_H1 = 0, SPACE_HCURL = 1, SPACE_HCURL_FREE = 2, SPACE_REALFORM = 3 };
+enum SpaceKind { SPACE_H1 = 0, SPACE_HCURL = 1, SPACE_HCURL_FREE = 2, SPACE_HDIV = 3, SPACE_REALFORM = 16 };
+// Walls of the unit square (riga_mesh.walls, the absorbing ones of the
+// divergence-conforming space).
+enum Wall { WALL_LEFT = 1, WALL_RIGHT = 2, WALL_BOTTOM = 4, WALL_TOP = 8 };
 
 struct Node {
   int x0, x1, y0, y1;          // box in element units
@@ -59,6 +64,7 @@ struct Plan {
   // has the tensor space cx[c] (x) cy[c], its dofs at cbase[c] + j n_x + i;
   // the CSR column indices are explicit (col).  Empty for the scalar space.
   int kind = SPACE_H1;
+  int walls = 0;               // SPACE_HDIV: the absorbing walls (Wall bits)
   int leaf_size = 8;           // the leaf length the tree was built with
   Space1D cx[2], cy[2];
   int64_t cbase[3] = {0, 0, 0};
@@ -96,6 +102,11 @@ struct Plan {
   // on the boundary (the degree-p factor loses its end functions), else no
   // boundary condition.  p >= 2.
   int build_hcurl(int p, int ne, int s, int leaf, bool pec);
+  // H(div) space S^{p,p-1} x S^{p-1,p} (eq. HdivBasis), the same hyperplanes;
+  // a rigid wall (bit clear in `absorbing`) removes the degree-p function of
+  // the normal direction that is nonzero on it (u.n = 0), an absorbing wall
+  // keeps it.  p >= 2.
+  int build_hdiv(int p, int ne, int s, int leaf, int absorbing);
   // The real form of a complex system on base's space: dof d of base becomes
   // the unknowns 2d (real part) and 2d + 1 (imaginary part), every coupling
   // of base a full 2 x 2 block; explicit columns; the same tree of boxes
@@ -129,6 +140,8 @@ struct Plan {
   // ndof, rowptr and the dofs' supports and neighbours.
   template <class Sup, class Nb>
   int finish(int ne, int s, int leaf, Sup support, Nb neighbours);
+  // vector space from its four component spaces (set in cx, cy) and kind
+  int build_vector(int ne, int s, int leaf);
 };
 
 }  // namespace riga

@@ -48,6 +48,9 @@ struct riga_problem {
   // H(curl) space: dense 1-D matrices of the degree-(p-1) space A and the
   // degree-p space B (MA, MB, KB, D = int A_a B_b')
   double *d_hMA = nullptr, *d_hMB = nullptr, *d_hKB = nullptr, *d_hD = nullptr;
+  // H(div) space: the degree-p space of y differs from that of x (walls):
+  // its MB, KB and D (the x ones above)
+  double *d_hMBy = nullptr, *d_hKBy = nullptr, *d_hDy = nullptr;
   bool gyro = false;
   double gx = 0.0, gy = 0.0;
   // Complex target shift sigma + i csig_im (riga_factor_complex; then
@@ -187,6 +190,8 @@ riga_status run(const std::function<riga_status()>& f);
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 // Canonical order: increasing |lam - sigma|, clusters by decreasing Im, then Re.
 std::vector<int> canonical_order(const std::vector<cplx>& lam, double sigma);
+// The plan of a mesh (scalar, curl- or divergence-conforming space); 0 on success.
+int build_plan(riga::Plan& P, const riga_mesh& m);
 // Upload h->plan and allocate every device array of the handle.
 void setup_device(riga_problem* h);
 // Sliced-ELL slabs over the row ranges {problem, first row, end row} and the

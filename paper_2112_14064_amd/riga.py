@@ -26,11 +26,13 @@ RIGA_WARN_NOT_CONVERGED = 1
 RIGA_WARN_IR_STAGNATED = 2
 RIGA_IR_MAX = 10
 RIGA_EIGS_TOAR = 4   # riga_options.flags: compact two-level Krylov basis
-RIGA_SPACE_H1, RIGA_SPACE_HCURL, RIGA_SPACE_HCURL_FREE = 0, 1, 2   # riga_mesh.space
+RIGA_SPACE_H1, RIGA_SPACE_HCURL, RIGA_SPACE_HCURL_FREE, RIGA_SPACE_HDIV = 0, 1, 2, 3   # riga_mesh.space
+RIGA_WALL_LEFT, RIGA_WALL_RIGHT, RIGA_WALL_BOTTOM, RIGA_WALL_TOP = 1, 2, 4, 8   # riga_mesh.walls
 
 
 class riga_mesh(C.Structure):
-    _fields_ = [("p", C.c_int), ("ne", C.c_int), ("hyper_every", C.c_int), ("leaf", C.c_int), ("space", C.c_int)]
+    _fields_ = [("p", C.c_int), ("ne", C.c_int), ("hyper_every", C.c_int), ("leaf", C.c_int), ("space", C.c_int),
+                ("walls", C.c_int)]
 
 
 class riga_damping(C.Structure):
@@ -152,12 +154,12 @@ def _stats_dict(s) -> dict:
     return out
 
 
-def riga_symbolic(p: int, ne: int, hyper_every: int, leaf: int = 0, space: int = 0):
+def riga_symbolic(p: int, ne: int, hyper_every: int, leaf: int = 0, space: int = 0, walls: int = 0):
     """Host-only symbolic Cholesky of Q's sparsity under the library's
     elimination order: (order, colcount, nnz_l, flops), order[k] the dof
     eliminated k-th and colcount[k] the nonzeros of column k of L."""
     lib = load()
-    mesh = riga_mesh(p, ne, hyper_every, leaf, space)
+    mesh = riga_mesh(p, ne, hyper_every, leaf, space, walls)
     n = C.c_int64(0)
     _check(lib.riga_symbolic(C.byref(mesh), C.byref(n), None, None, None, None), "riga_symbolic")
     order = np.zeros(n.value, dtype=np.int64)
@@ -221,7 +223,7 @@ class Problem:
     """One discretised QEP on one device (owns a riga_problem handle)."""
 
     def __init__(self, p: int, ne: int, hyper_every: int, leaf: int = 0, device: int = 0, stream=None,
-                 space: int = 0):
+                 space: int = 0, walls: int = 0):
         import torch
 
         self.torch = torch
@@ -231,8 +233,8 @@ class Problem:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
         self.h = C.c_void_p()
-        mesh = riga_mesh(p, ne, hyper_every, leaf, space)
-        self.p, self.ne, self.hyper_every, self.space = p, ne, hyper_every, space
+        mesh = riga_mesh(p, ne, hyper_every, leaf, space, walls)
+        self.p, self.ne, self.hyper_every, self.space, self.walls = p, ne, hyper_every, space, walls
         _check(self.lib.riga_create(C.byref(self.h), C.byref(mesh), device, C.c_void_p(stream.cuda_stream)),
                "riga_create")
         self._c_elem = None
@@ -464,7 +466,7 @@ class Batch:
         arr = (riga_mesh * self.n)()
         for i, m in enumerate(meshes):
             m = tuple(m) + (0,) * (4 - len(m))
-            arr[i] = riga_mesh(*[int(x) for x in m[:4]], 0)
+            arr[i] = riga_mesh(*[int(x) for x in m[:4]], 0, 0)
         self.meshes = [tuple(m) for m in meshes]
         self.h = C.c_void_p()
         _check(self.lib.riga_batch_create(C.byref(self.h), self.n, C.cast(arr, C.c_void_p), device,
