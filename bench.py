@@ -23,13 +23,15 @@ the full basis, and the headline mesh with a gyroscopic (skew) part in the
 damping, factored by LU.  The curl-conforming vector space (p=3, 256^2, perfect
 conductor) closes the run: factorization, FB elimination and Maxwell spectrum
 slicing, rIGA against IGA, and its conductive QEP at the complex target 7i
-(the real part of the shift-and-invert operator).  `--flop-table` prints the host-side symbolic cost
+(the real part of the shift-and-invert operator); the vibroacoustic cavity on
+the divergence-conforming space (absorbing top wall) at 0.5 + 7i.  `--flop-table` prints the host-side symbolic cost
 ratios of that space for p = 3..6 (the quantities of tab:FlopTest) and exits;
 `--flop-test` runs that space's conductive QEP at the target 7i for p = 3..5 on
 the device (100 pairs) and prints the same ratios from the runs' counts and times.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-iga] [--no-mixed] [--no-batch]
-                       [--no-undamped] [--no-toar] [--no-gyro] [--no-hcurl] [--no-em] [--basis full|toar]
+                       [--no-undamped] [--no-toar] [--no-gyro] [--no-hcurl] [--no-em] [--no-vibro]
+                       [--basis full|toar]
                        [--flop-table] [--flop-test]
 """
 from __future__ import annotations
@@ -466,16 +468,19 @@ def flop_table(riga, nes=(256, 1024), degrees=(3, 4, 5, 6)):
     return rows
 
 
-def complex_target_form(torch, riga, W, steps, block):
-    """The conductive electromagnetic QEP on the curl-conforming space (p=3,
-    256^2, perfect conductor), rIGA and IGA, at the complex target 7i: the
-    real form of Q(sigma) factored by LU, the eigensolve on the real part of
-    the operator; one step = assemble + factor + eigensolve, timed like the
+def complex_target_form(torch, riga, W, steps, block, cfg=None):
+    """A QEP at a complex target, rIGA and IGA: by default the conductive
+    electromagnetic QEP on the curl-conforming space (p=3, 256^2, perfect
+    conductor) at 7i, else the workload `cfg` gives (the vibroacoustic cavity);
+    the real form of Q(sigma) factored by LU, the eigensolve on the real part
+    of the operator; one step = assemble + factor + eigensolve, timed like the
     headline step."""
+    if cfg is None:
+        cfg = W.cfg_em_qep
     out, lams = {}, {}
     for s in (16, 0):
-        P = W.cfg_em_qep(s)
-        pr = riga.Problem(P.p, P.ne, P.hyper_every, space=P.extra["space"])
+        P = cfg(s)
+        pr = riga.Problem(P.p, P.ne, P.hyper_every, space=P.extra["space"], walls=P.extra.get("walls", 0))
         info = pr.info
         sig = P.extra["sigma_c"]
 
@@ -493,10 +498,13 @@ def complex_target_form(torch, riga, W, steps, block):
         ms = (time.perf_counter() - t0) * 1e3 / steps
         stats = pr.stats()
         good = int(sum(1 for e in eta[:nconv] if e <= 1e-10))
+        space = ("H(curl) p={}, {}x{}, perfect conductor".format(P.p, P.ne, P.ne) if P.extra["space"] == 1 else
+                 "H(div) p={}, {}x{}, rigid walls, absorbing top wall (alpha {}, beta {})".format(
+                     P.p, P.ne, P.ne, P.alpha, P.beta))
+        damping = f"C = {P.alpha}M + {P.beta}K, " if P.extra["space"] == 1 else ""
         out["riga" if s else "iga"] = {
-            "workload": f"H(curl) p={P.p}, {P.ne}x{P.ne}, perfect conductor, " + (f"rIGA s={s}" if s else "IGA") +
-                        f", C = {P.alpha}M + {P.beta}K, {P.nev} pairs of largest |psi| at sigma={sig}, "
-                        f"subspace {P.m}",
+            "workload": space + ", " + (f"rIGA s={s}" if s else "IGA") +
+                        f", {damping}{P.nev} pairs of largest |psi| at sigma={sig}, subspace {P.m}",
             "ndof": int(info["ndof"]), "ms_per_step": ms, "eigenpairs_per_s": good * 1e3 / ms, "pairs_ok": good,
             "status": int(st), "factor_ms": stats["t_factor_ms"], "eigs_ms": stats["t_eigs_ms"],
             # the real form: twice the unknowns, LU (two triangles) of the doubled fronts
@@ -570,6 +578,21 @@ def oracle_check_em(lams):
     return res
 
 
+def check_vibroacoustic(lams):
+    """The vibroacoustic leg has no closed form at full size: every returned
+    eigenvalue decays or oscillates without growth (Re lam <= 0, the
+    semidefinite K and C of eq. HdivQuadEig) and the set is closed under
+    conjugation."""
+    import numpy as np
+
+    res = {}
+    for k, (P, lam) in lams.items():
+        scale = np.abs(lam).max()
+        conj_ok = all(np.min(np.abs(lam - np.conj(x))) <= 1e-9 * abs(x) for x in lam[:-2])
+        res[k] = {"max_re_over_abs": float(lam.real.max() / scale), "conjugate_closed": bool(conj_ok)}
+    return res
+
+
 def oracle_check_hcurl(mus):
     """Count and eigenvalues of the Maxwell slices of the vector-space leg
     against the oracle's closed form (sums of 1-D values)."""
@@ -640,6 +663,7 @@ def main():
     ap.add_argument("--no-gyro", action="store_true")
     ap.add_argument("--no-hcurl", action="store_true")
     ap.add_argument("--no-em", action="store_true")
+    ap.add_argument("--no-vibro", action="store_true")
     ap.add_argument("--flop-test", action="store_true",
                     help="only run the device analog of tab:FlopTest (the conductive QEP on the curl-conforming "
                          "space at the target 7i, 100 pairs, p = 3..5 on 256^2, rIGA against IGA) and exit")
@@ -733,6 +757,11 @@ def main():
     em = None
     if not args.no_em:
         out["complex_target_form"], em = complex_target_form(torch, riga, W, min(args.steps, 2), args.block)
+    if not args.no_vibro:
+        out["vibroacoustic_form"], vib = complex_target_form(torch, riga, W, min(args.steps, 2), args.block,
+                                                             cfg=W.cfg_vibroacoustic)
+        for k, v in check_vibroacoustic(vib).items():
+            out["vibroacoustic_form"][k].update(v)
     if roof is not None:
         out["roofline"] = roof
     if not args.no_cpu:

@@ -163,3 +163,15 @@ def cfg_em_qep(hyper_every: int = 16) -> Problem:
     tag = f"s{hyper_every}" if hyper_every else "iga"
     return Problem(p=3, ne=256, hyper_every=hyper_every, alpha=0.05, beta=0.005, sigma=7.0, nev=38, m=80,
                    name=f"p3_256x256_{tag}_em_qep", extra={"space": 1, "sigma_c": 7.0j})
+
+
+def cfg_vibroacoustic(hyper_every: int = 16) -> Problem:
+    """The vibroacoustic QEP of an acoustic cavity (the divergence-conforming
+    space S^{3,2} x S^{2,3}, p=3, on 256x256): rigid walls except an absorbing
+    top wall with coefficients alpha = 0.5, beta = 0.8 (rho = c = 1), rIGA
+    (C^1/C^0 hyperplanes every 16 elements) or IGA (hyper_every=0); the 40
+    pairs of largest |psi| at the complex target 0.5 + 7i, subspace 80."""
+    tag = f"s{hyper_every}" if hyper_every else "iga"
+    return Problem(p=3, ne=256, hyper_every=hyper_every, alpha=0.5, beta=0.8, sigma=0.5, nev=40, m=80,
+                   name=f"p3_256x256_{tag}_vibroacoustic",
+                   extra={"space": 3, "walls": 8, "sigma_c": 0.5 + 7.0j})
