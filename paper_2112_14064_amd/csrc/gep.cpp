@@ -291,6 +291,145 @@ void rayleigh_quotients(riga_problem* h, int n, const double* U, double* mu) {
   }
 }
 
+// Near-degenerate groups of returned values (consecutive, spacing below
+// 1e-6 relative, at most 8): a slice resolves its Ritz vectors to its own
+// tolerance relative to its largest |theta|, and vectors of values closer than
+// that can be mixtures within their group, whose span is nevertheless accurate.
+// Rayleigh-Ritz with K and M on each group's span (a k x k definite pencil,
+// Cholesky of the M block and cyclic Jacobi) separates them: the values and
+// vectors of the group are replaced by its Ritz pairs (M-orthonormal).  A
+// group whose values already agree to 1e-12 is left alone (an exact multiple
+// eigenvalue: any basis of its space is exact).  All groups in one pass: the
+// products [K U_g | M U_g] side by side, their Gram blocks in one download,
+// the rotations in one upload.
+void group_rayleigh_ritz(riga_problem* h, int n, double* U, double* mu) {
+  const int64_t N = h->N();
+  std::vector<std::pair<int, int>> groups;   // (first column, size)
+  int cols = 0;
+  for (int i = 0; i < n;) {
+    int j = i + 1;
+    while (j < n && j - i < 8 && mu[j] - mu[j - 1] <= 1e-6 * std::abs(mu[j])) ++j;
+    if (j - i >= 2 && mu[j - 1] - mu[i] > 1e-12 * std::abs(mu[j - 1])) {
+      groups.push_back({i, j - i});
+      cols += j - i;
+    }
+    i = j;
+  }
+  if (groups.empty()) return;
+  if (h->grp_cols < cols) {
+    if (h->d_grp) h->dfree(h->d_grp);
+    if (h->d_grpG) h->dfree(h->d_grpG);
+    h->d_grp = h->dalloc<double>((size_t)2 * cols * N);
+    h->d_grpG = h->dalloc<double>((size_t)16 * cols + 64);
+    h->grp_cols = cols;
+  }
+  // products and Gram blocks: group g at column offset 2 o_g of d_grp and at
+  // 2 o_g k_g of d_grpG
+  std::vector<int> off(groups.size());
+  int o = 0, go = 0;
+  std::vector<int> goff(groups.size());
+  for (size_t g = 0; g < groups.size(); ++g) {
+    const int i = groups[g].first, k = groups[g].second;
+    off[g] = o;
+    goff[g] = go;
+    double* Uc = U + (size_t)i * N;
+    double* KM = h->d_grp + (size_t)2 * o * N;
+    riga::launch_spmv(h->ds, N, k, h->d_K, 1.0, Uc, N, KM, N, nullptr, 0, 0.0, nullptr, 0, h->st);
+    riga::launch_spmv(h->ds, N, k, h->d_M, 1.0, Uc, N, KM + (size_t)k * N, N, nullptr, 0, 0.0, nullptr, 0, h->st);
+    for (int q0 = 0; q0 < 2 * k; q0 += 4) {
+      const int nq = std::min(4, 2 * k - q0);
+      riga::launch_dots(N, k, Uc, nullptr, N, nq, KM + (size_t)q0 * N, nullptr, N, h->d_part,
+                        h->d_grpG + go + (size_t)k * q0, h->st);
+    }
+    o += k;
+    go += 2 * k * k;
+  }
+  std::vector<double> G((size_t)go);
+  ck(hipMemcpyAsync(G.data(), h->d_grpG, G.size() * sizeof(double), hipMemcpyDeviceToHost, h->st));
+  ck(hipStreamSynchronize(h->st));
+  std::vector<double> Yall((size_t)go / 2, 0.0);   // k x k per group, at goff / 2
+  std::vector<char> done(groups.size(), 0);
+  for (size_t g = 0; g < groups.size(); ++g) {
+    const int i = groups[g].first, k = groups[g].second;
+    const double* Gg = G.data() + goff[g];
+    // chunk q0 holds out[c nq + q] for column c of U_g and column q0 + q
+    std::vector<double> Kc((size_t)k * k), Mc((size_t)k * k);
+    for (int q0 = 0; q0 < 2 * k; q0 += 4) {
+      const int nq = std::min(4, 2 * k - q0);
+      for (int c = 0; c < k; ++c)
+        for (int q = 0; q < nq; ++q) {
+          const int col = q0 + q;
+          const double v = Gg[(size_t)k * q0 + (size_t)c * nq + q];
+          if (col < k) Kc[c + (size_t)col * k] = v; else Mc[c + (size_t)(col - k) * k] = v;
+        }
+    }
+    for (int a = 0; a < k; ++a)
+      for (int b = 0; b < a; ++b) {
+        const double ks = 0.5 * (Kc[a + (size_t)b * k] + Kc[b + (size_t)a * k]);
+        const double ms = 0.5 * (Mc[a + (size_t)b * k] + Mc[b + (size_t)a * k]);
+        Kc[a + (size_t)b * k] = Kc[b + (size_t)a * k] = ks;
+        Mc[a + (size_t)b * k] = Mc[b + (size_t)a * k] = ms;
+      }
+    // Mc = L L^T; the pencil becomes L^{-1} Kc L^{-T}
+    std::vector<double> L((size_t)k * k, 0.0);
+    bool spd = true;
+    for (int c = 0; c < k && spd; ++c) {
+      double d = Mc[c + (size_t)c * k];
+      for (int q = 0; q < c; ++q) d -= L[c + (size_t)q * k] * L[c + (size_t)q * k];
+      if (!(d > 0.0)) { spd = false; break; }
+      d = std::sqrt(d);
+      L[c + (size_t)c * k] = d;
+      for (int r = c + 1; r < k; ++r) {
+        double v = Mc[r + (size_t)c * k];
+        for (int q = 0; q < c; ++q) v -= L[r + (size_t)q * k] * L[c + (size_t)q * k];
+        L[r + (size_t)c * k] = v / d;
+      }
+    }
+    if (!spd) continue;
+    auto lsolve = [&](std::vector<double>& X) {   // X <- L^{-1} X (k columns)
+      for (int col = 0; col < k; ++col)
+        for (int r = 0; r < k; ++r) {
+          double v = X[r + (size_t)col * k];
+          for (int q = 0; q < r; ++q) v -= L[r + (size_t)q * k] * X[q + (size_t)col * k];
+          X[r + (size_t)col * k] = v / L[r + (size_t)r * k];
+        }
+    };
+    std::vector<double> A = Kc;
+    lsolve(A);
+    std::vector<double> At((size_t)k * k);
+    for (int a = 0; a < k; ++a)
+      for (int b = 0; b < k; ++b) At[a + (size_t)b * k] = A[b + (size_t)a * k];
+    lsolve(At);
+    std::vector<double> w, Z;
+    if (riga::sym_eig_jacobi(k, At.data(), w, Z) < 0) continue;
+    std::vector<int> ord(k);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return w[a] < w[b]; });
+    double* Y = Yall.data() + goff[g] / 2;   // L^{-T} Z, columns in ascending order of w
+    for (int c = 0; c < k; ++c) {
+      const int oc = ord[c];
+      for (int r = k - 1; r >= 0; --r) {
+        double v = Z[r + (size_t)oc * k];
+        for (int q = r + 1; q < k; ++q) v -= L[q + (size_t)r * k] * Y[q + (size_t)c * k];
+        Y[r + (size_t)c * k] = v / L[r + (size_t)r * k];
+      }
+      mu[i + c] = w[oc];
+    }
+    done[g] = 1;
+  }
+  // rotations: U_g <- U_g Y_g through the group's first k product columns
+  ck(hipMemcpyAsync(h->d_grpG, Yall.data(), Yall.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
+  for (size_t g = 0; g < groups.size(); ++g) {
+    if (!done[g]) continue;
+    const int i = groups[g].first, k = groups[g].second;
+    double* Uc = U + (size_t)i * N;
+    double* Wg = h->d_grp + (size_t)2 * off[g] * N;
+    riga::launch_gemm_tall(N, Uc, N, k, h->d_grpG + goff[g] / 2, k, Wg, N, h->st);
+    ck(hipMemcpyAsync(Uc, Wg, (size_t)k * N * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+  }
+  ck(hipStreamSynchronize(h->st));   // Yall is host memory read by the upload
+}
+
 // Ascending order of the n values, the columns of U permuted with them (a
 // polished value can pass a neighbour it was within rounding of).
 void order_pairs(riga_problem* h, int n, double* U, double* mu) {
@@ -433,6 +572,7 @@ riga_status riga_gep_slice(riga_problem* h, double a, double b, int max_slice, c
     if (U != nullptr && nout > 0) {
       rayleigh_quotients(h, nout, U, mu);
       order_pairs(h, nout, U, mu);
+      group_rayleigh_ritz(h, nout, U, mu);
     }
     if (resid != nullptr && U != nullptr && nout > 0) {
       ensure_norms(h);

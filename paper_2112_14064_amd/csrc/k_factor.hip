@@ -57,6 +57,9 @@ constexpr int LDT = TB + 1; // LDS row stride (elements)
 #ifndef LU_SPLIT_TILES
 #define LU_SPLIT_TILES 8
 #endif
+#ifndef CH_SPLIT_TILES
+#define CH_SPLIT_TILES 8
+#endif
 
 template <class E>
 struct Front {
@@ -117,6 +120,40 @@ struct Tile64 {
       for (int t = 0; t < TJ; ++t) {
         const E x = B[kin ? k * ldb + wc + 16 * t + mfma_b_col(lane) : 0];
         b[t] = kin ? x : E(0);
+      }
+#pragma unroll
+      for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < TJ; ++tj) c.a[ti][tj] = Mfma<E>::mma(a[ti], b[tj], c.a[ti][tj]);
+    }
+  }
+  // acc += A (64 x kw) B^T with A and B both stored as row panels in global
+  // memory: A(i, k) at A[k * lda + i] for i < nrows, B(j, k) at B[k * ldb + j]
+  // for j < ncols (rows past either bound are zero; masked lanes read a valid
+  // address and select zero); k < kw.
+  static __device__ __forceinline__ void mma_global_nt(const E* __restrict__ A, int64_t lda, int nrows,
+                                                       const E* __restrict__ B, int64_t ldb, int ncols, int kw,
+                                                       Acc& c, int lane, int wave, const E* kscale = nullptr) {
+    const int wr = (wave / WC) * (TB / WR), wc = (wave % WC) * (TB / WC);
+#pragma unroll 4
+    for (int k0 = 0; k0 < TB; k0 += 4) {
+      const int k = k0 + mfma_ab_k(lane);
+      const bool kin = k < kw;
+      E a[TI], b[TJ];
+#pragma unroll
+      for (int t = 0; t < TI; ++t) {
+        const int i = wr + 16 * t + mfma_a_row(lane);
+        const bool in = kin && i < nrows;
+        const E x = A[in ? (int64_t)k * lda + i : 0];
+        a[t] = in ? x : E(0);
+      }
+      const E ks = (kscale != nullptr && kin) ? kscale[k] : E(1);
+#pragma unroll
+      for (int t = 0; t < TJ; ++t) {
+        const int j = wc + 16 * t + mfma_b_col(lane);
+        const bool in = kin && j < ncols;
+        const E x = B[in ? (int64_t)k * ldb + j : 0];
+        b[t] = in ? x * ks : E(0);
       }
 #pragma unroll
       for (int ti = 0; ti < TI; ++ti)
@@ -907,6 +944,92 @@ __global__ __launch_bounds__(FT) void k_panel_update_lu(DevTree t, const int* __
         }
 }
 
+// Large symmetric fronts in two launches per panel (as for the LU fronts
+// below): k_panel_rows forms X_I = A_panel D^T once per row tile and stores
+// the factor rows X_I S; k_panel_trail updates each tile pair from them read
+// straight from the factor, C_IJ -= (X_I S) (X_J S)^T S (S = diag of the
+// pivot signs, S^2 = I).
+template <class E>
+__global__ __launch_bounds__(FT) void k_panel_rows(DevTree t, const int* __restrict__ level_nodes, int k0,
+                                                   E* __restrict__ Lbuf, E* __restrict__ Ubuf,
+                                                   E* __restrict__ Fbuf, const E* __restrict__ Dbuf) {
+  typedef Tile64<E, 4> TL;
+  const int v = level_nodes[blockIdx.x];
+  const Front<E> F = front_of(t, v, Lbuf, Ubuf);
+  if (F.no <= k0) return;
+  const int w = min(TB, F.no - k0);
+  const int rI = k0 + w + TB * (int)blockIdx.y;
+  const int nf = F.nf;
+  if (rI >= nf) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ E ps[TB];
+  if (tid < TB) ps[tid] = (t.sgn != nullptr && tid < w) ? (E)t.sgn[t.fdofs[t.foff[v] + k0 + tid]] : E(1);
+  const E* Dt = Dbuf + ((int64_t)t.doff[v] + k0 / TB) * (TB * TB);
+  typename TL::Acc x;
+  TL::zero(x);
+  TL::mma_global(F.L + (int64_t)k0 * nf + rI, nf, nf - rI, Dt, TB, w, x, lane, wave);
+  __syncthreads();   // ps
+  E* Lf = Fbuf + t.loff[v];
+#pragma unroll
+  for (int ti = 0; ti < TL::TI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TL::TJ; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = TL::row(lane, wave, ti, e), cl = TL::col(lane, wave, tj);
+        if (rI + r < nf && cl < w) Lf[(int64_t)(k0 + cl) * nf + rI + r] = x.a[ti][tj][e] * ps[cl];
+      }
+}
+
+template <class E>
+__global__ __launch_bounds__(FT) void k_panel_trail(DevTree t, const int* __restrict__ level_nodes, int k0,
+                                                    E* __restrict__ Lbuf, E* __restrict__ Ubuf,
+                                                    const E* __restrict__ Fbuf) {
+  typedef Tile64<E, 4> TL;
+  const int v = level_nodes[blockIdx.x];
+  const Front<E> F = front_of(t, v, Lbuf, Ubuf);
+  if (F.no <= k0) return;
+  const int w = min(TB, F.no - k0);
+  const int s0 = k0 + w;
+  const int pidx = blockIdx.y;
+  int I = (int)((sqrt(8.0 * pidx + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= pidx) ++I;
+  while (I * (I + 1) / 2 > pidx) --I;
+  const int J = pidx - I * (I + 1) / 2;
+  const int rI = s0 + TB * I, rJ = s0 + TB * J;
+  const int nf = F.nf;
+  if (rI >= nf) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ E ps[TB];
+  if (tid < TB) ps[tid] = (t.sgn != nullptr && tid < w) ? (E)t.sgn[t.fdofs[t.foff[v] + k0 + tid]] : E(1);
+  typename TL::Acc c;
+  E* cp[TL::TI][TL::TJ][4];
+#pragma unroll
+  for (int ti = 0; ti < TL::TI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TL::TJ; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = rI + TL::row(lane, wave, ti, e), cc = rJ + TL::col(lane, wave, tj);
+        const bool in = r < nf && cc < nf && r >= cc;
+        cp[ti][tj][e] = in ? F.at(r, cc) : nullptr;
+        c.a[ti][tj][e] = *(in ? cp[ti][tj][e] : F.at(rI, rJ));
+      }
+  const E* Lf = Fbuf + t.loff[v];
+  __syncthreads();   // ps
+  typename TL::Acc pr;
+  TL::zero(pr);
+  TL::mma_global_nt(Lf + (int64_t)k0 * nf + rI, nf, nf - rI, Lf + (int64_t)k0 * nf + rJ, nf, nf - rJ, w, pr, lane,
+                    wave, t.sgn != nullptr ? ps : nullptr);
+#pragma unroll
+  for (int ti = 0; ti < TL::TI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TL::TJ; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (cp[ti][tj][e] != nullptr) *cp[ti][tj][e] = c.a[ti][tj][e] - pr.a[ti][tj][e];
+}
+
 // Large LU fronts in two launches per panel, so that no panel row is formed
 // twice (the fused kernel above forms X_I, Y_I and X_J, Y_J for every tile
 // pair, i.e. each row tile once per pair it takes part in):
@@ -973,8 +1096,6 @@ __global__ __launch_bounds__(FT) void k_panel_trail_lu(DevTree t, const int* __r
   const int nf = FA.nf;
   if (rI >= nf) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ E Xa[TB * LDT];
-  __shared__ E Xb[TB * LDT];
   const E* Lf = Lfac + t.loff[v];
   const E* Rf = Rfac + t.loff[v];
   typename TL::Acc ca, ct;
@@ -993,23 +1114,27 @@ __global__ __launch_bounds__(FT) void k_panel_trail_lu(DevTree t, const int* __r
         ca.a[ti][tj][e] = *(in ? pa[ti][tj][e] : FA.at(rI, rJ));
         ct.a[ti][tj][e] = *(in ? pt[ti][tj][e] : FT_.at(rI, rJ));
       }
-  // stored rows: lane-consecutive rows of one panel column per pass (coalesced);
-  // rows past the front and columns past the panel are zeros
-  auto stage = [&](const E* Pi, const E* Pj) {
-    for (int idx = tid; idx < TB * TB; idx += FT) {
-      const int r = idx % TB, c = idx / TB;
-      const bool cin = c < w;
-      Xa[r * LDT + c] = (cin && rI + r < nf) ? Pi[(int64_t)(k0 + c) * nf + rI + r] : E(0);
-      Xb[c * LDT + r] = (cin && rJ + r < nf) ? Pj[(int64_t)(k0 + c) * nf + rJ + r] : E(0);
-    }
-  };
-  stage(Lf, Rf);   // X_I, Y_J^T
-  __syncthreads();
-  TL::mma(Xa, Xb, w, ca, lane, wave, E(-1));
-  __syncthreads();
-  stage(Rf, Lf);   // Y_I, X_J^T
-  __syncthreads();
-  TL::mma(Xa, Xb, w, ct, lane, wave, E(-1));
+  // C^A -= X_I Y_J^T and C^At -= Y_I X_J^T with the stored rows read straight
+  // from the factor (no staging: no LDS, more workgroups per compute unit)
+  typename TL::Acc pr;
+  TL::zero(pr);
+  TL::mma_global_nt(Lf + (int64_t)k0 * nf + rI, nf, nf - rI, Rf + (int64_t)k0 * nf + rJ, nf, nf - rJ, w, pr, lane,
+                    wave);
+#pragma unroll
+  for (int ti = 0; ti < TL::TI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TL::TJ; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ca.a[ti][tj][e] -= pr.a[ti][tj][e];
+  TL::zero(pr);
+  TL::mma_global_nt(Rf + (int64_t)k0 * nf + rI, nf, nf - rI, Lf + (int64_t)k0 * nf + rJ, nf, nf - rJ, w, pr, lane,
+                    wave);
+#pragma unroll
+  for (int ti = 0; ti < TL::TI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TL::TJ; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ct.a[ti][tj][e] -= pr.a[ti][tj][e];
 #pragma unroll
   for (int ti = 0; ti < TL::TI; ++ti)
 #pragma unroll
@@ -1218,8 +1343,15 @@ void front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, i
     // row tiles below a block that is at least one column wide; one workgroup per tile pair
     const int below = std::max(1, max_nf - k0 - 1);
     const int nrc = (below + TB - 1) / TB;
-    hipLaunchKernelGGL(k_panel_update<E>, dim3(count, nrc * (nrc + 1) / 2), dim3(FT), 0, st, t, level_nodes, k0,
-                       Lf, U, Lx, (const E*)D);
+    if (nrc >= CH_SPLIT_TILES) {
+      hipLaunchKernelGGL(k_panel_rows<E>, dim3(count, nrc), dim3(FT), 0, st, t, level_nodes, k0, Lf, U, Lx,
+                         (const E*)D);
+      hipLaunchKernelGGL(k_panel_trail<E>, dim3(count, nrc * (nrc + 1) / 2), dim3(FT), 0, st, t, level_nodes, k0,
+                         Lf, U, (const E*)Lx);
+    } else {
+      hipLaunchKernelGGL(k_panel_update<E>, dim3(count, nrc * (nrc + 1) / 2), dim3(FT), 0, st, t, level_nodes, k0,
+                         Lf, U, Lx, (const E*)D);
+    }
   }
   const int nrt = (max_nf + TB - 1) / TB;
   hipLaunchKernelGGL(k_rtrsm<E>, dim3(count, nrt), dim3(RT_THREADS), 0, st, t, level_nodes, (const E*)Lx, Lf,

@@ -62,6 +62,10 @@ struct riga_problem {
   double csig_im = 0.0;
   riga_problem* cshadow = nullptr;
   double *d_cw = nullptr, *d_cb = nullptr, *d_cx = nullptr;
+  // spectrum slicing: [K U_g | M U_g] of the near-degenerate groups (N x 2
+  // grp_cols), their Gram blocks and rotations (grp_cols x 16 + 64)
+  double *d_grp = nullptr, *d_grpG = nullptr;
+  int grp_cols = 0;
   double *d_tabS = nullptr, *d_S1 = nullptr, *d_Ct = nullptr;
   double *d_LR = nullptr, *d_UR = nullptr, *d_TR = nullptr, *d_DR = nullptr;
   double *d_L = nullptr, *d_U = nullptr, *d_T = nullptr, *d_upd = nullptr, *d_tmp = nullptr, *d_tmp2 = nullptr;
