@@ -29,6 +29,9 @@
 //                      block: the panel rows X_I = A_I D_k^T and X_J (MFMA),
 //                      X_I stored as factor rows by the diagonal pair, and
 //                      the trailing tile C_IJ -= X_I X_J^T (MFMA);
+//     or, on levels with many tile pairs, k_panel_rows (X_I once per row
+//                      tile, stored as factor rows) and k_panel_trail (the
+//                      tile pairs from the stored rows);
 //   k_rtrsm            rows of F = [L_oo^{-1}; L_bo L_oo^{-1}] from
 //                      X L_oo = [I; L_bo], block column by block column from
 //                      the right with the stored D_k (MFMA, 16 waves);
@@ -52,14 +55,21 @@ namespace riga {
 constexpr int FT = 256;     // threads per workgroup (four waves)
 constexpr int TB = 64;      // panel / tile width
 constexpr int LDT = TB + 1; // LDS row stride (elements)
-// LU fronts with at least this many row tiles below a panel form the panel
-// rows once (k_panel_rows_lu + k_panel_trail_lu) instead of per tile pair
-#ifndef LU_SPLIT_TILES
-#define LU_SPLIT_TILES 8
+// A panel's trailing update forms the panel rows once per row tile
+// (k_panel_rows*, then k_panel_trail* over the tile pairs: one product per
+// pair) instead of in every tile pair (the fused k_panel_update*: three
+// products per pair, one launch) when the level's tile pairs (fronts x pairs)
+// number at least SPLIT_MIN_PAIRS, i.e. when the fused kernel would need more
+// than one round of workgroups on the chip; below that the second launch
+// costs more than the products it saves.
+#ifndef SPLIT_MIN_PAIRS
+#define SPLIT_MIN_PAIRS 512
 #endif
-#ifndef CH_SPLIT_TILES
-#define CH_SPLIT_TILES 8
-#endif
+
+static bool split_panel(int count, int nrc) {
+  const long pairs = (long)count * nrc * (nrc + 1) / 2;
+  return nrc >= 2 && pairs >= SPLIT_MIN_PAIRS;
+}
 
 template <class E>
 struct Front {
@@ -1036,7 +1046,8 @@ __global__ __launch_bounds__(FT) void k_panel_trail(DevTree t, const int* __rest
 // k_panel_rows_lu, one workgroup per row tile I below the panel: X_I =
 // A_panel D_U^T and Y_I = At_panel D_L^T written as factor rows;
 // k_panel_trail_lu, one workgroup per tile pair (I, J), J <= I: the stored
-// rows staged in LDS, C^A_IJ -= X_I Y_J^T and C^At_IJ -= Y_I X_J^T.
+// rows read straight from the factor, C^A_IJ -= X_I Y_J^T and
+// C^At_IJ -= Y_I X_J^T.
 template <class E>
 __global__ __launch_bounds__(FT) void k_panel_rows_lu(DevTree t, const int* __restrict__ level_nodes, int k0,
                                                       E* __restrict__ Lbuf, E* __restrict__ Ubuf,
@@ -1343,7 +1354,7 @@ void front_factor(const DevSpace& s, const DevTree& t, const int* level_nodes, i
     // row tiles below a block that is at least one column wide; one workgroup per tile pair
     const int below = std::max(1, max_nf - k0 - 1);
     const int nrc = (below + TB - 1) / TB;
-    if (nrc >= CH_SPLIT_TILES) {
+    if (split_panel(count, nrc)) {
       hipLaunchKernelGGL(k_panel_rows<E>, dim3(count, nrc), dim3(FT), 0, st, t, level_nodes, k0, Lf, U, Lx,
                          (const E*)D);
       hipLaunchKernelGGL(k_panel_trail<E>, dim3(count, nrc * (nrc + 1) / 2), dim3(FT), 0, st, t, level_nodes, k0,
@@ -1389,7 +1400,7 @@ void launch_front_factor_lu(const DevSpace& s, const DevTree& t, const int* leve
                        Lx, Rx, D, DR, status);
     const int below = std::max(1, max_nf - k0 - 1);
     const int nrc = (below + TB - 1) / TB;
-    if (nrc >= LU_SPLIT_TILES) {
+    if (split_panel(count, nrc)) {
       hipLaunchKernelGGL(k_panel_rows_lu<E>, dim3(count, nrc), dim3(FT), 0, st, t, level_nodes, k0, L, U, R, UR, Lx,
                          Rx, (const E*)D, (const E*)DR);
       hipLaunchKernelGGL(k_panel_trail_lu<E>, dim3(count, nrc * (nrc + 1) / 2), dim3(FT), 0, st, t, level_nodes, k0,
