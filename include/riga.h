@@ -137,7 +137,11 @@ typedef struct {
  *           captured HIP graph; bit 1: check every block step on the host (the
  *           path otherwise taken only after a device-detected breakdown);
  *           RIGA_EIGS_TOAR (bit 2): keep the Krylov basis in compact two-level
- *           form (see riga_eigs).
+ *           form (see riga_eigs); RIGA_EIGS_CGS2 (bit 3): take both
+ *           Gram--Schmidt passes of a block within its own step (three reads
+ *           of the basis per step) instead of delaying the second pass to the
+ *           next step (two reads; the default for blocks of 1 and 2 on the
+ *           device path; larger blocks always take both passes in the step).
  *   keep    Ritz values kept at a Krylov-Schur restart (0: nev + (m - nev)/2;
  *           at least nev, at most m - block; extended to whole clusters).    */
 typedef struct {
@@ -149,6 +153,7 @@ typedef struct {
   int keep;
 } riga_options;
 #define RIGA_EIGS_TOAR 4
+#define RIGA_EIGS_CGS2 8
 
 typedef struct {
   int64_t n1d;          /* 1-D functions per direction after Dirichlet          */

@@ -1357,6 +1357,7 @@ struct KrylovRun {
   bool fast = true;        // device-resident normalisation, no host round-trip per step
   bool graphs = true;      // replay captured block steps (fast path only)
   bool pre = false;        // the next step's operator application is already queued
+  bool dcgs = false;       // fast path, block <= 2: the second Gram--Schmidt pass delayed by one step
   int64_t n_fb = 0, n_mv = 0, n_vv = 0;
 
   double& Hat(int r, int c) { return H[r + (size_t)c * ldh]; }
@@ -1535,13 +1536,50 @@ struct KrylovRun {
     apply_block(h, b, h->Vu + o, h->Wl + o, n, h->Ru, h->Rl, h->Tv);
   }
 
+  // Scratch of the delayed-pass steps in d_small: the products P ((k+b) x 2b)
+  // where the two pass coefficients lie otherwise, then G and R^{-1}, the
+  // update coefficients, the new column of H and T^{-1}.
+  double* dcgs_P() { return h->d_small; }
+  double* dcgs_hc() { return h->d_small + (size_t)2 * ldh * b + 64; }
+  double* dcgs_hcol() { return dcgs_hc() + (size_t)2 * ldh * b; }
+  double* dcgs_Xm() { return dcgs_hcol() + (size_t)ldh * b; }
+
+  // One block step with the delayed second pass: the block Y = V[:, k:k+b]
+  // is finished and W = S Y projected once against [V[:, 0:k] V_j] in two
+  // reads of the basis; the next block is W' R^{-1} (R from the B-Gram of W').
+  void dcgs_step_device(bool tensor) {
+    const int nc = k + b;
+    double* dG = h->d_small + (size_t)2 * ldh * b;
+    double* rbuf = dG + 16;
+    riga::launch_dcgs_dots(N, k, b, true, h->Vu, h->Vl, h->Wl, N, h->Ru, h->Rl, h->d_part, dcgs_P(),
+                           tensor ? &h->ds : nullptr, h->d_M1, h->MRl, h->st);
+    riga::launch_dcgs_coef(k, b, true, dcgs_P(), h->d_H, ldh, dcgs_hc(), dcgs_hcol(), dcgs_Xm(), h->d_flag, h->st);
+    const int gblk = riga::launch_dcgs_update(N, k, b, true, dcgs_hc(), dcgs_Xm(), h->Vu, h->Vl, h->Wl, N, h->Ru,
+                                              h->Rl, h->MRl, N, h->d_part, h->st);
+    const size_t o = (size_t)nc * N;
+    riga::launch_normalize_gemm3(N, nc, b, dcgs_hcol(), nullptr, dG, h->d_part, gblk, h->d_H, ldh, k, h->d_flag,
+                                 rbuf, h->Ru, h->Vu + o, h->Rl, h->Vl + o, h->MRl, h->Wl + o, N, h->st);
+  }
+
+  // The second pass of the last block V[:, k:k+b] (end of a cycle, before the
+  // projected matrix is read), with H's columns rewritten for it.
+  void dcgs_finish_device() {
+    riga::launch_dcgs_dots(N, k, b, false, h->Vu, h->Vl, h->Wl, N, nullptr, nullptr, h->d_part, dcgs_P(), nullptr,
+                           nullptr, nullptr, h->st);
+    riga::launch_dcgs_coef(k, b, false, dcgs_P(), h->d_H, ldh, dcgs_hc(), nullptr, nullptr, h->d_flag, h->st);
+    riga::launch_dcgs_update(N, k, b, false, dcgs_hc(), nullptr, h->Vu, h->Vl, h->Wl, N, nullptr, nullptr, nullptr,
+                             N, nullptr, h->st);
+    n_vv += 5LL * (k + b) * b;
+  }
+
   // (M Rl, which the Gram-Schmidt updates need, is formed with the first products)
   void enqueue_step_device() {
     if (!pre) enqueue_apply(k);
     const bool tensor = h->plan.kind == riga::SPACE_H1;
     if (!tensor)
       riga::launch_spmv(h->ds, N, b, h->d_M, 1.0, h->Rl, N, h->MRl, N, nullptr, 0, 0.0, nullptr, 0, h->st);
-    orthonormalize_device(k + b, h->d_H, k, tensor);
+    if (dcgs) dcgs_step_device(tensor);
+    else orthonormalize_device(k + b, h->d_H, k, tensor);
   }
 
   void step(uint64_t seed) {
@@ -1550,7 +1588,7 @@ struct KrylovRun {
     const int nc = k + b;
     if (fast) {
       if (graphs) {
-        auto key = std::make_tuple(k, b, (const double*)h->Vu, pre ? 1 : 0, ldh);
+        auto key = std::make_tuple(k, b, (const double*)h->Vu, (pre ? 1 : 0) + (dcgs ? 2 : 0), ldh);
         auto it = h->graphs.find(key);
         if (it == h->graphs.end()) {
           ck(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
@@ -1570,7 +1608,7 @@ struct KrylovRun {
       pre = false;
       n_fb += b;
       n_mv += 3LL * b;
-      n_vv += 8LL * nc * b + 2LL * b * b;
+      n_vv += (dcgs ? 10LL : 8LL) * nc * b + 2LL * b * b;
       k += b;
       return;
     }
@@ -1755,6 +1793,7 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     for (int attempt = 0; attempt < 2; ++attempt) {
     kr.fast = (attempt == 0) && !(opt->flags & 2);
     kr.graphs = !(opt->flags & 1);
+    kr.dcgs = kr.fast && b <= 2 && !(opt->flags & RIGA_EIGS_CGS2);
     if (!kr.fast && attempt == 0) attempt = 1;
     kr.H.assign((size_t)ldh * ldh, 0.0);
     kr.n_fb = kr.n_mv = kr.n_vv = 0;
@@ -1788,6 +1827,7 @@ extern "C" riga_status riga_eigs(riga_problem* h, const riga_options* opt, doubl
     bool broke = false;
     for (;;) {
       while (kr.k + b <= m) kr.step(step_seed++);
+      if (kr.dcgs) kr.dcgs_finish_device();
       if (kr.fast) {
         const size_t hl = (size_t)ldh * ldh;
         double* stage = h->pinned(3 * hl + 8);   // the size the restart stages with

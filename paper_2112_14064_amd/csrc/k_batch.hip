@@ -74,7 +74,7 @@ __global__ __launch_bounds__(BT) void k_dots_b(const int4* __restrict__ db, cons
   const int64_t i0 = b.y, i1 = b.z;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double* out = partial + (int64_t)blockIdx.x * pstride;
-  dots_body<NQ, BT / 64>(i0, i1, nc, Au, Al, lda, Xu, Xl, ldx, lane, wave,
+  dots_body<NQ, BT / 64>(i0, i1, nc, Au, Al, lda, Xu, Xl, ldx, NQ, nullptr, nullptr, lane, wave,
                          [&](int c, int q, double v) { out[c * NQ + q] = v; });
 }
 

@@ -344,7 +344,7 @@ __global__ __launch_bounds__(DOT_THREADS) void k_dots(
   const int64_t i1 = min(n, i0 + per);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int blk = blockIdx.x;
-  dots_body<NQ, DOT_THREADS / 64>(i0, i1, nc, Au, Al, lda, Xu, Xl, ldx, lane, wave,
+  dots_body<NQ, DOT_THREADS / 64>(i0, i1, nc, Au, Al, lda, Xu, Xl, ldx, NQ, nullptr, nullptr, lane, wave,
                                   [&](int c, int q, double v) { partial[((int64_t)c * NQ + q) * nblk + blk] = v; });
 }
 
@@ -596,7 +596,7 @@ __global__ __launch_bounds__(256) void k_dots_mr(int64_t n, int nc, const double
     const int64_t i0 = (int64_t)bx * per;
     const int64_t i1 = min(n, i0 + per);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    dots_body<NQ, 4>(i0, i1, nc, Au, Al, lda, Xu, Xl, ldx, lane, wave,
+    dots_body<NQ, 4>(i0, i1, nc, Au, Al, lda, Xu, Xl, ldx, NQ, nullptr, nullptr, lane, wave,
                      [&](int c, int q, double v) { partial[((int64_t)c * NQ + q) * nblk + bx] = v; });
   } else {
     const int t = bx - nblk, gx = (tn + TT_I - 1) / TT_I;
@@ -764,6 +764,404 @@ int launch_cgs_update_dots(int64_t n, int nc, int nq, const double* h, const dou
   const int nout = nc * nq;
   hipLaunchKernelGGL(k_dots_final, dim3((nout + 3) / 4), dim3(256), 0, st, nout, blocks, partial, out);
   return blocks;
+}
+
+// ---------------------------------------------------------------------------
+// Block Gram--Schmidt with the second pass delayed by one step (block size
+// NB <= 2).  At a step the basis holds the finished columns V = V[:, 0:k] and
+// the block Y = V[:, k:k+NB], projected once against V and B-normalised, and
+// W = S Y is the operator applied to it.  One read of [V Y] forms the
+// products of both blocks, one read updates both: Y is finished (its second
+// pass) and W is projected once against the finished basis, so a step reads
+// the basis twice where two full passes per step read it three times.
+//   k_dcgs_dots    P = [V Y]^T_B [Y W] ((k + NB) x 2NB, output-major;
+//                  Vu^T Xu + (M Vl)^T Xl as k_dots) and, on the tensor grid,
+//                  M W_l sum-factorised in the same launch (as k_dots_mr);
+//   k_dcgs_coef    one workgroup: with s = V^T Y, T^T T = Y^T Y - s^T s, the
+//                  finished block V_j = (Y - V s) T^{-1}.  S V_j = (W - S V s)
+//                  T^{-1}, where S V = V H00 + Y H10 (the projected matrix's
+//                  rows 0..k+NB of columns 0..k); its coefficients on V and V_j
+//                  are a = (p - H00 s - s z) T^{-1} and d = T^{-T} (Y^T W -
+//                  s^T p) T^{-1} - T z T^{-1} (p = V^T W, z = H10 s), and W' =
+//                  S V_j - V a - V_j d = W T^{-1} - V h_v - Y h_y with h_v =
+//                  (p - s z) T^{-1} - s T^{-1} d, h_y = z T^{-1} + T^{-1} d.
+//                  The earlier columns are rewritten for V_j: H00 += s H10,
+//                  H10 <- T H10.  Writes the update coefficients hc, the new
+//                  column (a; d) of H and T^{-1}; T not positive (the block
+//                  lies in the span of V) sets *flag = 1;
+//   k_dcgs_update  per row: W <- W T^{-1} - [V Y] hc_w and Y <- -[V Y] hc_y
+//                  (Y's own coefficients -T^{-1}), with the per-block partial
+//                  B-Gram sums of W' for k_normalize_gemm3, which writes the
+//                  next block Y' = W' R^{-1} and R into H.
+// Without W (the end of a cycle) the same kernels only finish Y.
+template <int NB, bool HASW>
+__global__ __launch_bounds__(256) void k_dcgs_dots(int64_t n, int nc, const double* __restrict__ Vu,
+                                                   const double* __restrict__ Wl, int64_t lda,
+                                                   const double* __restrict__ Yu, const double* __restrict__ Yl,
+                                                   const double* __restrict__ Ru, const double* __restrict__ Rl,
+                                                   double* __restrict__ partial, int nblk, int tn, int p,
+                                                   const double* __restrict__ M1, double* __restrict__ MRl) {
+  constexpr int NQ = HASW ? 2 * NB : NB;
+  extern __shared__ double sm[];
+  const int bx = blockIdx.x;
+  if (bx < nblk) {
+    const int64_t per = (n + nblk - 1) / nblk;
+    const int64_t i0 = (int64_t)bx * per;
+    const int64_t i1 = min(n, i0 + per);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    dots_body<NQ, 4>(i0, i1, nc, Vu, Wl, lda, Yu, Yl, lda, NB, Ru, Rl, lane, wave,
+                     [&](int c, int q, double v) { partial[((int64_t)c * NQ + q) * nblk + bx] = v; });
+  } else if (HASW) {
+    const int t = bx - nblk, gx = (tn + TT_I - 1) / TT_I;
+    tensor_tile<NB, false, TT_J1>(tn, p, (t % gx) * TT_I, (t / gx) * TT_J1, M1, nullptr, 1.0, 0.0, Rl, lda, MRl,
+                                  lda, nullptr, 0, 0.0, sm);
+  }
+}
+
+template <int NB, bool HASW>
+__global__ __launch_bounds__(256) void k_dcgs_coef(int k, const double* __restrict__ P, double* __restrict__ H,
+                                                   int ldh, double* __restrict__ hc, double* __restrict__ hcol,
+                                                   double* __restrict__ Xm, int* __restrict__ flag) {
+  constexpr int NQ = HASW ? 2 * NB : NB;
+  constexpr int OFF = HASW ? NB : 0;   // the Y coefficients' first column in hc
+  // dynamic shared memory: s (k x NB), H10 (NB x k), u = H00 s (k x NB)
+  extern __shared__ double sh[];
+  double* ss = sh;
+  double* h10 = sh + (size_t)k * NB;
+  double* u = h10 + (size_t)k * NB;
+  __shared__ double part[4][64][NB];
+  __shared__ double z[NB][NB], sts[NB][NB], stp[NB][NB], T[NB][NB], Ti[NB][NB], d[NB][NB], zc[NB][NB];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int t = tid; t < k * NB; t += blockDim.x) {
+    const int c = t / NB, e = t % NB;
+    ss[t] = P[c * NQ + e];
+    h10[e * k + c] = H[k + e + (int64_t)c * ldh];
+  }
+  __syncthreads();
+  // u = H00 s and z = H10 s from the projected matrix as it stands: 64 rows
+  // at a time, the four waves splitting the columns
+  for (int r0 = 0; r0 < k + NB; r0 += 64) {
+    const int r = r0 + lane;
+    double acc[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) acc[q] = 0.0;
+    if (r < k + NB) {
+#pragma unroll 4
+      for (int c = wv; c < k; c += 4) {
+        const double hv = H[r + (int64_t)c * ldh];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) acc[q] += hv * ss[c * NB + q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) part[wv][lane][q] = acc[q];
+    __syncthreads();
+    if (wv == 0 && r < k + NB) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const double v = part[0][lane][q] + part[1][lane][q] + part[2][lane][q] + part[3][lane][q];
+        if (r < k) u[r * NB + q] = v;
+        else z[r - k][q] = v;
+      }
+    }
+    __syncthreads();
+  }
+  // s^T s and s^T p (wave 0; lanes stride the basis columns)
+  if (wv == 0) {
+    for (int e = 0; e < NB; ++e)
+      for (int q = 0; q < NB; ++q) {
+        double a = 0.0, b = 0.0;
+        for (int c = lane; c < k; c += 64) {
+          a += ss[c * NB + e] * ss[c * NB + q];
+          if (HASW) b += ss[c * NB + e] * P[c * NQ + NB + q];
+        }
+        a = wave_sum(a);
+        b = wave_sum(b);
+        if (lane == 0) { sts[e][q] = a; stp[e][q] = b; }
+      }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // T^T T = Y^T Y - s^T s (T upper), Ti = T^{-1}
+    bool bad = false;
+    for (int i = 0; i < NB; ++i)
+      for (int j = 0; j < NB; ++j) { T[i][j] = 0.0; Ti[i][j] = 0.0; }
+    for (int j = 0; j < NB; ++j) {
+      const double gjj = P[(k + j) * NQ + j];
+      for (int i = 0; i <= j; ++i) {
+        double a = 0.5 * (P[(k + i) * NQ + j] + P[(k + j) * NQ + i]) - 0.5 * (sts[i][j] + sts[j][i]);
+        for (int kk = 0; kk < i; ++kk) a -= T[kk][i] * T[kk][j];
+        if (i == j) {
+          if (!(a > 1e-24 * gjj)) { bad = true; a = 1.0; }
+          T[j][j] = sqrt(a);
+        } else {
+          T[i][j] = a / T[i][i];
+        }
+      }
+    }
+    for (int j = 0; j < NB; ++j) {
+      Ti[j][j] = 1.0 / T[j][j];
+      for (int i = j - 1; i >= 0; --i) {
+        double a = 0.0;
+        for (int kk = i + 1; kk <= j; ++kk) a += T[i][kk] * Ti[kk][j];
+        Ti[i][j] = -a / T[i][i];
+      }
+    }
+    if (HASW) {
+      // d = Ti^T (Y^T W - s^T p) Ti - T z Ti;  zc = z Ti + Ti d
+      double ym[NB][NB], yt[NB][NB], zt[NB][NB];
+      for (int e = 0; e < NB; ++e)
+        for (int q = 0; q < NB; ++q) ym[e][q] = P[(k + e) * NQ + NB + q] - stp[e][q];
+      for (int e = 0; e < NB; ++e)
+        for (int q = 0; q < NB; ++q) {
+          double a = 0.0, b = 0.0;
+          for (int f = 0; f < NB; ++f) { a += ym[e][f] * Ti[f][q]; b += z[e][f] * Ti[f][q]; }
+          yt[e][q] = a;
+          zt[e][q] = b;
+        }
+      for (int e = 0; e < NB; ++e)
+        for (int q = 0; q < NB; ++q) {
+          double a = 0.0;
+          for (int f = 0; f < NB; ++f) a += Ti[f][e] * yt[f][q] - T[e][f] * zt[f][q];
+          d[e][q] = a;
+        }
+      for (int e = 0; e < NB; ++e)
+        for (int q = 0; q < NB; ++q) {
+          double a = zt[e][q];
+          for (int f = 0; f < NB; ++f) a += Ti[e][f] * d[f][q];
+          zc[e][q] = a;
+          Xm[e * NB + q] = Ti[e][q];
+        }
+    }
+    if (bad) *flag = 1;
+  }
+  __syncthreads();
+  // coefficients, one basis row c per thread
+  for (int c = tid; c < k + NB; c += blockDim.x) {
+    if (c < k) {
+      double sv[NB], sti[NB];
+#pragma unroll
+      for (int e = 0; e < NB; ++e) sv[e] = ss[c * NB + e];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        double a = 0.0;
+#pragma unroll
+        for (int e = 0; e < NB; ++e) a += sv[e] * Ti[e][q];
+        sti[q] = a;
+        hc[c * NQ + OFF + q] = a;
+      }
+      if (HASW) {
+        double psz[NB];
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+          double a = P[c * NQ + NB + e];
+#pragma unroll
+          for (int f = 0; f < NB; ++f) a -= sv[f] * z[f][e];
+          psz[e] = a;
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          double hv = 0.0, av = 0.0;
+#pragma unroll
+          for (int e = 0; e < NB; ++e) {
+            hv += psz[e] * Ti[e][q] - sti[e] * d[e][q];
+            av += (psz[e] - u[c * NB + e]) * Ti[e][q];
+          }
+          hc[c * NQ + q] = hv;
+          hcol[c * NB + q] = av;
+        }
+      }
+    } else {
+      const int e = c - k;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        hc[c * NQ + OFF + q] = -Ti[e][q];
+        if (HASW) {
+          hc[c * NQ + q] = zc[e][q];
+          hcol[c * NB + q] = d[e][q];
+        }
+      }
+    }
+  }
+  // the earlier columns in terms of V_j: H00 += s H10 over the columns where
+  // H10 is not zero (the last block column after a plain step, all of them
+  // after a restart), one row per thread; then H10 <- T H10
+  for (int c = 0; c < k; ++c) {
+    bool nz = false;
+#pragma unroll
+    for (int e = 0; e < NB; ++e) nz = nz || h10[e * k + c] != 0.0;
+    if (!nz) continue;
+    for (int r = tid; r < k; r += blockDim.x) {
+      double a = 0.0;
+#pragma unroll
+      for (int e = 0; e < NB; ++e) a += ss[r * NB + e] * h10[e * k + c];
+      H[r + (int64_t)c * ldh] += a;
+    }
+  }
+  for (int c = tid; c < k; c += blockDim.x) {
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      double a = 0.0;
+#pragma unroll
+      for (int f = 0; f < NB; ++f) a += T[e][f] * h10[f * k + c];
+      H[k + e + (int64_t)c * ldh] = a;
+    }
+  }
+}
+
+template <int NB, bool HASW>
+__global__ __launch_bounds__(UPD_THREADS) void k_dcgs_update(int64_t n, int k, const double* __restrict__ hc,
+                                                             const double* __restrict__ Xm, double* __restrict__ Vu,
+                                                             double* __restrict__ Vl, double* __restrict__ Wl,
+                                                             int64_t lda, double* __restrict__ Zu,
+                                                             double* __restrict__ Zl, double* __restrict__ Zw,
+                                                             int64_t ldz, double* __restrict__ gpart) {
+  constexpr int NQ = HASW ? 2 * NB : NB;
+  constexpr int OFF = HASW ? NB : 0;
+  extern __shared__ double hs[];
+  __shared__ double xm[NB * NB];
+  const int nc = k + NB;
+  for (int t = threadIdx.x; t < nc * NQ; t += UPD_THREADS) hs[t] = hc[t];
+  if (HASW && threadIdx.x < NB * NB) xm[threadIdx.x] = Xm[threadIdx.x];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * UPD_THREADS + threadIdx.x;
+  double w0[NB], w1[NB], w2[NB];
+  if (i < n) {
+    double y0[NB], y1[NB], y2[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) { y0[q] = 0.0; y1[q] = 0.0; y2[q] = 0.0; w0[q] = 0.0; w1[q] = 0.0; w2[q] = 0.0; }
+    if (HASW) {
+      double r0[NB], r1[NB], r2[NB];
+#pragma unroll
+      for (int e = 0; e < NB; ++e) {
+        r0[e] = Zu[i + e * ldz];
+        r1[e] = Zl[i + e * ldz];
+        r2[e] = Zw[i + e * ldz];
+      }
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+          const double x = xm[e * NB + q];
+          w0[q] += r0[e] * x;
+          w1[q] += r1[e] * x;
+          w2[q] += r2[e] * x;
+        }
+    }
+    for (int c0 = 0; c0 < nc; c0 += UPD_U) {
+      double a0[UPD_U], a1[UPD_U], a2[UPD_U];
+#pragma unroll
+      for (int e = 0; e < UPD_U; ++e) {
+        const bool in = c0 + e < nc;
+        const int64_t o = i + (int64_t)(c0 + e) * lda;
+        a0[e] = in ? Vu[o] : 0.0;
+        a1[e] = in ? Vl[o] : 0.0;
+        a2[e] = in ? Wl[o] : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < UPD_U; ++e) {
+        if (c0 + e >= nc) break;
+        const double* hr = hs + (c0 + e) * NQ;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          if (HASW) {
+            w0[q] -= a0[e] * hr[q];
+            w1[q] -= a1[e] * hr[q];
+            w2[q] -= a2[e] * hr[q];
+          }
+          y0[q] -= a0[e] * hr[OFF + q];
+          y1[q] -= a1[e] * hr[OFF + q];
+          y2[q] -= a2[e] * hr[OFF + q];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int64_t o = i + (int64_t)(k + q) * lda;
+      Vu[o] = y0[q];
+      Vl[o] = y1[q];
+      Wl[o] = y2[q];
+      if (HASW) {
+        Zu[i + q * ldz] = w0[q];
+        Zl[i + q * ldz] = w1[q];
+        Zw[i + q * ldz] = w2[q];
+      }
+    }
+  }
+  if (!HASW || gpart == nullptr) return;
+  // B-Gram of W' (W'_u^T W'_u + (M W'_l)^T W'_l) over the block's rows
+  __shared__ double gw[UPD_THREADS / 64][NB * NB];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      double g = (i < n) ? w0[c] * w0[q] + w2[c] * w1[q] : 0.0;
+      g = wave_sum(g);
+      if (lane == 0) gw[wave][c * NB + q] = g;
+    }
+  __syncthreads();
+  if (threadIdx.x < NB * NB) {
+    double g = 0.0;
+#pragma unroll
+    for (int w = 0; w < UPD_THREADS / 64; ++w) g += gw[w][threadIdx.x];
+    gpart[(int64_t)blockIdx.x * NB * NB + threadIdx.x] = g;
+  }
+}
+
+void launch_dcgs_dots(int64_t n, int k, int nb, bool hasw, const double* Vu, const double* Vl, const double* Wl,
+                      int64_t lda, const double* Ru, const double* Rl, double* partial, double* out,
+                      const DevSpace* s, const double* M1, double* MRl, hipStream_t st) {
+  const int blocks = dots_blocks(n);
+  const int nc = k + nb;
+  const int tn = (hasw && s != nullptr) ? s->n : 0;
+  const int gx = (tn + TT_I - 1) / TT_I, gy = (tn + TT_J1 - 1) / TT_J1;
+  const unsigned grid = (unsigned)(blocks + (tn > 0 ? gx * gy : 0));
+  const size_t shm = tn > 0 ? tensor_shm(s->p, nb, false, TT_J1) : 0;
+  const int p = s != nullptr ? s->p : 0;
+  const double* Yu = Vu + (int64_t)k * lda;
+  const double* Yl = Vl + (int64_t)k * lda;
+#define RIGA_DCD(NB, W)                                                                                         \
+  hipLaunchKernelGGL((k_dcgs_dots<NB, W>), dim3(grid), dim3(256), shm, st, n, nc, Vu, Wl, lda, Yu, Yl, Ru, Rl, \
+                     partial, blocks, tn, p, M1, MRl)
+  if (nb == 1) {
+    if (hasw) RIGA_DCD(1, true); else RIGA_DCD(1, false);
+  } else {
+    if (hasw) RIGA_DCD(2, true); else RIGA_DCD(2, false);
+  }
+#undef RIGA_DCD
+  const int nout = nc * (hasw ? 2 * nb : nb);
+  hipLaunchKernelGGL(k_dots_final, dim3((nout + 3) / 4), dim3(256), 0, st, nout, blocks, partial, out);
+}
+
+void launch_dcgs_coef(int k, int nb, bool hasw, const double* P, double* H, int ldh, double* hc, double* hcol,
+                      double* Xm, int* flag, hipStream_t st) {
+  const size_t shm = (size_t)3 * std::max(k, 1) * nb * sizeof(double);
+#define RIGA_DCC(NB, W) \
+  hipLaunchKernelGGL((k_dcgs_coef<NB, W>), dim3(1), dim3(256), shm, st, k, P, H, ldh, hc, hcol, Xm, flag)
+  if (nb == 1) {
+    if (hasw) RIGA_DCC(1, true); else RIGA_DCC(1, false);
+  } else {
+    if (hasw) RIGA_DCC(2, true); else RIGA_DCC(2, false);
+  }
+#undef RIGA_DCC
+}
+
+int launch_dcgs_update(int64_t n, int k, int nb, bool hasw, const double* hc, const double* Xm, double* Vu,
+                       double* Vl, double* Wl, int64_t lda, double* Zu, double* Zl, double* Zw, int64_t ldz,
+                       double* gpart, hipStream_t st) {
+  const int64_t blocks = std::max<int64_t>(1, (n + UPD_THREADS - 1) / UPD_THREADS);
+  const size_t shm = (size_t)(k + nb) * (hasw ? 2 * nb : nb) * sizeof(double);
+#define RIGA_DCU(NB, W)                                                                                        \
+  hipLaunchKernelGGL((k_dcgs_update<NB, W>), dim3((unsigned)blocks), dim3(UPD_THREADS), shm, st, n, k, hc, Xm, \
+                     Vu, Vl, Wl, lda, Zu, Zl, Zw, ldz, gpart)
+  if (nb == 1) {
+    if (hasw) RIGA_DCU(1, true); else RIGA_DCU(1, false);
+  } else {
+    if (hasw) RIGA_DCU(2, true); else RIGA_DCU(2, false);
+  }
+#undef RIGA_DCU
+  return (int)blocks;
 }
 
 // ---------------------------------------------------------------------------

@@ -45,19 +45,65 @@ __device__ __forceinline__ void tensor_row_sum(const double* __restrict__ a, int
   }
 }
 
+// Sums over the 64 lanes of a wave of V values per lane (V a power of two,
+// at most 64) by recursive halving: at exchange s (offset 32 >> s) a lane
+// keeps the lower or the upper half of its values, by bit 5 - s of its lane
+// index, and adds its partner's copy of that half, so log2 V exchanges move
+// V - 1 values in all, and 6 - log2 V plain exchanges finish the one left.
+// Lane l then holds the total of value l >> (6 - log2 V) (every lane of that
+// group of 64 / V lanes holds the same total).
+template <int V, int S = 0>
+__device__ __forceinline__ void wave_halve(double (&a)[V], int lane) {
+  if constexpr ((V >> S) > 1) {
+    constexpr int H = (V >> S) / 2;
+    const bool hi = (lane >> (5 - S)) & 1;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double keep = hi ? a[i + H] : a[i];
+      const double send = hi ? a[i] : a[i + H];
+      a[i] = keep + __shfl_xor(send, 32 >> S, 64);
+    }
+    wave_halve<V, S + 1>(a, lane);
+  }
+}
+
+__host__ __device__ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+template <int V>
+__device__ __forceinline__ double wave_sum_multi(double (&a)[V], int lane) {
+  static_assert((V & (V - 1)) == 0 && V >= 1 && V <= 64, "V: a power of two up to 64");
+  wave_halve<V>(a, lane);
+  double v = a[0];
+#pragma unroll
+  for (int off = 32 >> ilog2(V); off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__host__ __device__ constexpr int pow2_at_least(int v) { return v <= 1 ? 1 : 2 * pow2_at_least((v + 1) / 2); }
+
 // Multi-dot body: for the columns c = wave, wave + 2 NW, ... (and c + NW
 // beside each; four columns per pass when the rows fit one round) of Au/Al,
 // the sums over rows [i0, i1) of
 // Au[i,c] Xu[i,q] + Al[i,c] Xl[i,q] (Al, Xl may be null), reduced over the
 // wave; lane 0 calls put(c, q, value).  DOT_U rows per lane per round, every
-// load of a round issued before the first product.
+// load of a round issued before the first product.  The X columns q >= nq1
+// come from a second block (Xu2, Xl2, same leading dimension) as its columns
+// q - nq1; nq1 = NQ: one block.
 constexpr int DOT_U = 4;
 
 template <int NQ, int NW, class Put>
 __device__ __forceinline__ void dots_body(int64_t i0, int64_t i1, int nc, const double* __restrict__ Au,
                                           const double* __restrict__ Al, int64_t lda,
-                                          const double* __restrict__ Xu, const double* __restrict__ Xl,
-                                          int64_t ldx, int lane, int wave, Put put) {
+                                          const double* __restrict__ Xu1, const double* __restrict__ Xl1,
+                                          int64_t ldx, int nq1, const double* __restrict__ Xu2,
+                                          const double* __restrict__ Xl2, int lane, int wave, Put put) {
+  const double* Xu[NQ];
+  const double* Xl[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    Xu[q] = q < nq1 ? Xu1 + (int64_t)q * ldx : Xu2 + (int64_t)(q - nq1) * ldx;
+    Xl[q] = Xl1 == nullptr ? nullptr : q < nq1 ? Xl1 + (int64_t)q * ldx : Xl2 + (int64_t)(q - nq1) * ldx;
+  }
   if (i1 - i0 <= 64 * DOT_U) {
     // the rows fit one round: the X rows stay in registers and a wave takes
     // four columns per pass (c, c + NW, c + 2 NW, c + 3 NW), every load of a
@@ -71,8 +117,8 @@ __device__ __forceinline__ void dots_body(int64_t i0, int64_t i1, int nc, const 
       in[e] = i < i1;
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        xu[e][q] = in[e] ? Xu[i + q * ldx] : 0.0;
-        xl[e][q] = (in[e] && Xl) ? Xl[i + q * ldx] : 0.0;
+        xu[e][q] = in[e] ? Xu[q][i] : 0.0;
+        xl[e][q] = (in[e] && Xl[q]) ? Xl[q][i] : 0.0;
       }
     }
     for (int c = wave; c < nc; c += 4 * NW) {
@@ -99,19 +145,14 @@ __device__ __forceinline__ void dots_body(int64_t i0, int64_t i1, int nc, const 
           for (int e = 0; e < DOT_U; ++e) a += u[m][e] * xu[e][q] + l[m][e] * xl[e][q];
           acc[m][q] = a;
         }
+      constexpr int V = pow2_at_least(4 * NQ), L = ilog2(V);
+      double flat[V];
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int q = 0; q < NQ; ++q)
-#pragma unroll
-          for (int off = 32; off > 0; off >>= 1) acc[m][q] += __shfl_xor(acc[m][q], off, 64);
-      if (lane == 0) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-          if (c + m * NW < nc)
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) put(c + m * NW, q, acc[m][q]);
-      }
+      for (int t = 0; t < V; ++t) flat[t] = t < 4 * NQ ? acc[t / NQ][t % NQ] : 0.0;
+      const double v = wave_sum_multi<V>(flat, lane);
+      const int idx = lane >> (6 - L);
+      if ((lane & ((1 << (6 - L)) - 1)) == 0 && idx < 4 * NQ && c + (idx / NQ) * NW < nc)
+        put(c + (idx / NQ) * NW, idx % NQ, v);
     }
     return;
   }
@@ -137,8 +178,8 @@ __device__ __forceinline__ void dots_body(int64_t i0, int64_t i1, int nc, const 
         l2[e] = (in && bl) ? bl[i] : 0.0;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-          xu[e][q] = in ? Xu[i + q * ldx] : 0.0;
-          xl[e][q] = (in && Xl) ? Xl[i + q * ldx] : 0.0;
+          xu[e][q] = in ? Xu[q][i] : 0.0;
+          xl[e][q] = (in && Xl[q]) ? Xl[q][i] : 0.0;
         }
       }
 #pragma unroll
@@ -149,20 +190,14 @@ __device__ __forceinline__ void dots_body(int64_t i0, int64_t i1, int nc, const 
           acc2[q] += u2[e] * xu[e][q] + l2[e] * xl[e][q];
         }
     }
+    constexpr int V = pow2_at_least(2 * NQ), L = ilog2(V);
+    double flat[V];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q)
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        acc[q] += __shfl_xor(acc[q], off, 64);
-        acc2[q] += __shfl_xor(acc2[q], off, 64);
-      }
-    if (lane == 0) {
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        put(c, q, acc[q]);
-        if (two) put(c2, q, acc2[q]);
-      }
-    }
+    for (int t = 0; t < V; ++t) flat[t] = t < NQ ? acc[t] : t < 2 * NQ ? acc2[t - NQ] : 0.0;
+    const double v = wave_sum_multi<V>(flat, lane);
+    const int idx = lane >> (6 - L);
+    if ((lane & ((1 << (6 - L)) - 1)) == 0 && idx < 2 * NQ && (idx < NQ || two))
+      put(idx < NQ ? c : c2, idx % NQ, v);
   }
 }
 

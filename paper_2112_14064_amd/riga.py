@@ -26,6 +26,7 @@ RIGA_WARN_NOT_CONVERGED = 1
 RIGA_WARN_IR_STAGNATED = 2
 RIGA_IR_MAX = 10
 RIGA_EIGS_TOAR = 4   # riga_options.flags: compact two-level Krylov basis
+RIGA_EIGS_CGS2 = 8   # riga_options.flags: both Gram-Schmidt passes within each block step
 RIGA_SPACE_H1, RIGA_SPACE_HCURL, RIGA_SPACE_HCURL_FREE, RIGA_SPACE_HDIV = 0, 1, 2, 3   # riga_mesh.space
 RIGA_WALL_LEFT, RIGA_WALL_RIGHT, RIGA_WALL_BOTTOM, RIGA_WALL_TOP = 1, 2, 4, 8   # riga_mesh.walls
 
