@@ -819,7 +819,7 @@ __global__ __launch_bounds__(256) void k_dcgs_dots(int64_t n, int nc, const doub
 }
 
 template <int NB, bool HASW>
-__global__ __launch_bounds__(256) void k_dcgs_coef(int k, const double* __restrict__ P, double* __restrict__ H,
+__global__ __launch_bounds__(1024) void k_dcgs_coef(int k, const double* __restrict__ P, double* __restrict__ H,
                                                    int ldh, double* __restrict__ hc, double* __restrict__ hcol,
                                                    double* __restrict__ Xm, int* __restrict__ flag) {
   constexpr int NQ = HASW ? 2 * NB : NB;
@@ -829,39 +829,42 @@ __global__ __launch_bounds__(256) void k_dcgs_coef(int k, const double* __restri
   double* ss = sh;
   double* h10 = sh + (size_t)k * NB;
   double* u = h10 + (size_t)k * NB;
-  __shared__ double part[4][64][NB];
+  __shared__ double part[4][256][NB];
   __shared__ double z[NB][NB], sts[NB][NB], stp[NB][NB], T[NB][NB], Ti[NB][NB], d[NB][NB], zc[NB][NB];
+  __shared__ double py[NB][NQ];   // the rows of P at Y: Y^T Y (and Y^T W)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int t = tid; t < k * NB; t += blockDim.x) {
     const int c = t / NB, e = t % NB;
     ss[t] = P[c * NQ + e];
     h10[e * k + c] = H[k + e + (int64_t)c * ldh];
   }
+  if (tid < NB * NQ) py[tid / NQ][tid % NQ] = P[(k + tid / NQ) * NQ + tid % NQ];
   __syncthreads();
-  // u = H00 s and z = H10 s from the projected matrix as it stands: 64 rows
-  // at a time, the four waves splitting the columns
-  for (int r0 = 0; r0 < k + NB; r0 += 64) {
-    const int r = r0 + lane;
+  // u = H00 s and z = H10 s from the projected matrix as it stands: thread
+  // (row r, group g) sums a quarter of the columns, eight loads at a time
+  {
+    const int r = tid & 255, g = tid >> 8;
+    const int per = (k + 3) / 4, c0 = g * per, c1 = min(k, c0 + per);
     double acc[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) acc[q] = 0.0;
     if (r < k + NB) {
-#pragma unroll 4
-      for (int c = wv; c < k; c += 4) {
+#pragma unroll 8
+      for (int c = c0; c < c1; ++c) {
         const double hv = H[r + (int64_t)c * ldh];
 #pragma unroll
         for (int q = 0; q < NB; ++q) acc[q] += hv * ss[c * NB + q];
       }
     }
 #pragma unroll
-    for (int q = 0; q < NB; ++q) part[wv][lane][q] = acc[q];
+    for (int q = 0; q < NB; ++q) part[g][r][q] = acc[q];
     __syncthreads();
-    if (wv == 0 && r < k + NB) {
+    if (tid < k + NB) {
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
-        const double v = part[0][lane][q] + part[1][lane][q] + part[2][lane][q] + part[3][lane][q];
-        if (r < k) u[r * NB + q] = v;
-        else z[r - k][q] = v;
+        const double v = part[0][tid][q] + part[1][tid][q] + part[2][tid][q] + part[3][tid][q];
+        if (tid < k) u[tid * NB + q] = v;
+        else z[tid - k][q] = v;
       }
     }
     __syncthreads();
@@ -887,9 +890,9 @@ __global__ __launch_bounds__(256) void k_dcgs_coef(int k, const double* __restri
     for (int i = 0; i < NB; ++i)
       for (int j = 0; j < NB; ++j) { T[i][j] = 0.0; Ti[i][j] = 0.0; }
     for (int j = 0; j < NB; ++j) {
-      const double gjj = P[(k + j) * NQ + j];
+      const double gjj = py[j][j];
       for (int i = 0; i <= j; ++i) {
-        double a = 0.5 * (P[(k + i) * NQ + j] + P[(k + j) * NQ + i]) - 0.5 * (sts[i][j] + sts[j][i]);
+        double a = 0.5 * (py[i][j] + py[j][i]) - 0.5 * (sts[i][j] + sts[j][i]);
         for (int kk = 0; kk < i; ++kk) a -= T[kk][i] * T[kk][j];
         if (i == j) {
           if (!(a > 1e-24 * gjj)) { bad = true; a = 1.0; }
@@ -911,7 +914,7 @@ __global__ __launch_bounds__(256) void k_dcgs_coef(int k, const double* __restri
       // d = Ti^T (Y^T W - s^T p) Ti - T z Ti;  zc = z Ti + Ti d
       double ym[NB][NB], yt[NB][NB], zt[NB][NB];
       for (int e = 0; e < NB; ++e)
-        for (int q = 0; q < NB; ++q) ym[e][q] = P[(k + e) * NQ + NB + q] - stp[e][q];
+        for (int q = 0; q < NB; ++q) ym[e][q] = py[e][(NQ - NB) + q] - stp[e][q];
       for (int e = 0; e < NB; ++e)
         for (int q = 0; q < NB; ++q) {
           double a = 0.0, b = 0.0;
@@ -1138,7 +1141,7 @@ void launch_dcgs_coef(int k, int nb, bool hasw, const double* P, double* H, int 
                       double* Xm, int* flag, hipStream_t st) {
   const size_t shm = (size_t)3 * std::max(k, 1) * nb * sizeof(double);
 #define RIGA_DCC(NB, W) \
-  hipLaunchKernelGGL((k_dcgs_coef<NB, W>), dim3(1), dim3(256), shm, st, k, P, H, ldh, hc, hcol, Xm, flag)
+  hipLaunchKernelGGL((k_dcgs_coef<NB, W>), dim3(1), dim3(1024), shm, st, k, P, H, ldh, hc, hcol, Xm, flag)
   if (nb == 1) {
     if (hasw) RIGA_DCC(1, true); else RIGA_DCC(1, false);
   } else {
