@@ -824,11 +824,14 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int k, const double* __restr
                                                    double* __restrict__ Xm, int* __restrict__ flag) {
   constexpr int NQ = HASW ? 2 * NB : NB;
   constexpr int OFF = HASW ? NB : 0;   // the Y coefficients' first column in hc
-  // dynamic shared memory: s (k x NB), H10 (NB x k), u = H00 s (k x NB)
+  // dynamic shared memory: s (k x NB), H10 (NB x k), u = H00 s (k x NB),
+  // p = V^T W (k x NB)
   extern __shared__ double sh[];
   double* ss = sh;
   double* h10 = sh + (size_t)k * NB;
   double* u = h10 + (size_t)k * NB;
+  double* pp = u + (size_t)k * NB;
+  __shared__ unsigned long long nzmask[4];   // columns c < k where H10 is not zero
   __shared__ double part[4][256][NB];
   __shared__ double z[NB][NB], sts[NB][NB], stp[NB][NB], T[NB][NB], Ti[NB][NB], d[NB][NB], zc[NB][NB];
   __shared__ double py[NB][NQ];   // the rows of P at Y: Y^T Y (and Y^T W)
@@ -836,9 +839,19 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int k, const double* __restr
   for (int t = tid; t < k * NB; t += blockDim.x) {
     const int c = t / NB, e = t % NB;
     ss[t] = P[c * NQ + e];
+    if (HASW) pp[t] = P[c * NQ + NB + e];
     h10[e * k + c] = H[k + e + (int64_t)c * ldh];
   }
   if (tid < NB * NQ) py[tid / NQ][tid % NQ] = P[(k + tid / NQ) * NQ + tid % NQ];
+  __syncthreads();
+  if (tid < 256) {
+    bool nz = false;
+    if (tid < k)
+#pragma unroll
+      for (int e = 0; e < NB; ++e) nz = nz || h10[e * k + tid] != 0.0;
+    const unsigned long long m = __ballot(nz);
+    if (lane == 0) nzmask[wv] = m;
+  }
   __syncthreads();
   // u = H00 s and z = H10 s from the projected matrix as it stands: thread
   // (row r, group g) sums a quarter of the columns, eight loads at a time
@@ -876,7 +889,7 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int k, const double* __restr
         double a = 0.0, b = 0.0;
         for (int c = lane; c < k; c += 64) {
           a += ss[c * NB + e] * ss[c * NB + q];
-          if (HASW) b += ss[c * NB + e] * P[c * NQ + NB + q];
+          if (HASW) b += ss[c * NB + e] * pp[c * NB + q];
         }
         a = wave_sum(a);
         b = wave_sum(b);
@@ -957,7 +970,7 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int k, const double* __restr
         double psz[NB];
 #pragma unroll
         for (int e = 0; e < NB; ++e) {
-          double a = P[c * NQ + NB + e];
+          double a = pp[c * NB + e];
 #pragma unroll
           for (int f = 0; f < NB; ++f) a -= sv[f] * z[f][e];
           psz[e] = a;
@@ -989,16 +1002,17 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int k, const double* __restr
   // the earlier columns in terms of V_j: H00 += s H10 over the columns where
   // H10 is not zero (the last block column after a plain step, all of them
   // after a restart), one row per thread; then H10 <- T H10
-  for (int c = 0; c < k; ++c) {
-    bool nz = false;
+  for (int w = 0; w < 4; ++w) {
+    unsigned long long m = nzmask[w];
+    while (m != 0ull) {
+      const int c = w * 64 + __ffsll((long long)m) - 1;
+      m &= m - 1ull;
+      for (int r = tid; r < k; r += blockDim.x) {
+        double a = 0.0;
 #pragma unroll
-    for (int e = 0; e < NB; ++e) nz = nz || h10[e * k + c] != 0.0;
-    if (!nz) continue;
-    for (int r = tid; r < k; r += blockDim.x) {
-      double a = 0.0;
-#pragma unroll
-      for (int e = 0; e < NB; ++e) a += ss[r * NB + e] * h10[e * k + c];
-      H[r + (int64_t)c * ldh] += a;
+        for (int e = 0; e < NB; ++e) a += ss[r * NB + e] * h10[e * k + c];
+        H[r + (int64_t)c * ldh] += a;
+      }
     }
   }
   for (int c = tid; c < k; c += blockDim.x) {
@@ -1139,7 +1153,7 @@ void launch_dcgs_dots(int64_t n, int k, int nb, bool hasw, const double* Vu, con
 
 void launch_dcgs_coef(int k, int nb, bool hasw, const double* P, double* H, int ldh, double* hc, double* hcol,
                       double* Xm, int* flag, hipStream_t st) {
-  const size_t shm = (size_t)3 * std::max(k, 1) * nb * sizeof(double);
+  const size_t shm = (size_t)4 * std::max(k, 1) * nb * sizeof(double);
 #define RIGA_DCC(NB, W) \
   hipLaunchKernelGGL((k_dcgs_coef<NB, W>), dim3(1), dim3(1024), shm, st, k, P, H, ldh, hc, hcol, Xm, flag)
   if (nb == 1) {
