@@ -1537,28 +1537,22 @@ struct KrylovRun {
   }
 
   // Scratch of the delayed-pass steps in d_small: the products P ((k+b) x 2b)
-  // where the two pass coefficients lie otherwise, then G and R^{-1}, the
-  // update coefficients, the new column of H and T^{-1}.
+  // where the two pass coefficients lie otherwise, then the update
+  // coefficients and T^{-1}.
   double* dcgs_P() { return h->d_small; }
   double* dcgs_hc() { return h->d_small + (size_t)2 * ldh * b + 64; }
-  double* dcgs_hcol() { return dcgs_hc() + (size_t)2 * ldh * b; }
-  double* dcgs_Xm() { return dcgs_hcol() + (size_t)ldh * b; }
+  double* dcgs_Xm() { return dcgs_hc() + (size_t)2 * ldh * b; }
 
-  // One block step with the delayed second pass: the block Y = V[:, k:k+b]
-  // is finished and W = S Y projected once against [V[:, 0:k] V_j] in two
-  // reads of the basis; the next block is W' R^{-1} (R from the B-Gram of W').
+  // One block step with the delayed second pass: the pending block Y =
+  // V[:, k:k+b] is finished (second pass and normalisation) and W = S Y
+  // projected once against [V[:, 0:k] V_j] in two reads of the basis; the
+  // projected image is the next pending block V[:, k+b:k+2b] as it stands.
   void dcgs_step_device(bool tensor) {
-    const int nc = k + b;
-    double* dG = h->d_small + (size_t)2 * ldh * b;
-    double* rbuf = dG + 16;
     riga::launch_dcgs_dots(N, k, b, true, h->Vu, h->Vl, h->Wl, N, h->Ru, h->Rl, h->d_part, dcgs_P(),
                            tensor ? &h->ds : nullptr, h->d_M1, h->MRl, h->st);
-    riga::launch_dcgs_coef(k, b, true, dcgs_P(), h->d_H, ldh, dcgs_hc(), dcgs_hcol(), dcgs_Xm(), h->d_flag, h->st);
-    const int gblk = riga::launch_dcgs_update(N, k, b, true, dcgs_hc(), dcgs_Xm(), h->Vu, h->Vl, h->Wl, N, h->Ru,
-                                              h->Rl, h->MRl, N, h->d_part, h->st);
-    const size_t o = (size_t)nc * N;
-    riga::launch_normalize_gemm3(N, nc, b, dcgs_hcol(), nullptr, dG, h->d_part, gblk, h->d_H, ldh, k, h->d_flag,
-                                 rbuf, h->Ru, h->Vu + o, h->Rl, h->Vl + o, h->MRl, h->Wl + o, N, h->st);
+    riga::launch_dcgs_coef(k, b, true, dcgs_P(), h->d_H, ldh, dcgs_hc(), dcgs_Xm(), h->d_flag, h->st);
+    riga::launch_dcgs_update(N, k, b, true, dcgs_hc(), dcgs_Xm(), h->Vu, h->Vl, h->Wl, N, h->Ru, h->Rl, h->MRl, N,
+                             h->st);
   }
 
   // The second pass of the last block V[:, k:k+b] (end of a cycle, before the
@@ -1566,9 +1560,9 @@ struct KrylovRun {
   void dcgs_finish_device() {
     riga::launch_dcgs_dots(N, k, b, false, h->Vu, h->Vl, h->Wl, N, nullptr, nullptr, h->d_part, dcgs_P(), nullptr,
                            nullptr, nullptr, h->st);
-    riga::launch_dcgs_coef(k, b, false, dcgs_P(), h->d_H, ldh, dcgs_hc(), nullptr, nullptr, h->d_flag, h->st);
+    riga::launch_dcgs_coef(k, b, false, dcgs_P(), h->d_H, ldh, dcgs_hc(), nullptr, h->d_flag, h->st);
     riga::launch_dcgs_update(N, k, b, false, dcgs_hc(), nullptr, h->Vu, h->Vl, h->Wl, N, nullptr, nullptr, nullptr,
-                             N, nullptr, h->st);
+                             N, h->st);
     n_vv += 5LL * (k + b) * b;
   }
 

@@ -769,11 +769,12 @@ int launch_cgs_update_dots(int64_t n, int nc, int nq, const double* h, const dou
 // ---------------------------------------------------------------------------
 // Block Gram--Schmidt with the second pass delayed by one step (block size
 // NB <= 2).  At a step the basis holds the finished columns V = V[:, 0:k] and
-// the block Y = V[:, k:k+NB], projected once against V and B-normalised, and
-// W = S Y is the operator applied to it.  One read of [V Y] forms the
-// products of both blocks, one read updates both: Y is finished (its second
-// pass) and W is projected once against the finished basis, so a step reads
-// the basis twice where two full passes per step read it three times.
+// the pending block Y = V[:, k:k+NB], the previous image projected once (not
+// normalised), and W = S Y is the operator applied to it.  One read of [V Y]
+// forms the products of both blocks, one read updates both: Y is finished (its
+// second pass and its normalisation) and W is projected once against the
+// finished basis, so a step reads the basis twice where two full passes per
+// step read it three times, and no separate normalisation pass is needed.
 //   k_dcgs_dots    P = [V Y]^T_B [Y W] ((k + NB) x 2NB, output-major;
 //                  Vu^T Xu + (M Vl)^T Xl as k_dots) and, on the tensor grid,
 //                  M W_l sum-factorised in the same launch (as k_dots_mr);
@@ -786,13 +787,13 @@ int launch_cgs_update_dots(int64_t n, int nc, int nq, const double* h, const dou
 //                  S V_j - V a - V_j d = W T^{-1} - V h_v - Y h_y with h_v =
 //                  (p - s z) T^{-1} - s T^{-1} d, h_y = z T^{-1} + T^{-1} d.
 //                  The earlier columns are rewritten for V_j: H00 += s H10,
-//                  H10 <- T H10.  Writes the update coefficients hc, the new
-//                  column (a; d) of H and T^{-1}; T not positive (the block
-//                  lies in the span of V) sets *flag = 1;
-//   k_dcgs_update  per row: W <- W T^{-1} - [V Y] hc_w and Y <- -[V Y] hc_y
-//                  (Y's own coefficients -T^{-1}), with the per-block partial
-//                  B-Gram sums of W' for k_normalize_gemm3, which writes the
-//                  next block Y' = W' R^{-1} and R into H.
+//                  H10 <- T H10.  Writes the update coefficients hc, T^{-1},
+//                  and H's new column block (a; d; I: W' is the next pending
+//                  block as it stands); T not positive beyond rounding (the
+//                  block lies in the span of V) sets *flag = 1;
+//   k_dcgs_update  per row: W' = W T^{-1} - [V Y] hc_w into V[:, k+NB:k+2NB]
+//                  and Y <- -[V Y] hc_y in place (Y's own coefficients
+//                  -T^{-1}).
 // Without W (the end of a cycle) the same kernels only finish Y.
 template <int NB, bool HASW>
 __global__ __launch_bounds__(256) void k_dcgs_dots(int64_t n, int nc, const double* __restrict__ Vu,
@@ -820,8 +821,8 @@ __global__ __launch_bounds__(256) void k_dcgs_dots(int64_t n, int nc, const doub
 
 template <int NB, bool HASW>
 __global__ __launch_bounds__(1024) void k_dcgs_coef(int k, const double* __restrict__ P, double* __restrict__ H,
-                                                   int ldh, double* __restrict__ hc, double* __restrict__ hcol,
-                                                   double* __restrict__ Xm, int* __restrict__ flag) {
+                                                   int ldh, double* __restrict__ hc, double* __restrict__ Xm,
+                                                   int* __restrict__ flag) {
   constexpr int NQ = HASW ? 2 * NB : NB;
   constexpr int OFF = HASW ? NB : 0;   // the Y coefficients' first column in hc
   // dynamic shared memory: s (k x NB), H10 (NB x k), u = H00 s (k x NB),
@@ -835,6 +836,7 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int k, const double* __restr
   __shared__ double part[4][256][NB];
   __shared__ double z[NB][NB], sts[NB][NB], stp[NB][NB], T[NB][NB], Ti[NB][NB], d[NB][NB], zc[NB][NB];
   __shared__ double py[NB][NQ];   // the rows of P at Y: Y^T Y (and Y^T W)
+  __shared__ double hn[NB];       // squared norms of Y's projection coefficients (H's column block k-NB..k)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int t = tid; t < k * NB; t += blockDim.x) {
     const int c = t / NB, e = t % NB;
@@ -843,6 +845,19 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int k, const double* __restr
     h10[e * k + c] = H[k + e + (int64_t)c * ldh];
   }
   if (tid < NB * NQ) py[tid / NQ][tid % NQ] = P[(k + tid / NQ) * NQ + tid % NQ];
+  if (wv >= 4 && wv < 4 + NB) {
+    // Y = the projected image of the previous block, not normalised: its norm
+    // before projection adds these coefficients (read before the rewrite below)
+    const int q = wv - 4;
+    double a = 0.0;
+    if (k >= NB)
+      for (int c = lane; c < k; c += 64) {
+        const double h = H[c + (int64_t)(k - NB + q) * ldh];
+        a += h * h;
+      }
+    a = wave_sum(a);
+    if (lane == 0) hn[q] = a;
+  }
   __syncthreads();
   if (tid < 256) {
     bool nz = false;
@@ -898,12 +913,13 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int k, const double* __restr
   }
   __syncthreads();
   if (tid == 0) {
-    // T^T T = Y^T Y - s^T s (T upper), Ti = T^{-1}
+    // T^T T = Y^T Y - s^T s (T upper), Ti = T^{-1}; a column keeping at most
+    // 1e-12 of its norm before both projections marks a breakdown
     bool bad = false;
     for (int i = 0; i < NB; ++i)
       for (int j = 0; j < NB; ++j) { T[i][j] = 0.0; Ti[i][j] = 0.0; }
     for (int j = 0; j < NB; ++j) {
-      const double gjj = py[j][j];
+      const double gjj = py[j][j] + hn[j];
       for (int i = 0; i <= j; ++i) {
         double a = 0.5 * (py[i][j] + py[j][i]) - 0.5 * (sts[i][j] + sts[j][i]);
         for (int kk = 0; kk < i; ++kk) a -= T[kk][i] * T[kk][j];
@@ -984,7 +1000,7 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int k, const double* __restr
             av += (psz[e] - u[c * NB + e]) * Ti[e][q];
           }
           hc[c * NQ + q] = hv;
-          hcol[c * NB + q] = av;
+          H[c + (int64_t)(k + q) * ldh] = av;
         }
       }
     } else {
@@ -994,7 +1010,9 @@ __global__ __launch_bounds__(1024) void k_dcgs_coef(int k, const double* __restr
         hc[c * NQ + OFF + q] = -Ti[e][q];
         if (HASW) {
           hc[c * NQ + q] = zc[e][q];
-          hcol[c * NB + q] = d[e][q];
+          H[c + (int64_t)(k + q) * ldh] = d[e][q];
+          // the next pending block is W' itself: coefficient I
+          H[k + NB + e + (int64_t)(k + q) * ldh] = e == q ? 1.0 : 0.0;
         }
       }
     }
@@ -1030,9 +1048,11 @@ template <int NB, bool HASW>
 __global__ __launch_bounds__(UPD_THREADS) void k_dcgs_update(int64_t n, int k, const double* __restrict__ hc,
                                                              const double* __restrict__ Xm, double* __restrict__ Vu,
                                                              double* __restrict__ Vl, double* __restrict__ Wl,
-                                                             int64_t lda, double* __restrict__ Zu,
-                                                             double* __restrict__ Zl, double* __restrict__ Zw,
-                                                             int64_t ldz, double* __restrict__ gpart) {
+                                                             int64_t lda, const double* __restrict__ Zu,
+                                                             const double* __restrict__ Zl,
+                                                             const double* __restrict__ Zw, int64_t ldz,
+                                                             double* __restrict__ Ou, double* __restrict__ Ol,
+                                                             double* __restrict__ Ow) {
   constexpr int NQ = HASW ? 2 * NB : NB;
   constexpr int OFF = HASW ? NB : 0;
   extern __shared__ double hs[];
@@ -1099,30 +1119,11 @@ __global__ __launch_bounds__(UPD_THREADS) void k_dcgs_update(int64_t n, int k, c
       Vl[o] = y1[q];
       Wl[o] = y2[q];
       if (HASW) {
-        Zu[i + q * ldz] = w0[q];
-        Zl[i + q * ldz] = w1[q];
-        Zw[i + q * ldz] = w2[q];
+        Ou[i + q * lda] = w0[q];
+        Ol[i + q * lda] = w1[q];
+        Ow[i + q * lda] = w2[q];
       }
     }
-  }
-  if (!HASW || gpart == nullptr) return;
-  // B-Gram of W' (W'_u^T W'_u + (M W'_l)^T W'_l) over the block's rows
-  __shared__ double gw[UPD_THREADS / 64][NB * NB];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int c = 0; c < NB; ++c)
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      double g = (i < n) ? w0[c] * w0[q] + w2[c] * w1[q] : 0.0;
-      g = wave_sum(g);
-      if (lane == 0) gw[wave][c * NB + q] = g;
-    }
-  __syncthreads();
-  if (threadIdx.x < NB * NB) {
-    double g = 0.0;
-#pragma unroll
-    for (int w = 0; w < UPD_THREADS / 64; ++w) g += gw[w][threadIdx.x];
-    gpart[(int64_t)blockIdx.x * NB * NB + threadIdx.x] = g;
   }
 }
 
@@ -1151,11 +1152,11 @@ void launch_dcgs_dots(int64_t n, int k, int nb, bool hasw, const double* Vu, con
   hipLaunchKernelGGL(k_dots_final, dim3((nout + 3) / 4), dim3(256), 0, st, nout, blocks, partial, out);
 }
 
-void launch_dcgs_coef(int k, int nb, bool hasw, const double* P, double* H, int ldh, double* hc, double* hcol,
-                      double* Xm, int* flag, hipStream_t st) {
+void launch_dcgs_coef(int k, int nb, bool hasw, const double* P, double* H, int ldh, double* hc, double* Xm,
+                      int* flag, hipStream_t st) {
   const size_t shm = (size_t)4 * std::max(k, 1) * nb * sizeof(double);
 #define RIGA_DCC(NB, W) \
-  hipLaunchKernelGGL((k_dcgs_coef<NB, W>), dim3(1), dim3(1024), shm, st, k, P, H, ldh, hc, hcol, Xm, flag)
+  hipLaunchKernelGGL((k_dcgs_coef<NB, W>), dim3(1), dim3(1024), shm, st, k, P, H, ldh, hc, Xm, flag)
   if (nb == 1) {
     if (hasw) RIGA_DCC(1, true); else RIGA_DCC(1, false);
   } else {
@@ -1164,21 +1165,21 @@ void launch_dcgs_coef(int k, int nb, bool hasw, const double* P, double* H, int 
 #undef RIGA_DCC
 }
 
-int launch_dcgs_update(int64_t n, int k, int nb, bool hasw, const double* hc, const double* Xm, double* Vu,
-                       double* Vl, double* Wl, int64_t lda, double* Zu, double* Zl, double* Zw, int64_t ldz,
-                       double* gpart, hipStream_t st) {
+void launch_dcgs_update(int64_t n, int k, int nb, bool hasw, const double* hc, const double* Xm, double* Vu,
+                        double* Vl, double* Wl, int64_t lda, const double* Zu, const double* Zl, const double* Zw,
+                        int64_t ldz, hipStream_t st) {
   const int64_t blocks = std::max<int64_t>(1, (n + UPD_THREADS - 1) / UPD_THREADS);
   const size_t shm = (size_t)(k + nb) * (hasw ? 2 * nb : nb) * sizeof(double);
 #define RIGA_DCU(NB, W)                                                                                        \
   hipLaunchKernelGGL((k_dcgs_update<NB, W>), dim3((unsigned)blocks), dim3(UPD_THREADS), shm, st, n, k, hc, Xm, \
-                     Vu, Vl, Wl, lda, Zu, Zl, Zw, ldz, gpart)
+                     Vu, Vl, Wl, lda, Zu, Zl, Zw, ldz, Vu + (int64_t)(k + nb) * lda,                    \
+                     Vl + (int64_t)(k + nb) * lda, Wl + (int64_t)(k + nb) * lda)
   if (nb == 1) {
     if (hasw) RIGA_DCU(1, true); else RIGA_DCU(1, false);
   } else {
     if (hasw) RIGA_DCU(2, true); else RIGA_DCU(2, false);
   }
 #undef RIGA_DCU
-  return (int)blocks;
 }
 
 // ---------------------------------------------------------------------------

@@ -265,27 +265,28 @@ int launch_cgs_update_dots(int64_t n, int nc, int nq, const double* h, const dou
                            const double* Wl, int64_t lda, double* Zu, double* Zl, double* Zw, int64_t ldz,
                            double* partial, double* out, hipStream_t st);
 // Block Gram--Schmidt with the second pass delayed by one step (block nb <= 2;
-// the basis Vu, Vl, Wl = M Vl holds the finished columns 0..k and the block Y
-// at k..k+nb projected once; W = (Ru, Rl, MRl) the operator applied to Y):
+// the basis Vu, Vl, Wl = M Vl holds the finished columns 0..k and the pending
+// block Y at k..k+nb, projected once and not normalised; W = (Ru, Rl, MRl) the
+// operator applied to Y):
 //   launch_dcgs_dots    out = [V Y]^T_B [Y W] ((k+nb) x 2nb output-major; only
 //                       [V Y]^T_B Y without W) and, with s, MRl = M Rl on the
 //                       tensor grid in the same launch;
 //   launch_dcgs_coef    one workgroup: the coefficients hc ((k+nb) x 2nb, or
-//                       x nb), the new column hcol ((k+nb) x nb) of H, Xm =
-//                       T^{-1} (nb x nb), and H's columns 0..k rewritten for the
-//                       finished block; a block in the span of V sets *flag;
-//   launch_dcgs_update  Y finished in place and W projected once (W <- W Xm -
-//                       [V Y] hc), with per-block partial B-Gram sums of W
-//                       (nb^2 per block) when gpart is given; returns the
-//                       number of blocks.
+//                       x nb), Xm = T^{-1} (nb x nb), H's new column block
+//                       (rows 0..k+2nb of columns k..k+nb) and its columns 0..k
+//                       rewritten for the finished block; a block in the span
+//                       of V sets *flag;
+//   launch_dcgs_update  Y finished in place and, with W, the projected image
+//                       W Xm - [V Y] hc written to V[:, k+nb:k+2nb] as the next
+//                       pending block.
 void launch_dcgs_dots(int64_t n, int k, int nb, bool hasw, const double* Vu, const double* Vl, const double* Wl,
                       int64_t lda, const double* Ru, const double* Rl, double* partial, double* out,
                       const DevSpace* s, const double* M1, double* MRl, hipStream_t st);
-void launch_dcgs_coef(int k, int nb, bool hasw, const double* P, double* H, int ldh, double* hc, double* hcol,
-                      double* Xm, int* flag, hipStream_t st);
-int launch_dcgs_update(int64_t n, int k, int nb, bool hasw, const double* hc, const double* Xm, double* Vu,
-                       double* Vl, double* Wl, int64_t lda, double* Zu, double* Zl, double* Zw, int64_t ldz,
-                       double* gpart, hipStream_t st);
+void launch_dcgs_coef(int k, int nb, bool hasw, const double* P, double* H, int ldh, double* hc, double* Xm,
+                      int* flag, hipStream_t st);
+void launch_dcgs_update(int64_t n, int k, int nb, bool hasw, const double* hc, const double* Xm, double* Vu,
+                        double* Vl, double* Wl, int64_t lda, const double* Zu, const double* Zl, const double* Zw,
+                        int64_t ldz, hipStream_t st);
 // Y = a M X + b K X + c Z on the tensor grid of a space (X[j n + i], nq <= 4
 // columns; Z may be null) by sum factorisation with the banded 1-D factors:
 // per 64 x 8 tile of the grid, T = X M1^T and X K1^T along i, then
