@@ -608,6 +608,13 @@ riga_status assemble_impl(riga_problem* h, const riga_damping* damping, double g
       for (size_t v = 0; v < P.nf.size(); ++v) dblocks += (P.no[v] + 63) / 64;
       h->d_DR = h->dalloc<double>((size_t)dblocks * 4096);
     }
+    // captured block steps hold the operator's coefficients (alpha, beta, the
+    // skew part) and its kernel choice (an element damping field or not): they
+    // are kept only when a re-assembly leaves all of these as they were
+    const bool same_op = h->assembled && h->gyro == gyro && h->gx == gx && h->gy == gy &&
+                         h->alpha == damping->alpha && h->beta == damping->beta &&
+                         (h->c_elem == nullptr) == (damping->c_elem == nullptr);
+    if (!same_op) h->clear_graphs();
     ck(hipEventRecord(h->ev0, h->st));
     riga::launch_bspline_tables(h->ds, h->d_gx, h->d_gw, h->d_tabM, h->d_tabK, gyro ? h->d_tabS : nullptr, h->st);
     riga::launch_band_1d(h->ds, h->d_tabM, h->d_tabK, h->d_M1, h->d_K1, h->st);
@@ -619,7 +626,6 @@ riga_status assemble_impl(riga_problem* h, const riga_damping* damping, double g
     ck(hipEventRecord(h->ev1, h->st));
     h->gyro = gyro; h->gx = gx; h->gy = gy;
     h->alpha = damping->alpha; h->beta = damping->beta; h->c_elem = damping->c_elem;
-    h->clear_graphs();   // captured block steps hold the old operator coefficients
     h->assembled = true;
     h->factored = false;
     h->cmode = false;
@@ -905,7 +911,8 @@ riga_status riga_factor(riga_problem* h, double sigma, int64_t* bad_pivot) {
   if (!h->assembled) return RIGA_ERR_STATE;
   return run([&]() -> riga_status {
     ck(hipSetDevice(h->device));
-    h->clear_graphs();
+    // captured block steps stay valid for the same shift and factor kind
+    // (riga_eigs compares both before replaying them)
     h->mixed = false;
     return factor_all(h, sigma, bad_pivot);
   });

@@ -109,3 +109,29 @@ def test_full_size_headline_schedules_agree():
         assert st == 0 and nconv == 40
         assert rel.max() <= 1e-10 and eta.max() <= 1e-10
     pr.close()
+
+
+def test_graphs_kept_across_identical_steps_and_dropped_on_change():
+    """Re-assembling and re-factoring with the same damping and shift replays
+    the captured block steps (bitwise the same pairs); another damping or
+    shift drops them (the pairs of the new problem match its closed form)."""
+    p, ne, s, nev, m = 3, 32, 8, 12, 32
+    pr = _problem(p, ne, s, 0.05, 0.005)
+
+    def solve(alpha, beta, sigma):
+        pr.assemble(alpha, beta)
+        pr.factor(sigma)
+        lam, X, eta, nconv, st = pr.eigs(nev, m, block=2, seed=7)
+        assert st == 0 and nconv == nev
+        ref, _ = oeig.rayleigh_closed(p, ne, s, alpha, beta, sigma, nev)
+        assert np.abs(lam - ref).max() <= 1e-10 * np.abs(ref).max()
+        return lam, X
+
+    a = solve(0.05, 0.005, 2.0)
+    b = solve(0.05, 0.005, 2.0)
+    assert np.array_equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    solve(0.1, 0.002, 2.0)
+    solve(0.1, 0.002, 3.0)
+    c = solve(0.05, 0.005, 2.0)
+    assert np.array_equal(a[0], c[0]) and torch.equal(a[1], c[1])
+    pr.close()
