@@ -629,7 +629,9 @@ riga_status assemble_impl(riga_problem* h, const riga_damping* damping, double g
     h->assembled = true;
     h->factored = false;
     h->cmode = false;
-    h->norms[0] = h->norms[1] = h->norms[2] = -1;
+    // the 1-norms of K, C, M (residual scaling) are those of the same matrices
+    // when nothing but an element field's values could have changed, and it is absent
+    if (!(same_op && damping->c_elem == nullptr)) h->norms[0] = h->norms[1] = h->norms[2] = -1;
     h->stats.flops[RIGA_PHASE_ASSEMBLE] = 0.0;   // a lower-order term of eq. Cost
     h->stats.bytes[RIGA_PHASE_ASSEMBLE] =
         24.0 * (double)h->plan.nnz + (damping->c_elem ? 8.0 * h->mesh.ne * (double)h->mesh.ne : 0.0);
